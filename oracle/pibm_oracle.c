@@ -1,0 +1,671 @@
+/*
+ * pibm_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU reference of one coupled lattice-Boltzmann /
+ * particulate immersed boundary (PIBM) / discrete-element time step, written
+ * from Zhang et al., "PIBM: Particulate immersed boundary method for
+ * fluid-particle interaction problems" (arXiv:1407.6704).  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  It shares no source, header, table or helper with the GPU library;
+ * the lattice tables below are written out again from the textbook
+ * definitions of D2Q9 and D3Q19.
+ *
+ * Every loop is the definition, in the paper's order: no blocking, no
+ * fusion, no shortcut.  Where the paper is silent or garbled the reading
+ * taken is stated at the function (readings R1..R17 of the design notes).
+ *
+ * Pins (tests/test_oracle_*.py) tie each function to something other than
+ * itself: body-force Poiseuille closed form, delta-kernel moments, equilibrium
+ * moments, mass and momentum bookkeeping, interpolation/spreading adjointness,
+ * one-way terminal settling, brute-force contact lists, restitution.
+ * Parity unpinned: long multi-particle trajectories (chaotic; compared by
+ * statistics only).
+ *
+ * Layouts: populations f[q][z][y][x] (x fastest, z = 0 in 2D), vector fields
+ * v[a][z][y][x], particle arrays p[a*np + i] (axis-major).  Node (x,y,z) sits
+ * at (x+1/2, y+1/2, z+1/2); non-periodic axes have walls at 0 and n.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef struct {
+    int lattice;            /* 9 = D2Q9, 19 = D3Q19 */
+    int n[3];               /* nodes per axis; n[2] == 1 for D2Q9 */
+    int periodic[3];        /* 1: periodic lattice axis (no particles allowed) */
+    double tau;             /* BGK relaxation time, Eq. lbm2 */
+    double rho0;            /* fluid density used in the buoyancy term */
+    double gravity[3];      /* gravitational acceleration, Eq. demgov */
+    double fluid_force[3];  /* uniform body force density on the fluid */
+    int contact;            /* 0 none, 1 linear spring-dashpot, 2 soft */
+    double kn, restitution; /* linear spring-dashpot parameters */
+    double k_soft;          /* soft repulsion stiffness */
+    double skin;            /* candidate-list skin */
+    int n_sub;              /* DEM sub-steps per lattice step */
+    int two_way;            /* 1: spread the particle force onto the fluid */
+    int bin_log2;           /* cell-list bin edge, in node spacings, = 2^bin_log2 */
+} orc_cfg;
+
+/* ------------------------------------------------------------------ */
+/* Lattices (R1).  D2Q9 and D3Q19, c = 1, c_s^2 = 1/3.  Direction order is  */
+/* the exchange order of the public interface: rest, then opposite pairs.   */
+/* ------------------------------------------------------------------ */
+
+static const int E9[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+static const int E19[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+int orc_q(int lattice) { return lattice == 19 ? 19 : 9; }
+int orc_dim(int lattice) { return lattice == 19 ? 3 : 2; }
+
+/* Velocity set, weights and opposite directions.  Weights are the textbook
+ * values for the second-order equilibrium of Eq. lbm3 with c_s^2 = 1/3:
+ * D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36. */
+void orc_tables(int lattice, int *e, double *w, int *opp)
+{
+    int Q = orc_q(lattice);
+    for (int q = 0; q < Q; q++) {
+        const int *v = (Q == 19) ? E19[q] : E9[q];
+        int s = abs(v[0]) + abs(v[1]) + abs(v[2]);
+        for (int a = 0; a < 3; a++) e[3 * q + a] = v[a];
+        if (Q == 19)
+            w[q] = (s == 0) ? 1.0 / 3.0 : (s == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+        else
+            w[q] = (s == 0) ? 4.0 / 9.0 : (s == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+        /* opposite: search for -e_q */
+        for (int r = 0; r < Q; r++) {
+            const int *u = (Q == 19) ? E19[r] : E9[r];
+            if (u[0] == -v[0] && u[1] == -v[1] && u[2] == -v[2]) opp[q] = r;
+        }
+    }
+}
+
+/* Equilibrium distribution, Eq. lbm3 (c = 1). */
+void orc_equilibrium(int lattice, double rho, const double *u, double *feq)
+{
+    int Q = orc_q(lattice), e[19 * 3], opp[19];
+    double w[19];
+    orc_tables(lattice, e, w, opp);
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int q = 0; q < Q; q++) {
+        double eu = e[3 * q] * u[0] + e[3 * q + 1] * u[1] + e[3 * q + 2] * u[2];
+        feq[q] = rho * w[q] * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+}
+
+static size_t nnodes(const orc_cfg *c) { return (size_t)c->n[0] * c->n[1] * c->n[2]; }
+
+/* O1.  Density and momentum of the stored (post-stream, pre-collision)
+ * populations: rho = sum_q f_q, j = sum_q e_q f_q (Sec. 2.1, the moment
+ * definitions after Eq. lbm3). */
+void orc_moments(const orc_cfg *c, const double *f, double *rho, double *j)
+{
+    int Q = orc_q(c->lattice), e[19 * 3], opp[19];
+    double w[19];
+    orc_tables(c->lattice, e, w, opp);
+    size_t N = nnodes(c);
+    for (size_t r = 0; r < N; r++) {
+        double s = 0, m[3] = {0, 0, 0};
+        for (int q = 0; q < Q; q++) {
+            double v = f[q * N + r];
+            s += v;
+            for (int a = 0; a < 3; a++) m[a] += e[3 * q + a] * v;
+        }
+        rho[r] = s;
+        for (int a = 0; a < 3; a++) j[a * N + r] = m[a];
+    }
+}
+
+/* O6 + O7.  BGK collision with the body-force term of Eq. lbm9 (Guo form)
+ * and the half-force velocity rho u = sum f e + F/2 (end of Sec. 2.2),
+ * Eq. lbm2, followed by streaming.  F may be NULL (no force).  Streaming
+ * wraps on periodic axes; a link leaving the domain through a wall is
+ * reflected into the opposite direction at the same node (halfway
+ * bounce-back; R7: the paper's no-slip walls, nodes at i+1/2, walls at 0 and
+ * n).  A diagonal link counts as leaving if any of its components does. */
+void orc_collide_stream(const orc_cfg *c, const double *f, const double *F, double *fout)
+{
+    int Q = orc_q(c->lattice), e[19 * 3], opp[19];
+    double w[19];
+    orc_tables(c->lattice, e, w, opp);
+    size_t N = nnodes(c);
+    const double tau = c->tau;
+    for (int z = 0; z < c->n[2]; z++)
+        for (int y = 0; y < c->n[1]; y++)
+            for (int x = 0; x < c->n[0]; x++) {
+                size_t r = ((size_t)z * c->n[1] + y) * c->n[0] + x;
+                double rho = 0, jm[3] = {0, 0, 0}, Fr[3] = {0, 0, 0};
+                for (int q = 0; q < Q; q++) {
+                    rho += f[q * N + r];
+                    for (int a = 0; a < 3; a++) jm[a] += e[3 * q + a] * f[q * N + r];
+                }
+                if (F)
+                    for (int a = 0; a < 3; a++) Fr[a] = F[a * N + r];
+                double u[3];
+                for (int a = 0; a < 3; a++) u[a] = (jm[a] + 0.5 * Fr[a]) / rho;
+                double feq[19];
+                orc_equilibrium(c->lattice, rho, u, feq);
+                int pos[3] = {x, y, z};
+                for (int q = 0; q < Q; q++) {
+                    double eu = 0, eF = 0, uF = 0;
+                    for (int a = 0; a < 3; a++) {
+                        eu += e[3 * q + a] * u[a];
+                        eF += e[3 * q + a] * Fr[a];
+                        uF += u[a] * Fr[a];
+                    }
+                    /* Eq. lbm9: (1 - 1/2tau) w [3 (e - u) + 9 (e.u) e] . F */
+                    double S = (1.0 - 0.5 / tau) * w[q] * (3.0 * (eF - uF) + 9.0 * eu * eF);
+                    double fs = f[q * N + r] - (f[q * N + r] - feq[q]) / tau + S;
+                    int t[3], out = 0;
+                    for (int a = 0; a < 3; a++) {
+                        t[a] = pos[a] + e[3 * q + a];
+                        if (t[a] < 0 || t[a] >= c->n[a]) {
+                            if (c->periodic[a])
+                                t[a] = (t[a] + c->n[a]) % c->n[a];
+                            else
+                                out = 1;
+                        }
+                    }
+                    if (out)
+                        fout[opp[q] * N + r] = fs;
+                    else
+                        fout[q * N + ((size_t)t[2] * c->n[1] + t[1]) * c->n[0] + t[0]] = fs;
+                }
+            }
+}
+
+/* Eq. lbm12: the four-point cosine regularised delta function. */
+double orc_delta(double a)
+{
+    if (fabs(a) <= 2.0) return 0.25 * (1.0 + cos(M_PI * a / 2.0));
+    return 0.0;
+}
+
+/* O2.  One-dimensional weights of Eq. lbm11 (h = 1) for the four nodes
+ * base_a .. base_a+3 around X_a, base_a = floor(X_a - 1/2) - 1.  Nodes outside
+ * the domain get weight zero and the remaining weights of that axis are
+ * divided by their sum (R6), which keeps the partition of unity at walls. */
+void orc_weights(const orc_cfg *c, const double *X, int *base, double *phi)
+{
+    int D = orc_dim(c->lattice);
+    for (int a = 0; a < D; a++) {
+        base[a] = (int)floor(X[a] - 0.5) - 1;
+        double s = 0;
+        for (int k = 0; k < 4; k++) {
+            int i = base[a] + k;
+            double v = (i >= 0 && i < c->n[a]) ? orc_delta(X[a] - (i + 0.5)) : 0.0;
+            phi[4 * a + k] = v;
+            s += v;
+        }
+        for (int k = 0; k < 4; k++) phi[4 * a + k] /= s;
+    }
+    for (int a = D; a < 3; a++) {
+        base[a] = 0;
+        phi[4 * a] = 1.0;
+        phi[4 * a + 1] = phi[4 * a + 2] = phi[4 * a + 3] = 0.0;
+    }
+}
+
+/* O3.  Interpolation of density and momentum to each particle with the
+ * weights of O2: rho_i = sum_r W rho, j_i = sum_r W j (R3: moments of the
+ * pre-collision state; by linearity this equals interpolating every f_alpha
+ * as Eq. lbm5 does and taking moments). */
+void orc_interp(const orc_cfg *c, int np, const double *X, const double *rho,
+                const double *j, double *rho_i, double *j_i)
+{
+    int D = orc_dim(c->lattice);
+    size_t N = nnodes(c);
+    for (int p = 0; p < np; p++) {
+        double Xp[3] = {0.5, 0.5, 0.5}, phi[12];
+        int base[3];
+        for (int a = 0; a < D; a++) Xp[a] = X[a * np + p];
+        orc_weights(c, Xp, base, phi);
+        double sr = 0, sj[3] = {0, 0, 0};
+        int kz_n = (D == 3) ? 4 : 1;
+        for (int kz = 0; kz < kz_n; kz++)
+            for (int ky = 0; ky < 4; ky++)
+                for (int kx = 0; kx < 4; kx++) {
+                    double W = phi[kx] * phi[4 + ky] * phi[8 + kz];
+                    if (W == 0.0) continue;
+                    int x = base[0] + kx, y = base[1] + ky, z = base[2] + kz;
+                    size_t r = ((size_t)z * c->n[1] + y) * c->n[0] + x;
+                    sr += W * rho[r];
+                    for (int a = 0; a < 3; a++) sj[a] += W * j[a * N + r];
+                }
+        rho_i[p] = sr;
+        for (int a = 0; a < 3; a++) j_i[a * np + p] = sj[a];
+    }
+}
+
+/* O5.  Spreading, Eq. lbm10: F(r) += sum_l coef_l D(r - X_l), where the
+ * caller passes coef_l = A_p g_l.  Adds into F (which the caller clears). */
+void orc_spread(const orc_cfg *c, int np, const double *X, const double *coef, double *F)
+{
+    int D = orc_dim(c->lattice);
+    size_t N = nnodes(c);
+    for (int p = 0; p < np; p++) {
+        double Xp[3] = {0.5, 0.5, 0.5}, phi[12];
+        int base[3];
+        for (int a = 0; a < D; a++) Xp[a] = X[a * np + p];
+        orc_weights(c, Xp, base, phi);
+        int kz_n = (D == 3) ? 4 : 1;
+        for (int kz = 0; kz < kz_n; kz++)
+            for (int ky = 0; ky < 4; ky++)
+                for (int kx = 0; kx < 4; kx++) {
+                    double W = phi[kx] * phi[4 + ky] * phi[8 + kz];
+                    if (W == 0.0) continue;
+                    int x = base[0] + kx, y = base[1] + ky, z = base[2] + kz;
+                    size_t r = ((size_t)z * c->n[1] + y) * c->n[0] + x;
+                    for (int a = 0; a < D; a++) F[a * N + r] += W * coef[a * np + p];
+                }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Cell list (the paper is silent on neighbour search).  A particle's     */
+/* dual cell along axis a is c_a = floor(X_a - 1/2) in [-1, n_a - 1], its   */
+/* bin b_a = (c_a + 1) >> bin_log2, and its key the x-fastest linear index  */
+/* of the bin.  Particles are ordered by (key, id); bin_start[k] is the     */
+/* first sorted slot of bin k, bin_start[nbins] = np.                       */
+/* ------------------------------------------------------------------ */
+
+int64_t orc_nbins(const orc_cfg *c, int64_t *nb)
+{
+    int D = orc_dim(c->lattice);
+    int64_t total = 1;
+    for (int a = 0; a < 3; a++) {
+        nb[a] = (a < D) ? ((int64_t)c->n[a] >> c->bin_log2) + 1 : 1;
+        total *= nb[a];
+    }
+    return total;
+}
+
+static int64_t bin_coord(const orc_cfg *c, double x)
+{
+    int64_t cell = (int64_t)floor(x - 0.5);
+    return (cell + 1) >> c->bin_log2;
+}
+
+int64_t orc_key(const orc_cfg *c, const double *Xp)
+{
+    int D = orc_dim(c->lattice);
+    int64_t nb[3];
+    orc_nbins(c, nb);
+    int64_t b[3] = {0, 0, 0};
+    for (int a = 0; a < D; a++) b[a] = bin_coord(c, Xp[a]);
+    return (b[2] * nb[1] + b[1]) * nb[0] + b[0];
+}
+
+typedef struct { int64_t key; int id; } kv_t;
+static int kv_cmp(const void *pa, const void *pb)
+{
+    const kv_t *a = pa, *b = pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    return (a->id > b->id) - (a->id < b->id);
+}
+
+/* keys[s] and perm[s] are the key and id of sorted slot s. */
+void orc_cell_list(const orc_cfg *c, int np, const double *X, int64_t *keys,
+                   int *perm, int64_t *bin_start)
+{
+    int D = orc_dim(c->lattice);
+    int64_t nb[3];
+    int64_t nbins = orc_nbins(c, nb);
+    kv_t *kv = malloc(sizeof(kv_t) * (np > 0 ? np : 1));
+    for (int p = 0; p < np; p++) {
+        double Xp[3] = {0.5, 0.5, 0.5};
+        for (int a = 0; a < D; a++) Xp[a] = X[a * np + p];
+        kv[p].key = orc_key(c, Xp);
+        kv[p].id = p;
+    }
+    qsort(kv, np, sizeof(kv_t), kv_cmp);
+    for (int s = 0; s < np; s++) {
+        keys[s] = kv[s].key;
+        perm[s] = kv[s].id;
+    }
+    /* bin_start by counting */
+    for (int64_t k = 0; k <= nbins; k++) bin_start[k] = 0;
+    for (int s = 0; s < np; s++) bin_start[kv[s].key + 1]++;
+    for (int64_t k = 0; k < nbins; k++) bin_start[k + 1] += bin_start[k];
+    free(kv);
+}
+
+/* ------------------------------------------------------------------ */
+/* Particles and contacts.                                                */
+/* ------------------------------------------------------------------ */
+
+/* Particle volume: a disk of unit depth in 2D, a sphere in 3D (R5). */
+double orc_mass(int D, double d, double rho_p)
+{
+    return D == 3 ? rho_p * M_PI * d * d * d / 6.0 : rho_p * 0.25 * M_PI * d * d;
+}
+
+/* Cross-sectional area of Eq. lbm10. */
+double orc_area(double d) { return 0.25 * M_PI * d * d; }
+
+/* Damping ratio from the coefficient of restitution of a linear
+ * spring-dashpot (R10). */
+double orc_zeta(double e)
+{
+    double l = log(e);
+    return -l / sqrt(M_PI * M_PI + l * l);
+}
+
+/* Contact force on particle p from particle q (R10).  r = X_p - X_q,
+ * du = U_p - U_q.  Linear spring-dashpot, normal only, no clamp, force only
+ * for strictly positive overlap; or soft repulsion k_s (1 - r/r_c)^2. */
+static void pair_force(const orc_cfg *c, int D, const double *r, const double *du,
+                       double dp, double dq, double mp, double mq, double *Fout)
+{
+    double dist2 = 0;
+    for (int a = 0; a < D; a++) dist2 += r[a] * r[a];
+    double dist = sqrt(dist2);
+    double rc = 0.5 * (dp + dq);
+    for (int a = 0; a < 3; a++) Fout[a] = 0;
+    if (c->contact == 1) {
+        double delta = rc - dist;
+        if (!(delta > 0.0)) return;
+        double vn = 0;
+        for (int a = 0; a < D; a++) vn += du[a] * r[a] / dist;
+        double meff = mp * mq / (mp + mq);
+        double gam = 2.0 * orc_zeta(c->restitution) * sqrt(c->kn * meff);
+        double mag = c->kn * delta - gam * vn;
+        for (int a = 0; a < D; a++) Fout[a] = mag * r[a] / dist;
+    } else if (c->contact == 2) {
+        if (!(dist < rc)) return;
+        double s = 1.0 - dist / rc;
+        for (int a = 0; a < D; a++) Fout[a] = c->k_soft * s * s * r[a] / dist;
+    }
+}
+
+/* Contact with the walls at 0 and n_a of every non-periodic axis: the wall
+ * acts as a particle of infinite mass at distance dist along the inward
+ * normal, with r_c = d/2. */
+static void wall_force(const orc_cfg *c, int D, const double *X, const double *U,
+                       double dp, double mp, double *Fout)
+{
+    for (int a = 0; a < 3; a++) Fout[a] = 0;
+    if (c->contact == 0) return;
+    for (int a = 0; a < D; a++) {
+        if (c->periodic[a]) continue;
+        for (int side = 0; side < 2; side++) {
+            double nrm = side == 0 ? 1.0 : -1.0;         /* inward normal */
+            double dist = side == 0 ? X[a] : c->n[a] - X[a];
+            double vn = U[a] * nrm;
+            double rc = 0.5 * dp;
+            if (c->contact == 1) {
+                double delta = rc - dist;
+                if (!(delta > 0.0)) continue;
+                double gam = 2.0 * orc_zeta(c->restitution) * sqrt(c->kn * mp);
+                Fout[a] += (c->kn * delta - gam * vn) * nrm;
+            } else {
+                if (!(dist < rc)) continue;
+                double s = 1.0 - dist / rc;
+                Fout[a] += c->k_soft * s * s * nrm;
+            }
+        }
+    }
+}
+
+/* Candidate pairs: every unordered pair with |X_p - X_q| < (d_p+d_q)/2 + skin,
+ * found through the bins of orc_cell_list (bin edge >= cutoff + skin, so the
+ * 3^D neighbouring bins suffice).  Writes up to cap pairs (p < q) and returns
+ * the total count. */
+int64_t orc_candidate_pairs(const orc_cfg *c, int np, const double *X, const double *d,
+                            int *pairs, int64_t cap)
+{
+    int D = orc_dim(c->lattice);
+    int64_t nb[3];
+    int64_t nbins = orc_nbins(c, nb);
+    int64_t *keys = malloc(sizeof(int64_t) * (np > 0 ? np : 1));
+    int *perm = malloc(sizeof(int) * (np > 0 ? np : 1));
+    int64_t *bs = malloc(sizeof(int64_t) * (nbins + 1));
+    orc_cell_list(c, np, X, keys, perm, bs);
+    int64_t count = 0;
+    for (int p = 0; p < np; p++) {
+        int64_t b[3] = {0, 0, 0};
+        for (int a = 0; a < D; a++) b[a] = bin_coord(c, X[a * np + p]);
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; a++) {
+            lo[a] = (a < D) ? -1 : 0;
+            hi[a] = (a < D) ? 1 : 0;
+        }
+        for (int oz = lo[2]; oz <= hi[2]; oz++)
+            for (int oy = lo[1]; oy <= hi[1]; oy++)
+                for (int ox = lo[0]; ox <= hi[0]; ox++) {
+                    int64_t bb[3] = {b[0] + ox, b[1] + oy, b[2] + oz};
+                    int ok = 1;
+                    for (int a = 0; a < 3; a++)
+                        if (bb[a] < 0 || bb[a] >= nb[a]) ok = 0;
+                    if (!ok) continue;
+                    int64_t k = (bb[2] * nb[1] + bb[1]) * nb[0] + bb[0];
+                    for (int64_t s = bs[k]; s < bs[k + 1]; s++) {
+                        int q = perm[s];
+                        if (q <= p) continue;
+                        double d2 = 0;
+                        for (int a = 0; a < D; a++) {
+                            double t = X[a * np + p] - X[a * np + q];
+                            d2 += t * t;
+                        }
+                        double cut = 0.5 * (d[p] + d[q]) + c->skin;
+                        if (d2 < cut * cut) {
+                            if (count < cap) {
+                                pairs[2 * count] = p;
+                                pairs[2 * count + 1] = q;
+                            }
+                            count++;
+                        }
+                    }
+                }
+    }
+    free(keys);
+    free(perm);
+    free(bs);
+    return count;
+}
+
+/* Brute-force O(N^2) version of the same list (for pinning the cell list). */
+int64_t orc_candidate_pairs_brute(const orc_cfg *c, int np, const double *X, const double *d,
+                                  int *pairs, int64_t cap)
+{
+    int D = orc_dim(c->lattice);
+    int64_t count = 0;
+    for (int p = 0; p < np; p++)
+        for (int q = p + 1; q < np; q++) {
+            double d2 = 0;
+            for (int a = 0; a < D; a++) {
+                double t = X[a * np + p] - X[a * np + q];
+                d2 += t * t;
+            }
+            double cut = 0.5 * (d[p] + d[q]) + c->skin;
+            if (d2 < cut * cut) {
+                if (count < cap) {
+                    pairs[2 * count] = p;
+                    pairs[2 * count + 1] = q;
+                }
+                count++;
+            }
+        }
+    return count;
+}
+
+/* O4.  Particle sub-steps (R4, R8, R9).  For k = 0 .. n_sub-1 with h = 1/n_sub,
+ * every force uses the state at sub-step k (Jacobi):
+ *   g^k   = 2 (rho_i U^k - j_i)                (R2: momentum exchange, Eqs. lbm7-lbm8)
+ *   F_h^k = -A_p g^k                           (Eq. lbm13)
+ *   F_c^k = sum over candidate pairs and walls
+ *   U^{k+1} = U^k + h (F_h^k + F_c^k + (1 - rho0/rho_p) m g) / m   (Eq. demgov)
+ *   X^{k+1} = X^k + h U^{k+1}
+ * Outputs the final X, U, the sub-step mean gbar of g (what the fluid
+ * receives), the sub-step mean contact force, and vmax_p = max_k |U^k|
+ * over k = 0..n_sub (the skin check: displacement <= vmax * one step).
+ * pairs: candidate pairs at the start of the step (orc_candidate_pairs). */
+void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
+             const double *rho_p, const double *rho_i, const double *j_i,
+             int64_t npairs, const int *pairs, double *gbar, double *fc_mean, double *vmax)
+{
+    int D = orc_dim(c->lattice);
+    int n_sub = c->n_sub;
+    double h = 1.0 / n_sub;
+    double *m = malloc(sizeof(double) * (np > 0 ? np : 1));
+    double *g = malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+    double *Fc = malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+    for (int p = 0; p < np; p++) {
+        m[p] = orc_mass(D, d[p], rho_p[p]);
+        for (int a = 0; a < 3; a++) {
+            gbar[a * np + p] = 0;
+            fc_mean[a * np + p] = 0;
+        }
+        double s = 0;
+        for (int a = 0; a < D; a++) s += U[a * np + p] * U[a * np + p];
+        vmax[p] = sqrt(s);
+    }
+    for (int k = 0; k < n_sub; k++) {
+        /* forces at sub-step k */
+        for (int p = 0; p < np; p++) {
+            for (int a = 0; a < 3; a++) {
+                g[3 * p + a] = (a < D) ? 2.0 * (rho_i[p] * U[a * np + p] - j_i[a * np + p]) : 0.0;
+                Fc[3 * p + a] = 0;
+            }
+            double Xp[3] = {0, 0, 0}, Up[3] = {0, 0, 0}, Fw[3];
+            for (int a = 0; a < D; a++) {
+                Xp[a] = X[a * np + p];
+                Up[a] = U[a * np + p];
+            }
+            wall_force(c, D, Xp, Up, d[p], m[p], Fw);
+            for (int a = 0; a < D; a++) Fc[3 * p + a] += Fw[a];
+        }
+        if (c->contact != 0)
+            for (int64_t i = 0; i < npairs; i++) {
+                int p = pairs[2 * i], q = pairs[2 * i + 1];
+                double r[3] = {0, 0, 0}, du[3] = {0, 0, 0}, Fpq[3];
+                for (int a = 0; a < D; a++) {
+                    r[a] = X[a * np + p] - X[a * np + q];
+                    du[a] = U[a * np + p] - U[a * np + q];
+                }
+                pair_force(c, D, r, du, d[p], d[q], m[p], m[q], Fpq);
+                for (int a = 0; a < D; a++) {
+                    Fc[3 * p + a] += Fpq[a];
+                    Fc[3 * q + a] -= Fpq[a];
+                }
+            }
+        /* symplectic Euler update */
+        for (int p = 0; p < np; p++) {
+            double A = orc_area(d[p]);
+            double s = 0;
+            for (int a = 0; a < D; a++) {
+                double W = (1.0 - c->rho0 / rho_p[p]) * m[p] * c->gravity[a];
+                double Fh = -A * g[3 * p + a];
+                U[a * np + p] += h * (Fh + Fc[3 * p + a] + W) / m[p];
+                X[a * np + p] += h * U[a * np + p];
+                gbar[a * np + p] += g[3 * p + a];
+                fc_mean[a * np + p] += Fc[3 * p + a];
+                s += U[a * np + p] * U[a * np + p];
+            }
+            if (sqrt(s) > vmax[p]) vmax[p] = sqrt(s);
+        }
+    }
+    for (int p = 0; p < np; p++)
+        for (int a = 0; a < 3; a++) {
+            gbar[a * np + p] /= n_sub;
+            fc_mean[a * np + p] /= n_sub;
+        }
+    free(m);
+    free(g);
+    free(Fc);
+}
+
+/* One coupled step n -> n+1, O1..O7 (R9):
+ *   O1 moments of f;  O2-O3 weights and interpolation at the start-of-step
+ *   positions;  O4 particle sub-steps;  O5 spreading of A_p gbar with the
+ *   start-of-step weights (if two_way);  O6-O7 collision with
+ *   F = fluid_force + spread, and streaming.
+ * Particle state X, U is updated in place.  Outputs: fout; F (D x N, the
+ * force field used by the collision); gbar, fc_mean (D x np); returns the
+ * number of particles whose vmax exceeds skin/2 (the skin check). */
+int orc_step(const orc_cfg *c, const double *f, double *fout, double *F,
+             int np, double *X, double *U, const double *d, const double *rho_p,
+             double *gbar, double *fc_mean, double *rho_i_out, double *j_i_out)
+{
+    int D = orc_dim(c->lattice);
+    size_t N = nnodes(c);
+    double *rho = malloc(sizeof(double) * N);
+    double *j = malloc(sizeof(double) * 3 * N);
+    orc_moments(c, f, rho, j);
+
+    int npp = np > 0 ? np : 1;
+    double *X0 = malloc(sizeof(double) * 3 * npp);
+    double *rho_i = malloc(sizeof(double) * npp);
+    double *j_i = malloc(sizeof(double) * 3 * npp);
+    double *vmax = malloc(sizeof(double) * npp);
+    memcpy(X0, X, sizeof(double) * D * np);
+    orc_interp(c, np, X0, rho, j, rho_i, j_i);
+
+    int64_t npairs = 0;
+    int *pairs = NULL;
+    if (c->contact != 0 && np > 1) {
+        npairs = orc_candidate_pairs(c, np, X0, d, NULL, 0);
+        pairs = malloc(sizeof(int) * 2 * (npairs > 0 ? npairs : 1));
+        orc_candidate_pairs(c, np, X0, d, pairs, npairs);
+    }
+    orc_dem(c, np, X, U, d, rho_p, rho_i, j_i, npairs, pairs, gbar, fc_mean, vmax);
+
+    for (int a = 0; a < D; a++)
+        for (size_t r = 0; r < N; r++) F[a * N + r] = c->fluid_force[a];
+    if (c->two_way && np > 0) {
+        double *coef = malloc(sizeof(double) * 3 * npp);
+        for (int p = 0; p < np; p++)
+            for (int a = 0; a < D; a++) coef[a * np + p] = orc_area(d[p]) * gbar[a * np + p];
+        orc_spread(c, np, X0, coef, F);
+        free(coef);
+    }
+    /* the collision takes a 3-component field; pad the 2D case */
+    double *F3 = malloc(sizeof(double) * 3 * N);
+    for (int a = 0; a < 3; a++)
+        for (size_t r = 0; r < N; r++) F3[a * N + r] = (a < D) ? F[a * N + r] : 0.0;
+    orc_collide_stream(c, f, F3, fout);
+
+    int nskin = 0;
+    for (int p = 0; p < np; p++)
+        if (vmax[p] > 0.5 * c->skin) nskin++;
+    if (rho_i_out) memcpy(rho_i_out, rho_i, sizeof(double) * np);
+    if (j_i_out)
+        for (int a = 0; a < D; a++)
+            for (int p = 0; p < np; p++) j_i_out[a * np + p] = j_i[a * np + p];
+    free(F3);
+    free(rho);
+    free(j);
+    free(X0);
+    free(rho_i);
+    free(j_i);
+    free(vmax);
+    free(pairs);
+    return nskin;
+}
+
+/* Total fluid mass sum_r sum_q f and momentum sum_r sum_q e_q f. */
+void orc_fluid_totals(const orc_cfg *c, const double *f, double *mass, double *mom)
+{
+    int Q = orc_q(c->lattice), e[19 * 3], opp[19];
+    double w[19];
+    orc_tables(c->lattice, e, w, opp);
+    size_t N = nnodes(c);
+    *mass = 0;
+    mom[0] = mom[1] = mom[2] = 0;
+    for (int q = 0; q < Q; q++)
+        for (size_t r = 0; r < N; r++) {
+            *mass += f[q * N + r];
+            for (int a = 0; a < 3; a++) mom[a] += e[3 * q + a] * f[q * N + r];
+        }
+}
