@@ -1,0 +1,193 @@
+"""Benchmark of the coupled LBM-PIBM-DEM step on one MI355X.
+
+Default workload: D2Q9 2048^2, tau 0.6, 500k disks (d ~ U[0.3, 0.8],
+density ratio 2.5, upper 60 % of a closed cavity), FP32, linear
+spring-dashpot contacts with 677 sub-steps.  A "step" is one full coupled
+step: moments, cell list, interpolation, DEM, spreading, collision+streaming.
+Inputs are seeded synthetic (no dataset); the timed region starts with all
+state resident in HBM.
+
+Prints ONE JSON line.  Besides the contract fields it carries
+  roofline      - the dominant kernel against MI355X HBM peak (8 TB/s), from
+                  HIP events recorded on the library's stream around every
+                  phase during the timed region (algorithmic bytes / time)
+  cpu_baseline  - the FP64 oracle on the host cores, on a bounded sample
+  extra         - the same measurement for the D3Q19 256^3 / 2M-sphere case
+                  in FP32 and with FP16 deviation storage
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
+
+
+def algorithmic_bytes(phase: str, w, np_: int) -> float:
+    """Algorithmic bytes one launch of a phase moves (per step)."""
+    Q = 19 if w.lattice == 19 else 9
+    D = w.dim
+    es = 2 if w.storage == "fp16" else 4
+    N = w.nodes
+    coupled = np_ > 0 and w.two_way
+    if phase == "collide":
+        return N * (2 * Q * es + (4 * D if coupled else 0))
+    if phase == "moments":
+        return N * (Q * es + 16)
+    if phase == "spread":
+        # force field write + per-particle weights, base and coefficients read
+        return N * 4 * D + np_ * (8 + 16 * D + 4 * D)
+    if phase == "interp":
+        # particle position read, moments gathered once per node (dense), outputs
+        return np_ * (8 * D + 4 + 4 * D + 8 + 16 * D) + N * 16
+    if phase == "cell_list":
+        return np_ * (2 * (12 * D + 12) + 16)
+    if phase == "dem":
+        return np_ * (2 * 12 * D + 8 + 4 * (1 + D) + 8 * D)
+    return 0.0
+
+
+def run_gpu(w, steps: int, warmup: int, label: str):
+    import torch
+
+    from paper_1407_6704_amd import pibm, workloads as W
+
+    t0 = time.time()
+    X, U, d, rp = W.make_particles(w)
+    print(f"[bench] {label}: placed {X.shape[1]} particles in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    cfg = pibm.config_from_workload(w)
+    sim = pibm.Sim(cfg, X.shape[1])
+    sim.set_particles(X, U, d, rp)
+    sim.step(warmup)
+    sim.synchronize()
+    sim.set_profiling(True)
+    sim.phase_times()
+    stream = sim.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    phases, nsteps = sim.phase_times()
+    status = "ok"
+    try:
+        sim.synchronize()
+    except pibm.PibmError as e:
+        status = e.name
+    diag = sim.diagnostics()
+    sim.set_profiling(False)
+    np_ = X.shape[1]
+    res = {
+        "ms_per_step": ms / steps,
+        "mlups": w.nodes * steps / (ms * 1e-3) / 1e6,
+        "particle_updates_per_s": np_ * steps / (ms * 1e-3),
+        "phases_ms_per_step": {k: v / max(nsteps, 1) for k, v in phases.items()},
+        "active_particles": diag["active"],
+        "status": status,
+    }
+    # dominant kernel: the single-launch lattice phase with the most time
+    single = {k: v for k, v in res["phases_ms_per_step"].items() if k in ("collide", "moments", "spread")}
+    dom = max(single, key=single.get)
+    b = algorithmic_bytes(dom, w, np_)
+    t = single[dom] * 1e-3
+    ach = b / t / 1e9
+    res["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                       "bytes_per_launch": b, "avg_launch_ms": single[dom]}
+    del sim
+    torch.cuda.empty_cache()
+    return res, (X, U, d, rp)
+
+
+def cpu_baseline(w, particles, budget_s=30.0):
+    """The FP64 oracle (single thread, as it stands) on one full step of the
+    same workload."""
+    import numpy as np
+
+    from oracle import oracle as orc
+
+    X, U, d, rp = particles
+    oc = orc.make_cfg(lattice=w.lattice, n=w.n, tau=w.tau, gravity=w.gravity_vec(), contact=w.contact,
+                      kn=w.kn, restitution=w.restitution, k_soft=w.k_soft, skin=w.skin, n_sub=w.n_sub,
+                      two_way=w.two_way, bin_log2=w.bin_log2)
+    f = orc.rest_state(oc)
+    t0 = time.time()
+    orc.step(oc, f, X, U, d, rp)
+    dt = time.time() - t0
+    return {"value": w.nodes / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "particle_updates_per_s": X.shape[1] / dt,
+            "sample": f"one full coupled step of the same workload ({w.nodes} nodes, {X.shape[1]} particles, "
+                      f"{w.n_sub} sub-steps), FP64, single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--extra-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+              "(the lattice would shard into slabs with a halo exchange, which is not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1407_6704_amd import pibm, workloads as W
+
+    pibm.load()
+    w = W.WORKLOADS[args.workload]
+    res, parts = run_gpu(w, args.steps, args.warmup, w.name)
+    line = {
+        "metric": METRIC,
+        "value": res["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w.storage == "fp32" else "f16-storage/f32-compute",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: D2Q9 {w.n[0]}x{w.n[1]}" if w.dim == 2 else
+                   f"{w.name}: D3Q19 {w.n[0]}x{w.n[1]}x{w.n[2]}",
+                   "particles": w.n_particles, "tau": w.tau, "n_sub": w.n_sub, "contact": w.contact,
+                   "storage": w.storage, "seed": w.seed},
+        "particle_updates_per_s": res["particle_updates_per_s"],
+        "phases_ms_per_step": res["phases_ms_per_step"],
+        "active_particles": res["active_particles"],
+        "status": res["status"],
+        "roofline": res["roofline"],
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, parts)
+    if not args.no_extra:
+        extra = {}
+        for name in ("c2", "c3"):
+            r, _ = run_gpu(W.WORKLOADS[name], args.extra_steps, 2, name)
+            extra[name] = r
+        extra["fp16_speedup"] = extra["c2"]["ms_per_step"] / extra["c3"]["ms_per_step"]
+        line["extra"] = extra
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

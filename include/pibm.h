@@ -1,0 +1,185 @@
+/*
+ * pibm.h -- C ABI of the MI355X (gfx950) library for one coupled
+ * lattice-Boltzmann / particulate immersed boundary (PIBM) / DEM time step,
+ * after Zhang et al., "PIBM: Particulate immersed boundary method for
+ * fluid-particle interaction problems" (arXiv:1407.6704).
+ *
+ * One step n -> n+1 (Sec. 2 of the paper, in this order):
+ *   1. density and momentum of the stored populations (Sec. 2.1);
+ *   2. cell list of the particles (bins of 2^bin_log2 dual cells);
+ *   3. delta-kernel interpolation of density and momentum to every particle
+ *      (Eqs. lbm11-lbm12 weights);
+ *   4. momentum-exchange force g = 2 (rho_i U - j_i) (Eqs. lbm7-lbm8), its
+ *      reaction -A_p g on the particle (Eq. lbm13), contacts and buoyant
+ *      weight (Eq. demgov), integrated over n_sub sub-steps;
+ *   5. spreading of A_p * mean(g) back to the lattice (Eq. lbm10);
+ *   6. BGK collision with the forcing term (Eqs. lbm2, lbm3, lbm9) and
+ *      streaming with halfway bounce-back at the walls.
+ *
+ * Units are lattice units (node spacing 1, time step 1).  Node (x, y, z)
+ * sits at (x + 1/2, y + 1/2, z + 1/2); a non-periodic axis a has walls at 0
+ * and n[a].  Fields are laid out [component][z][y][x] with x fastest
+ * (nz = 1 for D2Q9).  Particle arrays are [axis][N] in the caller's id order,
+ * which every call preserves.
+ *
+ * Memory ownership: the caller owns all device memory.  pibm_create carves
+ * its buffers from one device workspace of pibm_workspace_bytes() bytes that
+ * the caller allocates (for instance as a torch uint8 tensor) and keeps alive
+ * until pibm_destroy.  The library never allocates or frees device memory;
+ * the context itself owns only host bookkeeping.  All GPU work goes to the
+ * HIP stream given at creation (or by pibm_set_stream), asynchronously.
+ *
+ * I/O calls (pibm_set_*, pibm_read_*, pibm_write_*) take HOST arrays, copy
+ * through the workspace and synchronise the stream before returning.
+ * pibm_step only enqueues work.  Numerical trouble found on the device
+ * (skin violation, NaN, a full candidate list, an unstable drag sub-step) is
+ * latched in a device flag and reported by the next synchronising call.
+ *
+ * Error behaviour: every call returns a pibm_status; nothing throws across
+ * the ABI.  pibm_last_error() gives a message for the last failure on that
+ * context.  A context must be used by one host thread at a time.
+ */
+#ifndef PIBM_H
+#define PIBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIBM_ABI_VERSION 1
+
+typedef enum {
+    PIBM_OK = 0,
+    PIBM_E_ARG = 1,       /* bad pointer, size, particle outside the box, ... */
+    PIBM_E_CONFIG = 2,    /* tau <= 1/2, n_sub < 1, unknown lattice, ABI mismatch */
+    PIBM_E_HIP = 3,       /* a HIP runtime call failed */
+    PIBM_E_STATE = 4,     /* call order (e.g. step before particles are set) */
+    PIBM_E_UNSTABLE = 5,  /* NaN/Inf, |u| > 0.1, or a drag sub-step with h c >= 1 */
+    PIBM_E_SKIN = 6,      /* a particle moved more than skin/2 within one step */
+    PIBM_E_CAPACITY = 7   /* more candidates per particle than max_candidates */
+} pibm_status;
+
+enum { PIBM_D2Q9 = 9, PIBM_D3Q19 = 19 };
+enum { PIBM_STORE_FP32 = 0, PIBM_STORE_FP16 = 1 };
+enum { PIBM_CONTACT_NONE = 0, PIBM_CONTACT_LSD = 1, PIBM_CONTACT_SOFT = 2 };
+
+/* Lattice velocity order used by pibm_read_populations/pibm_write_populations:
+ *   D2Q9 : 0 (0,0); 1 (1,0); 2 (-1,0); 3 (0,1); 4 (0,-1);
+ *          5 (1,1); 6 (-1,-1); 7 (1,-1); 8 (-1,1)
+ *   D3Q19: 0 rest; 1..6 (+-x, +-y, +-z) as (1,0,0),(-1,0,0),(0,1,0),(0,-1,0),
+ *          (0,0,1),(0,0,-1); 7..18 edges (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),
+ *          (1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),
+ *          (0,-1,1).
+ * Weights: D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36 (c_s^2 = 1/3). */
+
+typedef struct {
+    int32_t abi_version;      /* PIBM_ABI_VERSION */
+    int32_t lattice;          /* PIBM_D2Q9 or PIBM_D3Q19 */
+    int32_t storage;          /* PIBM_STORE_FP32: f - w in FP32;
+                                 PIBM_STORE_FP16: (f - w) * 2^fp16_scale_log2 in FP16 */
+    int32_t fp16_scale_log2;  /* 0 .. 24 */
+    int32_t n[3];             /* nodes per axis; n[2] = 1 for D2Q9 */
+    int32_t periodic[3];      /* 1: periodic axis (lattice only; then no particles) */
+    double tau;               /* BGK relaxation time, > 1/2 (Eq. lbm2) */
+    double rho0;              /* fluid density in the buoyancy term (Eq. demgov) */
+    double gravity[3];        /* acceleration on particles */
+    double fluid_force[3];    /* uniform body force density on the fluid */
+    int32_t contact;          /* PIBM_CONTACT_* */
+    int32_t n_sub;            /* DEM sub-steps per lattice step, >= 1 */
+    double kn;                /* linear spring stiffness */
+    double restitution;       /* normal restitution of the linear spring-dashpot, (0, 1] */
+    double k_soft;            /* soft repulsion k_s (1 - r/r_c)^2 */
+    double skin;              /* candidate-list skin; max d + skin <= 2^bin_log2 */
+    int32_t two_way;          /* 1: spread the particle forces onto the fluid */
+    int32_t bin_log2;         /* bin edge in node spacings, 0 .. 3 */
+    int32_t max_candidates;   /* per-particle candidate capacity, 1 .. 64 */
+    int32_t reserved;         /* 0 */
+} pibm_config;
+
+typedef struct {
+    double mass;              /* sum over nodes and directions of f */
+    double momentum[3];       /* fluid sum f e plus particle sum m U */
+    double fluid_momentum[3];
+    double max_speed;         /* max over nodes of |u| */
+    int64_t nonfinite;        /* nodes with a NaN/Inf population */
+    int64_t active;           /* particles with a candidate neighbour or wall, last step */
+    int64_t candidates;       /* directed candidate entries, last step */
+    double min_height;        /* min over particles of the last coordinate */
+    double mean_height;       /* mean over particles of the last coordinate */
+} pibm_diag;
+
+typedef struct pibm_ctx pibm_ctx;
+
+/* Bytes of device workspace for this configuration and particle count. */
+size_t pibm_workspace_bytes(const pibm_config* cfg, int64_t n_particles);
+
+/* Validate cfg, carve the workspace (device pointer dev_ws, ws_bytes bytes),
+ * bind the HIP stream (hipStream_t, may be NULL for the default stream) and
+ * set the fluid to rest (f = w).  On success *out owns host bookkeeping only. */
+pibm_status pibm_create(const pibm_config* cfg, int64_t n_particles, void* dev_ws,
+                        size_t ws_bytes, void* hip_stream, pibm_ctx** out);
+void pibm_destroy(pibm_ctx* ctx);
+const char* pibm_last_error(const pibm_ctx* ctx);
+pibm_status pibm_set_stream(pibm_ctx* ctx, void* hip_stream);
+
+/* Fluid at equilibrium (Eq. lbm3) with density rho and velocity u (host
+ * arrays of N and D x N floats); NULL means rho = 1, u = 0. */
+pibm_status pibm_init_equilibrium(pibm_ctx* ctx, const float* rho, const float* u);
+
+/* Populations as deviations from the rest state, h_q = f_q - w_q, Q x N FP32
+ * host arrays in the direction order above.  Writing rounds to the storage
+ * format; reading is exact for both storage formats. */
+pibm_status pibm_write_populations(pibm_ctx* ctx, const float* h);
+pibm_status pibm_read_populations(pibm_ctx* ctx, float* h);
+
+/* Particles: positions x (D x N, strictly inside the box), velocities v
+ * (D x N), diameters d and densities rho_p (N), host FP64 arrays.
+ * Positions are kept as an unevaluated sum of two FP32 numbers (about 48
+ * significant bits), velocities, diameters and densities in FP32. */
+pibm_status pibm_set_particles(pibm_ctx* ctx, const double* x, const double* v,
+                               const double* d, const double* rho_p);
+/* Any output may be NULL.  f_hydro = -A_p mean(g) (Eq. lbm13) and
+ * f_contact = sub-step mean of the contact force, both of the last step. */
+pibm_status pibm_read_particles(pibm_ctx* ctx, double* x, double* v, double* f_hydro,
+                                double* f_contact);
+
+/* Density (N) and velocity u = j / rho (D x N) of the stored populations. */
+pibm_status pibm_read_fields(pibm_ctx* ctx, float* rho, float* u);
+/* Force field F (D x N) used by the last collision (spread + fluid_force). */
+pibm_status pibm_read_force(pibm_ctx* ctx, float* F);
+/* Cell list built at the start of the last step: per sorted slot the bin key
+ * and particle id (N each), and bin_start (n_bins + 1 entries); bins are
+ * x-fastest over ((n_a >> bin_log2) + 1) per axis, a particle's bin being
+ * (floor(X_a - 1/2) + 1) >> bin_log2.  Order: (key, id). */
+int64_t pibm_num_bins(const pibm_ctx* ctx);
+pibm_status pibm_read_cell_list(pibm_ctx* ctx, uint32_t* keys, int32_t* ids,
+                                int32_t* bin_start);
+
+/* Enqueue n_steps coupled steps on the context's stream (no host sync). */
+pibm_status pibm_step(pibm_ctx* ctx, int32_t n_steps);
+
+/* Phase timing.  With profiling on, pibm_step records HIP events on the
+ * context's stream between its phases; pibm_phase_times synchronises and
+ * returns the milliseconds spent in each phase (and the number of steps)
+ * since profiling was enabled or last read, then resets the sums.  Phases:
+ * 0 moments, 1 cell list, 2 interpolation, 3 DEM, 4 spreading, 5 collision
+ * and streaming.  Profiling adds 7 event records per step. */
+#define PIBM_NUM_PHASES 6
+pibm_status pibm_set_profiling(pibm_ctx* ctx, int enable);
+pibm_status pibm_phase_times(pibm_ctx* ctx, double* ms, int64_t* steps);
+
+/* Wait for the stream; return the first latched device error, if any. */
+pibm_status pibm_synchronize(pibm_ctx* ctx);
+
+/* FP64 totals (synchronising): fluid mass and total momentum
+ * (fluid sum f e + particle sum m U). */
+pibm_status pibm_conservation(pibm_ctx* ctx, double* mass, double* momentum);
+pibm_status pibm_diagnostics(pibm_ctx* ctx, pibm_diag* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIBM_H */

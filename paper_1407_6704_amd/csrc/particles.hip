@@ -1,0 +1,1264 @@
+// particles.hip -- particle side of the coupled step (gfx950, wave64).
+//
+// Cell list (the paper is silent on neighbour search): every particle gets
+// the bin of its dual cell floor(X - 1/2) (bins of 2^L dual cells per axis);
+// a counting sort over bins (one radix digit = the bin index) with integer
+// atomics gives the bin ranges, and the slot of each particle inside its bin
+// is its rank by id, so the order (bin, id) is unique and the result is
+// bit-identical from run to run.  The particle state is kept in that order.
+//
+// Interpolation (Eqs. lbm11-lbm12): 4^D support nodes per particle; one
+// group of 4^(D-1) lanes per particle, each lane one x-row of 4 nodes, a
+// float4 (drho, j) load per node and a shuffle reduction.
+//
+// DEM (Eq. demgov with the reaction force of Eq. lbm13 and the momentum
+// exchange of Eqs. lbm7-lbm8, g = 2 (rho_i U - j_i)): n_sub sub-steps with
+// the fluid moments frozen.  A particle with no neighbour and no wall within
+// contact distance + skin has a linear sub-step recurrence and takes its
+// closed form; the others are grouped into islands (connected components of
+// the candidate graph, union-find with integer CAS) packed into waves, and
+// iterate their sub-steps in LDS with one barrier per sub-step.
+//
+// Spreading (Eq. lbm10): gathered per node over the bins whose particles
+// can reach it, in (bin, id) order: deterministic, no float atomics.
+#include <algorithm>
+#include <utility>
+
+#include "pibm_internal.h"
+
+namespace pibm {
+
+__device__ __forceinline__ float particle_mass(int D, float d, float rp) {
+    return D == 3 ? rp * (PI_F / 6.0f) * d * d * d : rp * 0.25f * PI_F * d * d;
+}
+
+__device__ __forceinline__ int bin_of(const PCfg& c, float xh, float xl, int a) {
+    int ci = dual_cell(xh, xl);
+    int b = (ci + 1) >> c.L;
+    return min(max(b, 0), c.nb[a] - 1);
+}
+
+// ---------------------------------------------------------------------------
+// generic helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* p, long long n, uint32_t v) {
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// fill p[0 .. count*mult) where count is read on the device
+__global__ void k_fill_dyn(uint32_t* p, const uint32_t* count, int mult, uint32_t v, long long cap) {
+    long long n = (long long)(*count) * mult;
+    if (n > cap) n = cap;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        p[i] = v;
+}
+
+// Three-phase exclusive scan (u32 or u64).  Tile = 256 threads x 8 items.
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
+
+template <class T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T& total) {
+    // sh: 256 entries of LDS
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        T add = (t >= off) ? sh[t - off] : (T)0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    T incl = sh[t];
+    total = sh[255];
+    __syncthreads();
+    return incl - v;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_scan_reduce(const T* __restrict__ in, long long n, T* __restrict__ bsum) {
+    __shared__ T sh[256];
+    long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++)
+        if (base + k < n) s += in[base + k];
+    T tot;
+    block_exclusive_scan<T>(s, sh, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_scan_top(T* __restrict__ bsum, long long nb, T* __restrict__ total) {
+    __shared__ T sh[256];
+    T carry = 0;
+    for (long long c0 = 0; c0 < nb; c0 += 256) {
+        long long i = c0 + threadIdx.x;
+        T v = (i < nb) ? bsum[i] : (T)0;
+        T tot;
+        T ex = block_exclusive_scan<T>(v, sh, tot);
+        if (i < nb) bsum[i] = ex + carry;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_scan_down(const T* __restrict__ in, T* __restrict__ out, long long n,
+                                                   const T* __restrict__ bsum) {
+    __shared__ T sh[256];
+    long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    T v[SCAN_ITEMS];
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        v[k] = (base + k < n) ? in[base + k] : (T)0;
+        s += v[k];
+    }
+    T tot;
+    T ex = block_exclusive_scan<T>(s, sh, tot) + bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+}
+
+template <class T>
+void scan_exclusive(const T* in, T* out, long long n, T* bsum, T* total, hipStream_t s) {
+    long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL((k_scan_reduce<T>), dim3((unsigned)nb), dim3(256), 0, s, in, n, bsum);
+    hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(256), 0, s, bsum, nb, total);
+    hipLaunchKernelGGL((k_scan_down<T>), dim3((unsigned)nb), dim3(256), 0, s, in, out, n, bsum);
+}
+
+long long scan_blocks(long long n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+// ---------------------------------------------------------------------------
+// cell list
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_bin_count(PState A, int np, PCfg c, uint32_t* __restrict__ cnt,
+                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ slot,
+                                                   uint32_t* __restrict__ flags) {
+    int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= np) return;
+    int b[3] = {0, 0, 0};
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        float xh = A.xh[a][s], xl = A.xl[a][s];
+        inside = inside && (xh > 0.0f) && (xh < (float)c.n[a]) && isfinite(xh);
+        b[a] = bin_of(c, xh, xl, a);
+    }
+    if (!inside) atomicOr(flags, FLAG_UNSTABLE);
+    uint32_t key = (uint32_t)(((long long)b[2] * c.nb[1] + b[1]) * c.nb[0] + b[0]);
+    keys[s] = key;
+    slot[s] = atomicAdd(&cnt[key], 1u);
+}
+
+__global__ void k_scatter(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ slot,
+                          const uint32_t* __restrict__ start, uint32_t* __restrict__ tmp, int np) {
+    int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= np) return;
+    tmp[start[keys[s]] + slot[s]] = s;
+}
+
+// Final slot = bin start + rank of the particle's id among its bin.
+template <int D>
+__global__ __launch_bounds__(256) void k_reorder(PState A, PState B, const uint32_t* __restrict__ keys,
+                                                 const uint32_t* __restrict__ start,
+                                                 const uint32_t* __restrict__ tmp,
+                                                 uint32_t* __restrict__ keys_sorted, int np) {
+    int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= np) return;
+    uint32_t k = keys[s];
+    uint32_t b0 = start[k], b1 = start[k + 1];
+    int myid = A.id[s];
+    uint32_t rank = 0;
+    for (uint32_t t = b0; t < b1; t++) rank += (A.id[tmp[t]] < myid) ? 1u : 0u;
+    uint32_t o = b0 + rank;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        B.xh[a][o] = A.xh[a][s];
+        B.xl[a][o] = A.xl[a][s];
+        B.u[a][o] = A.u[a][s];
+    }
+    B.d[o] = A.d[s];
+    B.rp[o] = A.rp[s];
+    B.id[o] = myid;
+    keys_sorted[o] = k;
+}
+
+// ---------------------------------------------------------------------------
+// interpolation (O2 + O3): weights phi_k = delta(X - (i + 1/2)) of the four
+// nodes i = floor(X - 1/2) - 1 + k, zero outside the domain, divided by
+// their sum.  With fr = X - 1/2 - floor(X - 1/2) the four cosines are
+// -sin, cos, sin, -cos of (pi fr / 2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void axis_weights(float xh, float xl, int n, int& base, float* phi) {
+    int c = dual_cell(xh, xl);
+    float fr = dual_frac(xh, xl, c);
+    float sv, cv;
+    sincospif(0.5f * fr, &sv, &cv);
+    base = c - 1;
+    float w0 = 0.25f * (1.0f - sv), w1 = 0.25f * (1.0f + cv), w2 = 0.25f * (1.0f + sv), w3 = 0.25f * (1.0f - cv);
+    if (base < 0 || base >= n) w0 = 0.f;
+    if (base + 1 < 0 || base + 1 >= n) w1 = 0.f;
+    if (base + 2 < 0 || base + 2 >= n) w2 = 0.f;
+    if (base + 3 < 0 || base + 3 >= n) w3 = 0.f;
+    float sum = w0 + w1 + w2 + w3;
+    float inv = sum > 0.f ? 1.0f / sum : 0.f;
+    phi[0] = w0 * inv; phi[1] = w1 * inv; phi[2] = w2 * inv; phi[3] = w3 * inv;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const float4* __restrict__ mom,
+                                                float* __restrict__ drho_i, float* __restrict__ j_i,
+                                                short4* __restrict__ wbase, float* __restrict__ wphi) {
+    constexpr int LP = (D == 3) ? 16 : 4;   // lanes per particle
+    long long gt = (long long)blockIdx.x * 256 + threadIdx.x;
+    int s = (int)(gt / LP);
+    int l = (int)(gt % LP);
+    bool valid = s < np;
+    int sc = valid ? s : np - 1;
+    int base[3] = {0, 0, 0};
+    float phi[3][4];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (a < D) axis_weights(A.xh[a][sc], A.xl[a][sc], g.n[a], base[a], phi[a]);
+        else { phi[a][0] = 1.f; phi[a][1] = phi[a][2] = phi[a][3] = 0.f; }
+    }
+    int ky = l & 3, kz = (D == 3) ? (l >> 2) : 0;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (valid) {
+        int y = base[1] + ky, z = base[2] + kz;
+        float wyz = phi[1][ky] * phi[2][kz];
+        if (wyz != 0.f) {
+            long long row = ((long long)z * g.n[1] + y) * g.n[0];
+#pragma unroll
+            for (int kx = 0; kx < 4; kx++) {
+                float W = phi[0][kx] * phi[1][ky] * phi[2][kz];
+                if (W != 0.f) {
+                    float4 m = mom[row + base[0] + kx];
+                    acc[0] += W * m.x; acc[1] += W * m.y; acc[2] += W * m.z; acc[3] += W * m.w;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < LP; off <<= 1)
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc[k] += __shfl_xor(acc[k], off, LP);
+    if (!valid) return;
+    if (l == 0) {
+        drho_i[s] = acc[0];
+        j_i[s] = acc[1];
+        j_i[(long long)np + s] = acc[2];
+        if (D == 3) j_i[2LL * np + s] = acc[3];
+        wbase[s] = make_short4((short)base[0], (short)base[1], (short)base[2], 0);
+    }
+    // weights for the spreading pass: 4 D floats per particle
+    if (D == 3) {
+        if (l < 12) wphi[(long long)s * 12 + l] = phi[l >> 2][l & 3];
+    } else {
+        wphi[(long long)s * 8 + l] = phi[0][l];
+        wphi[(long long)s * 8 + 4 + l] = phi[1][l];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// DEM: classification and the free-particle closed form
+// ---------------------------------------------------------------------------
+// Neighbour scan over the 3^D bins around particle s.  Counting mode: the
+// number of candidates within (d_s + d_t)/2 + skin, and whether any lies
+// within (d_s + d_t)/2 + thr.  Collect mode: the candidates that are active,
+// in scan order (bins ascending, sorted order within a bin).
+template <int D, bool COLLECT>
+__device__ __forceinline__ int scan_neighbours(const PState& A, const uint32_t* __restrict__ start, const PCfg& c,
+                                               int s, float thr, bool& close,
+                                               const unsigned long long* __restrict__ actcc, uint32_t* list,
+                                               int cap) {
+    float xh[3] = {0, 0, 0}, xl[3] = {0, 0, 0};
+    int b[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        xh[a] = A.xh[a][s];
+        xl[a] = A.xl[a][s];
+        b[a] = bin_of(c, xh[a], xl[a], a);
+    }
+    float ds = A.d[s];
+    int cnt = 0;
+    int zl = (D == 3) ? max(b[2] - 1, 0) : 0, zh = (D == 3) ? min(b[2] + 1, c.nb[2] - 1) : 0;
+    for (int bz = zl; bz <= zh; bz++)
+        for (int by = max(b[1] - 1, 0); by <= min(b[1] + 1, c.nb[1] - 1); by++) {
+            // bins of one row are contiguous in the sorted order
+            int bxl = max(b[0] - 1, 0), bxh = min(b[0] + 1, c.nb[0] - 1);
+            uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
+            uint32_t t0 = start[row + bxl], t1 = start[row + bxh + 1];
+            for (uint32_t t = t0; t < t1; t++) {
+                if ((int)t == s) continue;
+                float r2 = 0.f;
+#pragma unroll
+                for (int a = 0; a < D; a++) {
+                    float dx = (xh[a] - A.xh[a][t]) + (xl[a] - A.xl[a][t]);
+                    r2 += dx * dx;
+                }
+                float rc = 0.5f * (ds + A.d[t]);
+                float cut = rc + c.skin;
+                if (r2 < cut * cut) {
+                    if (!COLLECT) {
+                        cnt++;
+                        float lim = rc + thr;
+                        if (r2 <= lim * lim) close = true;
+                    } else if (actcc[t] != 0ULL) {
+                        if (cnt < cap) list[cnt] = t;
+                        cnt++;
+                    }
+                }
+            }
+        }
+    return cnt;
+}
+
+// Classification and the free-particle closed form.  With the fluid moments
+// frozen and no contact force, the sub-step recurrence
+//   U^{k+1} = U^k + h [cc (u* - U^k) + a],  cc = 2 A_p rho_i / m,  u* = j_i / rho_i
+// has the solution U^k = U_eq + (U^0 - U_eq) q^k, q = 1 - h cc.  The free
+// path then stays within B = max(|U^0|, |U^n|) (|U^k| is convex along the
+// segment), and every particle moves at most skin/2 (else E_SKIN).  So a
+// particle is provably free when every neighbour gap exceeds B + skin/2 and
+// every wall gap exceeds B; the others are active and run the sub-steps.
+template <int D>
+__global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, PCfg c,
+                                                  const uint32_t* __restrict__ start,
+                                                  const float* __restrict__ drho_i, const float* __restrict__ j_i,
+                                                  float* __restrict__ coef, float* __restrict__ fc,
+                                                  unsigned long long* __restrict__ actcc,
+                                                  uint32_t* __restrict__ flags) {
+    int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= np) return;
+    float d = A.d[s], rp = A.rp[s];
+    float m = particle_mass(D, d, rp);
+    float Ap = 0.25f * PI_F * d * d;
+    float ri = 1.0f + drho_i[s];
+    float cc = 2.0f * Ap * ri / m;
+    float hc = cc * c.h;
+    if (!(hc < 1.0f)) atomicOr(flags, FLAG_UNSTABLE);
+    float lq = log1pf(-hc);
+    float nl = (float)c.n_sub * lq;
+    float qn = expf(nl);
+    float omq = -expm1f(nl);             // 1 - q^n
+    float geo = omq / hc;                // sum_{k<n} q^k
+    float q = 1.0f - hc;
+    float bw = 1.0f - c.rho0 / rp;
+    float v0s = 0.f, vns = 0.f;
+    float un[3], dx[3], gb[3];
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        float ja = j_i[(long long)a * np + s];
+        float ustar = ja / ri;
+        float slip = bw * c.g[a] / cc;   // U_eq - u*
+        float ueq = ustar + slip;
+        float u0 = A.u[a][s];
+        un[a] = ueq + (u0 - ueq) * qn;
+        dx[a] = ueq + (u0 - ueq) * (c.h * q * geo);
+        gb[a] = 2.0f * ri * (slip + (u0 - ueq) * (geo * c.h));
+        v0s += u0 * u0;
+        vns += un[a] * un[a];
+    }
+    float B = sqrtf(fmaxf(v0s, vns));
+    if (c.contact != PIBM_CONTACT_NONE) {
+        bool close = false;
+        int cnt = scan_neighbours<D, false>(A, start, c, s, B + 0.5f * c.skin, close, nullptr, nullptr, 0);
+        bool wall = false;
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            float x = A.xh[a][s] + A.xl[a][s];
+            wall = wall || (x - 0.5f * d <= B) || (((float)c.n[a] - x) - 0.5f * d <= B);
+        }
+        if (close || wall) {
+            if (cnt > c.maxc) atomicOr(flags, FLAG_CAPACITY);
+            actcc[s] = (1ULL << 32) | (unsigned long long)min(cnt, c.maxc);
+            return;
+        }
+    }
+    actcc[s] = 0ULL;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        float xh = A.xh[a][s], xl = A.xl[a][s];
+        df_add(xh, xl, dx[a]);
+        Bn.xh[a][s] = xh;
+        Bn.xl[a][s] = xl;
+        Bn.u[a][s] = un[a];
+        coef[(long long)a * np + s] = Ap * gb[a];
+        fc[(long long)a * np + s] = 0.f;
+    }
+    if (B > 0.5f * c.skin) atomicOr(flags, FLAG_SKIN);
+}
+
+// active particles: compact index, candidate list (active partners only; a
+// free partner provably never touches), union-find init
+template <int D>
+__global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const uint32_t* __restrict__ start,
+                                                 const unsigned long long* __restrict__ actcc,
+                                                 const unsigned long long* __restrict__ prefix,
+                                                 uint32_t* __restrict__ alist, uint32_t* __restrict__ aidx,
+                                                 uint32_t* __restrict__ cand, uint32_t* __restrict__ ccount,
+                                                 uint32_t* __restrict__ parent) {
+    int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= np) return;
+    unsigned long long v = actcc[s];
+    if (v == 0ULL) return;
+    unsigned long long p = prefix[s];
+    uint32_t a = (uint32_t)(p >> 32), off = (uint32_t)(p & 0xffffffffULL);
+    int cap = (int)(v & 0xffffffffULL);
+    alist[a] = s;
+    aidx[s] = a;
+    parent[a] = a;
+    bool dummy = false;
+    int n = cap > 0 ? scan_neighbours<D, true>(A, start, c, s, 0.f, dummy, actcc, cand + off, cap) : 0;
+    ccount[s] = (uint32_t)min(n, cap);
+}
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x) {
+    uint32_t p = __atomic_load_n(&parent[x], __ATOMIC_RELAXED);
+    while (p != x) {
+        x = p;
+        p = __atomic_load_n(&parent[x], __ATOMIC_RELAXED);
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_uf_hook(const uint32_t* __restrict__ alist,
+                                                 const uint32_t* __restrict__ ccount,
+                                                 const unsigned long long* __restrict__ prefix,
+                                                 const uint32_t* __restrict__ cand, const uint32_t* __restrict__ aidx,
+                                                 uint32_t* parent, const uint32_t* __restrict__ counters) {
+    uint32_t na = counters[CNT_ACTIVE];
+    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
+        uint32_t s = alist[a];
+        uint32_t off = (uint32_t)(prefix[s] & 0xffffffffULL);
+        int cnt = (int)ccount[s];
+        for (int k = 0; k < cnt; k++) {
+            uint32_t b = aidx[cand[off + k]];
+            if (b <= a) continue;
+            while (true) {
+                uint32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+                if (ra == rb) break;
+                if (ra > rb) { uint32_t t = ra; ra = rb; rb = t; }
+                if (atomicCAS(&parent[rb], rb, ra) == rb) break;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_uf_flatten(uint32_t* parent, uint32_t* __restrict__ isize,
+                                                    const uint32_t* __restrict__ counters) {
+    uint32_t na = counters[CNT_ACTIVE];
+    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
+        uint32_t r = uf_find(parent, a);
+        parent[a] = r;
+        atomicAdd(&isize[r], 1u);
+    }
+}
+
+// islands by size class: 1..64 packed into waves, 65 = larger than a wave
+__global__ __launch_bounds__(256) void k_island_class(const uint32_t* __restrict__ parent,
+                                                      const uint32_t* __restrict__ isize, uint32_t* __restrict__ irank,
+                                                      uint32_t* __restrict__ bigroot, uint32_t* counters) {
+    uint32_t na = counters[CNT_ACTIVE];
+    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
+        if (parent[a] != a) continue;
+        uint32_t sz = isize[a];
+        uint32_t cls = sz <= WAVE ? sz : WAVE + 1;
+        uint32_t r = atomicAdd(&counters[CNT_CLASS + cls], 1u);
+        irank[a] = r;
+        if (cls == WAVE + 1) bigroot[r] = a;
+    }
+}
+
+__global__ void k_island_plan(uint32_t* counters, const uint32_t* __restrict__ isize,
+                              const uint32_t* __restrict__ bigroot, uint32_t* __restrict__ bigoff) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t waves = 0;
+    for (int s = 1; s <= WAVE; s++) {
+        counters[CNT_WAVEBASE + s] = waves;
+        uint32_t per = WAVE / s;
+        waves += (counters[CNT_CLASS + s] + per - 1) / per;
+    }
+    counters[CNT_WAVES] = waves;
+    uint32_t nbig = counters[CNT_CLASS + WAVE + 1];
+    counters[CNT_BIG] = nbig;
+    uint32_t off = 0;
+    for (uint32_t k = 0; k < nbig; k++) {
+        bigoff[k] = off;
+        off += isize[bigroot[k]];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_island_place(const uint32_t* __restrict__ parent,
+                                                      const uint32_t* __restrict__ isize,
+                                                      const uint32_t* __restrict__ irank, uint32_t* __restrict__ fill,
+                                                      int* __restrict__ lanemember, uint32_t* __restrict__ loc,
+                                                      const uint32_t* __restrict__ bigoff,
+                                                      uint32_t* __restrict__ bigmember,
+                                                      const uint32_t* __restrict__ counters) {
+    uint32_t na = counters[CNT_ACTIVE];
+    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
+        uint32_t r = parent[a];
+        uint32_t pos = atomicAdd(&fill[r], 1u);
+        uint32_t sz = isize[r];
+        if (sz <= WAVE) {
+            uint32_t per = WAVE / sz;
+            uint32_t w = counters[CNT_WAVEBASE + sz] + irank[r] / per;
+            uint32_t lane = (irank[r] % per) * sz + pos;
+            lanemember[(long long)w * WAVE + lane] = (int)a;
+            loc[a] = lane;
+        } else {
+            bigmember[bigoff[irank[r]] + pos] = a;
+            loc[a] = a;
+        }
+    }
+}
+
+// Candidate constants for the sub-steps.  K0 = r_c^2 - |r0|^2 is formed in
+// double-float so that overlaps far below the FP32 spacing of positions
+// (1e-9 .. 1e-6 for stiff springs and slow particles) stay resolved.
+template <int D>
+__global__ __launch_bounds__(256) void k_cand_prep(PState A, PCfg c, const uint32_t* __restrict__ alist,
+                                                   const uint32_t* __restrict__ ccount,
+                                                   const unsigned long long* __restrict__ prefix,
+                                                   const uint32_t* __restrict__ cand, const uint32_t* __restrict__ aidx,
+                                                   const uint32_t* __restrict__ loc, CandData* __restrict__ cdata,
+                                                   const uint32_t* __restrict__ counters) {
+    uint32_t na = counters[CNT_ACTIVE];
+    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
+        uint32_t s = alist[a];
+        uint32_t off = (uint32_t)(prefix[s] & 0xffffffffULL);
+        int cnt = (int)ccount[s];
+        float ms = particle_mass(D, A.d[s], A.rp[s]);
+        for (int k = 0; k < cnt; k++) {
+            uint32_t t = cand[off + k];
+            CandData cd;
+            cd.local = (int)loc[aidx[t]];
+            // r0 = X_s - X_t in double-float, |r0|^2 in double-float
+            float sh = 0.f, sl = 0.f;
+            float r0[3] = {0, 0, 0};
+#pragma unroll
+            for (int ax = 0; ax < D; ax++) {
+                float hi, e;
+                two_sum(A.xh[ax][s], -A.xh[ax][t], hi, e);
+                float lo = e + (A.xl[ax][s] - A.xl[ax][t]);
+                float rh, rl;
+                fast_two_sum(hi, lo, rh, rl);
+                r0[ax] = rh;
+                // (rh + rl)^2 = rh^2 + 2 rh rl (+ rl^2, negligible)
+                float p = rh * rh;
+                float pe = fmaf(rh, rh, -p);
+                pe = fmaf(2.0f * rh, rl, pe);
+                float ns, ne;
+                two_sum(sh, p, ns, ne);
+                sl += ne + pe;
+                sh = ns;
+            }
+            // r_c = (d_s + d_t)/2 exactly as a double-float, then r_c^2
+            float dsum, derr;
+            two_sum(A.d[s], A.d[t], dsum, derr);
+            float rch = 0.5f * dsum, rcl = 0.5f * derr;
+            float q = rch * rch;
+            float qe = fmaf(rch, rch, -q);
+            qe = fmaf(2.0f * rch, rcl, qe);
+            // K0 = (q + qe) - (sh + sl)
+            float k0h, k0e;
+            two_sum(q, -sh, k0h, k0e);
+            cd.K0 = k0h + (k0e + (qe - sl));
+            cd.rc = rch;
+            cd.r0[0] = r0[0]; cd.r0[1] = r0[1]; cd.r0[2] = r0[2];
+            float mt = particle_mass(D, A.d[t], A.rp[t]);
+            float meff = ms * mt / (ms + mt);
+            cd.gam = 2.0f * c.zeta * sqrtf(c.kn * meff);
+            cdata[off + k] = cd;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Active sub-steps.  Jacobi: every force of sub-step k uses the state at k.
+// ---------------------------------------------------------------------------
+template <int D>
+struct Active {
+    float xh[3], xl[3];     // start-of-step position
+    float dx[3], cdx[3];    // displacement in the step and its compensation
+    float u[3], cu[3];      // velocity and its compensation
+    float ri, j[3];
+    float m, Ap, bw[3], d, gw;
+    float gs[3], fs[3];     // sums of g and of the contact force
+    float vmax2;
+    uint32_t off;
+    int cnt;
+    bool wall;              // a wall lies within contact distance + skin
+    // contact-free closed form: U_eq = u* + slip, q = 1 - hc
+    float ueq[3], slip[3], hc, lq, veq;
+};
+
+template <int D>
+__device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const PCfg& c, uint32_t s,
+                                            const float* drho_i, const float* j_i, int np,
+                                            const uint32_t* ccount, const unsigned long long* prefix) {
+    P.d = A.d[s];
+    float rp = A.rp[s];
+    P.m = particle_mass(D, P.d, rp);
+    P.Ap = 0.25f * PI_F * P.d * P.d;
+    P.ri = 1.0f + drho_i[s];
+    P.gw = 2.0f * c.zeta * sqrtf(c.kn * P.m);
+    float v2 = 0.f;
+    bool wall = false;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        bool on = a < D;
+        P.xh[a] = on ? A.xh[a][s] : 0.f;
+        P.xl[a] = on ? A.xl[a][s] : 0.f;
+        P.u[a] = on ? A.u[a][s] : 0.f;
+        P.j[a] = on ? j_i[(long long)a * np + s] : 0.f;
+        P.bw[a] = on ? (1.0f - c.rho0 / rp) * c.g[a] : 0.f;
+        P.dx[a] = P.cdx[a] = P.cu[a] = 0.f;
+        P.gs[a] = P.fs[a] = 0.f;
+        v2 += P.u[a] * P.u[a];
+        if (on) {
+            float x = P.xh[a] + P.xl[a];
+            wall = wall || (x - 0.5f * P.d < c.skin) || (((float)c.n[a] - x) - 0.5f * P.d < c.skin);
+        }
+    }
+    // a wall farther than skin cannot be reached (displacement <= skin/2)
+    P.wall = wall && c.contact != PIBM_CONTACT_NONE;
+    const float cc = 2.0f * P.Ap * P.ri / P.m;
+    P.hc = cc * c.h;
+    P.lq = log1pf(-P.hc);
+    float ve = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        P.slip[a] = P.bw[a] / cc;
+        P.ueq[a] = (a < D ? P.j[a] / P.ri : 0.f) + P.slip[a];
+        ve += P.ueq[a] * P.ueq[a];
+    }
+    P.veq = sqrtf(ve);
+    P.vmax2 = v2;
+    P.off = (uint32_t)(prefix[s] & 0xffffffffULL);
+    P.cnt = c.contact != PIBM_CONTACT_NONE ? (int)ccount[s] : 0;
+}
+
+template <int D>
+__device__ __forceinline__ void wall_force(const Active<D>& P, const PCfg& c, float* F) {
+    const float rc = 0.5f * P.d;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        // lower wall at 0: overlap = d/2 - X; upper wall at n: d/2 - (n - X)
+        float dlo = ((rc - P.xh[a]) - P.xl[a]) - P.dx[a];
+        float dhi = ((rc - ((float)c.n[a] - P.xh[a])) + P.xl[a]) + P.dx[a];
+        if (c.contact == PIBM_CONTACT_LSD) {
+            if (dlo > 0.f) F[a] += c.kn * dlo - P.gw * P.u[a];
+            if (dhi > 0.f) F[a] -= c.kn * dhi + P.gw * P.u[a];
+        } else {
+            if (dlo > 0.f) { float q = dlo / rc; F[a] += c.ks * q * q; }
+            if (dhi > 0.f) { float q = dhi / rc; F[a] -= c.ks * q * q; }
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& cd, const float* odx,
+                                           const float* ou, const PCfg& c, float* F) {
+    float del[3] = {0, 0, 0}, r[3] = {0, 0, 0};
+    float rd = 0.f, dd = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        del[a] = P.dx[a] - odx[a];
+        r[a] = cd.r0[a] + del[a];
+        rd += cd.r0[a] * del[a];
+        dd += del[a] * del[a];
+    }
+    float num = cd.K0 - (2.0f * rd + dd);        // r_c^2 - |r|^2
+    if (!(num > 0.f)) return;
+    float r2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) r2 += r[a] * r[a];
+    float dist = sqrtf(r2);
+    float delta = num / (cd.rc + dist);          // r_c - |r|
+    float inv = 1.0f / dist;
+    if (c.contact == PIBM_CONTACT_LSD) {
+        float vn = 0.f;
+#pragma unroll
+        for (int a = 0; a < D; a++) vn += (P.u[a] - ou[a]) * (r[a] * inv);
+        float mag = c.kn * delta - cd.gam * vn;
+#pragma unroll
+        for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
+    } else {
+        float q = delta / cd.rc;
+        float mag = c.ks * q * q;
+#pragma unroll
+        for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
+    }
+}
+
+// One sub-step for particle P.  Partner states are read through arrays
+// (sdx, su) of stride `stride` indexed by the candidate's local index; the
+// first nfirst candidates come from `first` (an LDS copy), the rest from
+// `rest` (global).
+template <int D>
+__device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, const CandData* first, int nfirst,
+                                               const CandData* __restrict__ rest, const float* sdx,
+                                               const float* su, int stride) {
+    float F[3] = {0.f, 0.f, 0.f};
+    if (P.wall) wall_force<D>(P, c, F);
+    const int n1 = min(P.cnt, nfirst);
+    for (int k = 0; k < P.cnt; k++) {
+        CandData cd = (k < n1) ? first[k] : rest[k];
+        float odx[3] = {0, 0, 0}, ou[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            odx[a] = sdx[a * stride + cd.local];
+            ou[a] = su[a * stride + cd.local];
+        }
+        pair_force<D>(P, cd, odx, ou, c, F);
+    }
+    float v2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        float g = 2.0f * (P.ri * P.u[a] - P.j[a]);
+        P.gs[a] += g;
+        P.fs[a] += F[a];
+        float incr = c.h * ((-P.Ap * g + F[a]) / P.m + P.bw[a]);
+        // compensated sums keep the many tiny increments exact to FP32
+        float y = incr - P.cu[a];
+        float t = P.u[a] + y;
+        P.cu[a] = (t - P.u[a]) - y;
+        P.u[a] = t;
+        float yx = c.h * P.u[a] - P.cdx[a];
+        float tx = P.dx[a] + yx;
+        P.cdx[a] = (tx - P.dx[a]) - yx;
+        P.dx[a] = tx;
+        v2 += P.u[a] * P.u[a];
+    }
+    P.vmax2 = fmaxf(P.vmax2, v2);
+}
+
+template <int D>
+__device__ __forceinline__ void active_store(const Active<D>& P, PState& Bn, const PCfg& c, uint32_t s, int np,
+                                             float* coef, float* fc, uint32_t* flags) {
+    float invn = 1.0f / (float)c.n_sub;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        float xh = P.xh[a], xl = P.xl[a];
+        df_add(xh, xl, P.dx[a]);
+        Bn.xh[a][s] = xh;
+        Bn.xl[a][s] = xl;
+        Bn.u[a][s] = P.u[a];
+        coef[(long long)a * np + s] = P.Ap * (P.gs[a] * invn);
+        fc[(long long)a * np + s] = P.fs[a] * invn;
+    }
+    if (sqrtf(P.vmax2) > 0.5f * c.skin) atomicOr(flags, FLAG_SKIN);
+}
+
+constexpr int CAND_LDS = 8;   // candidates per lane cached in LDS
+
+// Number of sub-steps (<= remaining) that particle P can advance with no
+// contact: along a contact-free stretch U^{k+i} is a convex combination of
+// U^k and U_eq, so every particle moves at most V = max(|U^k|, |U_eq|) per
+// unit time, and a gap g closes by at most (V_p + V_q) i h after i sub-steps.
+template <int D>
+__device__ __forceinline__ int free_allowance(const Active<D>& P, const PCfg& c, const CandData* first, int nfirst,
+                                              const CandData* __restrict__ rest, const float* sdx, const float* su,
+                                              const float* sveq, int stride, int remaining) {
+    float u2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        float ut = P.u[a] - P.cu[a];
+        u2 += ut * ut;
+    }
+    const float V = fmaxf(sqrtf(u2), P.veq) * (1.0f + 1e-5f) + 1e-30f;
+    float allow = (float)remaining;
+    const float rc = 0.5f * P.d;
+    if (P.wall) {
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            float glo = P.dx[a] - ((rc - P.xh[a]) - P.xl[a]);
+            float ghi = -(((rc - ((float)c.n[a] - P.xh[a])) + P.xl[a]) + P.dx[a]);
+            allow = fminf(allow, fminf(glo, ghi) / (V * c.h));
+        }
+    }
+    const int n1 = min(P.cnt, nfirst);
+    for (int k = 0; k < P.cnt; k++) {
+        CandData cd = (k < n1) ? first[k] : rest[k];
+        float rd = 0.f, dd = 0.f, r2 = 0.f, ou2 = 0.f;
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            float del = P.dx[a] - sdx[a * stride + cd.local];
+            float r = cd.r0[a] + del;
+            rd += cd.r0[a] * del;
+            dd += del * del;
+            r2 += r * r;
+            float uo = su[a * stride + cd.local];
+            ou2 += uo * uo;
+        }
+        float num = cd.K0 - (2.0f * rd + dd);             // r_c^2 - |r|^2
+        float gap = -num / (cd.rc + sqrtf(r2));          // |r| - r_c
+        float Vt = fmaxf(sqrtf(ou2), sveq[cd.local]) * (1.0f + 1e-5f);
+        allow = fminf(allow, (gap * (1.0f - 1e-5f)) / ((V + Vt) * c.h));
+    }
+    if (!(allow > 0.f)) return 0;
+    return allow >= (float)remaining ? remaining : (int)allow;
+}
+
+// Advance P by m contact-free sub-steps in closed form:
+//   U^{k+m} = U_eq + (U^k - U_eq) q^m,  sum_{i=1..m} U^{k+i} = m U_eq + (U^k - U_eq) q S,
+//   sum_{i<m} g^{k+i} = 2 rho_i (m slip + (U^k - U_eq) S),  S = (1 - q^m)/(1 - q).
+template <int D>
+__device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m) {
+    const float mm = (float)m;
+    const float lqm = mm * P.lq;
+    const float qm = expf(lqm);
+    const float S = -expm1f(lqm) / P.hc;
+    const float q = 1.0f - P.hc;
+    float v2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        const float diff = (P.u[a] - P.ueq[a]) - P.cu[a];
+        const float incx = c.h * (mm * P.ueq[a] + diff * (q * S));
+        float yx = incx - P.cdx[a];
+        float tx = P.dx[a] + yx;
+        P.cdx[a] = (tx - P.dx[a]) - yx;
+        P.dx[a] = tx;
+        P.gs[a] += 2.0f * P.ri * (mm * P.slip[a] + diff * S);
+        P.u[a] = P.ueq[a] + diff * qm;
+        P.cu[a] = 0.f;
+        v2 += P.u[a] * P.u[a];
+    }
+    P.vmax2 = fmaxf(P.vmax2, v2);
+}
+
+// Small islands: one 64-lane workgroup per packed wave, states in LDS.  A
+// wave holds islands of one size s at lanes [i s, (i+1) s).  Each island
+// advances on its own clock: per iteration it either jumps over a
+// contact-free stretch (all of its members agree on the shortest allowance)
+// or takes one Jacobi sub-step; so the result of an island does not depend
+// on which other islands share its wave.
+template <int D>
+__global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np, PCfg c,
+                                                     const int* __restrict__ lanemember,
+                                                     const uint32_t* __restrict__ alist,
+                                                     const uint32_t* __restrict__ ccount,
+                                                     const unsigned long long* __restrict__ prefix,
+                                                     const uint32_t* __restrict__ parent,
+                                                     const uint32_t* __restrict__ isize,
+                                                     const CandData* __restrict__ cdata,
+                                                     const float* __restrict__ drho_i, const float* __restrict__ j_i,
+                                                     float* __restrict__ coef, float* __restrict__ fc,
+                                                     uint32_t* __restrict__ flags,
+                                                     const uint32_t* __restrict__ counters) {
+    __shared__ float sdx[2][3 * WAVE];
+    __shared__ float su[2][3 * WAVE];
+    __shared__ float sveq[WAVE];
+    __shared__ int sallow[WAVE];
+    __shared__ CandData scd[WAVE * CAND_LDS];
+    const uint32_t nw = counters[CNT_WAVES];
+    const int lane = threadIdx.x;
+    for (uint32_t w = blockIdx.x; w < nw; w += gridDim.x) {
+        int a = lanemember[(long long)w * WAVE + lane];
+        bool valid = a >= 0;
+        uint32_t s = valid ? alist[a] : 0;
+        Active<D> P;
+        int nfirst = 0, isz = 1;
+        if (valid) {
+            active_load<D>(P, A, c, s, drho_i, j_i, np, ccount, prefix);
+            nfirst = min(P.cnt, CAND_LDS);
+            for (int k = 0; k < nfirst; k++) scd[lane * CAND_LDS + k] = cdata[P.off + k];
+            isz = (int)isize[parent[a]];
+        }
+        const int ibase = (lane / isz) * isz;
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++) {
+            sdx[0][ax * WAVE + lane] = 0.f;
+            su[0][ax * WAVE + lane] = valid ? P.u[ax] : 0.f;
+        }
+        sveq[lane] = valid ? P.veq : 0.f;
+        __syncthreads();
+        const CandData* rest = cdata + (valid ? P.off : 0);
+        int k = 0, cur = 0;
+        while (__any(valid && k < c.n_sub)) {
+            const bool more = valid && k < c.n_sub;
+            int allow = 0;
+            if (more)
+                allow = free_allowance<D>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur], sveq, WAVE,
+                                          c.n_sub - k);
+            sallow[lane] = allow;
+            __syncthreads();
+            int m = allow;
+            for (int i = 0; i < isz; i++) m = min(m, sallow[ibase + i]);
+            if (more) {
+                if (m >= 2) {
+                    active_jump<D>(P, c, m);
+                    k += m;
+                } else {
+                    active_substep<D>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur], WAVE);
+                    k += 1;
+                }
+            }
+#pragma unroll
+            for (int ax = 0; ax < 3; ax++) {
+                sdx[cur ^ 1][ax * WAVE + lane] = valid ? P.dx[ax] : 0.f;
+                su[cur ^ 1][ax * WAVE + lane] = valid ? P.u[ax] : 0.f;
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        if (valid) active_store<D>(P, Bn, c, s, np, coef, fc, flags);
+        __syncthreads();
+    }
+}
+
+// Islands larger than a wave: one 256-lane workgroup per island, states in
+// global scratch indexed by the active index (gdx, gu: [2][3][cap]; the
+// compensations and running sums follow gdx at 6 cap .. 19 cap).
+template <int D>
+__global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np, PCfg c,
+                                                    const uint32_t* __restrict__ bigmember,
+                                                    const uint32_t* __restrict__ bigoff,
+                                                    const uint32_t* __restrict__ bigroot,
+                                                    const uint32_t* __restrict__ isize,
+                                                    const uint32_t* __restrict__ alist,
+                                                    const uint32_t* __restrict__ ccount,
+                                                    const unsigned long long* __restrict__ prefix,
+                                                    const CandData* __restrict__ cdata,
+                                                    const float* __restrict__ drho_i, const float* __restrict__ j_i,
+                                                    float* __restrict__ coef, float* __restrict__ fc,
+                                                    float* gdx, float* gu, long long cap,
+                                                    uint32_t* __restrict__ flags,
+                                                    const uint32_t* __restrict__ counters) {
+    const uint32_t nbig = counters[CNT_BIG];
+    for (uint32_t ib = blockIdx.x; ib < nbig; ib += gridDim.x) {
+        uint32_t base = bigoff[ib];
+        uint32_t sz = isize[bigroot[ib]];
+        for (uint32_t i = threadIdx.x; i < sz; i += 256) {
+            uint32_t a = bigmember[base + i];
+            uint32_t s = alist[a];
+#pragma unroll
+            for (int ax = 0; ax < 3; ax++) {
+                gdx[(0 * 3 + ax) * cap + a] = 0.f;
+                gu[(0 * 3 + ax) * cap + a] = ax < D ? A.u[ax][s] : 0.f;
+            }
+        }
+        __syncthreads();
+        // per-member state is re-read from scratch each sub-step (a lane may own several members)
+        for (int k = 0; k < c.n_sub; k++) {
+            int cur = k & 1;
+            for (uint32_t i = threadIdx.x; i < sz; i += 256) {
+                uint32_t a = bigmember[base + i];
+                uint32_t s = alist[a];
+                Active<D> P;
+                active_load<D>(P, A, c, s, drho_i, j_i, np, ccount, prefix);
+#pragma unroll
+                for (int ax = 0; ax < D; ax++) {
+                    P.dx[ax] = gdx[(cur * 3 + ax) * cap + a];
+                    P.u[ax] = gu[(cur * 3 + ax) * cap + a];
+                }
+                float* aux = gdx + 6 * cap;
+                if (k > 0) {
+#pragma unroll
+                    for (int ax = 0; ax < D; ax++) {
+                        P.cdx[ax] = aux[(0 * 3 + ax) * cap + a];
+                        P.cu[ax] = aux[(1 * 3 + ax) * cap + a];
+                        P.gs[ax] = aux[(2 * 3 + ax) * cap + a];
+                        P.fs[ax] = aux[(3 * 3 + ax) * cap + a];
+                    }
+                    P.vmax2 = aux[12 * cap + a];
+                }
+                active_substep<D>(P, c, cdata + P.off, P.cnt, cdata + P.off, gdx + cur * 3 * cap,
+                                  gu + cur * 3 * cap, (int)cap);
+#pragma unroll
+                for (int ax = 0; ax < D; ax++) {
+                    gdx[((cur ^ 1) * 3 + ax) * cap + a] = P.dx[ax];
+                    gu[((cur ^ 1) * 3 + ax) * cap + a] = P.u[ax];
+                    aux[(0 * 3 + ax) * cap + a] = P.cdx[ax];
+                    aux[(1 * 3 + ax) * cap + a] = P.cu[ax];
+                    aux[(2 * 3 + ax) * cap + a] = P.gs[ax];
+                    aux[(3 * 3 + ax) * cap + a] = P.fs[ax];
+                }
+                aux[12 * cap + a] = P.vmax2;
+                if (k == c.n_sub - 1) active_store<D>(P, Bn, c, s, np, coef, fc, flags);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// spreading (O5): F(r) = sum_p A_p gbar_p W_p(r) with the start-of-step
+// weights.  One wave per node tile.  The particles whose support can reach
+// the tile sit in the tile's halo bins; the bins of one (by, bz) row are
+// contiguous in the sorted order, so walking the rows in ascending key order
+// visits the particles in sorted order.  The wave loads 64 particles at a
+// time (coalesced), then adds each particle's contribution to its support
+// nodes held in LDS, one lane per support node: every node receives its
+// terms in the same fixed order, with no atomics.
+// ---------------------------------------------------------------------------
+template <int D> struct SpreadTile;
+template <> struct SpreadTile<3> { static constexpr int TX = 16, TY = 8, TZ = 4; };
+template <> struct SpreadTile<2> { static constexpr int TX = 64, TY = 8, TZ = 1; };
+
+__device__ __forceinline__ float rl(float v, int j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ __forceinline__ int rl(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+
+template <int D>
+__global__ __launch_bounds__(64) void k_spread(Grid g, PCfg c, const uint32_t* __restrict__ start,
+                                               const short4* __restrict__ wbase, const float* __restrict__ wphi,
+                                               const float* __restrict__ coef, int np, float* __restrict__ F,
+                                               int ntx, int nty) {
+    constexpr int TX = SpreadTile<D>::TX, TY = SpreadTile<D>::TY, TZ = SpreadTile<D>::TZ;
+    constexpr int TN = TX * TY * TZ;
+    __shared__ float acc[D * TN];
+    const int lane = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int tx = tile % ntx, t2 = tile / ntx;
+    const int ty = t2 % nty, tz = t2 / nty;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+    for (int i = lane; i < D * TN; i += WAVE) acc[i] = 0.f;
+    __syncthreads();
+
+    // halo bins: a particle in dual cell cd reaches nodes cd-1 .. cd+2
+    const int bx0 = max((x0 - 1) >> c.L, 0), bx1 = min((x0 + TX + 1) >> c.L, c.nb[0] - 1);
+    const int by0 = max((y0 - 1) >> c.L, 0), by1 = min((y0 + TY + 1) >> c.L, c.nb[1] - 1);
+    const int bz0 = (D == 3) ? max((z0 - 1) >> c.L, 0) : 0;
+    const int bz1 = (D == 3) ? min((z0 + TZ + 1) >> c.L, c.nb[2] - 1) : 0;
+    // this lane's support node offset
+    const int kx = lane & 3, ky = (lane >> 2) & 3, kz = (D == 3) ? (lane >> 4) : 0;
+    const bool lane_on = (D == 3) || lane < 16;
+
+    for (int bz = bz0; bz <= bz1; bz++)
+        for (int by = by0; by <= by1; by++) {
+            const uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
+            const uint32_t s0 = start[row + bx0], s1 = start[row + bx1 + 1];
+            for (uint32_t ch = s0; ch < s1; ch += WAVE) {
+                const uint32_t idx = ch + lane;
+                const bool v = idx < s1;
+                const uint32_t li = v ? idx : s0;
+                short4 b = wbase[li];
+                float ph[4 * D], cf[D];
+#pragma unroll
+                for (int k = 0; k < 4 * D; k++) ph[k] = wphi[(long long)li * (4 * D) + k];
+#pragma unroll
+                for (int a = 0; a < D; a++) cf[a] = coef[(long long)a * np + li];
+                const int bxi = b.x, byi = b.y, bzi = b.z;
+                const int cnt = (int)min((uint32_t)WAVE, s1 - ch);
+                for (int j = 0; j < cnt; j++) {
+                    const int lx = rl(bxi, j) + kx - x0;
+                    const int ly = rl(byi, j) + ky - y0;
+                    const int lz = (D == 3) ? rl(bzi, j) + kz - z0 : 0;
+                    float wx = rl(ph[0], j), wy = rl(ph[4], j), wz = 1.f;
+                    // select this lane's weights among the particle's four per axis
+                    {
+                        float p1 = rl(ph[1], j), p2 = rl(ph[2], j), p3 = rl(ph[3], j);
+                        wx = kx == 0 ? wx : (kx == 1 ? p1 : (kx == 2 ? p2 : p3));
+                        float q1 = rl(ph[5], j), q2 = rl(ph[6], j), q3 = rl(ph[7], j);
+                        wy = ky == 0 ? wy : (ky == 1 ? q1 : (ky == 2 ? q2 : q3));
+                    }
+                    if (D == 3) {
+                        float z0w = rl(ph[8 % (4 * D)], j), z1 = rl(ph[9 % (4 * D)], j);
+                        float z2 = rl(ph[10 % (4 * D)], j), z3 = rl(ph[11 % (4 * D)], j);
+                        wz = kz == 0 ? z0w : (kz == 1 ? z1 : (kz == 2 ? z2 : z3));
+                    }
+                    float cx = rl(cf[0], j), cy = rl(cf[1 % D], j), cz = (D == 3) ? rl(cf[2 % D], j) : 0.f;
+                    const bool in = lane_on && (unsigned)lx < (unsigned)TX && (unsigned)ly < (unsigned)TY &&
+                                    (unsigned)lz < (unsigned)TZ;
+                    if (in) {
+                        const float W = wx * wy * wz;
+                        const int li2 = (lz * TY + ly) * TX + lx;
+                        acc[li2] += W * cx;
+                        acc[TN + li2] += W * cy;
+                        if (D == 3) acc[2 * TN + li2] += W * cz;
+                    }
+                }
+            }
+        }
+    __syncthreads();
+    for (int i = lane; i < TN; i += WAVE) {
+        const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (x < g.n[0] && y < g.n[1] && z < g.n[2]) {
+            const long long r = ((long long)z * g.n[1] + y) * g.n[0] + x;
+#pragma unroll
+            for (int a = 0; a < D; a++) F[(long long)a * g.N + r] = acc[a * TN + i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 particle totals: momentum sum m U, min and sum of the last coordinate
+// part[b*8 + 0..2] momentum, 3 min height, 4 sum height
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_particle_totals(PState A, int np, double* __restrict__ part) {
+    __shared__ double sm[5][256];
+    double p0 = 0, p1 = 0, p2 = 0, mn = 1e300, sh = 0;
+    for (int s = blockIdx.x * 256 + threadIdx.x; s < np; s += gridDim.x * 256) {
+        double m = (double)particle_mass(D, A.d[s], A.rp[s]);
+        p0 += m * (double)A.u[0][s];
+        p1 += m * (double)A.u[1][s];
+        if (D == 3) p2 += m * (double)A.u[2][s];
+        double hgt = (double)A.xh[D - 1][s] + (double)A.xl[D - 1][s];
+        mn = fmin(mn, hgt);
+        sh += hgt;
+    }
+    int t = threadIdx.x;
+    sm[0][t] = p0; sm[1][t] = p1; sm[2][t] = p2; sm[3][t] = mn; sm[4][t] = sh;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) {
+            sm[0][t] += sm[0][t + st];
+            sm[1][t] += sm[1][t + st];
+            sm[2][t] += sm[2][t + st];
+            sm[3][t] = fmin(sm[3][t], sm[3][t + st]);
+            sm[4][t] += sm[4][t + st];
+        }
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int k = 0; k < 5; k++) part[blockIdx.x * 8 + k] = sm[k][0];
+}
+
+__global__ void k_particle_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    int k = threadIdx.x;
+    if (k >= 5) return;
+    double acc = (k == 3) ? 1e300 : 0.0;
+    for (int b = 0; b < nb; b++) acc = (k == 3) ? fmin(acc, part[b * 8 + k]) : acc + part[b * 8 + k];
+    out[k] = acc;
+}
+
+// state in sorted order -> staging arrays in id order
+template <int D>
+__global__ __launch_bounds__(256) void k_unpermute(PState A, int np, const float* __restrict__ coef,
+                                                   const float* __restrict__ fc, float* __restrict__ out) {
+    // out layout: [xh D][xl D][u D][fh D][fc D] x np
+    int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= np) return;
+    int id = A.id[s];
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        out[(long long)(0 * D + a) * np + id] = A.xh[a][s];
+        out[(long long)(1 * D + a) * np + id] = A.xl[a][s];
+        out[(long long)(2 * D + a) * np + id] = A.u[a][s];
+        out[(long long)(3 * D + a) * np + id] = coef ? -coef[(long long)a * np + s] : 0.f;
+        out[(long long)(4 * D + a) * np + id] = fc ? fc[(long long)a * np + s] : 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers (called from runtime.hip)
+// ---------------------------------------------------------------------------
+static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
+void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
+    long long nbins = c.nbins;
+    hipLaunchKernelGGL(k_fill_u32, dim3(nb256(nbins + 1)), dim3(256), 0, s, b.cnt, nbins + 1, 0u);
+    if (D == 3)
+        hipLaunchKernelGGL(k_bin_count<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.cnt, b.keys, b.slot, b.flags);
+    else
+        hipLaunchKernelGGL(k_bin_count<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.cnt, b.keys, b.slot, b.flags);
+    scan_exclusive<uint32_t>(b.cnt, b.start, nbins + 1, b.scan_u32, nullptr, s);
+    hipLaunchKernelGGL(k_scatter, dim3(nb256(np)), dim3(256), 0, s, b.keys, b.slot, b.start, b.tmp, np);
+    if (D == 3)
+        hipLaunchKernelGGL(k_reorder<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, np);
+    else
+        hipLaunchKernelGGL(k_reorder<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, np);
+    PState t = b.A;
+    b.A = b.B;
+    b.B = t;
+}
+
+void particles_interp(int D, PBuf& b, int np, const Grid& g, const float4* mom, hipStream_t s) {
+    long long threads = (long long)np * (D == 3 ? 16 : 4);
+    if (D == 3)
+        hipLaunchKernelGGL(k_interp<3>, dim3(nb256(threads)), dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+    else
+        hipLaunchKernelGGL(k_interp<2>, dim3(nb256(threads)), dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+}
+
+template <int D>
+static void dem_impl(PBuf& b, int np, const PCfg& c, hipStream_t s) {
+    const unsigned grid_act = std::min<unsigned>(nb256(np), 2048u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, b.counters, (long long)CNT_SIZE, 0u);
+    hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.drho_i, b.j_i,
+                       b.coef, b.fc, b.actcc, b.flags);
+    // exclusive scan of (active << 32 | candidates); total -> counters[0..1]
+    scan_exclusive<unsigned long long>(b.actcc, b.prefix, np, b.scan_u64,
+                                       (unsigned long long*)(void*)b.counters, s);
+    hipLaunchKernelGGL(k_collect<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.actcc, b.prefix,
+                       b.alist, b.aidx, b.cand, b.ccount, b.parent);
+    hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, b.isize, b.counters + CNT_ACTIVE, 1, 0u, (long long)np);
+    hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, b.fill, b.counters + CNT_ACTIVE, 1, 0u, (long long)np);
+    hipLaunchKernelGGL(k_uf_hook, dim3(grid_act), dim3(256), 0, s, b.alist, b.ccount, b.prefix, b.cand, b.aidx, b.parent,
+                       b.counters);
+    hipLaunchKernelGGL(k_uf_flatten, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.counters);
+    hipLaunchKernelGGL(k_island_class, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.bigroot, b.counters);
+    hipLaunchKernelGGL(k_island_plan, dim3(1), dim3(64), 0, s, b.counters, b.isize, b.bigroot, b.bigoff);
+    hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, (uint32_t*)b.lanemember, b.counters + CNT_WAVES,
+                       WAVE, 0xffffffffu, b.lane_cap);
+    hipLaunchKernelGGL(k_island_place, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.fill,
+                       b.lanemember, b.loc, b.bigoff, b.bigmember, b.counters);
+    hipLaunchKernelGGL(k_cand_prep<D>, dim3(grid_act), dim3(256), 0, s, b.A, c, b.alist, b.ccount, b.prefix, b.cand,
+                       b.aidx, b.loc, b.cdata, b.counters);
+    hipLaunchKernelGGL(k_island_small<D>, dim3(std::max<unsigned>(grid_act * 4, 256u)), dim3(64), 0, s, b.A, b.Bn,
+                       np, c, b.lanemember, b.alist, b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i,
+                       b.j_i, b.coef, b.fc,
+                       b.flags, b.counters);
+    hipLaunchKernelGGL(k_island_big<D>, dim3(256), dim3(256), 0, s, b.A, b.Bn, np, c, b.bigmember, b.bigoff,
+                       b.bigroot, b.isize, b.alist, b.ccount, b.prefix, b.cdata, b.drho_i, b.j_i, b.coef, b.fc,
+                       b.gdx, b.gu, (long long)np, b.flags, b.counters);
+}
+
+void particles_dem(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
+    if (D == 3) dem_impl<3>(b, np, c, s);
+    else dem_impl<2>(b, np, c, s);
+    // the new positions and velocities become the current ones
+    for (int a = 0; a < 3; a++) {
+        std::swap(b.A.xh[a], b.Bn.xh[a]);
+        std::swap(b.A.xl[a], b.Bn.xl[a]);
+        std::swap(b.A.u[a], b.Bn.u[a]);
+    }
+}
+
+void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, float* F, hipStream_t s) {
+    if (D == 3) {
+        using T = SpreadTile<3>;
+        int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY, ntz = (g.n[2] + T::TZ - 1) / T::TZ;
+        hipLaunchKernelGGL(k_spread<3>, dim3((unsigned)((long long)ntx * nty * ntz)), dim3(64), 0, s, g, c, b.start,
+                           b.wbase, b.wphi, b.coef, np, F, ntx, nty);
+    } else {
+        using T = SpreadTile<2>;
+        int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY;
+        hipLaunchKernelGGL(k_spread<2>, dim3((unsigned)((long long)ntx * nty)), dim3(64), 0, s, g, c, b.start,
+                           b.wbase, b.wphi, b.coef, np, F, ntx, nty);
+    }
+}
+
+int particles_totals_blocks() { return 256; }
+
+void particles_totals(int D, PBuf& b, int np, double* part, double* out, hipStream_t s) {
+    int nb = particles_totals_blocks();
+    if (D == 3) hipLaunchKernelGGL(k_particle_totals<3>, dim3(nb), dim3(256), 0, s, b.A, np, part);
+    else hipLaunchKernelGGL(k_particle_totals<2>, dim3(nb), dim3(256), 0, s, b.A, np, part);
+    hipLaunchKernelGGL(k_particle_final, dim3(1), dim3(64), 0, s, part, nb, out);
+}
+
+void particles_unpermute(int D, PBuf& b, int np, bool have_forces, float* out, hipStream_t s) {
+    const float* coef = have_forces ? b.coef : nullptr;
+    const float* fc = have_forces ? b.fc : nullptr;
+    if (D == 3) hipLaunchKernelGGL(k_unpermute<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, coef, fc, out);
+    else hipLaunchKernelGGL(k_unpermute<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, coef, fc, out);
+}
+
+}  // namespace pibm

@@ -1,0 +1,185 @@
+// pibm_internal.h -- device-side definitions shared by the HIP sources of
+// libpibm (gfx950, wave64).  Not part of the public ABI (include/pibm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pibm.h"
+
+namespace pibm {
+
+// ---------------------------------------------------------------------------
+// Lattices: D2Q9 and D3Q19 (c = 1, c_s^2 = 1/3), direction order of the ABI.
+// ---------------------------------------------------------------------------
+template <int Q> struct Lattice;
+
+template <> struct Lattice<9> {
+    static constexpr int D = 2;
+    __host__ __device__ static constexpr int ex(int q) {
+        constexpr int t[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+        return t[q];
+    }
+    __host__ __device__ static constexpr int ey(int q) {
+        constexpr int t[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+        return t[q];
+    }
+    __host__ __device__ static constexpr int ez(int) { return 0; }
+    __host__ __device__ static constexpr float w(int q) {
+        return q == 0 ? 4.0f / 9.0f : (q < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
+    }
+    __host__ __device__ static constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+};
+
+template <> struct Lattice<19> {
+    static constexpr int D = 3;
+    __host__ __device__ static constexpr int ex(int q) {
+        constexpr int t[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+        return t[q];
+    }
+    __host__ __device__ static constexpr int ey(int q) {
+        constexpr int t[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+        return t[q];
+    }
+    __host__ __device__ static constexpr int ez(int q) {
+        constexpr int t[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+        return t[q];
+    }
+    __host__ __device__ static constexpr float w(int q) {
+        return q == 0 ? 1.0f / 3.0f : (q < 7 ? 1.0f / 18.0f : 1.0f / 36.0f);
+    }
+    __host__ __device__ static constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+};
+
+// Storage codecs: the stored quantity is the deviation h = f - w, in FP32,
+// or scaled by 2^s and rounded to FP16 (nearest-even).  Arithmetic is FP32.
+struct StoreF32 {
+    using T = float;
+    float scale, inv_scale;
+    __device__ __forceinline__ float load(const T* p) const { return *p; }
+    __device__ __forceinline__ void store(T* p, float v) const { *p = v; }
+};
+struct StoreF16 {
+    using T = _Float16;
+    float scale, inv_scale;
+    __device__ __forceinline__ float load(const T* p) const { return (float)(*p) * inv_scale; }
+    __device__ __forceinline__ void store(T* p, float v) const { *p = (_Float16)(v * scale); }
+};
+
+struct Grid {
+    int n[3];
+    int periodic[3];
+    long long N;       // nodes
+};
+
+// ---------------------------------------------------------------------------
+// Double-float helpers (value = hi + lo, |lo| <= ulp(hi)/2), FP32 only.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__host__ __device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    e = b - (s - a);
+}
+// (hi, lo) += d
+__host__ __device__ __forceinline__ void df_add(float& hi, float& lo, float d) {
+    float s, e;
+    two_sum(hi, d, s, e);
+    e += lo;
+    fast_two_sum(s, e, hi, lo);
+}
+
+// Dual cell floor(X - 1/2) of X = hi + lo, exactly (hi - 1/2 is exact for
+// hi >= 1/4 and cannot reach an integer below; lo only matters when
+// hi - 1/2 is an integer).
+__device__ __forceinline__ int dual_cell(float hi, float lo) {
+    float t = hi - 0.5f;
+    float c = floorf(t);
+    int ci = (int)c;
+    if (t == c && lo < 0.0f) ci -= 1;
+    return ci;
+}
+// X - 1/2 - floor(X - 1/2), in [0, 1) up to rounding of the last add.
+__device__ __forceinline__ float dual_frac(float hi, float lo, int c) {
+    float f = ((hi - 0.5f) - (float)c) + lo;
+    return fminf(fmaxf(f, 0.0f), 0.99999994f);
+}
+
+// Particle state, structure of arrays in sorted (bin, id) order.
+struct PState {
+    float* xh[3];
+    float* xl[3];
+    float* u[3];
+    float* d;
+    float* rp;
+    int* id;
+};
+
+// Device-side error flags (bit mask), latched until read by the host.
+enum : unsigned {
+    FLAG_SKIN = 1u,
+    FLAG_CAPACITY = 2u,
+    FLAG_UNSTABLE = 4u,
+};
+
+// Counters written by the particle kernels (one small device array).
+enum {
+    CNT_CAND = 0,        // directed candidate entries (low word of the scan total)
+    CNT_ACTIVE = 1,      // active particles of the current step (high word)
+    CNT_WAVES = 2,       // packed waves of small islands
+    CNT_BIG = 3,         // islands larger than one wave
+    CNT_CLASS = 8,       // 65 class counters (index 1..64 sizes, 65 big) at 8..73
+    CNT_WAVEBASE = 80,   // 66 prefix entries at 80..145
+    CNT_SIZE = 160
+};
+
+constexpr int WAVE = 64;
+constexpr float PI_F = 3.14159265358979323846f;
+
+// Particle-side constants of one configuration.
+struct PCfg {
+    int D;
+    int n[3];
+    int L;              // bin edge 2^L dual cells
+    int nb[3];          // bins per axis
+    long long nbins;
+    float skin;
+    int contact;
+    float kn, zeta, ks;
+    int n_sub;
+    float h;            // 1 / n_sub
+    float rho0;
+    float g[3];
+    int maxc;
+};
+
+// Per-candidate constants of the active sub-steps.
+struct CandData {
+    int local;      // partner index in the island's state array
+    float r0[3];    // X_self - X_partner at the start of the step
+    float K0;       // r_c^2 - |r0|^2, accurate to FP32 relative precision
+    float rc;       // (d_self + d_partner) / 2
+    float gam;      // dashpot coefficient 2 zeta sqrt(kn m_eff)
+};
+
+// Device buffers of the particle side (carved from the workspace).
+struct PBuf {
+    PState A, B, Bn;             // current, reorder target, next (after DEM)
+    uint32_t *cnt, *start, *keys, *slot, *tmp, *keys_sorted;
+    uint32_t* scan_u32;          // scan block sums
+    unsigned long long *actcc, *prefix, *scan_u64;
+    float *drho_i, *j_i, *wphi, *coef, *fc;
+    short4* wbase;
+    uint32_t *alist, *aidx, *cand, *ccount, *parent, *isize, *irank, *fill, *loc, *bigroot, *bigoff, *bigmember;
+    int* lanemember;
+    CandData* cdata;
+    float *gdx, *gu;
+    uint32_t* counters;
+    uint32_t* flags;
+    long long cand_cap, lane_cap;
+};
+
+}  // namespace pibm

@@ -1,0 +1,574 @@
+// runtime.hip -- C ABI of libpibm (include/pibm.h): configuration checks,
+// workspace carving, host I/O and the launch sequence of one coupled step.
+// Every launch goes to the context's stream; only I/O, diagnostics and
+// pibm_synchronize wait for it.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pibm_internal.h"
+
+namespace pibm {
+constexpr size_t CAND_BYTES = sizeof(CandData);
+
+void lattice_moments(int Q, int fp16, int sl2, const void* f, float4* mom, long long N, hipStream_t s);
+void lattice_collide(int Q, int fp16, int sl2, const void* fin, void* fout, const float* F, int hasF,
+                     const float* ff, const Grid& g, float tau, hipStream_t s);
+void lattice_init_eq(int Q, int fp16, int sl2, void* f, const float* rho, const float* u, long long N,
+                     hipStream_t s);
+void lattice_decode(int fp16, int sl2, const void* f, float* out, long long n, hipStream_t s);
+void lattice_encode(int fp16, int sl2, void* f, const float* in, long long n, hipStream_t s);
+void lattice_fields(const float4* mom, float* rho, float* u, long long N, int D, hipStream_t s);
+int lattice_totals_blocks();
+void lattice_totals(int Q, int fp16, int sl2, const void* f, long long N, double* part, double* out,
+                    hipStream_t s);
+long long scan_blocks(long long n);
+void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s);
+void particles_interp(int D, PBuf& b, int np, const Grid& g, const float4* mom, hipStream_t s);
+void particles_dem(int D, PBuf& b, int np, const PCfg& c, hipStream_t s);
+void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, float* F, hipStream_t s);
+int particles_totals_blocks();
+void particles_totals(int D, PBuf& b, int np, double* part, double* out, hipStream_t s);
+void particles_unpermute(int D, PBuf& b, int np, bool have_forces, float* out, hipStream_t s);
+}  // namespace pibm
+
+using namespace pibm;
+
+struct pibm_ctx {
+    pibm_config cfg;
+    int Q = 9, D = 2, fp16 = 0, sl2 = 0;
+    long long N = 0;
+    int np = 0;
+    hipStream_t stream = nullptr;
+    void* fA = nullptr;
+    void* fB = nullptr;
+    float4* mom = nullptr;
+    float* F = nullptr;
+    float* stage = nullptr;
+    long long stage_floats = 0;
+    double* part = nullptr;
+    double* totals = nullptr;
+    PBuf pb{};
+    PCfg pc{};
+    Grid grid{};
+    bool particles_set = false;
+    bool stepped = false;
+    std::string err;
+    // phase timing: a ring of event rows, PIBM_NUM_PHASES + 1 events per step
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    int ev_rows = 0, ev_used = 0;
+    double phase_ms[PIBM_NUM_PHASES] = {0, 0, 0, 0, 0, 0};
+    int64_t prof_steps = 0;
+    ~pibm_ctx() {
+        for (hipEvent_t e : ev) hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <class T> T* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+pibm_status fail(pibm_ctx* c, pibm_status st, const std::string& msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+pibm_status check_hip(pibm_ctx* c, hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(c, PIBM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return PIBM_OK;
+}
+
+int dimension(int lattice) { return lattice == PIBM_D3Q19 ? 3 : 2; }
+
+std::string validate(const pibm_config* cfg, int64_t np) {
+    if (!cfg) return "null config";
+    if (cfg->abi_version != PIBM_ABI_VERSION) return "ABI version mismatch";
+    if (cfg->lattice != PIBM_D2Q9 && cfg->lattice != PIBM_D3Q19) return "lattice must be D2Q9 (9) or D3Q19 (19)";
+    if (cfg->storage != PIBM_STORE_FP32 && cfg->storage != PIBM_STORE_FP16) return "unknown storage";
+    if (cfg->fp16_scale_log2 < 0 || cfg->fp16_scale_log2 > 24) return "fp16_scale_log2 out of range";
+    int D = dimension(cfg->lattice);
+    for (int a = 0; a < 3; a++) {
+        if (cfg->n[a] < 1) return "lattice extent < 1";
+        if (a >= D && cfg->n[a] != 1) return "n[2] must be 1 for D2Q9";
+    }
+    long long N = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+    if (N > (1LL << 31) - 1) return "too many nodes";
+    for (int a = 0; a < D; a++)
+        if (cfg->n[a] > 30000) return "axis longer than 30000 nodes";
+    if (!(cfg->tau > 0.5)) return "tau must exceed 1/2";
+    if (cfg->n_sub < 1) return "n_sub must be >= 1";
+    if (cfg->contact < 0 || cfg->contact > 2) return "unknown contact model";
+    if (cfg->bin_log2 < 0 || cfg->bin_log2 > 3) return "bin_log2 must be 0..3";
+    if (cfg->max_candidates < 1 || cfg->max_candidates > 64) return "max_candidates must be 1..64";
+    if (cfg->contact == PIBM_CONTACT_LSD && (!(cfg->kn > 0) || !(cfg->restitution > 0) || cfg->restitution > 1))
+        return "linear spring-dashpot needs kn > 0 and 0 < restitution <= 1";
+    if (!(cfg->skin >= 0)) return "skin must be >= 0";
+    if (np < 0 || np > (1LL << 30)) return "particle count out of range";
+    if (np > 0)
+        for (int a = 0; a < D; a++)
+            if (cfg->periodic[a]) return "particles need walls on every axis";
+    return "";
+}
+
+// Lay out the workspace; with base == nullptr only the size is computed.
+size_t carve(pibm_ctx& c, char* base) {
+    Carver cv{base};
+    const long long N = c.N;
+    const size_t es = c.fp16 ? 2 : 4;
+    c.fA = cv.take<char>((size_t)c.Q * N * es);
+    c.fB = cv.take<char>((size_t)c.Q * N * es);
+    c.mom = cv.take<float4>(N);
+    c.F = cv.take<float>((size_t)c.D * N);
+    long long np = c.np;
+    c.stage_floats = std::max<long long>((long long)(c.D + 1) * N, 5LL * c.D * np);
+    c.stage = cv.take<float>(c.stage_floats);
+    c.part = cv.take<double>(8 * (std::max(lattice_totals_blocks(), particles_totals_blocks()) + 2));
+    c.totals = cv.take<double>(16);
+    PBuf& b = c.pb;
+    b.flags = cv.take<uint32_t>(4);
+    b.counters = cv.take<uint32_t>(CNT_SIZE);
+    if (np > 0) {
+        PState* S[3] = {&b.A, &b.B, &b.Bn};
+        for (int k = 0; k < 3; k++) {
+            for (int a = 0; a < 3; a++) {
+                S[k]->xh[a] = a < c.D ? cv.take<float>(np) : nullptr;
+                S[k]->xl[a] = a < c.D ? cv.take<float>(np) : nullptr;
+                S[k]->u[a] = a < c.D ? cv.take<float>(np) : nullptr;
+            }
+            S[k]->d = k < 2 ? cv.take<float>(np) : nullptr;
+            S[k]->rp = k < 2 ? cv.take<float>(np) : nullptr;
+            S[k]->id = k < 2 ? cv.take<int>(np) : nullptr;
+        }
+        long long nb1 = c.pc.nbins + 1;
+        b.cnt = cv.take<uint32_t>(nb1);
+        b.start = cv.take<uint32_t>(nb1);
+        b.keys = cv.take<uint32_t>(np);
+        b.slot = cv.take<uint32_t>(np);
+        b.tmp = cv.take<uint32_t>(np);
+        b.keys_sorted = cv.take<uint32_t>(np);
+        b.scan_u32 = cv.take<uint32_t>(scan_blocks(nb1) + 1);
+        b.scan_u64 = cv.take<unsigned long long>(scan_blocks(np) + 1);
+        b.actcc = cv.take<unsigned long long>(np);
+        b.prefix = cv.take<unsigned long long>(np);
+        b.drho_i = cv.take<float>(np);
+        b.j_i = cv.take<float>((size_t)c.D * np);
+        b.wphi = cv.take<float>((size_t)4 * c.D * np);
+        b.coef = cv.take<float>((size_t)c.D * np);
+        b.fc = cv.take<float>((size_t)c.D * np);
+        b.wbase = cv.take<short4>(np);
+        b.alist = cv.take<uint32_t>(np);
+        b.aidx = cv.take<uint32_t>(np);
+        b.ccount = cv.take<uint32_t>(np);
+        b.parent = cv.take<uint32_t>(np);
+        b.isize = cv.take<uint32_t>(np);
+        b.irank = cv.take<uint32_t>(np);
+        b.fill = cv.take<uint32_t>(np);
+        b.loc = cv.take<uint32_t>(np);
+        b.bigroot = cv.take<uint32_t>(np);
+        b.bigoff = cv.take<uint32_t>(np);
+        b.bigmember = cv.take<uint32_t>(np);
+        b.cand_cap = np * (long long)c.cfg.max_candidates;
+        b.cand = cv.take<uint32_t>(b.cand_cap);
+        b.cdata = (CandData*)cv.take<char>(b.cand_cap * CAND_BYTES);
+        b.lane_cap = 2 * np + (long long)(WAVE + 2) * WAVE;
+        b.lanemember = cv.take<int>(b.lane_cap);
+        b.gdx = cv.take<float>(19 * np);
+        b.gu = cv.take<float>(6 * np);
+    }
+    return cv.off + 256;
+}
+
+void fill_pcfg(pibm_ctx& c) {
+    PCfg& p = c.pc;
+    p.D = c.D;
+    for (int a = 0; a < 3; a++) p.n[a] = c.cfg.n[a];
+    p.L = c.cfg.bin_log2;
+    p.nbins = 1;
+    for (int a = 0; a < 3; a++) {
+        p.nb[a] = a < c.D ? (c.cfg.n[a] >> p.L) + 1 : 1;
+        p.nbins *= p.nb[a];
+    }
+    p.skin = (float)c.cfg.skin;
+    p.contact = c.cfg.contact;
+    p.kn = (float)c.cfg.kn;
+    double e = c.cfg.restitution > 0 ? c.cfg.restitution : 1.0;
+    double l = std::log(e);
+    p.zeta = (float)(-l / std::sqrt(M_PI * M_PI + l * l));
+    p.ks = (float)c.cfg.k_soft;
+    p.n_sub = c.cfg.n_sub;
+    p.h = (float)(1.0 / c.cfg.n_sub);
+    p.rho0 = (float)c.cfg.rho0;
+    for (int a = 0; a < 3; a++) p.g[a] = (float)c.cfg.gravity[a];
+    p.maxc = c.cfg.max_candidates;
+}
+
+bool init_ctx(pibm_ctx& c, const pibm_config* cfg, int64_t np) {
+    c.cfg = *cfg;
+    c.Q = cfg->lattice;
+    c.D = dimension(cfg->lattice);
+    c.fp16 = cfg->storage == PIBM_STORE_FP16;
+    c.sl2 = c.fp16 ? cfg->fp16_scale_log2 : 0;
+    c.N = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+    c.np = (int)np;
+    for (int a = 0; a < 3; a++) {
+        c.grid.n[a] = cfg->n[a];
+        c.grid.periodic[a] = cfg->periodic[a] ? 1 : 0;
+    }
+    c.grid.N = c.N;
+    fill_pcfg(c);
+    return true;
+}
+
+pibm_status sync_and_flags(pibm_ctx* c) {
+    pibm_status st = check_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return st;
+    uint32_t flags = 0;
+    st = check_hip(c, hipMemcpy(&flags, c->pb.flags, 4, hipMemcpyDeviceToHost), "read flags");
+    if (st) return st;
+    if (flags) {
+        uint32_t z = 0;
+        hipMemcpy(c->pb.flags, &z, 4, hipMemcpyHostToDevice);
+        if (flags & FLAG_UNSTABLE) return fail(c, PIBM_E_UNSTABLE, "unstable: a particle left the box or a drag sub-step had h c >= 1");
+        if (flags & FLAG_CAPACITY) return fail(c, PIBM_E_CAPACITY, "a particle had more candidates than max_candidates");
+        if (flags & FLAG_SKIN) return fail(c, PIBM_E_SKIN, "a particle moved more than skin/2 within one step");
+    }
+    return PIBM_OK;
+}
+
+constexpr int PROF_ROWS = 256;
+
+// Sum the elapsed times of the recorded rows and empty the ring.
+pibm_status drain_events(pibm_ctx* c) {
+    if (c->ev_used == 0) return PIBM_OK;
+    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
+    const int E = PIBM_NUM_PHASES + 1;
+    for (int r = 0; r < c->ev_used; r++)
+        for (int p = 0; p < PIBM_NUM_PHASES; p++) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, c->ev[r * E + p], c->ev[r * E + p + 1]);
+            c->phase_ms[p] += ms;
+        }
+    c->prof_steps += c->ev_used;
+    c->ev_used = 0;
+    return PIBM_OK;
+}
+
+inline void mark(pibm_ctx* c, int row, int p) {
+    if (row >= 0) hipEventRecord(c->ev[row * (PIBM_NUM_PHASES + 1) + p], c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pibm_workspace_bytes(const pibm_config* cfg, int64_t n_particles) {
+    if (!validate(cfg, n_particles).empty()) return 0;
+    pibm_ctx c;
+    init_ctx(c, cfg, n_particles);
+    return carve(c, nullptr);
+}
+
+pibm_status pibm_create(const pibm_config* cfg, int64_t n_particles, void* dev_ws, size_t ws_bytes,
+                        void* hip_stream, pibm_ctx** out) {
+    if (!out) return PIBM_E_ARG;
+    *out = nullptr;
+    std::string v = validate(cfg, n_particles);
+    if (!v.empty()) return PIBM_E_CONFIG;
+    pibm_ctx* c = new pibm_ctx();
+    init_ctx(*c, cfg, n_particles);
+    size_t need = carve(*c, nullptr);
+    if (!dev_ws || ws_bytes < need) {
+        delete c;
+        return PIBM_E_ARG;
+    }
+    char* base = (char*)(((uintptr_t)dev_ws + 255) & ~(uintptr_t)255);
+    if ((size_t)(base - (char*)dev_ws) + need - 256 > ws_bytes) {
+        delete c;
+        return PIBM_E_ARG;
+    }
+    carve(*c, base);
+    c->stream = (hipStream_t)hip_stream;
+    hipMemsetAsync(c->F, 0, sizeof(float) * c->D * c->N, c->stream);
+    hipMemsetAsync(c->pb.flags, 0, 16, c->stream);
+    lattice_init_eq(c->Q, c->fp16, c->sl2, c->fA, nullptr, nullptr, c->N, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
+        delete c;
+        return PIBM_E_HIP;
+    }
+    *out = c;
+    return PIBM_OK;
+}
+
+void pibm_destroy(pibm_ctx* ctx) { delete ctx; }
+
+const char* pibm_last_error(const pibm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+pibm_status pibm_set_stream(pibm_ctx* ctx, void* hip_stream) {
+    if (!ctx) return PIBM_E_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return PIBM_OK;
+}
+
+pibm_status pibm_init_equilibrium(pibm_ctx* c, const float* rho, const float* u) {
+    if (!c) return PIBM_E_ARG;
+    float* drho = nullptr;
+    float* du = nullptr;
+    if (rho) {
+        drho = c->stage;
+        if (pibm_status s = check_hip(c, hipMemcpyAsync(drho, rho, sizeof(float) * c->N, hipMemcpyHostToDevice, c->stream), "copy rho")) return s;
+    }
+    if (u) {
+        du = c->stage + c->N;
+        if (pibm_status s = check_hip(c, hipMemcpyAsync(du, u, sizeof(float) * c->D * c->N, hipMemcpyHostToDevice, c->stream), "copy u")) return s;
+    }
+    lattice_init_eq(c->Q, c->fp16, c->sl2, c->fA, drho, du, c->N, c->stream);
+    if (pibm_status s = check_hip(c, hipGetLastError(), "init_eq launch")) return s;
+    return check_hip(c, hipStreamSynchronize(c->stream), "sync");
+}
+
+pibm_status pibm_write_populations(pibm_ctx* c, const float* h) {
+    if (!c || !h) return fail(c, PIBM_E_ARG, "null argument");
+    const size_t es = c->fp16 ? 2 : 4;
+    for (int q = 0; q < c->Q; q++) {
+        if (pibm_status s = check_hip(c, hipMemcpyAsync(c->stage, h + (size_t)q * c->N, sizeof(float) * c->N,
+                                                         hipMemcpyHostToDevice, c->stream), "copy populations")) return s;
+        lattice_encode(c->fp16, c->sl2, (char*)c->fA + (size_t)q * c->N * es, c->stage, c->N, c->stream);
+    }
+    if (pibm_status s = check_hip(c, hipGetLastError(), "encode launch")) return s;
+    return check_hip(c, hipStreamSynchronize(c->stream), "sync");
+}
+
+pibm_status pibm_read_populations(pibm_ctx* c, float* h) {
+    if (!c || !h) return fail(c, PIBM_E_ARG, "null argument");
+    const size_t es = c->fp16 ? 2 : 4;
+    for (int q = 0; q < c->Q; q++) {
+        lattice_decode(c->fp16, c->sl2, (char*)c->fA + (size_t)q * c->N * es, c->stage, c->N, c->stream);
+        if (pibm_status s = check_hip(c, hipMemcpyAsync(h + (size_t)q * c->N, c->stage, sizeof(float) * c->N,
+                                                         hipMemcpyDeviceToHost, c->stream), "copy populations")) return s;
+        if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
+    }
+    return check_hip(c, hipGetLastError(), "decode launch");
+}
+
+pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, const double* d,
+                               const double* rho_p) {
+    if (!c) return PIBM_E_ARG;
+    if (c->np == 0) {
+        c->particles_set = true;
+        return PIBM_OK;
+    }
+    if (!x || !d || !rho_p) return fail(c, PIBM_E_ARG, "null particle array");
+    const int D = c->D, np = c->np;
+    const double edge = std::ldexp(1.0, c->cfg.bin_log2);
+    std::vector<float> buf((size_t)(3 * D + 3) * np);
+    float* xh = buf.data();
+    float* xl = xh + (size_t)D * np;
+    float* u = xl + (size_t)D * np;
+    float* dd = u + (size_t)D * np;
+    float* rp = dd + np;
+    int* id = (int*)(rp + np);
+    for (int i = 0; i < np; i++) {
+        if (!(d[i] > 0) || !(rho_p[i] > 0)) return fail(c, PIBM_E_ARG, "diameter and density must be positive");
+        if (d[i] + c->cfg.skin > edge) return fail(c, PIBM_E_ARG, "diameter + skin exceeds the bin edge 2^bin_log2");
+        dd[i] = (float)d[i];
+        rp[i] = (float)rho_p[i];
+        id[i] = i;
+        for (int a = 0; a < D; a++) {
+            double xa = x[(size_t)a * np + i];
+            if (!(xa > 0.0 && xa < (double)c->cfg.n[a])) return fail(c, PIBM_E_ARG, "particle outside the box");
+            float h = (float)xa;
+            xh[(size_t)a * np + i] = h;
+            xl[(size_t)a * np + i] = (float)(xa - (double)h);
+            u[(size_t)a * np + i] = v ? (float)v[(size_t)a * np + i] : 0.0f;
+        }
+    }
+    PState& A = c->pb.A;
+    for (int a = 0; a < D; a++) {
+        hipMemcpyAsync(A.xh[a], xh + (size_t)a * np, 4 * np, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(A.xl[a], xl + (size_t)a * np, 4 * np, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(A.u[a], u + (size_t)a * np, 4 * np, hipMemcpyHostToDevice, c->stream);
+    }
+    hipMemcpyAsync(A.d, dd, 4 * np, hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(A.rp, rp, 4 * np, hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(A.id, id, 4 * np, hipMemcpyHostToDevice, c->stream);
+    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "copy particles")) return s;
+    c->particles_set = true;
+    c->stepped = false;
+    return PIBM_OK;
+}
+
+pibm_status pibm_read_particles(pibm_ctx* c, double* x, double* v, double* f_hydro, double* f_contact) {
+    if (!c) return PIBM_E_ARG;
+    if (c->np == 0) return PIBM_OK;
+    if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
+    const int D = c->D, np = c->np;
+    particles_unpermute(D, c->pb, np, c->stepped, c->stage, c->stream);
+    std::vector<float> buf((size_t)5 * D * np);
+    if (pibm_status s = check_hip(c, hipMemcpyAsync(buf.data(), c->stage, buf.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy particles")) return s;
+    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
+    for (int a = 0; a < D; a++)
+        for (int i = 0; i < np; i++) {
+            size_t k = (size_t)a * np + i;
+            if (x) x[k] = (double)buf[k] + (double)buf[(size_t)D * np + k];
+            if (v) v[k] = buf[(size_t)2 * D * np + k];
+            if (f_hydro) f_hydro[k] = buf[(size_t)3 * D * np + k];
+            if (f_contact) f_contact[k] = buf[(size_t)4 * D * np + k];
+        }
+    return PIBM_OK;
+}
+
+pibm_status pibm_read_fields(pibm_ctx* c, float* rho, float* u) {
+    if (!c) return PIBM_E_ARG;
+    lattice_moments(c->Q, c->fp16, c->sl2, c->fA, c->mom, c->N, c->stream);
+    lattice_fields(c->mom, c->stage, c->stage + c->N, c->N, c->D, c->stream);
+    if (rho) hipMemcpyAsync(rho, c->stage, sizeof(float) * c->N, hipMemcpyDeviceToHost, c->stream);
+    if (u) hipMemcpyAsync(u, c->stage + c->N, sizeof(float) * c->D * c->N, hipMemcpyDeviceToHost, c->stream);
+    return check_hip(c, hipStreamSynchronize(c->stream), "read fields");
+}
+
+pibm_status pibm_read_force(pibm_ctx* c, float* F) {
+    if (!c || !F) return PIBM_E_ARG;
+    if (pibm_status s = check_hip(c, hipMemcpyAsync(F, c->F, sizeof(float) * c->D * c->N, hipMemcpyDeviceToHost, c->stream), "copy F")) return s;
+    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
+    for (int a = 0; a < c->D; a++) {
+        float ff = (float)c->cfg.fluid_force[a];
+        if (ff != 0.0f)
+            for (long long r = 0; r < c->N; r++) F[(size_t)a * c->N + r] += ff;
+    }
+    return PIBM_OK;
+}
+
+int64_t pibm_num_bins(const pibm_ctx* c) { return c ? c->pc.nbins : 0; }
+
+pibm_status pibm_read_cell_list(pibm_ctx* c, uint32_t* keys, int32_t* ids, int32_t* bin_start) {
+    if (!c) return PIBM_E_ARG;
+    if (c->np == 0) return PIBM_OK;
+    if (!c->stepped) return fail(c, PIBM_E_STATE, "no step taken yet");
+    if (keys) hipMemcpyAsync(keys, c->pb.keys_sorted, 4 * (size_t)c->np, hipMemcpyDeviceToHost, c->stream);
+    if (ids) hipMemcpyAsync(ids, c->pb.A.id, 4 * (size_t)c->np, hipMemcpyDeviceToHost, c->stream);
+    if (bin_start) hipMemcpyAsync(bin_start, c->pb.start, 4 * (size_t)(c->pc.nbins + 1), hipMemcpyDeviceToHost, c->stream);
+    return check_hip(c, hipStreamSynchronize(c->stream), "read cell list");
+}
+
+pibm_status pibm_step(pibm_ctx* c, int32_t n_steps) {
+    if (!c) return PIBM_E_ARG;
+    if (n_steps < 0) return fail(c, PIBM_E_ARG, "negative step count");
+    if (c->np > 0 && !c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
+    const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
+    const bool spread = c->np > 0 && c->cfg.two_way;
+    for (int it = 0; it < n_steps; it++) {
+        int row = -1;
+        if (c->prof) {
+            if (c->ev_used == c->ev_rows)
+                if (pibm_status s = drain_events(c)) return s;
+            row = c->ev_used++;
+        }
+        mark(c, row, 0);
+        lattice_moments(c->Q, c->fp16, c->sl2, c->fA, c->mom, c->N, c->stream);
+        mark(c, row, 1);
+        if (c->np > 0) particles_sort(c->D, c->pb, c->np, c->pc, c->stream);
+        mark(c, row, 2);
+        if (c->np > 0) particles_interp(c->D, c->pb, c->np, c->grid, c->mom, c->stream);
+        mark(c, row, 3);
+        if (c->np > 0) particles_dem(c->D, c->pb, c->np, c->pc, c->stream);
+        mark(c, row, 4);
+        if (spread) particles_spread(c->D, c->pb, c->np, c->pc, c->grid, c->F, c->stream);
+        mark(c, row, 5);
+        lattice_collide(c->Q, c->fp16, c->sl2, c->fA, c->fB, c->F, spread ? 1 : 0, ff, c->grid,
+                        (float)c->cfg.tau, c->stream);
+        mark(c, row, 6);
+        std::swap(c->fA, c->fB);
+    }
+    if (n_steps > 0) c->stepped = true;
+    return check_hip(c, hipGetLastError(), "step launch");
+}
+
+pibm_status pibm_set_profiling(pibm_ctx* c, int enable) {
+    if (!c) return PIBM_E_ARG;
+    if (enable && c->ev.empty()) {
+        c->ev.resize((size_t)PROF_ROWS * (PIBM_NUM_PHASES + 1));
+        for (hipEvent_t& e : c->ev)
+            if (pibm_status s = check_hip(c, hipEventCreate(&e), "hipEventCreate")) return s;
+        c->ev_rows = PROF_ROWS;
+    }
+    if (!enable && c->prof)
+        if (pibm_status s = drain_events(c)) return s;
+    c->prof = enable != 0;
+    return PIBM_OK;
+}
+
+pibm_status pibm_phase_times(pibm_ctx* c, double* ms, int64_t* steps) {
+    if (!c) return PIBM_E_ARG;
+    if (pibm_status s = drain_events(c)) return s;
+    for (int p = 0; p < PIBM_NUM_PHASES; p++) {
+        if (ms) ms[p] = c->phase_ms[p];
+        c->phase_ms[p] = 0;
+    }
+    if (steps) *steps = c->prof_steps;
+    c->prof_steps = 0;
+    return PIBM_OK;
+}
+
+pibm_status pibm_synchronize(pibm_ctx* c) {
+    if (!c) return PIBM_E_ARG;
+    return sync_and_flags(c);
+}
+
+pibm_status pibm_diagnostics(pibm_ctx* c, pibm_diag* out) {
+    if (!c || !out) return PIBM_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    lattice_totals(c->Q, c->fp16, c->sl2, c->fA, c->N, c->part, c->totals, c->stream);
+    double fl[8];
+    hipMemcpyAsync(fl, c->totals, sizeof(fl), hipMemcpyDeviceToHost, c->stream);
+    double pt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t cnt[2] = {0, 0};
+    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "fluid totals")) return s;
+    if (c->np > 0 && c->particles_set) {
+        particles_totals(c->D, c->pb, c->np, c->part, c->totals + 8, c->stream);
+        hipMemcpyAsync(pt, c->totals + 8, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        hipMemcpyAsync(cnt, c->pb.counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
+        if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "particle totals")) return s;
+    }
+    out->mass = (double)c->N + fl[0];
+    for (int a = 0; a < 3; a++) {
+        out->fluid_momentum[a] = fl[1 + a];
+        out->momentum[a] = fl[1 + a] + pt[a];
+    }
+    out->max_speed = std::sqrt(fl[4]);
+    out->nonfinite = (int64_t)fl[5];
+    out->candidates = cnt[CNT_CAND];
+    out->active = cnt[CNT_ACTIVE];
+    if (c->np > 0) {
+        out->min_height = pt[3];
+        out->mean_height = pt[4] / c->np;
+    }
+    pibm_status st = sync_and_flags(c);
+    if (st) return st;
+    if (out->nonfinite > 0 || out->max_speed > 0.1)
+        return fail(c, PIBM_E_UNSTABLE, "non-finite populations or |u| > 0.1");
+    return PIBM_OK;
+}
+
+pibm_status pibm_conservation(pibm_ctx* c, double* mass, double* momentum) {
+    pibm_diag dg;
+    pibm_status st = pibm_diagnostics(c, &dg);
+    if (mass) *mass = dg.mass;
+    if (momentum)
+        for (int a = 0; a < 3; a++) momentum[a] = dg.momentum[a];
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+"""Python binding of libpibm (C ABI in include/pibm.h).
+
+Argument marshalling only: every step of the coupled LBM-PIBM-DEM path runs
+in the library's HIP kernels.  PyTorch provides the device workspace (one
+uint8 tensor) and the HIP stream.  There is no fallback: if libpibm.so is not
+built, importing this module's loader raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpibm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pibm.h")
+
+ABI_VERSION = 1
+D2Q9, D3Q19 = 9, 19
+STORE_FP32, STORE_FP16 = 0, 1
+CONTACT = {"none": 0, "lsd": 1, "soft": 2}
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_CONFIG", 3: "E_HIP", 4: "E_STATE", 5: "E_UNSTABLE",
+          6: "E_SKIN", 7: "E_CAPACITY"}
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("lattice", C.c_int32), ("storage", C.c_int32),
+        ("fp16_scale_log2", C.c_int32), ("n", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
+        ("tau", C.c_double), ("rho0", C.c_double), ("gravity", C.c_double * 3),
+        ("fluid_force", C.c_double * 3), ("contact", C.c_int32), ("n_sub", C.c_int32),
+        ("kn", C.c_double), ("restitution", C.c_double), ("k_soft", C.c_double),
+        ("skin", C.c_double), ("two_way", C.c_int32), ("bin_log2", C.c_int32),
+        ("max_candidates", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class Diag(C.Structure):
+    _fields_ = [
+        ("mass", C.c_double), ("momentum", C.c_double * 3), ("fluid_momentum", C.c_double * 3),
+        ("max_speed", C.c_double), ("nonfinite", C.c_int64), ("active", C.c_int64),
+        ("candidates", C.c_int64), ("min_height", C.c_double), ("mean_height", C.c_double),
+    ]
+
+
+class PibmError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {msg}")
+
+
+_lib = None
+
+
+def load():
+    """Load libpibm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1407_6704_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    fp = C.POINTER(C.c_float)
+    dp = C.POINTER(C.c_double)
+    cp = C.POINTER(Config)
+    sig = {
+        "pibm_workspace_bytes": ([cp, C.c_int64], C.c_size_t),
+        "pibm_create": ([cp, C.c_int64, vp, C.c_size_t, vp, C.POINTER(vp)], C.c_int),
+        "pibm_destroy": ([vp], None),
+        "pibm_last_error": ([vp], C.c_char_p),
+        "pibm_set_stream": ([vp, vp], C.c_int),
+        "pibm_init_equilibrium": ([vp, fp, fp], C.c_int),
+        "pibm_write_populations": ([vp, fp], C.c_int),
+        "pibm_read_populations": ([vp, fp], C.c_int),
+        "pibm_set_particles": ([vp, dp, dp, dp, dp], C.c_int),
+        "pibm_read_particles": ([vp, dp, dp, dp, dp], C.c_int),
+        "pibm_read_fields": ([vp, fp, fp], C.c_int),
+        "pibm_read_force": ([vp, fp], C.c_int),
+        "pibm_num_bins": ([vp], C.c_int64),
+        "pibm_read_cell_list": ([vp, C.POINTER(C.c_uint32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+        "pibm_step": ([vp, C.c_int32], C.c_int),
+        "pibm_synchronize": ([vp], C.c_int),
+        "pibm_conservation": ([vp, dp, dp], C.c_int),
+        "pibm_diagnostics": ([vp, C.POINTER(Diag)], C.c_int),
+        "pibm_set_profiling": ([vp, C.c_int], C.c_int),
+        "pibm_phase_times": ([vp, dp, C.POINTER(C.c_int64)], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def header_symbols():
+    """Names of the functions declared in include/pibm.h."""
+    import re
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(pibm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, periodic=(0, 0, 0),
+                tau=0.8, rho0=1.0, gravity=(0.0, 0.0, 0.0), fluid_force=(0.0, 0.0, 0.0),
+                contact="lsd", n_sub=1, kn=1e3, restitution=0.9, k_soft=1e-3, skin=0.05,
+                two_way=1, bin_log2=1, max_candidates=16) -> Config:
+    c = Config()
+    c.abi_version = ABI_VERSION
+    c.lattice = int(lattice)
+    c.storage = STORE_FP16 if storage in ("fp16", STORE_FP16) else STORE_FP32
+    c.fp16_scale_log2 = int(fp16_scale_log2)
+    for a in range(3):
+        c.n[a] = int(n[a])
+        c.periodic[a] = int(periodic[a])
+        c.gravity[a] = float(gravity[a])
+        c.fluid_force[a] = float(fluid_force[a])
+    c.tau, c.rho0 = float(tau), float(rho0)
+    c.contact = CONTACT[contact] if isinstance(contact, str) else int(contact)
+    c.n_sub = int(n_sub)
+    c.kn, c.restitution, c.k_soft, c.skin = float(kn), float(restitution), float(k_soft), float(skin)
+    c.two_way, c.bin_log2, c.max_candidates = int(two_way), int(bin_log2), int(max_candidates)
+    c.reserved = 0
+    return c
+
+
+def config_from_workload(w, **over) -> Config:
+    kw = dict(lattice=w.lattice, n=w.n, storage=w.storage, fp16_scale_log2=w.fp16_scale_log2,
+              tau=w.tau, gravity=w.gravity_vec(), contact=w.contact, n_sub=w.n_sub, kn=w.kn,
+              restitution=w.restitution, k_soft=w.k_soft, skin=w.skin, two_way=w.two_way,
+              bin_log2=w.bin_log2)
+    kw.update(over)
+    return make_config(**kw)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else None
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+class Sim:
+    """One coupled LBM-PIBM-DEM simulation on one GPU."""
+
+    def __init__(self, cfg: Config, n_particles: int = 0, device="cuda:0", stream=None):
+        import torch
+
+        self.lib = load()
+        self.cfg = cfg
+        self.np = int(n_particles)
+        self.Q = 19 if cfg.lattice == 19 else 9
+        self.D = 3 if cfg.lattice == 19 else 2
+        self.n = tuple(int(cfg.n[a]) for a in range(3))
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        nbytes = self.lib.pibm_workspace_bytes(C.byref(cfg), self.np)
+        if nbytes == 0:
+            raise PibmError(2, "invalid configuration")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        st = self.lib.pibm_create(C.byref(cfg), self.np, C.c_void_p(self.workspace.data_ptr()),
+                                  int(nbytes), C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx))
+        if st != 0:
+            raise PibmError(st, "pibm_create failed")
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.pibm_last_error(self.ctx)
+            raise PibmError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if self.ctx:
+            self.lib.pibm_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- state -----------------------------------------------------------
+    def init_equilibrium(self, rho=None, u=None):
+        r = _f32(rho) if rho is not None else None
+        uu = _f32(u) if u is not None else None
+        self._check(self.lib.pibm_init_equilibrium(self.ctx, _fp(r), _fp(uu)))
+
+    def write_populations(self, h):
+        h = _f32(h).reshape(self.Q * self.N)
+        self._check(self.lib.pibm_write_populations(self.ctx, _fp(h)))
+
+    def read_populations(self):
+        h = np.empty(self.Q * self.N, np.float32)
+        self._check(self.lib.pibm_read_populations(self.ctx, _fp(h)))
+        return h.reshape(self.Q, self.N)
+
+    def set_particles(self, x, v=None, d=None, rho_p=None):
+        x = _f64(x).reshape(self.D, self.np)
+        v = _f64(v).reshape(self.D, self.np) if v is not None else None
+        self._check(self.lib.pibm_set_particles(self.ctx, _dp(x), _dp(v), _dp(_f64(d)), _dp(_f64(rho_p))))
+
+    def read_particles(self):
+        out = {k: np.empty((self.D, self.np)) for k in ("x", "v", "f_hydro", "f_contact")}
+        self._check(self.lib.pibm_read_particles(self.ctx, _dp(out["x"]), _dp(out["v"]),
+                                                 _dp(out["f_hydro"]), _dp(out["f_contact"])))
+        return out
+
+    def read_fields(self):
+        rho = np.empty(self.N, np.float32)
+        u = np.empty((self.D, self.N), np.float32)
+        self._check(self.lib.pibm_read_fields(self.ctx, _fp(rho), _fp(u)))
+        return rho, u
+
+    def read_force(self):
+        F = np.empty((self.D, self.N), np.float32)
+        self._check(self.lib.pibm_read_force(self.ctx, _fp(F)))
+        return F
+
+    def num_bins(self):
+        return int(self.lib.pibm_num_bins(self.ctx))
+
+    def read_cell_list(self):
+        keys = np.empty(max(self.np, 1), np.uint32)
+        ids = np.empty(max(self.np, 1), np.int32)
+        bs = np.empty(self.num_bins() + 1, np.int32)
+        self._check(self.lib.pibm_read_cell_list(
+            self.ctx, keys.ctypes.data_as(C.POINTER(C.c_uint32)),
+            ids.ctypes.data_as(C.POINTER(C.c_int32)), bs.ctypes.data_as(C.POINTER(C.c_int32))))
+        return keys[: self.np], ids[: self.np], bs
+
+    # --- stepping ----------------------------------------------------------
+    def step(self, n=1):
+        self._check(self.lib.pibm_step(self.ctx, int(n)))
+
+    PHASES = ("moments", "cell_list", "interp", "dem", "spread", "collide")
+
+    def set_profiling(self, on=True):
+        self._check(self.lib.pibm_set_profiling(self.ctx, 1 if on else 0))
+
+    def phase_times(self):
+        """Milliseconds per phase and the step count since the last call."""
+        ms = (C.c_double * 6)()
+        steps = C.c_int64()
+        self._check(self.lib.pibm_phase_times(self.ctx, ms, C.byref(steps)))
+        return dict(zip(self.PHASES, list(ms))), steps.value
+
+    def synchronize(self):
+        self._check(self.lib.pibm_synchronize(self.ctx))
+
+    def diagnostics(self):
+        d = Diag()
+        self._check(self.lib.pibm_diagnostics(self.ctx, C.byref(d)))
+        return {"mass": d.mass, "momentum": list(d.momentum), "fluid_momentum": list(d.fluid_momentum),
+                "max_speed": d.max_speed, "nonfinite": d.nonfinite, "active": d.active,
+                "candidates": d.candidates, "min_height": d.min_height, "mean_height": d.mean_height}
+
+    def conservation(self):
+        m = C.c_double()
+        p = (C.c_double * 3)()
+        self._check(self.lib.pibm_conservation(self.ctx, C.byref(m), p))
+        return m.value, list(p)

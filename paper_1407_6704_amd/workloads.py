@@ -19,7 +19,9 @@ keep that structure at larger scale:
   c4  D2Q9 512^2, tau 0.7, 10k disks d = 0.5, ratio 2.5, soft repulsion,
       dilute (gaps >= d, >= 3 from walls), objective = mean height
 
-Gravity is 1e-5 lattice units along -y (2D) or -z (3D).  The linear
+Gravity is 1e-5 lattice units along -y (2D) or -z (3D).  The candidate-list
+skin is 0.01: a particle may move at most skin/2 per step, 100 times the
+settling displacement per step of these flows.  The linear
 spring-dashpot contact has k_n = 1e3 and restitution 0.9; the sub-step count
 is the one that resolves the shortest contact (20 sub-steps per contact time
 of the two smallest particles): 508, 677, 3109 for c0, c1, c2.
@@ -53,7 +55,7 @@ class Workload:
     kn: float = 1e3
     restitution: float = 0.9
     k_soft: float = 1e-3
-    skin: float = 0.05
+    skin: float = 0.01
     n_sub: int = 1
     steps: int = 100
     storage: str = "fp32"             # "fp32" | "fp16"

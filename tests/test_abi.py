@@ -1,0 +1,69 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/pibm.h declares, sizes workspaces and rejects bad configurations
+without touching a GPU (no compute call is made here)."""
+import ctypes as C
+
+import pytest
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1407_6704_amd import pibm
+    try:
+        pibm.load()
+    except RuntimeError:
+        from paper_1407_6704_amd import build
+        build.build()
+    return pibm
+
+
+def test_exports_every_declared_symbol(P):
+    lib = P.load()
+    names = P.header_symbols()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+    # nm view as well: the symbols are real exports of the shared object
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert f" T {n}" in out, n
+
+
+def test_workspace_bytes_and_validation(P):
+    lib = P.load()
+    ok = P.make_config(lattice=9, n=(64, 32, 1), tau=0.8)
+    b0 = lib.pibm_workspace_bytes(C.byref(ok), 0)
+    b1 = lib.pibm_workspace_bytes(C.byref(ok), 100)
+    assert b0 > 9 * 64 * 32 * 4 * 2 and b1 > b0
+    fp16 = P.make_config(lattice=19, n=(16, 16, 16), tau=0.8, storage="fp16")
+    fp32 = P.make_config(lattice=19, n=(16, 16, 16), tau=0.8)
+    assert lib.pibm_workspace_bytes(C.byref(fp16), 0) < lib.pibm_workspace_bytes(C.byref(fp32), 0)
+    bad = [
+        dict(tau=0.5), dict(tau=0.3), dict(n_sub=0), dict(lattice=15), dict(n=(8, 8, 2)),
+        dict(bin_log2=5), dict(max_candidates=0), dict(restitution=0.0), dict(periodic=(1, 0, 0)),
+    ]
+    for kw in bad:
+        args = dict(lattice=9, n=(8, 8, 1), tau=0.8)
+        args.update(kw)
+        cfg = P.make_config(**args)
+        assert lib.pibm_workspace_bytes(C.byref(cfg), 10) == 0, kw
+    # a periodic lattice without particles is allowed (Poiseuille channel)
+    per = P.make_config(lattice=9, n=(1, 8, 1), periodic=(1, 0, 0))
+    assert lib.pibm_workspace_bytes(C.byref(per), 0) > 0
+    # ABI version is checked
+    v = P.make_config()
+    v.abi_version = 99
+    assert lib.pibm_workspace_bytes(C.byref(v), 0) == 0
+    # create refuses a too-small workspace and a bad config before any GPU call
+    ctx = C.c_void_p()
+    assert lib.pibm_create(C.byref(ok), 0, None, 0, None, C.byref(ctx)) == 1
+    badc = P.make_config(tau=0.4)
+    assert lib.pibm_create(C.byref(badc), 0, None, 0, None, C.byref(ctx)) == 2
+
+
+def test_config_struct_layout(P):
+    """The ctypes mirror has the C struct's size (ints and doubles, no
+    implicit tail padding beyond 8-byte alignment)."""
+    assert C.sizeof(P.Config) == 4 * 4 + 3 * 4 + 3 * 4 + 8 * 2 + 8 * 3 + 8 * 3 + 4 * 2 + 8 * 4 + 4 * 4
+    assert C.sizeof(P.Diag) == 8 + 24 + 24 + 8 + 8 * 3 + 8 * 2

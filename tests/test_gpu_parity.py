@@ -1,0 +1,390 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances (floating point, per field; see tests/gpu_helpers.py):
+  FP32 storage: eps_u <= 1e-5, eps_rho <= 1e-6 after one step from an
+                identical state; particles: velocity L2-relative <= 1e-5,
+                displacement max-relative <= 1e-5
+  FP16 storage (deviations scaled by 2^14): eps_u <= 1e-3, eps_rho <= 1e-5
+Integer results (cell-list keys, ids, bin ranges) are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+from tests import gpu_helpers as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1407_6704_amd import pibm
+    pibm.load()
+    return pibm
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_1407_6704_amd import workloads
+    return workloads
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# lattice only
+# ---------------------------------------------------------------------------
+LATTICE_CASES = [
+    (9, "fp32", (67, 45, 1), (0, 0, 0)),
+    (9, "fp32", (64, 33, 1), (1, 0, 0)),
+    (19, "fp32", (19, 13, 11), (0, 0, 0)),
+    (19, "fp32", (16, 9, 12), (1, 0, 1)),
+    (9, "fp16", (67, 45, 1), (0, 0, 0)),
+    (19, "fp16", (19, 13, 11), (0, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("lat,storage,n,per", LATTICE_CASES)
+def test_lattice_steps_match_oracle(P, W, orc, lat, storage, n, per):
+    _flush(f"lattice {lat} {storage} {n} periodic={per}")
+    cfg = P.make_config(lattice=lat, n=n, storage=storage, periodic=per, tau=0.7,
+                        fluid_force=(2e-6, -1e-6, 5e-7 if lat == 19 else 0.0), contact="none")
+    sim = P.Sim(cfg, 0)
+    w = W.C0.replace(lattice=lat, n=n)
+    h0 = G.perturbed_state(orc, sim, w, seed=5)
+    oc = G.oracle_cfg(orc, cfg)
+    N = sim.N
+    F = np.tile(np.array(cfg.fluid_force)[: sim.D, None], (1, N))
+    f = G.to_oracle_f(orc, lat, h0)
+    tol_u, tol_rho = (1e-5, 1e-6) if storage == "fp32" else (1e-3, 1e-5)
+    # one step from an identical state
+    sim.step(1)
+    f1 = orc.collide_stream(oc, f, F)
+    eu, er, eh = G.field_errors(orc, lat, sim.read_populations(), f1, N)
+    _flush(f"  1 step: eps_u={eu:.2e} eps_rho={er:.2e} eps_h={eh:.2e}")
+    assert eu <= tol_u and er <= tol_rho
+    # ten more steps
+    sim.step(10)
+    for _ in range(10):
+        f1 = orc.collide_stream(oc, f1, F)
+    eu, er, eh = G.field_errors(orc, lat, sim.read_populations(), f1, N)
+    _flush(f"  11 steps: eps_u={eu:.2e} eps_rho={er:.2e}")
+    assert eu <= 3 * tol_u and er <= 3 * tol_rho
+
+
+@pytest.mark.parametrize("lat,storage", [(9, "fp32"), (19, "fp32"), (9, "fp16"), (19, "fp16")])
+def test_poiseuille_gpu(P, lat, storage):
+    _flush(f"poiseuille {lat} {storage}")
+    H, Fx, tau = 16, 1e-6, 0.8
+    cfg = P.make_config(lattice=lat, n=(1, H, 1), periodic=(1, 0, 1), storage=storage, tau=tau,
+                        fluid_force=(Fx, 0, 0), contact="none")
+    sim = P.Sim(cfg, 0)
+    nu = (tau - 0.5) / 3
+    sim.step(int(30 * H * H / (np.pi ** 2 * nu)))
+    h = sim.read_populations().astype(np.float64)
+    Q = h.shape[0]
+    from oracle import oracle as orc
+    e, w, _ = orc.tables(lat)
+    dr = h.sum(axis=0)
+    jx = e[:, 0].astype(float) @ h
+    u = (jx + 0.5 * Fx) / (1 + dr)
+    y = np.arange(H) + 0.5
+    lam = (tau - 0.5) ** 2
+    ua = Fx / (2 * nu) * (y * (H - y) + (16 * lam - 3) / 12)
+    err = np.abs(u - ua).max() / ua.max()
+    _flush(f"  max rel err {err:.2e}")
+    # A steady state repeats the same roundings every step, so their bias adds
+    # up over the slowest viscous time T = H^2/(pi^2 nu) (about 260 steps):
+    # relative error <~ T * 2^-p with p = 24 (FP32) or 11 (FP16 storage).
+    T = H * H / (np.pi ** 2 * nu)
+    bound = T * 2.0 ** (-24 if storage == "fp32" else -11)
+    assert err < bound
+
+
+# ---------------------------------------------------------------------------
+# particles
+# ---------------------------------------------------------------------------
+def _random_particles(rng, D, n, npart, dlo=0.3, dhi=0.6, margin=1.0):
+    X = np.stack([rng.uniform(margin, n[a] - margin, npart) for a in range(D)])
+    X = X.astype(np.float32).astype(np.float64)
+    d = rng.uniform(dlo, dhi, npart).astype(np.float32).astype(np.float64)
+    return X, d
+
+
+@pytest.mark.parametrize("lat,n,npart", [(9, (40, 36, 1), 700), (19, (14, 12, 13), 900)])
+def test_cell_list_bit_exact(P, W, orc, lat, n, npart):
+    _flush(f"cell list {lat} {n} {npart}")
+    rng = np.random.default_rng(21)
+    D = 3 if lat == 19 else 2
+    X, d = _random_particles(rng, D, n, npart, margin=0.3)
+    # exact half-integers and node centres stress the floor of X - 1/2
+    X[:, :40] = np.round(X[:, :40] * 2) / 2 + 0.0
+    X[:, 40:60] = np.floor(X[:, 40:60]) + 0.5
+    X[:, 60:70] = X[:, 0:10]                                  # coincident keys, ids decide
+    X = np.clip(X, 0.25, np.array(n[:D])[:, None] - 0.25)
+    cfg = P.make_config(lattice=lat, n=n, contact="none", two_way=0, bin_log2=1)
+    sim = P.Sim(cfg, npart)
+    sim.set_particles(X, np.zeros_like(X), d, np.full(npart, 2.0))
+    sim.step(1)
+    keys, ids, bs = sim.read_cell_list()
+    oc = G.oracle_cfg(orc, cfg)
+    k_ref, p_ref, b_ref = orc.cell_list(oc, X)
+    assert np.array_equal(keys.astype(np.int64), k_ref)
+    assert np.array_equal(ids, p_ref)
+    assert np.array_equal(bs.astype(np.int64), b_ref)
+
+
+def _coupled_compare(P, orc, cfg, X, U, d, rp, h0=None, steps=1, seed=0, tol=None, label=""):
+    sim = P.Sim(cfg, X.shape[1])
+    if h0 is not None:
+        sim.write_populations(h0.astype(np.float32))
+    h0 = sim.read_populations()
+    sim.set_particles(X, U, d, rp)
+    oc = G.oracle_cfg(orc, cfg)
+    f = G.to_oracle_f(orc, cfg.lattice, h0)
+    Xo, Uo = X.copy(), U.copy()
+    for _ in range(steps):
+        out = orc.step(oc, f, Xo, Uo, d, rp)
+        f, Xo, Uo = out["f"], out["X"], out["U"]
+    sim.step(steps)
+    sim.synchronize()
+    got = sim.read_particles()
+    eu, er, eh = G.field_errors(orc, cfg.lattice, sim.read_populations(), f, sim.N)
+    disp = np.abs(Xo - X).max()
+    ex = np.abs(got["x"] - Xo).max() / max(disp, 1e-30)
+    ev = np.linalg.norm(got["v"] - Uo) / max(np.linalg.norm(Uo), 1e-30)
+    fh_ref = -np.pi * d ** 2 / 4 * out["gbar"]
+    efh = np.linalg.norm(got["f_hydro"] - fh_ref) / max(np.linalg.norm(fh_ref), 1e-30)
+    _flush(f"  {label} eps_u={eu:.2e} eps_rho={er:.2e} dX={ex:.2e} (disp {disp:.2e}) "
+           f"dU={ev:.2e} dFh={efh:.2e}")
+    return dict(eu=eu, er=er, ex=ex, ev=ev, efh=efh, sim=sim, out=out, got=got)
+
+
+@pytest.mark.parametrize("lat", [9, 19])
+def test_coupled_step_free_particles(P, W, orc, lat):
+    """Particles away from each other (free: closed-form sub-steps), some
+    near the walls (weights renormalised), on a perturbed fluid."""
+    _flush(f"coupled free {lat}")
+    D = 3 if lat == 19 else 2
+    n = (48, 40, 1) if D == 2 else (20, 18, 16)
+    rng = np.random.default_rng(31)
+    npart = 150 if D == 2 else 200
+    X, d = _random_particles(rng, D, n, npart, 0.3, 0.5, margin=0.4)
+    # push apart anything closer than contact + skin, so every particle is free
+    keep = [0]
+    for i in range(1, npart):
+        r = np.sqrt(((X[:, keep] - X[:, i:i + 1]) ** 2).sum(axis=0))
+        if np.all(r > 0.5 * (d[keep] + d[i]) + 0.2):
+            keep.append(i)
+    X, d = X[:, keep], d[keep]
+    X = np.clip(X, 0.5 * d + 0.06, np.array(n[:D])[:, None] - 0.5 * d - 0.06)
+    X = X.astype(np.float32).astype(np.float64)
+    npart = X.shape[1]
+    U = (1e-4 * rng.standard_normal((D, npart))).astype(np.float32).astype(np.float64)
+    rp = rng.uniform(1.5, 3.0, npart).astype(np.float32).astype(np.float64)
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-5
+    cfg = P.make_config(lattice=lat, n=n, tau=0.7, gravity=g, n_sub=200, contact="lsd")
+    w = W.C0.replace(lattice=lat, n=n)
+    sim0 = P.Sim(P.make_config(lattice=lat, n=n, tau=0.7, contact="none"), 0)
+    h0 = G.perturbed_state(orc, sim0, w, seed=7, amp=1e-4)
+    r = _coupled_compare(P, orc, cfg, X, U, d, rp, h0=h0, steps=1, label="1 step")
+    assert r["eu"] <= 1e-5 and r["er"] <= 1e-6
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["efh"] <= 1e-4
+    assert r["sim"].diagnostics()["active"] == 0
+    r = _coupled_compare(P, orc, cfg, X, U, d, rp, h0=h0, steps=5, label="5 steps")
+    assert r["eu"] <= 3e-5 and r["ex"] <= 3e-5 and r["ev"] <= 3e-5
+
+
+@pytest.mark.parametrize("lat", [9, 19])
+def test_coupled_step_with_contacts(P, orc, lat):
+    """Clusters of touching and approaching particles (islands of several
+    sizes, wall contacts), linear spring-dashpot, several steps."""
+    _flush(f"coupled contacts {lat}")
+    D = 3 if lat == 19 else 2
+    n = (40, 30, 1) if D == 2 else (16, 14, 18)
+    rng = np.random.default_rng(41)
+    blocks = []
+    ds = []
+    # clusters: k particles on a jittered line with gaps ~0.01 (k = 2..6)
+    for c in range(12 if D == 2 else 10):
+        k = 2 + c % 5
+        base = np.array([rng.uniform(3, n[a] - 3 - 0.5 * k) for a in range(D)])
+        for i in range(k):
+            p = base.copy()
+            p[0] += 0.501 * i
+            blocks.append(p)
+            ds.append(0.5)
+    # wall contacts: particles just touching the bottom wall
+    for i in range(6):
+        p = np.array([rng.uniform(2, n[a] - 2) for a in range(D)])
+        p[D - 1] = 0.24999
+        blocks.append(p)
+        ds.append(0.5)
+    X = np.array(blocks).T.astype(np.float32).astype(np.float64)
+    d = np.array(ds)
+    npart = X.shape[1]
+    U = (3e-4 * rng.standard_normal((D, npart))).astype(np.float32).astype(np.float64)
+    rp = np.full(npart, 2.5)
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-5
+    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact="lsd")
+    r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=1, label="1 step")
+    assert r["sim"].diagnostics()["active"] > 0
+    assert r["eu"] <= 1e-5 and r["er"] <= 1e-6
+    assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4
+    r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=4, label="4 steps")
+    assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4 and r["eu"] <= 1e-4
+
+
+def test_big_island(P, orc):
+    """150 particles linked by candidate pairs form one island larger than a
+    wave.  Gaps alternate 2e-4 (pairs that collide head-on within the step)
+    and 4e-3 (links that stay open), so the outcome is well conditioned.  (A
+    chain of touching particles is not: a 1e-11 change of one position moves
+    the FP64 result by 5e-4 within two steps.)"""
+    _flush("big island")
+    n = (200, 12, 1)
+    k = 150
+    x = [10.0]
+    for i in range(1, k):
+        x.append(x[-1] + 0.5 + (0.0002 if i % 2 == 1 else 0.004))
+    X = np.zeros((2, k))
+    X[0] = x
+    X[1] = 6.0
+    X = X.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(3)
+    U = np.zeros((2, k))
+    U[0, 0::2], U[0, 1::2] = 1e-3, -1e-3
+    U = (U + 1e-5 * rng.standard_normal((2, k))).astype(np.float32).astype(np.float64)
+    d = np.full(k, 0.5)
+    cfg = P.make_config(lattice=9, n=n, tau=0.8, gravity=(0, -1e-5, 0), n_sub=300, contact="lsd")
+    r = _coupled_compare(P, orc, cfg, X, U, d, np.full(k, 2.5), steps=1, label="chain")
+    assert r["sim"].diagnostics()["active"] == k
+    assert np.abs(r["got"]["f_contact"]).max() > 0
+    assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4 and r["eu"] <= 1e-5
+
+
+def test_soft_contact_parity(P, orc):
+    _flush("soft contacts")
+    n = (32, 32, 1)
+    rng = np.random.default_rng(8)
+    X = np.array([[10.0, 10.45, 20.0, 20.3, 15.0], [10.0, 10.05, 20.0, 20.2, 0.3]])
+    X = X.astype(np.float32).astype(np.float64)
+    U = (1e-3 * rng.standard_normal((2, 5))).astype(np.float32).astype(np.float64)
+    cfg = P.make_config(lattice=9, n=n, tau=0.7, gravity=(0, -1e-5, 0), n_sub=1, contact="soft",
+                        k_soft=1e-3)
+    r = _coupled_compare(P, orc, cfg, X, U, np.full(5, 0.5), np.full(5, 2.5), steps=3, label="soft")
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["eu"] <= 1e-5
+
+
+def test_c0_workload_100_steps(P, W, orc):
+    """The 128^2 / 200-particle sedimentation case, 100 steps from rest."""
+    _flush("c0 100 steps")
+    w = W.C0
+    X, U, d, rp = W.make_particles(w)
+    cfg = P.config_from_workload(w)
+    r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=100, label="c0")
+    assert r["eu"] <= 1e-4 and r["er"] <= 1e-6
+    assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4
+
+
+def test_deterministic_and_resume(P, W, orc):
+    _flush("determinism + resume")
+    w = W.C0.replace(n=(64, 64, 1), n_particles=300, region=(0.3, 1.0), seed=11)
+    X, U, d, rp = W.make_particles(w)
+    cfg = P.config_from_workload(w, n_sub=100)
+
+    def run(steps, state=None):
+        sim = P.Sim(cfg, X.shape[1])
+        if state is None:
+            sim.set_particles(X, U, d, rp)
+        else:
+            sim.write_populations(state[0])
+            sim.set_particles(state[1], state[2], d, rp)
+        sim.step(steps)
+        p = sim.read_particles()
+        return sim.read_populations(), p["x"], p["v"]
+
+    a = run(20)
+    b = run(20)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    mid = run(10)
+    c = run(10, state=mid)
+    assert np.array_equal(a[0], c[0])
+    assert np.array_equal(a[1], c[1]) and np.array_equal(a[2], c[2])
+
+
+def test_conservation_and_momentum(P, W, orc):
+    """FP64 totals on the GPU against the oracle's, and the momentum balance
+    while the disturbance stays away from the walls."""
+    _flush("conservation")
+    n = (48, 48, 1)
+    rng = np.random.default_rng(12)
+    npart = 40
+    X = np.stack([rng.uniform(18, 30, npart), rng.uniform(18, 30, npart)])
+    keep = [0]
+    for i in range(1, npart):
+        r = np.sqrt(((X[:, keep] - X[:, i:i + 1]) ** 2).sum(axis=0))
+        if np.all(r > 0.5):
+            keep.append(i)
+    X = X[:, keep].astype(np.float32).astype(np.float64)
+    npart = X.shape[1]
+    d = np.full(npart, 0.4)
+    rp = np.full(npart, 2.5)
+    U = np.zeros_like(X)
+    cfg = P.make_config(lattice=9, n=n, tau=0.8, gravity=(0, -1e-5, 0), n_sub=50)
+    sim = P.Sim(cfg, npart)
+    sim.set_particles(X, U, d, rp)
+    m0, p0 = sim.conservation()
+    steps = 8
+    sim.step(steps)
+    m1, p1 = sim.conservation()
+    N = sim.N
+    assert abs(m0 - N) < 1e-9
+    assert abs(m1 - m0) < steps * 9 * N * 2.0 ** -24 * 1e-4
+    m = rp * np.pi * d ** 2 / 4
+    Wsum = ((1 - 1 / rp) * m * cfg.gravity[1]).sum()
+    assert abs((p1[1] - p0[1]) - steps * Wsum) < 1e-6 * abs(steps * Wsum)
+    assert abs(p1[0] - p0[0]) < 1e-6 * abs(steps * Wsum)
+    # the same totals from the oracle's state after the same steps
+    oc = G.oracle_cfg(orc, cfg)
+    f = orc.rest_state(oc)
+    Xo, Uo = X.copy(), U.copy()
+    for _ in range(steps):
+        out = orc.step(oc, f, Xo, Uo, d, rp)
+        f, Xo, Uo = out["f"], out["X"], out["U"]
+    e, w, _ = orc.tables(9)
+    hdev = f.reshape(9, N) - w[:, None]
+    p_ref = e[:, 1].astype(float) @ hdev.sum(axis=1) + (m * Uo[1]).sum()
+    assert abs(p1[1] - p_ref) < 1e-5 * abs(p_ref)
+    diag = sim.diagnostics()
+    assert diag["nonfinite"] == 0 and diag["max_speed"] < 0.1
+
+
+def test_skin_violation_is_reported(P):
+    _flush("skin flag")
+    cfg = P.make_config(lattice=9, n=(16, 16, 1), tau=0.8, n_sub=10, contact="lsd", skin=0.05)
+    sim = P.Sim(cfg, 2)
+    X = np.array([[4.0, 10.0], [8.0, 8.0]])
+    U = np.array([[0.0, 0.04], [0.0, 0.0]])
+    sim.set_particles(X, U, np.full(2, 0.4), np.full(2, 2.5))
+    sim.step(1)
+    with pytest.raises(P.PibmError) as ei:
+        sim.synchronize()
+    assert ei.value.name == "E_SKIN"
+    sim.synchronize()                                           # latched flag was cleared
+
+
+def test_particle_outside_box_rejected(P):
+    cfg = P.make_config(lattice=9, n=(16, 16, 1))
+    sim = P.Sim(cfg, 1)
+    with pytest.raises(P.PibmError) as ei:
+        sim.set_particles(np.array([[17.0], [3.0]]), None, np.array([0.4]), np.array([2.5]))
+    assert ei.value.name == "E_ARG"
