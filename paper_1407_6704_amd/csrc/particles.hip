@@ -143,7 +143,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_bin_count(PState A, int np, PCfg c, uint32_t* __restrict__ cnt,
                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ slot,
                                                    uint32_t* __restrict__ flags) {
-    int s = blockIdx.x * 256 + threadIdx.x;
+    int s = xcd_block() * 256 + threadIdx.x;
     if (s >= np) return;
     int b[3] = {0, 0, 0};
     bool inside = true;
@@ -171,8 +171,9 @@ template <int D>
 __global__ __launch_bounds__(256) void k_reorder(PState A, PState B, const uint32_t* __restrict__ keys,
                                                  const uint32_t* __restrict__ start,
                                                  const uint32_t* __restrict__ tmp,
-                                                 uint32_t* __restrict__ keys_sorted, int np) {
-    int s = blockIdx.x * 256 + threadIdx.x;
+                                                 uint32_t* __restrict__ keys_sorted, float4* __restrict__ pos4,
+                                                 int np) {
+    int s = xcd_block() * 256 + threadIdx.x;
     if (s >= np) return;
     uint32_t k = keys[s];
     uint32_t b0 = start[k], b1 = start[k + 1];
@@ -190,6 +191,8 @@ __global__ __launch_bounds__(256) void k_reorder(PState A, PState B, const uint3
     B.rp[o] = A.rp[s];
     B.id[o] = myid;
     keys_sorted[o] = k;
+    // leading parts of the position and the diameter, for neighbour screening
+    pos4[o] = make_float4(A.xh[0][s], A.xh[1][s], D == 3 ? A.xh[2][s] : 0.f, A.d[s]);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,7 +222,7 @@ __global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const 
                                                 float* __restrict__ drho_i, float* __restrict__ j_i,
                                                 short4* __restrict__ wbase, float* __restrict__ wphi) {
     constexpr int LP = (D == 3) ? 16 : 4;   // lanes per particle
-    long long gt = (long long)blockIdx.x * 256 + threadIdx.x;
+    long long gt = (long long)xcd_block() * 256 + threadIdx.x;
     int s = (int)(gt / LP);
     int l = (int)(gt % LP);
     bool valid = s < np;
@@ -277,19 +280,20 @@ __global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const 
 // within (d_s + d_t)/2 + thr.  Collect mode: the candidates that are active,
 // in scan order (bins ascending, sorted order within a bin).
 template <int D, bool COLLECT>
-__device__ __forceinline__ int scan_neighbours(const PState& A, const uint32_t* __restrict__ start, const PCfg& c,
-                                               int s, float thr, bool& close,
+__device__ __forceinline__ int scan_neighbours(const float4* __restrict__ pos4, const uint32_t* __restrict__ start,
+                                               const uint32_t* __restrict__ keys_sorted,
+                                               const PCfg& c, int s, float thr, bool& close,
                                                const unsigned long long* __restrict__ actcc, uint32_t* list,
                                                int cap) {
-    float xh[3] = {0, 0, 0}, xl[3] = {0, 0, 0};
-    int b[3] = {0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < D; a++) {
-        xh[a] = A.xh[a][s];
-        xl[a] = A.xl[a][s];
-        b[a] = bin_of(c, xh[a], xl[a], a);
-    }
-    float ds = A.d[s];
+    // Screening uses the leading FP32 parts of the positions; c.eps bounds
+    // the neglected trailing parts, and every test is widened by it (more
+    // candidates or more active particles only cost time).
+    const float4 me = pos4[s];
+    const uint32_t key = keys_sorted[s];
+    int b[3];
+    b[0] = (int)(key % (uint32_t)c.nb[0]);
+    b[1] = (int)((key / (uint32_t)c.nb[0]) % (uint32_t)c.nb[1]);
+    b[2] = (int)(key / ((uint32_t)c.nb[0] * (uint32_t)c.nb[1]));
     int cnt = 0;
     int zl = (D == 3) ? max(b[2] - 1, 0) : 0, zh = (D == 3) ? min(b[2] + 1, c.nb[2] - 1) : 0;
     for (int bz = zl; bz <= zh; bz++)
@@ -300,18 +304,15 @@ __device__ __forceinline__ int scan_neighbours(const PState& A, const uint32_t* 
             uint32_t t0 = start[row + bxl], t1 = start[row + bxh + 1];
             for (uint32_t t = t0; t < t1; t++) {
                 if ((int)t == s) continue;
-                float r2 = 0.f;
-#pragma unroll
-                for (int a = 0; a < D; a++) {
-                    float dx = (xh[a] - A.xh[a][t]) + (xl[a] - A.xl[a][t]);
-                    r2 += dx * dx;
-                }
-                float rc = 0.5f * (ds + A.d[t]);
-                float cut = rc + c.skin;
+                const float4 o = pos4[t];
+                float dx = me.x - o.x, dy = me.y - o.y, dz = (D == 3) ? me.z - o.z : 0.f;
+                float r2 = dx * dx + dy * dy + dz * dz;
+                float rc = 0.5f * (me.w + o.w);
+                float cut = rc + c.skin + c.eps;
                 if (r2 < cut * cut) {
                     if (!COLLECT) {
                         cnt++;
-                        float lim = rc + thr;
+                        float lim = rc + thr + c.eps;
                         if (r2 <= lim * lim) close = true;
                     } else if (actcc[t] != 0ULL) {
                         if (cnt < cap) list[cnt] = t;
@@ -334,11 +335,13 @@ __device__ __forceinline__ int scan_neighbours(const PState& A, const uint32_t* 
 template <int D>
 __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, PCfg c,
                                                   const uint32_t* __restrict__ start,
+                                                  const float4* __restrict__ pos4,
+                                                  const uint32_t* __restrict__ keys_sorted,
                                                   const float* __restrict__ drho_i, const float* __restrict__ j_i,
                                                   float* __restrict__ coef, float* __restrict__ fc,
                                                   unsigned long long* __restrict__ actcc,
                                                   uint32_t* __restrict__ flags) {
-    int s = blockIdx.x * 256 + threadIdx.x;
+    int s = xcd_block() * 256 + threadIdx.x;
     if (s >= np) return;
     float d = A.d[s], rp = A.rp[s];
     float m = particle_mass(D, d, rp);
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
     float B = sqrtf(fmaxf(v0s, vns));
     if (c.contact != PIBM_CONTACT_NONE) {
         bool close = false;
-        int cnt = scan_neighbours<D, false>(A, start, c, s, B + 0.5f * c.skin, close, nullptr, nullptr, 0);
+        int cnt = scan_neighbours<D, false>(pos4, start, keys_sorted, c, s, B + 0.5f * c.skin, close, nullptr, nullptr, 0);
         bool wall = false;
 #pragma unroll
         for (int a = 0; a < D; a++) {
@@ -403,12 +406,14 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
 // free partner provably never touches), union-find init
 template <int D>
 __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const uint32_t* __restrict__ start,
+                                                 const float4* __restrict__ pos4,
+                                                 const uint32_t* __restrict__ keys_sorted,
                                                  const unsigned long long* __restrict__ actcc,
                                                  const unsigned long long* __restrict__ prefix,
                                                  uint32_t* __restrict__ alist, uint32_t* __restrict__ aidx,
                                                  uint32_t* __restrict__ cand, uint32_t* __restrict__ ccount,
                                                  uint32_t* __restrict__ parent) {
-    int s = blockIdx.x * 256 + threadIdx.x;
+    int s = xcd_block() * 256 + threadIdx.x;
     if (s >= np) return;
     unsigned long long v = actcc[s];
     if (v == 0ULL) return;
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const
     aidx[s] = a;
     parent[a] = a;
     bool dummy = false;
-    int n = cap > 0 ? scan_neighbours<D, true>(A, start, c, s, 0.f, dummy, actcc, cand + off, cap) : 0;
+    int n = cap > 0 ? scan_neighbours<D, true>(pos4, start, keys_sorted, c, s, 0.f, dummy, actcc, cand + off, cap) : 0;
     ccount[s] = (uint32_t)min(n, cap);
 }
 
@@ -534,6 +539,7 @@ __global__ __launch_bounds__(256) void k_cand_prep(PState A, PCfg c, const uint3
                                                    const uint32_t* __restrict__ cand, const uint32_t* __restrict__ aidx,
                                                    const uint32_t* __restrict__ loc, CandData* __restrict__ cdata,
                                                    const uint32_t* __restrict__ counters) {
+#pragma clang fp contract(off)
     uint32_t na = counters[CNT_ACTIVE];
     for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
         uint32_t s = alist[a];
@@ -727,6 +733,7 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
     float v2 = 0.f;
 #pragma unroll
     for (int a = 0; a < D; a++) {
+#pragma clang fp contract(off)
         float g = 2.0f * (P.ri * P.u[a] - P.j[a]);
         P.gs[a] += g;
         P.fs[a] += F[a];
@@ -825,6 +832,7 @@ __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m) 
     float v2 = 0.f;
 #pragma unroll
     for (int a = 0; a < D; a++) {
+#pragma clang fp contract(off)
         const float diff = (P.u[a] - P.ueq[a]) - P.cu[a];
         const float incx = c.h * (mm * P.ueq[a] + diff * (q * S));
         float yx = incx - P.cdx[a];
@@ -1005,29 +1013,28 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
 // terms in the same fixed order, with no atomics.
 // ---------------------------------------------------------------------------
 template <int D> struct SpreadTile;
-template <> struct SpreadTile<3> { static constexpr int TX = 16, TY = 8, TZ = 4; };
-template <> struct SpreadTile<2> { static constexpr int TX = 64, TY = 8, TZ = 1; };
-
-__device__ __forceinline__ float rl(float v, int j) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
-}
-__device__ __forceinline__ int rl(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+// LDS strides are padded so that the 4^D support nodes of one particle fall
+// in distinct banks: 3D offset kx + 16 ky + 132 kz = kx + 16 ky + 4 kz (mod 64).
+template <> struct SpreadTile<3> { static constexpr int TX = 16, TY = 8, TZ = 4, SY = 16, SZ = 132; };
+template <> struct SpreadTile<2> { static constexpr int TX = 64, TY = 8, TZ = 1, SY = 68, SZ = 68 * 8; };
 
 template <int D>
 __global__ __launch_bounds__(64) void k_spread(Grid g, PCfg c, const uint32_t* __restrict__ start,
                                                const short4* __restrict__ wbase, const float* __restrict__ wphi,
                                                const float* __restrict__ coef, int np, float* __restrict__ F,
                                                int ntx, int nty) {
-    constexpr int TX = SpreadTile<D>::TX, TY = SpreadTile<D>::TY, TZ = SpreadTile<D>::TZ;
-    constexpr int TN = TX * TY * TZ;
-    __shared__ float acc[D * TN];
+    using T = SpreadTile<D>;
+    constexpr int TX = T::TX, TY = T::TY, TZ = T::TZ, SY = T::SY, SZ = T::SZ;
+    constexpr int TL = SZ * TZ;              // padded floats per component
+    constexpr int PW = 16;                   // staged floats per particle: 12 weights, 3 coefficients, base
+    __shared__ float acc[D * TL];
+    __shared__ float sp[WAVE * PW];
     const int lane = threadIdx.x;
-    const int tile = blockIdx.x;
+    const int tile = (int)xcd_block();
     const int tx = tile % ntx, t2 = tile / ntx;
     const int ty = t2 % nty, tz = t2 / nty;
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-    for (int i = lane; i < D * TN; i += WAVE) acc[i] = 0.f;
-    __syncthreads();
+    for (int i = lane; i < D * TL; i += WAVE) acc[i] = 0.f;
 
     // halo bins: a particle in dual cell cd reaches nodes cd-1 .. cd+2
     const int bx0 = max((x0 - 1) >> c.L, 0), bx1 = min((x0 + TX + 1) >> c.L, c.nb[0] - 1);
@@ -1043,55 +1050,66 @@ __global__ __launch_bounds__(64) void k_spread(Grid g, PCfg c, const uint32_t* _
             const uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
             const uint32_t s0 = start[row + bx0], s1 = start[row + bx1 + 1];
             for (uint32_t ch = s0; ch < s1; ch += WAVE) {
+                // stage up to 64 particles (coalesced loads)
+                __syncthreads();
                 const uint32_t idx = ch + lane;
-                const bool v = idx < s1;
-                const uint32_t li = v ? idx : s0;
-                short4 b = wbase[li];
-                float ph[4 * D], cf[D];
+                if (idx < s1) {
+                    float* q = sp + lane * PW;
 #pragma unroll
-                for (int k = 0; k < 4 * D; k++) ph[k] = wphi[(long long)li * (4 * D) + k];
+                    for (int k = 0; k < 4 * D; k++) q[k] = wphi[(long long)idx * (4 * D) + k];
 #pragma unroll
-                for (int a = 0; a < D; a++) cf[a] = coef[(long long)a * np + li];
-                const int bxi = b.x, byi = b.y, bzi = b.z;
+                    for (int a = 0; a < D; a++) q[12 + a] = coef[(long long)a * np + idx];
+                    short4 bb = wbase[idx];
+                    // base relative to the tile origin, packed in 3 x 10 bits (offsets in [-3, 16])
+                    int pk = ((bb.x - x0 + 512) & 1023) | (((bb.y - y0 + 512) & 1023) << 10) |
+                             (((D == 3 ? bb.z - z0 : 0) + 512) & 1023) << 20;
+                    q[15] = __int_as_float(pk);
+                }
+                __syncthreads();
                 const int cnt = (int)min((uint32_t)WAVE, s1 - ch);
+                // next particle's data is fetched one iteration ahead
+                const float* q0 = sp;
+                int pk = __float_as_int(q0[15]);
+                float wx = q0[kx], wy = q0[4 + ky], wz = (D == 3) ? q0[8 + kz] : 1.f;
+                float c0 = q0[12], c1 = q0[13], c2 = (D == 3) ? q0[14] : 0.f;
                 for (int j = 0; j < cnt; j++) {
-                    const int lx = rl(bxi, j) + kx - x0;
-                    const int ly = rl(byi, j) + ky - y0;
-                    const int lz = (D == 3) ? rl(bzi, j) + kz - z0 : 0;
-                    float wx = rl(ph[0], j), wy = rl(ph[4], j), wz = 1.f;
-                    // select this lane's weights among the particle's four per axis
-                    {
-                        float p1 = rl(ph[1], j), p2 = rl(ph[2], j), p3 = rl(ph[3], j);
-                        wx = kx == 0 ? wx : (kx == 1 ? p1 : (kx == 2 ? p2 : p3));
-                        float q1 = rl(ph[5], j), q2 = rl(ph[6], j), q3 = rl(ph[7], j);
-                        wy = ky == 0 ? wy : (ky == 1 ? q1 : (ky == 2 ? q2 : q3));
+                    const int pkc = pk;
+                    const float W = wx * wy * wz, cx = c0, cy = c1, cz = c2;
+                    if (j + 1 < cnt) {
+                        const float* qn = sp + (j + 1) * PW;
+                        pk = __float_as_int(qn[15]);
+                        wx = qn[kx];
+                        wy = qn[4 + ky];
+                        if (D == 3) wz = qn[8 + kz];
+                        c0 = qn[12];
+                        c1 = qn[13];
+                        if (D == 3) c2 = qn[14];
                     }
-                    if (D == 3) {
-                        float z0w = rl(ph[8 % (4 * D)], j), z1 = rl(ph[9 % (4 * D)], j);
-                        float z2 = rl(ph[10 % (4 * D)], j), z3 = rl(ph[11 % (4 * D)], j);
-                        wz = kz == 0 ? z0w : (kz == 1 ? z1 : (kz == 2 ? z2 : z3));
-                    }
-                    float cx = rl(cf[0], j), cy = rl(cf[1 % D], j), cz = (D == 3) ? rl(cf[2 % D], j) : 0.f;
+                    const int lx = (pkc & 1023) - 512 + kx;
+                    const int ly = ((pkc >> 10) & 1023) - 512 + ky;
+                    const int lz = (D == 3) ? ((pkc >> 20) & 1023) - 512 + kz : 0;
                     const bool in = lane_on && (unsigned)lx < (unsigned)TX && (unsigned)ly < (unsigned)TY &&
                                     (unsigned)lz < (unsigned)TZ;
                     if (in) {
-                        const float W = wx * wy * wz;
-                        const int li2 = (lz * TY + ly) * TX + lx;
-                        acc[li2] += W * cx;
-                        acc[TN + li2] += W * cy;
-                        if (D == 3) acc[2 * TN + li2] += W * cz;
+                        // one wave: LDS operations complete in issue order, so each
+                        // node receives its terms in particle order
+                        const int li = lz * SZ + ly * SY + lx;
+                        acc[li] += W * cx;
+                        acc[TL + li] += W * cy;
+                        if (D == 3) acc[2 * TL + li] += W * cz;
                     }
                 }
             }
         }
     __syncthreads();
-    for (int i = lane; i < TN; i += WAVE) {
+    for (int i = lane; i < TX * TY * TZ; i += WAVE) {
         const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
         const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
         if (x < g.n[0] && y < g.n[1] && z < g.n[2]) {
             const long long r = ((long long)z * g.n[1] + y) * g.n[0] + x;
+            const int li = lz * SZ + ly * SY + lx;
 #pragma unroll
-            for (int a = 0; a < D; a++) F[(long long)a * g.N + r] = acc[a * TN + i];
+            for (int a = 0; a < D; a++) F[(long long)a * g.N + r] = acc[a * TL + li];
         }
     }
 }
@@ -1171,9 +1189,9 @@ void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
     scan_exclusive<uint32_t>(b.cnt, b.start, nbins + 1, b.scan_u32, nullptr, s);
     hipLaunchKernelGGL(k_scatter, dim3(nb256(np)), dim3(256), 0, s, b.keys, b.slot, b.start, b.tmp, np);
     if (D == 3)
-        hipLaunchKernelGGL(k_reorder<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, np);
+        hipLaunchKernelGGL(k_reorder<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, b.pos4, np);
     else
-        hipLaunchKernelGGL(k_reorder<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, np);
+        hipLaunchKernelGGL(k_reorder<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, b.pos4, np);
     PState t = b.A;
     b.A = b.B;
     b.B = t;
@@ -1191,12 +1209,12 @@ template <int D>
 static void dem_impl(PBuf& b, int np, const PCfg& c, hipStream_t s) {
     const unsigned grid_act = std::min<unsigned>(nb256(np), 2048u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, b.counters, (long long)CNT_SIZE, 0u);
-    hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.drho_i, b.j_i,
+    hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.pos4, b.keys_sorted, b.drho_i, b.j_i,
                        b.coef, b.fc, b.actcc, b.flags);
     // exclusive scan of (active << 32 | candidates); total -> counters[0..1]
     scan_exclusive<unsigned long long>(b.actcc, b.prefix, np, b.scan_u64,
                                        (unsigned long long*)(void*)b.counters, s);
-    hipLaunchKernelGGL(k_collect<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.actcc, b.prefix,
+    hipLaunchKernelGGL(k_collect<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.pos4, b.keys_sorted, b.actcc, b.prefix,
                        b.alist, b.aidx, b.cand, b.ccount, b.parent);
     hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, b.isize, b.counters + CNT_ACTIVE, 1, 0u, (long long)np);
     hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, b.fill, b.counters + CNT_ACTIVE, 1, 0u, (long long)np);

@@ -74,18 +74,23 @@ struct Grid {
 
 // ---------------------------------------------------------------------------
 // Double-float helpers (value = hi + lo, |lo| <= ulp(hi)/2), FP32 only.
+// Error-free transformations must not be contracted into FMAs, hence the
+// contract(off) pragmas here and wherever such sequences appear.
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
     s = a + b;
     float bb = s - a;
     e = (a - (s - bb)) + (b - bb);
 }
 __host__ __device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
     s = a + b;
     e = b - (s - a);
 }
 // (hi, lo) += d
 __host__ __device__ __forceinline__ void df_add(float& hi, float& lo, float d) {
+#pragma clang fp contract(off)
     float s, e;
     two_sum(hi, d, s, e);
     e += lo;
@@ -137,6 +142,18 @@ enum {
 };
 
 constexpr int WAVE = 64;
+constexpr unsigned NUM_XCD = 8;
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Map dispatch index b (on XCD b % 8) to a logical block so that every
+// XCD works on one contiguous eighth of the index space: neighbouring nodes
+// and neighbouring sorted particles then share an L2.  A bijection.
+__device__ __forceinline__ unsigned xcd_block() {
+    const unsigned n = gridDim.x, b = blockIdx.x;
+    const unsigned per = n / NUM_XCD, rem = n % NUM_XCD;
+    const unsigned x = b % NUM_XCD, i = b / NUM_XCD;
+    return x * per + min(x, rem) + i;
+}
 constexpr float PI_F = 3.14159265358979323846f;
 
 // Particle-side constants of one configuration.
@@ -154,6 +171,7 @@ struct PCfg {
     float rho0;
     float g[3];
     int maxc;
+    float eps;          // bound on the trailing position parts left out by screening
 };
 
 // Per-candidate constants of the active sub-steps.
@@ -169,6 +187,7 @@ struct CandData {
 struct PBuf {
     PState A, B, Bn;             // current, reorder target, next (after DEM)
     uint32_t *cnt, *start, *keys, *slot, *tmp, *keys_sorted;
+    float4* pos4;                // (x, y, z) leading parts and d, sorted order
     uint32_t* scan_u32;          // scan block sums
     unsigned long long *actcc, *prefix, *scan_u64;
     float *drho_i, *j_i, *wphi, *coef, *fc;

@@ -159,6 +159,7 @@ size_t carve(pibm_ctx& c, char* base) {
         b.slot = cv.take<uint32_t>(np);
         b.tmp = cv.take<uint32_t>(np);
         b.keys_sorted = cv.take<uint32_t>(np);
+        b.pos4 = cv.take<float4>(np);
         b.scan_u32 = cv.take<uint32_t>(scan_blocks(nb1) + 1);
         b.scan_u64 = cv.take<unsigned long long>(scan_blocks(np) + 1);
         b.actcc = cv.take<unsigned long long>(np);
@@ -213,6 +214,10 @@ void fill_pcfg(pibm_ctx& c) {
     p.rho0 = (float)c.cfg.rho0;
     for (int a = 0; a < 3; a++) p.g[a] = (float)c.cfg.gravity[a];
     p.maxc = c.cfg.max_candidates;
+    // trailing parts are at most half an ulp of the leading ones; the
+    // screened distance is off by at most sqrt(D) ulp(max extent)
+    int nmax = std::max(c.cfg.n[0], std::max(c.cfg.n[1], c.cfg.n[2]));
+    p.eps = (float)(std::sqrt((double)c.D) * std::ldexp(1.0, (int)std::ceil(std::log2((double)nmax + 1.0)) - 23));
 }
 
 bool init_ctx(pibm_ctx& c, const pibm_config* cfg, int64_t np) {

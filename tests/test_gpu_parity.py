@@ -243,15 +243,15 @@ def test_coupled_step_with_contacts(P, orc, lat):
     assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4 and r["eu"] <= 1e-4
 
 
-def test_big_island(P, orc):
+@pytest.mark.parametrize("k", [60, 150])
+def test_big_island(P, orc, k):
     """150 particles linked by candidate pairs form one island larger than a
     wave.  Gaps alternate 2e-4 (pairs that collide head-on within the step)
     and 4e-3 (links that stay open), so the outcome is well conditioned.  (A
     chain of touching particles is not: a 1e-11 change of one position moves
     the FP64 result by 5e-4 within two steps.)"""
-    _flush("big island")
+    _flush(f"island chain k={k}")
     n = (200, 12, 1)
-    k = 150
     x = [10.0]
     for i in range(1, k):
         x.append(x[-1] + 0.5 + (0.0002 if i % 2 == 1 else 0.004))
@@ -266,6 +266,8 @@ def test_big_island(P, orc):
     d = np.full(k, 0.5)
     cfg = P.make_config(lattice=9, n=n, tau=0.8, gravity=(0, -1e-5, 0), n_sub=300, contact="lsd")
     r = _coupled_compare(P, orc, cfg, X, U, d, np.full(k, 2.5), steps=1, label="chain")
+    dv = np.abs(r["got"]["v"] - r["out"]["U"]).max(axis=0)
+    _flush(f"  worst particles {np.argsort(dv)[-5:].tolist()} dv {np.sort(dv)[-5:].tolist()}")
     assert r["sim"].diagnostics()["active"] == k
     assert np.abs(r["got"]["f_contact"]).max() > 0
     assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4 and r["eu"] <= 1e-5
