@@ -92,9 +92,9 @@ typedef struct {
     double kn;                /* linear spring stiffness */
     double restitution;       /* normal restitution of the linear spring-dashpot, (0, 1] */
     double k_soft;            /* soft repulsion k_s (1 - r/r_c)^2 */
-    double skin;              /* candidate-list skin; max d + skin <= 2^bin_log2 */
+    double skin;              /* candidate-list skin: particles may move <= skin/2 per step */
     int32_t two_way;          /* 1: spread the particle forces onto the fluid */
-    int32_t bin_log2;         /* bin edge in node spacings, 0 .. 3 */
+    int32_t bin_log2;         /* cell-list bin edge 2^bin_log2 node spacings, 0 .. 3 (0: fastest spreading) */
     int32_t max_candidates;   /* per-particle candidate capacity, 1 .. 64 */
     int32_t reserved;         /* 0 */
 } pibm_config;

@@ -419,9 +419,10 @@ static void wall_force(const orc_cfg *c, int D, const double *X, const double *U
 }
 
 /* Candidate pairs: every unordered pair with |X_p - X_q| < (d_p+d_q)/2 + skin,
- * found through the bins of orc_cell_list (bin edge >= cutoff + skin, so the
- * 3^D neighbouring bins suffice).  Writes up to cap pairs (p < q) and returns
- * the total count. */
+ * found through the bins of orc_cell_list: the (2H+1)^D bins around a
+ * particle, H = ceil((d_max + skin) / bin edge), hold every particle within
+ * the largest cutoff.  Writes up to cap pairs (p < q) and returns the total
+ * count. */
 int64_t orc_candidate_pairs(const orc_cfg *c, int np, const double *X, const double *d,
                             int *pairs, int64_t cap)
 {
@@ -432,14 +433,20 @@ int64_t orc_candidate_pairs(const orc_cfg *c, int np, const double *X, const dou
     int *perm = malloc(sizeof(int) * (np > 0 ? np : 1));
     int64_t *bs = malloc(sizeof(int64_t) * (nbins + 1));
     orc_cell_list(c, np, X, keys, perm, bs);
+    /* the neighbouring bins must cover the largest cutoff */
+    double dmax = 0;
+    for (int p = 0; p < np; p++)
+        if (d[p] > dmax) dmax = d[p];
+    int H = (int)ceil((dmax + c->skin) / (double)(1 << c->bin_log2));
+    if (H < 1) H = 1;
     int64_t count = 0;
     for (int p = 0; p < np; p++) {
         int64_t b[3] = {0, 0, 0};
         for (int a = 0; a < D; a++) b[a] = bin_coord(c, X[a * np + p]);
         int lo[3], hi[3];
         for (int a = 0; a < 3; a++) {
-            lo[a] = (a < D) ? -1 : 0;
-            hi[a] = (a < D) ? 1 : 0;
+            lo[a] = (a < D) ? -H : 0;
+            hi[a] = (a < D) ? H : 0;
         }
         for (int oz = lo[2]; oz <= hi[2]; oz++)
             for (int oy = lo[1]; oy <= hi[1]; oy++)

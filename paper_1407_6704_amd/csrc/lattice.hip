@@ -23,7 +23,7 @@ template <int Q, class S>
 __global__ __launch_bounds__(256) void k_moments(const typename S::T* __restrict__ f,
                                                  float4* __restrict__ mom, long long N, S st) {
     using L = Lattice<Q>;
-    long long r = (long long)xcd_block() * 256 + threadIdx.x;
+    long long r = (long long)blockIdx.x * 256 + threadIdx.x;
     if (r >= N) return;
     float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_collide(const typename S::T* __restrict
                                                  float omega, float fpref, S st) {
     using L = Lattice<Q>;
     const long long N = g.N;
-    long long r = (long long)xcd_block() * 256 + threadIdx.x;
+    long long r = (long long)blockIdx.x * 256 + threadIdx.x;
     if (r >= N) return;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int x = (int)(r % nx);

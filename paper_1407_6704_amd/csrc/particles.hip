@@ -272,6 +272,113 @@ __global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const 
     }
 }
 
+// Interpolation by tiles: a workgroup owns a box of bins; the sorted
+// particles of those bins are contiguous per bin row.  It stages the moment
+// field of every node those particles can reach (the box of nodes plus a
+// halo of 2 below and 1 above, in dual-cell terms) in LDS once, then each
+// thread gathers one particle's 4^D support from LDS.  Tiles without
+// particles return before loading anything.
+// tile extent in dual cells (bins hold 2^L cells per axis)
+template <int D> struct InterpTile;
+template <> struct InterpTile<3> { static constexpr int CX = 16, CY = 8, CZ = 4; };
+template <> struct InterpTile<2> { static constexpr int CX = 32, CY = 16, CZ = 1; };
+
+template <int D>
+__global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, PCfg c,
+                                                     const uint32_t* __restrict__ start,
+                                                     const float4* __restrict__ mom,
+                                                     float* __restrict__ drho_i, float* __restrict__ j_i,
+                                                     short4* __restrict__ wbase, float* __restrict__ wphi,
+                                                     int ntx, int nty) {
+    using T0 = InterpTile<D>;
+    constexpr int NX = T0::CX + 3, NY = T0::CY + 3, NZ = (D == 3) ? T0::CZ + 3 : 1;
+    constexpr int MAXR = T0::CY * T0::CZ;                // bin rows per tile at most (L = 0)
+    struct TB { int TBX, TBY, TBZ; };
+    const int E = 1 << c.L;                               // dual cells per bin edge
+    const TB T{T0::CX / E, T0::CY / E, (D == 3) ? T0::CZ / E : 1};
+    __shared__ float4 sm[NX * NY * NZ];
+    __shared__ uint32_t rs[MAXR], re[MAXR], roff[MAXR + 1];
+    const int tile = (int)blockIdx.x;
+    const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
+    const int B0x = tx * T.TBX, B0y = ty * T.TBY, B0z = tz * T.TBZ;
+    const int t = threadIdx.x;
+    if (t < T.TBY * T.TBZ) {
+        const int by = B0y + t % T.TBY, bz = B0z + t / T.TBY;
+        uint32_t s0 = 0, s1 = 0;
+        if (by < c.nb[1] && bz < c.nb[2] && B0x < c.nb[0]) {
+            const int bx1 = min(B0x + T.TBX, c.nb[0]) - 1;
+            const uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
+            s0 = start[row + B0x];
+            s1 = start[row + bx1 + 1];
+        }
+        rs[t] = s0;
+        re[t] = s1;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int r = 0; r < T.TBY * T.TBZ; r++) {
+            roff[r] = acc;
+            acc += re[r] - rs[r];
+        }
+        roff[T.TBY * T.TBZ] = acc;
+    }
+    __syncthreads();
+    const uint32_t total = roff[T.TBY * T.TBZ];
+    if (total == 0) return;
+    // node box: dual cells of the tile are [B0 E - 1, (B0 + TB) E - 2], reaching nodes
+    // [B0 E - 2, (B0 + TB) E]
+    const int nx0 = B0x * E - 2, ny0 = B0y * E - 2, nz0 = (D == 3) ? B0z * E - 2 : 0;
+    const int lx = T.TBX * E + 3, ly = T.TBY * E + 3, lz = (D == 3) ? T.TBZ * E + 3 : 1;
+    for (int i = t; i < lx * ly * lz; i += 256) {
+        const int ix = i % lx, iy = (i / lx) % ly, iz = i / (lx * ly);
+        const int x = nx0 + ix, y = ny0 + iy, z = nz0 + iz;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2])
+            v = mom[((long long)z * g.n[1] + y) * g.n[0] + x];
+        sm[i] = v;
+    }
+    __syncthreads();
+    for (uint32_t k = t; k < total; k += 256) {
+        int r = 0;
+        while (roff[r + 1] <= k) r++;
+        const uint32_t s = rs[r] + (k - roff[r]);
+        int base[3] = {0, 0, 0};
+        float phi[3][4];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (a < D) axis_weights(A.xh[a][s], A.xl[a][s], g.n[a], base[a], phi[a]);
+            else { phi[a][0] = 1.f; phi[a][1] = phi[a][2] = phi[a][3] = 0.f; }
+        }
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+        const int ox = base[0] - nx0, oy = base[1] - ny0, oz = (D == 3) ? base[2] - nz0 : 0;
+#pragma unroll
+        for (int kz = 0; kz < (D == 3 ? 4 : 1); kz++)
+#pragma unroll
+            for (int ky = 0; ky < 4; ky++) {
+                const float wyz = phi[1][ky] * phi[2][kz];
+#pragma unroll
+                for (int kx = 0; kx < 4; kx++) {
+                    const float W = phi[0][kx] * phi[1][ky] * phi[2][kz];
+                    if (W != 0.f) {
+                        const float4 m = sm[((oz + kz) * ly + (oy + ky)) * lx + (ox + kx)];
+                        acc0 += W * m.x; acc1 += W * m.y; acc2 += W * m.z; acc3 += W * m.w;
+                    }
+                }
+                (void)wyz;
+            }
+        drho_i[s] = acc0;
+        j_i[s] = acc1;
+        j_i[(long long)np + s] = acc2;
+        if (D == 3) j_i[2LL * np + s] = acc3;
+        wbase[s] = make_short4((short)base[0], (short)base[1], (short)base[2], 0);
+#pragma unroll
+        for (int a = 0; a < D; a++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) wphi[(long long)s * (4 * D) + 4 * a + q] = phi[a][q];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // DEM: classification and the free-particle closed form
 // ---------------------------------------------------------------------------
@@ -295,11 +402,12 @@ __device__ __forceinline__ int scan_neighbours(const float4* __restrict__ pos4, 
     b[1] = (int)((key / (uint32_t)c.nb[0]) % (uint32_t)c.nb[1]);
     b[2] = (int)(key / ((uint32_t)c.nb[0] * (uint32_t)c.nb[1]));
     int cnt = 0;
-    int zl = (D == 3) ? max(b[2] - 1, 0) : 0, zh = (D == 3) ? min(b[2] + 1, c.nb[2] - 1) : 0;
+    const int H = c.H;
+    int zl = (D == 3) ? max(b[2] - H, 0) : 0, zh = (D == 3) ? min(b[2] + H, c.nb[2] - 1) : 0;
     for (int bz = zl; bz <= zh; bz++)
-        for (int by = max(b[1] - 1, 0); by <= min(b[1] + 1, c.nb[1] - 1); by++) {
+        for (int by = max(b[1] - H, 0); by <= min(b[1] + H, c.nb[1] - 1); by++) {
             // bins of one row are contiguous in the sorted order
-            int bxl = max(b[0] - 1, 0), bxh = min(b[0] + 1, c.nb[0] - 1);
+            int bxl = max(b[0] - H, 0), bxh = min(b[0] + H, c.nb[0] - 1);
             uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
             uint32_t t0 = start[row + bxl], t1 = start[row + bxh + 1];
             for (uint32_t t = t0; t < t1; t++) {
@@ -1012,105 +1120,210 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
 // nodes held in LDS, one lane per support node: every node receives its
 // terms in the same fixed order, with no atomics.
 // ---------------------------------------------------------------------------
-template <int D> struct SpreadTile;
-// LDS strides are padded so that the 4^D support nodes of one particle fall
-// in distinct banks: 3D offset kx + 16 ky + 132 kz = kx + 16 ky + 4 kz (mod 64).
-template <> struct SpreadTile<3> { static constexpr int TX = 16, TY = 8, TZ = 4, SY = 16, SZ = 132; };
-template <> struct SpreadTile<2> { static constexpr int TX = 64, TY = 8, TZ = 1, SY = 68, SZ = 68 * 8; };
+// One wave per block of nodes (3D 4x4x4, 2D 8x8), one node per lane, the
+// force accumulated in registers.  The wave walks the particles of the
+// block's halo bins in sorted order (rows of bins are contiguous), reading
+// each particle's base and weights with uniform (scalar) loads; a lane adds
+// the particle's term when its node lies in the particle's support.  Every
+// node thus sums its terms in the same fixed order: deterministic, with no
+// atomics and no shared-memory dependency chain.
+// Spreading with dual-cell bins (bin edge 1): cell c' = floor(X - 1/2) + 1.
+// Node r receives exactly the particles of cells c' in [r - 1, r + 2] per
+// axis, with support offset k = r + 2 - c'.  A workgroup owns a tile of
+// nodes; it stages, for the tile's halo of cells, the LDS position of each
+// cell's first particle, and the particles' weights and coefficients; each
+// thread then sums, for its nodes, the particles of its 4^D cells in a fixed
+// order (cells by kz, ky, kx; particles in sorted order).  No atomics, no
+// wasted candidate checks.  A tile holding more than CSR_MAXP particles
+// reads them from global memory instead of LDS (same order, same result).
+template <int D> struct CsrTile;
+template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4; };
+template <> struct CsrTile<2> { static constexpr int TX = 16, TY = 16, TZ = 1; };
+constexpr int CSR_MAXP = 384;
 
 template <int D>
-__global__ __launch_bounds__(64) void k_spread(Grid g, PCfg c, const uint32_t* __restrict__ start,
-                                               const short4* __restrict__ wbase, const float* __restrict__ wphi,
-                                               const float* __restrict__ coef, int np, float* __restrict__ F,
-                                               int ntx, int nty) {
-    using T = SpreadTile<D>;
-    constexpr int TX = T::TX, TY = T::TY, TZ = T::TZ, SY = T::SY, SZ = T::SZ;
-    constexpr int TL = SZ * TZ;              // padded floats per component
-    constexpr int PW = 16;                   // staged floats per particle: 12 weights, 3 coefficients, base
-    __shared__ float acc[D * TL];
-    __shared__ float sp[WAVE * PW];
-    const int lane = threadIdx.x;
-    const int tile = (int)xcd_block();
-    const int tx = tile % ntx, t2 = tile / ntx;
-    const int ty = t2 % nty, tz = t2 / nty;
+__global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32_t* __restrict__ start,
+                                                    const float* __restrict__ wphi, const float* __restrict__ coef,
+                                                    int np, float* __restrict__ F, int ntx, int nty) {
+    using T = CsrTile<D>;
+    constexpr int TX = T::TX, TY = T::TY, TZ = T::TZ;
+    constexpr int HX = TX + 3, HY = TY + 3, HZ = (D == 3) ? TZ + 3 : 1;
+    constexpr int NR = HY * HZ;                  // halo rows of cells
+    constexpr int PW = 4 * D + D;                // staged floats per particle
+    __shared__ uint32_t cs[NR * (HX + 1)];       // per row: LDS index of each cell's first particle, then the end
+    __shared__ uint32_t rowbase[NR + 1], rowg0[NR];
+    __shared__ float sp[CSR_MAXP * PW];
+    const int t = threadIdx.x;
+    const int tile = (int)blockIdx.x;
+    const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-    for (int i = lane; i < D * TL; i += WAVE) acc[i] = 0.f;
-
-    // halo bins: a particle in dual cell cd reaches nodes cd-1 .. cd+2
-    const int bx0 = max((x0 - 1) >> c.L, 0), bx1 = min((x0 + TX + 1) >> c.L, c.nb[0] - 1);
-    const int by0 = max((y0 - 1) >> c.L, 0), by1 = min((y0 + TY + 1) >> c.L, c.nb[1] - 1);
-    const int bz0 = (D == 3) ? max((z0 - 1) >> c.L, 0) : 0;
-    const int bz1 = (D == 3) ? min((z0 + TZ + 1) >> c.L, c.nb[2] - 1) : 0;
-    // this lane's support node offset
-    const int kx = lane & 3, ky = (lane >> 2) & 3, kz = (D == 3) ? (lane >> 4) : 0;
-    const bool lane_on = (D == 3) || lane < 16;
-
-    for (int bz = bz0; bz <= bz1; bz++)
-        for (int by = by0; by <= by1; by++) {
-            const uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
-            const uint32_t s0 = start[row + bx0], s1 = start[row + bx1 + 1];
-            for (uint32_t ch = s0; ch < s1; ch += WAVE) {
-                // stage up to 64 particles (coalesced loads)
-                __syncthreads();
-                const uint32_t idx = ch + lane;
-                if (idx < s1) {
-                    float* q = sp + lane * PW;
+    const int cx0 = x0 - 1, cy0 = y0 - 1, cz0 = (D == 3) ? z0 - 1 : 0;
+    const int lo = max(cx0, 0), hi = min(cx0 + HX - 1, c.nb[0] - 1);
+    uint32_t cnt_row = 0;
+    if (t < NR) {
+        const int cy = cy0 + t % HY, cz = cz0 + t / HY;
+        uint32_t g0 = 0, g1 = 0;
+        if (cy >= 0 && cy < c.nb[1] && cz >= 0 && cz < c.nb[2] && lo <= hi) {
+            const uint32_t row = (uint32_t)(((long long)cz * c.nb[1] + cy) * c.nb[0]);
+            g0 = start[row + lo];
+            g1 = start[row + hi + 1];
+        }
+        rowg0[t] = g0;
+        cnt_row = g1 - g0;
+        rowbase[t] = cnt_row;                    // counts first, prefix below
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int r = 0; r < NR; r++) {
+            const uint32_t n = rowbase[r];
+            rowbase[r] = acc;
+            acc += n;
+        }
+        rowbase[NR] = acc;
+    }
+    __syncthreads();
+    const uint32_t total = rowbase[NR];
+    for (int i = t; i < NR * (HX + 1); i += 256) {
+        const int r = i / (HX + 1), ix = i % (HX + 1);
+        const int cy = cy0 + r % HY, cz = cz0 + r / HY, cx = cx0 + ix;
+        uint32_t v = rowbase[r];
+        const bool rowok = cy >= 0 && cy < c.nb[1] && cz >= 0 && cz < c.nb[2] && lo <= hi;
+        if (rowok) {
+            if (cx > hi) v = rowbase[r + 1];
+            else if (cx > lo) {
+                const uint32_t row = (uint32_t)(((long long)cz * c.nb[1] + cy) * c.nb[0]);
+                v = rowbase[r] + (start[row + cx] - rowg0[r]);
+            }
+        }
+        cs[i] = v;
+    }
+    const bool staged = total <= (uint32_t)CSR_MAXP;
+    if (staged) {
+        for (uint32_t k = t; k < total; k += 256) {
+            int r = 0;
+            while (rowbase[r + 1] <= k) r++;
+            const uint32_t gsl = rowg0[r] + (k - rowbase[r]);
 #pragma unroll
-                    for (int k = 0; k < 4 * D; k++) q[k] = wphi[(long long)idx * (4 * D) + k];
+            for (int q = 0; q < 4 * D; q++) sp[k * PW + q] = wphi[(long long)gsl * (4 * D) + q];
 #pragma unroll
-                    for (int a = 0; a < D; a++) q[12 + a] = coef[(long long)a * np + idx];
-                    short4 bb = wbase[idx];
-                    // base relative to the tile origin, packed in 3 x 10 bits (offsets in [-3, 16])
-                    int pk = ((bb.x - x0 + 512) & 1023) | (((bb.y - y0 + 512) & 1023) << 10) |
-                             (((D == 3 ? bb.z - z0 : 0) + 512) & 1023) << 20;
-                    q[15] = __int_as_float(pk);
+            for (int a = 0; a < D; a++) sp[k * PW + 4 * D + a] = coef[(long long)a * np + gsl];
+        }
+    }
+    __syncthreads();
+    for (int node = t; node < TX * TY * TZ; node += 256) {
+        const int lx = node % TX, ly = (node / TX) % TY, lz = node / (TX * TY);
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (x >= g.n[0] || y >= g.n[1] || z >= g.n[2]) continue;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        if (total > 0) {
+#pragma unroll 1
+            for (int kz = 0; kz < (D == 3 ? 4 : 1); kz++)
+#pragma unroll 1
+                for (int ky = 0; ky < 4; ky++) {
+                    const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
+                    const uint32_t* rc = cs + r * (HX + 1);
+#pragma unroll
+                    for (int kx = 0; kx < 4; kx++) {
+                        const int ix = lx + 3 - kx;
+                        const uint32_t p0 = rc[ix], p1 = rc[ix + 1];
+                        for (uint32_t k = p0; k < p1; k++) {
+                            float wx, wy, wz = 1.f, cxv, cyv, czv = 0.f;
+                            if (staged) {
+                                const float* q = sp + k * PW;
+                                wx = q[kx];
+                                wy = q[4 + ky];
+                                if (D == 3) wz = q[8 + kz];
+                                cxv = q[4 * D];
+                                cyv = q[4 * D + 1];
+                                if (D == 3) czv = q[4 * D + (D - 1)];
+                            } else {
+                                int rr = 0;
+                                while (rowbase[rr + 1] <= k) rr++;
+                                const uint32_t gsl = rowg0[rr] + (k - rowbase[rr]);
+                                const float* q = wphi + (long long)gsl * (4 * D);
+                                wx = q[kx];
+                                wy = q[4 + ky];
+                                if (D == 3) wz = q[8 % (4 * D) + kz];
+                                cxv = coef[gsl];
+                                cyv = coef[(long long)np + gsl];
+                                if (D == 3) czv = coef[2LL * np + gsl];
+                            }
+                            const float W = wx * wy * wz;
+                            a0 += W * cxv;
+                            a1 += W * cyv;
+                            a2 += W * czv;
+                        }
+                    }
                 }
-                __syncthreads();
-                const int cnt = (int)min((uint32_t)WAVE, s1 - ch);
-                // next particle's data is fetched one iteration ahead
-                const float* q0 = sp;
-                int pk = __float_as_int(q0[15]);
-                float wx = q0[kx], wy = q0[4 + ky], wz = (D == 3) ? q0[8 + kz] : 1.f;
-                float c0 = q0[12], c1 = q0[13], c2 = (D == 3) ? q0[14] : 0.f;
-                for (int j = 0; j < cnt; j++) {
-                    const int pkc = pk;
-                    const float W = wx * wy * wz, cx = c0, cy = c1, cz = c2;
-                    if (j + 1 < cnt) {
-                        const float* qn = sp + (j + 1) * PW;
-                        pk = __float_as_int(qn[15]);
-                        wx = qn[kx];
-                        wy = qn[4 + ky];
-                        if (D == 3) wz = qn[8 + kz];
-                        c0 = qn[12];
-                        c1 = qn[13];
-                        if (D == 3) c2 = qn[14];
-                    }
-                    const int lx = (pkc & 1023) - 512 + kx;
-                    const int ly = ((pkc >> 10) & 1023) - 512 + ky;
-                    const int lz = (D == 3) ? ((pkc >> 20) & 1023) - 512 + kz : 0;
-                    const bool in = lane_on && (unsigned)lx < (unsigned)TX && (unsigned)ly < (unsigned)TY &&
-                                    (unsigned)lz < (unsigned)TZ;
-                    if (in) {
-                        // one wave: LDS operations complete in issue order, so each
-                        // node receives its terms in particle order
-                        const int li = lz * SZ + ly * SY + lx;
-                        acc[li] += W * cx;
-                        acc[TL + li] += W * cy;
-                        if (D == 3) acc[2 * TL + li] += W * cz;
-                    }
+        }
+        const long long rn = ((long long)z * g.n[1] + y) * g.n[0] + x;
+        F[rn] = a0;
+        F[g.N + rn] = a1;
+        if (D == 3) F[2 * g.N + rn] = a2;
+    }
+}
+
+template <int D> struct SpreadBlock;
+template <> struct SpreadBlock<3> { static constexpr int BX = 4, BY = 4, BZ = 4; };
+template <> struct SpreadBlock<2> { static constexpr int BX = 8, BY = 8, BZ = 1; };
+
+__device__ __forceinline__ float pick4(int k, float a, float b, float c, float d) {
+    const float lo = (k & 1) ? b : a, hi = (k & 1) ? d : c;
+    return (k & 2) ? hi : lo;
+}
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <int D>
+__global__ __launch_bounds__(256) void k_spread(Grid g, PCfg c, const uint32_t* __restrict__ start,
+                                                const short4* __restrict__ wbase, const float* __restrict__ wphi,
+                                                const float* __restrict__ coef, int np, float* __restrict__ F,
+                                                int nbx, int nby, int nbz) {
+    using B = SpreadBlock<D>;
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int blk = uni((int)blockIdx.x * 4 + wave);      // 4 waves per workgroup, neighbours along x
+    if (blk >= nbx * nby * nbz) return;                   // uniform per wave
+    const int bxi = blk % nbx, t2 = blk / nbx;
+    const int byi = t2 % nby, bzi = t2 / nby;
+    const int x0 = bxi * B::BX, y0 = byi * B::BY, z0 = bzi * B::BZ;
+    const int x = x0 + (D == 3 ? (lane & 3) : (lane & 7));
+    const int y = y0 + (D == 3 ? ((lane >> 2) & 3) : (lane >> 3));
+    const int z = z0 + (D == 3 ? (lane >> 4) : 0);
+
+    const int b0x = max((x0 - 1) >> c.L, 0), b1x = min((x0 + B::BX + 1) >> c.L, c.nb[0] - 1);
+    const int b0y = max((y0 - 1) >> c.L, 0), b1y = min((y0 + B::BY + 1) >> c.L, c.nb[1] - 1);
+    const int b0z = (D == 3) ? max((z0 - 1) >> c.L, 0) : 0;
+    const int b1z = (D == 3) ? min((z0 + B::BZ + 1) >> c.L, c.nb[2] - 1) : 0;
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    for (int bz = b0z; bz <= b1z; bz++)
+        for (int by = b0y; by <= b1y; by++) {
+            const uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
+            const uint32_t s0 = (uint32_t)uni((int)start[row + b0x]);
+            const uint32_t s1 = (uint32_t)uni((int)start[row + b1x + 1]);
+            for (uint32_t s = s0; s < s1; s++) {
+                const short4 b = wbase[s];
+                const int kx = x - b.x, ky = y - b.y, kz = (D == 3) ? z - b.z : 0;
+                const float* ph = wphi + (long long)s * (4 * D);
+                const float cx = coef[s], cy = coef[(long long)np + s];
+                const float cz = (D == 3) ? coef[2LL * np + s] : 0.f;
+                const float p0 = ph[0], p1 = ph[1], p2 = ph[2], p3 = ph[3];
+                const float q0 = ph[4], q1 = ph[5], q2 = ph[6], q3 = ph[7];
+                float r0 = 1.f, r1 = 0.f, r2 = 0.f, r3 = 0.f;
+                if (D == 3) { r0 = ph[8 % (4 * D)]; r1 = ph[9 % (4 * D)]; r2 = ph[10 % (4 * D)]; r3 = ph[11 % (4 * D)]; }
+                if ((unsigned)kx < 4u && (unsigned)ky < 4u && (unsigned)kz < 4u) {
+                    float W = pick4(kx, p0, p1, p2, p3) * pick4(ky, q0, q1, q2, q3);
+                    if (D == 3) W *= pick4(kz, r0, r1, r2, r3);
+                    ax += W * cx;
+                    ay += W * cy;
+                    az += W * cz;
                 }
             }
         }
-    __syncthreads();
-    for (int i = lane; i < TX * TY * TZ; i += WAVE) {
-        const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
-        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (x < g.n[0] && y < g.n[1] && z < g.n[2]) {
-            const long long r = ((long long)z * g.n[1] + y) * g.n[0] + x;
-            const int li = lz * SZ + ly * SY + lx;
-#pragma unroll
-            for (int a = 0; a < D; a++) F[(long long)a * g.N + r] = acc[a * TL + li];
-        }
+    if (x < g.n[0] && y < g.n[1] && z < g.n[2]) {
+        const long long r = ((long long)z * g.n[1] + y) * g.n[0] + x;
+        F[r] = ax;
+        F[g.N + r] = ay;
+        if (D == 3) F[2 * g.N + r] = az;
     }
 }
 
@@ -1197,7 +1410,24 @@ void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
     b.B = t;
 }
 
-void particles_interp(int D, PBuf& b, int np, const Grid& g, const float4* mom, hipStream_t s) {
+void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, const float4* mom, hipStream_t s) {
+    if (c.L <= 1) {
+        const int E = 1 << c.L;
+        if (D == 3) {
+            using T = InterpTile<3>;
+            const int bx = T::CX / E, by = T::CY / E, bz = T::CZ / E;
+            int ntx = (c.nb[0] + bx - 1) / bx, nty = (c.nb[1] + by - 1) / by, ntz = (c.nb[2] + bz - 1) / bz;
+            hipLaunchKernelGGL(k_interp_tile<3>, dim3((unsigned)((long long)ntx * nty * ntz)), dim3(256), 0, s, b.A,
+                               np, g, c, b.start, mom, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+        } else {
+            using T = InterpTile<2>;
+            const int bx = T::CX / E, by = T::CY / E;
+            int ntx = (c.nb[0] + bx - 1) / bx, nty = (c.nb[1] + by - 1) / by;
+            hipLaunchKernelGGL(k_interp_tile<2>, dim3((unsigned)((long long)ntx * nty)), dim3(256), 0, s, b.A, np, g,
+                               c, b.start, mom, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+        }
+        return;
+    }
     long long threads = (long long)np * (D == 3 ? 16 : 4);
     if (D == 3)
         hipLaunchKernelGGL(k_interp<3>, dim3(nb256(threads)), dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
@@ -1250,16 +1480,33 @@ void particles_dem(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
 }
 
 void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, float* F, hipStream_t s) {
+    if (c.L == 0) {
+        if (D == 3) {
+            using T = CsrTile<3>;
+            int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY, ntz = (g.n[2] + T::TZ - 1) / T::TZ;
+            hipLaunchKernelGGL(k_spread_csr<3>, dim3((unsigned)((long long)ntx * nty * ntz)), dim3(256), 0, s, g, c,
+                               b.start, b.wphi, b.coef, np, F, ntx, nty);
+        } else {
+            using T = CsrTile<2>;
+            int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY;
+            hipLaunchKernelGGL(k_spread_csr<2>, dim3((unsigned)((long long)ntx * nty)), dim3(256), 0, s, g, c,
+                               b.start, b.wphi, b.coef, np, F, ntx, nty);
+        }
+        return;
+    }
+
     if (D == 3) {
-        using T = SpreadTile<3>;
-        int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY, ntz = (g.n[2] + T::TZ - 1) / T::TZ;
-        hipLaunchKernelGGL(k_spread<3>, dim3((unsigned)((long long)ntx * nty * ntz)), dim3(64), 0, s, g, c, b.start,
-                           b.wbase, b.wphi, b.coef, np, F, ntx, nty);
+        using B = SpreadBlock<3>;
+        int nbx = (g.n[0] + B::BX - 1) / B::BX, nby = (g.n[1] + B::BY - 1) / B::BY, nbz = (g.n[2] + B::BZ - 1) / B::BZ;
+        long long nblk = (long long)nbx * nby * nbz;
+        hipLaunchKernelGGL(k_spread<3>, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, s, g, c, b.start, b.wbase,
+                           b.wphi, b.coef, np, F, nbx, nby, nbz);
     } else {
-        using T = SpreadTile<2>;
-        int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY;
-        hipLaunchKernelGGL(k_spread<2>, dim3((unsigned)((long long)ntx * nty)), dim3(64), 0, s, g, c, b.start,
-                           b.wbase, b.wphi, b.coef, np, F, ntx, nty);
+        using B = SpreadBlock<2>;
+        int nbx = (g.n[0] + B::BX - 1) / B::BX, nby = (g.n[1] + B::BY - 1) / B::BY;
+        long long nblk = (long long)nbx * nby;
+        hipLaunchKernelGGL(k_spread<2>, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, s, g, c, b.start, b.wbase,
+                           b.wphi, b.coef, np, F, nbx, nby, 1);
     }
 }
 

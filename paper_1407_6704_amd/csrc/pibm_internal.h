@@ -172,6 +172,7 @@ struct PCfg {
     float g[3];
     int maxc;
     float eps;          // bound on the trailing position parts left out by screening
+    int H;              // neighbour-search half-width in bins: ceil((d_max + skin + eps) / 2^L)
 };
 
 // Per-candidate constants of the active sub-steps.

@@ -27,7 +27,7 @@ void lattice_totals(int Q, int fp16, int sl2, const void* f, long long N, double
                     hipStream_t s);
 long long scan_blocks(long long n);
 void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s);
-void particles_interp(int D, PBuf& b, int np, const Grid& g, const float4* mom, hipStream_t s);
+void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, const float4* mom, hipStream_t s);
 void particles_dem(int D, PBuf& b, int np, const PCfg& c, hipStream_t s);
 void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, float* F, hipStream_t s);
 int particles_totals_blocks();
@@ -218,6 +218,13 @@ void fill_pcfg(pibm_ctx& c) {
     // screened distance is off by at most sqrt(D) ulp(max extent)
     int nmax = std::max(c.cfg.n[0], std::max(c.cfg.n[1], c.cfg.n[2]));
     p.eps = (float)(std::sqrt((double)c.D) * std::ldexp(1.0, (int)std::ceil(std::log2((double)nmax + 1.0)) - 23));
+    p.H = 1;
+}
+
+// Neighbour-search half-width for the largest diameter present.
+void set_stencil(pibm_ctx& c, double dmax) {
+    const double edge = std::ldexp(1.0, c.cfg.bin_log2);
+    c.pc.H = std::max(1, (int)std::ceil((dmax + c.cfg.skin + (double)c.pc.eps) / edge));
 }
 
 bool init_ctx(pibm_ctx& c, const pibm_config* cfg, int64_t np) {
@@ -377,8 +384,8 @@ pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, co
     }
     if (!x || !d || !rho_p) return fail(c, PIBM_E_ARG, "null particle array");
     const int D = c->D, np = c->np;
-    const double edge = std::ldexp(1.0, c->cfg.bin_log2);
     std::vector<float> buf((size_t)(3 * D + 3) * np);
+    double dmax = 0;
     float* xh = buf.data();
     float* xl = xh + (size_t)D * np;
     float* u = xl + (size_t)D * np;
@@ -387,7 +394,8 @@ pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, co
     int* id = (int*)(rp + np);
     for (int i = 0; i < np; i++) {
         if (!(d[i] > 0) || !(rho_p[i] > 0)) return fail(c, PIBM_E_ARG, "diameter and density must be positive");
-        if (d[i] + c->cfg.skin > edge) return fail(c, PIBM_E_ARG, "diameter + skin exceeds the bin edge 2^bin_log2");
+        if (d[i] > 0.5 * c->cfg.n[0] || d[i] > 64.0) return fail(c, PIBM_E_ARG, "diameter too large");
+        dmax = std::max(dmax, (double)(float)d[i]);
         dd[i] = (float)d[i];
         rp[i] = (float)rho_p[i];
         id[i] = i;
@@ -410,6 +418,7 @@ pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, co
     hipMemcpyAsync(A.rp, rp, 4 * np, hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(A.id, id, 4 * np, hipMemcpyHostToDevice, c->stream);
     if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "copy particles")) return s;
+    set_stencil(*c, dmax);
     c->particles_set = true;
     c->stepped = false;
     return PIBM_OK;
@@ -486,7 +495,7 @@ pibm_status pibm_step(pibm_ctx* c, int32_t n_steps) {
         mark(c, row, 1);
         if (c->np > 0) particles_sort(c->D, c->pb, c->np, c->pc, c->stream);
         mark(c, row, 2);
-        if (c->np > 0) particles_interp(c->D, c->pb, c->np, c->grid, c->mom, c->stream);
+        if (c->np > 0) particles_interp(c->D, c->pb, c->np, c->grid, c->pc, c->mom, c->stream);
         mark(c, row, 3);
         if (c->np > 0) particles_dem(c->D, c->pb, c->np, c->pc, c->stream);
         mark(c, row, 4);

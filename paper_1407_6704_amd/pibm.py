@@ -107,7 +107,7 @@ def header_symbols():
 def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, periodic=(0, 0, 0),
                 tau=0.8, rho0=1.0, gravity=(0.0, 0.0, 0.0), fluid_force=(0.0, 0.0, 0.0),
                 contact="lsd", n_sub=1, kn=1e3, restitution=0.9, k_soft=1e-3, skin=0.05,
-                two_way=1, bin_log2=1, max_candidates=16) -> Config:
+                two_way=1, bin_log2=0, max_candidates=16) -> Config:
     c = Config()
     c.abi_version = ABI_VERSION
     c.lattice = int(lattice)

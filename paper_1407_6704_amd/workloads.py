@@ -63,7 +63,7 @@ class Workload:
     seed: int = 0
     gap: float = 1e-3                 # minimum surface gap at placement
     wall_clear: float = 0.0           # extra clearance from walls beyond d/2
-    bin_log2: int = 1
+    bin_log2: int = 0                 # cell-list bins = dual cells
     two_way: int = 1
     extra: dict = field(default_factory=dict)
 
