@@ -62,6 +62,12 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1407_6704_amd/build.py")
+    # torch ships its own HIP runtime under the same soname as the system
+    # one; loading torch first makes the library bind to that single copy,
+    # so streams and device pointers from torch are valid in it.  Loading the
+    # library first would put two different HIP/HSA runtimes in the process.
+    import torch  # noqa: F401
+
     lib = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     fp = C.POINTER(C.c_float)

@@ -2,8 +2,11 @@
 include/pibm.h declares, sizes workspaces and rejects bad configurations
 without touching a GPU (no compute call is made here)."""
 import ctypes as C
+import os
 
 import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module")
@@ -67,3 +70,23 @@ def test_config_struct_layout(P):
     implicit tail padding beyond 8-byte alignment)."""
     assert C.sizeof(P.Config) == 4 * 4 + 3 * 4 + 3 * 4 + 8 * 2 + 8 * 3 + 8 * 3 + 4 * 2 + 8 * 4 + 4 * 4
     assert C.sizeof(P.Diag) == 8 + 24 + 24 + 8 + 8 * 3 + 8 * 2
+
+
+def test_single_hip_runtime_in_process(P):
+    """Loading the library before torch must still leave exactly one HIP and
+    one HSA runtime mapped (the library binds to torch's copy)."""
+    import subprocess
+    import sys
+
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1407_6704_amd import pibm\n"
+        "pibm.load()\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "hip = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+        "hsa = {l.split()[-1] for l in maps if 'libhsa-runtime64' in l}\n"
+        "print(len(hip), len(hsa))\n" % ROOT
+    )
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "1"], out.stdout
