@@ -103,7 +103,7 @@ def copy_probe():
                       "launches": 3}), flush=True)
 
 
-def run_gpu(w, steps: int, warmup: int, label: str):
+def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
     import torch
 
     from paper_1407_6704_amd import pibm, workloads as W
@@ -135,6 +135,7 @@ def run_gpu(w, steps: int, warmup: int, label: str):
         status = e.name
     diag = sim.diagnostics()
     sim.set_profiling(False)
+    fields = sim.read_fields() if keep_fields else None
     np_ = X.shape[1]
     res = {
         "ms_per_step": ms / steps,
@@ -153,6 +154,8 @@ def run_gpu(w, steps: int, warmup: int, label: str):
     res["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(dom, w.name),
                        "bytes_per_launch": b, "avg_launch_ms": single[dom]}
+    if keep_fields:
+        res["_fields"] = fields
     del sim
     torch.cuda.empty_cache()
     return res, (X, U, d, rp)
@@ -232,11 +235,20 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, parts)
     if not args.no_extra:
+        import numpy as np
+
         extra = {}
         for name in ("c2", "c3"):
-            r, _ = run_gpu(W.WORKLOADS[name], args.extra_steps, 2, name)
+            r, _ = run_gpu(W.WORKLOADS[name], args.extra_steps, 2, name, keep_fields=True)
             extra[name] = r
         extra["fp16_speedup"] = extra["c2"]["ms_per_step"] / extra["c3"]["ms_per_step"]
+        # FP16 storage against FP32 from the same initial state, same steps
+        (r32, u32), (r16, u16) = extra["c2"].pop("_fields"), extra["c3"].pop("_fields")
+        extra["fp16_vs_fp32"] = {
+            "steps": args.extra_steps + 2,
+            "eps_u": float(np.linalg.norm(u16.astype(np.float64) - u32) / np.linalg.norm(u32.astype(np.float64))),
+            "eps_rho": float(np.abs(r16.astype(np.float64) - r32).max()),
+        }
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 

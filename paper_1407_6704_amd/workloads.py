@@ -14,8 +14,8 @@ keep that structure at larger scale:
   c1  D2Q9 2048^2, tau 0.6, 500k disks d ~ U[0.3, 0.8], ratio 2.5, upper 60 %
   c2  D3Q19 256^3, tau 0.6, 2M spheres, d lognormal (mean 0.5, sd 0.2,
       truncated to [0.2, 1.0]), ratio 2.0, upper half
-  c3  c2 with populations stored as FP16 deviations (and its 64^3 crop with
-      the same number density, 31,250 spheres)
+  c3  c2 with populations stored as FP16 deviations, from the same initial
+      state (and a 64^3 crop with the same number density, 31,250 spheres)
   c4  D2Q9 512^2, tau 0.7, 10k disks d = 0.5, ratio 2.5, soft repulsion,
       dilute (gaps >= d, >= 3 from walls), objective = mean height
 
@@ -90,8 +90,8 @@ C1 = Workload("c1", 9, (2048, 2048, 1), 0.6, 500_000, ("uniform", 0.3, 0.8), 2.5
               n_sub=677, steps=5000, seed=1)
 C2 = Workload("c2", 19, (256, 256, 256), 0.6, 2_000_000, ("lognormal", 0.5, 0.2, 0.2, 1.0), 2.0,
               (0.5, 1.0), n_sub=3109, steps=2000, seed=2)
-C3 = C2.replace(name="c3", storage="fp16", seed=3)
-C3_CROP = C3.replace(name="c3_crop64", n=(64, 64, 64), n_particles=31_250, steps=100)
+C3 = C2.replace(name="c3", storage="fp16")          # same initial state as c2
+C3_CROP = C3.replace(name="c3_crop64", n=(64, 64, 64), n_particles=31_250, steps=100, seed=3)
 C4 = Workload("c4", 9, (512, 512, 1), 0.7, 10_000, ("const", 0.5), 2.5, (0.5, 1.0),
               contact="soft", n_sub=1, steps=2000, seed=4, gap=0.5, wall_clear=3.0)
 C4_FD = C4.replace(name="c4_fd", n=(64, 64, 1), n_particles=50, seed=40)
