@@ -13,7 +13,9 @@ Prints ONE JSON line.  Besides the contract fields it carries
                   phase during the timed region (algorithmic bytes / time)
   cpu_baseline  - the FP64 oracle on the host cores, on a bounded sample
   extra         - the same measurement for the D3Q19 256^3 / 2M-sphere case
-                  in FP32 and with FP16 deviation storage
+                  in FP32 and with FP16 deviation storage, the FP16-vs-FP32
+                  field errors, and the adjoint/forward cost ratio on the
+                  D2Q9 512^2 / 10k-particle differentiation workload
 """
 from __future__ import annotations
 
@@ -161,6 +163,54 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
     return res, (X, U, d, rp)
 
 
+def run_adjoint(w, K: int = 100):
+    """Adjoint/forward cost on the differentiation workload: plain FP32
+    stepping of w.steps steps against the backward pass (segment re-runs plus
+    the reverse steps) of a checkpointed rollout of the same steps, for
+    J = mean particle height."""
+    import numpy as np
+    import torch
+
+    from paper_1407_6704_amd import pibm, workloads as W
+
+    X, U, d, rp = W.make_particles(w)
+    cfg = pibm.config_from_workload(w)
+    steps = w.steps
+
+    def timed(fn, stream):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        out = fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1), out
+
+    sim = pibm.Sim(cfg, X.shape[1])
+    sim.set_particles(X, U, d, rp)
+    sim.step(10)
+    sim.synchronize()
+    t_fwd, _ = timed(lambda: sim.step(steps), sim.stream)
+    sim.synchronize()
+    del sim
+    rs = pibm.Sim(cfg, X.shape[1])
+    rs.set_particles(X, U, d, rp)
+    t_ck, _ = timed(lambda: rs.forward_ckpt(steps, K), rs.stream)
+    dJdx = np.zeros_like(X)
+    dJdx[w.dim - 1] = 1.0 / X.shape[1]
+    t_bwd, r = timed(lambda: rs.backward(dJ_dx=dJdx), rs.stream)
+    out = {"workload": f"{w.name}: D2Q9 {w.n[0]}x{w.n[1]}, {X.shape[1]} particles, soft contact, n_sub 1",
+           "steps": steps, "checkpoint_every": K, "forward_ms": t_fwd, "forward_ckpt_ms": t_ck,
+           "backward_ms": t_bwd, "ratio": t_bwd / t_fwd,
+           "rollout_buffer_MB": rs.rollout_buf.numel() / 1e6,
+           "dJ_dtau": r["dtau"], "dJ_dgravity_y": r["dgravity"][w.dim - 1],
+           "dJ_dv0_norm": float(np.linalg.norm(r["dv0"]))}
+    del rs
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, particles, budget_s=30.0):
     """The FP64 oracle (single thread, as it stands) on one full step of the
     same workload."""
@@ -244,6 +294,7 @@ def main():
         extra["fp16_speedup"] = extra["c2"]["ms_per_step"] / extra["c3"]["ms_per_step"]
         # FP16 storage against FP32 from the same initial state, same steps
         (r32, u32), (r16, u16) = extra["c2"].pop("_fields"), extra["c3"].pop("_fields")
+        extra["c4_adjoint"] = run_adjoint(W.WORKLOADS["c4"])
         extra["fp16_vs_fp32"] = {
             "steps": args.extra_steps + 2,
             "eps_u": float(np.linalg.norm(u16.astype(np.float64) - u32) / np.linalg.norm(u32.astype(np.float64))),

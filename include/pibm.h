@@ -57,7 +57,7 @@ typedef enum {
     PIBM_E_CONFIG = 2,    /* tau <= 1/2, n_sub < 1, unknown lattice, ABI mismatch */
     PIBM_E_HIP = 3,       /* a HIP runtime call failed */
     PIBM_E_STATE = 4,     /* call order (e.g. step before particles are set) */
-    PIBM_E_UNSTABLE = 5,  /* NaN/Inf, |u| > 0.1, or a drag sub-step with h c >= 1 */
+    PIBM_E_UNSTABLE = 5,  /* NaN/Inf, |u| > 0.1, or a drag sub-step with h c >= 2 */
     PIBM_E_SKIN = 6,      /* a particle moved more than skin/2 within one step */
     PIBM_E_CAPACITY = 7   /* more candidates per particle than max_candidates */
 } pibm_status;
@@ -178,6 +178,38 @@ pibm_status pibm_synchronize(pibm_ctx* ctx);
  * (fluid sum f e + particle sum m U). */
 pibm_status pibm_conservation(pibm_ctx* ctx, double* mass, double* momentum);
 pibm_status pibm_diagnostics(pibm_ctx* ctx, pibm_diag* out);
+
+/* ---- Adjoint of a rollout (reverse-mode gradients) ----------------------
+ * Gradients of a scalar objective J(X_T, U_T) of the particle state after
+ * n_steps coupled steps with respect to the relaxation time tau (Eq. lbm2),
+ * the gravity vector of the buoyant weight (Eq. demgov) and the initial
+ * particle velocities and positions.  The backward pass is the exact reverse
+ * of every operation of the step (collision and streaming, spreading,
+ * momentum exchange, particle update, interpolation, moments), in FP32 with
+ * double-float sums of the parameter gradients.
+ * Supported: n_sub = 1 (the explicit update of Eq. demgov), contact NONE or
+ * SOFT, bin_log2 = 0, FP32 or FP16 storage; other configurations return
+ * PIBM_E_CONFIG.  Memory stays bounded by checkpointing: the state is saved
+ * every K steps and each K-step segment is re-run before it is reversed.
+ *
+ * Bytes of the caller-owned device buffer for a rollout of n_steps steps with
+ * checkpoints every K steps (checkpoints, one segment's recorded states and
+ * the adjoint fields); 0 for invalid arguments or an unsupported context. */
+size_t pibm_rollout_bytes(const pibm_ctx* ctx, int32_t n_steps, int32_t K);
+/* Run n_steps steps from the current state (as pibm_step) and record the
+ * checkpoints in dev_buf (device memory of at least pibm_rollout_bytes bytes,
+ * owned by the caller and kept alive until pibm_backward).  Asynchronous. */
+pibm_status pibm_forward_ckpt(pibm_ctx* ctx, int32_t n_steps, int32_t K, void* dev_buf,
+                              size_t buf_bytes);
+/* Reverse the last recorded rollout.  Inputs dJ_dx_T, dJ_dv_T: DEVICE FP32
+ * arrays D x N (id order), dJ/dX and dJ/dU at the final state; NULL means 0.
+ * Outputs (each may be NULL): dJ_dx0, dJ_dv0 DEVICE FP32 D x N; dJ_dtau one
+ * HOST double; dJ_dgravity three HOST doubles (components beyond D are 0).
+ * Synchronises.  The context is left in the final state of the rollout, as
+ * after pibm_forward_ckpt; the recorded rollout stays valid until the next
+ * pibm_forward_ckpt, so several objectives may be reversed. */
+pibm_status pibm_backward(pibm_ctx* ctx, const float* dJ_dx_T, const float* dJ_dv_T, float* dJ_dx0,
+                          float* dJ_dv0, double* dJ_dtau, double* dJ_dgravity);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpibm.so")
-SOURCES = ["lattice.hip", "particles.hip", "runtime.hip"]
+SOURCES = ["lattice.hip", "particles.hip", "adjoint.hip", "runtime.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -28,9 +28,6 @@
 
 namespace pibm {
 
-__device__ __forceinline__ float particle_mass(int D, float d, float rp) {
-    return D == 3 ? rp * (PI_F / 6.0f) * d * d * d : rp * 0.25f * PI_F * d * d;
-}
 
 __device__ __forceinline__ int bin_of(const PCfg& c, float xh, float xl, int a) {
     int ci = dual_cell(xh, xl);
@@ -457,15 +454,13 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
     float ri = 1.0f + drho_i[s];
     float cc = 2.0f * Ap * ri / m;
     float hc = cc * c.h;
-    if (!(hc < 1.0f)) atomicOr(flags, FLAG_UNSTABLE);
-    float lq = log1pf(-hc);
-    float nl = (float)c.n_sub * lq;
-    float qn = expf(nl);
-    float omq = -expm1f(nl);             // 1 - q^n
+    if (!(hc < 2.0f)) atomicOr(flags, FLAG_UNSTABLE);   // explicit drag diverges
+    float qn, omq;                       // q^n, 1 - q^n
+    drag_power(hc, c.n_sub, qn, omq);
     float geo = omq / hc;                // sum_{k<n} q^k
     float q = 1.0f - hc;
     float bw = 1.0f - c.rho0 / rp;
-    float v0s = 0.f, vns = 0.f;
+    float v0s = 0.f, vns = 0.f, ves = 0.f, dvs = 0.f;
     float un[3], dx[3], gb[3];
 #pragma unroll
     for (int a = 0; a < D; a++) {
@@ -479,8 +474,12 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
         gb[a] = 2.0f * ri * (slip + (u0 - ueq) * (geo * c.h));
         v0s += u0 * u0;
         vns += un[a] * un[a];
+        ves += ueq * ueq;
+        dvs += (u0 - ueq) * (u0 - ueq);
     }
-    float B = sqrtf(fmaxf(v0s, vns));
+    // q > 0: U^k moves along the segment from U^0 to U^n; q < 0: it
+    // alternates around U_eq within |U^0 - U_eq|
+    float B = (q > 0.f) ? sqrtf(fmaxf(v0s, vns)) : sqrtf(ves) + sqrtf(dvs);
     if (c.contact != PIBM_CONTACT_NONE) {
         bool close = false;
         int cnt = scan_neighbours<D, false>(pos4, start, keys_sorted, c, s, B + 0.5f * c.skin, close, nullptr, nullptr, 0);
@@ -715,7 +714,7 @@ struct Active {
     int cnt;
     bool wall;              // a wall lies within contact distance + skin
     // contact-free closed form: U_eq = u* + slip, q = 1 - hc
-    float ueq[3], slip[3], hc, lq, veq;
+    float ueq[3], slip[3], hc, veq;
 };
 
 template <int D>
@@ -750,7 +749,6 @@ __device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const
     P.wall = wall && c.contact != PIBM_CONTACT_NONE;
     const float cc = 2.0f * P.Ap * P.ri / P.m;
     P.hc = cc * c.h;
-    P.lq = log1pf(-P.hc);
     float ve = 0.f;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -887,6 +885,8 @@ template <int D>
 __device__ __forceinline__ int free_allowance(const Active<D>& P, const PCfg& c, const CandData* first, int nfirst,
                                               const CandData* __restrict__ rest, const float* sdx, const float* su,
                                               const float* sveq, int stride, int remaining) {
+    // the convexity bound needs q = 1 - hc > 0; otherwise take sub-steps
+    if (!(P.hc < 1.0f)) return 0;
     float u2 = 0.f;
 #pragma unroll
     for (int a = 0; a < D; a++) {
@@ -933,9 +933,9 @@ __device__ __forceinline__ int free_allowance(const Active<D>& P, const PCfg& c,
 template <int D>
 __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m) {
     const float mm = (float)m;
-    const float lqm = mm * P.lq;
-    const float qm = expf(lqm);
-    const float S = -expm1f(lqm) / P.hc;
+    float qm, omq;
+    drag_power(P.hc, m, qm, omq);
+    const float S = omq / P.hc;
     const float q = 1.0f - P.hc;
     float v2 = 0.f;
 #pragma unroll
@@ -1141,7 +1141,9 @@ template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4; };
 template <> struct CsrTile<2> { static constexpr int TX = 16, TY = 16, TZ = 1; };
 constexpr int CSR_MAXP = 384;
 
-template <int D>
+// C components are spread: C = D for the force field; the adjoint spreads
+// C = D + 1 (density and momentum adjoints) with the same kernel.
+template <int D, int C = D>
 __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32_t* __restrict__ start,
                                                     const float* __restrict__ wphi, const float* __restrict__ coef,
                                                     int np, float* __restrict__ F, int ntx, int nty) {
@@ -1149,7 +1151,7 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     constexpr int TX = T::TX, TY = T::TY, TZ = T::TZ;
     constexpr int HX = TX + 3, HY = TY + 3, HZ = (D == 3) ? TZ + 3 : 1;
     constexpr int NR = HY * HZ;                  // halo rows of cells
-    constexpr int PW = 4 * D + D;                // staged floats per particle
+    constexpr int PW = 4 * D + C;                // staged floats per particle
     __shared__ uint32_t cs[NR * (HX + 1)];       // per row: LDS index of each cell's first particle, then the end
     __shared__ uint32_t rowbase[NR + 1], rowg0[NR];
     __shared__ float sp[CSR_MAXP * PW];
@@ -1207,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
 #pragma unroll
             for (int q = 0; q < 4 * D; q++) sp[k * PW + q] = wphi[(long long)gsl * (4 * D) + q];
 #pragma unroll
-            for (int a = 0; a < D; a++) sp[k * PW + 4 * D + a] = coef[(long long)a * np + gsl];
+            for (int a = 0; a < C; a++) sp[k * PW + 4 * D + a] = coef[(long long)a * np + gsl];
         }
     }
     __syncthreads();
@@ -1215,7 +1217,9 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
         const int lx = node % TX, ly = (node / TX) % TY, lz = node / (TX * TY);
         const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
         if (x >= g.n[0] || y >= g.n[1] || z >= g.n[2]) continue;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        float acc[C];
+#pragma unroll
+        for (int a = 0; a < C; a++) acc[a] = 0.f;
         if (total > 0) {
 #pragma unroll 1
             for (int kz = 0; kz < (D == 3 ? 4 : 1); kz++)
@@ -1228,15 +1232,14 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
                         const int ix = lx + 3 - kx;
                         const uint32_t p0 = rc[ix], p1 = rc[ix + 1];
                         for (uint32_t k = p0; k < p1; k++) {
-                            float wx, wy, wz = 1.f, cxv, cyv, czv = 0.f;
+                            float wx, wy, wz = 1.f, cv[C];
                             if (staged) {
                                 const float* q = sp + k * PW;
                                 wx = q[kx];
                                 wy = q[4 + ky];
                                 if (D == 3) wz = q[8 + kz];
-                                cxv = q[4 * D];
-                                cyv = q[4 * D + 1];
-                                if (D == 3) czv = q[4 * D + (D - 1)];
+#pragma unroll
+                                for (int a = 0; a < C; a++) cv[a] = q[4 * D + a];
                             } else {
                                 int rr = 0;
                                 while (rowbase[rr + 1] <= k) rr++;
@@ -1245,23 +1248,38 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
                                 wx = q[kx];
                                 wy = q[4 + ky];
                                 if (D == 3) wz = q[8 % (4 * D) + kz];
-                                cxv = coef[gsl];
-                                cyv = coef[(long long)np + gsl];
-                                if (D == 3) czv = coef[2LL * np + gsl];
+#pragma unroll
+                                for (int a = 0; a < C; a++) cv[a] = coef[(long long)a * np + gsl];
                             }
                             const float W = wx * wy * wz;
-                            a0 += W * cxv;
-                            a1 += W * cyv;
-                            a2 += W * czv;
+#pragma unroll
+                            for (int a = 0; a < C; a++) acc[a] += W * cv[a];
                         }
                     }
                 }
         }
         const long long rn = ((long long)z * g.n[1] + y) * g.n[0] + x;
-        F[rn] = a0;
-        F[g.N + rn] = a1;
-        if (D == 3) F[2 * g.N + rn] = a2;
+#pragma unroll
+        for (int a = 0; a < C; a++) F[(long long)a * g.N + rn] = acc[a];
     }
+}
+
+// Spread C per-particle components (coef[a * np + s], sorted order) with the
+// weights wphi of the same slots onto C node fields (L = 0 only).
+template <int D, int C>
+void spread_fields(const PBuf& b, int np, const PCfg& c, const Grid& g, const float* coef, float* out,
+                   hipStream_t s) {
+    using T = CsrTile<D>;
+    int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY;
+    int ntz = (D == 3) ? (g.n[2] + T::TZ - 1) / T::TZ : 1;
+    hipLaunchKernelGGL((k_spread_csr<D, C>), dim3((unsigned)((long long)ntx * nty * ntz)), dim3(256), 0, s, g, c,
+                       b.start, b.wphi, coef, np, out, ntx, nty);
+}
+
+void particles_spread_adjoint(int D, PBuf& b, int np, const PCfg& c, const Grid& g, const float* coef, float* out,
+                              hipStream_t s) {
+    if (D == 3) spread_fields<3, 4>(b, np, c, g, coef, out, s);
+    else spread_fields<2, 3>(b, np, c, g, coef, out, s);
 }
 
 template <int D> struct SpreadBlock;
@@ -1481,17 +1499,8 @@ void particles_dem(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
 
 void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, float* F, hipStream_t s) {
     if (c.L == 0) {
-        if (D == 3) {
-            using T = CsrTile<3>;
-            int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY, ntz = (g.n[2] + T::TZ - 1) / T::TZ;
-            hipLaunchKernelGGL(k_spread_csr<3>, dim3((unsigned)((long long)ntx * nty * ntz)), dim3(256), 0, s, g, c,
-                               b.start, b.wphi, b.coef, np, F, ntx, nty);
-        } else {
-            using T = CsrTile<2>;
-            int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY;
-            hipLaunchKernelGGL(k_spread_csr<2>, dim3((unsigned)((long long)ntx * nty)), dim3(256), 0, s, g, c,
-                               b.start, b.wphi, b.coef, np, F, ntx, nty);
-        }
+        if (D == 3) spread_fields<3, 3>(b, np, c, g, b.coef, F, s);
+        else spread_fields<2, 2>(b, np, c, g, b.coef, F, s);
         return;
     }
 

@@ -156,6 +156,27 @@ __device__ __forceinline__ unsigned xcd_block() {
 }
 constexpr float PI_F = 3.14159265358979323846f;
 
+// Powers of the drag recurrence factor q = 1 - hc for 0 < hc < 2 (|q| < 1):
+// qm = q^m and omq = 1 - q^m.  For q > 0 through log1p/expm1, accurate when
+// hc is small; for q <= 0 the powers alternate in sign and 1 - q^m has no
+// cancellation.
+__device__ __forceinline__ void drag_power(float hc, int m, float& qm, float& omq) {
+    if (hc < 1.0f) {
+        const float l = (float)m * log1pf(-hc);
+        qm = expf(l);
+        omq = -expm1f(l);
+    } else {
+        const float p = m == 0 ? 1.0f : powf(hc - 1.0f, (float)m);
+        qm = (m & 1) ? -p : p;
+        omq = 1.0f - qm;
+    }
+}
+
+// Particle mass: sphere (3D) or disk of unit depth (2D).
+__device__ __forceinline__ float particle_mass(int D, float d, float rp) {
+    return D == 3 ? rp * (PI_F / 6.0f) * d * d * d : rp * 0.25f * PI_F * d * d;
+}
+
 // Particle-side constants of one configuration.
 struct PCfg {
     int D;

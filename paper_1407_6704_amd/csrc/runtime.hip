@@ -33,6 +33,43 @@ void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, floa
 int particles_totals_blocks();
 void particles_totals(int D, PBuf& b, int np, double* part, double* out, hipStream_t s);
 void particles_unpermute(int D, PBuf& b, int np, bool have_forces, float* out, hipStream_t s);
+void particles_spread_adjoint(int D, PBuf& b, int np, const PCfg& c, const Grid& g, const float* coef, float* out,
+                              hipStream_t s);
+void adj_fill(float* p, long long n, float v, hipStream_t s);
+void adj_save_state(int D, const PBuf& b, int np, float* out, hipStream_t s);
+void adj_save_const(const PBuf& b, int np, float* d, float* rp, hipStream_t s);
+void adj_load_state(int D, PBuf& b, int np, const float* in, const float* d, const float* rp, hipStream_t s);
+void adj_df_collapse(const float* hi, const float* lo, float* out, long long n, hipStream_t s);
+int adj_collide_blocks(long long N);
+int adj_particle_blocks(int np);
+void adj_collide(int Q, int fp16, int sl2, const float* abar, const void* ft, const float* Ft, int hasF,
+                 const float* ff, const Grid& g, float tau, float4* mom, float* Fbar, float4* Mc, float* tpart,
+                 hipStream_t s);
+void adj_assemble(int Q, const float* abar, const float4* Mc, const float* Sf, int hasS, const Grid& g, float tau,
+                  float* abar_out, hipStream_t s);
+void adj_particles(int D, PBuf& b, int np, const Grid& g, const PCfg& c, int two_way, const float4* mom,
+                   const float* Fbar, const float* xbh, const float* xbl, const float* ub, float* xbh_o,
+                   float* xbl_o, float* ub_o, float* coefS, float* gpart, hipStream_t s);
+void adj_accumulate(const float* tpart, int ntb, const float* gpart, int ngb, float* acc, hipStream_t s);
+
+// Layout of the caller's rollout buffer (see pibm_rollout_bytes).
+struct Rollout {
+    int steps = 0, K = 0, nck = 0;
+    bool valid = false;
+    std::vector<char*> ck_f;      // populations (storage format) at steps 0, K, 2K, ... and the final step
+    std::vector<float*> ck_p;     // particle state [xh D][xl D][u D] x np, id order
+    float *d_id = nullptr, *rp_id = nullptr;
+    char* tape_f = nullptr;       // populations at the start of each step of one segment
+    float* tape_F = nullptr;      // force field of each step of one segment
+    float* tape_p = nullptr;      // particle state at the start of each step of one segment
+    float* abar[2] = {nullptr, nullptr};
+    float* Fbar = nullptr;
+    float4* Mc = nullptr;
+    float* Sf = nullptr;
+    float *xbh[2] = {nullptr, nullptr}, *xbl[2] = {nullptr, nullptr}, *ub[2] = {nullptr, nullptr};
+    float* coefS = nullptr;
+    float *tpart = nullptr, *gpart = nullptr, *acc = nullptr;
+};
 }  // namespace pibm
 
 using namespace pibm;
@@ -54,6 +91,7 @@ struct pibm_ctx {
     PBuf pb{};
     PCfg pc{};
     Grid grid{};
+    Rollout ro{};
     bool particles_set = false;
     bool stepped = false;
     std::string err;
@@ -227,6 +265,50 @@ void set_stencil(pibm_ctx& c, double dmax) {
     c.pc.H = std::max(1, (int)std::ceil((dmax + c.cfg.skin + (double)c.pc.eps) / edge));
 }
 
+// Why the adjoint cannot run on this context ("" if it can).
+std::string adjoint_unsupported(const pibm_ctx& c) {
+    if (c.np < 1) return "the adjoint needs at least one particle";
+    if (c.cfg.n_sub != 1) return "the adjoint supports n_sub = 1 only";
+    if (c.cfg.contact == PIBM_CONTACT_LSD) return "the adjoint supports no contact or soft contact only";
+    if (c.cfg.bin_log2 != 0) return "the adjoint needs bin_log2 = 0";
+    return "";
+}
+
+size_t carve_rollout(const pibm_ctx& c, int steps, int K, char* base, Rollout& R) {
+    Carver cv{base};
+    const size_t es = c.fp16 ? 2 : 4;
+    const size_t fbytes = (size_t)c.Q * c.N * es;
+    const long long np = c.np, N = c.N, D = c.D;
+    const size_t pf = (size_t)3 * D * np;
+    R.nck = (steps + K - 1) / K + 1;
+    R.ck_f.assign(R.nck, nullptr);
+    R.ck_p.assign(R.nck, nullptr);
+    for (int i = 0; i < R.nck; i++) {
+        R.ck_f[i] = cv.take<char>(fbytes);
+        R.ck_p[i] = cv.take<float>(pf);
+    }
+    R.d_id = cv.take<float>(np);
+    R.rp_id = cv.take<float>(np);
+    const long long len = std::max(1, std::min(K, steps));
+    R.tape_f = cv.take<char>(len * fbytes);
+    R.tape_F = cv.take<float>(len * D * N);
+    R.tape_p = cv.take<float>(len * pf);
+    for (int k = 0; k < 2; k++) R.abar[k] = cv.take<float>((size_t)c.Q * N);
+    R.Fbar = cv.take<float>(D * N);
+    R.Mc = cv.take<float4>(N);
+    R.Sf = cv.take<float>((D + 1) * N);
+    for (int k = 0; k < 2; k++) {
+        R.xbh[k] = cv.take<float>(D * np);
+        R.xbl[k] = cv.take<float>(D * np);
+        R.ub[k] = cv.take<float>(D * np);
+    }
+    R.coefS = cv.take<float>((D + 1) * np);
+    R.tpart = cv.take<float>(adj_collide_blocks(N));
+    R.gpart = cv.take<float>(3LL * adj_particle_blocks((int)np));
+    R.acc = cv.take<float>(8);
+    return cv.off + 256;
+}
+
 bool init_ctx(pibm_ctx& c, const pibm_config* cfg, int64_t np) {
     c.cfg = *cfg;
     c.Q = cfg->lattice;
@@ -253,7 +335,7 @@ pibm_status sync_and_flags(pibm_ctx* c) {
     if (flags) {
         uint32_t z = 0;
         hipMemcpy(c->pb.flags, &z, 4, hipMemcpyHostToDevice);
-        if (flags & FLAG_UNSTABLE) return fail(c, PIBM_E_UNSTABLE, "unstable: a particle left the box or a drag sub-step had h c >= 1");
+        if (flags & FLAG_UNSTABLE) return fail(c, PIBM_E_UNSTABLE, "unstable: a particle left the box or a drag sub-step had h c >= 2");
         if (flags & FLAG_CAPACITY) return fail(c, PIBM_E_CAPACITY, "a particle had more candidates than max_candidates");
         if (flags & FLAG_SKIN) return fail(c, PIBM_E_SKIN, "a particle moved more than skin/2 within one step");
     }
@@ -477,12 +559,43 @@ pibm_status pibm_read_cell_list(pibm_ctx* c, uint32_t* keys, int32_t* ids, int32
     return check_hip(c, hipStreamSynchronize(c->stream), "read cell list");
 }
 
+}  // extern "C"
+
+namespace {
+// One coupled step from populations fin to fout, with the force field in F.
+void launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
+    const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
+    const bool spread = c->np > 0 && c->cfg.two_way;
+    mark(c, row, 0);
+    lattice_moments(c->Q, c->fp16, c->sl2, fin, c->mom, c->N, c->stream);
+    mark(c, row, 1);
+    if (c->np > 0) particles_sort(c->D, c->pb, c->np, c->pc, c->stream);
+    mark(c, row, 2);
+    if (c->np > 0) particles_interp(c->D, c->pb, c->np, c->grid, c->pc, c->mom, c->stream);
+    mark(c, row, 3);
+    if (c->np > 0) particles_dem(c->D, c->pb, c->np, c->pc, c->stream);
+    mark(c, row, 4);
+    if (spread) particles_spread(c->D, c->pb, c->np, c->pc, c->grid, F, c->stream);
+    mark(c, row, 5);
+    lattice_collide(c->Q, c->fp16, c->sl2, fin, fout, F, spread ? 1 : 0, ff, c->grid, (float)c->cfg.tau,
+                    c->stream);
+    mark(c, row, 6);
+}
+
+size_t pop_bytes(const pibm_ctx* c) { return (size_t)c->Q * c->N * (c->fp16 ? 2 : 4); }
+
+void save_checkpoint(pibm_ctx* c, int i) {
+    hipMemcpyAsync(c->ro.ck_f[i], c->fA, pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    adj_save_state(c->D, c->pb, c->np, c->ro.ck_p[i], c->stream);
+}
+}  // namespace
+
+extern "C" {
+
 pibm_status pibm_step(pibm_ctx* c, int32_t n_steps) {
     if (!c) return PIBM_E_ARG;
     if (n_steps < 0) return fail(c, PIBM_E_ARG, "negative step count");
     if (c->np > 0 && !c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
-    const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
-    const bool spread = c->np > 0 && c->cfg.two_way;
     for (int it = 0; it < n_steps; it++) {
         int row = -1;
         if (c->prof) {
@@ -490,24 +603,105 @@ pibm_status pibm_step(pibm_ctx* c, int32_t n_steps) {
                 if (pibm_status s = drain_events(c)) return s;
             row = c->ev_used++;
         }
-        mark(c, row, 0);
-        lattice_moments(c->Q, c->fp16, c->sl2, c->fA, c->mom, c->N, c->stream);
-        mark(c, row, 1);
-        if (c->np > 0) particles_sort(c->D, c->pb, c->np, c->pc, c->stream);
-        mark(c, row, 2);
-        if (c->np > 0) particles_interp(c->D, c->pb, c->np, c->grid, c->pc, c->mom, c->stream);
-        mark(c, row, 3);
-        if (c->np > 0) particles_dem(c->D, c->pb, c->np, c->pc, c->stream);
-        mark(c, row, 4);
-        if (spread) particles_spread(c->D, c->pb, c->np, c->pc, c->grid, c->F, c->stream);
-        mark(c, row, 5);
-        lattice_collide(c->Q, c->fp16, c->sl2, c->fA, c->fB, c->F, spread ? 1 : 0, ff, c->grid,
-                        (float)c->cfg.tau, c->stream);
-        mark(c, row, 6);
+        launch_step(c, c->fA, c->fB, c->F, row);
         std::swap(c->fA, c->fB);
     }
     if (n_steps > 0) c->stepped = true;
     return check_hip(c, hipGetLastError(), "step launch");
+}
+
+size_t pibm_rollout_bytes(const pibm_ctx* c, int32_t n_steps, int32_t K) {
+    if (!c || n_steps < 0 || K < 1 || !adjoint_unsupported(*c).empty()) return 0;
+    Rollout R;
+    return carve_rollout(*c, n_steps, K, nullptr, R);
+}
+
+pibm_status pibm_forward_ckpt(pibm_ctx* c, int32_t n_steps, int32_t K, void* dev_buf, size_t buf_bytes) {
+    if (!c) return PIBM_E_ARG;
+    c->ro.valid = false;
+    if (n_steps < 0 || K < 1) return fail(c, PIBM_E_ARG, "need n_steps >= 0 and K >= 1");
+    std::string why = adjoint_unsupported(*c);
+    if (!why.empty()) return fail(c, PIBM_E_CONFIG, why);
+    if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
+    Rollout R;
+    const size_t need = carve_rollout(*c, n_steps, K, nullptr, R);
+    if (!dev_buf || buf_bytes < need) return fail(c, PIBM_E_ARG, "rollout buffer too small");
+    char* base = (char*)(((uintptr_t)dev_buf + 255) & ~(uintptr_t)255);
+    if ((size_t)(base - (char*)dev_buf) + need - 256 > buf_bytes) return fail(c, PIBM_E_ARG, "rollout buffer too small");
+    carve_rollout(*c, n_steps, K, base, c->ro);
+    c->ro.steps = n_steps;
+    c->ro.K = K;
+    adj_save_const(c->pb, c->np, c->ro.d_id, c->ro.rp_id, c->stream);
+    for (int t = 0; t < n_steps; t++) {
+        if (t % K == 0) save_checkpoint(c, t / K);
+        launch_step(c, c->fA, c->fB, c->F, -1);
+        std::swap(c->fA, c->fB);
+    }
+    save_checkpoint(c, c->ro.nck - 1);
+    if (n_steps > 0) c->stepped = true;
+    if (pibm_status s = check_hip(c, hipGetLastError(), "forward launch")) return s;
+    c->ro.valid = true;
+    return PIBM_OK;
+}
+
+pibm_status pibm_backward(pibm_ctx* c, const float* dJ_dx_T, const float* dJ_dv_T, float* dJ_dx0, float* dJ_dv0,
+                          double* dJ_dtau, double* dJ_dgravity) {
+    if (!c) return PIBM_E_ARG;
+    Rollout& R = c->ro;
+    if (!R.valid) return fail(c, PIBM_E_STATE, "no recorded rollout (call pibm_forward_ckpt first)");
+    const int D = c->D, np = c->np, Q = c->Q;
+    const long long N = c->N, DN = (long long)D * np;
+    const size_t fbytes = pop_bytes(c), pf = (size_t)3 * D * np;
+    hipStream_t s = c->stream;
+    const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
+    const int spread = c->cfg.two_way ? 1 : 0;
+    const float tau = (float)c->cfg.tau;
+    int cur = 0;
+    adj_fill(R.abar[0], (long long)Q * N, 0.f, s);
+    if (dJ_dx_T) hipMemcpyAsync(R.xbh[0], dJ_dx_T, 4 * DN, hipMemcpyDeviceToDevice, s);
+    else adj_fill(R.xbh[0], DN, 0.f, s);
+    adj_fill(R.xbl[0], DN, 0.f, s);
+    if (dJ_dv_T) hipMemcpyAsync(R.ub[0], dJ_dv_T, 4 * DN, hipMemcpyDeviceToDevice, s);
+    else adj_fill(R.ub[0], DN, 0.f, s);
+    adj_fill(R.acc, 8, 0.f, s);
+    const int nseg = (R.steps + R.K - 1) / R.K;
+    for (int seg = nseg - 1; seg >= 0; seg--) {
+        const int t0 = seg * R.K, len = std::min(R.K, R.steps - t0);
+        // re-run the segment, recording the state at the start of every step
+        hipMemcpyAsync(R.tape_f, R.ck_f[seg], fbytes, hipMemcpyDeviceToDevice, s);
+        adj_load_state(D, c->pb, np, R.ck_p[seg], R.d_id, R.rp_id, s);
+        for (int k = 0; k < len; k++) {
+            adj_save_state(D, c->pb, np, R.tape_p + k * pf, s);
+            void* fout = (k + 1 < len) ? (void*)(R.tape_f + (k + 1) * fbytes) : c->fB;
+            launch_step(c, R.tape_f + k * fbytes, fout, R.tape_F + (size_t)k * D * N, -1);
+        }
+        // reverse it
+        for (int k = len - 1; k >= 0; k--) {
+            adj_load_state(D, c->pb, np, R.tape_p + k * pf, R.d_id, R.rp_id, s);
+            particles_sort(D, c->pb, np, c->pc, s);
+            adj_collide(Q, c->fp16, c->sl2, R.abar[cur], R.tape_f + k * fbytes, R.tape_F + (size_t)k * D * N, spread,
+                        ff, c->grid, tau, c->mom, R.Fbar, R.Mc, R.tpart, s);
+            adj_particles(D, c->pb, np, c->grid, c->pc, spread, c->mom, R.Fbar, R.xbh[cur], R.xbl[cur], R.ub[cur],
+                          R.xbh[1 - cur], R.xbl[1 - cur], R.ub[1 - cur], R.coefS, R.gpart, s);
+            particles_spread_adjoint(D, c->pb, np, c->pc, c->grid, R.coefS, R.Sf, s);
+            adj_assemble(Q, R.abar[cur], R.Mc, R.Sf, 1, c->grid, tau, R.abar[1 - cur], s);
+            adj_accumulate(R.tpart, adj_collide_blocks(N), R.gpart, adj_particle_blocks(np), R.acc, s);
+            cur ^= 1;
+        }
+    }
+    if (dJ_dx0) adj_df_collapse(R.xbh[cur], R.xbl[cur], dJ_dx0, DN, s);
+    if (dJ_dv0) hipMemcpyAsync(dJ_dv0, R.ub[cur], 4 * DN, hipMemcpyDeviceToDevice, s);
+    float acc[8];
+    hipMemcpyAsync(acc, R.acc, sizeof(acc), hipMemcpyDeviceToHost, s);
+    // leave the context in the final state of the rollout
+    hipMemcpyAsync(c->fA, R.ck_f[R.nck - 1], fbytes, hipMemcpyDeviceToDevice, s);
+    adj_load_state(D, c->pb, np, R.ck_p[R.nck - 1], R.d_id, R.rp_id, s);
+    if (pibm_status st = check_hip(c, hipGetLastError(), "backward launch")) return st;
+    if (pibm_status st = sync_and_flags(c)) return st;
+    if (dJ_dtau) *dJ_dtau = (double)acc[0] + (double)acc[1];
+    if (dJ_dgravity)
+        for (int a = 0; a < 3; a++) dJ_dgravity[a] = a < D ? (double)acc[2 + 2 * a] + (double)acc[3 + 2 * a] : 0.0;
+    return PIBM_OK;
 }
 
 pibm_status pibm_set_profiling(pibm_ctx* c, int enable) {

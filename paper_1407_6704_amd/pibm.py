@@ -94,6 +94,9 @@ def load():
         "pibm_diagnostics": ([vp, C.POINTER(Diag)], C.c_int),
         "pibm_set_profiling": ([vp, C.c_int], C.c_int),
         "pibm_phase_times": ([vp, dp, C.POINTER(C.c_int64)], C.c_int),
+        "pibm_rollout_bytes": ([vp, C.c_int32, C.c_int32], C.c_size_t),
+        "pibm_forward_ckpt": ([vp, C.c_int32, C.c_int32, vp, C.c_size_t], C.c_int),
+        "pibm_backward": ([vp, fp, fp, fp, fp, dp, dp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -279,3 +282,75 @@ class Sim:
         p = (C.c_double * 3)()
         self._check(self.lib.pibm_conservation(self.ctx, C.byref(m), p))
         return m.value, list(p)
+
+    # --- adjoint ---------------------------------------------------------
+    def forward_ckpt(self, n_steps, K=100):
+        """Run n_steps steps, recording checkpoints every K steps in a device
+        buffer owned by this object (for backward)."""
+        import torch
+
+        nbytes = self.lib.pibm_rollout_bytes(self.ctx, int(n_steps), int(K))
+        if nbytes == 0:
+            raise PibmError(2, "rollout not supported for this configuration")
+        self.rollout_buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.pibm_forward_ckpt(self.ctx, int(n_steps), int(K),
+                                               C.c_void_p(self.rollout_buf.data_ptr()), int(nbytes)))
+
+    def backward(self, dJ_dx=None, dJ_dv=None):
+        """Gradients of J given dJ/dX_T and dJ/dU_T ((D, N) arrays or device
+        tensors, id order) for the last forward_ckpt.  Returns dx0, dv0 (numpy
+        (D, N) FP32), dtau (float) and dgravity (3 floats)."""
+        import torch
+
+        def dev(a):
+            if a is None:
+                return None
+            t = torch.as_tensor(a, dtype=torch.float32).to(self.device).reshape(self.D, self.np).contiguous()
+            return t
+
+        gx, gv = dev(dJ_dx), dev(dJ_dv)
+        dx0 = torch.empty((self.D, self.np), dtype=torch.float32, device=self.device)
+        dv0 = torch.empty_like(dx0)
+        dtau = C.c_double()
+        dg = (C.c_double * 3)()
+
+        def ptr(t):
+            return C.cast(C.c_void_p(t.data_ptr()), C.POINTER(C.c_float)) if t is not None else None
+
+        self._check(self.lib.pibm_backward(self.ctx, ptr(gx), ptr(gv), ptr(dx0), ptr(dv0), C.byref(dtau), dg))
+        return {"dx0": dx0.cpu().numpy(), "dv0": dv0.cpu().numpy(), "dtau": dtau.value, "dgravity": list(dg)}
+
+
+def settling_rollout(cfg_kwargs, x0, d, rho_p, steps, K=100):
+    """A torch.autograd.Function over a checkpointed rollout.
+
+    Returns a callable f(tau, gravity, v0) -> X_T, where tau is a 0-d tensor,
+    gravity a (3,) tensor and v0 a (D, N) tensor (CPU, float64); X_T is the
+    (D, N) final particle positions.  Its backward calls the library's
+    hand-written adjoint (pibm_backward), which gives dJ/dtau, dJ/dgravity and
+    dJ/dv0 for any J(X_T)."""
+    import torch
+
+    x0 = np.asarray(x0, np.float64)
+    npart = x0.shape[1]
+
+    class Rollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, tau, gravity, v0):
+            kw = dict(cfg_kwargs)
+            kw["tau"] = float(tau)
+            kw["gravity"] = tuple(float(g) for g in gravity.detach().cpu().numpy())
+            sim = Sim(make_config(**kw), npart)
+            sim.set_particles(x0, v0.detach().cpu().numpy(), d, rho_p)
+            sim.forward_ckpt(steps, K)
+            ctx.sim = sim
+            return torch.as_tensor(sim.read_particles()["x"], dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gx):
+            r = ctx.sim.backward(dJ_dx=gx.detach().cpu().numpy())
+            return (torch.tensor(r["dtau"], dtype=torch.float64),
+                    torch.tensor(r["dgravity"], dtype=torch.float64),
+                    torch.as_tensor(r["dv0"], dtype=torch.float64))
+
+    return Rollout.apply
