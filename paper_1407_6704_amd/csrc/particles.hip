@@ -51,74 +51,127 @@ __global__ void k_fill_dyn(uint32_t* p, const uint32_t* count, int mult, uint32_
         p[i] = v;
 }
 
-// Three-phase exclusive scan (u32 or u64).  Tile = 256 threads x 8 items.
-constexpr int SCAN_ITEMS = 8;
+// Three-phase exclusive scan (u32 or u64).  A tile is 256 threads x 16
+// consecutive items; within a block the thread sums are scanned with wave
+// shuffles (64 lanes) and the four wave totals through LDS.
+constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
 
 template <class T>
-__device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T& total) {
-    // sh: 256 entries of LDS
-    int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        T add = (t >= off) ? sh[t - off] : (T)0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
     }
-    T incl = sh[t];
-    total = sh[255];
+    return v;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+template <class T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* sh4, T& total) {
+    const int t = threadIdx.x, w = t >> 6;
+    const T inc = wave_inclusive_scan<T>(v);
+    if ((t & 63) == 63) sh4[w] = inc;
     __syncthreads();
-    return incl - v;
+    T before = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+        if (k < w) before += sh4[k];
+    total = sh4[0] + sh4[1] + sh4[2] + sh4[3];
+    __syncthreads();
+    return before + inc - v;
+}
+
+// Items [base, base + SCAN_ITEMS) of `in`, zero past n; full tiles are read
+// with 16-byte loads (the arrays are 256-byte aligned, base a multiple of 16).
+template <class T>
+__device__ __forceinline__ void load_items(const T* __restrict__ in, long long base, long long n, T* v) {
+    if (base + SCAN_ITEMS <= n) {
+        constexpr int PER = 16 / sizeof(T);
+        const uint4* p = reinterpret_cast<const uint4*>(in + base);
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS / PER; k++) {
+            uint4 q = p[k];
+            T tmp[PER];
+            __builtin_memcpy(tmp, &q, 16);
+#pragma unroll
+            for (int i = 0; i < PER; i++) v[k * PER + i] = tmp[i];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) v[k] = (base + k < n) ? in[base + k] : (T)0;
+    }
 }
 
 template <class T>
 __global__ __launch_bounds__(256) void k_scan_reduce(const T* __restrict__ in, long long n, T* __restrict__ bsum) {
-    __shared__ T sh[256];
-    long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    __shared__ T sh4[4];
+    const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    T v[SCAN_ITEMS];
+    load_items<T>(in, base, n, v);
     T s = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; k++)
-        if (base + k < n) s += in[base + k];
+    for (int k = 0; k < SCAN_ITEMS; k++) s += v[k];
     T tot;
-    block_exclusive_scan<T>(s, sh, tot);
+    block_exclusive_scan<T>(s, sh4, tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
+// One block: exclusive scan of the nb tile sums in place (each thread takes
+// a run of consecutive sums), grand total to *total.
 template <class T>
 __global__ __launch_bounds__(256) void k_scan_top(T* __restrict__ bsum, long long nb, T* __restrict__ total) {
-    __shared__ T sh[256];
-    T carry = 0;
-    for (long long c0 = 0; c0 < nb; c0 += 256) {
-        long long i = c0 + threadIdx.x;
-        T v = (i < nb) ? bsum[i] : (T)0;
-        T tot;
-        T ex = block_exclusive_scan<T>(v, sh, tot);
-        if (i < nb) bsum[i] = ex + carry;
-        carry += tot;
+    __shared__ T sh4[4];
+    const long long per = (nb + 255) / 256;
+    const long long b0 = (long long)threadIdx.x * per;
+    const long long b1 = b0 + per < nb ? b0 + per : nb;
+    T s = 0;
+    for (long long i = b0; i < b1; i++) s += bsum[i];
+    T tot;
+    T run = block_exclusive_scan<T>(s, sh4, tot);
+    for (long long i = b0; i < b1; i++) {
+        const T x = bsum[i];
+        bsum[i] = run;
+        run += x;
     }
-    if (threadIdx.x == 0 && total) *total = carry;
+    if (threadIdx.x == 0 && total) *total = tot;
 }
 
 template <class T>
 __global__ __launch_bounds__(256) void k_scan_down(const T* __restrict__ in, T* __restrict__ out, long long n,
                                                    const T* __restrict__ bsum) {
-    __shared__ T sh[256];
-    long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    __shared__ T sh4[4];
+    const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
     T v[SCAN_ITEMS];
+    load_items<T>(in, base, n, v);
     T s = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; k++) {
-        v[k] = (base + k < n) ? in[base + k] : (T)0;
-        s += v[k];
-    }
+    for (int k = 0; k < SCAN_ITEMS; k++) s += v[k];
     T tot;
-    T ex = block_exclusive_scan<T>(s, sh, tot) + bsum[blockIdx.x];
+    T ex = block_exclusive_scan<T>(s, sh4, tot) + bsum[blockIdx.x];
+    if (base + SCAN_ITEMS <= n) {
+        constexpr int PER = 16 / sizeof(T);
+        uint4* p = reinterpret_cast<uint4*>(out + base);
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; k++) {
-        if (base + k < n) out[base + k] = ex;
-        ex += v[k];
+        for (int k = 0; k < SCAN_ITEMS / PER; k++) {
+            T tmp[PER];
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                tmp[i] = ex;
+                ex += v[k * PER + i];
+            }
+            uint4 q;
+            __builtin_memcpy(&q, tmp, 16);
+            p[k] = q;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            if (base + k < n) out[base + k] = ex;
+            ex += v[k];
+        }
     }
 }
 
@@ -280,10 +333,35 @@ template <int D> struct InterpTile;
 template <> struct InterpTile<3> { static constexpr int CX = 16, CY = 8, CZ = 4; };
 template <> struct InterpTile<2> { static constexpr int CX = 32, CY = 16, CZ = 1; };
 
-template <int D>
+// Node moments (density deviation, momentum) staged into LDS either from
+// the moments pass (MomSrc) or, in D2Q9, straight from the stored
+// populations (PopSrc): only tiles holding particles read the lattice.
+struct MomSrc {
+    const float4* mom;
+    __device__ __forceinline__ float4 at(long long r, long long) const { return mom[r]; }
+};
+template <class S>
+struct PopSrc {
+    const typename S::T* f;
+    S st;
+    __device__ __forceinline__ float4 at(long long r, long long N) const {
+        using L = Lattice<9>;
+        float dr = 0.f, jx = 0.f, jy = 0.f;
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            const float h = st.load(f + (long long)q * N + r);
+            dr += h;
+            if (L::ex(q)) jx += L::ex(q) * h;
+            if (L::ey(q)) jy += L::ey(q) * h;
+        }
+        return make_float4(dr, jx, jy, 0.f);
+    }
+};
+
+template <int D, class Src>
 __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, PCfg c,
                                                      const uint32_t* __restrict__ start,
-                                                     const float4* __restrict__ mom,
+                                                     Src src,
                                                      float* __restrict__ drho_i, float* __restrict__ j_i,
                                                      short4* __restrict__ wbase, float* __restrict__ wphi,
                                                      int ntx, int nty) {
@@ -327,13 +405,24 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
     // [B0 E - 2, (B0 + TB) E]
     const int nx0 = B0x * E - 2, ny0 = B0y * E - 2, nz0 = (D == 3) ? B0z * E - 2 : 0;
     const int lx = T.TBX * E + 3, ly = T.TBY * E + 3, lz = (D == 3) ? T.TBZ * E + 3 : 1;
-    for (int i = t; i < lx * ly * lz; i += 256) {
-        const int ix = i % lx, iy = (i / lx) % ly, iz = i / (lx * ly);
-        const int x = nx0 + ix, y = ny0 + iy, z = nz0 + iz;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2])
-            v = mom[((long long)z * g.n[1] + y) * g.n[0] + x];
-        sm[i] = v;
+    {
+        // every thread issues all of its halo loads before using any (nodes
+        // outside the lattice read node 0 and are zeroed)
+        constexpr int IT = (NX * NY * NZ + 255) / 256;
+        const int nh = lx * ly * lz;
+        float4 v[IT];
+#pragma unroll
+        for (int k = 0; k < IT; k++) {
+            const int i = t + k * 256;
+            const int ix = i % lx, iy = (i / lx) % ly, iz = i / (lx * ly);
+            const int x = nx0 + ix, y = ny0 + iy, z = nz0 + iz;
+            const bool ok = i < nh && x >= 0 && x < g.n[0] && y >= 0 && y < g.n[1] && z >= 0 && z < g.n[2];
+            v[k] = src.at(ok ? ((long long)z * g.n[1] + y) * g.n[0] + x : 0LL, g.N);
+            if (!ok) v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < IT; k++)
+            if (t + k * 256 < nh) sm[t + k * 256] = v[k];
     }
     __syncthreads();
     for (uint32_t k = t; k < total; k += 256) {
@@ -1145,8 +1234,9 @@ constexpr int CSR_MAXP = 384;
 // C = D + 1 (density and momentum adjoints) with the same kernel.
 template <int D, int C = D>
 __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32_t* __restrict__ start,
-                                                    const float* __restrict__ wphi, const float* __restrict__ coef,
-                                                    int np, float* __restrict__ F, int ntx, int nty) {
+                                                    const float* __restrict__ wphi, const short4* __restrict__ wbase,
+                                                    const float* __restrict__ coef, int np, float* __restrict__ F,
+                                                    int ntx, int nty) {
     using T = CsrTile<D>;
     constexpr int TX = T::TX, TY = T::TY, TZ = T::TZ;
     constexpr int HX = TX + 3, HY = TY + 3, HZ = (D == 3) ? TZ + 3 : 1;
@@ -1155,6 +1245,7 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     __shared__ uint32_t cs[NR * (HX + 1)];       // per row: LDS index of each cell's first particle, then the end
     __shared__ uint32_t rowbase[NR + 1], rowg0[NR];
     __shared__ float sp[CSR_MAXP * PW];
+    __shared__ int sb[CSR_MAXP];                 // x index of each staged particle's first stencil node
     const int t = threadIdx.x;
     const int tile = (int)blockIdx.x;
     const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
@@ -1210,6 +1301,7 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
             for (int q = 0; q < 4 * D; q++) sp[k * PW + q] = wphi[(long long)gsl * (4 * D) + q];
 #pragma unroll
             for (int a = 0; a < C; a++) sp[k * PW + 4 * D + a] = coef[(long long)a * np + gsl];
+            sb[k] = wbase[gsl].x;
         }
     }
     __syncthreads();
@@ -1225,36 +1317,35 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
             for (int kz = 0; kz < (D == 3 ? 4 : 1); kz++)
 #pragma unroll 1
                 for (int ky = 0; ky < 4; ky++) {
+                    // the four cells of this row that reach the node are
+                    // contiguous in the row's CSR: one particle range, and
+                    // each particle's x weight index is x - base_x
                     const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
                     const uint32_t* rc = cs + r * (HX + 1);
+                    const uint32_t p0 = rc[lx], p1 = rc[lx + 4];
+                    for (uint32_t k = p0; k < p1; k++) {
+                        float wx, wy, wz = 1.f, cv[C];
+                        if (staged) {
+                            const float* q = sp + k * PW;
+                            wx = q[x - sb[k]];
+                            wy = q[4 + ky];
+                            if (D == 3) wz = q[8 + kz];
 #pragma unroll
-                    for (int kx = 0; kx < 4; kx++) {
-                        const int ix = lx + 3 - kx;
-                        const uint32_t p0 = rc[ix], p1 = rc[ix + 1];
-                        for (uint32_t k = p0; k < p1; k++) {
-                            float wx, wy, wz = 1.f, cv[C];
-                            if (staged) {
-                                const float* q = sp + k * PW;
-                                wx = q[kx];
-                                wy = q[4 + ky];
-                                if (D == 3) wz = q[8 + kz];
+                            for (int a = 0; a < C; a++) cv[a] = q[4 * D + a];
+                        } else {
+                            int rr = 0;
+                            while (rowbase[rr + 1] <= k) rr++;
+                            const uint32_t gsl = rowg0[rr] + (k - rowbase[rr]);
+                            const float* q = wphi + (long long)gsl * (4 * D);
+                            wx = q[x - wbase[gsl].x];
+                            wy = q[4 + ky];
+                            if (D == 3) wz = q[8 % (4 * D) + kz];
 #pragma unroll
-                                for (int a = 0; a < C; a++) cv[a] = q[4 * D + a];
-                            } else {
-                                int rr = 0;
-                                while (rowbase[rr + 1] <= k) rr++;
-                                const uint32_t gsl = rowg0[rr] + (k - rowbase[rr]);
-                                const float* q = wphi + (long long)gsl * (4 * D);
-                                wx = q[kx];
-                                wy = q[4 + ky];
-                                if (D == 3) wz = q[8 % (4 * D) + kz];
-#pragma unroll
-                                for (int a = 0; a < C; a++) cv[a] = coef[(long long)a * np + gsl];
-                            }
-                            const float W = wx * wy * wz;
-#pragma unroll
-                            for (int a = 0; a < C; a++) acc[a] += W * cv[a];
+                            for (int a = 0; a < C; a++) cv[a] = coef[(long long)a * np + gsl];
                         }
+                        const float W = wx * wy * wz;
+#pragma unroll
+                        for (int a = 0; a < C; a++) acc[a] += W * cv[a];
                     }
                 }
         }
@@ -1273,7 +1364,7 @@ void spread_fields(const PBuf& b, int np, const PCfg& c, const Grid& g, const fl
     int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY;
     int ntz = (D == 3) ? (g.n[2] + T::TZ - 1) / T::TZ : 1;
     hipLaunchKernelGGL((k_spread_csr<D, C>), dim3((unsigned)((long long)ntx * nty * ntz)), dim3(256), 0, s, g, c,
-                       b.start, b.wphi, coef, np, out, ntx, nty);
+                       b.start, b.wphi, b.wbase, coef, np, out, ntx, nty);
 }
 
 void particles_spread_adjoint(int D, PBuf& b, int np, const PCfg& c, const Grid& g, const float* coef, float* out,
@@ -1428,6 +1519,28 @@ void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
     b.B = t;
 }
 
+template <class Src>
+static void interp_tile_2d(PBuf& b, int np, const Grid& g, const PCfg& c, Src src, hipStream_t s) {
+    using T = InterpTile<2>;
+    const int E = 1 << c.L;
+    const int bx = T::CX / E, by = T::CY / E;
+    int ntx = (c.nb[0] + bx - 1) / bx, nty = (c.nb[1] + by - 1) / by;
+    hipLaunchKernelGGL((k_interp_tile<2, Src>), dim3((unsigned)((long long)ntx * nty)), dim3(256), 0, s, b.A, np, g,
+                       c, b.start, src, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+}
+
+// D2Q9 with bins of edge 1 or 2: moments straight from the populations f
+// (storage FP32 or FP16 with scale 2^sl2); no separate moments pass.
+void particles_interp_from_populations(PBuf& b, int np, const Grid& g, const PCfg& c, const void* f, int fp16,
+                                       int sl2, hipStream_t s) {
+    if (fp16) {
+        StoreF16 st{ldexpf(1.0f, sl2), ldexpf(1.0f, -sl2)};
+        interp_tile_2d(b, np, g, c, PopSrc<StoreF16>{(const _Float16*)f, st}, s);
+    } else {
+        interp_tile_2d(b, np, g, c, PopSrc<StoreF32>{(const float*)f, StoreF32{1.f, 1.f}}, s);
+    }
+}
+
 void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, const float4* mom, hipStream_t s) {
     if (c.L <= 1) {
         const int E = 1 << c.L;
@@ -1435,14 +1548,10 @@ void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, cons
             using T = InterpTile<3>;
             const int bx = T::CX / E, by = T::CY / E, bz = T::CZ / E;
             int ntx = (c.nb[0] + bx - 1) / bx, nty = (c.nb[1] + by - 1) / by, ntz = (c.nb[2] + bz - 1) / bz;
-            hipLaunchKernelGGL(k_interp_tile<3>, dim3((unsigned)((long long)ntx * nty * ntz)), dim3(256), 0, s, b.A,
-                               np, g, c, b.start, mom, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+            hipLaunchKernelGGL((k_interp_tile<3, MomSrc>), dim3((unsigned)((long long)ntx * nty * ntz)), dim3(256), 0,
+                               s, b.A, np, g, c, b.start, MomSrc{mom}, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
         } else {
-            using T = InterpTile<2>;
-            const int bx = T::CX / E, by = T::CY / E;
-            int ntx = (c.nb[0] + bx - 1) / bx, nty = (c.nb[1] + by - 1) / by;
-            hipLaunchKernelGGL(k_interp_tile<2>, dim3((unsigned)((long long)ntx * nty)), dim3(256), 0, s, b.A, np, g,
-                               c, b.start, mom, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+            interp_tile_2d(b, np, g, c, MomSrc{mom}, s);
         }
         return;
     }

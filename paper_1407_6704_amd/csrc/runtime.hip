@@ -28,6 +28,8 @@ void lattice_totals(int Q, int fp16, int sl2, const void* f, long long N, double
 long long scan_blocks(long long n);
 void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s);
 void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, const float4* mom, hipStream_t s);
+void particles_interp_from_populations(PBuf& b, int np, const Grid& g, const PCfg& c, const void* f, int fp16,
+                                       int sl2, hipStream_t s);
 void particles_dem(int D, PBuf& b, int np, const PCfg& c, hipStream_t s);
 void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, float* F, hipStream_t s);
 int particles_totals_blocks();
@@ -566,12 +568,19 @@ namespace {
 void launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
     const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
     const bool spread = c->np > 0 && c->cfg.two_way;
+    // D2Q9 interpolation takes the moments straight from the populations of
+    // the tiles that hold particles; D3Q19 (19 planes, a larger halo) and the
+    // coarse-bin path read them from a moments pass
+    const bool fused = c->D == 2 && c->pc.L <= 1;
     mark(c, row, 0);
-    lattice_moments(c->Q, c->fp16, c->sl2, fin, c->mom, c->N, c->stream);
+    if (c->np > 0 && !fused) lattice_moments(c->Q, c->fp16, c->sl2, fin, c->mom, c->N, c->stream);
     mark(c, row, 1);
     if (c->np > 0) particles_sort(c->D, c->pb, c->np, c->pc, c->stream);
     mark(c, row, 2);
-    if (c->np > 0) particles_interp(c->D, c->pb, c->np, c->grid, c->pc, c->mom, c->stream);
+    if (c->np > 0) {
+        if (fused) particles_interp_from_populations(c->pb, c->np, c->grid, c->pc, fin, c->fp16, c->sl2, c->stream);
+        else particles_interp(c->D, c->pb, c->np, c->grid, c->pc, c->mom, c->stream);
+    }
     mark(c, row, 3);
     if (c->np > 0) particles_dem(c->D, c->pb, c->np, c->pc, c->stream);
     mark(c, row, 4);
