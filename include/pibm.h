@@ -96,7 +96,9 @@ typedef struct {
     int32_t two_way;          /* 1: spread the particle forces onto the fluid */
     int32_t bin_log2;         /* cell-list bin edge 2^bin_log2 node spacings, 0 .. 3 (0: fastest spreading) */
     int32_t max_candidates;   /* per-particle candidate capacity, 1 .. 64 */
-    int32_t reserved;         /* 0 */
+    int32_t island_setup;     /* set-up of the active islands: 0 automatic, 1 one workgroup,
+                                 2 one launch per phase (identical results; 0 picks 1 while a
+                                 recent step had at most 1024 active particles) */
 } pibm_config;
 
 typedef struct {

@@ -488,7 +488,10 @@ __device__ __forceinline__ int scan_neighbours(const float4* __restrict__ pos4, 
     b[1] = (int)((key / (uint32_t)c.nb[0]) % (uint32_t)c.nb[1]);
     b[2] = (int)(key / ((uint32_t)c.nb[0] * (uint32_t)c.nb[1]));
     int cnt = 0;
-    const int H = c.H;
+    // a partner within (d_s + d_t)/2 + skin + eps <= r_s lies at most
+    // ceil(r_s / edge) bins away (bin = (floor(X - 1/2) + 1) >> L)
+    const float r_s = (0.5f * (me.w + c.dmax) + c.skin + c.eps) * (1.0f + 1e-6f);
+    const int H = min(c.H, max(1, (int)ceilf(r_s * ldexpf(1.0f, -c.L))));
     int zl = (D == 3) ? max(b[2] - H, 0) : 0, zh = (D == 3) ? min(b[2] + H, c.nb[2] - 1) : 0;
     for (int bz = zl; bz <= zh; bz++)
         for (int by = max(b[1] - H, 0); by <= min(b[1] + H, c.nb[1] - 1); by++) {
@@ -608,7 +611,8 @@ __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const
                                                  const unsigned long long* __restrict__ prefix,
                                                  uint32_t* __restrict__ alist, uint32_t* __restrict__ aidx,
                                                  uint32_t* __restrict__ cand, uint32_t* __restrict__ ccount,
-                                                 uint32_t* __restrict__ parent) {
+                                                 uint32_t* __restrict__ parent, uint32_t* __restrict__ isize,
+                                                 uint32_t* __restrict__ fill) {
     int s = xcd_block() * 256 + threadIdx.x;
     if (s >= np) return;
     unsigned long long v = actcc[s];
@@ -619,6 +623,8 @@ __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const
     alist[a] = s;
     aidx[s] = a;
     parent[a] = a;
+    isize[a] = 0;
+    fill[a] = 0;
     bool dummy = false;
     int n = cap > 0 ? scan_neighbours<D, true>(pos4, start, keys_sorted, c, s, 0.f, dummy, actcc, cand + off, cap) : 0;
     ccount[s] = (uint32_t)min(n, cap);
@@ -633,27 +639,36 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x) {
     return x;
 }
 
+// Union active particle a with its later candidates (the larger root is
+// hooked under the smaller, so every island's root is its smallest index).
+__device__ __forceinline__ void uf_hook_one(uint32_t a, const uint32_t* __restrict__ alist,
+                                            const uint32_t* __restrict__ ccount,
+                                            const unsigned long long* __restrict__ prefix,
+                                            const uint32_t* __restrict__ cand, const uint32_t* __restrict__ aidx,
+                                            uint32_t* parent) {
+    uint32_t s = alist[a];
+    uint32_t off = (uint32_t)(prefix[s] & 0xffffffffULL);
+    int cnt = (int)ccount[s];
+    for (int k = 0; k < cnt; k++) {
+        uint32_t b = aidx[cand[off + k]];
+        if (b <= a) continue;
+        while (true) {
+            uint32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+            if (ra == rb) break;
+            if (ra > rb) { uint32_t t = ra; ra = rb; rb = t; }
+            if (atomicCAS(&parent[rb], rb, ra) == rb) break;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_uf_hook(const uint32_t* __restrict__ alist,
                                                  const uint32_t* __restrict__ ccount,
                                                  const unsigned long long* __restrict__ prefix,
                                                  const uint32_t* __restrict__ cand, const uint32_t* __restrict__ aidx,
                                                  uint32_t* parent, const uint32_t* __restrict__ counters) {
     uint32_t na = counters[CNT_ACTIVE];
-    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
-        uint32_t s = alist[a];
-        uint32_t off = (uint32_t)(prefix[s] & 0xffffffffULL);
-        int cnt = (int)ccount[s];
-        for (int k = 0; k < cnt; k++) {
-            uint32_t b = aidx[cand[off + k]];
-            if (b <= a) continue;
-            while (true) {
-                uint32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
-                if (ra == rb) break;
-                if (ra > rb) { uint32_t t = ra; ra = rb; rb = t; }
-                if (atomicCAS(&parent[rb], rb, ra) == rb) break;
-            }
-        }
-    }
+    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256)
+        uf_hook_one(a, alist, ccount, prefix, cand, aidx, parent);
 }
 
 __global__ __launch_bounds__(256) void k_uf_flatten(uint32_t* parent, uint32_t* __restrict__ isize,
@@ -667,17 +682,34 @@ __global__ __launch_bounds__(256) void k_uf_flatten(uint32_t* parent, uint32_t* 
 }
 
 // islands by size class: 1..64 packed into waves, 65 = larger than a wave
+// (ranks within a class are counted in LDS per chunk of 256 and reserved
+// with one global atomic per class and chunk: no contended counter)
 __global__ __launch_bounds__(256) void k_island_class(const uint32_t* __restrict__ parent,
                                                       const uint32_t* __restrict__ isize, uint32_t* __restrict__ irank,
                                                       uint32_t* __restrict__ bigroot, uint32_t* counters) {
-    uint32_t na = counters[CNT_ACTIVE];
-    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
-        if (parent[a] != a) continue;
-        uint32_t sz = isize[a];
-        uint32_t cls = sz <= WAVE ? sz : WAVE + 1;
-        uint32_t r = atomicAdd(&counters[CNT_CLASS + cls], 1u);
-        irank[a] = r;
-        if (cls == WAVE + 1) bigroot[r] = a;
+    __shared__ uint32_t lc[WAVE + 2], gbase[WAVE + 2];
+    const uint32_t t = threadIdx.x;
+    const uint32_t na = counters[CNT_ACTIVE];
+    for (uint32_t c0 = blockIdx.x * 256; c0 < na; c0 += gridDim.x * 256) {
+        if (t < WAVE + 2) lc[t] = 0;
+        __syncthreads();
+        const uint32_t a = c0 + t;
+        uint32_t cls = 0, lr = 0;
+        const bool root = a < na && parent[a] == a;
+        if (root) {
+            const uint32_t sz = isize[a];
+            cls = sz <= WAVE ? sz : WAVE + 1;
+            lr = atomicAdd(&lc[cls], 1u);
+        }
+        __syncthreads();
+        if (t < WAVE + 2 && lc[t] > 0) gbase[t] = atomicAdd(&counters[CNT_CLASS + t], lc[t]);
+        __syncthreads();
+        if (root) {
+            const uint32_t r = gbase[cls] + lr;
+            irank[a] = r;
+            if (cls == WAVE + 1) bigroot[r] = a;
+        }
+        __syncthreads();
     }
 }
 
@@ -700,6 +732,29 @@ __global__ void k_island_plan(uint32_t* counters, const uint32_t* __restrict__ i
     }
 }
 
+// Lane (small islands, packed by size into waves) or slot (large islands)
+// of active particle a; wavebase[s] = first wave of size class s.
+__device__ __forceinline__ void island_place_one(uint32_t a, const uint32_t* __restrict__ parent,
+                                                 const uint32_t* __restrict__ isize,
+                                                 const uint32_t* __restrict__ irank, uint32_t* __restrict__ fill,
+                                                 int* __restrict__ lanemember, uint32_t* __restrict__ loc,
+                                                 const uint32_t* __restrict__ bigoff,
+                                                 uint32_t* __restrict__ bigmember, const uint32_t* wavebase) {
+    uint32_t r = parent[a];
+    uint32_t pos = atomicAdd(&fill[r], 1u);
+    uint32_t sz = isize[r];
+    if (sz <= WAVE) {
+        uint32_t per = WAVE / sz;
+        uint32_t w = wavebase[sz] + irank[r] / per;
+        uint32_t lane = (irank[r] % per) * sz + pos;
+        lanemember[(long long)w * WAVE + lane] = (int)a;
+        loc[a] = lane;
+    } else {
+        bigmember[bigoff[irank[r]] + pos] = a;
+        loc[a] = a;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_island_place(const uint32_t* __restrict__ parent,
                                                       const uint32_t* __restrict__ isize,
                                                       const uint32_t* __restrict__ irank, uint32_t* __restrict__ fill,
@@ -708,26 +763,69 @@ __global__ __launch_bounds__(256) void k_island_place(const uint32_t* __restrict
                                                       uint32_t* __restrict__ bigmember,
                                                       const uint32_t* __restrict__ counters) {
     uint32_t na = counters[CNT_ACTIVE];
-    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
-        uint32_t r = parent[a];
-        uint32_t pos = atomicAdd(&fill[r], 1u);
-        uint32_t sz = isize[r];
-        if (sz <= WAVE) {
-            uint32_t per = WAVE / sz;
-            uint32_t w = counters[CNT_WAVEBASE + sz] + irank[r] / per;
-            uint32_t lane = (irank[r] % per) * sz + pos;
-            lanemember[(long long)w * WAVE + lane] = (int)a;
-            loc[a] = lane;
-        } else {
-            bigmember[bigoff[irank[r]] + pos] = a;
-            loc[a] = a;
-        }
-    }
+    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256)
+        island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, counters + CNT_WAVEBASE);
 }
 
 // Candidate constants for the sub-steps.  K0 = r_c^2 - |r0|^2 is formed in
 // double-float so that overlaps far below the FP32 spacing of positions
 // (1e-9 .. 1e-6 for stiff springs and slow particles) stay resolved.
+template <int D>
+__device__ __forceinline__ void cand_prep_one(uint32_t a, const PState& A, const PCfg& c,
+                                              const uint32_t* __restrict__ alist,
+                                              const uint32_t* __restrict__ ccount,
+                                              const unsigned long long* __restrict__ prefix,
+                                              const uint32_t* __restrict__ cand, const uint32_t* __restrict__ aidx,
+                                              const uint32_t* __restrict__ loc, CandData* __restrict__ cdata) {
+#pragma clang fp contract(off)
+    uint32_t s = alist[a];
+    uint32_t off = (uint32_t)(prefix[s] & 0xffffffffULL);
+    int cnt = (int)ccount[s];
+    float ms = particle_mass(D, A.d[s], A.rp[s]);
+    for (int k = 0; k < cnt; k++) {
+        uint32_t t = cand[off + k];
+        CandData cd;
+        cd.local = (int)loc[aidx[t]];
+        // r0 = X_s - X_t in double-float, |r0|^2 in double-float
+        float sh = 0.f, sl = 0.f;
+        float r0[3] = {0, 0, 0};
+#pragma unroll
+        for (int ax = 0; ax < D; ax++) {
+            float hi, e;
+            two_sum(A.xh[ax][s], -A.xh[ax][t], hi, e);
+            float lo = e + (A.xl[ax][s] - A.xl[ax][t]);
+            float rh, rl;
+            fast_two_sum(hi, lo, rh, rl);
+            r0[ax] = rh;
+            // (rh + rl)^2 = rh^2 + 2 rh rl (+ rl^2, negligible)
+            float p = rh * rh;
+            float pe = fmaf(rh, rh, -p);
+            pe = fmaf(2.0f * rh, rl, pe);
+            float ns, ne;
+            two_sum(sh, p, ns, ne);
+            sl += ne + pe;
+            sh = ns;
+        }
+        // r_c = (d_s + d_t)/2 exactly as a double-float, then r_c^2
+        float dsum, derr;
+        two_sum(A.d[s], A.d[t], dsum, derr);
+        float rch = 0.5f * dsum, rcl = 0.5f * derr;
+        float q = rch * rch;
+        float qe = fmaf(rch, rch, -q);
+        qe = fmaf(2.0f * rch, rcl, qe);
+        // K0 = (q + qe) - (sh + sl)
+        float k0h, k0e;
+        two_sum(q, -sh, k0h, k0e);
+        cd.K0 = k0h + (k0e + (qe - sl));
+        cd.rc = rch;
+        cd.r0[0] = r0[0]; cd.r0[1] = r0[1]; cd.r0[2] = r0[2];
+        float mt = particle_mass(D, A.d[t], A.rp[t]);
+        float meff = ms * mt / (ms + mt);
+        cd.gam = 2.0f * c.zeta * sqrtf(c.kn * meff);
+        cdata[off + k] = cd;
+    }
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_cand_prep(PState A, PCfg c, const uint32_t* __restrict__ alist,
                                                    const uint32_t* __restrict__ ccount,
@@ -735,56 +833,79 @@ __global__ __launch_bounds__(256) void k_cand_prep(PState A, PCfg c, const uint3
                                                    const uint32_t* __restrict__ cand, const uint32_t* __restrict__ aidx,
                                                    const uint32_t* __restrict__ loc, CandData* __restrict__ cdata,
                                                    const uint32_t* __restrict__ counters) {
-#pragma clang fp contract(off)
     uint32_t na = counters[CNT_ACTIVE];
-    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256) {
-        uint32_t s = alist[a];
-        uint32_t off = (uint32_t)(prefix[s] & 0xffffffffULL);
-        int cnt = (int)ccount[s];
-        float ms = particle_mass(D, A.d[s], A.rp[s]);
-        for (int k = 0; k < cnt; k++) {
-            uint32_t t = cand[off + k];
-            CandData cd;
-            cd.local = (int)loc[aidx[t]];
-            // r0 = X_s - X_t in double-float, |r0|^2 in double-float
-            float sh = 0.f, sl = 0.f;
-            float r0[3] = {0, 0, 0};
-#pragma unroll
-            for (int ax = 0; ax < D; ax++) {
-                float hi, e;
-                two_sum(A.xh[ax][s], -A.xh[ax][t], hi, e);
-                float lo = e + (A.xl[ax][s] - A.xl[ax][t]);
-                float rh, rl;
-                fast_two_sum(hi, lo, rh, rl);
-                r0[ax] = rh;
-                // (rh + rl)^2 = rh^2 + 2 rh rl (+ rl^2, negligible)
-                float p = rh * rh;
-                float pe = fmaf(rh, rh, -p);
-                pe = fmaf(2.0f * rh, rl, pe);
-                float ns, ne;
-                two_sum(sh, p, ns, ne);
-                sl += ne + pe;
-                sh = ns;
-            }
-            // r_c = (d_s + d_t)/2 exactly as a double-float, then r_c^2
-            float dsum, derr;
-            two_sum(A.d[s], A.d[t], dsum, derr);
-            float rch = 0.5f * dsum, rcl = 0.5f * derr;
-            float q = rch * rch;
-            float qe = fmaf(rch, rch, -q);
-            qe = fmaf(2.0f * rch, rcl, qe);
-            // K0 = (q + qe) - (sh + sl)
-            float k0h, k0e;
-            two_sum(q, -sh, k0h, k0e);
-            cd.K0 = k0h + (k0e + (qe - sl));
-            cd.rc = rch;
-            cd.r0[0] = r0[0]; cd.r0[1] = r0[1]; cd.r0[2] = r0[2];
-            float mt = particle_mass(D, A.d[t], A.rp[t]);
-            float meff = ms * mt / (ms + mt);
-            cd.gam = 2.0f * c.zeta * sqrtf(c.kn * meff);
-            cdata[off + k] = cd;
+    for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256)
+        cand_prep_one<D>(a, A, c, alist, ccount, prefix, cand, aidx, loc, cdata);
+}
+
+// The whole island set-up of one step in one 1024-thread workgroup, phase
+// after phase (for a few active particles this replaces seven short
+// launches): union the candidates, flatten
+// and size the islands, class them by size, plan the waves, place every
+// member, and prepare the candidate constants.  Same results as the
+// multi-kernel chain (roots are the smallest index; sub-step results do not
+// depend on lane placement).
+constexpr int SETUP_THREADS = 1024;
+template <int D>
+__global__ __launch_bounds__(SETUP_THREADS) void k_island_setup(
+    PState A, PCfg c, const uint32_t* __restrict__ alist, const uint32_t* __restrict__ ccount,
+    const unsigned long long* __restrict__ prefix, const uint32_t* __restrict__ cand,
+    const uint32_t* __restrict__ aidx, uint32_t* parent, uint32_t* isize, uint32_t* irank, uint32_t* fill,
+    int* lanemember, uint32_t* loc, uint32_t* bigroot, uint32_t* bigoff, uint32_t* bigmember, CandData* cdata,
+    uint32_t* counters, long long lane_cap) {
+    __shared__ uint32_t ccls[WAVE + 2];
+    __shared__ uint32_t wbase[WAVE + 1];
+    __shared__ uint32_t nwaves;
+    const uint32_t t = threadIdx.x;
+    const uint32_t na = counters[CNT_ACTIVE];
+    if (t < WAVE + 2) ccls[t] = 0;
+    __syncthreads();
+    for (uint32_t a = t; a < na; a += SETUP_THREADS) uf_hook_one(a, alist, ccount, prefix, cand, aidx, parent);
+    __syncthreads();
+    for (uint32_t a = t; a < na; a += SETUP_THREADS) {
+        uint32_t r = uf_find(parent, a);
+        parent[a] = r;
+        atomicAdd(&isize[r], 1u);
+    }
+    __syncthreads();
+    for (uint32_t a = t; a < na; a += SETUP_THREADS) {
+        if (parent[a] != a) continue;
+        uint32_t sz = isize[a];
+        uint32_t cls = sz <= WAVE ? sz : WAVE + 1;
+        uint32_t r = atomicAdd(&ccls[cls], 1u);
+        irank[a] = r;
+        if (cls == WAVE + 1) bigroot[r] = a;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t waves = 0;
+        for (int sz = 1; sz <= WAVE; sz++) {
+            wbase[sz] = waves;
+            counters[CNT_WAVEBASE + sz] = waves;
+            counters[CNT_CLASS + sz] = ccls[sz];
+            uint32_t per = WAVE / sz;
+            waves += (ccls[sz] + per - 1) / per;
+        }
+        nwaves = waves;
+        counters[CNT_WAVES] = waves;
+        const uint32_t nbig = ccls[WAVE + 1];
+        counters[CNT_CLASS + WAVE + 1] = nbig;
+        counters[CNT_BIG] = nbig;
+        uint32_t off = 0;
+        for (uint32_t k = 0; k < nbig; k++) {
+            bigoff[k] = off;
+            off += isize[bigroot[k]];
         }
     }
+    __syncthreads();
+    const long long nl = min((long long)nwaves * WAVE, lane_cap);
+    for (long long i = t; i < nl; i += SETUP_THREADS) lanemember[i] = -1;
+    __syncthreads();
+    for (uint32_t a = t; a < na; a += SETUP_THREADS)
+        island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, wbase);
+    __syncthreads();
+    for (uint32_t a = t; a < na; a += SETUP_THREADS)
+        cand_prep_one<D>(a, A, c, alist, ccount, prefix, cand, aidx, loc, cdata);
 }
 
 // ---------------------------------------------------------------------------
@@ -1563,7 +1684,7 @@ void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, cons
 }
 
 template <int D>
-static void dem_impl(PBuf& b, int np, const PCfg& c, hipStream_t s) {
+static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s) {
     const unsigned grid_act = std::min<unsigned>(nb256(np), 2048u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, b.counters, (long long)CNT_SIZE, 0u);
     hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.pos4, b.keys_sorted, b.drho_i, b.j_i,
@@ -1572,20 +1693,24 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, hipStream_t s) {
     scan_exclusive<unsigned long long>(b.actcc, b.prefix, np, b.scan_u64,
                                        (unsigned long long*)(void*)b.counters, s);
     hipLaunchKernelGGL(k_collect<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.pos4, b.keys_sorted, b.actcc, b.prefix,
-                       b.alist, b.aidx, b.cand, b.ccount, b.parent);
-    hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, b.isize, b.counters + CNT_ACTIVE, 1, 0u, (long long)np);
-    hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, b.fill, b.counters + CNT_ACTIVE, 1, 0u, (long long)np);
-    hipLaunchKernelGGL(k_uf_hook, dim3(grid_act), dim3(256), 0, s, b.alist, b.ccount, b.prefix, b.cand, b.aidx, b.parent,
-                       b.counters);
-    hipLaunchKernelGGL(k_uf_flatten, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.counters);
-    hipLaunchKernelGGL(k_island_class, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.bigroot, b.counters);
-    hipLaunchKernelGGL(k_island_plan, dim3(1), dim3(64), 0, s, b.counters, b.isize, b.bigroot, b.bigoff);
-    hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, (uint32_t*)b.lanemember, b.counters + CNT_WAVES,
-                       WAVE, 0xffffffffu, b.lane_cap);
-    hipLaunchKernelGGL(k_island_place, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.fill,
-                       b.lanemember, b.loc, b.bigoff, b.bigmember, b.counters);
-    hipLaunchKernelGGL(k_cand_prep<D>, dim3(grid_act), dim3(256), 0, s, b.A, c, b.alist, b.ccount, b.prefix, b.cand,
-                       b.aidx, b.loc, b.cdata, b.counters);
+                       b.alist, b.aidx, b.cand, b.ccount, b.parent, b.isize, b.fill);
+    if (one_group) {
+        hipLaunchKernelGGL(k_island_setup<D>, dim3(1), dim3(SETUP_THREADS), 0, s, b.A, c, b.alist, b.ccount, b.prefix,
+                           b.cand, b.aidx, b.parent, b.isize, b.irank, b.fill, b.lanemember, b.loc, b.bigroot,
+                           b.bigoff, b.bigmember, b.cdata, b.counters, b.lane_cap);
+    } else {
+        hipLaunchKernelGGL(k_uf_hook, dim3(grid_act), dim3(256), 0, s, b.alist, b.ccount, b.prefix, b.cand, b.aidx, b.parent,
+                           b.counters);
+        hipLaunchKernelGGL(k_uf_flatten, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.counters);
+        hipLaunchKernelGGL(k_island_class, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.bigroot, b.counters);
+        hipLaunchKernelGGL(k_island_plan, dim3(1), dim3(64), 0, s, b.counters, b.isize, b.bigroot, b.bigoff);
+        hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, (uint32_t*)b.lanemember, b.counters + CNT_WAVES,
+                           WAVE, 0xffffffffu, b.lane_cap);
+        hipLaunchKernelGGL(k_island_place, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.fill,
+                           b.lanemember, b.loc, b.bigoff, b.bigmember, b.counters);
+        hipLaunchKernelGGL(k_cand_prep<D>, dim3(grid_act), dim3(256), 0, s, b.A, c, b.alist, b.ccount, b.prefix, b.cand,
+                           b.aidx, b.loc, b.cdata, b.counters);
+    }
     hipLaunchKernelGGL(k_island_small<D>, dim3(std::max<unsigned>(grid_act * 4, 256u)), dim3(64), 0, s, b.A, b.Bn,
                        np, c, b.lanemember, b.alist, b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i,
                        b.j_i, b.coef, b.fc,
@@ -1595,9 +1720,9 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, hipStream_t s) {
                        b.gdx, b.gu, (long long)np, b.flags, b.counters);
 }
 
-void particles_dem(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
-    if (D == 3) dem_impl<3>(b, np, c, s);
-    else dem_impl<2>(b, np, c, s);
+void particles_dem(int D, PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s) {
+    if (D == 3) dem_impl<3>(b, np, c, one_group, s);
+    else dem_impl<2>(b, np, c, one_group, s);
     // the new positions and velocities become the current ones
     for (int a = 0; a < 3; a++) {
         std::swap(b.A.xh[a], b.Bn.xh[a]);

@@ -194,6 +194,7 @@ struct PCfg {
     int maxc;
     float eps;          // bound on the trailing position parts left out by screening
     int H;              // neighbour-search half-width in bins: ceil((d_max + skin + eps) / 2^L)
+    float dmax;         // largest diameter present
 };
 
 // Per-candidate constants of the active sub-steps.

@@ -30,7 +30,7 @@ void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s);
 void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, const float4* mom, hipStream_t s);
 void particles_interp_from_populations(PBuf& b, int np, const Grid& g, const PCfg& c, const void* f, int fp16,
                                        int sl2, hipStream_t s);
-void particles_dem(int D, PBuf& b, int np, const PCfg& c, hipStream_t s);
+void particles_dem(int D, PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s);
 void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, float* F, hipStream_t s);
 int particles_totals_blocks();
 void particles_totals(int D, PBuf& b, int np, double* part, double* out, hipStream_t s);
@@ -103,8 +103,13 @@ struct pibm_ctx {
     int ev_rows = 0, ev_used = 0;
     double phase_ms[PIBM_NUM_PHASES] = {0, 0, 0, 0, 0, 0};
     int64_t prof_steps = 0;
+    // active-particle count of a recent step, copied to pinned host memory
+    // every few steps; selects the single-workgroup island set-up
+    uint32_t* host_active = nullptr;
+    uint64_t steps_done = 0;
     ~pibm_ctx() {
         for (hipEvent_t e : ev) hipEventDestroy(e);
+        if (host_active) hipHostFree(host_active);
     }
 };
 
@@ -153,6 +158,7 @@ std::string validate(const pibm_config* cfg, int64_t np) {
     if (cfg->contact < 0 || cfg->contact > 2) return "unknown contact model";
     if (cfg->bin_log2 < 0 || cfg->bin_log2 > 3) return "bin_log2 must be 0..3";
     if (cfg->max_candidates < 1 || cfg->max_candidates > 64) return "max_candidates must be 1..64";
+    if (cfg->island_setup < 0 || cfg->island_setup > 2) return "island_setup must be 0, 1 or 2";
     if (cfg->contact == PIBM_CONTACT_LSD && (!(cfg->kn > 0) || !(cfg->restitution > 0) || cfg->restitution > 1))
         return "linear spring-dashpot needs kn > 0 and 0 < restitution <= 1";
     if (!(cfg->skin >= 0)) return "skin must be >= 0";
@@ -265,6 +271,7 @@ void fill_pcfg(pibm_ctx& c) {
 void set_stencil(pibm_ctx& c, double dmax) {
     const double edge = std::ldexp(1.0, c.cfg.bin_log2);
     c.pc.H = std::max(1, (int)std::ceil((dmax + c.cfg.skin + (double)c.pc.eps) / edge));
+    c.pc.dmax = (float)dmax;
 }
 
 // Why the adjoint cannot run on this context ("" if it can).
@@ -397,6 +404,12 @@ pibm_status pibm_create(const pibm_config* cfg, int64_t n_particles, void* dev_w
     }
     carve(*c, base);
     c->stream = (hipStream_t)hip_stream;
+    if (hipHostMalloc((void**)&c->host_active, 64, hipHostMallocDefault) != hipSuccess) {
+        c->host_active = nullptr;
+        delete c;
+        return PIBM_E_HIP;
+    }
+    *(volatile uint32_t*)c->host_active = 0xffffffffu;   // unknown: multi-kernel set-up
     hipMemsetAsync(c->F, 0, sizeof(float) * c->D * c->N, c->stream);
     hipMemsetAsync(c->pb.flags, 0, 16, c->stream);
     lattice_init_eq(c->Q, c->fp16, c->sl2, c->fA, nullptr, nullptr, c->N, c->stream);
@@ -564,6 +577,8 @@ pibm_status pibm_read_cell_list(pibm_ctx* c, uint32_t* keys, int32_t* ids, int32
 }  // extern "C"
 
 namespace {
+constexpr uint32_t ONE_GROUP_MAX = 1024;   // one pass per phase: faster than nine launches
+
 // One coupled step from populations fin to fout, with the force field in F.
 void launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
     const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
@@ -582,7 +597,16 @@ void launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
         else particles_interp(c->D, c->pb, c->np, c->grid, c->pc, c->mom, c->stream);
     }
     mark(c, row, 3);
-    if (c->np > 0) particles_dem(c->D, c->pb, c->np, c->pc, c->stream);
+    if (c->np > 0) {
+        // island set-up in one workgroup while a recent step had at most
+        // ONE_GROUP_MAX active particles (both paths give the same result)
+        const uint32_t recent = *(volatile uint32_t*)c->host_active;
+        const bool one = c->cfg.island_setup == 1 || (c->cfg.island_setup == 0 && recent <= ONE_GROUP_MAX);
+        particles_dem(c->D, c->pb, c->np, c->pc, one, c->stream);
+        if (c->steps_done % 8 == 0)
+            hipMemcpyAsync(c->host_active, c->pb.counters + CNT_ACTIVE, 4, hipMemcpyDeviceToHost, c->stream);
+    }
+    c->steps_done++;
     mark(c, row, 4);
     if (spread) particles_spread(c->D, c->pb, c->np, c->pc, c->grid, F, c->stream);
     mark(c, row, 5);

@@ -33,7 +33,7 @@ class Config(C.Structure):
         ("fluid_force", C.c_double * 3), ("contact", C.c_int32), ("n_sub", C.c_int32),
         ("kn", C.c_double), ("restitution", C.c_double), ("k_soft", C.c_double),
         ("skin", C.c_double), ("two_way", C.c_int32), ("bin_log2", C.c_int32),
-        ("max_candidates", C.c_int32), ("reserved", C.c_int32),
+        ("max_candidates", C.c_int32), ("island_setup", C.c_int32),
     ]
 
 
@@ -116,7 +116,7 @@ def header_symbols():
 def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, periodic=(0, 0, 0),
                 tau=0.8, rho0=1.0, gravity=(0.0, 0.0, 0.0), fluid_force=(0.0, 0.0, 0.0),
                 contact="lsd", n_sub=1, kn=1e3, restitution=0.9, k_soft=1e-3, skin=0.05,
-                two_way=1, bin_log2=0, max_candidates=16) -> Config:
+                two_way=1, bin_log2=0, max_candidates=16, island_setup=0) -> Config:
     c = Config()
     c.abi_version = ABI_VERSION
     c.lattice = int(lattice)
@@ -132,7 +132,7 @@ def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, pe
     c.n_sub = int(n_sub)
     c.kn, c.restitution, c.k_soft, c.skin = float(kn), float(restitution), float(k_soft), float(skin)
     c.two_way, c.bin_log2, c.max_candidates = int(two_way), int(bin_log2), int(max_candidates)
-    c.reserved = 0
+    c.island_setup = int(island_setup)
     return c
 
 

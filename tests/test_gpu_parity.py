@@ -390,3 +390,47 @@ def test_particle_outside_box_rejected(P):
     with pytest.raises(P.PibmError) as ei:
         sim.set_particles(np.array([[17.0], [3.0]]), None, np.array([0.4]), np.array([2.5]))
     assert ei.value.name == "E_ARG"
+
+
+@pytest.mark.parametrize("lat", [9, 19])
+def test_island_setup_paths_agree(P, lat):
+    """The one-workgroup and the multi-kernel island set-up give bitwise
+    identical steps (clusters, a large island, wall contacts)."""
+    _flush(f"island set-up paths {lat}")
+    D = 3 if lat == 19 else 2
+    n = (48, 30, 1) if D == 2 else (20, 14, 18)
+    rng = np.random.default_rng(43)
+    pts = []
+    for c in range(10):
+        k = 2 + c % 6
+        base = np.array([rng.uniform(3, n[a] - 3 - 0.5 * k) for a in range(D)])
+        for i in range(k):
+            p = base.copy()
+            p[0] += 0.501 * i
+            pts.append(p)
+    base = np.array([4.0] * D)
+    for i in range(9):                      # a 9 x 9 (x 1) sheet: one island of 81
+        for j in range(9):
+            p = base.copy()
+            p[0] += 0.5005 * i
+            p[1] += 0.5005 * j
+            pts.append(p)
+    X = np.array(pts).T.astype(np.float32).astype(np.float64)
+    npart = X.shape[1]
+    d = np.full(npart, 0.5)
+    U = (3e-4 * rng.standard_normal((D, npart))).astype(np.float32).astype(np.float64)
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-5
+    out = []
+    for mode in (1, 2):
+        cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=200, contact="lsd", island_setup=mode)
+        sim = P.Sim(cfg, npart)
+        sim.set_particles(X, U, d, np.full(npart, 2.5))
+        sim.step(3)
+        sim.synchronize()
+        p = sim.read_particles()
+        out.append((sim.read_populations(), p["x"], p["v"], sim.diagnostics()["active"]))
+    assert out[0][3] > 81
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, b)
+
