@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_collide(const typename S::T* __restrict
 
     float h[Q];
 #pragma unroll
-    for (int q = 0; q < Q; q++) h[q] = st.load(fin + (long long)q * N + r);
+    for (int q = 0; q < Q; q++) h[q] = st.load_stream(fin + (long long)q * N + r);
 
     float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll

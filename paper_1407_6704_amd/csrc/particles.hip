@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const 
 // tile extent in dual cells (bins hold 2^L cells per axis)
 template <int D> struct InterpTile;
 template <> struct InterpTile<3> { static constexpr int CX = 16, CY = 8, CZ = 4; };
-template <> struct InterpTile<2> { static constexpr int CX = 32, CY = 16, CZ = 1; };
+template <> struct InterpTile<2> { static constexpr int CX = 128, CY = 8, CZ = 1; };
 
 // Node moments (density deviation, momentum) staged into LDS either from
 // the moments pass (MomSrc) or, in D2Q9, straight from the stored

@@ -53,17 +53,27 @@ template <> struct Lattice<19> {
 
 // Storage codecs: the stored quantity is the deviation h = f - w, in FP32,
 // or scaled by 2^s and rounded to FP16 (nearest-even).  Arithmetic is FP32.
+// load_stream/store_stream mark accesses that are used once per pass
+// (non-temporal), for the streaming lattice kernels.
 struct StoreF32 {
     using T = float;
     float scale, inv_scale;
     __device__ __forceinline__ float load(const T* p) const { return *p; }
     __device__ __forceinline__ void store(T* p, float v) const { *p = v; }
+    __device__ __forceinline__ float load_stream(const T* p) const { return __builtin_nontemporal_load(p); }
+    __device__ __forceinline__ void store_stream(T* p, float v) const { __builtin_nontemporal_store(v, p); }
 };
 struct StoreF16 {
     using T = _Float16;
     float scale, inv_scale;
     __device__ __forceinline__ float load(const T* p) const { return (float)(*p) * inv_scale; }
     __device__ __forceinline__ void store(T* p, float v) const { *p = (_Float16)(v * scale); }
+    __device__ __forceinline__ float load_stream(const T* p) const {
+        return (float)__builtin_nontemporal_load(p) * inv_scale;
+    }
+    __device__ __forceinline__ void store_stream(T* p, float v) const {
+        __builtin_nontemporal_store((_Float16)(v * scale), p);
+    }
 };
 
 struct Grid {
