@@ -529,6 +529,10 @@ __device__ __forceinline__ int scan_neighbours(const float4* __restrict__ pos4, 
 // segment), and every particle moves at most skin/2 (else E_SKIN).  So a
 // particle is provably free when every neighbour gap exceeds B + skin/2 and
 // every wall gap exceeds B; the others are active and run the sub-steps.
+// Active particles get a compact index and a candidate range in particle
+// order: each block's totals of (active, candidates) go to bsum, one small
+// scan turns them into block offsets, and k_collect adds the offsets within
+// the block.
 template <int D>
 __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, PCfg c,
                                                   const uint32_t* __restrict__ start,
@@ -537,68 +541,83 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
                                                   const float* __restrict__ drho_i, const float* __restrict__ j_i,
                                                   float* __restrict__ coef, float* __restrict__ fc,
                                                   unsigned long long* __restrict__ actcc,
+                                                  unsigned long long* __restrict__ bsum,
                                                   uint32_t* __restrict__ flags) {
-    int s = xcd_block() * 256 + threadIdx.x;
-    if (s >= np) return;
-    float d = A.d[s], rp = A.rp[s];
-    float m = particle_mass(D, d, rp);
-    float Ap = 0.25f * PI_F * d * d;
-    float ri = 1.0f + drho_i[s];
-    float cc = 2.0f * Ap * ri / m;
-    float hc = cc * c.h;
-    if (!(hc < 2.0f)) atomicOr(flags, FLAG_UNSTABLE);   // explicit drag diverges
-    float qn, omq;                       // q^n, 1 - q^n
-    drag_power(hc, c.n_sub, qn, omq);
-    float geo = omq / hc;                // sum_{k<n} q^k
-    float q = 1.0f - hc;
-    float bw = 1.0f - c.rho0 / rp;
-    float v0s = 0.f, vns = 0.f, ves = 0.f, dvs = 0.f;
-    float un[3], dx[3], gb[3];
-#pragma unroll
-    for (int a = 0; a < D; a++) {
-        float ja = j_i[(long long)a * np + s];
-        float ustar = ja / ri;
-        float slip = bw * c.g[a] / cc;   // U_eq - u*
-        float ueq = ustar + slip;
-        float u0 = A.u[a][s];
-        un[a] = ueq + (u0 - ueq) * qn;
-        dx[a] = ueq + (u0 - ueq) * (c.h * q * geo);
-        gb[a] = 2.0f * ri * (slip + (u0 - ueq) * (geo * c.h));
-        v0s += u0 * u0;
-        vns += un[a] * un[a];
-        ves += ueq * ueq;
-        dvs += (u0 - ueq) * (u0 - ueq);
-    }
-    // q > 0: U^k moves along the segment from U^0 to U^n; q < 0: it
-    // alternates around U_eq within |U^0 - U_eq|
-    float B = (q > 0.f) ? sqrtf(fmaxf(v0s, vns)) : sqrtf(ves) + sqrtf(dvs);
-    if (c.contact != PIBM_CONTACT_NONE) {
-        bool close = false;
-        int cnt = scan_neighbours<D, false>(pos4, start, keys_sorted, c, s, B + 0.5f * c.skin, close, nullptr, nullptr, 0);
-        bool wall = false;
+    __shared__ unsigned long long sh4[4];
+    const unsigned lb = xcd_block();
+    const int s = lb * 256 + threadIdx.x;
+    const bool valid = s < np;
+    bool active = false;
+    uint32_t ncand = 0;
+    if (valid) {
+        float d = A.d[s], rp = A.rp[s];
+        float m = particle_mass(D, d, rp);
+        float Ap = 0.25f * PI_F * d * d;
+        float ri = 1.0f + drho_i[s];
+        float cc = 2.0f * Ap * ri / m;
+        float hc = cc * c.h;
+        if (!(hc < 2.0f)) atomicOr(flags, FLAG_UNSTABLE);   // explicit drag diverges
+        float qn, omq;                       // q^n, 1 - q^n
+        drag_power(hc, c.n_sub, qn, omq);
+        float geo = omq / hc;                // sum_{k<n} q^k
+        float q = 1.0f - hc;
+        float bw = 1.0f - c.rho0 / rp;
+        float v0s = 0.f, vns = 0.f, ves = 0.f, dvs = 0.f;
+        float un[3], dx[3], gb[3];
 #pragma unroll
         for (int a = 0; a < D; a++) {
-            float x = A.xh[a][s] + A.xl[a][s];
-            wall = wall || (x - 0.5f * d <= B) || (((float)c.n[a] - x) - 0.5f * d <= B);
+            float ja = j_i[(long long)a * np + s];
+            float ustar = ja / ri;
+            float slip = bw * c.g[a] / cc;   // U_eq - u*
+            float ueq = ustar + slip;
+            float u0 = A.u[a][s];
+            un[a] = ueq + (u0 - ueq) * qn;
+            dx[a] = ueq + (u0 - ueq) * (c.h * q * geo);
+            gb[a] = 2.0f * ri * (slip + (u0 - ueq) * (geo * c.h));
+            v0s += u0 * u0;
+            vns += un[a] * un[a];
+            ves += ueq * ueq;
+            dvs += (u0 - ueq) * (u0 - ueq);
         }
-        if (close || wall) {
-            if (cnt > c.maxc) atomicOr(flags, FLAG_CAPACITY);
-            actcc[s] = (1ULL << 32) | (unsigned long long)min(cnt, c.maxc);
-            return;
-        }
-    }
-    actcc[s] = 0ULL;
+        // q > 0: U^k moves along the segment from U^0 to U^n; q < 0: it
+        // alternates around U_eq within |U^0 - U_eq|
+        float B = (q > 0.f) ? sqrtf(fmaxf(v0s, vns)) : sqrtf(ves) + sqrtf(dvs);
+        if (c.contact != PIBM_CONTACT_NONE) {
+            bool close = false;
+            int cnt = scan_neighbours<D, false>(pos4, start, keys_sorted, c, s, B + 0.5f * c.skin, close, nullptr,
+                                               nullptr, 0);
+            bool wall = false;
 #pragma unroll
-    for (int a = 0; a < D; a++) {
-        float xh = A.xh[a][s], xl = A.xl[a][s];
-        df_add(xh, xl, dx[a]);
-        Bn.xh[a][s] = xh;
-        Bn.xl[a][s] = xl;
-        Bn.u[a][s] = un[a];
-        coef[(long long)a * np + s] = Ap * gb[a];
-        fc[(long long)a * np + s] = 0.f;
+            for (int a = 0; a < D; a++) {
+                float x = A.xh[a][s] + A.xl[a][s];
+                wall = wall || (x - 0.5f * d <= B) || (((float)c.n[a] - x) - 0.5f * d <= B);
+            }
+            if (close || wall) {
+                if (cnt > c.maxc) atomicOr(flags, FLAG_CAPACITY);
+                active = true;
+                ncand = (uint32_t)min(cnt, c.maxc);
+            }
+        }
+        if (!active) {
+#pragma unroll
+            for (int a = 0; a < D; a++) {
+                float xh = A.xh[a][s], xl = A.xl[a][s];
+                df_add(xh, xl, dx[a]);
+                Bn.xh[a][s] = xh;
+                Bn.xl[a][s] = xl;
+                Bn.u[a][s] = un[a];
+                coef[(long long)a * np + s] = Ap * gb[a];
+                fc[(long long)a * np + s] = 0.f;
+            }
+            if (B > 0.5f * c.skin) atomicOr(flags, FLAG_SKIN);
+        }
+        actcc[s] = active ? ((1ULL << 32) | (unsigned long long)ncand) : 0ULL;
     }
-    if (B > 0.5f * c.skin) atomicOr(flags, FLAG_SKIN);
+    // block totals (every thread of the block takes part)
+    const unsigned long long v = active ? ((1ULL << 32) | (unsigned long long)ncand) : 0ULL;
+    unsigned long long tot;
+    block_exclusive_scan<unsigned long long>(v, sh4, tot);
+    if (threadIdx.x == 0) bsum[lb] = tot;
 }
 
 // active particles: compact index, candidate list (active partners only; a
@@ -608,16 +627,20 @@ __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const
                                                  const float4* __restrict__ pos4,
                                                  const uint32_t* __restrict__ keys_sorted,
                                                  const unsigned long long* __restrict__ actcc,
-                                                 const unsigned long long* __restrict__ prefix,
+                                                 const unsigned long long* __restrict__ bsum,
+                                                 unsigned long long* __restrict__ prefix,
                                                  uint32_t* __restrict__ alist, uint32_t* __restrict__ aidx,
                                                  uint32_t* __restrict__ cand, uint32_t* __restrict__ ccount,
                                                  uint32_t* __restrict__ parent, uint32_t* __restrict__ isize,
                                                  uint32_t* __restrict__ fill) {
-    int s = xcd_block() * 256 + threadIdx.x;
-    if (s >= np) return;
-    unsigned long long v = actcc[s];
-    if (v == 0ULL) return;
-    unsigned long long p = prefix[s];
+    __shared__ unsigned long long sh4[4];
+    const unsigned lb = xcd_block();
+    int s = lb * 256 + threadIdx.x;
+    const unsigned long long v = s < np ? actcc[s] : 0ULL;
+    unsigned long long tot;
+    const unsigned long long p = block_exclusive_scan<unsigned long long>(v, sh4, tot) + bsum[lb];
+    if (s >= np || v == 0ULL) return;
+    prefix[s] = p;
     uint32_t a = (uint32_t)(p >> 32), off = (uint32_t)(p & 0xffffffffULL);
     int cap = (int)(v & 0xffffffffULL);
     alist[a] = s;
@@ -897,9 +920,6 @@ __global__ __launch_bounds__(SETUP_THREADS) void k_island_setup(
             off += isize[bigroot[k]];
         }
     }
-    __syncthreads();
-    const long long nl = min((long long)nwaves * WAVE, lane_cap);
-    for (long long i = t; i < nl; i += SETUP_THREADS) lanemember[i] = -1;
     __syncthreads();
     for (uint32_t a = t; a < na; a += SETUP_THREADS)
         island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, wbase);
@@ -1191,9 +1211,19 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
     __shared__ CandData scd[WAVE * CAND_LDS];
     const uint32_t nw = counters[CNT_WAVES];
     const int lane = threadIdx.x;
+    // first wave of size class lane + 1 (non-decreasing in the class)
+    const uint32_t wb_lane = counters[CNT_WAVEBASE + 1 + lane];
     for (uint32_t w = blockIdx.x; w < nw; w += gridDim.x) {
-        int a = lanemember[(long long)w * WAVE + lane];
-        bool valid = a >= 0;
+        // the wave's size class is the largest whose first wave is <= w;
+        // its islands fill lanes [0, islands_here * size)
+        const unsigned long long le = __ballot(wb_lane <= w);
+        const int sz = 64 - __clzll(le);
+        const uint32_t per = WAVE / sz;
+        const uint32_t nisl = counters[CNT_CLASS + sz];
+        const uint32_t idx = w - counters[CNT_WAVEBASE + sz];
+        const uint32_t here = min(per, nisl - idx * per);
+        bool valid = (uint32_t)lane < here * (uint32_t)sz;
+        int a = valid ? lanemember[(long long)w * WAVE + lane] : -1;
         uint32_t s = valid ? alist[a] : 0;
         Active<D> P;
         int nfirst = 0, isz = 1;
@@ -1687,13 +1717,13 @@ template <int D>
 static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s) {
     const unsigned grid_act = std::min<unsigned>(nb256(np), 2048u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, b.counters, (long long)CNT_SIZE, 0u);
-    hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.pos4, b.keys_sorted, b.drho_i, b.j_i,
-                       b.coef, b.fc, b.actcc, b.flags);
-    // exclusive scan of (active << 32 | candidates); total -> counters[0..1]
-    scan_exclusive<unsigned long long>(b.actcc, b.prefix, np, b.scan_u64,
-                                       (unsigned long long*)(void*)b.counters, s);
-    hipLaunchKernelGGL(k_collect<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.pos4, b.keys_sorted, b.actcc, b.prefix,
-                       b.alist, b.aidx, b.cand, b.ccount, b.parent, b.isize, b.fill);
+    hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.pos4,
+                       b.keys_sorted, b.drho_i, b.j_i, b.coef, b.fc, b.actcc, b.bsum64, b.flags);
+    // block offsets; totals (candidates, active) -> counters[0..1]
+    hipLaunchKernelGGL((k_scan_top<unsigned long long>), dim3(1), dim3(256), 0, s, b.bsum64, (long long)nb256(np),
+                       (unsigned long long*)(void*)b.counters);
+    hipLaunchKernelGGL(k_collect<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.pos4, b.keys_sorted, b.actcc, b.bsum64,
+                       b.prefix, b.alist, b.aidx, b.cand, b.ccount, b.parent, b.isize, b.fill);
     if (one_group) {
         hipLaunchKernelGGL(k_island_setup<D>, dim3(1), dim3(SETUP_THREADS), 0, s, b.A, c, b.alist, b.ccount, b.prefix,
                            b.cand, b.aidx, b.parent, b.isize, b.irank, b.fill, b.lanemember, b.loc, b.bigroot,
@@ -1704,8 +1734,6 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
         hipLaunchKernelGGL(k_uf_flatten, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.counters);
         hipLaunchKernelGGL(k_island_class, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.bigroot, b.counters);
         hipLaunchKernelGGL(k_island_plan, dim3(1), dim3(64), 0, s, b.counters, b.isize, b.bigroot, b.bigoff);
-        hipLaunchKernelGGL(k_fill_dyn, dim3(grid_act), dim3(256), 0, s, (uint32_t*)b.lanemember, b.counters + CNT_WAVES,
-                           WAVE, 0xffffffffu, b.lane_cap);
         hipLaunchKernelGGL(k_island_place, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.fill,
                            b.lanemember, b.loc, b.bigoff, b.bigmember, b.counters);
         hipLaunchKernelGGL(k_cand_prep<D>, dim3(grid_act), dim3(256), 0, s, b.A, c, b.alist, b.ccount, b.prefix, b.cand,

@@ -222,7 +222,7 @@ struct PBuf {
     uint32_t *cnt, *start, *keys, *slot, *tmp, *keys_sorted;
     float4* pos4;                // (x, y, z) leading parts and d, sorted order
     uint32_t* scan_u32;          // scan block sums
-    unsigned long long *actcc, *prefix, *scan_u64;
+    unsigned long long *actcc, *prefix, *bsum64;   // bsum64: per-block totals of actcc
     float *drho_i, *j_i, *wphi, *coef, *fc;
     short4* wbase;
     uint32_t *alist, *aidx, *cand, *ccount, *parent, *isize, *irank, *fill, *loc, *bigroot, *bigoff, *bigmember;

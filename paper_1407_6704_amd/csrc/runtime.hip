@@ -207,9 +207,9 @@ size_t carve(pibm_ctx& c, char* base) {
         b.keys_sorted = cv.take<uint32_t>(np);
         b.pos4 = cv.take<float4>(np);
         b.scan_u32 = cv.take<uint32_t>(scan_blocks(nb1) + 1);
-        b.scan_u64 = cv.take<unsigned long long>(scan_blocks(np) + 1);
         b.actcc = cv.take<unsigned long long>(np);
         b.prefix = cv.take<unsigned long long>(np);
+        b.bsum64 = cv.take<unsigned long long>(np / 256 + 2);
         b.drho_i = cv.take<float>(np);
         b.j_i = cv.take<float>((size_t)c.D * np);
         b.wphi = cv.take<float>((size_t)4 * c.D * np);
