@@ -139,13 +139,25 @@ __global__ __launch_bounds__(256) void k_scan_top(T* __restrict__ bsum, long lon
     if (threadIdx.x == 0 && total) *total = tot;
 }
 
+// With zero_in the input is cleared after it has been read (the bin counts
+// then start from zero at the next sort without a separate fill).
 template <class T>
-__global__ __launch_bounds__(256) void k_scan_down(const T* __restrict__ in, T* __restrict__ out, long long n,
-                                                   const T* __restrict__ bsum) {
+__global__ __launch_bounds__(256) void k_scan_down(T* __restrict__ in, T* __restrict__ out, long long n,
+                                                   const T* __restrict__ bsum, int zero_in) {
     __shared__ T sh4[4];
     const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
     T v[SCAN_ITEMS];
     load_items<T>(in, base, n, v);
+    if (zero_in) {
+        if (base + SCAN_ITEMS <= n) {
+            uint4* p = reinterpret_cast<uint4*>(in + base);
+#pragma unroll
+            for (int k = 0; k < (int)(SCAN_ITEMS * sizeof(T) / 16); k++) p[k] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (int k = 0; k < SCAN_ITEMS; k++)
+                if (base + k < n) in[base + k] = (T)0;
+        }
+    }
     T s = 0;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; k++) s += v[k];
@@ -175,13 +187,15 @@ __global__ __launch_bounds__(256) void k_scan_down(const T* __restrict__ in, T* 
     }
 }
 
+// Exclusive scan of in[0, n) into out; the input is cleared afterwards when
+// zero_in is set.
 template <class T>
-void scan_exclusive(const T* in, T* out, long long n, T* bsum, T* total, hipStream_t s) {
+void scan_exclusive(T* in, T* out, long long n, T* bsum, T* total, bool zero_in, hipStream_t s) {
     long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL((k_scan_reduce<T>), dim3((unsigned)nb), dim3(256), 0, s, in, n, bsum);
     hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(256), 0, s, bsum, nb, total);
-    hipLaunchKernelGGL((k_scan_down<T>), dim3((unsigned)nb), dim3(256), 0, s, in, out, n, bsum);
+    hipLaunchKernelGGL((k_scan_down<T>), dim3((unsigned)nb), dim3(256), 0, s, in, out, n, bsum, zero_in ? 1 : 0);
 }
 
 long long scan_blocks(long long n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
@@ -542,11 +556,12 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
                                                   float* __restrict__ coef, float* __restrict__ fc,
                                                   unsigned long long* __restrict__ actcc,
                                                   unsigned long long* __restrict__ bsum,
-                                                  uint32_t* __restrict__ flags) {
+                                                  uint32_t* __restrict__ counters, uint32_t* __restrict__ flags) {
     __shared__ unsigned long long sh4[4];
     const unsigned lb = xcd_block();
     const int s = lb * 256 + threadIdx.x;
     const bool valid = s < np;
+    if (lb == 0 && threadIdx.x < CNT_SIZE) counters[threadIdx.x] = 0u;   // this step's counters
     bool active = false;
     uint32_t ncand = 0;
     if (valid) {
@@ -704,6 +719,26 @@ __global__ __launch_bounds__(256) void k_uf_flatten(uint32_t* parent, uint32_t* 
     }
 }
 
+// Wave plan of the small-island classes and offsets of the large islands
+// (one thread; the counts come from the class counters).
+__device__ void island_plan_serial(uint32_t* counters, const uint32_t* __restrict__ isize,
+                                   const uint32_t* __restrict__ bigroot, uint32_t* __restrict__ bigoff) {
+    uint32_t waves = 0;
+    for (int s = 1; s <= WAVE; s++) {
+        counters[CNT_WAVEBASE + s] = waves;
+        uint32_t per = WAVE / s;
+        waves += (counters[CNT_CLASS + s] + per - 1) / per;
+    }
+    counters[CNT_WAVES] = waves;
+    uint32_t nbig = counters[CNT_CLASS + WAVE + 1];
+    counters[CNT_BIG] = nbig;
+    uint32_t off = 0;
+    for (uint32_t k = 0; k < nbig; k++) {
+        bigoff[k] = off;
+        off += isize[bigroot[k]];
+    }
+}
+
 // islands by size class: 1..64 packed into waves, 65 = larger than a wave
 // (ranks within a class are counted in LDS per chunk of 256 and reserved
 // with one global atomic per class and chunk: no contended counter)
@@ -738,22 +773,9 @@ __global__ __launch_bounds__(256) void k_island_class(const uint32_t* __restrict
 
 __global__ void k_island_plan(uint32_t* counters, const uint32_t* __restrict__ isize,
                               const uint32_t* __restrict__ bigroot, uint32_t* __restrict__ bigoff) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint32_t waves = 0;
-    for (int s = 1; s <= WAVE; s++) {
-        counters[CNT_WAVEBASE + s] = waves;
-        uint32_t per = WAVE / s;
-        waves += (counters[CNT_CLASS + s] + per - 1) / per;
-    }
-    counters[CNT_WAVES] = waves;
-    uint32_t nbig = counters[CNT_CLASS + WAVE + 1];
-    counters[CNT_BIG] = nbig;
-    uint32_t off = 0;
-    for (uint32_t k = 0; k < nbig; k++) {
-        bigoff[k] = off;
-        off += isize[bigroot[k]];
-    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) island_plan_serial(counters, isize, bigroot, bigoff);
 }
+
 
 // Lane (small islands, packed by size into waves) or slot (large islands)
 // of active particle a; wavebase[s] = first wave of size class s.
@@ -1653,13 +1675,14 @@ __global__ __launch_bounds__(256) void k_unpermute(PState A, int np, const float
 static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
 void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
+    // the bin counts are zero here: cleared at creation and by the scan of
+    // the previous sort
     long long nbins = c.nbins;
-    hipLaunchKernelGGL(k_fill_u32, dim3(nb256(nbins + 1)), dim3(256), 0, s, b.cnt, nbins + 1, 0u);
     if (D == 3)
         hipLaunchKernelGGL(k_bin_count<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.cnt, b.keys, b.slot, b.flags);
     else
         hipLaunchKernelGGL(k_bin_count<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.cnt, b.keys, b.slot, b.flags);
-    scan_exclusive<uint32_t>(b.cnt, b.start, nbins + 1, b.scan_u32, nullptr, s);
+    scan_exclusive<uint32_t>(b.cnt, b.start, nbins + 1, b.scan_u32, nullptr, true, s);
     hipLaunchKernelGGL(k_scatter, dim3(nb256(np)), dim3(256), 0, s, b.keys, b.slot, b.start, b.tmp, np);
     if (D == 3)
         hipLaunchKernelGGL(k_reorder<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, b.pos4, np);
@@ -1715,10 +1738,10 @@ void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, cons
 
 template <int D>
 static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s) {
-    const unsigned grid_act = std::min<unsigned>(nb256(np), 2048u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, b.counters, (long long)CNT_SIZE, 0u);
+    // the island chain works on the active particles only (grid-stride)
+    const unsigned grid_act = std::min<unsigned>(nb256(np), 128u);
     hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.pos4,
-                       b.keys_sorted, b.drho_i, b.j_i, b.coef, b.fc, b.actcc, b.bsum64, b.flags);
+                       b.keys_sorted, b.drho_i, b.j_i, b.coef, b.fc, b.actcc, b.bsum64, b.counters, b.flags);
     // block offsets; totals (candidates, active) -> counters[0..1]
     hipLaunchKernelGGL((k_scan_top<unsigned long long>), dim3(1), dim3(256), 0, s, b.bsum64, (long long)nb256(np),
                        (unsigned long long*)(void*)b.counters);
@@ -1732,7 +1755,8 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
         hipLaunchKernelGGL(k_uf_hook, dim3(grid_act), dim3(256), 0, s, b.alist, b.ccount, b.prefix, b.cand, b.aidx, b.parent,
                            b.counters);
         hipLaunchKernelGGL(k_uf_flatten, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.counters);
-        hipLaunchKernelGGL(k_island_class, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.bigroot, b.counters);
+        hipLaunchKernelGGL(k_island_class, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.bigroot,
+                           b.counters);
         hipLaunchKernelGGL(k_island_plan, dim3(1), dim3(64), 0, s, b.counters, b.isize, b.bigroot, b.bigoff);
         hipLaunchKernelGGL(k_island_place, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.fill,
                            b.lanemember, b.loc, b.bigoff, b.bigmember, b.counters);
