@@ -1400,7 +1400,7 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
 // reads them from global memory instead of LDS (same order, same result).
 template <int D> struct CsrTile;
 template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4; };
-template <> struct CsrTile<2> { static constexpr int TX = 16, TY = 16, TZ = 1; };
+template <> struct CsrTile<2> { static constexpr int TX = 32, TY = 16, TZ = 1; };
 constexpr int CSR_MAXP = 384;
 
 // C components are spread: C = D for the force field; the adjoint spreads
