@@ -204,89 +204,28 @@ long long scan_blocks(long long n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1;
 // cell list
 // ---------------------------------------------------------------------------
 template <int D>
-// Bin counts, and the totals of each scan tile of SCAN_TILE bins (the
-// particles arrive in the previous step's sorted order, so a wave spans one
-// or two tiles: one atomic per tile and wave).
 __global__ __launch_bounds__(256) void k_bin_count(PState A, int np, PCfg c, uint32_t* __restrict__ cnt,
-                                                   uint32_t* __restrict__ tsum, uint32_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ slot, uint32_t* __restrict__ flags) {
-    const int s = xcd_block() * 256 + threadIdx.x;
-    const bool valid = s < np;
-    uint32_t tile = 0xffffffffu;
-    if (valid) {
-        int b[3] = {0, 0, 0};
-        bool inside = true;
+                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ slot,
+                                                   uint32_t* __restrict__ flags) {
+    int s = xcd_block() * 256 + threadIdx.x;
+    if (s >= np) return;
+    int b[3] = {0, 0, 0};
+    bool inside = true;
 #pragma unroll
-        for (int a = 0; a < D; a++) {
-            float xh = A.xh[a][s], xl = A.xl[a][s];
-            inside = inside && (xh > 0.0f) && (xh < (float)c.n[a]) && isfinite(xh);
-            b[a] = bin_of(c, xh, xl, a);
-        }
-        if (!inside) atomicOr(flags, FLAG_UNSTABLE);
-        uint32_t key = (uint32_t)(((long long)b[2] * c.nb[1] + b[1]) * c.nb[0] + b[0]);
-        keys[s] = key;
-        slot[s] = atomicAdd(&cnt[key], 1u);
-        tile = key / (uint32_t)SCAN_TILE;
+    for (int a = 0; a < D; a++) {
+        float xh = A.xh[a][s], xl = A.xl[a][s];
+        inside = inside && (xh > 0.0f) && (xh < (float)c.n[a]) && isfinite(xh);
+        b[a] = bin_of(c, xh, xl, a);
     }
-    // every lane takes part: one atomic per distinct tile of the wave
-    unsigned long long todo = __ballot(valid);
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const uint32_t t0 = __shfl(tile, leader, 64);
-        const unsigned long long same = __ballot(tile == t0);
-        if ((int)(threadIdx.x & 63) == leader) atomicAdd(&tsum[t0], (uint32_t)__popcll(same));
-        todo &= ~same;
-    }
-}
-
-// Exclusive scan of the bin counts into start[0, n): each block sums the
-// tile totals before it (no separate pass), scans its own tile, and clears
-// the counts it has read (the next sort starts from zero).
-__global__ __launch_bounds__(256) void k_bin_scan(uint32_t* __restrict__ cnt, uint32_t* __restrict__ start,
-                                                  long long n, const uint32_t* __restrict__ tsum) {
-    __shared__ uint32_t sh4[4];
-    const uint32_t b = blockIdx.x;
-    uint32_t pre = 0;
-    for (uint32_t j = threadIdx.x; j < b; j += 256) pre += tsum[j];
-    uint32_t tot;
-    block_exclusive_scan<uint32_t>(pre, sh4, tot);
-    const uint32_t before = tot;
-    const long long base = (long long)b * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
-    uint32_t v[SCAN_ITEMS];
-    load_items<uint32_t>(cnt, base, n, v);
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; k++) sum += v[k];
-    uint32_t btot;
-    uint32_t ex = block_exclusive_scan<uint32_t>(sum, sh4, btot) + before;
-    if (base + SCAN_ITEMS <= n) {
-        uint4* po = reinterpret_cast<uint4*>(start + base);
-        uint4* pc = reinterpret_cast<uint4*>(cnt + base);
-#pragma unroll
-        for (int k = 0; k < SCAN_ITEMS / 4; k++) {
-            uint4 q;
-            q.x = ex; ex += v[4 * k];
-            q.y = ex; ex += v[4 * k + 1];
-            q.z = ex; ex += v[4 * k + 2];
-            q.w = ex; ex += v[4 * k + 3];
-            po[k] = q;
-            pc[k] = make_uint4(0u, 0u, 0u, 0u);
-        }
-    } else {
-        for (int k = 0; k < SCAN_ITEMS; k++)
-            if (base + k < n) {
-                start[base + k] = ex;
-                ex += v[k];
-                cnt[base + k] = 0u;
-            }
-    }
+    if (!inside) atomicOr(flags, FLAG_UNSTABLE);
+    uint32_t key = (uint32_t)(((long long)b[2] * c.nb[1] + b[1]) * c.nb[0] + b[0]);
+    keys[s] = key;
+    slot[s] = atomicAdd(&cnt[key], 1u);
 }
 
 __global__ void k_scatter(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ slot,
-                          const uint32_t* __restrict__ start, uint32_t* __restrict__ tmp, int np,
-                          uint32_t* __restrict__ tsum, int ntiles) {
+                          const uint32_t* __restrict__ start, uint32_t* __restrict__ tmp, int np) {
     int s = blockIdx.x * 256 + threadIdx.x;
-    if (s < ntiles) tsum[s] = 0u;      // read by the scan; zero for the next sort
     if (s >= np) return;
     tmp[start[keys[s]] + slot[s]] = s;
 }
@@ -1739,16 +1678,12 @@ void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
     // the bin counts are zero here: cleared at creation and by the scan of
     // the previous sort
     long long nbins = c.nbins;
-    const long long ntiles = (nbins + 1 + SCAN_TILE - 1) / SCAN_TILE;
     if (D == 3)
-        hipLaunchKernelGGL(k_bin_count<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.cnt, b.scan_u32, b.keys,
-                           b.slot, b.flags);
+        hipLaunchKernelGGL(k_bin_count<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.cnt, b.keys, b.slot, b.flags);
     else
-        hipLaunchKernelGGL(k_bin_count<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.cnt, b.scan_u32, b.keys,
-                           b.slot, b.flags);
-    hipLaunchKernelGGL(k_bin_scan, dim3((unsigned)ntiles), dim3(256), 0, s, b.cnt, b.start, nbins + 1, b.scan_u32);
-    hipLaunchKernelGGL(k_scatter, dim3(nb256(std::max<long long>(np, ntiles))), dim3(256), 0, s, b.keys, b.slot,
-                       b.start, b.tmp, np, b.scan_u32, (int)ntiles);
+        hipLaunchKernelGGL(k_bin_count<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.cnt, b.keys, b.slot, b.flags);
+    scan_exclusive<uint32_t>(b.cnt, b.start, nbins + 1, b.scan_u32, nullptr, true, s);
+    hipLaunchKernelGGL(k_scatter, dim3(nb256(np)), dim3(256), 0, s, b.keys, b.slot, b.start, b.tmp, np);
     if (D == 3)
         hipLaunchKernelGGL(k_reorder<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, b.pos4, np);
     else

@@ -411,10 +411,7 @@ pibm_status pibm_create(const pibm_config* cfg, int64_t n_particles, void* dev_w
     }
     *(volatile uint32_t*)c->host_active = 0xffffffffu;   // unknown: multi-kernel set-up
     hipMemsetAsync(c->F, 0, sizeof(float) * c->D * c->N, c->stream);
-    if (c->np > 0) {
-        hipMemsetAsync(c->pb.cnt, 0, sizeof(uint32_t) * (c->pc.nbins + 1), c->stream);
-        hipMemsetAsync(c->pb.scan_u32, 0, sizeof(uint32_t) * scan_blocks(c->pc.nbins + 1), c->stream);
-    }
+    if (c->np > 0) hipMemsetAsync(c->pb.cnt, 0, sizeof(uint32_t) * (c->pc.nbins + 1), c->stream);
     hipMemsetAsync(c->pb.flags, 0, 16, c->stream);
     lattice_init_eq(c->Q, c->fp16, c->sl2, c->fA, nullptr, nullptr, c->N, c->stream);
     if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
