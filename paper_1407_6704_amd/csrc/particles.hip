@@ -68,18 +68,21 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
     return v;
 }
 
-// Exclusive scan of one value per thread over a 256-thread block.
-template <class T>
-__device__ __forceinline__ T block_exclusive_scan(T v, T* sh4, T& total) {
+// Exclusive scan of one value per thread over a block of NW waves (sh holds
+// NW entries of LDS).
+template <class T, int NW = 4>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T& total) {
     const int t = threadIdx.x, w = t >> 6;
     const T inc = wave_inclusive_scan<T>(v);
-    if ((t & 63) == 63) sh4[w] = inc;
+    if ((t & 63) == 63) sh[w] = inc;
     __syncthreads();
-    T before = 0;
+    T before = 0, all = 0;
 #pragma unroll
-    for (int k = 0; k < 4; k++)
-        if (k < w) before += sh4[k];
-    total = sh4[0] + sh4[1] + sh4[2] + sh4[3];
+    for (int k = 0; k < NW; k++) {
+        if (k < w) before += sh[k];
+        all += sh[k];
+    }
+    total = all;
     __syncthreads();
     return before + inc - v;
 }
@@ -119,18 +122,19 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const T* __restrict__ in, l
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// One block: exclusive scan of the nb tile sums in place (each thread takes
-// a run of consecutive sums), grand total to *total.
+// One block of 1024 threads: exclusive scan of the nb tile sums in place
+// (each thread takes a run of consecutive sums), grand total to *total.
+constexpr int TOP_THREADS = 1024;
 template <class T>
-__global__ __launch_bounds__(256) void k_scan_top(T* __restrict__ bsum, long long nb, T* __restrict__ total) {
-    __shared__ T sh4[4];
-    const long long per = (nb + 255) / 256;
+__global__ __launch_bounds__(TOP_THREADS) void k_scan_top(T* __restrict__ bsum, long long nb, T* __restrict__ total) {
+    __shared__ T sh[TOP_THREADS / 64];
+    const long long per = (nb + TOP_THREADS - 1) / TOP_THREADS;
     const long long b0 = (long long)threadIdx.x * per;
     const long long b1 = b0 + per < nb ? b0 + per : nb;
     T s = 0;
     for (long long i = b0; i < b1; i++) s += bsum[i];
     T tot;
-    T run = block_exclusive_scan<T>(s, sh4, tot);
+    T run = block_exclusive_scan<T, TOP_THREADS / 64>(s, sh, tot);
     for (long long i = b0; i < b1; i++) {
         const T x = bsum[i];
         bsum[i] = run;
@@ -194,7 +198,7 @@ void scan_exclusive(T* in, T* out, long long n, T* bsum, T* total, bool zero_in,
     long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL((k_scan_reduce<T>), dim3((unsigned)nb), dim3(256), 0, s, in, n, bsum);
-    hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(256), 0, s, bsum, nb, total);
+    hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(TOP_THREADS), 0, s, bsum, nb, total);
     hipLaunchKernelGGL((k_scan_down<T>), dim3((unsigned)nb), dim3(256), 0, s, in, out, n, bsum, zero_in ? 1 : 0);
 }
 
@@ -1743,7 +1747,7 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
     hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.pos4,
                        b.keys_sorted, b.drho_i, b.j_i, b.coef, b.fc, b.actcc, b.bsum64, b.counters, b.flags);
     // block offsets; totals (candidates, active) -> counters[0..1]
-    hipLaunchKernelGGL((k_scan_top<unsigned long long>), dim3(1), dim3(256), 0, s, b.bsum64, (long long)nb256(np),
+    hipLaunchKernelGGL((k_scan_top<unsigned long long>), dim3(1), dim3(TOP_THREADS), 0, s, b.bsum64, (long long)nb256(np),
                        (unsigned long long*)(void*)b.counters);
     hipLaunchKernelGGL(k_collect<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.pos4, b.keys_sorted, b.actcc, b.bsum64,
                        b.prefix, b.alist, b.aidx, b.cand, b.ccount, b.parent, b.isize, b.fill);
