@@ -37,16 +37,20 @@ COPY_PROBE_BYTES = 1 << 30
 # device copy of known size (--copy-probe).  Keyed by (kernel, workload); the
 # entry only applies while the kernel's source file hashes to `source_sha`.
 MEASURED_TRAFFIC = {
-    ("collide", "c1"): {"fetch_bytes": 90156.7 * 1024 * 1.9999, "write_bytes": 150347.6 * 1024,
-                        "source_sha": "000559e986cee4ef"},
-    ("moments", "c1"): {"fetch_bytes": 73742.2 * 1024 * 1.9999, "write_bytes": 65536.0 * 1024,
-                        "source_sha": "000559e986cee4ef"},
-    ("collide", "c2"): {"fetch_bytes": 720971.9 * 1024 * 1.9999, "write_bytes": 1260467.6 * 1024,
-                        "source_sha": "000559e986cee4ef"},
-    ("moments", "c2"): {"fetch_bytes": 622610.9 * 1024 * 1.9999, "write_bytes": 262144.0 * 1024,
-                        "source_sha": "000559e986cee4ef"},
-    ("spread", "c2"): {"fetch_bytes": 580638.4 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
-                       "source_sha": "a5d9bd8909ec0070"},
+    ("collide", "c1"): {"fetch_bytes": 90157.0 * 1024 * 1.9999, "write_bytes": 150218.6 * 1024,
+                       "source_sha": "eb1ec442e135ff98"},
+    ("spread", "c1"): {"fetch_bytes": 47800.4 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
+                       "source_sha": "e866b24fb85fc3a5"},
+    ("interp", "c1"): {"fetch_bytes": 98679.1 * 1024 * 1.9999, "write_bytes": 27477.4 * 1024,
+                       "source_sha": "e866b24fb85fc3a5"},
+    ("collide", "c2"): {"fetch_bytes": 720972.0 * 1024 * 1.9999, "write_bytes": 1256009.1 * 1024,
+                       "source_sha": "eb1ec442e135ff98"},
+    ("moments", "c2"): {"fetch_bytes": 622611.5 * 1024 * 1.9999, "write_bytes": 262144.0 * 1024,
+                       "source_sha": "eb1ec442e135ff98"},
+    ("spread", "c2"): {"fetch_bytes": 676075.7 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
+                       "source_sha": "e866b24fb85fc3a5"},
+    ("interp", "c2"): {"fetch_bytes": 515499.0 * 1024 * 1.9999, "write_bytes": 219907.3 * 1024,
+                       "source_sha": "e866b24fb85fc3a5"},
 }
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
 
