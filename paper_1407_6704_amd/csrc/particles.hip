@@ -391,6 +391,7 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
     const TB T{T0::CX / E, T0::CY / E, (D == 3) ? T0::CZ / E : 1};
     __shared__ float4 sm[NX * NY * NZ];
     __shared__ uint32_t rs[MAXR], re[MAXR], roff[MAXR + 1];
+    __shared__ uint32_t scan4[4];
     const int tile = (int)blockIdx.x;
     const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
     const int B0x = tx * T.TBX, B0y = ty * T.TBY, B0z = tz * T.TBZ;
@@ -407,14 +408,13 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
         rs[t] = s0;
         re[t] = s1;
     }
-    __syncthreads();
-    if (t == 0) {
-        uint32_t acc = 0;
-        for (int r = 0; r < T.TBY * T.TBZ; r++) {
-            roff[r] = acc;
-            acc += re[r] - rs[r];
-        }
-        roff[T.TBY * T.TBZ] = acc;
+    {
+        // row offsets: exclusive scan of the row counts over the block
+        const uint32_t n = (t < T.TBY * T.TBZ) ? re[t] - rs[t] : 0u;
+        uint32_t all;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(n, scan4, all);
+        if (t < T.TBY * T.TBZ) roff[t] = ex;
+        if (t == 0) roff[T.TBY * T.TBZ] = all;
     }
     __syncthreads();
     const uint32_t total = roff[T.TBY * T.TBZ];
@@ -444,8 +444,13 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
     }
     __syncthreads();
     for (uint32_t k = t; k < total; k += 256) {
-        int r = 0;
-        while (roff[r + 1] <= k) r++;
+        // row of entry k: the largest r with roff[r] <= k
+        int r = 0, rh = T.TBY * T.TBZ;
+        while (rh - r > 1) {
+            const int mid = (r + rh) >> 1;
+            if (roff[mid] <= k) r = mid;
+            else rh = mid;
+        }
         const uint32_t s = rs[r] + (k - roff[r]);
         int base[3] = {0, 0, 0};
         float phi[3][4];
@@ -1423,6 +1428,9 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     __shared__ uint32_t rowbase[NR + 1], rowg0[NR];
     __shared__ float sp[CSR_MAXP * PW];
     __shared__ int sb[CSR_MAXP];                 // x index of each staged particle's first stencil node
+    __shared__ uint8_t rowof[CSR_MAXP];          // halo row of each staged particle
+    __shared__ uint32_t scan4[4];
+    static_assert(NR <= 255, "halo rows must fit the row table");
     const int t = threadIdx.x;
     const int tile = (int)blockIdx.x;
     const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
@@ -1440,17 +1448,13 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
         }
         rowg0[t] = g0;
         cnt_row = g1 - g0;
-        rowbase[t] = cnt_row;                    // counts first, prefix below
     }
-    __syncthreads();
-    if (t == 0) {
-        uint32_t acc = 0;
-        for (int r = 0; r < NR; r++) {
-            const uint32_t n = rowbase[r];
-            rowbase[r] = acc;
-            acc += n;
-        }
-        rowbase[NR] = acc;
+    {
+        // row offsets: exclusive scan of the row counts over the block
+        uint32_t all;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(cnt_row, scan4, all);
+        if (t < NR) rowbase[t] = ex;
+        if (t == 0) rowbase[NR] = all;
     }
     __syncthreads();
     const uint32_t total = rowbase[NR];
@@ -1470,9 +1474,11 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     }
     const bool staged = total <= (uint32_t)CSR_MAXP;
     if (staged) {
+        if (t < NR)
+            for (uint32_t k = rowbase[t]; k < rowbase[t + 1]; k++) rowof[k] = (uint8_t)t;
+        __syncthreads();
         for (uint32_t k = t; k < total; k += 256) {
-            int r = 0;
-            while (rowbase[r + 1] <= k) r++;
+            const int r = rowof[k];
             const uint32_t gsl = rowg0[r] + (k - rowbase[r]);
 #pragma unroll
             for (int q = 0; q < 4 * D; q++) sp[k * PW + q] = wphi[(long long)gsl * (4 * D) + q];
