@@ -348,7 +348,7 @@ __global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const 
 // particles return before loading anything.
 // tile extent in dual cells (bins hold 2^L cells per axis)
 template <int D> struct InterpTile;
-template <> struct InterpTile<3> { static constexpr int CX = 16, CY = 8, CZ = 4; };
+template <> struct InterpTile<3> { static constexpr int CX = 32, CY = 4, CZ = 4; };
 template <> struct InterpTile<2> { static constexpr int CX = 128, CY = 8, CZ = 1; };
 
 // Node moments (density deviation, momentum) staged into LDS either from
