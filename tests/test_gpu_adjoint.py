@@ -235,3 +235,31 @@ def test_adjoint_c4_copy_against_autograd(P):
          "dx0": _rel(gpu["dx0"], ref["dx0"])}
     _flush("  " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
     assert e["dtau"] <= 1e-4 and e["dg"] <= 1e-4 and e["dv0"] <= 1e-4 and e["dx0"] <= 1e-3
+
+
+def test_adjoint_rejects_unsupported_and_edge_cases(P):
+    """Unsupported forms are refused with PIBM_E_CONFIG; a rollout of zero
+    steps returns the final-state adjoints unchanged; K larger than the
+    rollout is one segment."""
+    n, X, U, d, rp = _small_case(9, 8)
+    for kw in (dict(contact="lsd", n_sub=1), dict(contact="soft", n_sub=4), dict(contact="soft", bin_log2=1)):
+        cfg = P.make_config(lattice=9, n=n, tau=0.7, gravity=(0.0, -1e-3, 0.0), k_soft=2e-3, skin=0.05, **kw)
+        sim = P.Sim(cfg, X.shape[1])
+        sim.set_particles(X, U, d, rp)
+        assert sim.lib.pibm_rollout_bytes(sim.ctx, 10, 5) == 0
+        with pytest.raises(P.PibmError):
+            sim.forward_ckpt(10, 5)
+    cfg = P.make_config(lattice=9, n=n, tau=0.7, gravity=(0.0, -1e-3, 0.0), contact="soft", k_soft=2e-3,
+                        skin=0.05, n_sub=1)
+    sim = P.Sim(cfg, X.shape[1])
+    sim.set_particles(X, U, d, rp)
+    sim.forward_ckpt(0, 4)
+    gx = np.arange(X.size, dtype=np.float64).reshape(X.shape) * 1e-3
+    gv = -gx
+    r = sim.backward(dJ_dx=gx, dJ_dv=gv)
+    assert np.array_equal(r["dx0"], gx.astype(np.float32)) and np.array_equal(r["dv0"], gv.astype(np.float32))
+    assert r["dtau"] == 0.0 and r["dgravity"] == [0.0, 0.0, 0.0]
+    a = _gpu_grads(P, 9, n, X, U, d, rp, 0.7, 1e-3, 6, 50)
+    b = _gpu_grads(P, 9, n, X, U, d, rp, 0.7, 1e-3, 6, 6)
+    assert a["dtau"] == b["dtau"] and np.array_equal(a["dv0"], b["dv0"])
+

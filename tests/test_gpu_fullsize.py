@@ -210,6 +210,34 @@ def test_fp16_crop_against_oracle(P, W, orc):
         assert ex <= 1e-4 and ev <= 1e-4
 
 
+def test_fp16_scale_reading(P, W, orc):
+    """FP16 storage of f - w with the deviations scaled by 2^14 against the
+    unscaled form (scale 2^0), on the 64^3 crop over three steps: slow-flow
+    deviations of 1e-7..1e-5 fall in FP16's subnormal range without the
+    scale, so the scaled form must be clearly more accurate."""
+    w = W.C3_CROP
+    X, U, d, rp = W.make_particles(w)
+    res = {}
+    for sl2 in (14, 0):
+        cfg = P.config_from_workload(w, fp16_scale_log2=sl2)
+        sim = P.Sim(cfg, X.shape[1])
+        sim.set_particles(X, U, d, rp)
+        sim.step(3)
+        sim.synchronize()
+        res[sl2] = (sim.read_populations(), sim.N)
+    oc = G.oracle_cfg(orc, P.config_from_workload(w))
+    f = orc.rest_state(oc)
+    Xo, Uo = X.copy(), U.copy()
+    for _ in range(3):
+        out = orc.step(oc, f, Xo, Uo, d, rp)
+        f, Xo, Uo = out["f"], out["X"], out["U"]
+    e = {sl2: G.field_errors(orc, w.lattice, h, f, N)[:2] for sl2, (h, N) in res.items()}
+    _flush(f"  scale 2^14: eps_u={e[14][0]:.2e} eps_rho={e[14][1]:.2e};  scale 2^0: eps_u={e[0][0]:.2e} "
+           f"eps_rho={e[0][1]:.2e}")
+    assert e[14][0] <= 1e-3 and e[14][1] <= 1e-5
+    assert e[0][0] > 10 * e[14][0]
+
+
 def test_fp16_against_fp32_full_size(P, W, orc):
     """c3 (FP16 storage) against c2 (FP32) from the same initial state, ten
     steps, same error measures."""
