@@ -34,7 +34,7 @@ class Cfg(C.Structure):
         ("tau", C.c_double), ("rho0", C.c_double), ("gravity", C.c_double * 3),
         ("fluid_force", C.c_double * 3), ("contact", C.c_int), ("kn", C.c_double),
         ("restitution", C.c_double), ("k_soft", C.c_double), ("skin", C.c_double),
-        ("n_sub", C.c_int), ("two_way", C.c_int), ("bin_log2", C.c_int),
+        ("n_sub", C.c_int), ("two_way", C.c_int), ("bin_log2", C.c_int), ("interp", C.c_int),
     ]
 
 
@@ -60,6 +60,7 @@ def lib():
             "orc_collide_stream": ([cp, d, d, d], None),
             "orc_delta": ([C.c_double], C.c_double),
             "orc_weights": ([cp, d, i, d], None),
+            "orc_weights_lagrange": ([cp, d, i, d], None),
             "orc_interp": ([cp, C.c_int, d, d, d, d, d], None),
             "orc_spread": ([cp, C.c_int, d, d, d], None),
             "orc_nbins": ([cp, i64], C.c_int64),
@@ -103,7 +104,7 @@ def _f64(a, shape=None):
 def make_cfg(lattice=9, n=(16, 16, 1), periodic=(0, 0, 0), tau=0.8, rho0=1.0,
              gravity=(0.0, 0.0, 0.0), fluid_force=(0.0, 0.0, 0.0), contact="lsd",
              kn=1e3, restitution=0.9, k_soft=1e-3, skin=0.05, n_sub=1, two_way=1,
-             bin_log2=1) -> Cfg:
+             bin_log2=1, interp="delta") -> Cfg:
     c = Cfg()
     c.lattice = int(lattice)
     for a in range(3):
@@ -115,15 +116,16 @@ def make_cfg(lattice=9, n=(16, 16, 1), periodic=(0, 0, 0), tau=0.8, rho0=1.0,
     c.contact = CONTACT[contact] if isinstance(contact, str) else int(contact)
     c.kn, c.restitution, c.k_soft, c.skin = float(kn), float(restitution), float(k_soft), float(skin)
     c.n_sub, c.two_way, c.bin_log2 = int(n_sub), int(two_way), int(bin_log2)
+    c.interp = {"delta": 0, "lagrange": 1}[interp] if isinstance(interp, str) else int(interp)
     return c
 
 
 def Q(cfg):
-    return 19 if cfg.lattice == 19 else 9
+    return int(cfg.lattice)
 
 
 def D(cfg):
-    return 3 if cfg.lattice == 19 else 2
+    return 2 if cfg.lattice == 9 else 3
 
 
 def nnodes(cfg):
@@ -131,7 +133,7 @@ def nnodes(cfg):
 
 
 def tables(lattice):
-    q = 19 if lattice == 19 else 9
+    q = int(lattice)
     e = np.zeros((q, 3), np.int32)
     w = np.zeros(q)
     opp = np.zeros(q, np.int32)
@@ -140,7 +142,7 @@ def tables(lattice):
 
 
 def equilibrium(lattice, rho, u):
-    q = 19 if lattice == 19 else 9
+    q = int(lattice)
     out = np.zeros(q)
     u3 = np.zeros(3)
     u3[: len(u)] = u
@@ -181,6 +183,15 @@ def weights(cfg, X):
     base = np.zeros(3, np.int32)
     phi = np.zeros(12)
     lib().orc_weights(C.byref(cfg), _d(X3), _i(base), _d(phi))
+    return base, phi.reshape(3, 4)
+
+
+def weights_lagrange(cfg, X):
+    X3 = np.full(3, 0.5)
+    X3[: len(X)] = X
+    base = np.zeros(3, np.int32)
+    phi = np.zeros(12)
+    lib().orc_weights_lagrange(C.byref(cfg), _d(X3), _i(base), _d(phi))
     return base, phi.reshape(3, 4)
 
 

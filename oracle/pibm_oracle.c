@@ -8,7 +8,7 @@
  * suite, the smoke check and the CPU-baseline leg of the benchmark may load
  * it.  It shares no source, header, table or helper with the GPU library;
  * the lattice tables below are written out again from the textbook
- * definitions of D2Q9 and D3Q19.
+ * definitions of D2Q9, D3Q15 and D3Q19.
  *
  * Every loop is the definition, in the paper's order: no blocking, no
  * fusion, no shortcut.  Where the paper is silent or garbled the reading
@@ -35,7 +35,7 @@
 #endif
 
 typedef struct {
-    int lattice;            /* 9 = D2Q9, 19 = D3Q19 */
+    int lattice;            /* 9 = D2Q9, 15 = D3Q15, 19 = D3Q19 */
     int n[3];               /* nodes per axis; n[2] == 1 for D2Q9 */
     int periodic[3];        /* 1: periodic lattice axis (no particles allowed) */
     double tau;             /* BGK relaxation time, Eq. lbm2 */
@@ -49,10 +49,14 @@ typedef struct {
     int n_sub;              /* DEM sub-steps per lattice step */
     int two_way;            /* 1: spread the particle force onto the fluid */
     int bin_log2;           /* cell-list bin edge, in node spacings, = 2^bin_log2 */
+    int interp;             /* 0: cosine delta kernel (Eq. lbm11-lbm12); 1: Lagrange
+                               polynomials (Eq. lbm5-lbm6) for the interpolation, the
+                               delta kernel still spreads (Eq. lbm10-lbm11) */
 } orc_cfg;
 
 /* ------------------------------------------------------------------ */
-/* Lattices (R1).  D2Q9 and D3Q19, c = 1, c_s^2 = 1/3.  Direction order is  */
+/* Lattices (R1).  D2Q9, D3Q15 (the paper's lattice, Sec. 2.1) and D3Q19,  */
+/* c = 1, c_s^2 = 1/3.  Direction order is                                  */
 /* the exchange order of the public interface: rest, then opposite pairs.   */
 /* ------------------------------------------------------------------ */
 
@@ -66,26 +70,40 @@ static const int E19[19][3] = {
     {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
     {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
 
-int orc_q(int lattice) { return lattice == 19 ? 19 : 9; }
-int orc_dim(int lattice) { return lattice == 19 ? 3 : 2; }
+static const int E15[15][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
+
+int orc_q(int lattice) { return lattice == 19 ? 19 : (lattice == 15 ? 15 : 9); }
+int orc_dim(int lattice) { return lattice == 9 ? 2 : 3; }
+
+static const int *lattice_vector(int Q, int q)
+{
+    return Q == 19 ? E19[q] : (Q == 15 ? E15[q] : E9[q]);
+}
 
 /* Velocity set, weights and opposite directions.  Weights are the textbook
  * values for the second-order equilibrium of Eq. lbm3 with c_s^2 = 1/3:
- * D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36. */
+ * D2Q9 4/9, 1/9, 1/36; D3Q15 2/9, 1/9, 1/72 (as listed in Sec. 2.1);
+ * D3Q19 1/3, 1/18, 1/36. */
 void orc_tables(int lattice, int *e, double *w, int *opp)
 {
     int Q = orc_q(lattice);
     for (int q = 0; q < Q; q++) {
-        const int *v = (Q == 19) ? E19[q] : E9[q];
+        const int *v = lattice_vector(Q, q);
         int s = abs(v[0]) + abs(v[1]) + abs(v[2]);
         for (int a = 0; a < 3; a++) e[3 * q + a] = v[a];
         if (Q == 19)
             w[q] = (s == 0) ? 1.0 / 3.0 : (s == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+        else if (Q == 15)
+            w[q] = (s == 0) ? 2.0 / 9.0 : (s == 1 ? 1.0 / 9.0 : 1.0 / 72.0);
         else
             w[q] = (s == 0) ? 4.0 / 9.0 : (s == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
         /* opposite: search for -e_q */
         for (int r = 0; r < Q; r++) {
-            const int *u = (Q == 19) ? E19[r] : E9[r];
+            const int *u = lattice_vector(Q, r);
             if (u[0] == -v[0] && u[1] == -v[1] && u[2] == -v[2]) opp[q] = r;
         }
     }
@@ -217,10 +235,47 @@ void orc_weights(const orc_cfg *c, const double *X, int *base, double *phi)
     }
 }
 
+/* O2 with the Lagrange polynomials of Eq. lbm5-lbm6 instead: on the same
+ * four nodes per axis, the basis polynomial of node k through the in-domain
+ * nodes of that axis (four in the interior: cubic; fewer next to a wall),
+ *   l_k(X) = prod over in-domain m != k of (X - x_m) / (x_k - x_m),
+ * x_m = base_a + m + 1/2, and zero for nodes outside the domain. */
+void orc_weights_lagrange(const orc_cfg *c, const double *X, int *base, double *phi)
+{
+    int D = orc_dim(c->lattice);
+    for (int a = 0; a < D; a++) {
+        base[a] = (int)floor(X[a] - 0.5) - 1;
+        int in[4];
+        for (int k = 0; k < 4; k++) {
+            int i = base[a] + k;
+            in[k] = (i >= 0 && i < c->n[a]);
+        }
+        for (int k = 0; k < 4; k++) {
+            double v = 0.0;
+            if (in[k]) {
+                v = 1.0;
+                double xk = base[a] + k + 0.5;
+                for (int m = 0; m < 4; m++) {
+                    if (m == k || !in[m]) continue;
+                    double xm = base[a] + m + 0.5;
+                    v *= (X[a] - xm) / (xk - xm);
+                }
+            }
+            phi[4 * a + k] = v;
+        }
+    }
+    for (int a = D; a < 3; a++) {
+        base[a] = 0;
+        phi[4 * a] = 1.0;
+        phi[4 * a + 1] = phi[4 * a + 2] = phi[4 * a + 3] = 0.0;
+    }
+}
+
 /* O3.  Interpolation of density and momentum to each particle with the
- * weights of O2: rho_i = sum_r W rho, j_i = sum_r W j (R3: moments of the
- * pre-collision state; by linearity this equals interpolating every f_alpha
- * as Eq. lbm5 does and taking moments). */
+ * weights of O2 (or their Lagrange form when interp = 1): rho_i = sum_r W
+ * rho, j_i = sum_r W j (R3: moments of the pre-collision state; by linearity
+ * this equals interpolating every f_alpha as Eq. lbm5 does and taking
+ * moments). */
 void orc_interp(const orc_cfg *c, int np, const double *X, const double *rho,
                 const double *j, double *rho_i, double *j_i)
 {
@@ -230,7 +285,10 @@ void orc_interp(const orc_cfg *c, int np, const double *X, const double *rho,
         double Xp[3] = {0.5, 0.5, 0.5}, phi[12];
         int base[3];
         for (int a = 0; a < D; a++) Xp[a] = X[a * np + p];
-        orc_weights(c, Xp, base, phi);
+        if (c->interp == 1)
+            orc_weights_lagrange(c, Xp, base, phi);
+        else
+            orc_weights(c, Xp, base, phi);
         double sr = 0, sj[3] = {0, 0, 0};
         int kz_n = (D == 3) ? 4 : 1;
         for (int kz = 0; kz < kz_n; kz++)

@@ -33,7 +33,7 @@ def to_oracle_f(orc, lattice, h):
 
 def moments64(orc, lattice, f, N):
     e, _, _ = orc.tables(lattice)
-    D = 3 if lattice == 19 else 2
+    D = 2 if lattice == 9 else 3
     f = np.asarray(f, np.float64).reshape(-1, N)
     rho = f.sum(axis=0)
     j = e[:, :D].T.astype(np.float64) @ f
@@ -44,7 +44,7 @@ def moments_dev(orc, lattice, h):
     """Density deviation and momentum from deviations h (sums of small
     numbers; exact enough to compare FP32 states)."""
     e, _, _ = orc.tables(lattice)
-    D = 3 if lattice == 19 else 2
+    D = 2 if lattice == 9 else 3
     h = np.asarray(h, np.float64)
     return h.sum(axis=0), e[:, :D].T.astype(np.float64) @ h
 

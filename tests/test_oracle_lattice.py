@@ -14,10 +14,10 @@ import numpy as np
 import pytest
 
 
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 15, 19])
 def test_lattice_isotropy(orc, lat):
     e, w, opp = orc.tables(lat)
-    D = 3 if lat == 19 else 2
+    D = 2 if lat == 9 else 3
     e = e[:, :D].astype(float)
     assert abs(w.sum() - 1) < 1e-15
     assert np.abs(w @ e).max() < 1e-15
@@ -36,11 +36,11 @@ def test_lattice_isotropy(orc, lat):
     assert len({tuple(v) for v in e}) == len(e)
 
 
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 15, 19])
 def test_equilibrium_moments(orc, lat):
     rng = np.random.default_rng(1)
     e, w, _ = orc.tables(lat)
-    D = 3 if lat == 19 else 2
+    D = 2 if lat == 9 else 3
     for _ in range(5):
         rho = 1 + 0.1 * rng.standard_normal()
         u = 0.05 * rng.standard_normal(D)
@@ -52,11 +52,11 @@ def test_equilibrium_moments(orc, lat):
         assert np.allclose(Pi, rho * np.eye(D) / 3 + rho * np.outer(u, u), atol=1e-15)
 
 
-@pytest.mark.parametrize("lat,tau", [(9, 0.8), (9, 0.55), (19, 0.6), (19, 1.3)])
+@pytest.mark.parametrize("lat,tau", [(9, 0.8), (9, 0.55), (15, 0.65), (19, 0.6), (19, 1.3)])
 def test_guo_forcing_moments(orc, lat, tau):
     """One node, all axes periodic: streaming returns every population to the
     node, so the step is the collision alone."""
-    D = 3 if lat == 19 else 2
+    D = 2 if lat == 9 else 3
     cfg = orc.make_cfg(lattice=lat, n=(1, 1, 1), periodic=(1, 1, 1), tau=tau, contact="none")
     e, w, _ = orc.tables(lat)
     ef = e[:, :D].astype(float)
@@ -77,7 +77,7 @@ def test_guo_forcing_moments(orc, lat, tau):
     assert np.allclose(got, expect, atol=1e-15)
 
 
-@pytest.mark.parametrize("lat,tau", [(9, 0.8), (9, 0.6), (19, 0.8)])
+@pytest.mark.parametrize("lat,tau", [(9, 0.8), (9, 0.6), (15, 0.85), (19, 0.8)])
 def test_poiseuille_closed_form(orc, lat, tau):
     H, Fx = 8, 1e-6
     cfg = orc.make_cfg(lattice=lat, n=(1, H, 1), periodic=(1, 0, 1), tau=tau, contact="none")
@@ -100,7 +100,7 @@ def test_poiseuille_closed_form(orc, lat, tau):
     assert np.abs(j[1]).max() < 1e-8 * ua.max()
 
 
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 15, 19])
 def test_mass_conservation_walls(orc, lat):
     n = (12, 10, 1) if lat == 9 else (6, 5, 7)
     cfg = orc.make_cfg(lattice=lat, n=n, tau=0.7, contact="none")
