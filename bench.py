@@ -57,7 +57,7 @@ METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint
 
 def algorithmic_bytes(phase: str, w, np_: int) -> float:
     """Algorithmic bytes one launch of a phase moves (per step)."""
-    Q = 19 if w.lattice == 19 else 9
+    Q = int(w.lattice)
     D = w.dim
     es = 2 if w.storage == "fp16" else 4
     N = w.nodes

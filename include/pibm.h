@@ -7,8 +7,9 @@
  * One step n -> n+1 (Sec. 2 of the paper, in this order):
  *   1. density and momentum of the stored populations (Sec. 2.1);
  *   2. cell list of the particles (bins of 2^bin_log2 dual cells);
- *   3. delta-kernel interpolation of density and momentum to every particle
- *      (Eqs. lbm11-lbm12 weights);
+ *   3. interpolation of density and momentum to every particle with the
+ *      delta-kernel weights of Eqs. lbm11-lbm12, or with the Lagrange
+ *      polynomials of Eqs. lbm5-lbm6 on the same four nodes per axis;
  *   4. momentum-exchange force g = 2 (rho_i U - j_i) (Eqs. lbm7-lbm8), its
  *      reaction -A_p g on the particle (Eq. lbm13), contacts and buoyant
  *      weight (Eq. demgov), integrated over n_sub sub-steps;
@@ -49,7 +50,7 @@
 extern "C" {
 #endif
 
-#define PIBM_ABI_VERSION 1
+#define PIBM_ABI_VERSION 2
 
 typedef enum {
     PIBM_OK = 0,
@@ -62,9 +63,10 @@ typedef enum {
     PIBM_E_CAPACITY = 7   /* more candidates per particle than max_candidates */
 } pibm_status;
 
-enum { PIBM_D2Q9 = 9, PIBM_D3Q19 = 19 };
+enum { PIBM_D2Q9 = 9, PIBM_D3Q15 = 15, PIBM_D3Q19 = 19 };
 enum { PIBM_STORE_FP32 = 0, PIBM_STORE_FP16 = 1 };
 enum { PIBM_CONTACT_NONE = 0, PIBM_CONTACT_LSD = 1, PIBM_CONTACT_SOFT = 2 };
+enum { PIBM_INTERP_DELTA = 0, PIBM_INTERP_LAGRANGE = 1 };
 
 /* Lattice velocity order used by pibm_read_populations/pibm_write_populations:
  *   D2Q9 : 0 (0,0); 1 (1,0); 2 (-1,0); 3 (0,1); 4 (0,-1);
@@ -73,11 +75,15 @@ enum { PIBM_CONTACT_NONE = 0, PIBM_CONTACT_LSD = 1, PIBM_CONTACT_SOFT = 2 };
  *          (0,0,1),(0,0,-1); 7..18 edges (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),
  *          (1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),
  *          (0,-1,1).
- * Weights: D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36 (c_s^2 = 1/3). */
+ *   D3Q15 (Sec. 2.1): 0 rest; 1..6 faces in the D3Q19 order; 7..14 corners
+ *          (1,1,1),(-1,-1,-1),(1,1,-1),(-1,-1,1),(1,-1,1),(-1,1,-1),(-1,1,1),
+ *          (1,-1,-1).
+ * Weights: D2Q9 4/9, 1/9, 1/36; D3Q15 2/9, 1/9, 1/72; D3Q19 1/3, 1/18, 1/36
+ * (c_s^2 = 1/3). */
 
 typedef struct {
     int32_t abi_version;      /* PIBM_ABI_VERSION */
-    int32_t lattice;          /* PIBM_D2Q9 or PIBM_D3Q19 */
+    int32_t lattice;          /* PIBM_D2Q9, PIBM_D3Q15 or PIBM_D3Q19 */
     int32_t storage;          /* PIBM_STORE_FP32: f - w in FP32;
                                  PIBM_STORE_FP16: (f - w) * 2^fp16_scale_log2 in FP16 */
     int32_t fp16_scale_log2;  /* 0 .. 24 */
@@ -99,6 +105,11 @@ typedef struct {
     int32_t island_setup;     /* set-up of the active islands: 0 automatic, 1 one workgroup,
                                  2 one launch per phase (identical results; 0 picks 1 while a
                                  recent step had at most 1024 active particles) */
+    int32_t interp;           /* PIBM_INTERP_DELTA: gather with the delta-kernel weights;
+                                 PIBM_INTERP_LAGRANGE: gather with the Lagrange polynomials
+                                 through the in-domain nodes of the same four per axis (cubic
+                                 in the interior, Eqs. lbm5-lbm6).  Spreading always uses
+                                 the delta kernel (Eq. lbm10) */
 } pibm_config;
 
 typedef struct {
@@ -189,8 +200,9 @@ pibm_status pibm_diagnostics(pibm_ctx* ctx, pibm_diag* out);
  * of every operation of the step (collision and streaming, spreading,
  * momentum exchange, particle update, interpolation, moments), in FP32 with
  * double-float sums of the parameter gradients.
- * Supported: n_sub = 1 (the explicit update of Eq. demgov), contact NONE or
- * SOFT, bin_log2 = 0, FP32 or FP16 storage; other configurations return
+ * Supported: D2Q9 or D3Q19, delta-kernel interpolation, n_sub = 1 (the
+ * explicit update of Eq. demgov), contact NONE or SOFT, bin_log2 = 0, FP32
+ * or FP16 storage; other configurations return
  * PIBM_E_CONFIG.  Memory stays bounded by checkpointing: the state is saved
  * every K steps and each K-step segment is re-run before it is reversed.
  *

@@ -12,7 +12,7 @@
  *
  * Every loop is the definition, in the paper's order: no blocking, no
  * fusion, no shortcut.  Where the paper is silent or garbled the reading
- * taken is stated at the function (readings R1..R17 of the design notes).
+ * taken is stated at the function, tagged R1..R17.
  *
  * Pins (tests/test_oracle_*.py) tie each function to something other than
  * itself: body-force Poiseuille closed form, delta-kernel moments, equilibrium

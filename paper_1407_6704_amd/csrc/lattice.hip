@@ -238,6 +238,8 @@ static void launch_lattice_collide(const void* fin, void* fout, const float* F, 
     do {                                                              \
         if ((Q) == 9 && !(FP16)) { constexpr int QQ = 9; using SS = StoreF32; __VA_ARGS__; }        \
         else if ((Q) == 9) { constexpr int QQ = 9; using SS = StoreF16; __VA_ARGS__; }              \
+        else if ((Q) == 15 && !(FP16)) { constexpr int QQ = 15; using SS = StoreF32; __VA_ARGS__; } \
+        else if ((Q) == 15) { constexpr int QQ = 15; using SS = StoreF16; __VA_ARGS__; }            \
         else if (!(FP16)) { constexpr int QQ = 19; using SS = StoreF32; __VA_ARGS__; }              \
         else { constexpr int QQ = 19; using SS = StoreF16; __VA_ARGS__; }                           \
     } while (0)

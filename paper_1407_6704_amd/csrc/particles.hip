@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_reorder(PState A, PState B, const uint3
 }
 
 // ---------------------------------------------------------------------------
-// interpolation (O2 + O3): weights phi_k = delta(X - (i + 1/2)) of the four
+// interpolation (Eqs. lbm11-lbm12 weights, moments gathered): phi_k = delta(X - (i + 1/2)) of the four
 // nodes i = floor(X - 1/2) - 1 + k, zero outside the domain, divided by
 // their sum.  With fr = X - 1/2 - floor(X - 1/2) the four cosines are
 // -sin, cos, sin, -cos of (pi fr / 2).
@@ -285,7 +285,40 @@ __device__ __forceinline__ void axis_weights(float xh, float xl, int n, int& bas
     phi[0] = w0 * inv; phi[1] = w1 * inv; phi[2] = w2 * inv; phi[3] = w3 * inv;
 }
 
-template <int D>
+// Lagrange form of the gather (Eq. lbm5-lbm6) on the same four nodes: the
+// basis polynomial of node k through the in-domain nodes of the axis,
+// l_k = prod_{m != k, in domain} (t - m) / (k - m), with the particle at
+// t = fr + 1 in node units from node 0 of the stencil.  Cubic in the
+// interior, of lower order next to a wall; zero for nodes outside.
+__device__ __forceinline__ void axis_lagrange(float xh, float xl, int n, float* lag) {
+    const int c = dual_cell(xh, xl);
+    const float t = dual_frac(xh, xl, c) + 1.0f;
+    const int base = c - 1;
+    bool in[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) in[k] = base + k >= 0 && base + k < n;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        float v = in[k] ? 1.0f : 0.0f;
+#pragma unroll
+        for (int m = 0; m < 4; m++)
+            if (m != k && in[m]) v *= (t - (float)m) * (1.0f / (float)(k - m));
+        lag[k] = v;
+    }
+}
+
+// Gather weights of one axis: the delta-kernel weights phi (always: the
+// spreading pass reuses them) and, with LAG, the Lagrange weights in gw.
+template <bool LAG>
+__device__ __forceinline__ void axis_gather(float xh, float xl, int n, int& base, float* phi, float* gw) {
+    axis_weights(xh, xl, n, base, phi);
+    if (LAG) axis_lagrange(xh, xl, n, gw);
+    else
+#pragma unroll
+        for (int k = 0; k < 4; k++) gw[k] = phi[k];
+}
+
+template <int D, bool LAG>
 __global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const float4* __restrict__ mom,
                                                 float* __restrict__ drho_i, float* __restrict__ j_i,
                                                 short4* __restrict__ wbase, float* __restrict__ wphi) {
@@ -296,22 +329,25 @@ __global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const 
     bool valid = s < np;
     int sc = valid ? s : np - 1;
     int base[3] = {0, 0, 0};
-    float phi[3][4];
+    float phi[3][4], gw[3][4];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        if (a < D) axis_weights(A.xh[a][sc], A.xl[a][sc], g.n[a], base[a], phi[a]);
-        else { phi[a][0] = 1.f; phi[a][1] = phi[a][2] = phi[a][3] = 0.f; }
+        if (a < D) axis_gather<LAG>(A.xh[a][sc], A.xl[a][sc], g.n[a], base[a], phi[a], gw[a]);
+        else {
+            phi[a][0] = gw[a][0] = 1.f;
+            phi[a][1] = phi[a][2] = phi[a][3] = gw[a][1] = gw[a][2] = gw[a][3] = 0.f;
+        }
     }
     int ky = l & 3, kz = (D == 3) ? (l >> 2) : 0;
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     if (valid) {
         int y = base[1] + ky, z = base[2] + kz;
-        float wyz = phi[1][ky] * phi[2][kz];
+        float wyz = gw[1][ky] * gw[2][kz];
         if (wyz != 0.f) {
             long long row = ((long long)z * g.n[1] + y) * g.n[0];
 #pragma unroll
             for (int kx = 0; kx < 4; kx++) {
-                float W = phi[0][kx] * phi[1][ky] * phi[2][kz];
+                float W = gw[0][kx] * gw[1][ky] * gw[2][kz];
                 if (W != 0.f) {
                     float4 m = mom[row + base[0] + kx];
                     acc[0] += W * m.x; acc[1] += W * m.y; acc[2] += W * m.z; acc[3] += W * m.w;
@@ -376,7 +412,7 @@ struct PopSrc {
     }
 };
 
-template <int D, class Src>
+template <int D, class Src, bool LAG>
 __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, PCfg c,
                                                      const uint32_t* __restrict__ start,
                                                      Src src,
@@ -453,29 +489,29 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
         }
         const uint32_t s = rs[r] + (k - roff[r]);
         int base[3] = {0, 0, 0};
-        float phi[3][4];
+        float phi[3][4], gw[3][4];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            if (a < D) axis_weights(A.xh[a][s], A.xl[a][s], g.n[a], base[a], phi[a]);
-            else { phi[a][0] = 1.f; phi[a][1] = phi[a][2] = phi[a][3] = 0.f; }
+            if (a < D) axis_gather<LAG>(A.xh[a][s], A.xl[a][s], g.n[a], base[a], phi[a], gw[a]);
+            else {
+                phi[a][0] = gw[a][0] = 1.f;
+                phi[a][1] = phi[a][2] = phi[a][3] = gw[a][1] = gw[a][2] = gw[a][3] = 0.f;
+            }
         }
         float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
         const int ox = base[0] - nx0, oy = base[1] - ny0, oz = (D == 3) ? base[2] - nz0 : 0;
 #pragma unroll
         for (int kz = 0; kz < (D == 3 ? 4 : 1); kz++)
 #pragma unroll
-            for (int ky = 0; ky < 4; ky++) {
-                const float wyz = phi[1][ky] * phi[2][kz];
+            for (int ky = 0; ky < 4; ky++)
 #pragma unroll
                 for (int kx = 0; kx < 4; kx++) {
-                    const float W = phi[0][kx] * phi[1][ky] * phi[2][kz];
+                    const float W = gw[0][kx] * gw[1][ky] * gw[2][kz];
                     if (W != 0.f) {
                         const float4 m = sm[((oz + kz) * ly + (oy + ky)) * lx + (ox + kx)];
                         acc0 += W * m.x; acc1 += W * m.y; acc2 += W * m.z; acc3 += W * m.w;
                     }
                 }
-                (void)wyz;
-            }
         drho_i[s] = acc0;
         j_i[s] = acc1;
         j_i[(long long)np + s] = acc2;
@@ -1382,7 +1418,7 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
 }
 
 // ---------------------------------------------------------------------------
-// spreading (O5): F(r) = sum_p A_p gbar_p W_p(r) with the start-of-step
+// spreading (Eq. lbm10): F(r) = sum_p A_p gbar_p W_p(r) with the start-of-step
 // weights.  One wave per node tile.  The particles whose support can reach
 // the tile sit in the tile's halo bins; the bins of one (by, bz) row are
 // contiguous in the sorted order, so walking the rows in ascending key order
@@ -1709,8 +1745,13 @@ static void interp_tile_2d(PBuf& b, int np, const Grid& g, const PCfg& c, Src sr
     const int E = 1 << c.L;
     const int bx = T::CX / E, by = T::CY / E;
     int ntx = (c.nb[0] + bx - 1) / bx, nty = (c.nb[1] + by - 1) / by;
-    hipLaunchKernelGGL((k_interp_tile<2, Src>), dim3((unsigned)((long long)ntx * nty)), dim3(256), 0, s, b.A, np, g,
-                       c, b.start, src, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+    const dim3 grid((unsigned)((long long)ntx * nty));
+    if (c.lagrange)
+        hipLaunchKernelGGL((k_interp_tile<2, Src, true>), grid, dim3(256), 0, s, b.A, np, g, c, b.start, src,
+                           b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+    else
+        hipLaunchKernelGGL((k_interp_tile<2, Src, false>), grid, dim3(256), 0, s, b.A, np, g, c, b.start, src,
+                           b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
 }
 
 // D2Q9 with bins of edge 1 or 2: moments straight from the populations f
@@ -1732,18 +1773,28 @@ void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, cons
             using T = InterpTile<3>;
             const int bx = T::CX / E, by = T::CY / E, bz = T::CZ / E;
             int ntx = (c.nb[0] + bx - 1) / bx, nty = (c.nb[1] + by - 1) / by, ntz = (c.nb[2] + bz - 1) / bz;
-            hipLaunchKernelGGL((k_interp_tile<3, MomSrc>), dim3((unsigned)((long long)ntx * nty * ntz)), dim3(256), 0,
-                               s, b.A, np, g, c, b.start, MomSrc{mom}, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+            const dim3 grid((unsigned)((long long)ntx * nty * ntz));
+            if (c.lagrange)
+                hipLaunchKernelGGL((k_interp_tile<3, MomSrc, true>), grid, dim3(256), 0, s, b.A, np, g, c, b.start,
+                                   MomSrc{mom}, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+            else
+                hipLaunchKernelGGL((k_interp_tile<3, MomSrc, false>), grid, dim3(256), 0, s, b.A, np, g, c, b.start,
+                                   MomSrc{mom}, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
         } else {
             interp_tile_2d(b, np, g, c, MomSrc{mom}, s);
         }
         return;
     }
     long long threads = (long long)np * (D == 3 ? 16 : 4);
-    if (D == 3)
-        hipLaunchKernelGGL(k_interp<3>, dim3(nb256(threads)), dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+    const dim3 grid(nb256(threads));
+    if (D == 3 && c.lagrange)
+        hipLaunchKernelGGL((k_interp<3, true>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+    else if (D == 3)
+        hipLaunchKernelGGL((k_interp<3, false>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+    else if (c.lagrange)
+        hipLaunchKernelGGL((k_interp<2, true>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
     else
-        hipLaunchKernelGGL(k_interp<2>, dim3(nb256(threads)), dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+        hipLaunchKernelGGL((k_interp<2, false>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
 }
 
 template <int D>

@@ -10,7 +10,8 @@
 namespace pibm {
 
 // ---------------------------------------------------------------------------
-// Lattices: D2Q9 and D3Q19 (c = 1, c_s^2 = 1/3), direction order of the ABI.
+// Lattices: D2Q9, D3Q15 and D3Q19 (c = 1, c_s^2 = 1/3), direction order of
+// the ABI.
 // ---------------------------------------------------------------------------
 template <int Q> struct Lattice;
 
@@ -27,6 +28,27 @@ template <> struct Lattice<9> {
     __host__ __device__ static constexpr int ez(int) { return 0; }
     __host__ __device__ static constexpr float w(int q) {
         return q == 0 ? 4.0f / 9.0f : (q < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
+    }
+    __host__ __device__ static constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+};
+
+// D3Q15, the three-dimensional lattice of Sec. 2.1: rest, 6 faces, 8 corners.
+template <> struct Lattice<15> {
+    static constexpr int D = 3;
+    __host__ __device__ static constexpr int ex(int q) {
+        constexpr int t[15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+        return t[q];
+    }
+    __host__ __device__ static constexpr int ey(int q) {
+        constexpr int t[15] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1};
+        return t[q];
+    }
+    __host__ __device__ static constexpr int ez(int q) {
+        constexpr int t[15] = {0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1};
+        return t[q];
+    }
+    __host__ __device__ static constexpr float w(int q) {
+        return q == 0 ? 2.0f / 9.0f : (q < 7 ? 1.0f / 9.0f : 1.0f / 72.0f);
     }
     __host__ __device__ static constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
 };
@@ -205,6 +227,7 @@ struct PCfg {
     float eps;          // bound on the trailing position parts left out by screening
     int H;              // neighbour-search half-width in bins: ceil((d_max + skin + eps) / 2^L)
     float dmax;         // largest diameter present
+    int lagrange;       // 1: gather with the Lagrange polynomials of Eq. lbm5-lbm6
 };
 
 // Per-candidate constants of the active sub-steps.

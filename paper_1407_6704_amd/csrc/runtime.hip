@@ -136,12 +136,13 @@ pibm_status check_hip(pibm_ctx* c, hipError_t e, const char* what) {
     return PIBM_OK;
 }
 
-int dimension(int lattice) { return lattice == PIBM_D3Q19 ? 3 : 2; }
+int dimension(int lattice) { return lattice == PIBM_D2Q9 ? 2 : 3; }
 
 std::string validate(const pibm_config* cfg, int64_t np) {
     if (!cfg) return "null config";
     if (cfg->abi_version != PIBM_ABI_VERSION) return "ABI version mismatch";
-    if (cfg->lattice != PIBM_D2Q9 && cfg->lattice != PIBM_D3Q19) return "lattice must be D2Q9 (9) or D3Q19 (19)";
+    if (cfg->lattice != PIBM_D2Q9 && cfg->lattice != PIBM_D3Q15 && cfg->lattice != PIBM_D3Q19)
+        return "lattice must be D2Q9 (9), D3Q15 (15) or D3Q19 (19)";
     if (cfg->storage != PIBM_STORE_FP32 && cfg->storage != PIBM_STORE_FP16) return "unknown storage";
     if (cfg->fp16_scale_log2 < 0 || cfg->fp16_scale_log2 > 24) return "fp16_scale_log2 out of range";
     int D = dimension(cfg->lattice);
@@ -159,6 +160,7 @@ std::string validate(const pibm_config* cfg, int64_t np) {
     if (cfg->bin_log2 < 0 || cfg->bin_log2 > 3) return "bin_log2 must be 0..3";
     if (cfg->max_candidates < 1 || cfg->max_candidates > 64) return "max_candidates must be 1..64";
     if (cfg->island_setup < 0 || cfg->island_setup > 2) return "island_setup must be 0, 1 or 2";
+    if (cfg->interp != PIBM_INTERP_DELTA && cfg->interp != PIBM_INTERP_LAGRANGE) return "unknown interpolation";
     if (cfg->contact == PIBM_CONTACT_LSD && (!(cfg->kn > 0) || !(cfg->restitution > 0) || cfg->restitution > 1))
         return "linear spring-dashpot needs kn > 0 and 0 < restitution <= 1";
     if (!(cfg->skin >= 0)) return "skin must be >= 0";
@@ -260,6 +262,7 @@ void fill_pcfg(pibm_ctx& c) {
     p.rho0 = (float)c.cfg.rho0;
     for (int a = 0; a < 3; a++) p.g[a] = (float)c.cfg.gravity[a];
     p.maxc = c.cfg.max_candidates;
+    p.lagrange = c.cfg.interp == PIBM_INTERP_LAGRANGE;
     // trailing parts are at most half an ulp of the leading ones; the
     // screened distance is off by at most sqrt(D) ulp(max extent)
     int nmax = std::max(c.cfg.n[0], std::max(c.cfg.n[1], c.cfg.n[2]));
@@ -280,6 +283,8 @@ std::string adjoint_unsupported(const pibm_ctx& c) {
     if (c.cfg.n_sub != 1) return "the adjoint supports n_sub = 1 only";
     if (c.cfg.contact == PIBM_CONTACT_LSD) return "the adjoint supports no contact or soft contact only";
     if (c.cfg.bin_log2 != 0) return "the adjoint needs bin_log2 = 0";
+    if (c.cfg.lattice == PIBM_D3Q15) return "the adjoint supports D2Q9 and D3Q19 only";
+    if (c.cfg.interp != PIBM_INTERP_DELTA) return "the adjoint supports delta-kernel interpolation only";
     return "";
 }
 

@@ -17,10 +17,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpibm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pibm.h")
 
-ABI_VERSION = 1
-D2Q9, D3Q19 = 9, 19
+ABI_VERSION = 2
+D2Q9, D3Q15, D3Q19 = 9, 15, 19
 STORE_FP32, STORE_FP16 = 0, 1
 CONTACT = {"none": 0, "lsd": 1, "soft": 2}
+INTERP = {"delta": 0, "lagrange": 1}
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_CONFIG", 3: "E_HIP", 4: "E_STATE", 5: "E_UNSTABLE",
           6: "E_SKIN", 7: "E_CAPACITY"}
 
@@ -33,7 +34,7 @@ class Config(C.Structure):
         ("fluid_force", C.c_double * 3), ("contact", C.c_int32), ("n_sub", C.c_int32),
         ("kn", C.c_double), ("restitution", C.c_double), ("k_soft", C.c_double),
         ("skin", C.c_double), ("two_way", C.c_int32), ("bin_log2", C.c_int32),
-        ("max_candidates", C.c_int32), ("island_setup", C.c_int32),
+        ("max_candidates", C.c_int32), ("island_setup", C.c_int32), ("interp", C.c_int32),
     ]
 
 
@@ -116,7 +117,7 @@ def header_symbols():
 def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, periodic=(0, 0, 0),
                 tau=0.8, rho0=1.0, gravity=(0.0, 0.0, 0.0), fluid_force=(0.0, 0.0, 0.0),
                 contact="lsd", n_sub=1, kn=1e3, restitution=0.9, k_soft=1e-3, skin=0.05,
-                two_way=1, bin_log2=0, max_candidates=16, island_setup=0) -> Config:
+                two_way=1, bin_log2=0, max_candidates=16, island_setup=0, interp="delta") -> Config:
     c = Config()
     c.abi_version = ABI_VERSION
     c.lattice = int(lattice)
@@ -133,6 +134,7 @@ def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, pe
     c.kn, c.restitution, c.k_soft, c.skin = float(kn), float(restitution), float(k_soft), float(skin)
     c.two_way, c.bin_log2, c.max_candidates = int(two_way), int(bin_log2), int(max_candidates)
     c.island_setup = int(island_setup)
+    c.interp = INTERP[interp] if isinstance(interp, str) else int(interp)
     return c
 
 
@@ -170,8 +172,8 @@ class Sim:
         self.lib = load()
         self.cfg = cfg
         self.np = int(n_particles)
-        self.Q = 19 if cfg.lattice == 19 else 9
-        self.D = 3 if cfg.lattice == 19 else 2
+        self.Q = int(cfg.lattice)
+        self.D = 2 if cfg.lattice == 9 else 3
         self.n = tuple(int(cfg.n[a]) for a in range(3))
         self.N = self.n[0] * self.n[1] * self.n[2]
         nbytes = self.lib.pibm_workspace_bytes(C.byref(cfg), self.np)

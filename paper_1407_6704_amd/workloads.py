@@ -69,7 +69,7 @@ class Workload:
 
     @property
     def dim(self) -> int:
-        return 3 if self.lattice == 19 else 2
+        return 2 if self.lattice == 9 else 3
 
     @property
     def nodes(self) -> int:

@@ -17,7 +17,8 @@ def oracle_cfg(orc, cfg):
         lattice=cfg.lattice, n=tuple(cfg.n), periodic=tuple(cfg.periodic), tau=cfg.tau,
         rho0=cfg.rho0, gravity=tuple(cfg.gravity), fluid_force=tuple(cfg.fluid_force),
         contact=cfg.contact, kn=cfg.kn, restitution=cfg.restitution, k_soft=cfg.k_soft,
-        skin=cfg.skin, n_sub=cfg.n_sub, two_way=cfg.two_way, bin_log2=cfg.bin_log2)
+        skin=cfg.skin, n_sub=cfg.n_sub, two_way=cfg.two_way, bin_log2=cfg.bin_log2,
+        interp="lagrange" if cfg.interp == 1 else "delta")
 
 
 def weights(orc, lattice):

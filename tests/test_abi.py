@@ -43,7 +43,7 @@ def test_workspace_bytes_and_validation(P):
     fp32 = P.make_config(lattice=19, n=(16, 16, 16), tau=0.8)
     assert lib.pibm_workspace_bytes(C.byref(fp16), 0) < lib.pibm_workspace_bytes(C.byref(fp32), 0)
     bad = [
-        dict(tau=0.5), dict(tau=0.3), dict(n_sub=0), dict(lattice=15), dict(n=(8, 8, 2)),
+        dict(tau=0.5), dict(tau=0.3), dict(n_sub=0), dict(lattice=27), dict(interp=2), dict(n=(8, 8, 2)),
         dict(bin_log2=5), dict(max_candidates=0), dict(restitution=0.0), dict(periodic=(1, 0, 0)),
     ]
     for kw in bad:
@@ -65,11 +65,26 @@ def test_workspace_bytes_and_validation(P):
     assert lib.pibm_create(C.byref(badc), 0, None, 0, None, C.byref(ctx)) == 2
 
 
-def test_config_struct_layout(P):
-    """The ctypes mirror has the C struct's size (ints and doubles, no
-    implicit tail padding beyond 8-byte alignment)."""
-    assert C.sizeof(P.Config) == 4 * 4 + 3 * 4 + 3 * 4 + 8 * 2 + 8 * 3 + 8 * 3 + 4 * 2 + 8 * 4 + 4 * 4
-    assert C.sizeof(P.Diag) == 8 + 24 + 24 + 8 + 8 * 3 + 8 * 2
+def test_config_struct_layout(P, tmp_path):
+    """The ctypes mirrors have the C structs' sizes and field offsets, as a C
+    compiler lays them out from include/pibm.h."""
+    import subprocess
+
+    lines = []
+    for cname, py in (("pibm_config", P.Config), ("pibm_diag", P.Diag)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pibm.h"\nint main(void) {\n'
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in (("pibm_config", P.Config), ("pibm_diag", P.Diag)):
+        assert int(got[f"{cname} size"]) == C.sizeof(py)
+        for f in py._fields_:
+            assert int(got[f"{cname} {f[0]}"]) == getattr(py, f[0]).offset, (cname, f[0])
 
 
 def test_single_hip_runtime_in_process(P):

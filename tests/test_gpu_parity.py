@@ -45,8 +45,11 @@ LATTICE_CASES = [
     (9, "fp32", (64, 33, 1), (1, 0, 0)),
     (19, "fp32", (19, 13, 11), (0, 0, 0)),
     (19, "fp32", (16, 9, 12), (1, 0, 1)),
+    (15, "fp32", (19, 13, 11), (0, 0, 0)),
+    (15, "fp32", (16, 9, 12), (1, 0, 1)),
     (9, "fp16", (67, 45, 1), (0, 0, 0)),
     (19, "fp16", (19, 13, 11), (0, 0, 0)),
+    (15, "fp16", (19, 13, 11), (0, 0, 0)),
 ]
 
 
@@ -54,7 +57,7 @@ LATTICE_CASES = [
 def test_lattice_steps_match_oracle(P, W, orc, lat, storage, n, per):
     _flush(f"lattice {lat} {storage} {n} periodic={per}")
     cfg = P.make_config(lattice=lat, n=n, storage=storage, periodic=per, tau=0.7,
-                        fluid_force=(2e-6, -1e-6, 5e-7 if lat == 19 else 0.0), contact="none")
+                        fluid_force=(2e-6, -1e-6, 5e-7 if lat != 9 else 0.0), contact="none")
     sim = P.Sim(cfg, 0)
     w = W.C0.replace(lattice=lat, n=n)
     h0 = G.perturbed_state(orc, sim, w, seed=5)
@@ -78,7 +81,8 @@ def test_lattice_steps_match_oracle(P, W, orc, lat, storage, n, per):
     assert eu <= 3 * tol_u and er <= 3 * tol_rho
 
 
-@pytest.mark.parametrize("lat,storage", [(9, "fp32"), (19, "fp32"), (9, "fp16"), (19, "fp16")])
+@pytest.mark.parametrize("lat,storage", [(9, "fp32"), (19, "fp32"), (15, "fp32"), (9, "fp16"), (19, "fp16"),
+                                         (15, "fp16")])
 def test_poiseuille_gpu(P, lat, storage):
     _flush(f"poiseuille {lat} {storage}")
     H, Fx, tau = 16, 1e-6, 0.8
@@ -101,9 +105,12 @@ def test_poiseuille_gpu(P, lat, storage):
     _flush(f"  max rel err {err:.2e}")
     # A steady state repeats the same roundings every step, so their bias adds
     # up over the slowest viscous time T = H^2/(pi^2 nu) (about 260 steps):
-    # relative error <~ T * 2^-p with p = 24 (FP32) or 11 (FP16 storage).
+    # relative error <~ c T 2^-p with p = 24 (FP32) or 11 (FP16 storage) and
+    # c = 2 for the two roundings of each stored value per step (relaxation
+    # with forcing, then the store).  The FP64 oracle meets the same closed
+    # form to 1e-9 on every lattice, so the excess is rounding alone.
     T = H * H / (np.pi ** 2 * nu)
-    bound = T * 2.0 ** (-24 if storage == "fp32" else -11)
+    bound = 2 * T * 2.0 ** (-24 if storage == "fp32" else -11)
     assert err < bound
 
 
@@ -121,7 +128,7 @@ def _random_particles(rng, D, n, npart, dlo=0.3, dhi=0.6, margin=1.0):
 def test_cell_list_bit_exact(P, W, orc, lat, n, npart):
     _flush(f"cell list {lat} {n} {npart}")
     rng = np.random.default_rng(21)
-    D = 3 if lat == 19 else 2
+    D = 2 if lat == 9 else 3
     X, d = _random_particles(rng, D, n, npart, margin=0.3)
     # exact half-integers and node centres stress the floor of X - 1/2
     X[:, :40] = np.round(X[:, :40] * 2) / 2 + 0.0
@@ -166,12 +173,18 @@ def _coupled_compare(P, orc, cfg, X, U, d, rp, h0=None, steps=1, seed=0, tol=Non
     return dict(eu=eu, er=er, ex=ex, ev=ev, efh=efh, sim=sim, out=out, got=got)
 
 
-@pytest.mark.parametrize("lat", [9, 19])
-def test_coupled_step_free_particles(P, W, orc, lat):
+FREE_CASES = [(9, "delta", 0), (19, "delta", 0), (15, "delta", 0), (9, "lagrange", 0), (15, "lagrange", 0),
+              (19, "lagrange", 0), (15, "lagrange", 2), (9, "lagrange", 2)]
+
+
+@pytest.mark.parametrize("lat,interp,bl", FREE_CASES)
+def test_coupled_step_free_particles(P, W, orc, lat, interp, bl):
     """Particles away from each other (free: closed-form sub-steps), some
-    near the walls (weights renormalised), on a perturbed fluid."""
-    _flush(f"coupled free {lat}")
-    D = 3 if lat == 19 else 2
+    near the walls (delta weights renormalised, Lagrange polynomials of lower
+    order), on a perturbed fluid; both gathers, tiled (bins of one dual cell)
+    and per-particle (bins of four)."""
+    _flush(f"coupled free {lat} {interp} bin_log2={bl}")
+    D = 2 if lat == 9 else 3
     n = (48, 40, 1) if D == 2 else (20, 18, 16)
     rng = np.random.default_rng(31)
     npart = 150 if D == 2 else 200
@@ -190,7 +203,8 @@ def test_coupled_step_free_particles(P, W, orc, lat):
     rp = rng.uniform(1.5, 3.0, npart).astype(np.float32).astype(np.float64)
     g = [0.0, 0.0, 0.0]
     g[D - 1] = -1e-5
-    cfg = P.make_config(lattice=lat, n=n, tau=0.7, gravity=g, n_sub=200, contact="lsd")
+    cfg = P.make_config(lattice=lat, n=n, tau=0.7, gravity=g, n_sub=200, contact="lsd", interp=interp,
+                        bin_log2=bl)
     w = W.C0.replace(lattice=lat, n=n)
     sim0 = P.Sim(P.make_config(lattice=lat, n=n, tau=0.7, contact="none"), 0)
     h0 = G.perturbed_state(orc, sim0, w, seed=7, amp=1e-4)
@@ -202,12 +216,12 @@ def test_coupled_step_free_particles(P, W, orc, lat):
     assert r["eu"] <= 3e-5 and r["ex"] <= 3e-5 and r["ev"] <= 3e-5
 
 
-@pytest.mark.parametrize("lat", [9, 19])
+@pytest.mark.parametrize("lat", [9, 19, 15])
 def test_coupled_step_with_contacts(P, orc, lat):
     """Clusters of touching and approaching particles (islands of several
     sizes, wall contacts), linear spring-dashpot, several steps."""
     _flush(f"coupled contacts {lat}")
-    D = 3 if lat == 19 else 2
+    D = 2 if lat == 9 else 3
     n = (40, 30, 1) if D == 2 else (16, 14, 18)
     rng = np.random.default_rng(41)
     blocks = []
@@ -397,7 +411,7 @@ def test_island_setup_paths_agree(P, lat):
     """The one-workgroup and the multi-kernel island set-up give bitwise
     identical steps (clusters, a large island, wall contacts)."""
     _flush(f"island set-up paths {lat}")
-    D = 3 if lat == 19 else 2
+    D = 2 if lat == 9 else 3
     n = (48, 30, 1) if D == 2 else (20, 14, 18)
     rng = np.random.default_rng(43)
     pts = []

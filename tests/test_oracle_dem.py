@@ -28,7 +28,7 @@ def _particles(D, X, U, d, rho_p):
 
 @pytest.mark.parametrize("lat,d,rp,n_sub", [(9, 0.4, 2.5, 508), (19, 0.5, 2.0, 64), (19, 0.2, 2.0, 3109)])
 def test_one_way_settling_closed_form(orc, lat, d, rp, n_sub):
-    D = 3 if lat == 19 else 2
+    D = 2 if lat == 9 else 3
     g = [0.0, 0.0, 0.0]
     g[D - 1] = -1e-5
     n = (16, 16, 1) if D == 2 else (8, 8, 8)
@@ -68,7 +68,7 @@ def test_one_way_settling_closed_form(orc, lat, d, rp, n_sub):
 
 @pytest.mark.parametrize("lat", [9, 19])
 def test_candidates_match_brute_force(orc, lat):
-    D = 3 if lat == 19 else 2
+    D = 2 if lat == 9 else 3
     n = (12, 12, 1) if D == 2 else (6, 6, 6)
     rng = np.random.default_rng(5)
     for trial in range(6):
@@ -162,7 +162,7 @@ def test_soft_repulsion_energy(orc, D):
 def test_newton_third_law_cluster(orc):
     rng = np.random.default_rng(7)
     for lat in (9, 19):
-        D = 3 if lat == 19 else 2
+        D = 2 if lat == 9 else 3
         n = (12, 12, 1) if D == 2 else (10, 10, 10)
         cfg = orc.make_cfg(lattice=lat, n=n, n_sub=50, two_way=0, kn=1e-3)
         npart = 40
