@@ -13,7 +13,8 @@ The oracle cannot run these sizes for many steps, so the checks are:
        collision with the GPU's force field,
      - mass conservation;
   the 64^3 / 31,250-sphere crop with FP16 and FP32 storage against the oracle
-  over three steps; and the FP16 run of c2 against the FP32 run, ten steps.
+  over three steps, and over its 100 steps against a stored oracle state;
+  and the FP16 run of c2 against the FP32 run, ten steps.
 Tolerances are the per-field bounds of the parity tests: FP32 velocity 1e-5
 relative (L2), density 1e-6 absolute; FP16 storage 1e-3 and 1e-5.
 """
@@ -208,6 +209,47 @@ def test_fp16_crop_against_oracle(P, W, orc):
         tol_u, tol_r = (3e-5, 1e-6) if storage == "fp32" else (1e-3, 1e-5)
         assert eu <= tol_u and er <= tol_r
         assert ex <= 1e-4 and ev <= 1e-4
+
+
+def test_crop_100_steps_against_stored_oracle(P, W, orc):
+    """The 64^3 crop over its full 100 steps, FP32 and FP16 storage, against
+    the FP64 oracle's state after the same 100 steps, written beforehand by
+    tests/golden/make_crop_reference.py (density deviation and velocity at
+    32,768 sampled nodes, every particle's displacement and velocity).
+    Bounds: the per-field bounds of the short tests widened by a factor of
+    ten for a hundred steps of error growth (FP32 velocity 1e-4, density
+    1e-5; FP16 storage 1e-2 and 1e-4); particles 1e-4 (FP32) and 1e-3
+    (FP16) relative."""
+    import os
+
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                               "crop64_fp64_100steps.npz"))
+    steps = int(ref["steps"])
+    nodes = ref["nodes"].astype(np.int64)
+    w = W.C3_CROP
+    _flush(f"crop {w.n} {w.n_particles}, {steps} steps against the stored oracle state")
+    X, U, d, rp = W.make_particles(w)
+    dx_ref, v_ref = ref["dx"].astype(np.float64), ref["v"].astype(np.float64)
+    u_ref, dr_ref = ref["u"].astype(np.float64), ref["drho"].astype(np.float64)
+    for storage in ("fp32", "fp16"):
+        cfg = P.config_from_workload(w.replace(storage=storage))
+        sim = P.Sim(cfg, X.shape[1])
+        sim.set_particles(X, U, d, rp)
+        sim.step(steps)
+        sim.synchronize()
+        h = sim.read_populations()[:, nodes]
+        dr, j = G.moments_dev(orc, w.lattice, h)
+        u = j / (1.0 + dr)
+        eu = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        er = np.abs(dr - dr_ref).max()
+        got = sim.read_particles()
+        dx = got["x"] - X
+        ex = np.abs(dx - dx_ref).max() / np.abs(dx_ref).max()
+        ev = np.linalg.norm(got["v"] - v_ref) / np.linalg.norm(v_ref)
+        _flush(f"  {storage}: eps_u={eu:.2e} eps_rho={er:.2e} dX={ex:.2e} dU={ev:.2e}")
+        tu, tr, tp = (1e-4, 1e-5, 1e-4) if storage == "fp32" else (1e-2, 1e-4, 1e-3)
+        assert eu <= tu and er <= tr
+        assert ex <= tp and ev <= tp
 
 
 def test_fp16_scale_reading(P, W, orc):
