@@ -277,7 +277,7 @@ def main():
         "dtype": "f32" if w.storage == "fp32" else "f16-storage/f32-compute",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: D2Q9 {w.n[0]}x{w.n[1]}" if w.dim == 2 else
-                   f"{w.name}: D3Q19 {w.n[0]}x{w.n[1]}x{w.n[2]}",
+                   f"{w.name}: D3Q{w.lattice} {w.n[0]}x{w.n[1]}x{w.n[2]}",
                    "particles": w.n_particles, "tau": w.tau, "n_sub": w.n_sub, "contact": w.contact,
                    "storage": w.storage, "seed": w.seed},
         "particle_updates_per_s": res["particle_updates_per_s"],
@@ -298,6 +298,9 @@ def main():
         extra["fp16_speedup"] = extra["c2"]["ms_per_step"] / extra["c3"]["ms_per_step"]
         # FP16 storage against FP32 from the same initial state, same steps
         (r32, u32), (r16, u16) = extra["c2"].pop("_fields"), extra["c3"].pop("_fields")
+        # the paper's lattice and gather on the c2 particles
+        r, _ = run_gpu(W.WORKLOADS["c2_d3q15"], args.extra_steps, 2, "c2_d3q15")
+        extra["c2_d3q15_lagrange"] = r
         extra["c4_adjoint"] = run_adjoint(W.WORKLOADS["c4"])
         extra["fp16_vs_fp32"] = {
             "steps": args.extra_steps + 2,
