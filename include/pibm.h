@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define PIBM_ABI_VERSION 2
+#define PIBM_ABI_VERSION 3
 
 typedef enum {
     PIBM_OK = 0,
@@ -65,7 +65,7 @@ typedef enum {
 
 enum { PIBM_D2Q9 = 9, PIBM_D3Q15 = 15, PIBM_D3Q19 = 19 };
 enum { PIBM_STORE_FP32 = 0, PIBM_STORE_FP16 = 1 };
-enum { PIBM_CONTACT_NONE = 0, PIBM_CONTACT_LSD = 1, PIBM_CONTACT_SOFT = 2 };
+enum { PIBM_CONTACT_NONE = 0, PIBM_CONTACT_LSD = 1, PIBM_CONTACT_SOFT = 2, PIBM_CONTACT_HERTZ = 3 };
 enum { PIBM_INTERP_DELTA = 0, PIBM_INTERP_LAGRANGE = 1 };
 
 /* Lattice velocity order used by pibm_read_populations/pibm_write_populations:
@@ -93,7 +93,8 @@ typedef struct {
     double rho0;              /* fluid density in the buoyancy term (Eq. demgov) */
     double gravity[3];        /* acceleration on particles */
     double fluid_force[3];    /* uniform body force density on the fluid */
-    int32_t contact;          /* PIBM_CONTACT_* */
+    int32_t contact;          /* PIBM_CONTACT_*: none, linear spring-dashpot, soft repulsion, or
+                                 Hertz (Sec. 2.3; young and poisson below) */
     int32_t n_sub;            /* DEM sub-steps per lattice step, >= 1 */
     double kn;                /* linear spring stiffness */
     double restitution;       /* normal restitution of the linear spring-dashpot, (0, 1] */
@@ -110,6 +111,11 @@ typedef struct {
                                  through the in-domain nodes of the same four per axis (cubic
                                  in the interior, Eqs. lbm5-lbm6).  Spreading always uses
                                  the delta kernel (Eq. lbm10) */
+    double young;             /* PIBM_CONTACT_HERTZ: Young's modulus E of the particles and the
+                                 walls (one material), lattice units; > 0 */
+    double poisson;           /* PIBM_CONTACT_HERTZ: Poisson ratio nu, 0 <= nu < 1/2.  The normal
+                                 force is (4/3) E* sqrt(R*) delta^(3/2) with E* = E / (2 (1 - nu^2)),
+                                 1/R* = 1/R_p + 1/R_q (R* = R_p at a wall), undamped (Sec. 2.3) */
 } pibm_config;
 
 typedef struct {

@@ -35,10 +35,11 @@ class Cfg(C.Structure):
         ("fluid_force", C.c_double * 3), ("contact", C.c_int), ("kn", C.c_double),
         ("restitution", C.c_double), ("k_soft", C.c_double), ("skin", C.c_double),
         ("n_sub", C.c_int), ("two_way", C.c_int), ("bin_log2", C.c_int), ("interp", C.c_int),
+        ("young", C.c_double), ("poisson", C.c_double),
     ]
 
 
-CONTACT = {"none": 0, "lsd": 1, "soft": 2}
+CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3}
 
 _lib = None
 
@@ -104,7 +105,7 @@ def _f64(a, shape=None):
 def make_cfg(lattice=9, n=(16, 16, 1), periodic=(0, 0, 0), tau=0.8, rho0=1.0,
              gravity=(0.0, 0.0, 0.0), fluid_force=(0.0, 0.0, 0.0), contact="lsd",
              kn=1e3, restitution=0.9, k_soft=1e-3, skin=0.05, n_sub=1, two_way=1,
-             bin_log2=1, interp="delta") -> Cfg:
+             bin_log2=1, interp="delta", young=1e-3, poisson=0.33) -> Cfg:
     c = Cfg()
     c.lattice = int(lattice)
     for a in range(3):
@@ -117,6 +118,7 @@ def make_cfg(lattice=9, n=(16, 16, 1), periodic=(0, 0, 0), tau=0.8, rho0=1.0,
     c.kn, c.restitution, c.k_soft, c.skin = float(kn), float(restitution), float(k_soft), float(skin)
     c.n_sub, c.two_way, c.bin_log2 = int(n_sub), int(two_way), int(bin_log2)
     c.interp = {"delta": 0, "lagrange": 1}[interp] if isinstance(interp, str) else int(interp)
+    c.young, c.poisson = float(young), float(poisson)
     return c
 
 

@@ -52,6 +52,8 @@ typedef struct {
     int interp;             /* 0: cosine delta kernel (Eq. lbm11-lbm12); 1: Lagrange
                                polynomials (Eq. lbm5-lbm6) for the interpolation, the
                                delta kernel still spreads (Eq. lbm10-lbm11) */
+    double young, poisson;  /* Hertz contact (contact = 3): Young's modulus and Poisson
+                               ratio of the particles and the walls (one material) */
 } orc_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -420,9 +422,25 @@ double orc_zeta(double e)
     return -l / sqrt(M_PI * M_PI + l * l);
 }
 
+/* Hertz normal force of Sec. 2.3 for overlap delta > 0:
+ *   F_n = (4/3) E* sqrt(R*) delta^(3/2),
+ *   1/E* = (1 - nu^2)/E + (1 - nu^2)/E  (both bodies of the one material),
+ *   1/R* = 1/R_p + 1/R_q, or R* = R_p against a flat wall.
+ * The paper gives no damping term, so none is added (R24). */
+static double hertz_estar(const orc_cfg *c)
+{
+    return c->young / (2.0 * (1.0 - c->poisson * c->poisson));
+}
+
+static double hertz_force(const orc_cfg *c, double rstar, double delta)
+{
+    return 4.0 / 3.0 * hertz_estar(c) * sqrt(rstar) * delta * sqrt(delta);
+}
+
 /* Contact force on particle p from particle q (R10).  r = X_p - X_q,
  * du = U_p - U_q.  Linear spring-dashpot, normal only, no clamp, force only
- * for strictly positive overlap; or soft repulsion k_s (1 - r/r_c)^2. */
+ * for strictly positive overlap; soft repulsion k_s (1 - r/r_c)^2; or the
+ * Hertz force above. */
 static void pair_force(const orc_cfg *c, int D, const double *r, const double *du,
                        double dp, double dq, double mp, double mq, double *Fout)
 {
@@ -444,12 +462,18 @@ static void pair_force(const orc_cfg *c, int D, const double *r, const double *d
         if (!(dist < rc)) return;
         double s = 1.0 - dist / rc;
         for (int a = 0; a < D; a++) Fout[a] = c->k_soft * s * s * r[a] / dist;
+    } else if (c->contact == 3) {
+        double delta = rc - dist;
+        if (!(delta > 0.0)) return;
+        double Rp = 0.5 * dp, Rq = 0.5 * dq;
+        double mag = hertz_force(c, Rp * Rq / (Rp + Rq), delta);
+        for (int a = 0; a < D; a++) Fout[a] = mag * r[a] / dist;
     }
 }
 
 /* Contact with the walls at 0 and n_a of every non-periodic axis: the wall
- * acts as a particle of infinite mass at distance dist along the inward
- * normal, with r_c = d/2. */
+ * acts as a particle of infinite mass (and, for Hertz, infinite radius) at
+ * distance dist along the inward normal, with r_c = d/2. */
 static void wall_force(const orc_cfg *c, int D, const double *X, const double *U,
                        double dp, double mp, double *Fout)
 {
@@ -467,6 +491,10 @@ static void wall_force(const orc_cfg *c, int D, const double *X, const double *U
                 if (!(delta > 0.0)) continue;
                 double gam = 2.0 * orc_zeta(c->restitution) * sqrt(c->kn * mp);
                 Fout[a] += (c->kn * delta - gam * vn) * nrm;
+            } else if (c->contact == 3) {
+                double delta = rc - dist;
+                if (!(delta > 0.0)) continue;
+                Fout[a] += hertz_force(c, 0.5 * dp, delta) * nrm;
             } else {
                 if (!(dist < rc)) continue;
                 double s = 1.0 - dist / rc;

@@ -909,9 +909,15 @@ __device__ __forceinline__ void cand_prep_one(uint32_t a, const PState& A, const
         cd.K0 = k0h + (k0e + (qe - sl));
         cd.rc = rch;
         cd.r0[0] = r0[0]; cd.r0[1] = r0[1]; cd.r0[2] = r0[2];
-        float mt = particle_mass(D, A.d[t], A.rp[t]);
-        float meff = ms * mt / (ms + mt);
-        cd.gam = 2.0f * c.zeta * sqrtf(c.kn * meff);
+        if (c.contact == PIBM_CONTACT_HERTZ) {
+            // Hertz: gam holds the pair's stiffness (4/3) E* sqrt(R*)
+            const float rs = 0.5f * A.d[s], rt = 0.5f * A.d[t];
+            cd.gam = c.hk * sqrtf(rs * rt / (rs + rt));
+        } else {
+            float mt = particle_mass(D, A.d[t], A.rp[t]);
+            float meff = ms * mt / (ms + mt);
+            cd.gam = 2.0f * c.zeta * sqrtf(c.kn * meff);
+        }
         cdata[off + k] = cd;
     }
 }
@@ -1023,7 +1029,8 @@ __device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const
     P.m = particle_mass(D, P.d, rp);
     P.Ap = 0.25f * PI_F * P.d * P.d;
     P.ri = 1.0f + drho_i[s];
-    P.gw = 2.0f * c.zeta * sqrtf(c.kn * P.m);
+    // wall dashpot coefficient, or the Hertz wall stiffness (4/3) E* sqrt(R_p)
+    P.gw = c.contact == PIBM_CONTACT_HERTZ ? c.hk * sqrtf(0.5f * P.d) : 2.0f * c.zeta * sqrtf(c.kn * P.m);
     float v2 = 0.f;
     bool wall = false;
 #pragma unroll
@@ -1070,6 +1077,9 @@ __device__ __forceinline__ void wall_force(const Active<D>& P, const PCfg& c, fl
         if (c.contact == PIBM_CONTACT_LSD) {
             if (dlo > 0.f) F[a] += c.kn * dlo - P.gw * P.u[a];
             if (dhi > 0.f) F[a] -= c.kn * dhi + P.gw * P.u[a];
+        } else if (c.contact == PIBM_CONTACT_HERTZ) {
+            if (dlo > 0.f) F[a] += P.gw * dlo * sqrtf(dlo);
+            if (dhi > 0.f) F[a] -= P.gw * dhi * sqrtf(dhi);
         } else {
             if (dlo > 0.f) { float q = dlo / rc; F[a] += c.ks * q * q; }
             if (dhi > 0.f) { float q = dhi / rc; F[a] -= c.ks * q * q; }
@@ -1102,6 +1112,10 @@ __device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& c
 #pragma unroll
         for (int a = 0; a < D; a++) vn += (P.u[a] - ou[a]) * (r[a] * inv);
         float mag = c.kn * delta - cd.gam * vn;
+#pragma unroll
+        for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
+    } else if (c.contact == PIBM_CONTACT_HERTZ) {
+        float mag = cd.gam * delta * sqrtf(delta);
 #pragma unroll
         for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
     } else {

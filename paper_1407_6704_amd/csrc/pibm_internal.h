@@ -228,6 +228,7 @@ struct PCfg {
     int H;              // neighbour-search half-width in bins: ceil((d_max + skin + eps) / 2^L)
     float dmax;         // largest diameter present
     int lagrange;       // 1: gather with the Lagrange polynomials of Eq. lbm5-lbm6
+    float hk;           // Hertz: (4/3) E*, so that F_n = hk sqrt(R*) delta^(3/2)
 };
 
 // Per-candidate constants of the active sub-steps.

@@ -156,7 +156,9 @@ std::string validate(const pibm_config* cfg, int64_t np) {
         if (cfg->n[a] > 30000) return "axis longer than 30000 nodes";
     if (!(cfg->tau > 0.5)) return "tau must exceed 1/2";
     if (cfg->n_sub < 1) return "n_sub must be >= 1";
-    if (cfg->contact < 0 || cfg->contact > 2) return "unknown contact model";
+    if (cfg->contact < 0 || cfg->contact > 3) return "unknown contact model";
+    if (cfg->contact == PIBM_CONTACT_HERTZ && (!(cfg->young > 0) || !(cfg->poisson >= 0) || !(cfg->poisson < 0.5)))
+        return "Hertz contact needs young > 0 and 0 <= poisson < 1/2";
     if (cfg->bin_log2 < 0 || cfg->bin_log2 > 3) return "bin_log2 must be 0..3";
     if (cfg->max_candidates < 1 || cfg->max_candidates > 64) return "max_candidates must be 1..64";
     if (cfg->island_setup < 0 || cfg->island_setup > 2) return "island_setup must be 0, 1 or 2";
@@ -263,6 +265,7 @@ void fill_pcfg(pibm_ctx& c) {
     for (int a = 0; a < 3; a++) p.g[a] = (float)c.cfg.gravity[a];
     p.maxc = c.cfg.max_candidates;
     p.lagrange = c.cfg.interp == PIBM_INTERP_LAGRANGE;
+    p.hk = (float)(4.0 / 3.0 * c.cfg.young / (2.0 * (1.0 - c.cfg.poisson * c.cfg.poisson)));
     // trailing parts are at most half an ulp of the leading ones; the
     // screened distance is off by at most sqrt(D) ulp(max extent)
     int nmax = std::max(c.cfg.n[0], std::max(c.cfg.n[1], c.cfg.n[2]));
@@ -281,7 +284,8 @@ void set_stencil(pibm_ctx& c, double dmax) {
 std::string adjoint_unsupported(const pibm_ctx& c) {
     if (c.np < 1) return "the adjoint needs at least one particle";
     if (c.cfg.n_sub != 1) return "the adjoint supports n_sub = 1 only";
-    if (c.cfg.contact == PIBM_CONTACT_LSD) return "the adjoint supports no contact or soft contact only";
+    if (c.cfg.contact == PIBM_CONTACT_LSD || c.cfg.contact == PIBM_CONTACT_HERTZ)
+        return "the adjoint supports no contact or soft contact only";
     if (c.cfg.bin_log2 != 0) return "the adjoint needs bin_log2 = 0";
     if (c.cfg.lattice == PIBM_D3Q15) return "the adjoint supports D2Q9 and D3Q19 only";
     if (c.cfg.interp != PIBM_INTERP_DELTA) return "the adjoint supports delta-kernel interpolation only";

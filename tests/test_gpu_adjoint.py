@@ -242,7 +242,8 @@ def test_adjoint_rejects_unsupported_and_edge_cases(P):
     steps returns the final-state adjoints unchanged; K larger than the
     rollout is one segment."""
     n, X, U, d, rp = _small_case(9, 8)
-    for kw in (dict(contact="lsd", n_sub=1), dict(contact="soft", n_sub=4), dict(contact="soft", bin_log2=1)):
+    for kw in (dict(contact="lsd", n_sub=1), dict(contact="soft", n_sub=4), dict(contact="soft", bin_log2=1),
+               dict(contact="hertz", n_sub=1), dict(contact="soft", interp="lagrange")):
         cfg = P.make_config(lattice=9, n=n, tau=0.7, gravity=(0.0, -1e-3, 0.0), k_soft=2e-3, skin=0.05, **kw)
         sim = P.Sim(cfg, X.shape[1])
         sim.set_particles(X, U, d, rp)

@@ -216,11 +216,11 @@ def test_coupled_step_free_particles(P, W, orc, lat, interp, bl):
     assert r["eu"] <= 3e-5 and r["ex"] <= 3e-5 and r["ev"] <= 3e-5
 
 
-@pytest.mark.parametrize("lat", [9, 19, 15])
-def test_coupled_step_with_contacts(P, orc, lat):
+@pytest.mark.parametrize("lat,contact", [(9, "lsd"), (19, "lsd"), (15, "lsd"), (9, "hertz"), (19, "hertz")])
+def test_coupled_step_with_contacts(P, orc, lat, contact):
     """Clusters of touching and approaching particles (islands of several
-    sizes, wall contacts), linear spring-dashpot, several steps."""
-    _flush(f"coupled contacts {lat}")
+    sizes, wall contacts), linear spring-dashpot or Hertz, several steps."""
+    _flush(f"coupled contacts {lat} {contact}")
     D = 2 if lat == 9 else 3
     n = (40, 30, 1) if D == 2 else (16, 14, 18)
     rng = np.random.default_rng(41)
@@ -248,7 +248,7 @@ def test_coupled_step_with_contacts(P, orc, lat):
     rp = np.full(npart, 2.5)
     g = [0.0, 0.0, 0.0]
     g[D - 1] = -1e-5
-    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact="lsd")
+    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact=contact, young=1e3)
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=1, label="1 step")
     assert r["sim"].diagnostics()["active"] > 0
     assert r["eu"] <= 1e-5 and r["er"] <= 1e-6
