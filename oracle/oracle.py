@@ -35,11 +35,11 @@ class Cfg(C.Structure):
         ("fluid_force", C.c_double * 3), ("contact", C.c_int), ("kn", C.c_double),
         ("restitution", C.c_double), ("k_soft", C.c_double), ("skin", C.c_double),
         ("n_sub", C.c_int), ("two_way", C.c_int), ("bin_log2", C.c_int), ("interp", C.c_int),
-        ("young", C.c_double), ("poisson", C.c_double),
+        ("young", C.c_double), ("poisson", C.c_double), ("friction", C.c_double),
     ]
 
 
-CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3}
+CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3, "hertz_mindlin": 4}
 
 _lib = None
 
@@ -73,6 +73,10 @@ def lib():
             "orc_candidate_pairs": ([cp, C.c_int, d, d, i, C.c_int64], C.c_int64),
             "orc_candidate_pairs_brute": ([cp, C.c_int, d, d, i, C.c_int64], C.c_int64),
             "orc_dem": ([cp, C.c_int, d, d, d, d, d, d, C.c_int64, i, d, d, d], None),
+            "orc_dem_full": ([cp, C.c_int, d, d, d, d, d, d, d, C.c_int64, i, C.c_int64, i, d, i, d, d, d, d],
+                             C.c_int64),
+            "orc_step_full": ([cp, d, d, d, C.c_int, d, d, d, d, d, C.c_int64, i, d, i, d, i64, d, d, d, d],
+                              C.c_int),
             "orc_step": ([cp, d, d, d, C.c_int, d, d, d, d, d, d, d, d], C.c_int),
             "orc_fluid_totals": ([cp, d, d, d], None),
         }
@@ -105,7 +109,7 @@ def _f64(a, shape=None):
 def make_cfg(lattice=9, n=(16, 16, 1), periodic=(0, 0, 0), tau=0.8, rho0=1.0,
              gravity=(0.0, 0.0, 0.0), fluid_force=(0.0, 0.0, 0.0), contact="lsd",
              kn=1e3, restitution=0.9, k_soft=1e-3, skin=0.05, n_sub=1, two_way=1,
-             bin_log2=1, interp="delta", young=1e-3, poisson=0.33) -> Cfg:
+             bin_log2=1, interp="delta", young=1e-3, poisson=0.33, friction=0.33) -> Cfg:
     c = Cfg()
     c.lattice = int(lattice)
     for a in range(3):
@@ -118,7 +122,7 @@ def make_cfg(lattice=9, n=(16, 16, 1), periodic=(0, 0, 0), tau=0.8, rho0=1.0,
     c.kn, c.restitution, c.k_soft, c.skin = float(kn), float(restitution), float(k_soft), float(skin)
     c.n_sub, c.two_way, c.bin_log2 = int(n_sub), int(two_way), int(bin_log2)
     c.interp = {"delta": 0, "lagrange": 1}[interp] if isinstance(interp, str) else int(interp)
-    c.young, c.poisson = float(young), float(poisson)
+    c.young, c.poisson, c.friction = float(young), float(poisson), float(friction)
     return c
 
 
@@ -274,6 +278,78 @@ def dem(cfg, X, U, d, rho_p, rho_i, j_i, pairs=None):
     lib().orc_dem(C.byref(cfg), np_, _d(X), _d(U), _d(_f64(d)), _d(_f64(rho_p)),
                   _d(_f64(rho_i)), _d(j3), len(pairs), _i(pairs), _d(gbar), _d(fc), _d(vmax))
     return X, U, gbar.reshape(3, np_)[:dim], fc.reshape(3, np_)[:dim], vmax
+
+
+def _hist_arrays(hist):
+    if hist is None:
+        return np.zeros((1, 2), np.int32), np.zeros((1, 3)), 0
+    keys, T = hist
+    n = len(keys)
+    k = np.ascontiguousarray(np.asarray(keys, np.int32).reshape(-1, 2)) if n else np.zeros((1, 2), np.int32)
+    t = np.ascontiguousarray(np.asarray(T, np.float64).reshape(-1, 3)) if n else np.zeros((1, 3))
+    return k, t, n
+
+
+def dem_hm(cfg, X, U, W, d, rho_p, rho_i, j_i, hist=None, pairs=None):
+    """O4 with the Hertz-Mindlin contact and rotation (contact = 4) on
+    copies; W is (3, np) (2D: the z row only is used).  hist = (keys (n, 2),
+    T (n, 3)) or None.  Returns (X', U', W', gbar, fc_mean, vmax, hist')."""
+    dim = D(cfg)
+    X = _f64(X).copy()
+    U = _f64(U).copy()
+    np_ = X.shape[-1]
+    W = np.ascontiguousarray(np.asarray(W, np.float64).reshape(3, np_)).copy()
+    if pairs is None:
+        pairs = candidate_pairs(cfg, X, d)
+    pairs = np.ascontiguousarray(pairs, np.int32)
+    j3 = np.zeros((3, np_))
+    j3[:dim] = np.asarray(j_i, float).reshape(-1, np_)[:dim]
+    gbar = np.zeros(3 * np_)
+    fc = np.zeros(3 * np_)
+    vmax = np.zeros(np_)
+    kin, tin, hn = _hist_arrays(hist)
+    cap = len(pairs) + 6 * np_ + 1
+    kout = np.zeros((cap, 2), np.int32)
+    tout = np.zeros((cap, 3))
+    n = lib().orc_dem_full(C.byref(cfg), np_, _d(X), _d(U), _d(W), _d(_f64(d)), _d(_f64(rho_p)),
+                           _d(_f64(rho_i)), _d(j3), len(pairs), _i(pairs), hn, _i(kin), _d(tin),
+                           _i(kout), _d(tout), _d(gbar), _d(fc), _d(vmax))
+    return (X, U, W, gbar.reshape(3, np_)[:dim], fc.reshape(3, np_)[:dim], vmax,
+            (kout[:n].copy(), tout[:n].copy()))
+
+
+def step_hm(cfg, f, X, U, W, d, rho_p, hist=None):
+    """One coupled step with the Hertz-Mindlin contact and rotation; as
+    step(), plus "W" and "hist" in the result."""
+    dim = D(cfg)
+    N = nnodes(cfg)
+    f = _f64(f)
+    X = _f64(X).copy()
+    U = _f64(U).copy()
+    np_ = X.shape[-1]
+    W = np.ascontiguousarray(np.asarray(W, np.float64).reshape(3, np_)).copy()
+    fout = np.zeros_like(f)
+    F = np.zeros(dim * N)
+    gbar = np.zeros(3 * np_)
+    fc = np.zeros(3 * np_)
+    rho_i = np.zeros(np_)
+    j_i = np.zeros(3 * np_)
+    kin, tin, hn = _hist_arrays(hist)
+    cap = 64 * np_ + 6 * np_ + 1
+    kout = np.zeros((cap, 2), np.int32)
+    tout = np.zeros((cap, 3))
+    hout = np.zeros(1, np.int64)
+    nskin = lib().orc_step_full(C.byref(cfg), _d(f), _d(fout), _d(F), np_, _d(X), _d(U), _d(W),
+                                _d(_f64(d)), _d(_f64(rho_p)), hn, _i(kin), _d(tin), _i(kout), _d(tout),
+                                hout.ctypes.data_as(C.POINTER(C.c_int64)), _d(gbar), _d(fc), _d(rho_i),
+                                _d(j_i))
+    n = int(hout[0])
+    return {
+        "f": fout, "F": F.reshape(dim, N), "X": X, "U": U, "W": W,
+        "gbar": gbar.reshape(3, np_)[:dim], "fc": fc.reshape(3, np_)[:dim],
+        "rho_i": rho_i, "j_i": j_i.reshape(3, np_)[:dim], "nskin": nskin,
+        "hist": (kout[:n].copy(), tout[:n].copy()),
+    }
 
 
 def step(cfg, f, X, U, d, rho_p):

@@ -52,8 +52,9 @@ typedef struct {
     int interp;             /* 0: cosine delta kernel (Eq. lbm11-lbm12); 1: Lagrange
                                polynomials (Eq. lbm5-lbm6) for the interpolation, the
                                delta kernel still spreads (Eq. lbm10-lbm11) */
-    double young, poisson;  /* Hertz contact (contact = 3): Young's modulus and Poisson
+    double young, poisson;  /* Hertz contact (contact = 3, 4): Young's modulus and Poisson
                                ratio of the particles and the walls (one material) */
+    double friction;        /* contact = 4: Coulomb friction coefficient mu */
 } orc_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -593,6 +594,71 @@ int64_t orc_candidate_pairs_brute(const orc_cfg *c, int np, const double *X, con
     return count;
 }
 
+/* Mindlin tangential force and rotation (contact = 4, Sec. 2.3, R25).
+ * The paper's increment dT = 8 G* r_a theta_k d(delta_t) + (-1)^k mu dF_n (1 - theta_k)
+ * is taken in its no-slip limit theta_k = 1, dT = 8 G* r_a d(delta_t), with
+ * r_a = sqrt(delta_n R*) and, as printed, 1/G* = (1 - nu^2)/G + (1 - nu^2)/G,
+ * G = E / (2 (1 + nu)); the Coulomb bound |T| <= mu F_n caps it (sliding).
+ * Per sub-step and contact, with n the unit normal from the partner to the
+ * particle and v_t the tangential part of the velocity of the particle's
+ * contact point relative to the partner's:
+ *   T <- T - (T.n) n, rescaled to its former length (the contact plane turns)
+ *   T <- T - 8 G* r_a h v_t,   then |T| <= mu F_n
+ * T is the tangential force on the particle; it is zero while the bodies do
+ * not overlap.  Moments of inertia: 2/5 m R^2 (sphere), 1/2 m R^2 (disk);
+ * torque (-R n) x T on each body; I dW/dt = torque (Eq. demgov, second line). */
+static double mindlin_gstar(const orc_cfg *c)
+{
+    double G = c->young / (2.0 * (1.0 + c->poisson));
+    return G / (2.0 * (1.0 - c->poisson * c->poisson));
+}
+
+static double inertia(int D, double m, double d)
+{
+    return (D == 3 ? 0.4 : 0.5) * m * 0.25 * d * d;
+}
+
+/* z = x cross y; in 2D vectors lie in the plane and angular quantities are
+ * stored in component 2 (the z axis). */
+static void cross3(const double *x, const double *y, double *z)
+{
+    z[0] = x[1] * y[2] - x[2] * y[1];
+    z[1] = x[2] * y[0] - x[0] * y[2];
+    z[2] = x[0] * y[1] - x[1] * y[0];
+}
+
+/* One contact's tangential update.  n: unit normal (3 components, z = 0 in
+ * 2D); vrel: contact-point velocity of the particle minus the partner's;
+ * Fn: Hertz normal force; rstar: effective radius; delta: overlap.
+ * T (in/out): tangential force on the particle. */
+static void mindlin_update(const orc_cfg *c, double h, const double *n, const double *vrel,
+                           double Fn, double rstar, double delta, double *T)
+{
+    double tn = T[0] * n[0] + T[1] * n[1] + T[2] * n[2];
+    double old = sqrt(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
+    double P[3];
+    for (int a = 0; a < 3; a++) P[a] = T[a] - tn * n[a];
+    double pl = sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+    for (int a = 0; a < 3; a++) T[a] = pl > 0.0 ? P[a] * (old / pl) : 0.0;
+    double vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+    double kt = 8.0 * mindlin_gstar(c) * sqrt(delta * rstar);
+    for (int a = 0; a < 3; a++) T[a] -= kt * h * (vrel[a] - vn * n[a]);
+    double tl = sqrt(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
+    double lim = c->friction * Fn;
+    if (tl > lim)
+        for (int a = 0; a < 3; a++) T[a] *= lim / tl;
+}
+
+/* History of the tangential forces between steps: entry i is the pair
+ * key[2i], key[2i+1] (particle indices p < q, or p and -1 - (2 a + side) for
+ * the wall at side 0 / n of axis a) with the force T[3i..3i+2] on p. */
+static int64_t hist_find(int64_t hn, const int *key, int p, int q)
+{
+    for (int64_t i = 0; i < hn; i++)
+        if (key[2 * i] == p && key[2 * i + 1] == q) return i;
+    return -1;
+}
+
 /* O4.  Particle sub-steps (R4, R8, R9).  For k = 0 .. n_sub-1 with h = 1/n_sub,
  * every force uses the state at sub-step k (Jacobi):
  *   g^k   = 2 (rho_i U^k - j_i)                (R2: momentum exchange, Eqs. lbm7-lbm8)
@@ -600,20 +666,41 @@ int64_t orc_candidate_pairs_brute(const orc_cfg *c, int np, const double *X, con
  *   F_c^k = sum over candidate pairs and walls
  *   U^{k+1} = U^k + h (F_h^k + F_c^k + (1 - rho0/rho_p) m g) / m   (Eq. demgov)
  *   X^{k+1} = X^k + h U^{k+1}
+ *   W^{k+1} = W^k + h torque^k / I             (contact = 4 only)
  * Outputs the final X, U, the sub-step mean gbar of g (what the fluid
  * receives), the sub-step mean contact force, and vmax_p = max_k |U^k|
  * over k = 0..n_sub (the skin check: displacement <= vmax * one step).
- * pairs: candidate pairs at the start of the step (orc_candidate_pairs). */
-void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
-             const double *rho_p, const double *rho_i, const double *j_i,
-             int64_t npairs, const int *pairs, double *gbar, double *fc_mean, double *vmax)
+ * pairs: candidate pairs at the start of the step (orc_candidate_pairs).
+ * With contact = 4: W (3 x np, angular velocities) is updated, and the
+ * tangential-force history (hn_in entries) is read and rewritten to
+ * key_out / T_out (capacity npairs + 2 D np), returning the entry count. */
+int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, const double *d,
+                     const double *rho_p, const double *rho_i, const double *j_i,
+                     int64_t npairs, const int *pairs, int64_t hn_in, const int *key_in,
+                     const double *T_in, int *key_out, double *T_out,
+                     double *gbar, double *fc_mean, double *vmax)
 {
     int D = orc_dim(c->lattice);
     int n_sub = c->n_sub;
     double h = 1.0 / n_sub;
-    double *m = malloc(sizeof(double) * (np > 0 ? np : 1));
-    double *g = malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
-    double *Fc = malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+    int mind = c->contact == 4;
+    int npp = np > 0 ? np : 1;
+    double *m = malloc(sizeof(double) * npp);
+    double *g = malloc(sizeof(double) * 3 * npp);
+    double *Fc = malloc(sizeof(double) * 3 * npp);
+    double *tq = malloc(sizeof(double) * 3 * npp);
+    double *Tp = malloc(sizeof(double) * 3 * (npairs > 0 ? npairs : 1));
+    double *Tw = malloc(sizeof(double) * 3 * 6 * npp);
+    /* tangential forces carried over from the previous step */
+    for (int64_t i = 0; i < npairs; i++) {
+        int64_t e = mind ? hist_find(hn_in, key_in, pairs[2 * i], pairs[2 * i + 1]) : -1;
+        for (int a = 0; a < 3; a++) Tp[3 * i + a] = e >= 0 ? T_in[3 * e + a] : 0.0;
+    }
+    for (int p = 0; p < np; p++)
+        for (int w = 0; w < 6; w++) {
+            int64_t e = mind ? hist_find(hn_in, key_in, p, -1 - w) : -1;
+            for (int a = 0; a < 3; a++) Tw[3 * (6 * p + w) + a] = e >= 0 ? T_in[3 * e + a] : 0.0;
+        }
     for (int p = 0; p < np; p++) {
         m[p] = orc_mass(D, d[p], rho_p[p]);
         for (int a = 0; a < 3; a++) {
@@ -630,14 +717,48 @@ void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
             for (int a = 0; a < 3; a++) {
                 g[3 * p + a] = (a < D) ? 2.0 * (rho_i[p] * U[a * np + p] - j_i[a * np + p]) : 0.0;
                 Fc[3 * p + a] = 0;
+                tq[3 * p + a] = 0;
             }
             double Xp[3] = {0, 0, 0}, Up[3] = {0, 0, 0}, Fw[3];
             for (int a = 0; a < D; a++) {
                 Xp[a] = X[a * np + p];
                 Up[a] = U[a * np + p];
             }
-            wall_force(c, D, Xp, Up, d[p], m[p], Fw);
-            for (int a = 0; a < D; a++) Fc[3 * p + a] += Fw[a];
+            if (!mind) {
+                wall_force(c, D, Xp, Up, d[p], m[p], Fw);
+                for (int a = 0; a < D; a++) Fc[3 * p + a] += Fw[a];
+                continue;
+            }
+            /* Hertz-Mindlin walls: infinite radius and mass, at rest */
+            double R = 0.5 * d[p];
+            for (int a = 0; a < D; a++) {
+                if (c->periodic[a]) continue;
+                for (int side = 0; side < 2; side++) {
+                    double *T = Tw + 3 * (6 * p + 2 * a + side);
+                    double dist = side == 0 ? Xp[a] : c->n[a] - Xp[a];
+                    double delta = R - dist;
+                    if (!(delta > 0.0)) {
+                        T[0] = T[1] = T[2] = 0.0;
+                        continue;
+                    }
+                    double n[3] = {0, 0, 0};
+                    n[a] = side == 0 ? 1.0 : -1.0;          /* from the wall to the particle */
+                    double Fn = hertz_force(c, R, delta);
+                    double arm[3], wr[3], vrel[3];
+                    for (int b = 0; b < 3; b++) arm[b] = -R * n[b];
+                    double Wp[3] = {0, 0, W[2 * np + p]};
+                    if (D == 3) { Wp[0] = W[p]; Wp[1] = W[np + p]; }
+                    cross3(Wp, arm, wr);
+                    for (int b = 0; b < 3; b++) vrel[b] = Up[b] + wr[b];
+                    mindlin_update(c, h, n, vrel, Fn, R, delta, T);
+                    double t[3];
+                    cross3(arm, T, t);
+                    for (int b = 0; b < 3; b++) {
+                        Fc[3 * p + b] += Fn * n[b] + T[b];
+                        tq[3 * p + b] += t[b];
+                    }
+                }
+            }
         }
         if (c->contact != 0)
             for (int64_t i = 0; i < npairs; i++) {
@@ -647,10 +768,47 @@ void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
                     r[a] = X[a * np + p] - X[a * np + q];
                     du[a] = U[a * np + p] - U[a * np + q];
                 }
-                pair_force(c, D, r, du, d[p], d[q], m[p], m[q], Fpq);
-                for (int a = 0; a < D; a++) {
-                    Fc[3 * p + a] += Fpq[a];
-                    Fc[3 * q + a] -= Fpq[a];
+                if (!mind) {
+                    pair_force(c, D, r, du, d[p], d[q], m[p], m[q], Fpq);
+                    for (int a = 0; a < D; a++) {
+                        Fc[3 * p + a] += Fpq[a];
+                        Fc[3 * q + a] -= Fpq[a];
+                    }
+                    continue;
+                }
+                double *T = Tp + 3 * i;
+                double dist = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                double Rp = 0.5 * d[p], Rq = 0.5 * d[q];
+                double delta = Rp + Rq - dist;
+                if (!(delta > 0.0)) {
+                    T[0] = T[1] = T[2] = 0.0;
+                    continue;
+                }
+                double rstar = Rp * Rq / (Rp + Rq);
+                double Fn = hertz_force(c, rstar, delta);
+                double n[3], ap[3], aq[3], wp[3], wq[3], vrel[3];
+                for (int a = 0; a < 3; a++) {
+                    n[a] = r[a] / dist;                     /* from q to p */
+                    ap[a] = -Rp * n[a];                      /* contact point from p's centre */
+                    aq[a] = Rq * n[a];                       /* contact point from q's centre */
+                }
+                double Wp[3] = {0, 0, W[2 * np + p]}, Wq[3] = {0, 0, W[2 * np + q]};
+                if (D == 3) {
+                    Wp[0] = W[p]; Wp[1] = W[np + p];
+                    Wq[0] = W[q]; Wq[1] = W[np + q];
+                }
+                cross3(Wp, ap, wp);
+                cross3(Wq, aq, wq);
+                for (int a = 0; a < 3; a++) vrel[a] = (du[a] + wp[a]) - wq[a];
+                mindlin_update(c, h, n, vrel, Fn, rstar, delta, T);
+                double tp[3], tqq[3], mT[3] = {-T[0], -T[1], -T[2]};
+                cross3(ap, T, tp);
+                cross3(aq, mT, tqq);
+                for (int a = 0; a < 3; a++) {
+                    Fc[3 * p + a] += Fn * n[a] + T[a];
+                    Fc[3 * q + a] -= Fn * n[a] + T[a];
+                    tq[3 * p + a] += tp[a];
+                    tq[3 * q + a] += tqq[a];
                 }
             }
         /* symplectic Euler update */
@@ -658,13 +816,17 @@ void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
             double A = orc_area(d[p]);
             double s = 0;
             for (int a = 0; a < D; a++) {
-                double W = (1.0 - c->rho0 / rho_p[p]) * m[p] * c->gravity[a];
+                double Wg = (1.0 - c->rho0 / rho_p[p]) * m[p] * c->gravity[a];
                 double Fh = -A * g[3 * p + a];
-                U[a * np + p] += h * (Fh + Fc[3 * p + a] + W) / m[p];
+                U[a * np + p] += h * (Fh + Fc[3 * p + a] + Wg) / m[p];
                 X[a * np + p] += h * U[a * np + p];
                 gbar[a * np + p] += g[3 * p + a];
                 fc_mean[a * np + p] += Fc[3 * p + a];
                 s += U[a * np + p] * U[a * np + p];
+            }
+            if (mind) {
+                double I = inertia(D, m[p], d[p]);
+                for (int a = (D == 3 ? 0 : 2); a < 3; a++) W[a * np + p] += h * tq[3 * p + a] / I;
             }
             if (sqrt(s) > vmax[p]) vmax[p] = sqrt(s);
         }
@@ -674,9 +836,42 @@ void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
             gbar[a * np + p] /= n_sub;
             fc_mean[a * np + p] /= n_sub;
         }
+    /* the new history: every contact that still carries a tangential force */
+    int64_t hn = 0;
+    if (mind) {
+        for (int64_t i = 0; i < npairs; i++) {
+            double *T = Tp + 3 * i;
+            if (T[0] == 0.0 && T[1] == 0.0 && T[2] == 0.0) continue;
+            key_out[2 * hn] = pairs[2 * i];
+            key_out[2 * hn + 1] = pairs[2 * i + 1];
+            for (int a = 0; a < 3; a++) T_out[3 * hn + a] = T[a];
+            hn++;
+        }
+        for (int p = 0; p < np; p++)
+            for (int w = 0; w < 6; w++) {
+                double *T = Tw + 3 * (6 * p + w);
+                if (T[0] == 0.0 && T[1] == 0.0 && T[2] == 0.0) continue;
+                key_out[2 * hn] = p;
+                key_out[2 * hn + 1] = -1 - w;
+                for (int a = 0; a < 3; a++) T_out[3 * hn + a] = T[a];
+                hn++;
+            }
+    }
     free(m);
     free(g);
     free(Fc);
+    free(tq);
+    free(Tp);
+    free(Tw);
+    return hn;
+}
+
+void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
+             const double *rho_p, const double *rho_i, const double *j_i,
+             int64_t npairs, const int *pairs, double *gbar, double *fc_mean, double *vmax)
+{
+    orc_dem_full(c, np, X, U, NULL, d, rho_p, rho_i, j_i, npairs, pairs, 0, NULL, NULL, NULL, NULL,
+                 gbar, fc_mean, vmax);
 }
 
 /* One coupled step n -> n+1, O1..O7 (R9):
@@ -684,12 +879,14 @@ void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
  *   positions;  O4 particle sub-steps;  O5 spreading of A_p gbar with the
  *   start-of-step weights (if two_way);  O6-O7 collision with
  *   F = fluid_force + spread, and streaming.
- * Particle state X, U is updated in place.  Outputs: fout; F (D x N, the
- * force field used by the collision); gbar, fc_mean (D x np); returns the
- * number of particles whose vmax exceeds skin/2 (the skin check). */
-int orc_step(const orc_cfg *c, const double *f, double *fout, double *F,
-             int np, double *X, double *U, const double *d, const double *rho_p,
-             double *gbar, double *fc_mean, double *rho_i_out, double *j_i_out)
+ * Particle state X, U (and, with contact = 4, W and the tangential-force
+ * history of orc_dem_full) is updated in place.  Outputs: fout; F (D x N,
+ * the force field used by the collision); gbar, fc_mean (D x np); returns
+ * the number of particles whose vmax exceeds skin/2 (the skin check). */
+int orc_step_full(const orc_cfg *c, const double *f, double *fout, double *F,
+                  int np, double *X, double *U, double *W, const double *d, const double *rho_p,
+                  int64_t hn_in, const int *key_in, const double *T_in, int *key_out, double *T_out,
+                  int64_t *hn_out, double *gbar, double *fc_mean, double *rho_i_out, double *j_i_out)
 {
     int D = orc_dim(c->lattice);
     size_t N = nnodes(c);
@@ -712,7 +909,9 @@ int orc_step(const orc_cfg *c, const double *f, double *fout, double *F,
         pairs = malloc(sizeof(int) * 2 * (npairs > 0 ? npairs : 1));
         orc_candidate_pairs(c, np, X0, d, pairs, npairs);
     }
-    orc_dem(c, np, X, U, d, rho_p, rho_i, j_i, npairs, pairs, gbar, fc_mean, vmax);
+    int64_t hn = orc_dem_full(c, np, X, U, W, d, rho_p, rho_i, j_i, npairs, pairs, hn_in, key_in, T_in,
+                              key_out, T_out, gbar, fc_mean, vmax);
+    if (hn_out) *hn_out = hn;
 
     for (int a = 0; a < D; a++)
         for (size_t r = 0; r < N; r++) F[a * N + r] = c->fluid_force[a];
@@ -745,6 +944,14 @@ int orc_step(const orc_cfg *c, const double *f, double *fout, double *F,
     free(vmax);
     free(pairs);
     return nskin;
+}
+
+int orc_step(const orc_cfg *c, const double *f, double *fout, double *F,
+             int np, double *X, double *U, const double *d, const double *rho_p,
+             double *gbar, double *fc_mean, double *rho_i_out, double *j_i_out)
+{
+    return orc_step_full(c, f, fout, F, np, X, U, NULL, d, rho_p, 0, NULL, NULL, NULL, NULL, NULL,
+                         gbar, fc_mean, rho_i_out, j_i_out);
 }
 
 /* Total fluid mass sum_r sum_q f and momentum sum_r sum_q e_q f. */
