@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define PIBM_ABI_VERSION 3
+#define PIBM_ABI_VERSION 4
 
 typedef enum {
     PIBM_OK = 0,
@@ -65,7 +65,13 @@ typedef enum {
 
 enum { PIBM_D2Q9 = 9, PIBM_D3Q15 = 15, PIBM_D3Q19 = 19 };
 enum { PIBM_STORE_FP32 = 0, PIBM_STORE_FP16 = 1 };
-enum { PIBM_CONTACT_NONE = 0, PIBM_CONTACT_LSD = 1, PIBM_CONTACT_SOFT = 2, PIBM_CONTACT_HERTZ = 3 };
+enum {
+    PIBM_CONTACT_NONE = 0,
+    PIBM_CONTACT_LSD = 1,
+    PIBM_CONTACT_SOFT = 2,
+    PIBM_CONTACT_HERTZ = 3,
+    PIBM_CONTACT_HERTZ_MINDLIN = 4
+};
 enum { PIBM_INTERP_DELTA = 0, PIBM_INTERP_LAGRANGE = 1 };
 
 /* Lattice velocity order used by pibm_read_populations/pibm_write_populations:
@@ -93,8 +99,9 @@ typedef struct {
     double rho0;              /* fluid density in the buoyancy term (Eq. demgov) */
     double gravity[3];        /* acceleration on particles */
     double fluid_force[3];    /* uniform body force density on the fluid */
-    int32_t contact;          /* PIBM_CONTACT_*: none, linear spring-dashpot, soft repulsion, or
-                                 Hertz (Sec. 2.3; young and poisson below) */
+    int32_t contact;          /* PIBM_CONTACT_*: none, linear spring-dashpot, soft repulsion,
+                                 Hertz, or Hertz with the Mindlin tangential force and particle
+                                 rotation (Sec. 2.3; young, poisson, friction below) */
     int32_t n_sub;            /* DEM sub-steps per lattice step, >= 1 */
     double kn;                /* linear spring stiffness */
     double restitution;       /* normal restitution of the linear spring-dashpot, (0, 1] */
@@ -116,6 +123,14 @@ typedef struct {
     double poisson;           /* PIBM_CONTACT_HERTZ: Poisson ratio nu, 0 <= nu < 1/2.  The normal
                                  force is (4/3) E* sqrt(R*) delta^(3/2) with E* = E / (2 (1 - nu^2)),
                                  1/R* = 1/R_p + 1/R_q (R* = R_p at a wall), undamped (Sec. 2.3) */
+    double friction;          /* PIBM_CONTACT_HERTZ_MINDLIN: Coulomb coefficient mu >= 0.  The
+                                 tangential force T on a particle grows by -8 G* r_a h v_t per
+                                 sub-step (v_t: tangential contact-point velocity relative to the
+                                 partner, r_a = sqrt(delta R*), 1/G* = 2 (1 - nu^2)/G as printed in
+                                 the paper, G = E / (2 (1 + nu))), is turned into the current
+                                 contact plane, capped at mu F_n, and carried between steps per
+                                 pair of particle ids; spheres (disks) spin with I = 2/5 m R^2
+                                 (1/2 m R^2) under the torque (-R n) x T.  No hydrodynamic torque */
 } pibm_config;
 
 typedef struct {
@@ -164,6 +179,13 @@ pibm_status pibm_set_particles(pibm_ctx* ctx, const double* x, const double* v,
  * f_contact = sub-step mean of the contact force, both of the last step. */
 pibm_status pibm_read_particles(pibm_ctx* ctx, double* x, double* v, double* f_hydro,
                                 double* f_contact);
+/* Angular velocities for PIBM_CONTACT_HERTZ_MINDLIN (the second line of
+ * Eq. demgov), host FP64 arrays in id order: 3 x N (x, y, z) in 3D, N (the
+ * z component) in 2D.  pibm_set_particles sets them to zero and clears the
+ * tangential-force history; pibm_set_rotation may follow it before the first
+ * step (PIBM_E_STATE afterwards).  Other contact models: PIBM_E_CONFIG. */
+pibm_status pibm_set_rotation(pibm_ctx* ctx, const double* w);
+pibm_status pibm_read_rotation(pibm_ctx* ctx, double* w);
 
 /* Density (N) and velocity u = j / rho (D x N) of the stored populations. */
 pibm_status pibm_read_fields(pibm_ctx* ctx, float* rho, float* u);

@@ -258,6 +258,9 @@ __global__ __launch_bounds__(256) void k_reorder(PState A, PState B, const uint3
     B.d[o] = A.d[s];
     B.rp[o] = A.rp[s];
     B.id[o] = myid;
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+        if (A.w[a]) B.w[a][o] = A.w[a][s];
     keys_sorted[o] = k;
     // leading parts of the position and the diameter, for neighbour screening
     pos4[o] = make_float4(A.xh[0][s], A.xh[1][s], D == 3 ? A.xh[2][s] : 0.f, A.d[s]);
@@ -601,7 +604,8 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
                                                   float* __restrict__ coef, float* __restrict__ fc,
                                                   unsigned long long* __restrict__ actcc,
                                                   unsigned long long* __restrict__ bsum,
-                                                  uint32_t* __restrict__ counters, uint32_t* __restrict__ flags) {
+                                                  uint32_t* __restrict__ counters, uint32_t* __restrict__ flags,
+                                                  uint32_t* __restrict__ hcnt) {
     __shared__ unsigned long long sh4[4];
     const unsigned lb = xcd_block();
     const int s = lb * 256 + threadIdx.x;
@@ -668,6 +672,13 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
                 Bn.u[a][s] = un[a];
                 coef[(long long)a * np + s] = Ap * gb[a];
                 fc[(long long)a * np + s] = 0.f;
+            }
+            if (hcnt) {
+                // no contact: the spin is unchanged and no tangential force is carried
+#pragma unroll
+                for (int a = 0; a < 3; a++)
+                    if (A.w[a]) Bn.w[a][s] = A.w[a][s];
+                hcnt[A.id[s]] = 0u;
             }
             if (B > 0.5f * c.skin) atomicOr(flags, FLAG_SKIN);
         }
@@ -866,7 +877,8 @@ __device__ __forceinline__ void cand_prep_one(uint32_t a, const PState& A, const
                                               const uint32_t* __restrict__ ccount,
                                               const unsigned long long* __restrict__ prefix,
                                               const uint32_t* __restrict__ cand, const uint32_t* __restrict__ aidx,
-                                              const uint32_t* __restrict__ loc, CandData* __restrict__ cdata) {
+                                              const uint32_t* __restrict__ loc, CandData* __restrict__ cdata,
+                                              MdBuf md) {
 #pragma clang fp contract(off)
     uint32_t s = alist[a];
     uint32_t off = (uint32_t)(prefix[s] & 0xffffffffULL);
@@ -909,10 +921,27 @@ __device__ __forceinline__ void cand_prep_one(uint32_t a, const PState& A, const
         cd.K0 = k0h + (k0e + (qe - sl));
         cd.rc = rch;
         cd.r0[0] = r0[0]; cd.r0[1] = r0[1]; cd.r0[2] = r0[2];
-        if (c.contact == PIBM_CONTACT_HERTZ) {
+        if (c.contact == PIBM_CONTACT_HERTZ || c.contact == PIBM_CONTACT_HERTZ_MINDLIN) {
             // Hertz: gam holds the pair's stiffness (4/3) E* sqrt(R*)
             const float rs = 0.5f * A.d[s], rt = 0.5f * A.d[t];
-            cd.gam = c.hk * sqrtf(rs * rt / (rs + rt));
+            const float rstar = rs * rt / (rs + rt);
+            cd.gam = c.hk * sqrtf(rstar);
+            if (md.cmd) {
+                // the tangential force this pair carried at the end of the last step
+                const int pid = A.id[t];
+                const long long base = (long long)A.id[s] * c.hmax;
+                const uint32_t hn = md.hcnt[A.id[s]];
+                float T[3] = {0.f, 0.f, 0.f};
+                for (uint32_t e = 0; e < hn; e++)
+                    if (md.hkey[base + e] == pid) {
+                        T[0] = md.hT[3 * (base + e)];
+                        T[1] = md.hT[3 * (base + e) + 1];
+                        T[2] = md.hT[3 * (base + e) + 2];
+                        break;
+                    }
+                md.cmd[off + k] = make_float4(T[0], T[1], T[2], c.kt8 * sqrtf(rstar));
+                md.cpid[off + k] = pid;
+            }
         } else {
             float mt = particle_mass(D, A.d[t], A.rp[t]);
             float meff = ms * mt / (ms + mt);
@@ -928,10 +957,10 @@ __global__ __launch_bounds__(256) void k_cand_prep(PState A, PCfg c, const uint3
                                                    const unsigned long long* __restrict__ prefix,
                                                    const uint32_t* __restrict__ cand, const uint32_t* __restrict__ aidx,
                                                    const uint32_t* __restrict__ loc, CandData* __restrict__ cdata,
-                                                   const uint32_t* __restrict__ counters) {
+                                                   MdBuf md, const uint32_t* __restrict__ counters) {
     uint32_t na = counters[CNT_ACTIVE];
     for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256)
-        cand_prep_one<D>(a, A, c, alist, ccount, prefix, cand, aidx, loc, cdata);
+        cand_prep_one<D>(a, A, c, alist, ccount, prefix, cand, aidx, loc, cdata, md);
 }
 
 // The whole island set-up of one step in one 1024-thread workgroup, phase
@@ -947,7 +976,7 @@ __global__ __launch_bounds__(SETUP_THREADS) void k_island_setup(
     PState A, PCfg c, const uint32_t* __restrict__ alist, const uint32_t* __restrict__ ccount,
     const unsigned long long* __restrict__ prefix, const uint32_t* __restrict__ cand,
     const uint32_t* __restrict__ aidx, uint32_t* parent, uint32_t* isize, uint32_t* irank, uint32_t* fill,
-    int* lanemember, uint32_t* loc, uint32_t* bigroot, uint32_t* bigoff, uint32_t* bigmember, CandData* cdata,
+    int* lanemember, uint32_t* loc, uint32_t* bigroot, uint32_t* bigoff, uint32_t* bigmember, CandData* cdata, MdBuf md,
     uint32_t* counters, long long lane_cap) {
     __shared__ uint32_t ccls[WAVE + 2];
     __shared__ uint32_t wbase[WAVE + 1];
@@ -998,7 +1027,7 @@ __global__ __launch_bounds__(SETUP_THREADS) void k_island_setup(
         island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, wbase);
     __syncthreads();
     for (uint32_t a = t; a < na; a += SETUP_THREADS)
-        cand_prep_one<D>(a, A, c, alist, ccount, prefix, cand, aidx, loc, cdata);
+        cand_prep_one<D>(a, A, c, alist, ccount, prefix, cand, aidx, loc, cdata, md);
 }
 
 // ---------------------------------------------------------------------------
@@ -1018,19 +1047,62 @@ struct Active {
     bool wall;              // a wall lies within contact distance + skin
     // contact-free closed form: U_eq = u* + slip, q = 1 - hc
     float ueq[3], slip[3], hc, veq;
+    // Hertz-Mindlin only: angular velocity (2D: z), the tangential force of
+    // the wall contact of each axis (bit a of wside: the upper wall), moment
+    // of inertia, radius, id
+    float W[3];
+    float wT[3][3];
+    uint32_t wside;
+    float I, R;
+    int id;
 };
 
-template <int D>
+__device__ __forceinline__ void cross3(const float* x, const float* y, float* z) {
+    z[0] = x[1] * y[2] - x[2] * y[1];
+    z[1] = x[2] * y[0] - x[0] * y[2];
+    z[2] = x[0] * y[1] - x[1] * y[0];
+}
+
+// Tangential force of one contact, one sub-step (Mindlin in its no-slip
+// limit with the Coulomb bound, Sec. 2.3): turn T into the contact plane
+// keeping its length, add -k_t h v_t, cap |T| at mu F_n.  n: unit normal
+// from the partner to the particle; vrel: contact-point velocity relative to
+// the partner's.
+__device__ __forceinline__ void mindlin_update(const PCfg& c, const float* n, const float* vrel, float Fn, float kt,
+                                               float* T) {
+    const float tn = T[0] * n[0] + T[1] * n[1] + T[2] * n[2];
+    const float old = sqrtf(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
+    float P[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) P[a] = T[a] - tn * n[a];
+    const float pl = sqrtf(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) T[a] = pl > 0.f ? P[a] * (old / pl) : 0.f;
+    const float vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+#pragma unroll
+    for (int a = 0; a < 3; a++) T[a] -= kt * c.h * (vrel[a] - vn * n[a]);
+    const float tl = sqrtf(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
+    const float lim = c.mu * Fn;
+    if (tl > lim) {
+        const float sc = lim / tl;
+#pragma unroll
+        for (int a = 0; a < 3; a++) T[a] *= sc;
+    }
+}
+
+template <int D, bool MD>
 __device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const PCfg& c, uint32_t s,
                                             const float* drho_i, const float* j_i, int np,
-                                            const uint32_t* ccount, const unsigned long long* prefix) {
+                                            const uint32_t* ccount, const unsigned long long* prefix,
+                                            const MdBuf& md) {
     P.d = A.d[s];
     float rp = A.rp[s];
     P.m = particle_mass(D, P.d, rp);
     P.Ap = 0.25f * PI_F * P.d * P.d;
     P.ri = 1.0f + drho_i[s];
     // wall dashpot coefficient, or the Hertz wall stiffness (4/3) E* sqrt(R_p)
-    P.gw = c.contact == PIBM_CONTACT_HERTZ ? c.hk * sqrtf(0.5f * P.d) : 2.0f * c.zeta * sqrtf(c.kn * P.m);
+    const bool hertz = c.contact == PIBM_CONTACT_HERTZ || c.contact == PIBM_CONTACT_HERTZ_MINDLIN;
+    P.gw = hertz ? c.hk * sqrtf(0.5f * P.d) : 2.0f * c.zeta * sqrtf(c.kn * P.m);
     float v2 = 0.f;
     bool wall = false;
 #pragma unroll
@@ -1064,6 +1136,73 @@ __device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const
     P.vmax2 = v2;
     P.off = (uint32_t)(prefix[s] & 0xffffffffULL);
     P.cnt = c.contact != PIBM_CONTACT_NONE ? (int)ccount[s] : 0;
+    if (MD) {
+        P.R = 0.5f * P.d;
+        P.I = (D == 3 ? 0.4f : 0.5f) * P.m * P.R * P.R;
+        P.W[0] = D == 3 ? A.w[0][s] : 0.f;
+        P.W[1] = D == 3 ? A.w[1][s] : 0.f;
+        P.W[2] = D == 3 ? A.w[2][s] : A.w[0][s];
+        P.id = A.id[s];
+        P.wside = 0u;
+#pragma unroll
+        for (int a = 0; a < 3; a++) P.wT[a][0] = P.wT[a][1] = P.wT[a][2] = 0.f;
+        // wall contacts carried over from the last step
+        const long long base = (long long)P.id * c.hmax;
+        const uint32_t hn = md.hcnt[P.id];
+        for (uint32_t e = 0; e < hn; e++) {
+            const int key = md.hkey[base + e];
+            if (key >= 0) continue;
+            const int code = -1 - key, a = code >> 1;
+#pragma unroll
+            for (int ax = 0; ax < D; ax++)
+                if (ax == a) {
+                    P.wT[ax][0] = md.hT[3 * (base + e)];
+                    P.wT[ax][1] = md.hT[3 * (base + e) + 1];
+                    P.wT[ax][2] = md.hT[3 * (base + e) + 2];
+                    P.wside |= (uint32_t)(code & 1) << ax;
+                }
+        }
+    }
+}
+
+// Hertz-Mindlin wall contacts: Hertz normal force with R* = R, tangential
+// force on the contact point at -R n, its torque.
+template <int D>
+__device__ __forceinline__ void wall_force_md(Active<D>& P, const PCfg& c, float* F, float* tq) {
+    const float rc = 0.5f * P.d;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        const float dlo = ((rc - P.xh[a]) - P.xl[a]) - P.dx[a];
+        const float dhi = ((rc - ((float)c.n[a] - P.xh[a])) + P.xl[a]) + P.dx[a];
+        const bool lo = dlo > 0.f, hi = !lo && dhi > 0.f;
+        if (!lo && !hi) {
+            P.wT[a][0] = P.wT[a][1] = P.wT[a][2] = 0.f;
+            continue;
+        }
+        const uint32_t side = hi ? 1u : 0u;
+        if (((P.wside >> a) & 1u) != side) {
+            P.wT[a][0] = P.wT[a][1] = P.wT[a][2] = 0.f;
+            P.wside ^= 1u << a;
+        }
+        const float delta = lo ? dlo : dhi;
+        float n[3] = {0.f, 0.f, 0.f};
+        n[a] = lo ? 1.0f : -1.0f;              // from the wall to the particle
+        const float Fn = P.gw * delta * sqrtf(delta);
+        float arm[3], wr[3], vrel[3];
+#pragma unroll
+        for (int b = 0; b < 3; b++) arm[b] = -P.R * n[b];
+        cross3(P.W, arm, wr);
+#pragma unroll
+        for (int b = 0; b < 3; b++) vrel[b] = (b < D ? P.u[b] : 0.f) + wr[b];
+        mindlin_update(c, n, vrel, Fn, c.kt8 * sqrtf(delta * P.R), P.wT[a]);
+        float t[3];
+        cross3(arm, P.wT[a], t);
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            if (b < D) F[b] += Fn * n[b] + P.wT[a][b];
+            tq[b] += t[b];
+        }
+    }
 }
 
 template <int D>
@@ -1126,16 +1265,72 @@ __device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& c
     }
 }
 
-// One sub-step for particle P.  Partner states are read through arrays
-// (sdx, su) of stride `stride` indexed by the candidate's local index; the
-// first nfirst candidates come from `first` (an LDS copy), the rest from
-// `rest` (global).
+// Hertz-Mindlin pair contact: Hertz normal force, tangential force T
+// (carried in cmd, the force on this particle), torque of T about the
+// centre.  Partner spin ow; contact point at -R_self n from this centre and
+// at +R_partner n from the partner's.
 template <int D>
+__device__ __forceinline__ void pair_force_md(const Active<D>& P, const CandData& cd, float4* __restrict__ cmd,
+                                              const float* odx, const float* ou, const float* ow, const PCfg& c,
+                                              float* F, float* tq) {
+    float r[3] = {0, 0, 0};
+    float rd = 0.f, dd = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        const float del = P.dx[a] - odx[a];
+        r[a] = cd.r0[a] + del;
+        rd += cd.r0[a] * del;
+        dd += del * del;
+    }
+    const float num = cd.K0 - (2.0f * rd + dd);          // r_c^2 - |r|^2
+    float4 m = *cmd;
+    if (!(num > 0.f)) {
+        if (m.x != 0.f || m.y != 0.f || m.z != 0.f) *cmd = make_float4(0.f, 0.f, 0.f, m.w);
+        return;
+    }
+    float r2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) r2 += r[a] * r[a];
+    const float dist = sqrtf(r2);
+    const float delta = num / (cd.rc + dist);            // r_c - |r|
+    const float inv = 1.0f / dist;
+    float n[3], as[3], at[3], ws[3], wt[3], vrel[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        n[a] = r[a] * inv;
+        as[a] = -P.R * n[a];
+        at[a] = (cd.rc - P.R) * n[a];
+    }
+    cross3(P.W, as, ws);
+    cross3(ow, at, wt);
+#pragma unroll
+    for (int a = 0; a < 3; a++) vrel[a] = (((a < D ? P.u[a] : 0.f) - ou[a]) + ws[a]) - wt[a];
+    const float Fn = cd.gam * delta * sqrtf(delta);
+    float T[3] = {m.x, m.y, m.z};
+    mindlin_update(c, n, vrel, Fn, m.w * sqrtf(delta), T);
+    *cmd = make_float4(T[0], T[1], T[2], m.w);
+    float t[3];
+    cross3(as, T, t);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (a < D) F[a] += Fn * n[a] + T[a];
+        tq[a] += t[a];
+    }
+}
+
+// One sub-step for particle P.  Partner states are read through arrays
+// (sdx, su, and with MD the spins sw) of stride `stride` indexed by the
+// candidate's local index; the first nfirst candidates come from `first`
+// (an LDS copy), the rest from `rest` (global).
+template <int D, bool MD>
 __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, const CandData* first, int nfirst,
                                                const CandData* __restrict__ rest, const float* sdx,
-                                               const float* su, int stride) {
-    float F[3] = {0.f, 0.f, 0.f};
-    if (P.wall) wall_force<D>(P, c, F);
+                                               const float* su, const float* sw, int stride, const MdBuf& md) {
+    float F[3] = {0.f, 0.f, 0.f}, tq[3] = {0.f, 0.f, 0.f};
+    if (P.wall) {
+        if (MD) wall_force_md<D>(P, c, F, tq);
+        else wall_force<D>(P, c, F);
+    }
     const int n1 = min(P.cnt, nfirst);
     for (int k = 0; k < P.cnt; k++) {
         CandData cd = (k < n1) ? first[k] : rest[k];
@@ -1145,7 +1340,19 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
             odx[a] = sdx[a * stride + cd.local];
             ou[a] = su[a * stride + cd.local];
         }
-        pair_force<D>(P, cd, odx, ou, c, F);
+        if (MD) {
+            float ow[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) ow[a] = sw[a * stride + cd.local];
+            pair_force_md<D>(P, cd, md.cmd + P.off + k, odx, ou, ow, c, F, tq);
+        } else {
+            pair_force<D>(P, cd, odx, ou, c, F);
+        }
+    }
+    if (MD) {
+        // I dW/dt = torque (second line of Eq. demgov)
+#pragma unroll
+        for (int a = (D == 3 ? 0 : 2); a < 3; a++) P.W[a] += c.h * tq[a] / P.I;
     }
     float v2 = 0.f;
 #pragma unroll
@@ -1169,9 +1376,9 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
     P.vmax2 = fmaxf(P.vmax2, v2);
 }
 
-template <int D>
+template <int D, bool MD>
 __device__ __forceinline__ void active_store(const Active<D>& P, PState& Bn, const PCfg& c, uint32_t s, int np,
-                                             float* coef, float* fc, uint32_t* flags) {
+                                             float* coef, float* fc, uint32_t* flags, const MdBuf& md) {
     float invn = 1.0f / (float)c.n_sub;
 #pragma unroll
     for (int a = 0; a < D; a++) {
@@ -1184,6 +1391,37 @@ __device__ __forceinline__ void active_store(const Active<D>& P, PState& Bn, con
         fc[(long long)a * np + s] = P.fs[a] * invn;
     }
     if (sqrtf(P.vmax2) > 0.5f * c.skin) atomicOr(flags, FLAG_SKIN);
+    if (MD) {
+        if (D == 3) {
+            Bn.w[0][s] = P.W[0];
+            Bn.w[1][s] = P.W[1];
+            Bn.w[2][s] = P.W[2];
+        } else {
+            Bn.w[0][s] = P.W[2];
+        }
+        // the history for the next step: every contact that carries a force
+        const long long base = (long long)P.id * c.hmax;
+        uint32_t n = 0;
+        for (int k = 0; k < P.cnt; k++) {
+            const float4 m = md.cmd[P.off + k];
+            if (m.x == 0.f && m.y == 0.f && m.z == 0.f) continue;
+            md.hkey[base + n] = md.cpid[P.off + k];
+            md.hT[3 * (base + n)] = m.x;
+            md.hT[3 * (base + n) + 1] = m.y;
+            md.hT[3 * (base + n) + 2] = m.z;
+            n++;
+        }
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            if (P.wT[a][0] == 0.f && P.wT[a][1] == 0.f && P.wT[a][2] == 0.f) continue;
+            md.hkey[base + n] = -1 - (2 * a + (int)((P.wside >> a) & 1u));
+            md.hT[3 * (base + n)] = P.wT[a][0];
+            md.hT[3 * (base + n) + 1] = P.wT[a][1];
+            md.hT[3 * (base + n) + 2] = P.wT[a][2];
+            n++;
+        }
+        md.hcnt[P.id] = n;
+    }
 }
 
 constexpr int CAND_LDS = 8;   // candidates per lane cached in LDS
@@ -1241,8 +1479,18 @@ __device__ __forceinline__ int free_allowance(const Active<D>& P, const PCfg& c,
 // Advance P by m contact-free sub-steps in closed form:
 //   U^{k+m} = U_eq + (U^k - U_eq) q^m,  sum_{i=1..m} U^{k+i} = m U_eq + (U^k - U_eq) q S,
 //   sum_{i<m} g^{k+i} = 2 rho_i (m slip + (U^k - U_eq) S),  S = (1 - q^m)/(1 - q).
-template <int D>
-__device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m) {
+template <int D, bool MD>
+__device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m, const MdBuf& md) {
+    if (MD) {
+        // no contact along the stretch: every tangential force lapses, the
+        // spin is unchanged
+#pragma unroll
+        for (int a = 0; a < 3; a++) P.wT[a][0] = P.wT[a][1] = P.wT[a][2] = 0.f;
+        for (int k = 0; k < P.cnt; k++) {
+            const float4 q = md.cmd[P.off + k];
+            if (q.x != 0.f || q.y != 0.f || q.z != 0.f) md.cmd[P.off + k] = make_float4(0.f, 0.f, 0.f, q.w);
+        }
+    }
     const float mm = (float)m;
     float qm, omq;
     drag_power(P.hc, m, qm, omq);
@@ -1272,7 +1520,7 @@ __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m) 
 // contact-free stretch (all of its members agree on the shortest allowance)
 // or takes one Jacobi sub-step; so the result of an island does not depend
 // on which other islands share its wave.
-template <int D>
+template <int D, bool MD>
 __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np, PCfg c,
                                                      const int* __restrict__ lanemember,
                                                      const uint32_t* __restrict__ alist,
@@ -1284,9 +1532,10 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
                                                      const float* __restrict__ drho_i, const float* __restrict__ j_i,
                                                      float* __restrict__ coef, float* __restrict__ fc,
                                                      uint32_t* __restrict__ flags,
-                                                     const uint32_t* __restrict__ counters) {
+                                                     const uint32_t* __restrict__ counters, MdBuf md) {
     __shared__ float sdx[2][3 * WAVE];
     __shared__ float su[2][3 * WAVE];
+    __shared__ float sw[MD ? 2 : 1][MD ? 3 * WAVE : 1];
     __shared__ float sveq[WAVE];
     __shared__ int sallow[WAVE];
     __shared__ CandData scd[WAVE * CAND_LDS];
@@ -1309,7 +1558,7 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
         Active<D> P;
         int nfirst = 0, isz = 1;
         if (valid) {
-            active_load<D>(P, A, c, s, drho_i, j_i, np, ccount, prefix);
+            active_load<D, MD>(P, A, c, s, drho_i, j_i, np, ccount, prefix, md);
             nfirst = min(P.cnt, CAND_LDS);
             for (int k = 0; k < nfirst; k++) scd[lane * CAND_LDS + k] = cdata[P.off + k];
             isz = (int)isize[parent[a]];
@@ -1319,6 +1568,7 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
         for (int ax = 0; ax < 3; ax++) {
             sdx[0][ax * WAVE + lane] = 0.f;
             su[0][ax * WAVE + lane] = valid ? P.u[ax] : 0.f;
+            if (MD) sw[0][ax * WAVE + lane] = valid ? P.W[ax] : 0.f;
         }
         sveq[lane] = valid ? P.veq : 0.f;
         __syncthreads();
@@ -1336,10 +1586,11 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
             for (int i = 0; i < isz; i++) m = min(m, sallow[ibase + i]);
             if (more) {
                 if (m >= 2) {
-                    active_jump<D>(P, c, m);
+                    active_jump<D, MD>(P, c, m, md);
                     k += m;
                 } else {
-                    active_substep<D>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur], WAVE);
+                    active_substep<D, MD>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur],
+                                          MD ? sw[cur] : nullptr, WAVE, md);
                     k += 1;
                 }
             }
@@ -1347,11 +1598,12 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
             for (int ax = 0; ax < 3; ax++) {
                 sdx[cur ^ 1][ax * WAVE + lane] = valid ? P.dx[ax] : 0.f;
                 su[cur ^ 1][ax * WAVE + lane] = valid ? P.u[ax] : 0.f;
+                if (MD) sw[cur ^ 1][ax * WAVE + lane] = valid ? P.W[ax] : 0.f;
             }
             __syncthreads();
             cur ^= 1;
         }
-        if (valid) active_store<D>(P, Bn, c, s, np, coef, fc, flags);
+        if (valid) active_store<D, MD>(P, Bn, c, s, np, coef, fc, flags, md);
         __syncthreads();
     }
 }
@@ -1359,7 +1611,7 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
 // Islands larger than a wave: one 256-lane workgroup per island, states in
 // global scratch indexed by the active index (gdx, gu: [2][3][cap]; the
 // compensations and running sums follow gdx at 6 cap .. 19 cap).
-template <int D>
+template <int D, bool MD>
 __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np, PCfg c,
                                                     const uint32_t* __restrict__ bigmember,
                                                     const uint32_t* __restrict__ bigoff,
@@ -1373,7 +1625,11 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
                                                     float* __restrict__ coef, float* __restrict__ fc,
                                                     float* gdx, float* gu, long long cap,
                                                     uint32_t* __restrict__ flags,
-                                                    const uint32_t* __restrict__ counters) {
+                                                    const uint32_t* __restrict__ counters, MdBuf md) {
+    // MD scratch: spin [2][3][cap], wall tangential forces [9][cap], wall sides [cap]
+    float* gw = md.gmd;
+    float* gwt = md.gmd + 6 * cap;
+    uint32_t* gside = (uint32_t*)(md.gmd + 15 * cap);
     const uint32_t nbig = counters[CNT_BIG];
     for (uint32_t ib = blockIdx.x; ib < nbig; ib += gridDim.x) {
         uint32_t base = bigoff[ib];
@@ -1386,6 +1642,11 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
                 gdx[(0 * 3 + ax) * cap + a] = 0.f;
                 gu[(0 * 3 + ax) * cap + a] = ax < D ? A.u[ax][s] : 0.f;
             }
+            if (MD) {
+                gw[(0 * 3 + 0) * cap + a] = D == 3 ? A.w[0][s] : 0.f;
+                gw[(0 * 3 + 1) * cap + a] = D == 3 ? A.w[1][s] : 0.f;
+                gw[(0 * 3 + 2) * cap + a] = D == 3 ? A.w[2][s] : A.w[0][s];
+            }
         }
         __syncthreads();
         // per-member state is re-read from scratch each sub-step (a lane may own several members)
@@ -1395,11 +1656,22 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
                 uint32_t a = bigmember[base + i];
                 uint32_t s = alist[a];
                 Active<D> P;
-                active_load<D>(P, A, c, s, drho_i, j_i, np, ccount, prefix);
+                active_load<D, MD>(P, A, c, s, drho_i, j_i, np, ccount, prefix, md);
 #pragma unroll
                 for (int ax = 0; ax < D; ax++) {
                     P.dx[ax] = gdx[(cur * 3 + ax) * cap + a];
                     P.u[ax] = gu[(cur * 3 + ax) * cap + a];
+                }
+                if (MD) {
+#pragma unroll
+                    for (int ax = 0; ax < 3; ax++) P.W[ax] = gw[(cur * 3 + ax) * cap + a];
+                    if (k > 0) {
+#pragma unroll
+                        for (int ax = 0; ax < 3; ax++)
+#pragma unroll
+                            for (int b = 0; b < 3; b++) P.wT[ax][b] = gwt[(3 * ax + b) * cap + a];
+                        P.wside = gside[a];
+                    }
                 }
                 float* aux = gdx + 6 * cap;
                 if (k > 0) {
@@ -1412,8 +1684,17 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
                     }
                     P.vmax2 = aux[12 * cap + a];
                 }
-                active_substep<D>(P, c, cdata + P.off, P.cnt, cdata + P.off, gdx + cur * 3 * cap,
-                                  gu + cur * 3 * cap, (int)cap);
+                active_substep<D, MD>(P, c, cdata + P.off, P.cnt, cdata + P.off, gdx + cur * 3 * cap,
+                                      gu + cur * 3 * cap, MD ? gw + cur * 3 * cap : nullptr, (int)cap, md);
+                if (MD) {
+#pragma unroll
+                    for (int ax = 0; ax < 3; ax++) {
+                        gw[((cur ^ 1) * 3 + ax) * cap + a] = P.W[ax];
+#pragma unroll
+                        for (int b = 0; b < 3; b++) gwt[(3 * ax + b) * cap + a] = P.wT[ax][b];
+                    }
+                    gside[a] = P.wside;
+                }
 #pragma unroll
                 for (int ax = 0; ax < D; ax++) {
                     gdx[((cur ^ 1) * 3 + ax) * cap + a] = P.dx[ax];
@@ -1424,7 +1705,7 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
                     aux[(3 * 3 + ax) * cap + a] = P.fs[ax];
                 }
                 aux[12 * cap + a] = P.vmax2;
-                if (k == c.n_sub - 1) active_store<D>(P, Bn, c, s, np, coef, fc, flags);
+                if (k == c.n_sub - 1) active_store<D, MD>(P, Bn, c, s, np, coef, fc, flags, md);
             }
             __syncthreads();
         }
@@ -1729,6 +2010,17 @@ __global__ __launch_bounds__(256) void k_unpermute(PState A, int np, const float
     }
 }
 
+// Angular velocities in id order: [component][id], 3 components in 3D, the
+// z component in 2D.
+template <int D>
+__global__ __launch_bounds__(256) void k_unpermute_spin(PState A, int np, float* __restrict__ out) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= np) return;
+    const int id = A.id[s];
+#pragma unroll
+    for (int a = 0; a < (D == 3 ? 3 : 1); a++) out[(long long)a * np + id] = A.w[a][s];
+}
+
 // ---------------------------------------------------------------------------
 // launchers (called from runtime.hip)
 // ---------------------------------------------------------------------------
@@ -1815,8 +2107,10 @@ template <int D>
 static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s) {
     // the island chain works on the active particles only (grid-stride)
     const unsigned grid_act = std::min<unsigned>(nb256(np), 128u);
+    const MdBuf md{b.cmd, b.cpid, b.hcnt, b.hkey, b.hT, b.gmd};
     hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.pos4,
-                       b.keys_sorted, b.drho_i, b.j_i, b.coef, b.fc, b.actcc, b.bsum64, b.counters, b.flags);
+                       b.keys_sorted, b.drho_i, b.j_i, b.coef, b.fc, b.actcc, b.bsum64, b.counters, b.flags,
+                       b.hcnt);
     // block offsets; totals (candidates, active) -> counters[0..1]
     hipLaunchKernelGGL((k_scan_top<unsigned long long>), dim3(1), dim3(TOP_THREADS), 0, s, b.bsum64, (long long)nb256(np),
                        (unsigned long long*)(void*)b.counters);
@@ -1825,7 +2119,7 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
     if (one_group) {
         hipLaunchKernelGGL(k_island_setup<D>, dim3(1), dim3(SETUP_THREADS), 0, s, b.A, c, b.alist, b.ccount, b.prefix,
                            b.cand, b.aidx, b.parent, b.isize, b.irank, b.fill, b.lanemember, b.loc, b.bigroot,
-                           b.bigoff, b.bigmember, b.cdata, b.counters, b.lane_cap);
+                           b.bigoff, b.bigmember, b.cdata, md, b.counters, b.lane_cap);
     } else {
         hipLaunchKernelGGL(k_uf_hook, dim3(grid_act), dim3(256), 0, s, b.alist, b.ccount, b.prefix, b.cand, b.aidx, b.parent,
                            b.counters);
@@ -1836,25 +2130,35 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
         hipLaunchKernelGGL(k_island_place, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.fill,
                            b.lanemember, b.loc, b.bigoff, b.bigmember, b.counters);
         hipLaunchKernelGGL(k_cand_prep<D>, dim3(grid_act), dim3(256), 0, s, b.A, c, b.alist, b.ccount, b.prefix, b.cand,
-                           b.aidx, b.loc, b.cdata, b.counters);
+                           b.aidx, b.loc, b.cdata, md, b.counters);
     }
-    hipLaunchKernelGGL(k_island_small<D>, dim3(std::max<unsigned>(grid_act * 4, 256u)), dim3(64), 0, s, b.A, b.Bn,
-                       np, c, b.lanemember, b.alist, b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i,
-                       b.j_i, b.coef, b.fc,
-                       b.flags, b.counters);
-    hipLaunchKernelGGL(k_island_big<D>, dim3(256), dim3(256), 0, s, b.A, b.Bn, np, c, b.bigmember, b.bigoff,
-                       b.bigroot, b.isize, b.alist, b.ccount, b.prefix, b.cdata, b.drho_i, b.j_i, b.coef, b.fc,
-                       b.gdx, b.gu, (long long)np, b.flags, b.counters);
+    const dim3 gsmall(std::max<unsigned>(grid_act * 4, 256u));
+    if (c.contact == PIBM_CONTACT_HERTZ_MINDLIN) {
+        hipLaunchKernelGGL((k_island_small<D, true>), gsmall, dim3(64), 0, s, b.A, b.Bn, np, c, b.lanemember, b.alist,
+                           b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.coef, b.fc, b.flags,
+                           b.counters, md);
+        hipLaunchKernelGGL((k_island_big<D, true>), dim3(256), dim3(256), 0, s, b.A, b.Bn, np, c, b.bigmember,
+                           b.bigoff, b.bigroot, b.isize, b.alist, b.ccount, b.prefix, b.cdata, b.drho_i, b.j_i,
+                           b.coef, b.fc, b.gdx, b.gu, (long long)np, b.flags, b.counters, md);
+    } else {
+        hipLaunchKernelGGL((k_island_small<D, false>), gsmall, dim3(64), 0, s, b.A, b.Bn, np, c, b.lanemember, b.alist,
+                           b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.coef, b.fc, b.flags,
+                           b.counters, md);
+        hipLaunchKernelGGL((k_island_big<D, false>), dim3(256), dim3(256), 0, s, b.A, b.Bn, np, c, b.bigmember,
+                           b.bigoff, b.bigroot, b.isize, b.alist, b.ccount, b.prefix, b.cdata, b.drho_i, b.j_i,
+                           b.coef, b.fc, b.gdx, b.gu, (long long)np, b.flags, b.counters, md);
+    }
 }
 
 void particles_dem(int D, PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s) {
     if (D == 3) dem_impl<3>(b, np, c, one_group, s);
     else dem_impl<2>(b, np, c, one_group, s);
-    // the new positions and velocities become the current ones
+    // the new positions, velocities and spins become the current ones
     for (int a = 0; a < 3; a++) {
         std::swap(b.A.xh[a], b.Bn.xh[a]);
         std::swap(b.A.xl[a], b.Bn.xl[a]);
         std::swap(b.A.u[a], b.Bn.u[a]);
+        std::swap(b.A.w[a], b.Bn.w[a]);
     }
 }
 
@@ -1887,6 +2191,11 @@ void particles_totals(int D, PBuf& b, int np, double* part, double* out, hipStre
     if (D == 3) hipLaunchKernelGGL(k_particle_totals<3>, dim3(nb), dim3(256), 0, s, b.A, np, part);
     else hipLaunchKernelGGL(k_particle_totals<2>, dim3(nb), dim3(256), 0, s, b.A, np, part);
     hipLaunchKernelGGL(k_particle_final, dim3(1), dim3(64), 0, s, part, nb, out);
+}
+
+void particles_unpermute_spin(int D, PBuf& b, int np, float* out, hipStream_t s) {
+    if (D == 3) hipLaunchKernelGGL(k_unpermute_spin<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, out);
+    else hipLaunchKernelGGL(k_unpermute_spin<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, out);
 }
 
 void particles_unpermute(int D, PBuf& b, int np, bool have_forces, float* out, hipStream_t s) {

@@ -150,6 +150,7 @@ struct PState {
     float* xh[3];
     float* xl[3];
     float* u[3];
+    float* w[3];        // angular velocity (Hertz-Mindlin only, else null): x, y, z in 3D; z in 2D
     float* d;
     float* rp;
     int* id;
@@ -229,6 +230,9 @@ struct PCfg {
     float dmax;         // largest diameter present
     int lagrange;       // 1: gather with the Lagrange polynomials of Eq. lbm5-lbm6
     float hk;           // Hertz: (4/3) E*, so that F_n = hk sqrt(R*) delta^(3/2)
+    float kt8;          // Mindlin: 8 G*, so that k_t = kt8 sqrt(delta R*)
+    float mu;           // Coulomb friction coefficient
+    int hmax;           // tangential-history entries per particle: max candidates + D walls
 };
 
 // Per-candidate constants of the active sub-steps.
@@ -238,6 +242,17 @@ struct CandData {
     float K0;       // r_c^2 - |r0|^2, accurate to FP32 relative precision
     float rc;       // (d_self + d_partner) / 2
     float gam;      // dashpot coefficient 2 zeta sqrt(kn m_eff)
+};
+
+// The Hertz-Mindlin buffers handed to the DEM kernels (all null for the
+// other contact models); see PBuf.
+struct MdBuf {
+    float4* cmd;        // per candidate entry: tangential force on the particle (xyz), 8 G* sqrt(R*) (w)
+    int* cpid;          // per candidate entry: partner id
+    uint32_t* hcnt;     // per particle id: history entries
+    int* hkey;          // per particle id, hmax slots: partner id, or -1 - (2 axis + side) for a wall
+    float* hT;          // per slot: tangential force (3 floats)
+    float* gmd;         // big islands: spin [2][3][cap], wall forces [9][cap], wall sides [cap]
 };
 
 // Device buffers of the particle side (carved from the workspace).
@@ -253,6 +268,15 @@ struct PBuf {
     int* lanemember;
     CandData* cdata;
     float *gdx, *gu;
+    // Hertz-Mindlin: per-candidate tangential force (xyz) and 8 G* sqrt(R*) (w),
+    // partner id; per-particle-id history (count, partner ids or wall codes
+    // -1 - (2 axis + side), forces); spin and wall scratch of big islands
+    float4* cmd;
+    int* cpid;
+    uint32_t* hcnt;
+    int* hkey;
+    float* hT;
+    float* gmd;
     uint32_t* counters;
     uint32_t* flags;
     long long cand_cap, lane_cap;

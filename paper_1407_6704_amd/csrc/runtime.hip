@@ -28,6 +28,7 @@ void lattice_totals(int Q, int fp16, int sl2, const void* f, long long N, double
 long long scan_blocks(long long n);
 void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s);
 void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, const float4* mom, hipStream_t s);
+void particles_unpermute_spin(int D, PBuf& b, int np, float* out, hipStream_t s);
 void particles_interp_from_populations(PBuf& b, int np, const Grid& g, const PCfg& c, const void* f, int fp16,
                                        int sl2, hipStream_t s);
 void particles_dem(int D, PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s);
@@ -138,6 +139,9 @@ pibm_status check_hip(pibm_ctx* c, hipError_t e, const char* what) {
 
 int dimension(int lattice) { return lattice == PIBM_D2Q9 ? 2 : 3; }
 
+// angular-velocity components: 3 in 3D, the z component in 2D
+int spin_components(int D) { return D == 3 ? 3 : 1; }
+
 std::string validate(const pibm_config* cfg, int64_t np) {
     if (!cfg) return "null config";
     if (cfg->abi_version != PIBM_ABI_VERSION) return "ABI version mismatch";
@@ -156,9 +160,11 @@ std::string validate(const pibm_config* cfg, int64_t np) {
         if (cfg->n[a] > 30000) return "axis longer than 30000 nodes";
     if (!(cfg->tau > 0.5)) return "tau must exceed 1/2";
     if (cfg->n_sub < 1) return "n_sub must be >= 1";
-    if (cfg->contact < 0 || cfg->contact > 3) return "unknown contact model";
-    if (cfg->contact == PIBM_CONTACT_HERTZ && (!(cfg->young > 0) || !(cfg->poisson >= 0) || !(cfg->poisson < 0.5)))
+    if (cfg->contact < 0 || cfg->contact > 4) return "unknown contact model";
+    if ((cfg->contact == PIBM_CONTACT_HERTZ || cfg->contact == PIBM_CONTACT_HERTZ_MINDLIN) &&
+        (!(cfg->young > 0) || !(cfg->poisson >= 0) || !(cfg->poisson < 0.5)))
         return "Hertz contact needs young > 0 and 0 <= poisson < 1/2";
+    if (cfg->contact == PIBM_CONTACT_HERTZ_MINDLIN && !(cfg->friction >= 0)) return "friction must be >= 0";
     if (cfg->bin_log2 < 0 || cfg->bin_log2 > 3) return "bin_log2 must be 0..3";
     if (cfg->max_candidates < 1 || cfg->max_candidates > 64) return "max_candidates must be 1..64";
     if (cfg->island_setup < 0 || cfg->island_setup > 2) return "island_setup must be 0, 1 or 2";
@@ -183,6 +189,7 @@ size_t carve(pibm_ctx& c, char* base) {
     c.mom = cv.take<float4>(N);
     c.F = cv.take<float>((size_t)c.D * N);
     long long np = c.np;
+    const bool md = c.cfg.contact == PIBM_CONTACT_HERTZ_MINDLIN;
     c.stage_floats = std::max<long long>((long long)(c.D + 1) * N, 5LL * c.D * np);
     c.stage = cv.take<float>(c.stage_floats);
     c.part = cv.take<double>(8 * (std::max(lattice_totals_blocks(), particles_totals_blocks()) + 2));
@@ -197,6 +204,7 @@ size_t carve(pibm_ctx& c, char* base) {
                 S[k]->xh[a] = a < c.D ? cv.take<float>(np) : nullptr;
                 S[k]->xl[a] = a < c.D ? cv.take<float>(np) : nullptr;
                 S[k]->u[a] = a < c.D ? cv.take<float>(np) : nullptr;
+                S[k]->w[a] = (md && a < spin_components(c.D)) ? cv.take<float>(np) : nullptr;
             }
             S[k]->d = k < 2 ? cv.take<float>(np) : nullptr;
             S[k]->rp = k < 2 ? cv.take<float>(np) : nullptr;
@@ -238,6 +246,22 @@ size_t carve(pibm_ctx& c, char* base) {
         b.lanemember = cv.take<int>(b.lane_cap);
         b.gdx = cv.take<float>(19 * np);
         b.gu = cv.take<float>(6 * np);
+        if (md) {
+            const long long hmax = (long long)c.cfg.max_candidates + c.D;
+            b.cmd = cv.take<float4>(b.cand_cap);
+            b.cpid = cv.take<int>(b.cand_cap);
+            b.hcnt = cv.take<uint32_t>(np);
+            b.hkey = cv.take<int>(np * hmax);
+            b.hT = cv.take<float>(3 * np * hmax);
+            b.gmd = cv.take<float>(16 * np);
+        } else {
+            b.cmd = nullptr;
+            b.cpid = nullptr;
+            b.hcnt = nullptr;
+            b.hkey = nullptr;
+            b.hT = nullptr;
+            b.gmd = nullptr;
+        }
     }
     return cv.off + 256;
 }
@@ -266,6 +290,11 @@ void fill_pcfg(pibm_ctx& c) {
     p.maxc = c.cfg.max_candidates;
     p.lagrange = c.cfg.interp == PIBM_INTERP_LAGRANGE;
     p.hk = (float)(4.0 / 3.0 * c.cfg.young / (2.0 * (1.0 - c.cfg.poisson * c.cfg.poisson)));
+    // G* as printed: 1/G* = 2 (1 - nu^2) / G, G = E / (2 (1 + nu))
+    const double G = c.cfg.young / (2.0 * (1.0 + c.cfg.poisson));
+    p.kt8 = (float)(8.0 * G / (2.0 * (1.0 - c.cfg.poisson * c.cfg.poisson)));
+    p.mu = (float)c.cfg.friction;
+    p.hmax = c.cfg.max_candidates + c.D;
     // trailing parts are at most half an ulp of the leading ones; the
     // screened distance is off by at most sqrt(D) ulp(max extent)
     int nmax = std::max(c.cfg.n[0], std::max(c.cfg.n[1], c.cfg.n[2]));
@@ -284,7 +313,8 @@ void set_stencil(pibm_ctx& c, double dmax) {
 std::string adjoint_unsupported(const pibm_ctx& c) {
     if (c.np < 1) return "the adjoint needs at least one particle";
     if (c.cfg.n_sub != 1) return "the adjoint supports n_sub = 1 only";
-    if (c.cfg.contact == PIBM_CONTACT_LSD || c.cfg.contact == PIBM_CONTACT_HERTZ)
+    if (c.cfg.contact == PIBM_CONTACT_LSD || c.cfg.contact == PIBM_CONTACT_HERTZ ||
+        c.cfg.contact == PIBM_CONTACT_HERTZ_MINDLIN)
         return "the adjoint supports no contact or soft contact only";
     if (c.cfg.bin_log2 != 0) return "the adjoint needs bin_log2 = 0";
     if (c.cfg.lattice == PIBM_D3Q15) return "the adjoint supports D2Q9 and D3Q19 only";
@@ -524,10 +554,43 @@ pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, co
     hipMemcpyAsync(A.d, dd, 4 * np, hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(A.rp, rp, 4 * np, hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(A.id, id, 4 * np, hipMemcpyHostToDevice, c->stream);
+    if (c->pb.hcnt) {
+        // at rest, no tangential-force history
+        for (int a = 0; a < spin_components(D); a++) hipMemsetAsync(A.w[a], 0, 4 * (size_t)np, c->stream);
+        hipMemsetAsync(c->pb.hcnt, 0, 4 * (size_t)np, c->stream);
+    }
     if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "copy particles")) return s;
     set_stencil(*c, dmax);
     c->particles_set = true;
     c->stepped = false;
+    return PIBM_OK;
+}
+
+pibm_status pibm_set_rotation(pibm_ctx* c, const double* w) {
+    if (!c || !w) return PIBM_E_ARG;
+    if (c->cfg.contact != PIBM_CONTACT_HERTZ_MINDLIN) return fail(c, PIBM_E_CONFIG, "no rotation without Hertz-Mindlin contact");
+    if (c->np == 0) return PIBM_OK;
+    if (!c->particles_set || c->stepped) return fail(c, PIBM_E_STATE, "set the rotation right after the particles");
+    const int nw = spin_components(c->D), np = c->np;
+    std::vector<float> buf((size_t)nw * np);
+    for (size_t k = 0; k < buf.size(); k++) buf[k] = (float)w[k];
+    // before the first step the state is in id order
+    for (int a = 0; a < nw; a++)
+        hipMemcpyAsync(c->pb.A.w[a], buf.data() + (size_t)a * np, 4 * (size_t)np, hipMemcpyHostToDevice, c->stream);
+    return check_hip(c, hipStreamSynchronize(c->stream), "copy rotation");
+}
+
+pibm_status pibm_read_rotation(pibm_ctx* c, double* w) {
+    if (!c || !w) return PIBM_E_ARG;
+    if (c->cfg.contact != PIBM_CONTACT_HERTZ_MINDLIN) return fail(c, PIBM_E_CONFIG, "no rotation without Hertz-Mindlin contact");
+    if (c->np == 0) return PIBM_OK;
+    if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
+    const int nw = spin_components(c->D), np = c->np;
+    particles_unpermute_spin(c->D, c->pb, np, c->stage, c->stream);
+    std::vector<float> buf((size_t)nw * np);
+    if (pibm_status s = check_hip(c, hipMemcpyAsync(buf.data(), c->stage, buf.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy rotation")) return s;
+    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
+    for (size_t k = 0; k < buf.size(); k++) w[k] = buf[k];
     return PIBM_OK;
 }
 

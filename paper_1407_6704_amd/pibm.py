@@ -17,10 +17,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpibm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pibm.h")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 D2Q9, D3Q15, D3Q19 = 9, 15, 19
 STORE_FP32, STORE_FP16 = 0, 1
-CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3}
+CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3, "hertz_mindlin": 4}
 INTERP = {"delta": 0, "lagrange": 1}
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_CONFIG", 3: "E_HIP", 4: "E_STATE", 5: "E_UNSTABLE",
           6: "E_SKIN", 7: "E_CAPACITY"}
@@ -35,7 +35,7 @@ class Config(C.Structure):
         ("kn", C.c_double), ("restitution", C.c_double), ("k_soft", C.c_double),
         ("skin", C.c_double), ("two_way", C.c_int32), ("bin_log2", C.c_int32),
         ("max_candidates", C.c_int32), ("island_setup", C.c_int32), ("interp", C.c_int32),
-        ("young", C.c_double), ("poisson", C.c_double),
+        ("young", C.c_double), ("poisson", C.c_double), ("friction", C.c_double),
     ]
 
 
@@ -86,6 +86,8 @@ def load():
         "pibm_read_populations": ([vp, fp], C.c_int),
         "pibm_set_particles": ([vp, dp, dp, dp, dp], C.c_int),
         "pibm_read_particles": ([vp, dp, dp, dp, dp], C.c_int),
+        "pibm_set_rotation": ([vp, dp], C.c_int),
+        "pibm_read_rotation": ([vp, dp], C.c_int),
         "pibm_read_fields": ([vp, fp, fp], C.c_int),
         "pibm_read_force": ([vp, fp], C.c_int),
         "pibm_num_bins": ([vp], C.c_int64),
@@ -119,7 +121,7 @@ def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, pe
                 tau=0.8, rho0=1.0, gravity=(0.0, 0.0, 0.0), fluid_force=(0.0, 0.0, 0.0),
                 contact="lsd", n_sub=1, kn=1e3, restitution=0.9, k_soft=1e-3, skin=0.05,
                 two_way=1, bin_log2=0, max_candidates=16, island_setup=0, interp="delta", young=1e-3,
-                poisson=0.33) -> Config:
+                poisson=0.33, friction=0.33) -> Config:
     c = Config()
     c.abi_version = ABI_VERSION
     c.lattice = int(lattice)
@@ -137,7 +139,7 @@ def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, pe
     c.two_way, c.bin_log2, c.max_candidates = int(two_way), int(bin_log2), int(max_candidates)
     c.island_setup = int(island_setup)
     c.interp = INTERP[interp] if isinstance(interp, str) else int(interp)
-    c.young, c.poisson = float(young), float(poisson)
+    c.young, c.poisson, c.friction = float(young), float(poisson), float(friction)
     return c
 
 
@@ -232,6 +234,17 @@ class Sim:
         self._check(self.lib.pibm_read_particles(self.ctx, _dp(out["x"]), _dp(out["v"]),
                                                  _dp(out["f_hydro"]), _dp(out["f_contact"])))
         return out
+
+    def set_rotation(self, w):
+        """Angular velocities (3 x N in 3D, N in 2D), Hertz-Mindlin contact only,
+        right after set_particles."""
+        w = _f64(w).reshape(-1, self.np)
+        self._check(self.lib.pibm_set_rotation(self.ctx, _dp(w)))
+
+    def read_rotation(self):
+        w = np.empty((3 if self.D == 3 else 1, self.np))
+        self._check(self.lib.pibm_read_rotation(self.ctx, _dp(w)))
+        return w
 
     def read_fields(self):
         rho = np.empty(self.N, np.float32)

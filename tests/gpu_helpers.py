@@ -18,7 +18,8 @@ def oracle_cfg(orc, cfg):
         rho0=cfg.rho0, gravity=tuple(cfg.gravity), fluid_force=tuple(cfg.fluid_force),
         contact=cfg.contact, kn=cfg.kn, restitution=cfg.restitution, k_soft=cfg.k_soft,
         skin=cfg.skin, n_sub=cfg.n_sub, two_way=cfg.two_way, bin_log2=cfg.bin_log2,
-        interp="lagrange" if cfg.interp == 1 else "delta", young=cfg.young, poisson=cfg.poisson)
+        interp="lagrange" if cfg.interp == 1 else "delta", young=cfg.young, poisson=cfg.poisson,
+        friction=cfg.friction)
 
 
 def weights(orc, lattice):
