@@ -312,6 +312,9 @@ def main():
         # the paper's lattice and gather on the c2 particles
         r, _ = run_gpu(W.WORKLOADS["c2_d3q15"], args.extra_steps, 2, "c2_d3q15")
         extra["c2_d3q15_lagrange"] = r
+        # the paper's contact law on the c2 particles
+        r, _ = run_gpu(W.WORKLOADS["c2_hm"], args.extra_steps, 2, "c2_hm")
+        extra["c2_hertz_mindlin"] = r
         extra["c4_adjoint"] = run_adjoint(W.WORKLOADS["c4"])
         extra["fp16_vs_fp32"] = {
             "steps": args.extra_steps + 2,

@@ -147,7 +147,8 @@ def config_from_workload(w, **over) -> Config:
     kw = dict(lattice=w.lattice, n=w.n, storage=w.storage, fp16_scale_log2=w.fp16_scale_log2,
               tau=w.tau, gravity=w.gravity_vec(), contact=w.contact, n_sub=w.n_sub, kn=w.kn,
               restitution=w.restitution, k_soft=w.k_soft, skin=w.skin, two_way=w.two_way,
-              bin_log2=w.bin_log2, interp=getattr(w, "interp", "delta"))
+              bin_log2=w.bin_log2, interp=getattr(w, "interp", "delta"), young=w.young, poisson=w.poisson,
+              friction=w.friction)
     kw.update(over)
     return make_config(**kw)
 

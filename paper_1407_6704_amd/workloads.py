@@ -66,6 +66,9 @@ class Workload:
     bin_log2: int = 0                 # cell-list bins = dual cells
     two_way: int = 1
     interp: str = "delta"             # gather: "delta" (Eqs. lbm11-lbm12) | "lagrange" (Eqs. lbm5-lbm6)
+    young: float = 1e3                # Hertz contacts: Young's modulus (lattice units)
+    poisson: float = 0.33             # Hertz contacts: Poisson ratio (Table 1)
+    friction: float = 0.33            # Hertz-Mindlin: Coulomb coefficient (Table 1)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -95,11 +98,14 @@ C3 = C2.replace(name="c3", storage="fp16")          # same initial state as c2
 C3_CROP = C3.replace(name="c3_crop64", n=(64, 64, 64), n_particles=31_250, steps=100, seed=3)
 # c2 on the paper's own lattice and gather: D3Q15 with Lagrange polynomials (same particles)
 C2_D3Q15 = C2.replace(name="c2_d3q15", lattice=15, interp="lagrange")
+# c2 particles with the paper's contact law: Hertz normal and Mindlin tangential
+# forces with rotation (Table 1 Poisson ratio and friction)
+C2_HM = C2.replace(name="c2_hm", contact="hertz_mindlin")
 C4 = Workload("c4", 9, (512, 512, 1), 0.7, 10_000, ("const", 0.5), 2.5, (0.5, 1.0),
               contact="soft", n_sub=1, steps=2000, seed=4, gap=0.5, wall_clear=3.0)
 C4_FD = C4.replace(name="c4_fd", n=(64, 64, 1), n_particles=50, seed=40)
 
-WORKLOADS = {w.name: w for w in (C0, C1, C2, C3, C3_CROP, C2_D3Q15, C4, C4_FD)}
+WORKLOADS = {w.name: w for w in (C0, C1, C2, C3, C3_CROP, C2_D3Q15, C2_HM, C4, C4_FD)}
 
 
 def draw_diameters(rng, spec, n):
