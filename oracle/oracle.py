@@ -73,10 +73,10 @@ def lib():
             "orc_candidate_pairs": ([cp, C.c_int, d, d, i, C.c_int64], C.c_int64),
             "orc_candidate_pairs_brute": ([cp, C.c_int, d, d, i, C.c_int64], C.c_int64),
             "orc_dem": ([cp, C.c_int, d, d, d, d, d, d, C.c_int64, i, d, d, d], None),
-            "orc_dem_full": ([cp, C.c_int, d, d, d, d, d, d, d, C.c_int64, i, C.c_int64, i, d, i, d, d, d, d],
-                             C.c_int64),
-            "orc_step_full": ([cp, d, d, d, C.c_int, d, d, d, d, d, C.c_int64, i, d, i, d, i64, d, d, d, d],
-                              C.c_int),
+            "orc_dem_full": ([cp, C.c_int, d, d, d, d, d, i, d, d, C.c_int64, i, C.c_int64, i, d, i, d, d, d,
+                              d], C.c_int64),
+            "orc_step_full": ([cp, d, d, d, C.c_int, d, d, d, d, d, i, d, C.c_int64, i, d, i, d, i64, d, d, d,
+                               d], C.c_int),
             "orc_step": ([cp, d, d, d, C.c_int, d, d, d, d, d, d, d, d], C.c_int),
             "orc_fluid_totals": ([cp, d, d, d], None),
         }
@@ -290,10 +290,12 @@ def _hist_arrays(hist):
     return k, t, n
 
 
-def dem_hm(cfg, X, U, W, d, rho_p, rho_i, j_i, hist=None, pairs=None):
+def dem_hm(cfg, X, U, W, d, rho_p, rho_i, j_i, hist=None, pairs=None, fixed=None):
     """O4 with the Hertz-Mindlin contact and rotation (contact = 4) on
     copies; W is (3, np) (2D: the z row only is used).  hist = (keys (n, 2),
-    T (n, 3)) or None.  Returns (X', U', W', gbar, fc_mean, vmax, hist')."""
+    T (n, 3)) or None; fixed: np flags of fixed obstacle points or None.
+    Returns (X', U', W', gbar, fc_mean, vmax, hist').  Works for every
+    contact model (W and hist then stay unused)."""
     dim = D(cfg)
     X = _f64(X).copy()
     U = _f64(U).copy()
@@ -311,7 +313,9 @@ def dem_hm(cfg, X, U, W, d, rho_p, rho_i, j_i, hist=None, pairs=None):
     cap = len(pairs) + 6 * np_ + 1
     kout = np.zeros((cap, 2), np.int32)
     tout = np.zeros((cap, 3))
+    fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, np.int32))
     n = lib().orc_dem_full(C.byref(cfg), np_, _d(X), _d(U), _d(W), _d(_f64(d)), _d(_f64(rho_p)),
+                           None if fx is None else _i(fx),
                            _d(_f64(rho_i)), _d(j3), len(pairs), _i(pairs), hn, _i(kin), _d(tin),
                            _i(kout), _d(tout), _d(gbar), _d(fc), _d(vmax))
     return (X, U, W, gbar.reshape(3, np_)[:dim], fc.reshape(3, np_)[:dim], vmax,
@@ -321,13 +325,25 @@ def dem_hm(cfg, X, U, W, d, rho_p, rho_i, j_i, hist=None, pairs=None):
 def step_hm(cfg, f, X, U, W, d, rho_p, hist=None):
     """One coupled step with the Hertz-Mindlin contact and rotation; as
     step(), plus "W" and "hist" in the result."""
+    return step_full(cfg, f, X, U, d, rho_p, W=W, hist=hist)
+
+
+def step_full(cfg, f, X, U, d, rho_p, W=None, hist=None, fixed=None, area=None):
+    """One coupled step with every option: angular velocities W (3, np) and
+    the tangential history for the Hertz-Mindlin contact, and the points of
+    fixed obstacle bodies (fixed: np flags; area: np areas used for the
+    fixed points' spreading, None for pi d^2 / 4).  Returns step()'s dict
+    plus "W" and "hist"."""
     dim = D(cfg)
     N = nnodes(cfg)
     f = _f64(f)
     X = _f64(X).copy()
     U = _f64(U).copy()
     np_ = X.shape[-1]
-    W = np.ascontiguousarray(np.asarray(W, np.float64).reshape(3, np_)).copy()
+    W = np.zeros((3, np_)) if W is None else np.asarray(W, np.float64).reshape(3, np_)
+    W = np.ascontiguousarray(W).copy()
+    fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, np.int32))
+    ar = None if area is None else _f64(area)
     fout = np.zeros_like(f)
     F = np.zeros(dim * N)
     gbar = np.zeros(3 * np_)
@@ -340,7 +356,8 @@ def step_hm(cfg, f, X, U, W, d, rho_p, hist=None):
     tout = np.zeros((cap, 3))
     hout = np.zeros(1, np.int64)
     nskin = lib().orc_step_full(C.byref(cfg), _d(f), _d(fout), _d(F), np_, _d(X), _d(U), _d(W),
-                                _d(_f64(d)), _d(_f64(rho_p)), hn, _i(kin), _d(tin), _i(kout), _d(tout),
+                                _d(_f64(d)), _d(_f64(rho_p)), None if fx is None else _i(fx),
+                                None if ar is None else _d(ar), hn, _i(kin), _d(tin), _i(kout), _d(tout),
                                 hout.ctypes.data_as(C.POINTER(C.c_int64)), _d(gbar), _d(fc), _d(rho_i),
                                 _d(j_i))
     n = int(hout[0])

@@ -443,7 +443,7 @@ static double hertz_force(const orc_cfg *c, double rstar, double delta)
  * for strictly positive overlap; soft repulsion k_s (1 - r/r_c)^2; or the
  * Hertz force above. */
 static void pair_force(const orc_cfg *c, int D, const double *r, const double *du,
-                       double dp, double dq, double mp, double mq, double *Fout)
+                       double dp, double dq, double meff, double *Fout)
 {
     double dist2 = 0;
     for (int a = 0; a < D; a++) dist2 += r[a] * r[a];
@@ -455,7 +455,6 @@ static void pair_force(const orc_cfg *c, int D, const double *r, const double *d
         if (!(delta > 0.0)) return;
         double vn = 0;
         for (int a = 0; a < D; a++) vn += du[a] * r[a] / dist;
-        double meff = mp * mq / (mp + mq);
         double gam = 2.0 * orc_zeta(c->restitution) * sqrt(c->kn * meff);
         double mag = c->kn * delta - gam * vn;
         for (int a = 0; a < D; a++) Fout[a] = mag * r[a] / dist;
@@ -673,9 +672,20 @@ static int64_t hist_find(int64_t hn, const int *key, int p, int q)
  * pairs: candidate pairs at the start of the step (orc_candidate_pairs).
  * With contact = 4: W (3 x np, angular velocities) is updated, and the
  * tangential-force history (hn_in entries) is read and rewritten to
- * key_out / T_out (capacity npairs + 2 D np), returning the entry count. */
+ * key_out / T_out (capacity npairs + 2 D np), returning the entry count.
+ * fixed (nullable): points of fixed obstacle bodies (R26), which keep X,
+ * U = 0 and W = 0, exchange momentum with the fluid like any point (g with
+ * U = 0), act on moving particles with infinite mass, and feel neither the
+ * walls nor each other. */
+static double pair_meff(const int *fixed, int p, int q, const double *m)
+{
+    if (fixed && fixed[p]) return m[q];
+    if (fixed && fixed[q]) return m[p];
+    return m[p] * m[q] / (m[p] + m[q]);
+}
+
 int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, const double *d,
-                     const double *rho_p, const double *rho_i, const double *j_i,
+                     const double *rho_p, const int *fixed, const double *rho_i, const double *j_i,
                      int64_t npairs, const int *pairs, int64_t hn_in, const int *key_in,
                      const double *T_in, int *key_out, double *T_out,
                      double *gbar, double *fc_mean, double *vmax)
@@ -724,6 +734,7 @@ int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, 
                 Xp[a] = X[a * np + p];
                 Up[a] = U[a * np + p];
             }
+            if (fixed && fixed[p]) continue;
             if (!mind) {
                 wall_force(c, D, Xp, Up, d[p], m[p], Fw);
                 for (int a = 0; a < D; a++) Fc[3 * p + a] += Fw[a];
@@ -763,13 +774,14 @@ int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, 
         if (c->contact != 0)
             for (int64_t i = 0; i < npairs; i++) {
                 int p = pairs[2 * i], q = pairs[2 * i + 1];
+                if (fixed && fixed[p] && fixed[q]) continue;
                 double r[3] = {0, 0, 0}, du[3] = {0, 0, 0}, Fpq[3];
                 for (int a = 0; a < D; a++) {
                     r[a] = X[a * np + p] - X[a * np + q];
                     du[a] = U[a * np + p] - U[a * np + q];
                 }
                 if (!mind) {
-                    pair_force(c, D, r, du, d[p], d[q], m[p], m[q], Fpq);
+                    pair_force(c, D, r, du, d[p], d[q], pair_meff(fixed, p, q, m), Fpq);
                     for (int a = 0; a < D; a++) {
                         Fc[3 * p + a] += Fpq[a];
                         Fc[3 * q + a] -= Fpq[a];
@@ -815,6 +827,13 @@ int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, 
         for (int p = 0; p < np; p++) {
             double A = orc_area(d[p]);
             double s = 0;
+            if (fixed && fixed[p]) {
+                for (int a = 0; a < D; a++) {
+                    gbar[a * np + p] += g[3 * p + a];
+                    fc_mean[a * np + p] += Fc[3 * p + a];
+                }
+                continue;
+            }
             for (int a = 0; a < D; a++) {
                 double Wg = (1.0 - c->rho0 / rho_p[p]) * m[p] * c->gravity[a];
                 double Fh = -A * g[3 * p + a];
@@ -870,7 +889,7 @@ void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
              const double *rho_p, const double *rho_i, const double *j_i,
              int64_t npairs, const int *pairs, double *gbar, double *fc_mean, double *vmax)
 {
-    orc_dem_full(c, np, X, U, NULL, d, rho_p, rho_i, j_i, npairs, pairs, 0, NULL, NULL, NULL, NULL,
+    orc_dem_full(c, np, X, U, NULL, d, rho_p, NULL, rho_i, j_i, npairs, pairs, 0, NULL, NULL, NULL, NULL,
                  gbar, fc_mean, vmax);
 }
 
@@ -885,6 +904,7 @@ void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
  * the number of particles whose vmax exceeds skin/2 (the skin check). */
 int orc_step_full(const orc_cfg *c, const double *f, double *fout, double *F,
                   int np, double *X, double *U, double *W, const double *d, const double *rho_p,
+                  const int *fixed, const double *area,
                   int64_t hn_in, const int *key_in, const double *T_in, int *key_out, double *T_out,
                   int64_t *hn_out, double *gbar, double *fc_mean, double *rho_i_out, double *j_i_out)
 {
@@ -909,7 +929,7 @@ int orc_step_full(const orc_cfg *c, const double *f, double *fout, double *F,
         pairs = malloc(sizeof(int) * 2 * (npairs > 0 ? npairs : 1));
         orc_candidate_pairs(c, np, X0, d, pairs, npairs);
     }
-    int64_t hn = orc_dem_full(c, np, X, U, W, d, rho_p, rho_i, j_i, npairs, pairs, hn_in, key_in, T_in,
+    int64_t hn = orc_dem_full(c, np, X, U, W, d, rho_p, fixed, rho_i, j_i, npairs, pairs, hn_in, key_in, T_in,
                               key_out, T_out, gbar, fc_mean, vmax);
     if (hn_out) *hn_out = hn;
 
@@ -918,7 +938,11 @@ int orc_step_full(const orc_cfg *c, const double *f, double *fout, double *F,
     if (c->two_way && np > 0) {
         double *coef = malloc(sizeof(double) * 3 * npp);
         for (int p = 0; p < np; p++)
-            for (int a = 0; a < D; a++) coef[a * np + p] = orc_area(d[p]) * gbar[a * np + p];
+            for (int a = 0; a < D; a++) {
+                /* a fixed point may carry its own area (an IBM surface element, R26) */
+                double A = (fixed && fixed[p] && area) ? area[p] : orc_area(d[p]);
+                coef[a * np + p] = A * gbar[a * np + p];
+            }
         orc_spread(c, np, X0, coef, F);
         free(coef);
     }
@@ -950,7 +974,7 @@ int orc_step(const orc_cfg *c, const double *f, double *fout, double *F,
              int np, double *X, double *U, const double *d, const double *rho_p,
              double *gbar, double *fc_mean, double *rho_i_out, double *j_i_out)
 {
-    return orc_step_full(c, f, fout, F, np, X, U, NULL, d, rho_p, 0, NULL, NULL, NULL, NULL, NULL,
+    return orc_step_full(c, f, fout, F, np, X, U, NULL, d, rho_p, NULL, NULL, 0, NULL, NULL, NULL, NULL, NULL,
                          gbar, fc_mean, rho_i_out, j_i_out);
 }
 
