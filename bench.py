@@ -126,11 +126,16 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
     from paper_1407_6704_amd import pibm, workloads as W
 
     t0 = time.time()
-    X, U, d, rp = W.make_particles(w)
+    if w.obstacles:
+        X, U, d, rp, body, area = W.make_hybrid(w)
+    else:
+        X, U, d, rp = W.make_particles(w)
     print(f"[bench] {label}: placed {X.shape[1]} particles in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     cfg = pibm.config_from_workload(w)
     sim = pibm.Sim(cfg, X.shape[1])
     sim.set_particles(X, U, d, rp)
+    if w.obstacles:
+        sim.set_bodies(body, area)
     sim.step(warmup)
     sim.synchronize()
     sim.set_profiling(True)
@@ -152,6 +157,12 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
         status = e.name
     diag = sim.diagnostics()
     sim.set_profiling(False)
+    bodies = None
+    if w.obstacles:
+        nb = int(body.max()) + 1
+        bf = sim.read_bodies(nb)
+        bodies = {"points": int((body >= 0).sum()),
+                  "f_hydro": bf["f_hydro"].T.tolist(), "f_contact": bf["f_contact"].T.tolist()}
     fields = sim.read_fields() if keep_fields else None
     np_ = X.shape[1]
     res = {
@@ -162,6 +173,8 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
         "active_particles": diag["active"],
         "status": status,
     }
+    if bodies is not None:
+        res["bodies"] = bodies
     # dominant kernel: the single-launch lattice phase with the most time
     single = {k: v for k, v in res["phases_ms_per_step"].items() if k in ("collide", "moments", "spread")}
     dom = max(single, key=single.get)
@@ -315,6 +328,9 @@ def main():
         # the paper's contact law on the c2 particles
         r, _ = run_gpu(W.WORKLOADS["c2_hm"], args.extra_steps, 2, "c2_hm")
         extra["c2_hertz_mindlin"] = r
+        # the hybrid IBM-PIBM case: particles above fixed obstacle bodies
+        r, _ = run_gpu(W.WORKLOADS["hybrid"], args.extra_steps, 2, "hybrid")
+        extra["hybrid_obstacles"] = r
         extra["c4_adjoint"] = run_adjoint(W.WORKLOADS["c4"])
         extra["fp16_vs_fp32"] = {
             "steps": args.extra_steps + 2,

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define PIBM_ABI_VERSION 4
+#define PIBM_ABI_VERSION 5
 
 typedef enum {
     PIBM_OK = 0,
@@ -131,6 +131,8 @@ typedef struct {
                                  contact plane, capped at mu F_n, and carried between steps per
                                  pair of particle ids; spheres (disks) spin with I = 2/5 m R^2
                                  (1/2 m R^2) under the torque (-R n) x T.  No hydrodynamic torque */
+    int32_t bodies;           /* 1: particles may be made points of fixed obstacle bodies
+                                 (pibm_set_bodies); 0: all particles move */
 } pibm_config;
 
 typedef struct {
@@ -187,6 +189,27 @@ pibm_status pibm_read_particles(pibm_ctx* ctx, double* x, double* v, double* f_h
 pibm_status pibm_set_rotation(pibm_ctx* ctx, const double* w);
 pibm_status pibm_read_rotation(pibm_ctx* ctx, double* w);
 
+/* Fixed obstacle bodies (the hybrid IBM-PIBM case of Sec. 3.3; needs
+ * cfg.bodies = 1).  body (N int32, host): -1 for a moving particle, else
+ * the index (0 .. n_bodies-1) of the fixed body the point belongs to.  area
+ * (N doubles, host, may be NULL): the area a fixed point spreads with, e.g.
+ * a conventional-IBM surface element (sphere area / point count); NULL or a
+ * value <= 0 means pi d^2 / 4.  Fixed points keep their position, have zero
+ * velocity and spin, exchange momentum with the fluid with U = 0
+ * (Eqs. lbm7-lbm8, g = -2 j_i), and act on moving particles as contact
+ * partners of infinite mass at rest; they feel neither walls nor each
+ * other.  Call after pibm_set_particles and before the first step
+ * (PIBM_E_STATE otherwise); pibm_set_particles makes every particle move
+ * again. */
+pibm_status pibm_set_bodies(pibm_ctx* ctx, const int32_t* body, const double* area);
+/* Per body, from the last step (host FP64 arrays of 3 x n_bodies, any may be
+ * NULL; z is zero in 2D): f_hydro = sum over the body's points of
+ * -A_l mean(g_l) (Eq. lbm13), f_contact = sum of the contact reactions from
+ * moving particles, torque of both about the centroid of the body's points
+ * (in 2D only its z component is set).  Sums in id order, deterministic. */
+pibm_status pibm_read_bodies(pibm_ctx* ctx, int32_t n_bodies, double* f_hydro, double* f_contact,
+                             double* torque);
+
 /* Density (N) and velocity u = j / rho (D x N) of the stored populations. */
 pibm_status pibm_read_fields(pibm_ctx* ctx, float* rho, float* u);
 /* Force field F (D x N) used by the last collision (spread + fluid_force). */
@@ -228,7 +251,7 @@ pibm_status pibm_diagnostics(pibm_ctx* ctx, pibm_diag* out);
  * of every operation of the step (collision and streaming, spreading,
  * momentum exchange, particle update, interpolation, moments), in FP32 with
  * double-float sums of the parameter gradients.
- * Supported: D2Q9 or D3Q19, delta-kernel interpolation, n_sub = 1 (the
+ * Supported: D2Q9 or D3Q19, no fixed bodies, delta-kernel interpolation, n_sub = 1 (the
  * explicit update of Eq. demgov), contact NONE or SOFT, bin_log2 = 0, FP32
  * or FP16 storage; other configurations return
  * PIBM_E_CONFIG.  Memory stays bounded by checkpointing: the state is saved

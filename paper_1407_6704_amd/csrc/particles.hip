@@ -261,6 +261,7 @@ __global__ __launch_bounds__(256) void k_reorder(PState A, PState B, const uint3
 #pragma unroll
     for (int a = 0; a < 3; a++)
         if (A.w[a]) B.w[a][o] = A.w[a][s];
+    if (A.fixa) B.fixa[o] = A.fixa[s];
     keys_sorted[o] = k;
     // leading parts of the position and the diameter, for neighbour screening
     pos4[o] = make_float4(A.xh[0][s], A.xh[1][s], D == 3 ? A.xh[2][s] : 0.f, A.d[s]);
@@ -539,7 +540,9 @@ __device__ __forceinline__ int scan_neighbours(const float4* __restrict__ pos4, 
                                                const uint32_t* __restrict__ keys_sorted,
                                                const PCfg& c, int s, float thr, bool& close,
                                                const unsigned long long* __restrict__ actcc, uint32_t* list,
-                                               int cap) {
+                                               int cap, const float* __restrict__ fixa) {
+    // points of fixed bodies do not interact with each other
+    const bool mefix = fixa && fixa[s] > 0.f;
     // Screening uses the leading FP32 parts of the positions; c.eps bounds
     // the neglected trailing parts, and every test is widened by it (more
     // candidates or more active particles only cost time).
@@ -563,6 +566,7 @@ __device__ __forceinline__ int scan_neighbours(const float4* __restrict__ pos4, 
             uint32_t t0 = start[row + bxl], t1 = start[row + bxh + 1];
             for (uint32_t t = t0; t < t1; t++) {
                 if ((int)t == s) continue;
+                if (mefix && fixa[t] > 0.f) continue;
                 const float4 o = pos4[t];
                 float dx = me.x - o.x, dy = me.y - o.y, dz = (D == 3) ? me.z - o.z : 0.f;
                 float r2 = dx * dx + dy * dy + dz * dz;
@@ -620,7 +624,8 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
         float ri = 1.0f + drho_i[s];
         float cc = 2.0f * Ap * ri / m;
         float hc = cc * c.h;
-        if (!(hc < 2.0f)) atomicOr(flags, FLAG_UNSTABLE);   // explicit drag diverges
+        const bool fixedp = A.fixa && A.fixa[s] > 0.f;     // a point of a fixed body
+        if (!(hc < 2.0f) && !fixedp) atomicOr(flags, FLAG_UNSTABLE);   // explicit drag diverges
         float qn, omq;                       // q^n, 1 - q^n
         drag_power(hc, c.n_sub, qn, omq);
         float geo = omq / hc;                // sum_{k<n} q^k
@@ -643,19 +648,31 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
             ves += ueq * ueq;
             dvs += (u0 - ueq) * (u0 - ueq);
         }
+        if (fixedp) {
+            // at rest: g = 2 (rho_i 0 - j_i) at every sub-step, spread with the point's own area
+#pragma unroll
+            for (int a = 0; a < D; a++) {
+                un[a] = 0.f;
+                dx[a] = 0.f;
+                gb[a] = -2.0f * j_i[(long long)a * np + s];
+            }
+            v0s = vns = ves = dvs = 0.f;
+            Ap = A.fixa[s];
+        }
         // q > 0: U^k moves along the segment from U^0 to U^n; q < 0: it
         // alternates around U_eq within |U^0 - U_eq|
         float B = (q > 0.f) ? sqrtf(fmaxf(v0s, vns)) : sqrtf(ves) + sqrtf(dvs);
         if (c.contact != PIBM_CONTACT_NONE) {
             bool close = false;
             int cnt = scan_neighbours<D, false>(pos4, start, keys_sorted, c, s, B + 0.5f * c.skin, close, nullptr,
-                                               nullptr, 0);
+                                               nullptr, 0, A.fixa);
             bool wall = false;
 #pragma unroll
             for (int a = 0; a < D; a++) {
                 float x = A.xh[a][s] + A.xl[a][s];
                 wall = wall || (x - 0.5f * d <= B) || (((float)c.n[a] - x) - 0.5f * d <= B);
             }
+            wall = wall && !fixedp;                         // fixed points feel no wall
             if (close || wall) {
                 if (cnt > c.maxc) atomicOr(flags, FLAG_CAPACITY);
                 active = true;
@@ -720,7 +737,9 @@ __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const
     isize[a] = 0;
     fill[a] = 0;
     bool dummy = false;
-    int n = cap > 0 ? scan_neighbours<D, true>(pos4, start, keys_sorted, c, s, 0.f, dummy, actcc, cand + off, cap) : 0;
+    int n = cap > 0 ? scan_neighbours<D, true>(pos4, start, keys_sorted, c, s, 0.f, dummy, actcc, cand + off, cap,
+                                               A.fixa)
+                    : 0;
     ccount[s] = (uint32_t)min(n, cap);
 }
 
@@ -945,6 +964,10 @@ __device__ __forceinline__ void cand_prep_one(uint32_t a, const PState& A, const
         } else {
             float mt = particle_mass(D, A.d[t], A.rp[t]);
             float meff = ms * mt / (ms + mt);
+            if (A.fixa) {                            // a fixed partner has infinite mass
+                if (A.fixa[t] > 0.f) meff = ms;
+                else if (A.fixa[s] > 0.f) meff = mt;
+            }
             cd.gam = 2.0f * c.zeta * sqrtf(c.kn * meff);
         }
         cdata[off + k] = cd;
@@ -1055,6 +1078,9 @@ struct Active {
     uint32_t wside;
     float I, R;
     int id;
+    // a point of a fixed body: never moves, spreads with its own area Af
+    bool fixed;
+    float Af;
 };
 
 __device__ __forceinline__ void cross3(const float* x, const float* y, float* z) {
@@ -1136,6 +1162,17 @@ __device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const
     P.vmax2 = v2;
     P.off = (uint32_t)(prefix[s] & 0xffffffffULL);
     P.cnt = c.contact != PIBM_CONTACT_NONE ? (int)ccount[s] : 0;
+    P.fixed = A.fixa && A.fixa[s] > 0.f;
+    P.Af = P.fixed ? A.fixa[s] : P.Ap;
+    if (P.fixed) {
+        // at rest for good: no wall, no drift, no contact-free motion
+        P.wall = false;
+        P.hc = 0.f;
+        P.veq = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; a++) P.ueq[a] = P.slip[a] = P.u[a] = 0.f;
+        P.vmax2 = 0.f;
+    }
     if (MD) {
         P.R = 0.5f * P.d;
         P.I = (D == 3 ? 0.4f : 0.5f) * P.m * P.R * P.R;
@@ -1349,6 +1386,15 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
             pair_force<D>(P, cd, odx, ou, c, F);
         }
     }
+    if (P.fixed) {
+        // a fixed point keeps its state; g = -2 j_i with U = 0, contact reactions summed
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            P.gs[a] += -2.0f * P.j[a];
+            P.fs[a] += F[a];
+        }
+        return;
+    }
     if (MD) {
         // I dW/dt = torque (second line of Eq. demgov)
 #pragma unroll
@@ -1387,7 +1433,7 @@ __device__ __forceinline__ void active_store(const Active<D>& P, PState& Bn, con
         Bn.xh[a][s] = xh;
         Bn.xl[a][s] = xl;
         Bn.u[a][s] = P.u[a];
-        coef[(long long)a * np + s] = P.Ap * (P.gs[a] * invn);
+        coef[(long long)a * np + s] = P.Af * (P.gs[a] * invn);
         fc[(long long)a * np + s] = P.fs[a] * invn;
     }
     if (sqrtf(P.vmax2) > 0.5f * c.skin) atomicOr(flags, FLAG_SKIN);
@@ -1490,6 +1536,11 @@ __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m, 
             const float4 q = md.cmd[P.off + k];
             if (q.x != 0.f || q.y != 0.f || q.z != 0.f) md.cmd[P.off + k] = make_float4(0.f, 0.f, 0.f, q.w);
         }
+    }
+    if (P.fixed) {
+#pragma unroll
+        for (int a = 0; a < D; a++) P.gs[a] += (float)m * (-2.0f * P.j[a]);
+        return;
     }
     const float mm = (float)m;
     float qm, omq;

@@ -151,6 +151,7 @@ struct PState {
     float* xl[3];
     float* u[3];
     float* w[3];        // angular velocity (Hertz-Mindlin only, else null): x, y, z in 3D; z in 2D
+    float* fixa;        // fixed obstacle points (bodies only, else null): their area; 0 for moving ones
     float* d;
     float* rp;
     int* id;

@@ -108,6 +108,8 @@ struct pibm_ctx {
     // every few steps; selects the single-workgroup island set-up
     uint32_t* host_active = nullptr;
     uint64_t steps_done = 0;
+    // fixed obstacle bodies: the body of each particle id (-1: moving)
+    std::vector<int> body_of;
     ~pibm_ctx() {
         for (hipEvent_t e : ev) hipEventDestroy(e);
         if (host_active) hipHostFree(host_active);
@@ -165,6 +167,7 @@ std::string validate(const pibm_config* cfg, int64_t np) {
         (!(cfg->young > 0) || !(cfg->poisson >= 0) || !(cfg->poisson < 0.5)))
         return "Hertz contact needs young > 0 and 0 <= poisson < 1/2";
     if (cfg->contact == PIBM_CONTACT_HERTZ_MINDLIN && !(cfg->friction >= 0)) return "friction must be >= 0";
+    if (cfg->bodies != 0 && cfg->bodies != 1) return "bodies must be 0 or 1";
     if (cfg->bin_log2 < 0 || cfg->bin_log2 > 3) return "bin_log2 must be 0..3";
     if (cfg->max_candidates < 1 || cfg->max_candidates > 64) return "max_candidates must be 1..64";
     if (cfg->island_setup < 0 || cfg->island_setup > 2) return "island_setup must be 0, 1 or 2";
@@ -209,6 +212,7 @@ size_t carve(pibm_ctx& c, char* base) {
             S[k]->d = k < 2 ? cv.take<float>(np) : nullptr;
             S[k]->rp = k < 2 ? cv.take<float>(np) : nullptr;
             S[k]->id = k < 2 ? cv.take<int>(np) : nullptr;
+            S[k]->fixa = (k < 2 && c.cfg.bodies) ? cv.take<float>(np) : nullptr;
         }
         long long nb1 = c.pc.nbins + 1;
         b.cnt = cv.take<uint32_t>(nb1);
@@ -318,6 +322,7 @@ std::string adjoint_unsupported(const pibm_ctx& c) {
         return "the adjoint supports no contact or soft contact only";
     if (c.cfg.bin_log2 != 0) return "the adjoint needs bin_log2 = 0";
     if (c.cfg.lattice == PIBM_D3Q15) return "the adjoint supports D2Q9 and D3Q19 only";
+    if (c.cfg.bodies) return "the adjoint supports no fixed bodies";
     if (c.cfg.interp != PIBM_INTERP_DELTA) return "the adjoint supports delta-kernel interpolation only";
     return "";
 }
@@ -554,6 +559,8 @@ pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, co
     hipMemcpyAsync(A.d, dd, 4 * np, hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(A.rp, rp, 4 * np, hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(A.id, id, 4 * np, hipMemcpyHostToDevice, c->stream);
+    if (A.fixa) hipMemsetAsync(A.fixa, 0, 4 * (size_t)np, c->stream);   // every particle moves
+    c->body_of.assign(np, -1);
     if (c->pb.hcnt) {
         // at rest, no tangential-force history
         for (int a = 0; a < spin_components(D); a++) hipMemsetAsync(A.w[a], 0, 4 * (size_t)np, c->stream);
@@ -578,6 +585,82 @@ pibm_status pibm_set_rotation(pibm_ctx* c, const double* w) {
     for (int a = 0; a < nw; a++)
         hipMemcpyAsync(c->pb.A.w[a], buf.data() + (size_t)a * np, 4 * (size_t)np, hipMemcpyHostToDevice, c->stream);
     return check_hip(c, hipStreamSynchronize(c->stream), "copy rotation");
+}
+
+pibm_status pibm_set_bodies(pibm_ctx* c, const int32_t* body, const double* area) {
+    if (!c || !body) return PIBM_E_ARG;
+    if (!c->cfg.bodies) return fail(c, PIBM_E_CONFIG, "fixed bodies need cfg.bodies = 1");
+    if (c->np == 0) return PIBM_OK;
+    if (!c->particles_set || c->stepped) return fail(c, PIBM_E_STATE, "set the bodies right after the particles");
+    const int D = c->D, np = c->np;
+    // before the first step the state is in id order
+    std::vector<float> d(np), fa(np, 0.0f), u((size_t)D * np);
+    hipMemcpyAsync(d.data(), c->pb.A.d, 4 * (size_t)np, hipMemcpyDeviceToHost, c->stream);
+    for (int a = 0; a < D; a++)
+        hipMemcpyAsync(u.data() + (size_t)a * np, c->pb.A.u[a], 4 * (size_t)np, hipMemcpyDeviceToHost, c->stream);
+    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "read particles")) return s;
+    for (int i = 0; i < np; i++) {
+        if (body[i] < -1) return fail(c, PIBM_E_ARG, "body index must be >= -1");
+        if (body[i] < 0) continue;
+        const double ar = (area && area[i] > 0) ? area[i] : 0.25 * M_PI * (double)d[i] * d[i];
+        fa[i] = (float)ar;
+        for (int a = 0; a < D; a++) u[(size_t)a * np + i] = 0.0f;      // fixed points are at rest
+    }
+    hipMemcpyAsync(c->pb.A.fixa, fa.data(), 4 * (size_t)np, hipMemcpyHostToDevice, c->stream);
+    for (int a = 0; a < D; a++)
+        hipMemcpyAsync(c->pb.A.u[a], u.data() + (size_t)a * np, 4 * (size_t)np, hipMemcpyHostToDevice, c->stream);
+    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "copy bodies")) return s;
+    c->body_of.assign(body, body + np);
+    return PIBM_OK;
+}
+
+pibm_status pibm_read_bodies(pibm_ctx* c, int32_t n_bodies, double* f_hydro, double* f_contact, double* torque) {
+    if (!c || n_bodies < 0) return PIBM_E_ARG;
+    if (!c->cfg.bodies) return fail(c, PIBM_E_CONFIG, "fixed bodies need cfg.bodies = 1");
+    for (int32_t b = 0; b < 3 * n_bodies; b++) {
+        if (f_hydro) f_hydro[b] = 0.0;
+        if (f_contact) f_contact[b] = 0.0;
+        if (torque) torque[b] = 0.0;
+    }
+    if (c->np == 0 || n_bodies == 0) return PIBM_OK;
+    if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
+    const int D = c->D, np = c->np;
+    particles_unpermute(D, c->pb, np, c->stepped, c->stage, c->stream);
+    std::vector<float> buf((size_t)5 * D * np);
+    if (pibm_status s = check_hip(c, hipMemcpyAsync(buf.data(), c->stage, buf.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy particles")) return s;
+    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
+    // centroids, then forces and torques, summed in id order in FP64
+    std::vector<double> cen((size_t)3 * n_bodies, 0.0), cnt(n_bodies, 0.0);
+    auto pos = [&](int a, int i) { return (double)buf[(size_t)a * np + i] + (double)buf[(size_t)(D + a) * np + i]; };
+    for (int i = 0; i < np; i++) {
+        const int b = c->body_of[i];
+        if (b < 0 || b >= n_bodies) continue;
+        cnt[b] += 1.0;
+        for (int a = 0; a < D; a++) cen[3 * b + a] += pos(a, i);
+    }
+    for (int b = 0; b < n_bodies; b++)
+        for (int a = 0; a < 3; a++) cen[3 * b + a] = cnt[b] > 0 ? cen[3 * b + a] / cnt[b] : 0.0;
+    for (int i = 0; i < np; i++) {
+        const int b = c->body_of[i];
+        if (b < 0 || b >= n_bodies) continue;
+        double fh[3] = {0, 0, 0}, fcn[3] = {0, 0, 0}, r[3] = {0, 0, 0};
+        for (int a = 0; a < D; a++) {
+            fh[a] = buf[(size_t)(3 * D + a) * np + i];
+            fcn[a] = buf[(size_t)(4 * D + a) * np + i];
+            r[a] = pos(a, i) - cen[3 * b + a];
+        }
+        const double ft[3] = {fh[0] + fcn[0], fh[1] + fcn[1], fh[2] + fcn[2]};
+        for (int a = 0; a < 3; a++) {
+            if (f_hydro) f_hydro[3 * b + a] += fh[a];
+            if (f_contact) f_contact[3 * b + a] += fcn[a];
+        }
+        if (torque) {
+            torque[3 * b + 0] += D == 3 ? r[1] * ft[2] - r[2] * ft[1] : 0.0;
+            torque[3 * b + 1] += D == 3 ? r[2] * ft[0] - r[0] * ft[2] : 0.0;
+            torque[3 * b + 2] += r[0] * ft[1] - r[1] * ft[0];
+        }
+    }
+    return PIBM_OK;
 }
 
 pibm_status pibm_read_rotation(pibm_ctx* c, double* w) {

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpibm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pibm.h")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 D2Q9, D3Q15, D3Q19 = 9, 15, 19
 STORE_FP32, STORE_FP16 = 0, 1
 CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3, "hertz_mindlin": 4}
@@ -35,7 +35,7 @@ class Config(C.Structure):
         ("kn", C.c_double), ("restitution", C.c_double), ("k_soft", C.c_double),
         ("skin", C.c_double), ("two_way", C.c_int32), ("bin_log2", C.c_int32),
         ("max_candidates", C.c_int32), ("island_setup", C.c_int32), ("interp", C.c_int32),
-        ("young", C.c_double), ("poisson", C.c_double), ("friction", C.c_double),
+        ("young", C.c_double), ("poisson", C.c_double), ("friction", C.c_double), ("bodies", C.c_int32),
     ]
 
 
@@ -87,6 +87,8 @@ def load():
         "pibm_set_particles": ([vp, dp, dp, dp, dp], C.c_int),
         "pibm_read_particles": ([vp, dp, dp, dp, dp], C.c_int),
         "pibm_set_rotation": ([vp, dp], C.c_int),
+        "pibm_set_bodies": ([vp, C.POINTER(C.c_int32), dp], C.c_int),
+        "pibm_read_bodies": ([vp, C.c_int32, dp, dp, dp], C.c_int),
         "pibm_read_rotation": ([vp, dp], C.c_int),
         "pibm_read_fields": ([vp, fp, fp], C.c_int),
         "pibm_read_force": ([vp, fp], C.c_int),
@@ -121,7 +123,7 @@ def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, pe
                 tau=0.8, rho0=1.0, gravity=(0.0, 0.0, 0.0), fluid_force=(0.0, 0.0, 0.0),
                 contact="lsd", n_sub=1, kn=1e3, restitution=0.9, k_soft=1e-3, skin=0.05,
                 two_way=1, bin_log2=0, max_candidates=16, island_setup=0, interp="delta", young=1e-3,
-                poisson=0.33, friction=0.33) -> Config:
+                poisson=0.33, friction=0.33, bodies=0) -> Config:
     c = Config()
     c.abi_version = ABI_VERSION
     c.lattice = int(lattice)
@@ -140,6 +142,7 @@ def make_config(lattice=9, n=(16, 16, 1), storage="fp32", fp16_scale_log2=14, pe
     c.island_setup = int(island_setup)
     c.interp = INTERP[interp] if isinstance(interp, str) else int(interp)
     c.young, c.poisson, c.friction = float(young), float(poisson), float(friction)
+    c.bodies = int(bodies)
     return c
 
 
@@ -148,7 +151,7 @@ def config_from_workload(w, **over) -> Config:
               tau=w.tau, gravity=w.gravity_vec(), contact=w.contact, n_sub=w.n_sub, kn=w.kn,
               restitution=w.restitution, k_soft=w.k_soft, skin=w.skin, two_way=w.two_way,
               bin_log2=w.bin_log2, interp=getattr(w, "interp", "delta"), young=w.young, poisson=w.poisson,
-              friction=w.friction)
+              friction=w.friction, bodies=int(w.obstacles))
     kw.update(over)
     return make_config(**kw)
 
@@ -241,6 +244,22 @@ class Sim:
         right after set_particles."""
         w = _f64(w).reshape(-1, self.np)
         self._check(self.lib.pibm_set_rotation(self.ctx, _dp(w)))
+
+    def set_bodies(self, body, area=None):
+        """Make particles points of fixed obstacle bodies (body index >= 0; -1
+        moves); area: the area each fixed point spreads with (None: pi d^2/4).
+        Needs make_config(bodies=1); right after set_particles."""
+        body = np.ascontiguousarray(body, np.int32)
+        self._check(self.lib.pibm_set_bodies(self.ctx, body.ctypes.data_as(C.POINTER(C.c_int32)),
+                                             _dp(_f64(area)) if area is not None else None))
+
+    def read_bodies(self, n_bodies):
+        """Per body: hydrodynamic and contact force, torque about the centroid
+        of its points (each 3 x n_bodies), from the last step."""
+        out = {k: np.zeros((n_bodies, 3)) for k in ("f_hydro", "f_contact", "torque")}
+        self._check(self.lib.pibm_read_bodies(self.ctx, int(n_bodies), _dp(out["f_hydro"]), _dp(out["f_contact"]),
+                                              _dp(out["torque"])))
+        return {k: v.T.copy() for k, v in out.items()}
 
     def read_rotation(self):
         w = np.empty((3 if self.D == 3 else 1, self.np))

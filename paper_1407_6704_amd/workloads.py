@@ -18,6 +18,10 @@ keep that structure at larger scale:
       state (and a 64^3 crop with the same number density, 31,250 spheres)
   c4  D2Q9 512^2, tau 0.7, 10k disks d = 0.5, ratio 2.5, soft repulsion,
       dilute (gaps >= d, >= 3 from walls), objective = mean height
+  hybrid  the hybrid IBM-PIBM case of Sec. 3.3 at scale: c2's particle
+      statistics in a 128^3 cavity (250k spheres in the upper half) above
+      five fixed obstacles (make_hybrid): four spheres of radius 10 made of
+      conventional-IBM surface points and a cube of 27 fixed PIBM points
 
 Gravity is 1e-5 lattice units along -y (2D) or -z (3D).  The candidate-list
 skin is 0.01: a particle may move at most skin/2 per step, 100 times the
@@ -69,6 +73,7 @@ class Workload:
     young: float = 1e3                # Hertz contacts: Young's modulus (lattice units)
     poisson: float = 0.33             # Hertz contacts: Poisson ratio (Table 1)
     friction: float = 0.33            # Hertz-Mindlin: Coulomb coefficient (Table 1)
+    obstacles: bool = False           # fixed obstacle bodies below the particles (make_hybrid)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -101,11 +106,12 @@ C2_D3Q15 = C2.replace(name="c2_d3q15", lattice=15, interp="lagrange")
 # c2 particles with the paper's contact law: Hertz normal and Mindlin tangential
 # forces with rotation (Table 1 Poisson ratio and friction)
 C2_HM = C2.replace(name="c2_hm", contact="hertz_mindlin")
+HYBRID = C2.replace(name="hybrid", n=(128, 128, 128), n_particles=250_000, steps=200, seed=6, obstacles=True)
 C4 = Workload("c4", 9, (512, 512, 1), 0.7, 10_000, ("const", 0.5), 2.5, (0.5, 1.0),
               contact="soft", n_sub=1, steps=2000, seed=4, gap=0.5, wall_clear=3.0)
 C4_FD = C4.replace(name="c4_fd", n=(64, 64, 1), n_particles=50, seed=40)
 
-WORKLOADS = {w.name: w for w in (C0, C1, C2, C3, C3_CROP, C2_D3Q15, C2_HM, C4, C4_FD)}
+WORKLOADS = {w.name: w for w in (C0, C1, C2, C3, C3_CROP, C2_D3Q15, C2_HM, HYBRID, C4, C4_FD)}
 
 
 def draw_diameters(rng, spec, n):
@@ -198,6 +204,52 @@ def make_particles(w: Workload, seed: int | None = None):
     U = np.zeros_like(X)
     rho_p = np.full(d.shape, float(w.density_ratio))
     return X, U, d, rho_p
+
+
+def sphere_points(k: int):
+    """k nearly uniform unit vectors (Fibonacci sphere), (3, k)."""
+    t = np.arange(k) + 0.5
+    z = 1.0 - 2.0 * t / k
+    phi = np.pi * (1.0 + 5.0 ** 0.5) * t
+    r = np.sqrt(1.0 - z * z)
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z])
+
+
+def make_hybrid(w: Workload, radius: float = 10.0, spacing: float = 0.8, cube_spacing: float = 1.0,
+                cube_d: float = 1.0):
+    """The moving particles of w (upper part) plus five fixed obstacles at a
+    quarter of the height: four spheres of the given radius, each k surface
+    points about `spacing` apart (contact diameter = spacing, area = the
+    sphere's area / k), centred over the quarters of the floor, and a
+    3 x 3 x 3 cube of PIBM points (diameter cube_d, area pi d^2/4) in the
+    middle.  Returns X, U, d, rho_p, body (-1: moving; 0..3 spheres, 4 the
+    cube), area (0 for the moving particles and the cube's points: pi d^2/4).
+    Obstacle points come first."""
+    Xm, Um, dm, rpm = make_particles(w)
+    n = [float(v) for v in w.n]
+    zc = 0.25 * n[2]
+    k = int(round(4.0 * np.pi * radius * radius / (spacing * spacing)))
+    S = sphere_points(k)
+    pts, body, dd, area = [], [], [], []
+    for b, (fx, fy) in enumerate([(0.25, 0.25), (0.75, 0.25), (0.25, 0.75), (0.75, 0.75)]):
+        c = np.array([fx * n[0], fy * n[1], zc])
+        pts.append(c[:, None] + radius * S)
+        body += [b] * k
+        dd += [spacing] * k
+        area += [4.0 * np.pi * radius * radius / k] * k
+    g = (np.arange(3) - 1.0) * cube_spacing
+    cube = np.stack(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1) + np.array([0.5 * n[0], 0.5 * n[1], zc])[:, None]
+    pts.append(cube)
+    body += [4] * 27
+    dd += [cube_d] * 27
+    area += [0.0] * 27
+    Xf = np.concatenate(pts, axis=1).astype(np.float32).astype(np.float64)
+    nf = Xf.shape[1]
+    X = np.concatenate([Xf, Xm], axis=1)
+    U = np.concatenate([np.zeros((3, nf)), Um], axis=1)
+    d = np.concatenate([np.array(dd, np.float32).astype(np.float64), dm])
+    rp = np.concatenate([np.ones(nf), rpm])
+    return X, U, d, rp, np.array(body + [-1] * Xm.shape[1], np.int32), np.concatenate([np.array(area), np.zeros(Xm.shape[1])])
 
 
 def perturbed_fluid(w: Workload, seed: int, amp: float = 1e-3):
