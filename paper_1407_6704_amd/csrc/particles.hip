@@ -87,6 +87,27 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T& total) {
     return before + inc - v;
 }
 
+// Largest number of blocks for which every block adds up the totals of the
+// blocks before it itself (the sum costs O(blocks^2) reads over the grid).
+constexpr long long RAW_MAX_BLOCKS = 2048;
+
+// Sum of x[0, n) over one block of NT threads, returned to every thread
+// (sh: NT / 64 entries of LDS).  Integer sums: exact in any order.
+template <class T, int NT>
+__device__ __forceinline__ T block_sum(const T* __restrict__ x, long long n, T* sh) {
+    T s = 0;
+    for (long long i = threadIdx.x; i < n; i += NT) s += x[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    T t = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; k++) t += sh[k];
+    __syncthreads();
+    return t;
+}
+
 // Items [base, base + SCAN_ITEMS) of `in`, zero past n; full tiles are read
 // with 16-byte loads (the arrays are 256-byte aligned, base a multiple of 16).
 template <class T>
@@ -144,11 +165,14 @@ __global__ __launch_bounds__(TOP_THREADS) void k_scan_top(T* __restrict__ bsum, 
 }
 
 // With zero_in the input is cleared after it has been read (the bin counts
-// then start from zero at the next sort without a separate fill).
-template <class T>
+// then start from zero at the next sort without a separate fill).  With RAW
+// the tile sums in bsum are not scanned yet: each block adds up those of
+// the tiles before it itself (no one-block pass in between).
+template <class T, bool RAW>
 __global__ __launch_bounds__(256) void k_scan_down(T* __restrict__ in, T* __restrict__ out, long long n,
                                                    const T* __restrict__ bsum, int zero_in) {
     __shared__ T sh4[4];
+    const T before = RAW ? block_sum<T, 256>(bsum, (long long)blockIdx.x, sh4) : bsum[blockIdx.x];
     const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
     T v[SCAN_ITEMS];
     load_items<T>(in, base, n, v);
@@ -166,7 +190,7 @@ __global__ __launch_bounds__(256) void k_scan_down(T* __restrict__ in, T* __rest
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; k++) s += v[k];
     T tot;
-    T ex = block_exclusive_scan<T>(s, sh4, tot) + bsum[blockIdx.x];
+    T ex = block_exclusive_scan<T>(s, sh4, tot) + before;
     if (base + SCAN_ITEMS <= n) {
         constexpr int PER = 16 / sizeof(T);
         uint4* p = reinterpret_cast<uint4*>(out + base);
@@ -193,13 +217,22 @@ __global__ __launch_bounds__(256) void k_scan_down(T* __restrict__ in, T* __rest
 
 // Exclusive scan of in[0, n) into out; the input is cleared afterwards when
 // zero_in is set.
+// Without a total, two passes (tile sums, then tiles adding up their
+// predecessors' sums themselves); with one, three (the tile sums scanned by
+// one block, which also writes the total).
 template <class T>
 void scan_exclusive(T* in, T* out, long long n, T* bsum, T* total, bool zero_in, hipStream_t s) {
     long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL((k_scan_reduce<T>), dim3((unsigned)nb), dim3(256), 0, s, in, n, bsum);
-    hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(TOP_THREADS), 0, s, bsum, nb, total);
-    hipLaunchKernelGGL((k_scan_down<T>), dim3((unsigned)nb), dim3(256), 0, s, in, out, n, bsum, zero_in ? 1 : 0);
+    if (total || nb > 2 * RAW_MAX_BLOCKS) {
+        hipLaunchKernelGGL((k_scan_top<T>), dim3(1), dim3(TOP_THREADS), 0, s, bsum, nb, total);
+        hipLaunchKernelGGL((k_scan_down<T, false>), dim3((unsigned)nb), dim3(256), 0, s, in, out, n, bsum,
+                           zero_in ? 1 : 0);
+    } else {
+        hipLaunchKernelGGL((k_scan_down<T, true>), dim3((unsigned)nb), dim3(256), 0, s, in, out, n, bsum,
+                           zero_in ? 1 : 0);
+    }
 }
 
 long long scan_blocks(long long n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
@@ -709,8 +742,10 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
 }
 
 // active particles: compact index, candidate list (active partners only; a
-// free partner provably never touches), union-find init
-template <int D>
+// free partner provably never touches), union-find init.  RAW: bsum holds
+// the blocks' unscanned totals and each block adds up those before it (for
+// up to RAW_MAX_BLOCKS blocks; beyond, a one-block scan runs first).
+template <int D, bool RAW>
 __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const uint32_t* __restrict__ start,
                                                  const float4* __restrict__ pos4,
                                                  const uint32_t* __restrict__ keys_sorted,
@@ -720,13 +755,24 @@ __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const
                                                  uint32_t* __restrict__ alist, uint32_t* __restrict__ aidx,
                                                  uint32_t* __restrict__ cand, uint32_t* __restrict__ ccount,
                                                  uint32_t* __restrict__ parent, uint32_t* __restrict__ isize,
-                                                 uint32_t* __restrict__ fill) {
+                                                 uint32_t* __restrict__ fill, uint32_t* __restrict__ counters) {
     __shared__ unsigned long long sh4[4];
     const unsigned lb = xcd_block();
     int s = lb * 256 + threadIdx.x;
+    // bsum holds the blocks' (active << 32 | candidates) totals of k_classify:
+    // this block's offset is the sum of those before it; block 0 also writes
+    // the grand totals (candidates, active) to counters[0..1]
+    const unsigned long long before = RAW ? block_sum<unsigned long long, 256>(bsum, (long long)lb, sh4) : bsum[lb];
+    if (RAW && lb == 0) {
+        const unsigned long long all = block_sum<unsigned long long, 256>(bsum, (long long)gridDim.x, sh4);
+        if (threadIdx.x == 0) {
+            counters[CNT_CAND] = (uint32_t)(all & 0xffffffffULL);
+            counters[CNT_ACTIVE] = (uint32_t)(all >> 32);
+        }
+    }
     const unsigned long long v = s < np ? actcc[s] : 0ULL;
     unsigned long long tot;
-    const unsigned long long p = block_exclusive_scan<unsigned long long>(v, sh4, tot) + bsum[lb];
+    const unsigned long long p = block_exclusive_scan<unsigned long long>(v, sh4, tot) + before;
     if (s >= np || v == 0ULL) return;
     prefix[s] = p;
     uint32_t a = (uint32_t)(p >> 32), off = (uint32_t)(p & 0xffffffffULL);
@@ -846,10 +892,6 @@ __global__ __launch_bounds__(256) void k_island_class(const uint32_t* __restrict
     }
 }
 
-__global__ void k_island_plan(uint32_t* counters, const uint32_t* __restrict__ isize,
-                              const uint32_t* __restrict__ bigroot, uint32_t* __restrict__ bigoff) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) island_plan_serial(counters, isize, bigroot, bigoff);
-}
 
 
 // Lane (small islands, packed by size into waves) or slot (large islands)
@@ -875,16 +917,47 @@ __device__ __forceinline__ void island_place_one(uint32_t a, const uint32_t* __r
     }
 }
 
+// Every block first forms the wave plan and the large-island offsets itself
+// (a few hundred loads; it saves a one-block launch); block 0 stores the
+// plan for the sub-step kernels, and every block writes the same offsets.
 __global__ __launch_bounds__(256) void k_island_place(const uint32_t* __restrict__ parent,
                                                       const uint32_t* __restrict__ isize,
                                                       const uint32_t* __restrict__ irank, uint32_t* __restrict__ fill,
                                                       int* __restrict__ lanemember, uint32_t* __restrict__ loc,
-                                                      const uint32_t* __restrict__ bigoff,
+                                                      uint32_t* __restrict__ bigoff,
                                                       uint32_t* __restrict__ bigmember,
-                                                      const uint32_t* __restrict__ counters) {
-    uint32_t na = counters[CNT_ACTIVE];
+                                                      const uint32_t* __restrict__ bigroot,
+                                                      uint32_t* __restrict__ counters) {
+    __shared__ uint32_t wb[WAVE + 1];
+    __shared__ uint32_t scan4[4];
+    if (threadIdx.x == 0) {
+        uint32_t waves = 0;
+        for (int s = 1; s <= WAVE; s++) {
+            wb[s] = waves;
+            const uint32_t per = WAVE / s;
+            waves += (counters[CNT_CLASS + s] + per - 1) / per;
+        }
+        wb[0] = waves;
+    }
+    const uint32_t nbig = counters[CNT_CLASS + WAVE + 1];
+    uint32_t run = 0;
+    for (uint32_t k0 = 0; k0 < nbig; k0 += 256) {
+        const uint32_t k = k0 + threadIdx.x;
+        const uint32_t v = k < nbig ? isize[bigroot[k]] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(v, scan4, tot);
+        if (k < nbig) bigoff[k] = run + ex;
+        run += tot;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int s = 1; s <= WAVE; s++) counters[CNT_WAVEBASE + s] = wb[s];
+        counters[CNT_WAVES] = wb[0];
+        counters[CNT_BIG] = nbig;
+    }
+    const uint32_t na = counters[CNT_ACTIVE];
     for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256)
-        island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, counters + CNT_WAVEBASE);
+        island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, wb);
 }
 
 // Candidate constants for the sub-steps.  K0 = r_c^2 - |r0|^2 is formed in
@@ -987,7 +1060,7 @@ __global__ __launch_bounds__(256) void k_cand_prep(PState A, PCfg c, const uint3
 }
 
 // The whole island set-up of one step in one 1024-thread workgroup, phase
-// after phase (for a few active particles this replaces seven short
+// after phase (for a few active particles this replaces five short
 // launches): union the candidates, flatten
 // and size the islands, class them by size, plan the waves, place every
 // member, and prepare the candidate constants.  Same results as the
@@ -2162,11 +2235,18 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
     hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.pos4,
                        b.keys_sorted, b.drho_i, b.j_i, b.coef, b.fc, b.actcc, b.bsum64, b.counters, b.flags,
                        b.hcnt);
-    // block offsets; totals (candidates, active) -> counters[0..1]
-    hipLaunchKernelGGL((k_scan_top<unsigned long long>), dim3(1), dim3(TOP_THREADS), 0, s, b.bsum64, (long long)nb256(np),
-                       (unsigned long long*)(void*)b.counters);
-    hipLaunchKernelGGL(k_collect<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.pos4, b.keys_sorted, b.actcc, b.bsum64,
-                       b.prefix, b.alist, b.aidx, b.cand, b.ccount, b.parent, b.isize, b.fill);
+    // block offsets and the totals (candidates, active) -> counters[0..1]
+    if ((long long)nb256(np) <= RAW_MAX_BLOCKS) {
+        hipLaunchKernelGGL((k_collect<D, true>), dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.pos4,
+                           b.keys_sorted, b.actcc, b.bsum64, b.prefix, b.alist, b.aidx, b.cand, b.ccount, b.parent,
+                           b.isize, b.fill, b.counters);
+    } else {
+        hipLaunchKernelGGL((k_scan_top<unsigned long long>), dim3(1), dim3(TOP_THREADS), 0, s, b.bsum64,
+                           (long long)nb256(np), (unsigned long long*)(void*)b.counters);
+        hipLaunchKernelGGL((k_collect<D, false>), dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.start, b.pos4,
+                           b.keys_sorted, b.actcc, b.bsum64, b.prefix, b.alist, b.aidx, b.cand, b.ccount, b.parent,
+                           b.isize, b.fill, b.counters);
+    }
     if (one_group) {
         hipLaunchKernelGGL(k_island_setup<D>, dim3(1), dim3(SETUP_THREADS), 0, s, b.A, c, b.alist, b.ccount, b.prefix,
                            b.cand, b.aidx, b.parent, b.isize, b.irank, b.fill, b.lanemember, b.loc, b.bigroot,
@@ -2177,9 +2257,8 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
         hipLaunchKernelGGL(k_uf_flatten, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.counters);
         hipLaunchKernelGGL(k_island_class, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.bigroot,
                            b.counters);
-        hipLaunchKernelGGL(k_island_plan, dim3(1), dim3(64), 0, s, b.counters, b.isize, b.bigroot, b.bigoff);
         hipLaunchKernelGGL(k_island_place, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.fill,
-                           b.lanemember, b.loc, b.bigoff, b.bigmember, b.counters);
+                           b.lanemember, b.loc, b.bigoff, b.bigmember, b.bigroot, b.counters);
         hipLaunchKernelGGL(k_cand_prep<D>, dim3(grid_act), dim3(256), 0, s, b.A, c, b.alist, b.ccount, b.prefix, b.cand,
                            b.aidx, b.loc, b.cdata, md, b.counters);
     }
