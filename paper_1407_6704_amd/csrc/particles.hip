@@ -1860,12 +1860,14 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
 // cell's first particle, and the particles' weights and coefficients; each
 // thread then sums, for its nodes, the particles of its 4^D cells in a fixed
 // order (cells by kz, ky, kx; particles in sorted order).  No atomics, no
-// wasted candidate checks.  A tile holding more than CSR_MAXP particles
+// wasted candidate checks.  A tile holding more than MAXP particles
 // reads them from global memory instead of LDS (same order, same result).
 template <int D> struct CsrTile;
-template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4; };
-template <> struct CsrTile<2> { static constexpr int TX = 32, TY = 16, TZ = 1; };
-constexpr int CSR_MAXP = 384;
+// MAXP: particles staged in LDS per tile (the halo of a 3D tile holds about
+// 200 at 0.24 particles per cell; fewer slots push tiles onto the slow
+// unstaged path)
+template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4, MAXP = 384; };
+template <> struct CsrTile<2> { static constexpr int TX = 32, TY = 16, TZ = 1, MAXP = 384; };
 
 // C components are spread: C = D for the force field; the adjoint spreads
 // C = D + 1 (density and momentum adjoints) with the same kernel.
@@ -1879,11 +1881,12 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     constexpr int HX = TX + 3, HY = TY + 3, HZ = (D == 3) ? TZ + 3 : 1;
     constexpr int NR = HY * HZ;                  // halo rows of cells
     constexpr int PW = 4 * D + C;                // staged floats per particle
+    constexpr int MAXP = T::MAXP;
     __shared__ uint32_t cs[NR * (HX + 1)];       // per row: LDS index of each cell's first particle, then the end
     __shared__ uint32_t rowbase[NR + 1], rowg0[NR];
-    __shared__ float sp[CSR_MAXP * PW];
-    __shared__ int sb[CSR_MAXP];                 // x index of each staged particle's first stencil node
-    __shared__ uint8_t rowof[CSR_MAXP];          // halo row of each staged particle
+    __shared__ float sp[MAXP * PW];
+    __shared__ int sb[MAXP];                     // x index of each staged particle's first stencil node
+    __shared__ uint8_t rowof[MAXP];              // halo row of each staged particle
     __shared__ uint32_t scan4[4];
     static_assert(NR <= 255, "halo rows must fit the row table");
     const int t = threadIdx.x;
@@ -1927,7 +1930,7 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
         }
         cs[i] = v;
     }
-    const bool staged = total <= (uint32_t)CSR_MAXP;
+    const bool staged = total <= (uint32_t)MAXP;
     if (staged) {
         if (t < NR)
             for (uint32_t k = rowbase[t]; k < rowbase[t + 1]; k++) rowof[k] = (uint8_t)t;
@@ -1971,9 +1974,8 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
 #pragma unroll
                             for (int a = 0; a < C; a++) cv[a] = q[4 * D + a];
                         } else {
-                            int rr = 0;
-                            while (rowbase[rr + 1] <= k) rr++;
-                            const uint32_t gsl = rowg0[rr] + (k - rowbase[rr]);
+                            // particle k of halo row r sits at sorted slot rowg0[r] + (k - rowbase[r])
+                            const uint32_t gsl = rowg0[r] + (k - rowbase[r]);
                             const float* q = wphi + (long long)gsl * (4 * D);
                             wx = q[x - wbase[gsl].x];
                             wy = q[4 + ky];

@@ -448,3 +448,27 @@ def test_island_setup_paths_agree(P, lat):
     for a, b in zip(out[0][:3], out[1][:3]):
         assert np.array_equal(a, b)
 
+
+
+@pytest.mark.parametrize("lat", [9, 19])
+def test_dense_tile_spreads_unstaged(P, W, orc, lat):
+    """More particles in one spreading tile's halo than it stages in LDS
+    (384): those tiles read the particles from global memory instead; the
+    coupled step must agree with the oracle all the same."""
+    _flush(f"dense tile {lat}")
+    D = 2 if lat == 9 else 3
+    n = (48, 40, 1) if D == 2 else (20, 18, 16)
+    rng = np.random.default_rng(77)
+    npart = 900 if D == 2 else 700
+    c = np.array([n[a] / 2 for a in range(D)])
+    X = (c[:, None] + rng.uniform(-2.5 if D == 3 else -4.0, 2.5 if D == 3 else 4.0, (D, npart)))
+    X = X.astype(np.float32).astype(np.float64)
+    U = (1e-4 * rng.standard_normal((D, npart))).astype(np.float32).astype(np.float64)
+    d = np.full(npart, 0.3)
+    rp = np.full(npart, 2.5)
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-5
+    cfg = P.make_config(lattice=lat, n=n, tau=0.7, gravity=g, n_sub=20, contact="none")
+    r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=2, label="dense")
+    assert r["eu"] <= 1e-5 and r["er"] <= 1e-6 and r["efh"] <= 1e-4
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5
