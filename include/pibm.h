@@ -251,7 +251,7 @@ pibm_status pibm_diagnostics(pibm_ctx* ctx, pibm_diag* out);
  * of every operation of the step (collision and streaming, spreading,
  * momentum exchange, particle update, interpolation, moments), in FP32 with
  * double-float sums of the parameter gradients.
- * Supported: D2Q9 or D3Q19, no fixed bodies, delta-kernel interpolation, n_sub = 1 (the
+ * Supported: any lattice, no fixed bodies, delta-kernel interpolation, n_sub = 1 (the
  * explicit update of Eq. demgov), contact NONE or SOFT, bin_log2 = 0, FP32
  * or FP16 storage; other configurations return
  * PIBM_E_CONFIG.  Memory stays bounded by checkpointing: the state is saved

@@ -36,14 +36,19 @@ _E19 = [(0, 0, 0),
         (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0),
         (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1),
         (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+_E15 = [(0, 0, 0),
+        (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+        (1, 1, 1), (-1, -1, -1), (1, 1, -1), (-1, -1, 1),
+        (1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1)]
 
 
 def lattice_tables(lattice: int):
     """Velocities e (Q, 3), weights w (Q,) and opposite directions."""
-    E = _E19 if lattice == 19 else _E9
+    E = {19: _E19, 15: _E15}.get(lattice, _E9)
     e = torch.tensor(E, dtype=torch.float64)
-    by_speed2 = {0: 1.0 / 3.0, 1: 1.0 / 18.0, 2: 1.0 / 36.0} if lattice == 19 else \
-        {0: 4.0 / 9.0, 1: 1.0 / 9.0, 2: 1.0 / 36.0}
+    by_speed2 = {19: {0: 1.0 / 3.0, 1: 1.0 / 18.0, 2: 1.0 / 36.0},
+                 15: {0: 2.0 / 9.0, 1: 1.0 / 9.0, 3: 1.0 / 72.0}}.get(lattice, {0: 4.0 / 9.0, 1: 1.0 / 9.0,
+                                                                               2: 1.0 / 36.0})
     w = torch.tensor([by_speed2[sum(c * c for c in v)] for v in E], dtype=torch.float64)
     opp = [E.index(tuple(-c for c in v)) for v in E]
     return e, w, opp
@@ -55,7 +60,7 @@ class Ref:
     def __init__(self, lattice, n, d, rho_p, periodic=(0, 0, 0), rho0=1.0, k_soft=1e-3,
                  contact="soft", n_sub=1, two_way=True):
         self.lattice = lattice
-        self.D = 3 if lattice == 19 else 2
+        self.D = 2 if lattice == 9 else 3
         self.n = tuple(int(v) for v in n)
         self.periodic = tuple(int(v) for v in periodic)
         self.N = self.n[0] * self.n[1] * self.n[2]

@@ -535,6 +535,9 @@ void adj_collide(int Q, int fp16, int sl2, const float* abar, const void* ft, co
     if (Q == 19) {
         if (fp16) collide_launch<19>(abar, ft, Ft, hasF, ff, g, tau, StoreF16{sc, isc}, mom, Fbar, Mc, tpart, s);
         else collide_launch<19>(abar, ft, Ft, hasF, ff, g, tau, StoreF32{1.f, 1.f}, mom, Fbar, Mc, tpart, s);
+    } else if (Q == 15) {
+        if (fp16) collide_launch<15>(abar, ft, Ft, hasF, ff, g, tau, StoreF16{sc, isc}, mom, Fbar, Mc, tpart, s);
+        else collide_launch<15>(abar, ft, Ft, hasF, ff, g, tau, StoreF32{1.f, 1.f}, mom, Fbar, Mc, tpart, s);
     } else {
         if (fp16) collide_launch<9>(abar, ft, Ft, hasF, ff, g, tau, StoreF16{sc, isc}, mom, Fbar, Mc, tpart, s);
         else collide_launch<9>(abar, ft, Ft, hasF, ff, g, tau, StoreF32{1.f, 1.f}, mom, Fbar, Mc, tpart, s);
@@ -545,6 +548,9 @@ void adj_assemble(int Q, const float* abar, const float4* Mc, const float* Sf, i
                   float* abar_out, hipStream_t s) {
     if (Q == 19)
         hipLaunchKernelGGL(k_adj_assemble<19>, dim3(blocks256(g.N)), dim3(256), 0, s, abar, Mc, Sf, hasS, g, tau,
+                           abar_out);
+    else if (Q == 15)
+        hipLaunchKernelGGL(k_adj_assemble<15>, dim3(blocks256(g.N)), dim3(256), 0, s, abar, Mc, Sf, hasS, g, tau,
                            abar_out);
     else
         hipLaunchKernelGGL(k_adj_assemble<9>, dim3(blocks256(g.N)), dim3(256), 0, s, abar, Mc, Sf, hasS, g, tau,

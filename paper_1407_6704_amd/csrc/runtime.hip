@@ -321,7 +321,6 @@ std::string adjoint_unsupported(const pibm_ctx& c) {
         c.cfg.contact == PIBM_CONTACT_HERTZ_MINDLIN)
         return "the adjoint supports no contact or soft contact only";
     if (c.cfg.bin_log2 != 0) return "the adjoint needs bin_log2 = 0";
-    if (c.cfg.lattice == PIBM_D3Q15) return "the adjoint supports D2Q9 and D3Q19 only";
     if (c.cfg.bodies) return "the adjoint supports no fixed bodies";
     if (c.cfg.interp != PIBM_INTERP_DELTA) return "the adjoint supports delta-kernel interpolation only";
     return "";

@@ -100,7 +100,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("lattice", [9, 19])
+@pytest.mark.parametrize("lattice", [9, 19, 15])
 def test_adjoint_matches_autograd_reference(P, lattice):
     n, X, U, d, rp = _small_case(lattice, 5)
     tau, g, steps, K = 0.7, 1e-3, 15, 4
@@ -243,7 +243,8 @@ def test_adjoint_rejects_unsupported_and_edge_cases(P):
     rollout is one segment."""
     n, X, U, d, rp = _small_case(9, 8)
     for kw in (dict(contact="lsd", n_sub=1), dict(contact="soft", n_sub=4), dict(contact="soft", bin_log2=1),
-               dict(contact="hertz", n_sub=1), dict(contact="soft", interp="lagrange")):
+               dict(contact="hertz", n_sub=1), dict(contact="soft", interp="lagrange"),
+               dict(contact="soft", bodies=1), dict(contact="hertz_mindlin", young=1e-3)):
         cfg = P.make_config(lattice=9, n=n, tau=0.7, gravity=(0.0, -1e-3, 0.0), k_soft=2e-3, skin=0.05, **kw)
         sim = P.Sim(cfg, X.shape[1])
         sim.set_particles(X, U, d, rp)
