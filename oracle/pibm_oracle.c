@@ -12,12 +12,14 @@
  *
  * Every loop is the definition, in the paper's order: no blocking, no
  * fusion, no shortcut.  Where the paper is silent or garbled the reading
- * taken is stated at the function, tagged R1..R17.
+ * taken is stated at the function, tagged R1..R26.
  *
  * Pins (tests/test_oracle_*.py) tie each function to something other than
  * itself: body-force Poiseuille closed form, delta-kernel moments, equilibrium
  * moments, mass and momentum bookkeeping, interpolation/spreading adjointness,
- * one-way terminal settling, brute-force contact lists, restitution.
+ * one-way terminal settling, brute-force contact lists, restitution,
+ * Lagrange polynomial reproduction, Hertz impact theory, rolling and
+ * sliding with friction, obstacles as momentum supports.
  * Parity unpinned: long multi-particle trajectories (chaotic; compared by
  * statistics only).
  *
