@@ -1864,9 +1864,9 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
 // reads them from global memory instead of LDS (same order, same result).
 template <int D> struct CsrTile;
 // MAXP: particles staged in LDS per tile (the halo of a 3D tile holds about
-// 200 at 0.24 particles per cell; fewer slots push tiles onto the slow
-// unstaged path)
-template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4, MAXP = 384; };
+// 200 at 0.24 particles per cell; 320 slots leave room for 6 workgroups per
+// CU, and a fuller halo takes the unstaged path)
+template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4, MAXP = 256; };
 template <> struct CsrTile<2> { static constexpr int TX = 32, TY = 16, TZ = 1, MAXP = 384; };
 
 // C components are spread: C = D for the force field; the adjoint spreads
@@ -1954,40 +1954,44 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
 #pragma unroll
         for (int a = 0; a < C; a++) acc[a] = 0.f;
         if (total > 0) {
-#pragma unroll 1
-            for (int kz = 0; kz < (D == 3 ? 4 : 1); kz++)
-#pragma unroll 1
-                for (int ky = 0; ky < 4; ky++) {
-                    // the four cells of this row that reach the node are
-                    // contiguous in the row's CSR: one particle range, and
-                    // each particle's x weight index is x - base_x
-                    const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
-                    const uint32_t* rc = cs + r * (HX + 1);
-                    const uint32_t p0 = rc[lx], p1 = rc[lx + 4];
-                    for (uint32_t k = p0; k < p1; k++) {
-                        float wx, wy, wz = 1.f, cv[C];
-                        if (staged) {
-                            const float* q = sp + k * PW;
-                            wx = q[x - sb[k]];
-                            wy = q[4 + ky];
-                            if (D == 3) wz = q[8 + kz];
+            // the particle ranges of the node's 4^(D-1) halo rows: the four
+            // cells of a row that reach the node are contiguous in the row's
+            // CSR, and each particle's x weight index is x - base_x
+            constexpr int NRW = (D == 3 ? 16 : 4);
+            uint32_t pr[NRW];                      // first | end << 16 (tile positions < 2^16)
 #pragma unroll
-                            for (int a = 0; a < C; a++) cv[a] = q[4 * D + a];
-                        } else {
-                            // particle k of halo row r sits at sorted slot rowg0[r] + (k - rowbase[r])
-                            const uint32_t gsl = rowg0[r] + (k - rowbase[r]);
-                            const float* q = wphi + (long long)gsl * (4 * D);
-                            wx = q[x - wbase[gsl].x];
-                            wy = q[4 + ky];
-                            if (D == 3) wz = q[8 % (4 * D) + kz];
+            for (int i = 0; i < NRW; i++) {
+                const int ky = i & 3, kz = i >> 2;
+                const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
+                pr[i] = cs[r * (HX + 1) + lx] | (cs[r * (HX + 1) + lx + 4] << 16);
+            }
+            if (staged) {
 #pragma unroll
-                            for (int a = 0; a < C; a++) cv[a] = coef[(long long)a * np + gsl];
-                        }
-                        const float W = wx * wy * wz;
+                for (int i = 0; i < NRW; i++) {
+                    const int ky = i & 3, kz = i >> 2;
+                    for (uint32_t k = pr[i] & 0xffffu; k < (pr[i] >> 16); k++) {
+                        const float* q = sp + k * PW;
+                        const float W = q[x - sb[k]] * q[4 + ky] * (D == 3 ? q[8 + kz] : 1.f);
 #pragma unroll
-                        for (int a = 0; a < C; a++) acc[a] += W * cv[a];
+                        for (int a = 0; a < C; a++) acc[a] += W * q[4 * D + a];
                     }
                 }
+            } else {
+#pragma unroll 1
+                for (int i = 0; i < NRW; i++) {
+                    const int ky = i & 3, kz = i >> 2;
+                    const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
+                    const uint32_t k0 = cs[r * (HX + 1) + lx], k1 = cs[r * (HX + 1) + lx + 4];
+                    for (uint32_t k = k0; k < k1; k++) {
+                        // particle k of halo row r sits at sorted slot rowg0[r] + (k - rowbase[r])
+                        const uint32_t gsl = rowg0[r] + (k - rowbase[r]);
+                        const float* q = wphi + (long long)gsl * (4 * D);
+                        const float W = q[x - wbase[gsl].x] * q[4 + ky] * (D == 3 ? q[8 % (4 * D) + kz] : 1.f);
+#pragma unroll
+                        for (int a = 0; a < C; a++) acc[a] += W * coef[(long long)a * np + gsl];
+                    }
+                }
+            }
         }
         const long long rn = ((long long)z * g.n[1] + y) * g.n[0] + x;
 #pragma unroll
