@@ -37,20 +37,20 @@ COPY_PROBE_BYTES = 1 << 30
 # device copy of known size (--copy-probe).  Keyed by (kernel, workload); the
 # entry only applies while the kernel's source file hashes to `source_sha`.
 MEASURED_TRAFFIC = {
-    ("collide", "c1"): {"fetch_bytes": 90151.3 * 1024 * 1.9999, "write_bytes": 150210.6 * 1024,
+    ("collide", "c1"): {"fetch_bytes": 90151.3 * 1024 * 1.9999, "write_bytes": 150202.7 * 1024,
                        "source_sha": "b5f944bdaea84603"},
-    ("spread", "c1"): {"fetch_bytes": 47806.9 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
-                      "source_sha": "65798e0da27d7a6f"},
-    ("interp", "c1"): {"fetch_bytes": 98054.2 * 1024 * 1.9999, "write_bytes": 27472.4 * 1024,
-                      "source_sha": "65798e0da27d7a6f"},
-    ("collide", "c2"): {"fetch_bytes": 720964.0 * 1024 * 1.9999, "write_bytes": 1256054.3 * 1024,
+    ("spread", "c1"): {"fetch_bytes": 47812.9 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
+                      "source_sha": "4fa3b99e89e7bf9f"},
+    ("interp", "c1"): {"fetch_bytes": 98368.1 * 1024 * 1.9999, "write_bytes": 27473.5 * 1024,
+                      "source_sha": "4fa3b99e89e7bf9f"},
+    ("collide", "c2"): {"fetch_bytes": 720964.2 * 1024 * 1.9999, "write_bytes": 1256040.4 * 1024,
                        "source_sha": "b5f944bdaea84603"},
     ("moments", "c2"): {"fetch_bytes": 622610.7 * 1024 * 1.9999, "write_bytes": 262144.0 * 1024,
                        "source_sha": "b5f944bdaea84603"},
-    ("spread", "c2"): {"fetch_bytes": 700072.2 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
-                      "source_sha": "65798e0da27d7a6f"},
-    ("interp", "c2"): {"fetch_bytes": 396445.5 * 1024 * 1.9999, "write_bytes": 180019.5 * 1024,
-                      "source_sha": "65798e0da27d7a6f"},
+    ("spread", "c2"): {"fetch_bytes": 691901.5 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
+                      "source_sha": "4fa3b99e89e7bf9f"},
+    ("interp", "c2"): {"fetch_bytes": 396354.4 * 1024 * 1.9999, "write_bytes": 180024.3 * 1024,
+                      "source_sha": "4fa3b99e89e7bf9f"},
 }
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
 
