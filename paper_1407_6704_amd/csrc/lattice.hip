@@ -28,7 +28,9 @@ __global__ __launch_bounds__(256) void k_moments(const typename S::T* __restrict
     float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
-        float h = st.load(f + (long long)q * N + r);
+        // non-temporal: the populations outgrow the last-level cache, and
+        // the collision reads them again only after the particle phases
+        float h = st.load_stream(f + (long long)q * N + r);
         dr += h;
         if (L::ex(q)) jx += L::ex(q) * h;
         if (L::ey(q)) jy += L::ey(q) * h;

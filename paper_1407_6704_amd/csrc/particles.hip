@@ -1978,16 +1978,43 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
                 const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
                 pr[i] = cs[r * (HX + 1) + lx] | (cs[r * (HX + 1) + lx + 4] << 16);
             }
-            if (staged) {
+            if (staged && D == 2) {
 #pragma unroll
                 for (int i = 0; i < NRW; i++) {
-                    const int ky = i & 3, kz = i >> 2;
                     for (uint32_t k = pr[i] & 0xffffu; k < (pr[i] >> 16); k++) {
                         const float* q = sp + k * PW;
-                        const float W = q[x - sb[k]] * q[4 + ky] * (D == 3 ? q[8 + kz] : 1.f);
+                        const float W = q[x - sb[k]] * q[4 + (i & 3)];
 #pragma unroll
                         for (int a = 0; a < C; a++) acc[a] += W * q[4 * D + a];
                     }
+                }
+            } else if (staged) {
+                // 3D: one flat loop over the lane's particles, rows in
+                // order: a wave then runs as many trips as its busiest lane
+                // has particles, not the sum over the 16 rows of each row's
+                // busiest lane (in 2D the 4-row loop is as fast)
+                uint32_t mask = 0;
+#pragma unroll
+                for (int i = 0; i < NRW; i++)
+                    if ((pr[i] >> 16) > (pr[i] & 0xffffu)) mask |= 1u << i;
+                uint32_t k = 0, e = 0;
+                int ky = 0, kz = 0;
+                while (true) {
+                    if (k == e) {
+                        if (!mask) break;
+                        const int i = __builtin_ctz(mask);
+                        mask &= mask - 1u;
+                        ky = i & 3;
+                        kz = i >> 2;
+                        const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
+                        k = cs[r * (HX + 1) + lx];
+                        e = cs[r * (HX + 1) + lx + 4];
+                    }
+                    const float* q = sp + k * PW;
+                    const float W = q[x - sb[k]] * q[4 + ky] * (D == 3 ? q[8 + kz] : 1.f);
+#pragma unroll
+                    for (int a = 0; a < C; a++) acc[a] += W * q[4 * D + a];
+                    k++;
                 }
             } else {
 #pragma unroll 1
