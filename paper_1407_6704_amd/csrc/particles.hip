@@ -590,11 +590,28 @@ __device__ __forceinline__ int scan_neighbours(const float4* __restrict__ pos4, 
     // ceil(r_s / edge) bins away (bin = (floor(X - 1/2) + 1) >> L)
     const float r_s = (0.5f * (me.w + c.dmax) + c.skin + c.eps) * (1.0f + 1e-6f);
     const int H = min(c.H, max(1, (int)ceilf(r_s * ldexpf(1.0f, -c.L))));
-    int zl = (D == 3) ? max(b[2] - H, 0) : 0, zh = (D == 3) ? min(b[2] + H, c.nb[2] - 1) : 0;
-    for (int bz = zl; bz <= zh; bz++)
-        for (int by = max(b[1] - H, 0); by <= min(b[1] + H, c.nb[1] - 1); by++) {
+    // Per axis, only the bins that meet [X - r_s, X + r_s]: a particle of
+    // bin k lies in [k - 1/2, k + 1/2) (edge 1), so every bin beyond
+    // bin(X + r_s) or below bin(X - r_s) is farther than r_s along that axis.
+    // The 1/64 margin covers the rounding of X +- r_s against the bin keys.
+    // Usually 2 bins per axis instead of 3: the same candidates, in the
+    // same order.
+    const float rr = r_s + 0.015625f;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        const float xa = a == 0 ? me.x : (a == 1 ? me.y : me.z);
+        const int l = ((int)floorf(xa - rr - 0.5f) + 1) >> c.L;
+        const int h = ((int)floorf(xa + rr - 0.5f) + 1) >> c.L;
+        // within b +- H and the grid, and never excluding the own bin (so
+        // also a stray position cannot widen the range)
+        lo[a] = min(max(max(l, b[a] - H), 0), b[a]);
+        hi[a] = max(min(min(h, b[a] + H), c.nb[a] - 1), b[a]);
+    }
+    for (int bz = lo[2]; bz <= hi[2]; bz++)
+        for (int by = lo[1]; by <= hi[1]; by++) {
             // bins of one row are contiguous in the sorted order
-            int bxl = max(b[0] - H, 0), bxh = min(b[0] + H, c.nb[0] - 1);
+            const int bxl = lo[0], bxh = hi[0];
             uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
             uint32_t t0 = start[row + bxl], t1 = start[row + bxh + 1];
             for (uint32_t t = t0; t < t1; t++) {
