@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define PIBM_ABI_VERSION 5
+#define PIBM_ABI_VERSION 6
 
 typedef enum {
     PIBM_OK = 0,
@@ -229,7 +229,7 @@ pibm_status pibm_step(pibm_ctx* ctx, int32_t n_steps);
  * context's stream between its phases; pibm_phase_times synchronises and
  * returns the milliseconds spent in each phase (and the number of steps)
  * since profiling was enabled or last read, then resets the sums.  Phases:
- * 0 moments, 1 cell list, 2 interpolation, 3 DEM, 4 spreading, 5 collision
+ * 0 cell list, 1 moments, 2 interpolation, 3 DEM, 4 spreading, 5 collision
  * and streaming.  Profiling adds 7 event records per step. */
 #define PIBM_NUM_PHASES 6
 pibm_status pibm_set_profiling(pibm_ctx* ctx, int enable);

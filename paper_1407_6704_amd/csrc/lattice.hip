@@ -1,7 +1,9 @@
 // lattice.hip -- lattice-Boltzmann kernels of the coupled step (gfx950).
 //
 //  k_moments  : density deviation and momentum of the stored populations
-//               (moment definitions of Sec. 2.1), one float4 per node.
+//               (moment definitions of Sec. 2.1), one float4 per node; in
+//               the coupled step only on the node rows that some particle's
+//               4-node gather stencil reaches (the others are never read).
 //  k_collide  : BGK collision, Eq. lbm2, towards the equilibrium of Eq. lbm3,
 //               with the forcing term of Eq. lbm9 and the half-force velocity
 //               rho u = sum f e + F/2 (end of Sec. 2.2); the post-collision
@@ -19,11 +21,40 @@
 
 namespace pibm {
 
+// Node y of an axis is a gather node of the particles whose dual cell
+// c' = floor(X - 1/2) + 1 lies in [y - 1, y + 2] (stencil c' - 2 .. c' + 1).
+// A row of nodes (y, z) along x is needed when the bins of those cells hold
+// a particle: 16 bin rows (4 in 2D), each a contiguous run of the sorted
+// order.  A workgroup whose nodes span at most ROWS_MAX rows decides for
+// all of them together and skips when none is needed; otherwise it computes.
+constexpr int ROWS_MAX = 4;
+__device__ __forceinline__ bool rows_needed(const RowMask& m, long long r0, long long r1) {
+    const long long R0 = r0 / m.n[0], R1 = r1 / m.n[0];
+    if (R1 - R0 >= ROWS_MAX) return true;
+    uint32_t cnt = 0;
+    const int t = threadIdx.x;
+    if (t < 16 * (int)(R1 - R0 + 1)) {
+        const long long R = R0 + t / 16;
+        const int y = (int)(R % m.n[1]), z = (int)(R / m.n[1]);
+        const int cy = y - 1 + (t & 3), cz = z - 1 + ((t >> 2) & 3);
+        if (cy >= 0 && cz >= 0) {
+            const int by = cy >> m.L, bz = cz >> m.L;
+            if (by < m.nb[1] && bz < m.nb[2]) {
+                const long long row = ((long long)bz * m.nb[1] + by) * m.nb[0];
+                cnt = m.start[row + m.nb[0]] - m.start[row];
+            }
+        }
+    }
+    return __syncthreads_or(cnt != 0u) != 0;
+}
+
 template <int Q, class S>
 __global__ __launch_bounds__(256) void k_moments(const typename S::T* __restrict__ f,
-                                                 float4* __restrict__ mom, long long N, S st) {
+                                                 float4* __restrict__ mom, long long N, S st, RowMask m) {
     using L = Lattice<Q>;
-    long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long r0 = (long long)blockIdx.x * 256;
+    if (m.start && !rows_needed(m, r0, min(r0 + 255, N - 1))) return;   // uniform over the block
+    long long r = r0 + threadIdx.x;
     if (r >= N) return;
     float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
@@ -224,8 +255,9 @@ __global__ void k_sum_partials(const double* __restrict__ part, int nblocks, dou
 static inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 
 template <int Q, class S>
-static void launch_lattice_moments(const void* f, float4* mom, long long N, S st, hipStream_t s) {
-    hipLaunchKernelGGL((k_moments<Q, S>), dim3(nblk(N)), dim3(256), 0, s, (const typename S::T*)f, mom, N, st);
+static void launch_lattice_moments(const void* f, float4* mom, long long N, S st, const RowMask& m,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL((k_moments<Q, S>), dim3(nblk(N)), dim3(256), 0, s, (const typename S::T*)f, mom, N, st, m);
 }
 
 template <int Q, class S>
@@ -253,8 +285,9 @@ template <class S> static S make_store(int scale_log2) {
     return st;
 }
 
-void lattice_moments(int Q, int fp16, int sl2, const void* f, float4* mom, long long N, hipStream_t s) {
-    PIBM_DISPATCH(Q, fp16, launch_lattice_moments<QQ, SS>(f, mom, N, make_store<SS>(sl2), s));
+void lattice_moments(int Q, int fp16, int sl2, const void* f, float4* mom, long long N, const RowMask& m,
+                     hipStream_t s) {
+    PIBM_DISPATCH(Q, fp16, launch_lattice_moments<QQ, SS>(f, mom, N, make_store<SS>(sl2), m, s));
 }
 
 void lattice_collide(int Q, int fp16, int sl2, const void* fin, void* fout, const float* F, int hasF,

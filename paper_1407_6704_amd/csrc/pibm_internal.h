@@ -104,6 +104,15 @@ struct Grid {
     long long N;       // nodes
 };
 
+// Which node rows the particle gather can reach: the cell list's bin starts
+// (start == nullptr: every row), the grid and the binning.
+struct RowMask {
+    const uint32_t* start;
+    int n[3];
+    int nb[3];
+    int L;
+};
+
 // ---------------------------------------------------------------------------
 // Double-float helpers (value = hi + lo, |lo| <= ulp(hi)/2), FP32 only.
 // Error-free transformations must not be contracted into FMAs, hence the

@@ -14,7 +14,8 @@
 namespace pibm {
 constexpr size_t CAND_BYTES = sizeof(CandData);
 
-void lattice_moments(int Q, int fp16, int sl2, const void* f, float4* mom, long long N, hipStream_t s);
+void lattice_moments(int Q, int fp16, int sl2, const void* f, float4* mom, long long N, const RowMask& m,
+                     hipStream_t s);
 void lattice_collide(int Q, int fp16, int sl2, const void* fin, void* fout, const float* F, int hasF,
                      const float* ff, const Grid& g, float tau, hipStream_t s);
 void lattice_init_eq(int Q, int fp16, int sl2, void* f, const float* rho, const float* u, long long N,
@@ -698,7 +699,7 @@ pibm_status pibm_read_particles(pibm_ctx* c, double* x, double* v, double* f_hyd
 
 pibm_status pibm_read_fields(pibm_ctx* c, float* rho, float* u) {
     if (!c) return PIBM_E_ARG;
-    lattice_moments(c->Q, c->fp16, c->sl2, c->fA, c->mom, c->N, c->stream);
+    lattice_moments(c->Q, c->fp16, c->sl2, c->fA, c->mom, c->N, RowMask{}, c->stream);   // every node
     lattice_fields(c->mom, c->stage, c->stage + c->N, c->N, c->D, c->stream);
     if (rho) hipMemcpyAsync(rho, c->stage, sizeof(float) * c->N, hipMemcpyDeviceToHost, c->stream);
     if (u) hipMemcpyAsync(u, c->stage + c->N, sizeof(float) * c->D * c->N, hipMemcpyDeviceToHost, c->stream);
@@ -739,13 +740,18 @@ void launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
     const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
     const bool spread = c->np > 0 && c->cfg.two_way;
     // D2Q9 interpolation takes the moments straight from the populations of
-    // the tiles that hold particles; D3Q19 (19 planes, a larger halo) and the
-    // coarse-bin path read them from a moments pass
+    // the tiles that hold particles; 3D (15 or 19 planes, a larger halo) and
+    // the coarse-bin path read them from a moments pass, which the cell list
+    // restricts to the node rows that the particles' stencils reach
     const bool fused = c->D == 2 && c->pc.L <= 1;
     mark(c, row, 0);
-    if (c->np > 0 && !fused) lattice_moments(c->Q, c->fp16, c->sl2, fin, c->mom, c->N, c->stream);
-    mark(c, row, 1);
     if (c->np > 0) particles_sort(c->D, c->pb, c->np, c->pc, c->stream);
+    mark(c, row, 1);
+    if (c->np > 0 && !fused) {
+        RowMask m{c->pb.start, {c->pc.n[0], c->pc.n[1], c->pc.n[2]}, {c->pc.nb[0], c->pc.nb[1], c->pc.nb[2]},
+                  c->pc.L};
+        lattice_moments(c->Q, c->fp16, c->sl2, fin, c->mom, c->N, m, c->stream);
+    }
     mark(c, row, 2);
     if (c->np > 0) {
         if (fused) particles_interp_from_populations(c->pb, c->np, c->grid, c->pc, fin, c->fp16, c->sl2, c->stream);

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpibm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pibm.h")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 D2Q9, D3Q15, D3Q19 = 9, 15, 19
 STORE_FP32, STORE_FP16 = 0, 1
 CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3, "hertz_mindlin": 4}
@@ -293,7 +293,7 @@ class Sim:
     def step(self, n=1):
         self._check(self.lib.pibm_step(self.ctx, int(n)))
 
-    PHASES = ("moments", "cell_list", "interp", "dem", "spread", "collide")
+    PHASES = ("cell_list", "moments", "interp", "dem", "spread", "collide")
 
     def set_profiling(self, on=True):
         self._check(self.lib.pibm_set_profiling(self.ctx, 1 if on else 0))
