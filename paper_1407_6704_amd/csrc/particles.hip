@@ -1946,6 +1946,17 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     }
     __syncthreads();
     const uint32_t total = rowbase[NR];
+    if (total == 0) {
+        // no particle reaches the tile (the same for the whole workgroup)
+        for (int node = t; node < TX * TY * TZ; node += 256) {
+            const int x = x0 + node % TX, y = y0 + (node / TX) % TY, z = z0 + node / (TX * TY);
+            if (x >= g.n[0] || y >= g.n[1] || z >= g.n[2]) continue;
+            const long long rn = ((long long)z * g.n[1] + y) * g.n[0] + x;
+#pragma unroll
+            for (int a = 0; a < C; a++) F[(long long)a * g.N + rn] = 0.f;
+        }
+        return;
+    }
     for (int i = t; i < NR * (HX + 1); i += 256) {
         const int r = i / (HX + 1), ix = i % (HX + 1);
         const int cy = cy0 + r % HY, cz = cz0 + r / HY, cx = cx0 + ix;
