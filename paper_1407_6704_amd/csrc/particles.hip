@@ -1863,38 +1863,23 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
     }
 }
 
-// Islands larger than a wave: one 256-lane workgroup per island, states in
-// global scratch indexed by the active index (gdx, gu: [2][3][cap]; the
-// compensations and running sums follow gdx at 6 cap .. 19 cap).
 // ---------------------------------------------------------------------------
 // spreading (Eq. lbm10): F(r) = sum_p A_p gbar_p W_p(r) with the start-of-step
-// weights.  One wave per node tile.  The particles whose support can reach
-// the tile sit in the tile's halo bins; the bins of one (by, bz) row are
-// contiguous in the sorted order, so walking the rows in ascending key order
-// visits the particles in sorted order.  The wave loads 64 particles at a
-// time (coalesced), then adds each particle's contribution to its support
-// nodes held in LDS, one lane per support node: every node receives its
-// terms in the same fixed order, with no atomics.
+// weights.
 // ---------------------------------------------------------------------------
-// One wave per block of nodes (3D 4x4x4, 2D 8x8), one node per lane, the
-// force accumulated in registers.  The wave walks the particles of the
-// block's halo bins in sorted order (rows of bins are contiguous), reading
-// each particle's base and weights with uniform (scalar) loads; a lane adds
-// the particle's term when its node lies in the particle's support.  Every
-// node thus sums its terms in the same fixed order: deterministic, with no
-// atomics and no shared-memory dependency chain.
 // Spreading with dual-cell bins (bin edge 1): cell c' = floor(X - 1/2) + 1.
 // Node r receives exactly the particles of cells c' in [r - 1, r + 2] per
 // axis, with support offset k = r + 2 - c'.  A workgroup owns a tile of
 // nodes; it stages, for the tile's halo of cells, the LDS position of each
 // cell's first particle, and the particles' weights and coefficients; each
 // thread then sums, for its nodes, the particles of its 4^D cells in a fixed
-// order (cells by kz, ky, kx; particles in sorted order).  No atomics, no
-// wasted candidate checks.  A tile holding more than MAXP particles
-// reads them from global memory instead of LDS (same order, same result).
+// order (rows of cells by kz, ky; cells by kx; particles in sorted order).
+// No atomics, no wasted candidate checks.  A tile holding more than MAXP
+// particles reads them from global memory instead of LDS (same order, same
+// result); a tile that no particle reaches writes zeros at once.
 template <int D> struct CsrTile;
 // MAXP: particles staged in LDS per tile (the halo of a 3D tile holds about
-// 200 at 0.24 particles per cell; 320 slots leave room for 6 workgroups per
+// 200 at 0.24 particles per cell; 256 slots leave room for 7 workgroups per
 // CU, and a fuller halo takes the unstaged path)
 template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4, MAXP = 256; };
 template <> struct CsrTile<2> { static constexpr int TX = 32, TY = 16, TZ = 1, MAXP = 384; };
