@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 1 << 30
+PROFILE_EVERY = 10       # timed steps per step that records the phase events
 
 # HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, then
 # WRITE_SIZE, each in its own run), scaled by the same counters over a plain
@@ -138,7 +139,9 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
         sim.set_bodies(body, area)
     sim.step(warmup)
     sim.synchronize()
-    sim.set_profiling(True)
+    # phase events on every PROFILE_EVERY-th timed step: each recorded step
+    # carries 7 event records, which add a few microseconds each
+    sim.set_profiling(True, every=PROFILE_EVERY)
     sim.phase_times()
     stream = sim.stream
     ev0 = torch.cuda.Event(enable_timing=True)

@@ -225,12 +225,15 @@ pibm_status pibm_read_cell_list(pibm_ctx* ctx, uint32_t* keys, int32_t* ids,
 /* Enqueue n_steps coupled steps on the context's stream (no host sync). */
 pibm_status pibm_step(pibm_ctx* ctx, int32_t n_steps);
 
-/* Phase timing.  With profiling on, pibm_step records HIP events on the
- * context's stream between its phases; pibm_phase_times synchronises and
- * returns the milliseconds spent in each phase (and the number of steps)
- * since profiling was enabled or last read, then resets the sums.  Phases:
- * 0 cell list, 1 moments, 2 interpolation, 3 DEM, 4 spreading, 5 collision
- * and streaming.  Profiling adds 7 event records per step. */
+/* Phase timing.  pibm_set_profiling(ctx, n) with n >= 1 makes pibm_step
+ * record HIP events on the context's stream between the phases of every
+ * n-th step (the first step after the call included); n <= 0 turns it off.
+ * pibm_phase_times synchronises and returns the milliseconds spent in each
+ * phase, summed over the recorded steps, and their number, since profiling
+ * was enabled or last read, then resets the sums.  Phases: 0 cell list,
+ * 1 moments, 2 interpolation, 3 DEM, 4 spreading, 5 collision and
+ * streaming.  A recorded step carries 7 event records, which cost a few
+ * microseconds each on the stream. */
 #define PIBM_NUM_PHASES 6
 pibm_status pibm_set_profiling(pibm_ctx* ctx, int enable);
 pibm_status pibm_phase_times(pibm_ctx* ctx, double* ms, int64_t* steps);

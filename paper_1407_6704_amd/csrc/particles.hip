@@ -1459,8 +1459,13 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
         else wall_force<D>(P, c, F);
     }
     const int n1 = min(P.cnt, nfirst);
+    // the next candidate is loaded while the current one is evaluated (a
+    // sub-step is a serial latency chain when few islands are left)
+    CandData nx{};
+    if (P.cnt > 0) nx = (0 < n1) ? first[0] : rest[0];
     for (int k = 0; k < P.cnt; k++) {
-        CandData cd = (k < n1) ? first[k] : rest[k];
+        const CandData cd = nx;
+        if (k + 1 < P.cnt) nx = (k + 1 < n1) ? first[k + 1] : rest[k + 1];
         float odx[3] = {0, 0, 0}, ou[3] = {0, 0, 0};
 #pragma unroll
         for (int a = 0; a < D; a++) {
@@ -1655,107 +1660,6 @@ __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m, 
     P.vmax2 = fmaxf(P.vmax2, v2);
 }
 
-// Islands larger than a wave: one workgroup per island, states in global
-// scratch indexed by the active index (gdx, gu: [2][3][cap]; the
-// compensations and running sums follow gdx at 6 cap .. 19 cap).
-template <int D, bool MD>
-__device__ __forceinline__ void island_big_one(uint32_t ib, PState& A, PState& Bn, int np, const PCfg& c,
-                                               const uint32_t* __restrict__ bigmember,
-                                               const uint32_t* __restrict__ bigoff,
-                                               const uint32_t* __restrict__ bigroot,
-                                               const uint32_t* __restrict__ isize,
-                                               const uint32_t* __restrict__ alist,
-                                               const uint32_t* __restrict__ ccount,
-                                               const unsigned long long* __restrict__ prefix,
-                                               const CandData* __restrict__ cdata,
-                                               const float* __restrict__ drho_i, const float* __restrict__ j_i,
-                                               float* __restrict__ coef, float* __restrict__ fc,
-                                               float* gdx, float* gu, long long cap,
-                                               uint32_t* __restrict__ flags, const MdBuf& md) {
-    // MD scratch: spin [2][3][cap], wall tangential forces [9][cap], wall sides [cap]
-    float* gw = md.gmd;
-    float* gwt = md.gmd + 6 * cap;
-    uint32_t* gside = (uint32_t*)(md.gmd + 15 * cap);
-    const uint32_t nt = blockDim.x;
-    uint32_t base = bigoff[ib];
-    uint32_t sz = isize[bigroot[ib]];
-    for (uint32_t i = threadIdx.x; i < sz; i += nt) {
-        uint32_t a = bigmember[base + i];
-        uint32_t s = alist[a];
-#pragma unroll
-        for (int ax = 0; ax < 3; ax++) {
-            gdx[(0 * 3 + ax) * cap + a] = 0.f;
-            gu[(0 * 3 + ax) * cap + a] = ax < D ? A.u[ax][s] : 0.f;
-        }
-        if (MD) {
-            gw[(0 * 3 + 0) * cap + a] = D == 3 ? A.w[0][s] : 0.f;
-            gw[(0 * 3 + 1) * cap + a] = D == 3 ? A.w[1][s] : 0.f;
-            gw[(0 * 3 + 2) * cap + a] = D == 3 ? A.w[2][s] : A.w[0][s];
-        }
-    }
-    __syncthreads();
-    // per-member state is re-read from scratch each sub-step (a lane may own several members)
-    for (int k = 0; k < c.n_sub; k++) {
-        int cur = k & 1;
-        for (uint32_t i = threadIdx.x; i < sz; i += nt) {
-            uint32_t a = bigmember[base + i];
-            uint32_t s = alist[a];
-            Active<D> P;
-            active_load<D, MD>(P, A, c, s, drho_i, j_i, np, ccount, prefix, md);
-#pragma unroll
-            for (int ax = 0; ax < D; ax++) {
-                P.dx[ax] = gdx[(cur * 3 + ax) * cap + a];
-                P.u[ax] = gu[(cur * 3 + ax) * cap + a];
-            }
-            if (MD) {
-#pragma unroll
-                for (int ax = 0; ax < 3; ax++) P.W[ax] = gw[(cur * 3 + ax) * cap + a];
-                if (k > 0) {
-#pragma unroll
-                    for (int ax = 0; ax < 3; ax++)
-#pragma unroll
-                        for (int b = 0; b < 3; b++) P.wT[ax][b] = gwt[(3 * ax + b) * cap + a];
-                    P.wside = gside[a];
-                }
-            }
-            float* aux = gdx + 6 * cap;
-            if (k > 0) {
-#pragma unroll
-                for (int ax = 0; ax < D; ax++) {
-                    P.cdx[ax] = aux[(0 * 3 + ax) * cap + a];
-                    P.cu[ax] = aux[(1 * 3 + ax) * cap + a];
-                    P.gs[ax] = aux[(2 * 3 + ax) * cap + a];
-                    P.fs[ax] = aux[(3 * 3 + ax) * cap + a];
-                }
-                P.vmax2 = aux[12 * cap + a];
-            }
-            active_substep<D, MD>(P, c, cdata + P.off, P.cnt, cdata + P.off, gdx + cur * 3 * cap,
-                                  gu + cur * 3 * cap, MD ? gw + cur * 3 * cap : nullptr, (int)cap, md);
-            if (MD) {
-#pragma unroll
-                for (int ax = 0; ax < 3; ax++) {
-                    gw[((cur ^ 1) * 3 + ax) * cap + a] = P.W[ax];
-#pragma unroll
-                    for (int b = 0; b < 3; b++) gwt[(3 * ax + b) * cap + a] = P.wT[ax][b];
-                }
-                gside[a] = P.wside;
-            }
-#pragma unroll
-            for (int ax = 0; ax < D; ax++) {
-                gdx[((cur ^ 1) * 3 + ax) * cap + a] = P.dx[ax];
-                gu[((cur ^ 1) * 3 + ax) * cap + a] = P.u[ax];
-                aux[(0 * 3 + ax) * cap + a] = P.cdx[ax];
-                aux[(1 * 3 + ax) * cap + a] = P.cu[ax];
-                aux[(2 * 3 + ax) * cap + a] = P.gs[ax];
-                aux[(3 * 3 + ax) * cap + a] = P.fs[ax];
-            }
-            aux[12 * cap + a] = P.vmax2;
-            if (k == c.n_sub - 1) active_store<D, MD>(P, Bn, c, s, np, coef, fc, flags, md);
-        }
-        __syncthreads();
-    }
-}
-
 // Small islands: one 64-lane workgroup per packed wave, states in LDS.  A
 // wave holds islands of one size s at lanes [i s, (i+1) s).  Each island
 // advances on its own clock: per iteration it either jumps over a
@@ -1774,11 +1678,7 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
                                                      const float* __restrict__ drho_i, const float* __restrict__ j_i,
                                                      float* __restrict__ coef, float* __restrict__ fc,
                                                      uint32_t* __restrict__ flags,
-                                                     const uint32_t* __restrict__ counters, MdBuf md,
-                                                     const uint32_t* __restrict__ bigmember,
-                                                     const uint32_t* __restrict__ bigoff,
-                                                     const uint32_t* __restrict__ bigroot, float* gdx, float* gu,
-                                                     long long cap) {
+                                                     const uint32_t* __restrict__ counters, MdBuf md) {
     __shared__ float sdx[2][3 * WAVE];
     __shared__ float su[2][3 * WAVE];
     __shared__ float sw[MD ? 2 : 1][MD ? 3 * WAVE : 1];
@@ -1786,19 +1686,10 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
     __shared__ int sallow[WAVE];
     __shared__ CandData scd[WAVE * CAND_LDS];
     const uint32_t nw = counters[CNT_WAVES];
-    const uint32_t nbig = counters[CNT_BIG];
     const int lane = threadIdx.x;
     // first wave of size class lane + 1 (non-decreasing in the class)
     const uint32_t wb_lane = counters[CNT_WAVEBASE + 1 + lane];
-    // work items: the islands larger than a wave first (one workgroup
-    // each), then the packed waves of small islands
-    for (uint32_t item = blockIdx.x; item < nbig + nw; item += gridDim.x) {
-        if (item < nbig) {
-            island_big_one<D, MD>(item, A, Bn, np, c, bigmember, bigoff, bigroot, isize, alist, ccount, prefix,
-                                  cdata, drho_i, j_i, coef, fc, gdx, gu, cap, flags, md);
-            continue;
-        }
-        const uint32_t w = item - nbig;
+    for (uint32_t w = blockIdx.x; w < nw; w += gridDim.x) {
         // the wave's size class is the largest whose first wave is <= w;
         // its islands fill lanes [0, islands_here * size)
         const unsigned long long le = __ballot(wb_lane <= w);
@@ -1829,24 +1720,39 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
         __syncthreads();
         const CandData* rest = cdata + (valid ? P.off : 0);
         int k = 0, cur = 0;
+        // After a check that finds no stretch to jump, the island waits 1, 2,
+        // 4, .. 32 sub-steps before it checks again (a pair in lasting
+        // contact would fail every check); a jump resets the wait.  Every
+        // member of an island takes the same decisions (they share k and
+        // the island minimum), and plain sub-steps are always valid.
+        int wait = 0, backoff = 1;
         while (__any(valid && k < c.n_sub)) {
             const bool more = valid && k < c.n_sub;
+            const bool check = more && wait == 0;
             int allow = 0;
-            if (more)
+            if (check)
                 allow = free_allowance<D>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur], sveq, WAVE,
                                           c.n_sub - k);
             sallow[lane] = allow;
             __syncthreads();
             int m = allow;
-            for (int i = 0; i < isz; i++) m = min(m, sallow[ibase + i]);
+            if (check)
+                for (int i = 0; i < isz; i++) m = min(m, sallow[ibase + i]);
             if (more) {
                 if (m >= 2) {
                     active_jump<D, MD>(P, c, m, md);
                     k += m;
+                    backoff = 1;
                 } else {
                     active_substep<D, MD>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur],
                                           MD ? sw[cur] : nullptr, WAVE, md);
                     k += 1;
+                    if (check) {
+                        wait = backoff;
+                        backoff = min(2 * backoff, 32);
+                    } else {
+                        wait--;
+                    }
                 }
             }
 #pragma unroll
@@ -1860,6 +1766,110 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
         }
         if (valid) active_store<D, MD>(P, Bn, c, s, np, coef, fc, flags, md);
         __syncthreads();
+    }
+}
+
+// Islands larger than a wave: one 256-lane workgroup per island, states in
+// global scratch indexed by the active index (gdx, gu: [2][3][cap]; the
+// compensations and running sums follow gdx at 6 cap .. 19 cap).
+template <int D, bool MD>
+__global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np, PCfg c,
+                                                    const uint32_t* __restrict__ bigmember,
+                                                    const uint32_t* __restrict__ bigoff,
+                                                    const uint32_t* __restrict__ bigroot,
+                                                    const uint32_t* __restrict__ isize,
+                                                    const uint32_t* __restrict__ alist,
+                                                    const uint32_t* __restrict__ ccount,
+                                                    const unsigned long long* __restrict__ prefix,
+                                                    const CandData* __restrict__ cdata,
+                                                    const float* __restrict__ drho_i, const float* __restrict__ j_i,
+                                                    float* __restrict__ coef, float* __restrict__ fc,
+                                                    float* gdx, float* gu, long long cap,
+                                                    uint32_t* __restrict__ flags,
+                                                    const uint32_t* __restrict__ counters, MdBuf md) {
+    // MD scratch: spin [2][3][cap], wall tangential forces [9][cap], wall sides [cap]
+    float* gw = md.gmd;
+    float* gwt = md.gmd + 6 * cap;
+    uint32_t* gside = (uint32_t*)(md.gmd + 15 * cap);
+    const uint32_t nbig = counters[CNT_BIG];
+    for (uint32_t ib = blockIdx.x; ib < nbig; ib += gridDim.x) {
+        uint32_t base = bigoff[ib];
+        uint32_t sz = isize[bigroot[ib]];
+        for (uint32_t i = threadIdx.x; i < sz; i += 256) {
+            uint32_t a = bigmember[base + i];
+            uint32_t s = alist[a];
+#pragma unroll
+            for (int ax = 0; ax < 3; ax++) {
+                gdx[(0 * 3 + ax) * cap + a] = 0.f;
+                gu[(0 * 3 + ax) * cap + a] = ax < D ? A.u[ax][s] : 0.f;
+            }
+            if (MD) {
+                gw[(0 * 3 + 0) * cap + a] = D == 3 ? A.w[0][s] : 0.f;
+                gw[(0 * 3 + 1) * cap + a] = D == 3 ? A.w[1][s] : 0.f;
+                gw[(0 * 3 + 2) * cap + a] = D == 3 ? A.w[2][s] : A.w[0][s];
+            }
+        }
+        __syncthreads();
+        // per-member state is re-read from scratch each sub-step (a lane may own several members)
+        for (int k = 0; k < c.n_sub; k++) {
+            int cur = k & 1;
+            for (uint32_t i = threadIdx.x; i < sz; i += 256) {
+                uint32_t a = bigmember[base + i];
+                uint32_t s = alist[a];
+                Active<D> P;
+                active_load<D, MD>(P, A, c, s, drho_i, j_i, np, ccount, prefix, md);
+#pragma unroll
+                for (int ax = 0; ax < D; ax++) {
+                    P.dx[ax] = gdx[(cur * 3 + ax) * cap + a];
+                    P.u[ax] = gu[(cur * 3 + ax) * cap + a];
+                }
+                if (MD) {
+#pragma unroll
+                    for (int ax = 0; ax < 3; ax++) P.W[ax] = gw[(cur * 3 + ax) * cap + a];
+                    if (k > 0) {
+#pragma unroll
+                        for (int ax = 0; ax < 3; ax++)
+#pragma unroll
+                            for (int b = 0; b < 3; b++) P.wT[ax][b] = gwt[(3 * ax + b) * cap + a];
+                        P.wside = gside[a];
+                    }
+                }
+                float* aux = gdx + 6 * cap;
+                if (k > 0) {
+#pragma unroll
+                    for (int ax = 0; ax < D; ax++) {
+                        P.cdx[ax] = aux[(0 * 3 + ax) * cap + a];
+                        P.cu[ax] = aux[(1 * 3 + ax) * cap + a];
+                        P.gs[ax] = aux[(2 * 3 + ax) * cap + a];
+                        P.fs[ax] = aux[(3 * 3 + ax) * cap + a];
+                    }
+                    P.vmax2 = aux[12 * cap + a];
+                }
+                active_substep<D, MD>(P, c, cdata + P.off, P.cnt, cdata + P.off, gdx + cur * 3 * cap,
+                                      gu + cur * 3 * cap, MD ? gw + cur * 3 * cap : nullptr, (int)cap, md);
+                if (MD) {
+#pragma unroll
+                    for (int ax = 0; ax < 3; ax++) {
+                        gw[((cur ^ 1) * 3 + ax) * cap + a] = P.W[ax];
+#pragma unroll
+                        for (int b = 0; b < 3; b++) gwt[(3 * ax + b) * cap + a] = P.wT[ax][b];
+                    }
+                    gside[a] = P.wside;
+                }
+#pragma unroll
+                for (int ax = 0; ax < D; ax++) {
+                    gdx[((cur ^ 1) * 3 + ax) * cap + a] = P.dx[ax];
+                    gu[((cur ^ 1) * 3 + ax) * cap + a] = P.u[ax];
+                    aux[(0 * 3 + ax) * cap + a] = P.cdx[ax];
+                    aux[(1 * 3 + ax) * cap + a] = P.cu[ax];
+                    aux[(2 * 3 + ax) * cap + a] = P.gs[ax];
+                    aux[(3 * 3 + ax) * cap + a] = P.fs[ax];
+                }
+                aux[12 * cap + a] = P.vmax2;
+                if (k == c.n_sub - 1) active_store<D, MD>(P, Bn, c, s, np, coef, fc, flags, md);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -2322,15 +2332,21 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
                            b.aidx, b.loc, b.cdata, md, b.counters);
     }
     const dim3 gsmall(std::max<unsigned>(grid_act * 4, 256u));
-    // one launch runs the islands larger than a wave and the packed waves
-    if (c.contact == PIBM_CONTACT_HERTZ_MINDLIN)
+    if (c.contact == PIBM_CONTACT_HERTZ_MINDLIN) {
         hipLaunchKernelGGL((k_island_small<D, true>), gsmall, dim3(64), 0, s, b.A, b.Bn, np, c, b.lanemember, b.alist,
                            b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.coef, b.fc, b.flags,
-                           b.counters, md, b.bigmember, b.bigoff, b.bigroot, b.gdx, b.gu, (long long)np);
-    else
+                           b.counters, md);
+        hipLaunchKernelGGL((k_island_big<D, true>), dim3(256), dim3(256), 0, s, b.A, b.Bn, np, c, b.bigmember,
+                           b.bigoff, b.bigroot, b.isize, b.alist, b.ccount, b.prefix, b.cdata, b.drho_i, b.j_i,
+                           b.coef, b.fc, b.gdx, b.gu, (long long)np, b.flags, b.counters, md);
+    } else {
         hipLaunchKernelGGL((k_island_small<D, false>), gsmall, dim3(64), 0, s, b.A, b.Bn, np, c, b.lanemember, b.alist,
                            b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.coef, b.fc, b.flags,
-                           b.counters, md, b.bigmember, b.bigoff, b.bigroot, b.gdx, b.gu, (long long)np);
+                           b.counters, md);
+        hipLaunchKernelGGL((k_island_big<D, false>), dim3(256), dim3(256), 0, s, b.A, b.Bn, np, c, b.bigmember,
+                           b.bigoff, b.bigroot, b.isize, b.alist, b.ccount, b.prefix, b.cdata, b.drho_i, b.j_i,
+                           b.coef, b.fc, b.gdx, b.gu, (long long)np, b.flags, b.counters, md);
+    }
 }
 
 void particles_dem(int D, PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s) {

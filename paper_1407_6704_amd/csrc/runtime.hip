@@ -101,6 +101,8 @@ struct pibm_ctx {
     std::string err;
     // phase timing: a ring of event rows, PIBM_NUM_PHASES + 1 events per step
     bool prof = false;
+    int prof_every = 1;          // events on every n-th step
+    int64_t prof_tick = 0;
     std::vector<hipEvent_t> ev;
     int ev_rows = 0, ev_used = 0;
     double phase_ms[PIBM_NUM_PHASES] = {0, 0, 0, 0, 0, 0};
@@ -792,7 +794,7 @@ pibm_status pibm_step(pibm_ctx* c, int32_t n_steps) {
     if (c->np > 0 && !c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
     for (int it = 0; it < n_steps; it++) {
         int row = -1;
-        if (c->prof) {
+        if (c->prof && c->prof_tick++ % c->prof_every == 0) {
             if (c->ev_used == c->ev_rows)
                 if (pibm_status s = drain_events(c)) return s;
             row = c->ev_used++;
@@ -906,9 +908,11 @@ pibm_status pibm_set_profiling(pibm_ctx* c, int enable) {
             if (pibm_status s = check_hip(c, hipEventCreate(&e), "hipEventCreate")) return s;
         c->ev_rows = PROF_ROWS;
     }
-    if (!enable && c->prof)
+    if (enable <= 0 && c->prof)
         if (pibm_status s = drain_events(c)) return s;
-    c->prof = enable != 0;
+    c->prof = enable > 0;
+    c->prof_every = enable > 0 ? enable : 1;
+    c->prof_tick = 0;
     return PIBM_OK;
 }
 

@@ -295,11 +295,13 @@ class Sim:
 
     PHASES = ("cell_list", "moments", "interp", "dem", "spread", "collide")
 
-    def set_profiling(self, on=True):
-        self._check(self.lib.pibm_set_profiling(self.ctx, 1 if on else 0))
+    def set_profiling(self, on=True, every=1):
+        """Phase events on every `every`-th step while on (see phase_times)."""
+        self._check(self.lib.pibm_set_profiling(self.ctx, max(1, int(every)) if on else 0))
 
     def phase_times(self):
-        """Milliseconds per phase and the step count since the last call."""
+        """Milliseconds per phase summed over the recorded steps, and their
+        number, since the last call."""
         ms = (C.c_double * 6)()
         steps = C.c_int64()
         self._check(self.lib.pibm_phase_times(self.ctx, ms, C.byref(steps)))

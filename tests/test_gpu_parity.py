@@ -510,3 +510,22 @@ def test_dense_tile_spreads_unstaged(P, W, orc, lat):
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=2, label="dense")
     assert r["eu"] <= 1e-5 and r["er"] <= 1e-6 and r["efh"] <= 1e-4
     assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5
+
+
+def test_phase_times_sampled(P):
+    """Phase events on every third step: 7 steps record 3 (the first, the
+    fourth and the seventh), each phase non-negative."""
+    _flush("phase times every 3")
+    cfg = P.make_config(lattice=9, n=(32, 24, 1), tau=0.8, contact="lsd")
+    sim = P.Sim(cfg, 2)
+    X = np.array([[10.0, 20.0], [12.0, 12.5]])
+    sim.set_particles(X, np.zeros((2, 2)), np.array([0.5, 0.5]), np.array([2.0, 2.0]))
+    sim.set_profiling(True, every=3)
+    sim.step(7)
+    ph, n = sim.phase_times()
+    assert n == 3
+    assert all(v >= 0.0 for v in ph.values()) and ph["collide"] > 0.0
+    sim.set_profiling(False)
+    sim.step(2)
+    ph, n = sim.phase_times()
+    assert n == 0
