@@ -3,19 +3,22 @@
 Default workload: D2Q9 2048^2, tau 0.6, 500k disks (d ~ U[0.3, 0.8],
 density ratio 2.5, upper 60 % of a closed cavity), FP32, linear
 spring-dashpot contacts with 677 sub-steps.  A "step" is one full coupled
-step: moments, cell list, interpolation, DEM, spreading, collision+streaming.
+step: cell list, moments (3D), interpolation, DEM, spreading,
+collision+streaming.
 Inputs are seeded synthetic (no dataset); the timed region starts with all
 state resident in HBM.
 
 Prints ONE JSON line.  Besides the contract fields it carries
   roofline      - the dominant kernel against MI355X HBM peak (8 TB/s), from
                   HIP events recorded on the library's stream around every
-                  phase during the timed region (algorithmic bytes / time)
+                  phase of every tenth timed step (algorithmic bytes / time)
   cpu_baseline  - the FP64 oracle on the host cores, on a bounded sample
   extra         - the same measurement for the D3Q19 256^3 / 2M-sphere case
                   in FP32 and with FP16 deviation storage, the FP16-vs-FP32
-                  field errors, and the adjoint/forward cost ratio on the
-                  D2Q9 512^2 / 10k-particle differentiation workload
+                  field errors, the D3Q15/Lagrange and Hertz-Mindlin variants
+                  of that case, the hybrid obstacle case, and the
+                  adjoint/forward cost ratio on the D2Q9 512^2 /
+                  10k-particle differentiation workload
 """
 from __future__ import annotations
 
@@ -38,20 +41,20 @@ PROFILE_EVERY = 10       # timed steps per step that records the phase events
 # device copy of known size (--copy-probe).  Keyed by (kernel, workload); the
 # entry only applies while the kernel's source file hashes to `source_sha`.
 MEASURED_TRAFFIC = {
-    ("collide", "c1"): {"fetch_bytes": 90151.3 * 1024 * 1.9999, "write_bytes": 150202.7 * 1024,
-                       "source_sha": "b5f944bdaea84603"},
-    ("spread", "c1"): {"fetch_bytes": 47812.9 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
-                      "source_sha": "4fa3b99e89e7bf9f"},
-    ("interp", "c1"): {"fetch_bytes": 98368.1 * 1024 * 1.9999, "write_bytes": 27473.5 * 1024,
-                      "source_sha": "4fa3b99e89e7bf9f"},
-    ("collide", "c2"): {"fetch_bytes": 720964.2 * 1024 * 1.9999, "write_bytes": 1256040.4 * 1024,
-                       "source_sha": "b5f944bdaea84603"},
-    ("moments", "c2"): {"fetch_bytes": 622610.7 * 1024 * 1.9999, "write_bytes": 262144.0 * 1024,
-                       "source_sha": "b5f944bdaea84603"},
-    ("spread", "c2"): {"fetch_bytes": 691901.5 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
-                      "source_sha": "4fa3b99e89e7bf9f"},
-    ("interp", "c2"): {"fetch_bytes": 396354.4 * 1024 * 1.9999, "write_bytes": 180024.3 * 1024,
-                      "source_sha": "4fa3b99e89e7bf9f"},
+    ("collide", "c1"): {"fetch_bytes": 90158.6 * 1024 * 1.9999, "write_bytes": 150213.6 * 1024,
+                       "source_sha": "6c24cf98d9e531f8"},
+    ("spread", "c1"): {"fetch_bytes": 47516.6 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
+                      "source_sha": "70c97d9215d03563"},
+    ("interp", "c1"): {"fetch_bytes": 98426.9 * 1024 * 1.9999, "write_bytes": 27472.3 * 1024,
+                      "source_sha": "70c97d9215d03563"},
+    ("collide", "c2"): {"fetch_bytes": 720973.8 * 1024 * 1.9999, "write_bytes": 1255980.9 * 1024,
+                       "source_sha": "6c24cf98d9e531f8"},
+    ("moments", "c2"): {"fetch_bytes": 336723.3 * 1024 * 1.9999, "write_bytes": 133120.0 * 1024,
+                       "source_sha": "6c24cf98d9e531f8"},
+    ("spread", "c2"): {"fetch_bytes": 693546.0 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
+                      "source_sha": "70c97d9215d03563"},
+    ("interp", "c2"): {"fetch_bytes": 397785.5 * 1024 * 1.9999, "write_bytes": 180028.5 * 1024,
+                      "source_sha": "70c97d9215d03563"},
 }
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
 
