@@ -11,7 +11,7 @@ state resident in HBM.
 Prints ONE JSON line.  Besides the contract fields it carries
   roofline      - the dominant kernel against MI355X HBM peak (8 TB/s), from
                   HIP events recorded on the library's stream around every
-                  phase of every tenth timed step (algorithmic bytes / time)
+                  phase of ten evenly spaced timed steps (algorithmic bytes / time)
   cpu_baseline  - the FP64 oracle on the host cores, on a bounded sample
   extra         - the same measurement for the D3Q19 256^3 / 2M-sphere case
                   in FP32 and with FP16 deviation storage, the FP16-vs-FP32
@@ -34,26 +34,26 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 1 << 30
-PROFILE_EVERY = 10       # timed steps per step that records the phase events
+PROFILE_SAMPLES = 10     # timed steps that record the phase events (evenly spaced)
 
 # HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, then
 # WRITE_SIZE, each in its own run), scaled by the same counters over a plain
 # device copy of known size (--copy-probe).  Keyed by (kernel, workload); the
 # entry only applies while the kernel's source file hashes to `source_sha`.
 MEASURED_TRAFFIC = {
-    ("collide", "c1"): {"fetch_bytes": 90158.6 * 1024 * 1.9999, "write_bytes": 150213.6 * 1024,
-                       "source_sha": "6c24cf98d9e531f8"},
-    ("spread", "c1"): {"fetch_bytes": 47516.6 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
+    ("collide", "c1"): {"fetch_bytes": 90158.6 * 1024 * 1.9999, "write_bytes": 150216.6 * 1024,
+                       "source_sha": "4ef8dfd1a49054f3"},
+    ("spread", "c1"): {"fetch_bytes": 47517.8 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
                       "source_sha": "70c97d9215d03563"},
-    ("interp", "c1"): {"fetch_bytes": 98426.9 * 1024 * 1.9999, "write_bytes": 27472.3 * 1024,
+    ("interp", "c1"): {"fetch_bytes": 98032.9 * 1024 * 1.9999, "write_bytes": 27473.1 * 1024,
                       "source_sha": "70c97d9215d03563"},
-    ("collide", "c2"): {"fetch_bytes": 720973.8 * 1024 * 1.9999, "write_bytes": 1255980.9 * 1024,
-                       "source_sha": "6c24cf98d9e531f8"},
-    ("moments", "c2"): {"fetch_bytes": 336723.3 * 1024 * 1.9999, "write_bytes": 133120.0 * 1024,
-                       "source_sha": "6c24cf98d9e531f8"},
-    ("spread", "c2"): {"fetch_bytes": 693546.0 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
+    ("collide", "c2"): {"fetch_bytes": 720974.5 * 1024 * 1.9999, "write_bytes": 1253253.9 * 1024,
+                       "source_sha": "4ef8dfd1a49054f3"},
+    ("moments", "c2"): {"fetch_bytes": 336723.6 * 1024 * 1.9999, "write_bytes": 133120.0 * 1024,
+                       "source_sha": "4ef8dfd1a49054f3"},
+    ("spread", "c2"): {"fetch_bytes": 693514.0 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
                       "source_sha": "70c97d9215d03563"},
-    ("interp", "c2"): {"fetch_bytes": 397785.5 * 1024 * 1.9999, "write_bytes": 180028.5 * 1024,
+    ("interp", "c2"): {"fetch_bytes": 397524.4 * 1024 * 1.9999, "write_bytes": 180025.0 * 1024,
                       "source_sha": "70c97d9215d03563"},
 }
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
@@ -142,9 +142,9 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
         sim.set_bodies(body, area)
     sim.step(warmup)
     sim.synchronize()
-    # phase events on every PROFILE_EVERY-th timed step: each recorded step
-    # carries 7 event records, which add a few microseconds each
-    sim.set_profiling(True, every=PROFILE_EVERY)
+    # phase events on PROFILE_SAMPLES evenly spaced timed steps: each recorded
+    # step carries 7 event records, which add a few microseconds each
+    sim.set_profiling(True, every=max(1, steps // PROFILE_SAMPLES))
     sim.phase_times()
     stream = sim.stream
     ev0 = torch.cuda.Event(enable_timing=True)
