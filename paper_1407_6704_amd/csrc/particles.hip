@@ -1459,23 +1459,35 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
         else wall_force<D>(P, c, F);
     }
     const int n1 = min(P.cnt, nfirst);
-    // the next candidate is loaded while the current one is evaluated (a
-    // sub-step is a serial latency chain when few islands are left)
+    // the next candidate and its partner's state are loaded while the
+    // current one is evaluated (a sub-step is a serial latency chain when few
+    // islands are left); the partner states do not change within a sub-step
     CandData nx{};
-    if (P.cnt > 0) nx = (0 < n1) ? first[0] : rest[0];
-    for (int k = 0; k < P.cnt; k++) {
-        const CandData cd = nx;
-        if (k + 1 < P.cnt) nx = (k + 1 < n1) ? first[k + 1] : rest[k + 1];
-        float odx[3] = {0, 0, 0}, ou[3] = {0, 0, 0};
+    float ndx[3] = {0, 0, 0}, nu[3] = {0, 0, 0}, nw[3] = {0, 0, 0};
+    auto fetch = [&](int k) {
+        nx = (k < n1) ? first[k] : rest[k];
 #pragma unroll
         for (int a = 0; a < D; a++) {
-            odx[a] = sdx[a * stride + cd.local];
-            ou[a] = su[a * stride + cd.local];
+            ndx[a] = sdx[a * stride + nx.local];
+            nu[a] = su[a * stride + nx.local];
         }
         if (MD) {
-            float ow[3];
 #pragma unroll
-            for (int a = 0; a < 3; a++) ow[a] = sw[a * stride + cd.local];
+            for (int a = 0; a < 3; a++) nw[a] = sw[a * stride + nx.local];
+        }
+    };
+    if (P.cnt > 0) fetch(0);
+    for (int k = 0; k < P.cnt; k++) {
+        const CandData cd = nx;
+        float odx[3], ou[3], ow[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            odx[a] = ndx[a];
+            ou[a] = nu[a];
+            ow[a] = nw[a];
+        }
+        if (k + 1 < P.cnt) fetch(k + 1);
+        if (MD) {
             pair_force_md<D>(P, cd, md.cmd + P.off + k, odx, ou, ow, c, F, tq);
         } else {
             pair_force<D>(P, cd, odx, ou, c, F);
