@@ -216,20 +216,28 @@ def test_coupled_step_free_particles(P, W, orc, lat, interp, bl):
     assert r["eu"] <= 3e-5 and r["ex"] <= 3e-5 and r["ev"] <= 3e-5
 
 
-@pytest.mark.parametrize("lat,interp,bl", [(19, "delta", 0), (15, "lagrange", 0), (19, "delta", 2)])
+@pytest.mark.parametrize("lat,interp,bl", [(19, "delta", 0), (15, "lagrange", 0), (19, "delta", 2),
+                                            (9, "delta", 2)])
 def test_moments_only_where_gathered(P, W, orc, lat, interp, bl):
     """The moments pass of the coupled step skips the node rows that no
     particle's gather stencil reaches.  Particles confined to a band
-    (y in [6, 9], z in [9, 12]) of a box whose x rows are long enough for a
-    workgroup to span at most four rows, several exactly on the band's edges
-    (their stencils end on the last rows computed): one step matches the
-    oracle as in the free-particle case, also with bins of four cells."""
+    (3D: y in [6, 9], z in [9, 12]; 2D: y in [15, 20]) of a box whose x rows
+    are long enough for a workgroup to span at most four rows, several
+    exactly on the band's edges (their stencils end on the last rows
+    computed): one step matches the oracle as in the free-particle case,
+    also with bins of four cells (in 2D the only path with a moments pass)."""
     _flush(f"moments rows {lat} {interp} bin_log2={bl}")
-    n = (100, 16, 16)
+    D = 2 if lat == 9 else 3
     rng = np.random.default_rng(77)
-    cand = np.stack([rng.uniform(1.0, 99.0, 400), rng.uniform(6.0, 9.0, 400), rng.uniform(9.0, 12.0, 400)])
-    cand[1, :8] = [6.0, 9.0, 6.0, 9.0, 6.0, 9.0, 6.0, 9.0]
-    cand[2, :8] = [9.0, 9.0, 12.0, 12.0, 9.0, 12.0, 9.0, 12.0]
+    if D == 3:
+        n = (100, 16, 16)
+        cand = np.stack([rng.uniform(1.0, 99.0, 400), rng.uniform(6.0, 9.0, 400), rng.uniform(9.0, 12.0, 400)])
+        cand[1, :8] = [6.0, 9.0, 6.0, 9.0, 6.0, 9.0, 6.0, 9.0]
+        cand[2, :8] = [9.0, 9.0, 12.0, 12.0, 9.0, 12.0, 9.0, 12.0]
+    else:
+        n = (100, 40, 1)
+        cand = np.stack([rng.uniform(1.0, 99.0, 400), rng.uniform(15.0, 20.0, 400)])
+        cand[1, :6] = [15.0, 20.0, 15.0, 20.0, 15.0, 20.0]
     d_all = rng.uniform(0.3, 0.5, 400)
     keep = [0]
     for i in range(1, 400):
@@ -240,9 +248,11 @@ def test_moments_only_where_gathered(P, W, orc, lat, interp, bl):
     d = d_all[keep].astype(np.float32).astype(np.float64)
     npart = X.shape[1]
     assert npart > 60
-    U = (1e-4 * rng.standard_normal((3, npart))).astype(np.float32).astype(np.float64)
+    U = (1e-4 * rng.standard_normal((D, npart))).astype(np.float32).astype(np.float64)
     rp = rng.uniform(1.5, 3.0, npart).astype(np.float32).astype(np.float64)
-    cfg = P.make_config(lattice=lat, n=n, tau=0.7, gravity=[0.0, 0.0, -1e-5], n_sub=200, contact="lsd",
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-5
+    cfg = P.make_config(lattice=lat, n=n, tau=0.7, gravity=g, n_sub=200, contact="lsd",
                         interp=interp, bin_log2=bl)
     w = W.C0.replace(lattice=lat, n=n)
     sim0 = P.Sim(P.make_config(lattice=lat, n=n, tau=0.7, contact="none"), 0)
