@@ -1922,7 +1922,7 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     __shared__ uint32_t cs[NR * (HX + 1)];       // per row: LDS index of each cell's first particle, then the end
     __shared__ uint32_t rowbase[NR + 1], rowg0[NR];
     __shared__ float sp[MAXP * PW];
-    __shared__ int sb[MAXP];                     // x index of each staged particle's first stencil node
+    __shared__ short sb[MAXP];                   // x index of each staged particle's first stencil node (short: 8 workgroups per CU fit the LDS in 3D)
     __shared__ uint8_t rowof[MAXP];              // halo row of each staged particle
     __shared__ uint32_t scan4[4];
     static_assert(NR <= 255, "halo rows must fit the row table");
