@@ -1901,7 +1901,7 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
 // result); a tile that no particle reaches writes zeros at once.
 template <int D> struct CsrTile;
 // MAXP: particles staged in LDS per tile (the halo of a 3D tile holds about
-// 200 at 0.24 particles per cell; 256 slots leave room for 7 workgroups per
+// 200 at 0.24 particles per cell; 256 slots leave room for 8 workgroups per
 // CU, and a fuller halo takes the unstaged path)
 template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4, MAXP = 256; };
 template <> struct CsrTile<2> { static constexpr int TX = 32, TY = 16, TZ = 1, MAXP = 384; };
