@@ -41,20 +41,20 @@ PROFILE_SAMPLES = 10     # timed steps that record the phase events (evenly spac
 # device copy of known size (--copy-probe).  Keyed by (kernel, workload); the
 # entry only applies while the kernel's source file hashes to `source_sha`.
 MEASURED_TRAFFIC = {
-    ("collide", "c1"): {"fetch_bytes": 90158.6 * 1024 * 1.9999, "write_bytes": 150210.3 * 1024,
+    ("collide", "c1"): {"fetch_bytes": 90158.6 * 1024 * 1.9999, "write_bytes": 150218.4 * 1024,
                        "source_sha": "4ef8dfd1a49054f3"},
-    ("spread", "c1"): {"fetch_bytes": 47518.4 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
-                      "source_sha": "a01530440f5350d3"},
-    ("interp", "c1"): {"fetch_bytes": 98087.3 * 1024 * 1.9999, "write_bytes": 27472.6 * 1024,
-                      "source_sha": "a01530440f5350d3"},
-    ("collide", "c2"): {"fetch_bytes": 720974.5 * 1024 * 1.9999, "write_bytes": 1253323.0 * 1024,
+    ("spread", "c1"): {"fetch_bytes": 47519.3 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
+                      "source_sha": "6df6086ed16e9cfb"},
+    ("interp", "c1"): {"fetch_bytes": 98086.6 * 1024 * 1.9999, "write_bytes": 27472.5 * 1024,
+                      "source_sha": "6df6086ed16e9cfb"},
+    ("collide", "c2"): {"fetch_bytes": 720974.6 * 1024 * 1.9999, "write_bytes": 1253238.7 * 1024,
                        "source_sha": "4ef8dfd1a49054f3"},
-    ("moments", "c2"): {"fetch_bytes": 336723.4 * 1024 * 1.9999, "write_bytes": 133120.0 * 1024,
+    ("moments", "c2"): {"fetch_bytes": 336723.5 * 1024 * 1.9999, "write_bytes": 133120.0 * 1024,
                        "source_sha": "4ef8dfd1a49054f3"},
-    ("spread", "c2"): {"fetch_bytes": 693553.6 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
-                      "source_sha": "a01530440f5350d3"},
-    ("interp", "c2"): {"fetch_bytes": 397610.0 * 1024 * 1.9999, "write_bytes": 180025.7 * 1024,
-                      "source_sha": "a01530440f5350d3"},
+    ("spread", "c2"): {"fetch_bytes": 704234.6 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
+                      "source_sha": "6df6086ed16e9cfb"},
+    ("interp", "c2"): {"fetch_bytes": 397662.1 * 1024 * 1.9999, "write_bytes": 180023.2 * 1024,
+                      "source_sha": "6df6086ed16e9cfb"},
 }
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
 
