@@ -857,23 +857,18 @@ __global__ __launch_bounds__(256) void k_uf_flatten(uint32_t* parent, uint32_t* 
     }
 }
 
-// Wave plan of the small-island classes and offsets of the large islands
-// (one thread; the counts come from the class counters).
-__device__ void island_plan_serial(uint32_t* counters, const uint32_t* __restrict__ isize,
-                                   const uint32_t* __restrict__ bigroot, uint32_t* __restrict__ bigoff) {
-    uint32_t waves = 0;
-    for (int s = 1; s <= WAVE; s++) {
-        counters[CNT_WAVEBASE + s] = waves;
-        uint32_t per = WAVE / s;
-        waves += (counters[CNT_CLASS + s] + per - 1) / per;
-    }
-    counters[CNT_WAVES] = waves;
-    uint32_t nbig = counters[CNT_CLASS + WAVE + 1];
-    counters[CNT_BIG] = nbig;
-    uint32_t off = 0;
-    for (uint32_t k = 0; k < nbig; k++) {
-        bigoff[k] = off;
-        off += isize[bigroot[k]];
+// Wave plan of the small-island size classes, computed by wave 0 of the
+// block (one class per lane, then a wave scan): wb[s] = first wave of class
+// s = 1..64 (a wave holds 64 / s islands of size s), wb[0] = all waves.
+// cls[s] is the number of islands of size s.  The caller synchronises.
+__device__ __forceinline__ void wave_plan(const uint32_t* cls, uint32_t* wb) {
+    if (threadIdx.x < WAVE) {
+        const uint32_t s = threadIdx.x + 1;
+        const uint32_t per = WAVE / s;
+        const uint32_t v = (cls[s] + per - 1) / per;
+        const uint32_t inc = wave_inclusive_scan<uint32_t>(v);
+        wb[s] = inc - v;
+        if (s == WAVE) wb[0] = inc;
     }
 }
 
@@ -947,15 +942,7 @@ __global__ __launch_bounds__(256) void k_island_place(const uint32_t* __restrict
                                                       uint32_t* __restrict__ counters) {
     __shared__ uint32_t wb[WAVE + 1];
     __shared__ uint32_t scan4[4];
-    if (threadIdx.x == 0) {
-        uint32_t waves = 0;
-        for (int s = 1; s <= WAVE; s++) {
-            wb[s] = waves;
-            const uint32_t per = WAVE / s;
-            waves += (counters[CNT_CLASS + s] + per - 1) / per;
-        }
-        wb[0] = waves;
-    }
+    wave_plan(counters + CNT_CLASS, wb);
     const uint32_t nbig = counters[CNT_CLASS + WAVE + 1];
     uint32_t run = 0;
     for (uint32_t k0 = 0; k0 < nbig; k0 += 256) {
@@ -1115,17 +1102,15 @@ __global__ __launch_bounds__(SETUP_THREADS) void k_island_setup(
         if (cls == WAVE + 1) bigroot[r] = a;
     }
     __syncthreads();
+    wave_plan(ccls, wbase);
+    __syncthreads();
+    if (t < WAVE) {
+        counters[CNT_WAVEBASE + t + 1] = wbase[t + 1];
+        counters[CNT_CLASS + t + 1] = ccls[t + 1];
+    }
     if (t == 0) {
-        uint32_t waves = 0;
-        for (int sz = 1; sz <= WAVE; sz++) {
-            wbase[sz] = waves;
-            counters[CNT_WAVEBASE + sz] = waves;
-            counters[CNT_CLASS + sz] = ccls[sz];
-            uint32_t per = WAVE / sz;
-            waves += (ccls[sz] + per - 1) / per;
-        }
-        nwaves = waves;
-        counters[CNT_WAVES] = waves;
+        nwaves = wbase[0];
+        counters[CNT_WAVES] = wbase[0];
         const uint32_t nbig = ccls[WAVE + 1];
         counters[CNT_CLASS + WAVE + 1] = nbig;
         counters[CNT_BIG] = nbig;
