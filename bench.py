@@ -41,20 +41,20 @@ PROFILE_SAMPLES = 10     # timed steps that record the phase events (evenly spac
 # device copy of known size (--copy-probe).  Keyed by (kernel, workload); the
 # entry only applies while the kernel's source file hashes to `source_sha`.
 MEASURED_TRAFFIC = {
-    ("collide", "c1"): {"fetch_bytes": 90158.6 * 1024 * 1.9999, "write_bytes": 150218.4 * 1024,
+    ("collide", "c1"): {"fetch_bytes": 90158.6 * 1024 * 1.9999, "write_bytes": 150214.1 * 1024,
                        "source_sha": "4ef8dfd1a49054f3"},
-    ("spread", "c1"): {"fetch_bytes": 47519.3 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
-                      "source_sha": "6df6086ed16e9cfb"},
-    ("interp", "c1"): {"fetch_bytes": 98086.6 * 1024 * 1.9999, "write_bytes": 27472.5 * 1024,
-                      "source_sha": "6df6086ed16e9cfb"},
-    ("collide", "c2"): {"fetch_bytes": 720974.6 * 1024 * 1.9999, "write_bytes": 1253238.7 * 1024,
+    ("spread", "c1"): {"fetch_bytes": 47517.5 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
+                      "source_sha": "e67f83bacf182cec"},
+    ("interp", "c1"): {"fetch_bytes": 98291.9 * 1024 * 1.9999, "write_bytes": 27474.0 * 1024,
+                      "source_sha": "e67f83bacf182cec"},
+    ("collide", "c2"): {"fetch_bytes": 720974.5 * 1024 * 1.9999, "write_bytes": 1253280.8 * 1024,
                        "source_sha": "4ef8dfd1a49054f3"},
     ("moments", "c2"): {"fetch_bytes": 336723.5 * 1024 * 1.9999, "write_bytes": 133120.0 * 1024,
                        "source_sha": "4ef8dfd1a49054f3"},
-    ("spread", "c2"): {"fetch_bytes": 704234.6 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
-                      "source_sha": "6df6086ed16e9cfb"},
-    ("interp", "c2"): {"fetch_bytes": 397662.1 * 1024 * 1.9999, "write_bytes": 180023.2 * 1024,
-                      "source_sha": "6df6086ed16e9cfb"},
+    ("spread", "c2"): {"fetch_bytes": 704123.3 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
+                      "source_sha": "e67f83bacf182cec"},
+    ("interp", "c2"): {"fetch_bytes": 397785.0 * 1024 * 1.9999, "write_bytes": 180022.1 * 1024,
+                      "source_sha": "e67f83bacf182cec"},
 }
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
 
