@@ -44,17 +44,17 @@ MEASURED_TRAFFIC = {
     ("collide", "c1"): {"fetch_bytes": 90158.6 * 1024 * 1.9999, "write_bytes": 150214.1 * 1024,
                        "source_sha": "4ef8dfd1a49054f3"},
     ("spread", "c1"): {"fetch_bytes": 47517.5 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
-                      "source_sha": "e67f83bacf182cec"},
+                      "source_sha": "7b3ffaebd410b3ee"},
     ("interp", "c1"): {"fetch_bytes": 98291.9 * 1024 * 1.9999, "write_bytes": 27474.0 * 1024,
-                      "source_sha": "e67f83bacf182cec"},
+                      "source_sha": "7b3ffaebd410b3ee"},
     ("collide", "c2"): {"fetch_bytes": 720974.5 * 1024 * 1.9999, "write_bytes": 1253280.8 * 1024,
                        "source_sha": "4ef8dfd1a49054f3"},
     ("moments", "c2"): {"fetch_bytes": 336723.5 * 1024 * 1.9999, "write_bytes": 133120.0 * 1024,
                        "source_sha": "4ef8dfd1a49054f3"},
     ("spread", "c2"): {"fetch_bytes": 704123.3 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
-                      "source_sha": "e67f83bacf182cec"},
+                      "source_sha": "7b3ffaebd410b3ee"},
     ("interp", "c2"): {"fetch_bytes": 397785.0 * 1024 * 1.9999, "write_bytes": 180022.1 * 1024,
-                      "source_sha": "e67f83bacf182cec"},
+                      "source_sha": "7b3ffaebd410b3ee"},
 }
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
 

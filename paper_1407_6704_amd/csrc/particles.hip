@@ -564,7 +564,8 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
 // ---------------------------------------------------------------------------
 // DEM: classification and the free-particle closed form
 // ---------------------------------------------------------------------------
-// Neighbour scan over the 3^D bins around particle s.  Counting mode: the
+// Neighbour scan over the bins around particle s that its reach meets (at
+// most (2H + 1)^D, usually 2^D).  Counting mode: the
 // number of candidates within (d_s + d_t)/2 + skin, and whether any lies
 // within (d_s + d_t)/2 + thr.  Collect mode: the candidates that are active,
 // in scan order (bins ascending, sorted order within a bin).
