@@ -284,7 +284,7 @@ def main():
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+        print("bench.py: this library runs on one GPU only; multi-GPU runs are not supported "
               "(the lattice would shard into slabs with a halo exchange, which is not built).",
               file=sys.stderr)
         sys.exit(2)

@@ -8,7 +8,7 @@ diameters with their relaxation times and time steps.
   particle speed 1e-5 relative;
 * the settling speeds after 20,000 steps: increasing with the diameter and
   within 25 % of Stokes' law (Eq. lbm14).  The paper's own numbers agree
-  with Stokes to 1.5 % after a calibration it does not print; this build's
+  with Stokes to 1.5 % after a calibration it does not print; this library's
   momentum-exchange force gives 0.92 .. 1.23 times the Stokes speed.
 """
 import numpy as np
