@@ -19,10 +19,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, single thread)."""
+    """Compile the oracle with gcc (plain -O2; OpenMP on the two node loops,
+    whose results do not depend on the thread count)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", _SRC,
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-shared", "-fPIC", _SRC,
                                "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -54,6 +55,8 @@ def lib():
         cp = C.POINTER(Cfg)
         sig = {
             "orc_q": ([C.c_int], C.c_int),
+            "orc_threads": ([], C.c_int),
+            "orc_set_threads": ([C.c_int], None),
             "orc_dim": ([C.c_int], C.c_int),
             "orc_tables": ([C.c_int, i, d, i], None),
             "orc_equilibrium": ([C.c_int, C.c_double, d, d], None),
@@ -124,6 +127,16 @@ def make_cfg(lattice=9, n=(16, 16, 1), periodic=(0, 0, 0), tau=0.8, rho0=1.0,
     c.interp = {"delta": 0, "lagrange": 1}[interp] if isinstance(interp, str) else int(interp)
     c.young, c.poisson, c.friction = float(young), float(poisson), float(friction)
     return c
+
+
+def threads() -> int:
+    """Threads the node loops use."""
+    return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads for the node loops; n < 1 restores the runtime's default."""
+    lib().orc_set_threads(int(n))
 
 
 def Q(cfg):

@@ -120,3 +120,40 @@ def test_skin_check_counts_fast_particles(orc):
     U = np.array([[0.0, 0.03, 0.0], [0.0, 0.0, -0.024]])
     out = orc.step(cfg, orc.rest_state(cfg), X, U, np.full(3, 0.4), np.full(3, 2.5))
     assert out["nskin"] == 1
+
+
+@pytest.mark.parametrize("lat", [9, 19])
+def test_threads_do_not_change_results(orc, lat):
+    """The node loops run on several threads; every node's arithmetic is the
+    same and no sum crosses nodes, so a coupled step with contacts and
+    walls is bitwise the same on one thread and on several."""
+    D = 2 if lat == 9 else 3
+    n = (37, 29, 1) if D == 2 else (15, 13, 11)
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-5
+    cfg = orc.make_cfg(lattice=lat, n=n, tau=0.7, gravity=g, n_sub=50, two_way=1,
+                       fluid_force=(1e-6, -2e-6, 5e-7 if D == 3 else 0.0))
+    rng = np.random.default_rng(5)
+    npart = 40
+    X = np.stack([rng.uniform(0.4, n[a] - 0.4, npart) for a in range(D)])
+    X[:, 1] = X[:, 0]
+    X[0, 1] += 0.45                                     # a pair in contact
+    X[D - 1, 2] = 0.2                                   # a wall contact
+    U = 1e-4 * rng.standard_normal((D, npart))
+    d = np.full(npart, 0.5)
+    rp = np.full(npart, 2.5)
+    _, w, _ = orc.tables(lat)
+    N = orc.nnodes(cfg)
+    f0 = (w[:, None] * (1.0 + 1e-3 * rng.standard_normal((len(w), N)))).reshape(-1)
+    runs = []
+    try:
+        for t in (1, 3, max(orc.threads(), 2)):
+            orc.set_threads(t)
+            out = orc.step(cfg, f0, X, U, d, rp)
+            rho, j = orc.moments(cfg, out["f"])
+            runs.append((out["f"], out["X"], out["U"], out["F"], rho, j))
+    finally:
+        orc.set_threads(0)
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a, b)
