@@ -1,24 +1,26 @@
 """Benchmark of the coupled LBM-PIBM-DEM step on one MI355X.
 
-Default workload: D2Q9 2048^2, tau 0.6, 500k disks (d ~ U[0.3, 0.8],
-density ratio 2.5, upper 60 % of a closed cavity), FP32, linear
-spring-dashpot contacts with 677 sub-steps.  A "step" is one full coupled
-step: cell list, moments (3D), interpolation, DEM, spreading,
-collision+streaming.
-Inputs are seeded synthetic (no dataset); the timed region starts with all
-state resident in HBM.
+Default workload (the largest configuration that fits one GPU): D3Q19
+256^3, tau 0.6, walls on every face, 2M spheres (diameters lognormal with
+mean 0.5 and SD 0.2, truncated to [0.2, 1], density ratio 2.0, upper half of
+the cavity), FP32, linear spring-dashpot contacts with 3109 sub-steps.  A
+"step" is one full coupled step: cell list, moments, interpolation, DEM,
+spreading, collision+streaming.  Inputs are seeded synthetic (no dataset);
+the timed region starts with all state resident in HBM.
 
 Prints ONE JSON line.  Besides the contract fields it carries
-  roofline      - the dominant kernel against MI355X HBM peak (8 TB/s), from
-                  HIP events recorded on the library's stream around every
-                  phase of ten evenly spaced timed steps (algorithmic bytes / time)
-  cpu_baseline  - the FP64 oracle on the host cores, on a bounded sample
-  extra         - the same measurement for the D3Q19 256^3 / 2M-sphere case
-                  in FP32 and with FP16 deviation storage, the FP16-vs-FP32
-                  field errors, the D3Q15/Lagrange and Hertz-Mindlin variants
-                  of that case, the hybrid obstacle case, and the
-                  adjoint/forward cost ratio on the D2Q9 512^2 /
-                  10k-particle differentiation workload
+  roofline      - the dominant kernel (collision+streaming) against MI355X HBM
+                  peak (8 TB/s), from HIP events recorded on the library's
+                  stream around every phase of ten evenly spaced timed steps
+                  (algorithmic bytes / time)
+  cpu_baseline  - the FP64 oracle on the host cores, on a bounded sample of
+                  the same workload (its 64^3 crop), one thread and all
+  extra         - the D2Q9 2048^2 / 500k-disk case, the same 256^3 case with
+                  FP16 deviation storage and the FP16-vs-FP32 field errors,
+                  both cases timed again after contacts have formed (late
+                  phase), the D3Q15/Lagrange and Hertz-Mindlin variants, the
+                  hybrid obstacle case, and the adjoint/forward cost ratio on
+                  the D2Q9 512^2 / 10k-particle differentiation workload
 """
 from __future__ import annotations
 
@@ -38,24 +40,13 @@ PROFILE_SAMPLES = 10     # timed steps that record the phase events (evenly spac
 
 # HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, then
 # WRITE_SIZE, each in its own run), scaled by the same counters over a plain
-# device copy of known size (--copy-probe).  Keyed by (kernel, workload); the
-# entry only applies while the kernel's source file hashes to `source_sha`.
-MEASURED_TRAFFIC = {
-    ("collide", "c1"): {"fetch_bytes": 90158.6 * 1024 * 1.9999, "write_bytes": 150214.1 * 1024,
-                       "source_sha": "4ef8dfd1a49054f3"},
-    ("spread", "c1"): {"fetch_bytes": 47517.5 * 1024 * 1.9999, "write_bytes": 32768.0 * 1024,
-                      "source_sha": "7b3ffaebd410b3ee"},
-    ("interp", "c1"): {"fetch_bytes": 98291.9 * 1024 * 1.9999, "write_bytes": 27474.0 * 1024,
-                      "source_sha": "7b3ffaebd410b3ee"},
-    ("collide", "c2"): {"fetch_bytes": 720974.5 * 1024 * 1.9999, "write_bytes": 1253280.8 * 1024,
-                       "source_sha": "4ef8dfd1a49054f3"},
-    ("moments", "c2"): {"fetch_bytes": 336723.5 * 1024 * 1.9999, "write_bytes": 133120.0 * 1024,
-                       "source_sha": "4ef8dfd1a49054f3"},
-    ("spread", "c2"): {"fetch_bytes": 704123.3 * 1024 * 1.9999, "write_bytes": 196608.0 * 1024,
-                      "source_sha": "7b3ffaebd410b3ee"},
-    ("interp", "c2"): {"fetch_bytes": 397785.0 * 1024 * 1.9999, "write_bytes": 180022.1 * 1024,
-                      "source_sha": "7b3ffaebd410b3ee"},
-}
+# device copy of known size (--copy-probe).  Keyed by (kernel, workload); an
+# entry applies only while the kernel's own source (its __global__ function
+# and the shared device header) hashes to `kernel_sha`: a changed kernel
+# reports null until it is measured again.
+MEASURED_TRAFFIC = {}
+KERNEL_SOURCES = {"collide": ("lattice.hip", "k_collide"), "moments": ("lattice.hip", "k_moments"),
+                  "spread": ("particles.hip", "k_spread_csr"), "interp": ("particles.hip", "k_interp_tile")}
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
 
 
@@ -83,17 +74,32 @@ def algorithmic_bytes(phase: str, w, np_: int) -> float:
     return 0.0
 
 
+def kernel_text(src: str, name: str) -> str:
+    """The source text of kernel `name` in csrc/`src`: from the template line
+    before its __global__ declaration to the closing brace in column 0."""
+    with open(os.path.join(ROOT, "paper_1407_6704_amd", "csrc", src)) as fh:
+        lines = fh.read().split("\n")
+    start = next(i for i, ln in enumerate(lines) if "__global__" in ln and f" {name}(" in ln)
+    if start > 0 and lines[start - 1].startswith("template"):
+        start -= 1
+    end = next(i for i in range(start + 1, len(lines)) if lines[i] == "}")
+    return "\n".join(lines[start:end + 1])
+
+
 def source_sha(kernel: str) -> str:
+    """Hash of a kernel's own source and of the device header it includes."""
     import hashlib
 
-    f = "lattice.hip" if kernel in ("collide", "moments") else "particles.hip"
-    with open(os.path.join(ROOT, "paper_1407_6704_amd", "csrc", f), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    src, name = KERNEL_SOURCES[kernel]
+    h = hashlib.sha256(kernel_text(src, name).encode())
+    with open(os.path.join(ROOT, "paper_1407_6704_amd", "csrc", "pibm_internal.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, workload: str):
     rec = MEASURED_TRAFFIC.get((kernel, workload))
-    if rec is None or rec["source_sha"] != source_sha(kernel):
+    if rec is None or rec["kernel_sha"] != source_sha(kernel):
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
 
@@ -125,6 +131,7 @@ def copy_probe():
 
 
 def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
+    """Time `steps` coupled steps after `warmup` untimed ones (from rest)."""
     import torch
 
     from paper_1407_6704_amd import pibm, workloads as W
@@ -140,8 +147,16 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
     sim.set_particles(X, U, d, rp)
     if w.obstacles:
         sim.set_bodies(body, area)
-    sim.step(warmup)
-    sim.synchronize()
+    t_w = time.time()
+    done = 0
+    while done < warmup:                       # in chunks, printing progress on long warm-ups
+        k = min(500, warmup - done)
+        sim.step(k)
+        torch.cuda.synchronize()
+        done += k
+        if warmup > 500:
+            print(f"[bench] {label}: {done} of {warmup} untimed steps ({time.time() - t_w:.1f} s)",
+                  file=sys.stderr, flush=True)
     # phase events on PROFILE_SAMPLES evenly spaced timed steps: each recorded
     # step carries 7 event records, which add a few microseconds each
     sim.set_profiling(True, every=max(1, steps // PROFILE_SAMPLES))
@@ -247,39 +262,91 @@ def run_adjoint(w, K: int = 100):
     return out
 
 
-def cpu_baseline(w, particles, budget_s=10.0, max_steps=4):
-    """The FP64 oracle (single thread, as it stands) on full coupled steps of
-    the same workload: steps are taken until about budget_s seconds of CPU
-    work (at least one, at most max_steps)."""
-    from oracle import oracle as orc
+def host_cpu():
+    """CPU model, physical and logical cores of this host, and the cores this
+    process may run on."""
+    model, phys = "unknown", set()
+    try:
+        cur = {}
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ":" not in ln:
+                    if cur:
+                        phys.add((cur.get("physical id"), cur.get("core id")))
+                    cur = {}
+                    continue
+                k, v = (t.strip() for t in ln.split(":", 1))
+                cur[k] = v
+                if k == "model name":
+                    model = v
+        if cur:
+            phys.add((cur.get("physical id"), cur.get("core id")))
+    except OSError:
+        pass
+    return {"cpu_model": model, "physical_cores": len(phys) or None, "logical_cores": os.cpu_count(),
+            "usable_cores": len(os.sched_getaffinity(0))}
 
-    X, U, d, rp = particles
-    oc = orc.make_cfg(lattice=w.lattice, n=w.n, tau=w.tau, gravity=w.gravity_vec(), contact=w.contact,
-                      kn=w.kn, restitution=w.restitution, k_soft=w.k_soft, skin=w.skin, n_sub=w.n_sub,
-                      two_way=w.two_way, bin_log2=w.bin_log2)
-    f = orc.rest_state(oc)
-    t0 = time.time()
-    steps = 0
-    while steps < max_steps and (steps == 0 or time.time() - t0 < budget_s):
-        out = orc.step(oc, f, X, U, d, rp)
-        f, X, U = out["f"], out["X"], out["U"]
-        steps += 1
-    dt = time.time() - t0
-    return {"value": w.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "particle_updates_per_s": X.shape[1] * steps / dt,
-            "sample": f"{steps} full coupled step(s) of the same workload ({w.nodes} nodes, {X.shape[1]} particles, "
-                      f"{w.n_sub} sub-steps) from rest, FP64, single thread, {dt:.1f} s"}
+
+def cpu_baseline(w, budget_s=8.0, max_steps=4):
+    """The FP64 oracle as it stands, on host cores, on a bounded sample of the
+    workload: its 64^3 crop (the same tau, walls, diameter distribution,
+    density ratio, particle number density and sub-steps; 31,250 spheres),
+    full coupled steps from rest until about budget_s seconds per run (at
+    least one, at most max_steps).  Run once on one thread and once on all
+    the threads the oracle's node loops get (OpenMP; particle, pair and
+    spreading loops are serial in both).  value/cores: the all-thread run."""
+    from oracle import oracle as orc
+    from paper_1407_6704_amd import workloads as W
+
+    s = w.replace(name=w.name + "_crop64", n=(64, 64, 64) if w.dim == 3 else (256, 256, 1),
+                  n_particles=max(1, round(w.n_particles * (64 ** 3 if w.dim == 3 else 256 ** 2) / w.nodes)),
+                  storage="fp32", seed=w.seed + 100)
+    X0, U0, d, rp = W.make_particles(s)
+    oc = orc.make_cfg(lattice=s.lattice, n=s.n, tau=s.tau, gravity=s.gravity_vec(), contact=s.contact,
+                      kn=s.kn, restitution=s.restitution, k_soft=s.k_soft, skin=s.skin, n_sub=s.n_sub,
+                      two_way=s.two_way, bin_log2=s.bin_log2, interp=s.interp)
+    runs = {}
+    all_threads = orc.threads()
+    for label, th in (("single_thread", 1), ("all_threads", all_threads)):
+        orc.set_threads(th)
+        f, X, U = orc.rest_state(oc), X0.copy(), U0.copy()
+        t0 = time.time()
+        steps = 0
+        while steps < max_steps and (steps == 0 or time.time() - t0 < budget_s):
+            out = orc.step(oc, f, X, U, d, rp)
+            f, X, U = out["f"], out["X"], out["U"]
+            steps += 1
+        dt = time.time() - t0
+        runs[label] = {"threads": th, "steps": steps, "seconds": dt, "mlups": s.nodes * steps / dt / 1e6,
+                       "particle_updates_per_s": X.shape[1] * steps / dt}
+        print(f"[bench] cpu_baseline {label}: {steps} steps in {dt:.1f} s", file=sys.stderr, flush=True)
+    orc.set_threads(0)
+    best = runs["all_threads"]
+    return {"value": best["mlups"], "unit": "MLUPS", "cores": best["threads"], "kind": "oracle",
+            "particle_updates_per_s": best["particle_updates_per_s"], **host_cpu(),
+            "single_thread": runs["single_thread"], "all_threads": runs["all_threads"],
+            "sample": f"{s.name}: the workload's {'x'.join(map(str, s.n))} crop ({s.nodes} nodes, {X0.shape[1]} "
+                      f"particles at the same number density, same tau, diameters, density ratio and "
+                      f"{s.n_sub} sub-steps), full FP64 coupled steps from rest; MLUPS = crop nodes x steps / "
+                      f"time; node loops on {best['threads']} threads (OpenMP), particle loops serial"}
+
+
+def workload_name(w) -> str:
+    return (f"{w.name}: D2Q9 {w.n[0]}x{w.n[1]}" if w.dim == 2 else
+            f"{w.name}: D3Q{w.lattice} {w.n[0]}x{w.n[1]}x{w.n[2]}")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--extra-steps", type=int, default=20)
+    ap.add_argument("--late-c1", type=int, default=500, help="untimed steps before the late-phase c1 window")
+    ap.add_argument("--late-c2", type=int, default=1900, help="untimed steps before the late-phase c2 window")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -297,7 +364,9 @@ def main():
 
     pibm.load()
     w = W.WORKLOADS[args.workload]
-    res, parts = run_gpu(w, args.steps, args.warmup, w.name)
+    fp16_twin = {"c2": "c3"}.get(w.name)
+    res, parts = run_gpu(w, args.steps, args.warmup, w.name, keep_fields=fp16_twin is not None)
+    fields32 = res.pop("_fields", None)
     line = {
         "metric": METRIC,
         "value": res["mlups"],
@@ -311,10 +380,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if w.storage == "fp32" else "f16-storage/f32-compute",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: D2Q9 {w.n[0]}x{w.n[1]}" if w.dim == 2 else
-                   f"{w.name}: D3Q{w.lattice} {w.n[0]}x{w.n[1]}x{w.n[2]}",
-                   "particles": w.n_particles, "tau": w.tau, "n_sub": w.n_sub, "contact": w.contact,
-                   "storage": w.storage, "seed": w.seed},
+        "config": {"workload": workload_name(w), "particles": w.n_particles, "tau": w.tau, "n_sub": w.n_sub,
+                   "contact": w.contact, "storage": w.storage, "seed": w.seed},
         "particle_updates_per_s": res["particle_updates_per_s"],
         "phases_ms_per_step": res["phases_ms_per_step"],
         "active_particles": res["active_particles"],
@@ -322,17 +389,36 @@ def main():
         "roofline": res["roofline"],
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, parts)
+        line["cpu_baseline"] = cpu_baseline(w)
     if not args.no_extra:
         import numpy as np
 
         extra = {}
-        for name in ("c2", "c3"):
-            r, _ = run_gpu(W.WORKLOADS[name], args.extra_steps, 2, name, keep_fields=True)
-            extra[name] = r
-        extra["fp16_speedup"] = extra["c2"]["ms_per_step"] / extra["c3"]["ms_per_step"]
-        # FP16 storage against FP32 from the same initial state, same steps
-        (r32, u32), (r16, u16) = extra["c2"].pop("_fields"), extra["c3"].pop("_fields")
+        if fp16_twin:
+            # FP16 deviation storage from the same initial state over the same steps
+            r16, _ = run_gpu(W.WORKLOADS[fp16_twin], args.steps, args.warmup, fp16_twin, keep_fields=True)
+            (rho16, u16), (rho32, u32) = r16.pop("_fields"), fields32
+            extra[fp16_twin] = r16
+            extra["fp16_speedup"] = res["ms_per_step"] / r16["ms_per_step"]
+            extra["fp16_vs_fp32"] = {
+                "steps": args.steps + args.warmup,
+                "eps_u": float(np.linalg.norm(u16.astype(np.float64) - u32) / np.linalg.norm(u32.astype(np.float64))),
+                "eps_rho": float(np.abs(rho16.astype(np.float64) - rho32).max()),
+            }
+        if w.name != "c1":
+            r, _ = run_gpu(W.C1, args.extra_steps, 5, "c1")
+            r["workload"] = workload_name(W.C1)
+            extra["c1"] = r
+        # the step once contacts have formed and lasted: c1 after 500 steps
+        # (lasting contacts from about step 300), c2 up to step 2000 (its
+        # stated length), each timed over 100 more steps
+        late = {}
+        for name, before in (("c1", args.late_c1), ("c2", args.late_c2)):
+            r, _ = run_gpu(W.WORKLOADS[name], 100, before, f"{name}_late")
+            r["workload"] = workload_name(W.WORKLOADS[name])
+            r["timed_steps"] = f"{before + 1}..{before + 100}"
+            late[name] = r
+        extra["late_phase"] = late
         # the paper's lattice and gather on the c2 particles
         r, _ = run_gpu(W.WORKLOADS["c2_d3q15"], args.extra_steps, 2, "c2_d3q15")
         extra["c2_d3q15_lagrange"] = r
@@ -343,11 +429,6 @@ def main():
         r, _ = run_gpu(W.WORKLOADS["hybrid"], args.extra_steps, 2, "hybrid")
         extra["hybrid_obstacles"] = r
         extra["c4_adjoint"] = run_adjoint(W.WORKLOADS["c4"])
-        extra["fp16_vs_fp32"] = {
-            "steps": args.extra_steps + 2,
-            "eps_u": float(np.linalg.norm(u16.astype(np.float64) - u32) / np.linalg.norm(u32.astype(np.float64))),
-            "eps_rho": float(np.abs(r16.astype(np.float64) - r32).max()),
-        }
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 

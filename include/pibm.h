@@ -30,11 +30,18 @@
  * the context itself owns only host bookkeeping.  All GPU work goes to the
  * HIP stream given at creation (or by pibm_set_stream), asynchronously.
  *
- * I/O calls (pibm_set_*, pibm_read_*, pibm_write_*) take HOST arrays, copy
- * through the workspace and synchronise the stream before returning.
- * pibm_step only enqueues work.  Numerical trouble found on the device
- * (skin violation, NaN, a full candidate list, an unstable drag sub-step) is
- * latched in a device flag and reported by the next synchronising call.
+ * I/O calls come in two forms.  pibm_set_*, pibm_read_* and pibm_write_*
+ * take HOST arrays, copy through the workspace and synchronise the stream
+ * before returning (convenient for tests and small cases).  The *_device
+ * forms take caller-owned DEVICE arrays (for instance torch tensors on the
+ * context's GPU), only enqueue work on the context's stream and never wait
+ * for it, so state moves between the caller's tensors and the library with
+ * no host round trip; the caller orders its own use of those arrays after
+ * the stream (as with any asynchronous HIP call).  pibm_step only enqueues
+ * work.  Numerical trouble found on the device (skin violation, NaN, a full
+ * candidate list, an unstable drag sub-step, an invalid particle array handed
+ * over in device memory) is latched in a device flag and reported by the
+ * next synchronising call.
  *
  * Error behaviour: every call returns a pibm_status; nothing throws across
  * the ABI.  pibm_last_error() gives a message for the last failure on that
@@ -181,6 +188,27 @@ pibm_status pibm_set_particles(pibm_ctx* ctx, const double* x, const double* v,
  * f_contact = sub-step mean of the contact force, both of the last step. */
 pibm_status pibm_read_particles(pibm_ctx* ctx, double* x, double* v, double* f_hydro,
                                 double* f_contact);
+
+/* The same particle state (Sec. 2.2-2.3: position X, velocity U, diameter d,
+ * density rho_p of each Lagrangian point) in caller-owned DEVICE FP32 arrays,
+ * id order, [axis][N] for vectors.  A position is x_hi + x_lo (x_lo may be
+ * NULL: zero); the pair is renormalised, so the split does not matter.  v may
+ * be NULL (at rest).  d_max (host) must be >= every diameter: it sizes the
+ * neighbour search (a larger value is correct but slower).  Asynchronous on
+ * the context's stream: the arrays must stay valid until the stream has run
+ * the copy.  Host-side checks (null arrays, d_max) return PIBM_E_ARG at once;
+ * a position outside the open box, a diameter <= 0 or > d_max, a density
+ * <= 0 or a non-finite value is found on the device and returned as
+ * PIBM_E_ARG by the next synchronising call.  Resets rotation and tangential
+ * history like pibm_set_particles. */
+pibm_status pibm_set_particles_device(pibm_ctx* ctx, const float* x_hi, const float* x_lo, const float* v,
+                                      const float* d, const float* rho_p, double d_max);
+/* The particle state after the last step into caller-owned DEVICE FP32
+ * arrays (D x N, id order; any may be NULL): position as x_hi + x_lo (the
+ * exact double-float state), velocity, f_hydro = -A_p mean(g) (Eq. lbm13) and
+ * the sub-step mean contact force.  Asynchronous on the context's stream. */
+pibm_status pibm_read_particles_device(pibm_ctx* ctx, float* x_hi, float* x_lo, float* v,
+                                       float* f_hydro, float* f_contact);
 /* Angular velocities for PIBM_CONTACT_HERTZ_MINDLIN (the second line of
  * Eq. demgov), host FP64 arrays in id order: 3 x N (x, y, z) in 3D, N (the
  * z component) in 2D.  pibm_set_particles sets them to zero and clears the
@@ -210,10 +238,17 @@ pibm_status pibm_set_bodies(pibm_ctx* ctx, const int32_t* body, const double* ar
 pibm_status pibm_read_bodies(pibm_ctx* ctx, int32_t n_bodies, double* f_hydro, double* f_contact,
                              double* torque);
 
-/* Density (N) and velocity u = j / rho (D x N) of the stored populations. */
+/* Density (N) and velocity u = j / rho (D x N) of the stored populations
+ * (the moments after Eq. lbm3: rho = sum f, rho u = sum e f). */
 pibm_status pibm_read_fields(pibm_ctx* ctx, float* rho, float* u);
 /* Force field F (D x N) used by the last collision (spread + fluid_force). */
 pibm_status pibm_read_force(pibm_ctx* ctx, float* F);
+/* The same two outputs into caller-owned DEVICE FP32 arrays of the same
+ * layout, asynchronously on the context's stream.  Both arrays of
+ * pibm_read_fields_device are required; the force is the field F of Eq. lbm9
+ * (spreading of Eq. lbm10 plus the uniform fluid force). */
+pibm_status pibm_read_fields_device(pibm_ctx* ctx, float* rho, float* u);
+pibm_status pibm_read_force_device(pibm_ctx* ctx, float* F);
 /* Cell list built at the start of the last step: per sorted slot the bin key
  * and particle id (N each), and bin_start (n_bins + 1 entries); bins are
  * x-fastest over ((n_a >> bin_log2) + 1) per axis, a particle's bin being

@@ -21,6 +21,8 @@ CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    # every hipError_t is checked: an ignored one fails the build
+    "-Werror=unused-value", "-Werror=unused-result",
 ]
 
 

@@ -332,6 +332,20 @@ void lattice_fields(const float4* mom, float* rho, float* u, long long N, int D,
     hipLaunchKernelGGL(k_fields, dim3(nblk(N)), dim3(256), 0, s, mom, rho, u, N, D);
 }
 
+// out[a N + r] = in[a N + r] + c[a] for a < D: the spread force field plus
+// the uniform fluid force, as the collision uses it.
+__global__ __launch_bounds__(256) void k_add_const(const float* __restrict__ in, float* __restrict__ out,
+                                                   long long N, int D, float c0, float c1, float c2) {
+    const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (r >= N) return;
+    const float c[3] = {c0, c1, c2};
+    for (int a = 0; a < D; a++) out[a * N + r] = c[a] != 0.0f ? in[a * N + r] + c[a] : in[a * N + r];
+}
+
+void lattice_add_const(const float* in, float* out, long long N, int D, const float* c, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_const, dim3(nblk(N)), dim3(256), 0, s, in, out, N, D, c[0], c[1], c[2]);
+}
+
 int lattice_totals_blocks() { return 1024; }
 
 void lattice_totals(int Q, int fp16, int sl2, const void* f, long long N, double* part, double* out,

@@ -2212,6 +2212,43 @@ __global__ __launch_bounds__(256) void k_unpermute_spin(PState A, int np, float*
     for (int a = 0; a < (D == 3 ? 3 : 1); a++) out[(long long)a * np + id] = A.w[a][s];
 }
 
+// Particle state from caller-owned device arrays in id order (positions as
+// leading and trailing FP32 parts): PState A in id order (the first sort
+// orders it).  (hi, lo) is renormalised with an error-free sum, so any split
+// of the same value gives the same state.  Invalid input (a position outside
+// the open box, a diameter <= 0, above dmax or above the limits of the host
+// path, a density <= 0, anything not finite) raises FLAG_ARG.
+template <int D>
+__global__ __launch_bounds__(256) void k_set_state(const float* __restrict__ xh, const float* __restrict__ xl,
+                                                   const float* __restrict__ v, const float* __restrict__ d,
+                                                   const float* __restrict__ rp, int np, Grid g, float dmax,
+                                                   PState A, uint32_t* flags) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= np) return;
+    bool bad = false;
+    const float di = d[i], ri = rp[i];
+    bad |= !(di > 0.0f) || !(di <= dmax) || !(di <= 0.5f * (float)g.n[0]) || !(di <= 64.0f) || !(ri > 0.0f) ||
+           !isfinite(ri);
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        const long long k = (long long)a * np + i;
+        float hi, lo;
+        two_sum(xh[k], xl ? xl[k] : 0.0f, hi, lo);
+        const float ua = v ? v[k] : 0.0f;
+        // strictly inside (0, n): the leading part decides except on the walls
+        bad |= !(hi >= 0.0f) || !(hi <= (float)g.n[a]) || (hi == 0.0f && !(lo > 0.0f)) ||
+               (hi == (float)g.n[a] && !(lo < 0.0f)) || !isfinite(lo) || !isfinite(ua);
+        A.xh[a][i] = hi;
+        A.xl[a][i] = lo;
+        A.u[a][i] = ua;
+    }
+    A.d[i] = di;
+    A.rp[i] = ri;
+    A.id[i] = i;
+    if (A.fixa) A.fixa[i] = 0.0f;
+    if (bad) atomicOr(flags, FLAG_ARG);
+}
+
 // ---------------------------------------------------------------------------
 // launchers (called from runtime.hip)
 // ---------------------------------------------------------------------------
@@ -2393,6 +2430,14 @@ void particles_totals(int D, PBuf& b, int np, double* part, double* out, hipStre
 void particles_unpermute_spin(int D, PBuf& b, int np, float* out, hipStream_t s) {
     if (D == 3) hipLaunchKernelGGL(k_unpermute_spin<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, out);
     else hipLaunchKernelGGL(k_unpermute_spin<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, out);
+}
+
+void particles_set_state(int D, PBuf& b, int np, const Grid& g, const float* xh, const float* xl, const float* v,
+                         const float* d, const float* rp, float dmax, hipStream_t s) {
+    if (D == 3)
+        hipLaunchKernelGGL(k_set_state<3>, dim3(nb256(np)), dim3(256), 0, s, xh, xl, v, d, rp, np, g, dmax, b.A, b.flags);
+    else
+        hipLaunchKernelGGL(k_set_state<2>, dim3(nb256(np)), dim3(256), 0, s, xh, xl, v, d, rp, np, g, dmax, b.A, b.flags);
 }
 
 void particles_unpermute(int D, PBuf& b, int np, bool have_forces, float* out, hipStream_t s) {

@@ -171,6 +171,7 @@ enum : unsigned {
     FLAG_SKIN = 1u,
     FLAG_CAPACITY = 2u,
     FLAG_UNSTABLE = 4u,
+    FLAG_ARG = 8u,       // a particle array handed over in device memory was invalid
 };
 
 // Counters written by the particle kernels (one small device array).

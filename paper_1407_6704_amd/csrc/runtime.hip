@@ -37,6 +37,9 @@ void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, floa
 int particles_totals_blocks();
 void particles_totals(int D, PBuf& b, int np, double* part, double* out, hipStream_t s);
 void particles_unpermute(int D, PBuf& b, int np, bool have_forces, float* out, hipStream_t s);
+void particles_set_state(int D, PBuf& b, int np, const Grid& g, const float* xh, const float* xl, const float* v,
+                         const float* d, const float* rp, float dmax, hipStream_t s);
+void lattice_add_const(const float* in, float* out, long long N, int D, const float* c, hipStream_t s);
 void particles_spread_adjoint(int D, PBuf& b, int np, const PCfg& c, const Grid& g, const float* coef, float* out,
                               hipStream_t s);
 void adj_fill(float* p, long long n, float v, hipStream_t s);
@@ -98,6 +101,9 @@ struct pibm_ctx {
     Rollout ro{};
     bool particles_set = false;
     bool stepped = false;
+    // particles handed over in device memory whose validity the device has
+    // reported but the host has not read yet: the first step waits for it
+    bool device_input_unchecked = false;
     std::string err;
     // phase timing: a ring of event rows, PIBM_NUM_PHASES + 1 events per step
     bool prof = false;
@@ -114,8 +120,9 @@ struct pibm_ctx {
     // fixed obstacle bodies: the body of each particle id (-1: moving)
     std::vector<int> body_of;
     ~pibm_ctx() {
-        for (hipEvent_t e : ev) hipEventDestroy(e);
-        if (host_active) hipHostFree(host_active);
+        // nothing to report from a destructor: failures are dropped on purpose
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        if (host_active) (void)hipHostFree(host_active);
     }
 };
 
@@ -141,6 +148,21 @@ pibm_status check_hip(pibm_ctx* c, hipError_t e, const char* what) {
     if (e != hipSuccess) return fail(c, PIBM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
     return PIBM_OK;
 }
+
+// Return from the calling entry point with PIBM_E_HIP on the first failed
+// HIP call.
+#define HIP_TRY(c, call, what)                                            \
+    do {                                                                  \
+        if (pibm_status st_ = check_hip((c), (call), (what))) return st_; \
+    } while (0)
+
+// Keeps the first failure of a sequence of enqueued HIP calls.
+struct HipSeq {
+    hipError_t e = hipSuccess;
+    void operator()(hipError_t r) {
+        if (e == hipSuccess) e = r;
+    }
+};
 
 int dimension(int lattice) { return lattice == PIBM_D2Q9 ? 2 : 3; }
 
@@ -381,6 +403,16 @@ bool init_ctx(pibm_ctx& c, const pibm_config* cfg, int64_t np) {
     return true;
 }
 
+// Zero angular velocities and the tangential-force history (Hertz-Mindlin
+// contexts only): the state of freshly set particles.
+hipError_t clear_spin_history(pibm_ctx* c) {
+    if (!c->pb.hcnt) return hipSuccess;
+    HipSeq q;
+    for (int a = 0; a < spin_components(c->D); a++) q(hipMemsetAsync(c->pb.A.w[a], 0, 4 * (size_t)c->np, c->stream));
+    q(hipMemsetAsync(c->pb.hcnt, 0, 4 * (size_t)c->np, c->stream));
+    return q.e;
+}
+
 pibm_status sync_and_flags(pibm_ctx* c) {
     pibm_status st = check_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (st) return st;
@@ -389,12 +421,30 @@ pibm_status sync_and_flags(pibm_ctx* c) {
     if (st) return st;
     if (flags) {
         uint32_t z = 0;
-        hipMemcpy(c->pb.flags, &z, 4, hipMemcpyHostToDevice);
+        st = check_hip(c, hipMemcpy(c->pb.flags, &z, 4, hipMemcpyHostToDevice), "clear flags");
+        if (st) return st;
+        if (flags & FLAG_ARG) {
+            // the particle state handed over in device memory is invalid: no
+            // step may run on it until valid particles are set
+            c->particles_set = false;
+            c->device_input_unchecked = false;
+            return fail(c, PIBM_E_ARG, "a particle array passed in device memory was invalid (position outside the box, "
+                                       "diameter <= 0 or above d_max, density <= 0, or not finite)");
+        }
         if (flags & FLAG_UNSTABLE) return fail(c, PIBM_E_UNSTABLE, "unstable: a particle left the box or a drag sub-step had h c >= 2");
         if (flags & FLAG_CAPACITY) return fail(c, PIBM_E_CAPACITY, "a particle had more candidates than max_candidates");
         if (flags & FLAG_SKIN) return fail(c, PIBM_E_SKIN, "a particle moved more than skin/2 within one step");
     }
     return PIBM_OK;
+}
+
+// Before the first step on particles handed over in device memory, wait for
+// the device's check of them: no kernel ever runs on an invalid state.
+pibm_status check_device_input(pibm_ctx* c) {
+    if (!c->device_input_unchecked) return PIBM_OK;
+    pibm_status st = sync_and_flags(c);
+    if (st == PIBM_OK) c->device_input_unchecked = false;
+    return st;
 }
 
 constexpr int PROF_ROWS = 256;
@@ -407,7 +457,7 @@ pibm_status drain_events(pibm_ctx* c) {
     for (int r = 0; r < c->ev_used; r++)
         for (int p = 0; p < PIBM_NUM_PHASES; p++) {
             float ms = 0.f;
-            hipEventElapsedTime(&ms, c->ev[r * E + p], c->ev[r * E + p + 1]);
+            HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[r * E + p], c->ev[r * E + p + 1]), "hipEventElapsedTime");
             c->phase_ms[p] += ms;
         }
     c->prof_steps += c->ev_used;
@@ -415,8 +465,8 @@ pibm_status drain_events(pibm_ctx* c) {
     return PIBM_OK;
 }
 
-inline void mark(pibm_ctx* c, int row, int p) {
-    if (row >= 0) hipEventRecord(c->ev[row * (PIBM_NUM_PHASES + 1) + p], c->stream);
+inline hipError_t mark(pibm_ctx* c, int row, int p) {
+    return row >= 0 ? hipEventRecord(c->ev[row * (PIBM_NUM_PHASES + 1) + p], c->stream) : hipSuccess;
 }
 
 }  // namespace
@@ -456,11 +506,14 @@ pibm_status pibm_create(const pibm_config* cfg, int64_t n_particles, void* dev_w
         return PIBM_E_HIP;
     }
     *(volatile uint32_t*)c->host_active = 0xffffffffu;   // unknown: multi-kernel set-up
-    hipMemsetAsync(c->F, 0, sizeof(float) * c->D * c->N, c->stream);
-    if (c->np > 0) hipMemsetAsync(c->pb.cnt, 0, sizeof(uint32_t) * (c->pc.nbins + 1), c->stream);
-    hipMemsetAsync(c->pb.flags, 0, 16, c->stream);
+    HipSeq q;
+    q(hipMemsetAsync(c->F, 0, sizeof(float) * c->D * c->N, c->stream));
+    if (c->np > 0) q(hipMemsetAsync(c->pb.cnt, 0, sizeof(uint32_t) * (c->pc.nbins + 1), c->stream));
+    q(hipMemsetAsync(c->pb.flags, 0, 16, c->stream));
     lattice_init_eq(c->Q, c->fp16, c->sl2, c->fA, nullptr, nullptr, c->N, c->stream);
-    if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
+    q(hipGetLastError());
+    q(hipStreamSynchronize(c->stream));
+    if (q.e != hipSuccess) {
         delete c;
         return PIBM_E_HIP;
     }
@@ -553,25 +606,47 @@ pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, co
         }
     }
     PState& A = c->pb.A;
+    HipSeq q;
     for (int a = 0; a < D; a++) {
-        hipMemcpyAsync(A.xh[a], xh + (size_t)a * np, 4 * np, hipMemcpyHostToDevice, c->stream);
-        hipMemcpyAsync(A.xl[a], xl + (size_t)a * np, 4 * np, hipMemcpyHostToDevice, c->stream);
-        hipMemcpyAsync(A.u[a], u + (size_t)a * np, 4 * np, hipMemcpyHostToDevice, c->stream);
+        q(hipMemcpyAsync(A.xh[a], xh + (size_t)a * np, 4 * np, hipMemcpyHostToDevice, c->stream));
+        q(hipMemcpyAsync(A.xl[a], xl + (size_t)a * np, 4 * np, hipMemcpyHostToDevice, c->stream));
+        q(hipMemcpyAsync(A.u[a], u + (size_t)a * np, 4 * np, hipMemcpyHostToDevice, c->stream));
     }
-    hipMemcpyAsync(A.d, dd, 4 * np, hipMemcpyHostToDevice, c->stream);
-    hipMemcpyAsync(A.rp, rp, 4 * np, hipMemcpyHostToDevice, c->stream);
-    hipMemcpyAsync(A.id, id, 4 * np, hipMemcpyHostToDevice, c->stream);
-    if (A.fixa) hipMemsetAsync(A.fixa, 0, 4 * (size_t)np, c->stream);   // every particle moves
+    q(hipMemcpyAsync(A.d, dd, 4 * np, hipMemcpyHostToDevice, c->stream));
+    q(hipMemcpyAsync(A.rp, rp, 4 * np, hipMemcpyHostToDevice, c->stream));
+    q(hipMemcpyAsync(A.id, id, 4 * np, hipMemcpyHostToDevice, c->stream));
+    if (A.fixa) q(hipMemsetAsync(A.fixa, 0, 4 * (size_t)np, c->stream));   // every particle moves
+    q(clear_spin_history(c));
+    // the staging vector must outlive the copies: wait before returning
+    q(hipStreamSynchronize(c->stream));
+    HIP_TRY(c, q.e, "copy particles");
     c->body_of.assign(np, -1);
-    if (c->pb.hcnt) {
-        // at rest, no tangential-force history
-        for (int a = 0; a < spin_components(D); a++) hipMemsetAsync(A.w[a], 0, 4 * (size_t)np, c->stream);
-        hipMemsetAsync(c->pb.hcnt, 0, 4 * (size_t)np, c->stream);
-    }
-    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "copy particles")) return s;
     set_stencil(*c, dmax);
     c->particles_set = true;
     c->stepped = false;
+    c->device_input_unchecked = false;
+    return PIBM_OK;
+}
+
+pibm_status pibm_set_particles_device(pibm_ctx* c, const float* x_hi, const float* x_lo, const float* v,
+                                      const float* d, const float* rho_p, double d_max) {
+    if (!c) return PIBM_E_ARG;
+    if (c->np == 0) {
+        c->particles_set = true;
+        return PIBM_OK;
+    }
+    if (!x_hi || !d || !rho_p) return fail(c, PIBM_E_ARG, "null particle array");
+    if (!(d_max > 0.0) || d_max > 64.0 || d_max > 0.5 * c->cfg.n[0])
+        return fail(c, PIBM_E_ARG, "d_max must be positive and within the diameter limits");
+    const float dmax = (float)d_max;
+    particles_set_state(c->D, c->pb, c->np, c->grid, x_hi, x_lo, v, d, rho_p, dmax, c->stream);
+    HIP_TRY(c, hipGetLastError(), "set particles launch");
+    HIP_TRY(c, clear_spin_history(c), "clear rotation");
+    c->body_of.assign(c->np, -1);
+    set_stencil(*c, (double)dmax);
+    c->particles_set = true;
+    c->stepped = false;
+    c->device_input_unchecked = true;
     return PIBM_OK;
 }
 
@@ -584,9 +659,11 @@ pibm_status pibm_set_rotation(pibm_ctx* c, const double* w) {
     std::vector<float> buf((size_t)nw * np);
     for (size_t k = 0; k < buf.size(); k++) buf[k] = (float)w[k];
     // before the first step the state is in id order
+    HipSeq q;
     for (int a = 0; a < nw; a++)
-        hipMemcpyAsync(c->pb.A.w[a], buf.data() + (size_t)a * np, 4 * (size_t)np, hipMemcpyHostToDevice, c->stream);
-    return check_hip(c, hipStreamSynchronize(c->stream), "copy rotation");
+        q(hipMemcpyAsync(c->pb.A.w[a], buf.data() + (size_t)a * np, 4 * (size_t)np, hipMemcpyHostToDevice, c->stream));
+    q(hipStreamSynchronize(c->stream));
+    return check_hip(c, q.e, "copy rotation");
 }
 
 pibm_status pibm_set_bodies(pibm_ctx* c, const int32_t* body, const double* area) {
@@ -597,10 +674,12 @@ pibm_status pibm_set_bodies(pibm_ctx* c, const int32_t* body, const double* area
     const int D = c->D, np = c->np;
     // before the first step the state is in id order
     std::vector<float> d(np), fa(np, 0.0f), u((size_t)D * np);
-    hipMemcpyAsync(d.data(), c->pb.A.d, 4 * (size_t)np, hipMemcpyDeviceToHost, c->stream);
+    HipSeq q;
+    q(hipMemcpyAsync(d.data(), c->pb.A.d, 4 * (size_t)np, hipMemcpyDeviceToHost, c->stream));
     for (int a = 0; a < D; a++)
-        hipMemcpyAsync(u.data() + (size_t)a * np, c->pb.A.u[a], 4 * (size_t)np, hipMemcpyDeviceToHost, c->stream);
-    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "read particles")) return s;
+        q(hipMemcpyAsync(u.data() + (size_t)a * np, c->pb.A.u[a], 4 * (size_t)np, hipMemcpyDeviceToHost, c->stream));
+    q(hipStreamSynchronize(c->stream));
+    HIP_TRY(c, q.e, "read particles");
     for (int i = 0; i < np; i++) {
         if (body[i] < -1) return fail(c, PIBM_E_ARG, "body index must be >= -1");
         if (body[i] < 0) continue;
@@ -608,10 +687,11 @@ pibm_status pibm_set_bodies(pibm_ctx* c, const int32_t* body, const double* area
         fa[i] = (float)ar;
         for (int a = 0; a < D; a++) u[(size_t)a * np + i] = 0.0f;      // fixed points are at rest
     }
-    hipMemcpyAsync(c->pb.A.fixa, fa.data(), 4 * (size_t)np, hipMemcpyHostToDevice, c->stream);
+    q(hipMemcpyAsync(c->pb.A.fixa, fa.data(), 4 * (size_t)np, hipMemcpyHostToDevice, c->stream));
     for (int a = 0; a < D; a++)
-        hipMemcpyAsync(c->pb.A.u[a], u.data() + (size_t)a * np, 4 * (size_t)np, hipMemcpyHostToDevice, c->stream);
-    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "copy bodies")) return s;
+        q(hipMemcpyAsync(c->pb.A.u[a], u.data() + (size_t)a * np, 4 * (size_t)np, hipMemcpyHostToDevice, c->stream));
+    q(hipStreamSynchronize(c->stream));
+    HIP_TRY(c, q.e, "copy bodies");
     c->body_of.assign(body, body + np);
     return PIBM_OK;
 }
@@ -628,6 +708,7 @@ pibm_status pibm_read_bodies(pibm_ctx* c, int32_t n_bodies, double* f_hydro, dou
     if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
     const int D = c->D, np = c->np;
     particles_unpermute(D, c->pb, np, c->stepped, c->stage, c->stream);
+    HIP_TRY(c, hipGetLastError(), "unpermute launch");
     std::vector<float> buf((size_t)5 * D * np);
     if (pibm_status s = check_hip(c, hipMemcpyAsync(buf.data(), c->stage, buf.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy particles")) return s;
     if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
@@ -672,11 +753,29 @@ pibm_status pibm_read_rotation(pibm_ctx* c, double* w) {
     if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
     const int nw = spin_components(c->D), np = c->np;
     particles_unpermute_spin(c->D, c->pb, np, c->stage, c->stream);
+    HIP_TRY(c, hipGetLastError(), "unpermute launch");
     std::vector<float> buf((size_t)nw * np);
     if (pibm_status s = check_hip(c, hipMemcpyAsync(buf.data(), c->stage, buf.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy rotation")) return s;
     if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
     for (size_t k = 0; k < buf.size(); k++) w[k] = buf[k];
     return PIBM_OK;
+}
+
+pibm_status pibm_read_particles_device(pibm_ctx* c, float* x_hi, float* x_lo, float* v, float* f_hydro,
+                                       float* f_contact) {
+    if (!c) return PIBM_E_ARG;
+    if (c->np == 0) return PIBM_OK;
+    if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
+    const int D = c->D, np = c->np;
+    particles_unpermute(D, c->pb, np, c->stepped, c->stage, c->stream);
+    HIP_TRY(c, hipGetLastError(), "unpermute launch");
+    // staging layout [x_hi D][x_lo D][v D][f_hydro D][f_contact D] x np
+    float* out[5] = {x_hi, x_lo, v, f_hydro, f_contact};
+    const size_t plane = sizeof(float) * (size_t)D * np;
+    HipSeq q;
+    for (int k = 0; k < 5; k++)
+        if (out[k]) q(hipMemcpyAsync(out[k], c->stage + (size_t)k * D * np, plane, hipMemcpyDeviceToDevice, c->stream));
+    return check_hip(c, q.e, "copy particles");
 }
 
 pibm_status pibm_read_particles(pibm_ctx* c, double* x, double* v, double* f_hydro, double* f_contact) {
@@ -685,6 +784,7 @@ pibm_status pibm_read_particles(pibm_ctx* c, double* x, double* v, double* f_hyd
     if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
     const int D = c->D, np = c->np;
     particles_unpermute(D, c->pb, np, c->stepped, c->stage, c->stream);
+    HIP_TRY(c, hipGetLastError(), "unpermute launch");
     std::vector<float> buf((size_t)5 * D * np);
     if (pibm_status s = check_hip(c, hipMemcpyAsync(buf.data(), c->stage, buf.size() * 4, hipMemcpyDeviceToHost, c->stream), "copy particles")) return s;
     if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
@@ -699,19 +799,35 @@ pibm_status pibm_read_particles(pibm_ctx* c, double* x, double* v, double* f_hyd
     return PIBM_OK;
 }
 
+// Density and velocity of the stored populations into device arrays (the
+// caller's, or the staging area).
+hipError_t fields_to(pibm_ctx* c, float* rho, float* u) {
+    lattice_moments(c->Q, c->fp16, c->sl2, c->fA, c->mom, c->N, RowMask{}, c->stream);   // every node
+    lattice_fields(c->mom, rho, u, c->N, c->D, c->stream);
+    return hipGetLastError();
+}
+
 pibm_status pibm_read_fields(pibm_ctx* c, float* rho, float* u) {
     if (!c) return PIBM_E_ARG;
-    lattice_moments(c->Q, c->fp16, c->sl2, c->fA, c->mom, c->N, RowMask{}, c->stream);   // every node
-    lattice_fields(c->mom, c->stage, c->stage + c->N, c->N, c->D, c->stream);
-    if (rho) hipMemcpyAsync(rho, c->stage, sizeof(float) * c->N, hipMemcpyDeviceToHost, c->stream);
-    if (u) hipMemcpyAsync(u, c->stage + c->N, sizeof(float) * c->D * c->N, hipMemcpyDeviceToHost, c->stream);
-    return check_hip(c, hipStreamSynchronize(c->stream), "read fields");
+    HIP_TRY(c, fields_to(c, c->stage, c->stage + c->N), "fields launch");
+    HipSeq q;
+    if (rho) q(hipMemcpyAsync(rho, c->stage, sizeof(float) * c->N, hipMemcpyDeviceToHost, c->stream));
+    if (u) q(hipMemcpyAsync(u, c->stage + c->N, sizeof(float) * c->D * c->N, hipMemcpyDeviceToHost, c->stream));
+    q(hipStreamSynchronize(c->stream));
+    return check_hip(c, q.e, "read fields");
+}
+
+pibm_status pibm_read_fields_device(pibm_ctx* c, float* rho, float* u) {
+    if (!c || !rho || !u) return fail(c, PIBM_E_ARG, "null field array");
+    return check_hip(c, fields_to(c, rho, u), "fields launch");
 }
 
 pibm_status pibm_read_force(pibm_ctx* c, float* F) {
     if (!c || !F) return PIBM_E_ARG;
-    if (pibm_status s = check_hip(c, hipMemcpyAsync(F, c->F, sizeof(float) * c->D * c->N, hipMemcpyDeviceToHost, c->stream), "copy F")) return s;
-    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "sync")) return s;
+    HipSeq q;
+    q(hipMemcpyAsync(F, c->F, sizeof(float) * c->D * c->N, hipMemcpyDeviceToHost, c->stream));
+    q(hipStreamSynchronize(c->stream));
+    HIP_TRY(c, q.e, "copy F");
     for (int a = 0; a < c->D; a++) {
         float ff = (float)c->cfg.fluid_force[a];
         if (ff != 0.0f)
@@ -720,16 +836,25 @@ pibm_status pibm_read_force(pibm_ctx* c, float* F) {
     return PIBM_OK;
 }
 
+pibm_status pibm_read_force_device(pibm_ctx* c, float* F) {
+    if (!c || !F) return PIBM_E_ARG;
+    const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
+    lattice_add_const(c->F, F, c->N, c->D, ff, c->stream);
+    return check_hip(c, hipGetLastError(), "force launch");
+}
+
 int64_t pibm_num_bins(const pibm_ctx* c) { return c ? c->pc.nbins : 0; }
 
 pibm_status pibm_read_cell_list(pibm_ctx* c, uint32_t* keys, int32_t* ids, int32_t* bin_start) {
     if (!c) return PIBM_E_ARG;
     if (c->np == 0) return PIBM_OK;
     if (!c->stepped) return fail(c, PIBM_E_STATE, "no step taken yet");
-    if (keys) hipMemcpyAsync(keys, c->pb.keys_sorted, 4 * (size_t)c->np, hipMemcpyDeviceToHost, c->stream);
-    if (ids) hipMemcpyAsync(ids, c->pb.A.id, 4 * (size_t)c->np, hipMemcpyDeviceToHost, c->stream);
-    if (bin_start) hipMemcpyAsync(bin_start, c->pb.start, 4 * (size_t)(c->pc.nbins + 1), hipMemcpyDeviceToHost, c->stream);
-    return check_hip(c, hipStreamSynchronize(c->stream), "read cell list");
+    HipSeq q;
+    if (keys) q(hipMemcpyAsync(keys, c->pb.keys_sorted, 4 * (size_t)c->np, hipMemcpyDeviceToHost, c->stream));
+    if (ids) q(hipMemcpyAsync(ids, c->pb.A.id, 4 * (size_t)c->np, hipMemcpyDeviceToHost, c->stream));
+    if (bin_start) q(hipMemcpyAsync(bin_start, c->pb.start, 4 * (size_t)(c->pc.nbins + 1), hipMemcpyDeviceToHost, c->stream));
+    q(hipStreamSynchronize(c->stream));
+    return check_hip(c, q.e, "read cell list");
 }
 
 }  // extern "C"
@@ -738,7 +863,10 @@ namespace {
 constexpr uint32_t ONE_GROUP_MAX = 1024;   // one pass per phase: faster than nine launches
 
 // One coupled step from populations fin to fout, with the force field in F.
-void launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
+// Returns the first failure of the enqueued event records and copies (kernel
+// launch errors are read by the caller with hipGetLastError).
+hipError_t launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
+    HipSeq q;
     const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
     const bool spread = c->np > 0 && c->cfg.two_way;
     // D2Q9 interpolation takes the moments straight from the populations of
@@ -746,20 +874,20 @@ void launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
     // the coarse-bin path read them from a moments pass, which the cell list
     // restricts to the node rows that the particles' stencils reach
     const bool fused = c->D == 2 && c->pc.L <= 1;
-    mark(c, row, 0);
+    q(mark(c, row, 0));
     if (c->np > 0) particles_sort(c->D, c->pb, c->np, c->pc, c->stream);
-    mark(c, row, 1);
+    q(mark(c, row, 1));
     if (c->np > 0 && !fused) {
         RowMask m{c->pb.start, {c->pc.n[0], c->pc.n[1], c->pc.n[2]}, {c->pc.nb[0], c->pc.nb[1], c->pc.nb[2]},
                   c->pc.L};
         lattice_moments(c->Q, c->fp16, c->sl2, fin, c->mom, c->N, m, c->stream);
     }
-    mark(c, row, 2);
+    q(mark(c, row, 2));
     if (c->np > 0) {
         if (fused) particles_interp_from_populations(c->pb, c->np, c->grid, c->pc, fin, c->fp16, c->sl2, c->stream);
         else particles_interp(c->D, c->pb, c->np, c->grid, c->pc, c->mom, c->stream);
     }
-    mark(c, row, 3);
+    q(mark(c, row, 3));
     if (c->np > 0) {
         // island set-up in one workgroup while a recent step had at most
         // ONE_GROUP_MAX active particles (both paths give the same result)
@@ -767,22 +895,24 @@ void launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
         const bool one = c->cfg.island_setup == 1 || (c->cfg.island_setup == 0 && recent <= ONE_GROUP_MAX);
         particles_dem(c->D, c->pb, c->np, c->pc, one, c->stream);
         if (c->steps_done % 8 == 0)
-            hipMemcpyAsync(c->host_active, c->pb.counters + CNT_ACTIVE, 4, hipMemcpyDeviceToHost, c->stream);
+            q(hipMemcpyAsync(c->host_active, c->pb.counters + CNT_ACTIVE, 4, hipMemcpyDeviceToHost, c->stream));
     }
     c->steps_done++;
-    mark(c, row, 4);
+    q(mark(c, row, 4));
     if (spread) particles_spread(c->D, c->pb, c->np, c->pc, c->grid, F, c->stream);
-    mark(c, row, 5);
+    q(mark(c, row, 5));
     lattice_collide(c->Q, c->fp16, c->sl2, fin, fout, F, spread ? 1 : 0, ff, c->grid, (float)c->cfg.tau,
                     c->stream);
-    mark(c, row, 6);
+    q(mark(c, row, 6));
+    return q.e;
 }
 
 size_t pop_bytes(const pibm_ctx* c) { return (size_t)c->Q * c->N * (c->fp16 ? 2 : 4); }
 
-void save_checkpoint(pibm_ctx* c, int i) {
-    hipMemcpyAsync(c->ro.ck_f[i], c->fA, pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+hipError_t save_checkpoint(pibm_ctx* c, int i) {
+    hipError_t e = hipMemcpyAsync(c->ro.ck_f[i], c->fA, pop_bytes(c), hipMemcpyDeviceToDevice, c->stream);
     adj_save_state(c->D, c->pb, c->np, c->ro.ck_p[i], c->stream);
+    return e;
 }
 }  // namespace
 
@@ -792,6 +922,8 @@ pibm_status pibm_step(pibm_ctx* c, int32_t n_steps) {
     if (!c) return PIBM_E_ARG;
     if (n_steps < 0) return fail(c, PIBM_E_ARG, "negative step count");
     if (c->np > 0 && !c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
+    if (n_steps > 0)
+        if (pibm_status st = check_device_input(c)) return st;
     for (int it = 0; it < n_steps; it++) {
         int row = -1;
         if (c->prof && c->prof_tick++ % c->prof_every == 0) {
@@ -799,10 +931,11 @@ pibm_status pibm_step(pibm_ctx* c, int32_t n_steps) {
                 if (pibm_status s = drain_events(c)) return s;
             row = c->ev_used++;
         }
-        launch_step(c, c->fA, c->fB, c->F, row);
+        const hipError_t e = launch_step(c, c->fA, c->fB, c->F, row);
         std::swap(c->fA, c->fB);
+        c->stepped = true;
+        HIP_TRY(c, e, "step: event record or copy");
     }
-    if (n_steps > 0) c->stepped = true;
     return check_hip(c, hipGetLastError(), "step launch");
 }
 
@@ -819,6 +952,7 @@ pibm_status pibm_forward_ckpt(pibm_ctx* c, int32_t n_steps, int32_t K, void* dev
     std::string why = adjoint_unsupported(*c);
     if (!why.empty()) return fail(c, PIBM_E_CONFIG, why);
     if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
+    if (pibm_status st = check_device_input(c)) return st;
     Rollout R;
     const size_t need = carve_rollout(*c, n_steps, K, nullptr, R);
     if (!dev_buf || buf_bytes < need) return fail(c, PIBM_E_ARG, "rollout buffer too small");
@@ -828,13 +962,15 @@ pibm_status pibm_forward_ckpt(pibm_ctx* c, int32_t n_steps, int32_t K, void* dev
     c->ro.steps = n_steps;
     c->ro.K = K;
     adj_save_const(c->pb, c->np, c->ro.d_id, c->ro.rp_id, c->stream);
+    HipSeq q;
     for (int t = 0; t < n_steps; t++) {
-        if (t % K == 0) save_checkpoint(c, t / K);
-        launch_step(c, c->fA, c->fB, c->F, -1);
+        if (t % K == 0) q(save_checkpoint(c, t / K));
+        q(launch_step(c, c->fA, c->fB, c->F, -1));
         std::swap(c->fA, c->fB);
     }
-    save_checkpoint(c, c->ro.nck - 1);
+    q(save_checkpoint(c, c->ro.nck - 1));
     if (n_steps > 0) c->stepped = true;
+    HIP_TRY(c, q.e, "forward: copy");
     if (pibm_status s = check_hip(c, hipGetLastError(), "forward launch")) return s;
     c->ro.valid = true;
     return PIBM_OK;
@@ -853,23 +989,24 @@ pibm_status pibm_backward(pibm_ctx* c, const float* dJ_dx_T, const float* dJ_dv_
     const int spread = c->cfg.two_way ? 1 : 0;
     const float tau = (float)c->cfg.tau;
     int cur = 0;
+    HipSeq q;
     adj_fill(R.abar[0], (long long)Q * N, 0.f, s);
-    if (dJ_dx_T) hipMemcpyAsync(R.xbh[0], dJ_dx_T, 4 * DN, hipMemcpyDeviceToDevice, s);
+    if (dJ_dx_T) q(hipMemcpyAsync(R.xbh[0], dJ_dx_T, 4 * DN, hipMemcpyDeviceToDevice, s));
     else adj_fill(R.xbh[0], DN, 0.f, s);
     adj_fill(R.xbl[0], DN, 0.f, s);
-    if (dJ_dv_T) hipMemcpyAsync(R.ub[0], dJ_dv_T, 4 * DN, hipMemcpyDeviceToDevice, s);
+    if (dJ_dv_T) q(hipMemcpyAsync(R.ub[0], dJ_dv_T, 4 * DN, hipMemcpyDeviceToDevice, s));
     else adj_fill(R.ub[0], DN, 0.f, s);
     adj_fill(R.acc, 8, 0.f, s);
     const int nseg = (R.steps + R.K - 1) / R.K;
     for (int seg = nseg - 1; seg >= 0; seg--) {
         const int t0 = seg * R.K, len = std::min(R.K, R.steps - t0);
         // re-run the segment, recording the state at the start of every step
-        hipMemcpyAsync(R.tape_f, R.ck_f[seg], fbytes, hipMemcpyDeviceToDevice, s);
+        q(hipMemcpyAsync(R.tape_f, R.ck_f[seg], fbytes, hipMemcpyDeviceToDevice, s));
         adj_load_state(D, c->pb, np, R.ck_p[seg], R.d_id, R.rp_id, s);
         for (int k = 0; k < len; k++) {
             adj_save_state(D, c->pb, np, R.tape_p + k * pf, s);
             void* fout = (k + 1 < len) ? (void*)(R.tape_f + (k + 1) * fbytes) : c->fB;
-            launch_step(c, R.tape_f + k * fbytes, fout, R.tape_F + (size_t)k * D * N, -1);
+            q(launch_step(c, R.tape_f + k * fbytes, fout, R.tape_F + (size_t)k * D * N, -1));
         }
         // reverse it
         for (int k = len - 1; k >= 0; k--) {
@@ -886,13 +1023,20 @@ pibm_status pibm_backward(pibm_ctx* c, const float* dJ_dx_T, const float* dJ_dv_
         }
     }
     if (dJ_dx0) adj_df_collapse(R.xbh[cur], R.xbl[cur], dJ_dx0, DN, s);
-    if (dJ_dv0) hipMemcpyAsync(dJ_dv0, R.ub[cur], 4 * DN, hipMemcpyDeviceToDevice, s);
+    if (dJ_dv0) q(hipMemcpyAsync(dJ_dv0, R.ub[cur], 4 * DN, hipMemcpyDeviceToDevice, s));
     float acc[8];
-    hipMemcpyAsync(acc, R.acc, sizeof(acc), hipMemcpyDeviceToHost, s);
+    q(hipMemcpyAsync(acc, R.acc, sizeof(acc), hipMemcpyDeviceToHost, s));
     // leave the context in the final state of the rollout
-    hipMemcpyAsync(c->fA, R.ck_f[R.nck - 1], fbytes, hipMemcpyDeviceToDevice, s);
+    q(hipMemcpyAsync(c->fA, R.ck_f[R.nck - 1], fbytes, hipMemcpyDeviceToDevice, s));
     adj_load_state(D, c->pb, np, R.ck_p[R.nck - 1], R.d_id, R.rp_id, s);
-    if (pibm_status st = check_hip(c, hipGetLastError(), "backward launch")) return st;
+    if (q.e != hipSuccess) {
+        (void)hipStreamSynchronize(s);          // acc is written by the copy above
+        return check_hip(c, q.e, "backward: copy");
+    }
+    if (pibm_status st = check_hip(c, hipGetLastError(), "backward launch")) {
+        (void)hipStreamSynchronize(s);
+        return st;
+    }
     if (pibm_status st = sync_and_flags(c)) return st;
     if (dJ_dtau) *dJ_dtau = (double)acc[0] + (double)acc[1];
     if (dJ_dgravity)
@@ -938,16 +1082,20 @@ pibm_status pibm_diagnostics(pibm_ctx* c, pibm_diag* out) {
     std::memset(out, 0, sizeof(*out));
     lattice_totals(c->Q, c->fp16, c->sl2, c->fA, c->N, c->part, c->totals, c->stream);
     double fl[8];
-    hipMemcpyAsync(fl, c->totals, sizeof(fl), hipMemcpyDeviceToHost, c->stream);
     double pt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t cnt[2] = {0, 0};
-    if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "fluid totals")) return s;
+    HipSeq q;
+    q(hipGetLastError());
+    q(hipMemcpyAsync(fl, c->totals, sizeof(fl), hipMemcpyDeviceToHost, c->stream));
     if (c->np > 0 && c->particles_set) {
         particles_totals(c->D, c->pb, c->np, c->part, c->totals + 8, c->stream);
-        hipMemcpyAsync(pt, c->totals + 8, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-        hipMemcpyAsync(cnt, c->pb.counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
-        if (pibm_status s = check_hip(c, hipStreamSynchronize(c->stream), "particle totals")) return s;
+        q(hipGetLastError());
+        q(hipMemcpyAsync(pt, c->totals + 8, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        q(hipMemcpyAsync(cnt, c->pb.counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
     }
+    // the host buffers above are written by the stream: wait before any return
+    q(hipStreamSynchronize(c->stream));
+    HIP_TRY(c, q.e, "totals");
     out->mass = (double)c->N + fl[0];
     for (int a = 0; a < 3; a++) {
         out->fluid_momentum[a] = fl[1 + a];

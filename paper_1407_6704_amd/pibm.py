@@ -103,6 +103,10 @@ def load():
         "pibm_rollout_bytes": ([vp, C.c_int32, C.c_int32], C.c_size_t),
         "pibm_forward_ckpt": ([vp, C.c_int32, C.c_int32, vp, C.c_size_t], C.c_int),
         "pibm_backward": ([vp, fp, fp, fp, fp, dp, dp], C.c_int),
+        "pibm_set_particles_device": ([vp, vp, vp, vp, vp, vp, C.c_double], C.c_int),
+        "pibm_read_particles_device": ([vp, vp, vp, vp, vp, vp], C.c_int),
+        "pibm_read_fields_device": ([vp, vp, vp], C.c_int),
+        "pibm_read_force_device": ([vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -233,6 +237,61 @@ class Sim:
         v = _f64(v).reshape(self.D, self.np) if v is not None else None
         self._check(self.lib.pibm_set_particles(self.ctx, _dp(x), _dp(v), _dp(_f64(d)), _dp(_f64(rho_p))))
 
+    # --- state in device tensors (no host round trip) ---------------------
+    def _dev_f32(self, t):
+        """A contiguous FP32 tensor on this simulation's device (marshalling)."""
+        import torch
+
+        return torch.as_tensor(t).to(device=self.device, dtype=torch.float32).contiguous()
+
+    @staticmethod
+    def _vp(t):
+        return C.c_void_p(t.data_ptr()) if t is not None else None
+
+    def set_particles_device(self, x_hi, d, rho_p, v=None, x_lo=None, d_max=None):
+        """Particles from device tensors ((D, N) positions as x_hi + x_lo,
+        velocities; (N,) diameters and densities), asynchronously on this
+        simulation's stream.  d_max >= every diameter (None: taken from d,
+        which waits for the device)."""
+        xh = self._dev_f32(x_hi).reshape(self.D, self.np)
+        xl = self._dev_f32(x_lo).reshape(self.D, self.np) if x_lo is not None else None
+        vv = self._dev_f32(v).reshape(self.D, self.np) if v is not None else None
+        dd = self._dev_f32(d).reshape(self.np)
+        rp = self._dev_f32(rho_p).reshape(self.np)
+        if d_max is None:
+            d_max = float(dd.max().item()) if self.np else 1.0
+        self._keep = (xh, xl, vv, dd, rp)          # alive until the stream has copied them
+        self._check(self.lib.pibm_set_particles_device(self.ctx, self._vp(xh), self._vp(xl), self._vp(vv),
+                                                       self._vp(dd), self._vp(rp), float(d_max)))
+
+    def read_particles_device(self):
+        """The particle state in id order as FP32 device tensors (D, N):
+        x_hi, x_lo (position = x_hi + x_lo), v, f_hydro, f_contact."""
+        import torch
+
+        out = {k: torch.empty((self.D, self.np), dtype=torch.float32, device=self.device)
+               for k in ("x_hi", "x_lo", "v", "f_hydro", "f_contact")}
+        self._check(self.lib.pibm_read_particles_device(self.ctx, *(self._vp(out[k]) for k in
+                                                                    ("x_hi", "x_lo", "v", "f_hydro", "f_contact"))))
+        return out
+
+    def read_fields_device(self):
+        """Density (N,) and velocity (D, N) as FP32 device tensors."""
+        import torch
+
+        rho = torch.empty(self.N, dtype=torch.float32, device=self.device)
+        u = torch.empty((self.D, self.N), dtype=torch.float32, device=self.device)
+        self._check(self.lib.pibm_read_fields_device(self.ctx, self._vp(rho), self._vp(u)))
+        return rho, u
+
+    def read_force_device(self):
+        """The force field of the last collision (D, N) as an FP32 device tensor."""
+        import torch
+
+        F = torch.empty((self.D, self.N), dtype=torch.float32, device=self.device)
+        self._check(self.lib.pibm_read_force_device(self.ctx, self._vp(F)))
+        return F
+
     def read_particles(self):
         out = {k: np.empty((self.D, self.np)) for k in ("x", "v", "f_hydro", "f_contact")}
         self._check(self.lib.pibm_read_particles(self.ctx, _dp(out["x"]), _dp(out["v"]),
@@ -336,17 +395,14 @@ class Sim:
         self._check(self.lib.pibm_forward_ckpt(self.ctx, int(n_steps), int(K),
                                                C.c_void_p(self.rollout_buf.data_ptr()), int(nbytes)))
 
-    def backward(self, dJ_dx=None, dJ_dv=None):
-        """Gradients of J given dJ/dX_T and dJ/dU_T ((D, N) arrays or device
-        tensors, id order) for the last forward_ckpt.  Returns dx0, dv0 (numpy
-        (D, N) FP32), dtau (float) and dgravity (3 floats)."""
+    def backward_device(self, dJ_dx=None, dJ_dv=None):
+        """Gradients of J given dJ/dX_T and dJ/dU_T ((D, N) arrays or tensors,
+        id order) for the last forward_ckpt.  Returns dx0, dv0 as FP32 device
+        tensors (D, N), dtau (float) and dgravity (3 floats)."""
         import torch
 
         def dev(a):
-            if a is None:
-                return None
-            t = torch.as_tensor(a, dtype=torch.float32).to(self.device).reshape(self.D, self.np).contiguous()
-            return t
+            return self._dev_f32(a).reshape(self.D, self.np) if a is not None else None
 
         gx, gv = dev(dJ_dx), dev(dJ_dv)
         dx0 = torch.empty((self.D, self.np), dtype=torch.float32, device=self.device)
@@ -358,20 +414,36 @@ class Sim:
             return C.cast(C.c_void_p(t.data_ptr()), C.POINTER(C.c_float)) if t is not None else None
 
         self._check(self.lib.pibm_backward(self.ctx, ptr(gx), ptr(gv), ptr(dx0), ptr(dv0), C.byref(dtau), dg))
-        return {"dx0": dx0.cpu().numpy(), "dv0": dv0.cpu().numpy(), "dtau": dtau.value, "dgravity": list(dg)}
+        return {"dx0": dx0, "dv0": dv0, "dtau": dtau.value, "dgravity": list(dg)}
+
+    def backward(self, dJ_dx=None, dJ_dv=None):
+        """As backward_device, with dx0 and dv0 returned as numpy arrays."""
+        r = self.backward_device(dJ_dx, dJ_dv)
+        r["dx0"], r["dv0"] = r["dx0"].cpu().numpy(), r["dv0"].cpu().numpy()
+        return r
 
 
-def settling_rollout(cfg_kwargs, x0, d, rho_p, steps, K=100):
-    """A torch.autograd.Function over a checkpointed rollout.
+def settling_rollout(cfg_kwargs, x0, d, rho_p, steps, K=100, device="cuda:0"):
+    """A torch.autograd.Function over a checkpointed rollout of `steps`
+    coupled steps, whose backward is the library's hand-written adjoint.
 
-    Returns a callable f(tau, gravity, v0) -> X_T, where tau is a 0-d tensor,
-    gravity a (3,) tensor and v0 a (D, N) tensor (CPU, float64); X_T is the
-    (D, N) final particle positions.  Its backward calls the library's
-    hand-written adjoint (pibm_backward), which gives dJ/dtau, dJ/dgravity and
-    dJ/dv0 for any J(X_T)."""
+    Returns a callable f(tau, gravity, v0) -> X_T: tau a 0-d tensor, gravity
+    a (3,) tensor (both small host parameters: they configure the step), v0
+    a (D, N) tensor of initial velocities on the GPU.  X_T, the (D, N) final
+    positions (FP64, the double-float state), stays on the GPU, and so do
+    dJ/dv0 and the position data: the particle state moves in and out
+    through the device-pointer calls, with no host copy.  x0 (D, N), d and
+    rho_p (N) may be host arrays or device tensors.  Gradients of any
+    J(X_T) with respect to tau, gravity and v0 come from pibm_backward."""
     import torch
 
-    x0 = np.asarray(x0, np.float64)
+    dev = torch.device(device)
+    x0 = torch.as_tensor(x0, dtype=torch.float64).to(dev)
+    x_hi = x0.to(torch.float32)
+    x_lo = (x0 - x_hi.to(torch.float64)).to(torch.float32)        # the exact double-float split
+    d_t = torch.as_tensor(d).to(dev, torch.float32)
+    rp_t = torch.as_tensor(rho_p).to(dev, torch.float32)
+    d_max = float(np.max(np.asarray(d, np.float32))) if not torch.is_tensor(d) else float(d_t.max().item())
     npart = x0.shape[1]
 
     class Rollout(torch.autograd.Function):
@@ -379,18 +451,21 @@ def settling_rollout(cfg_kwargs, x0, d, rho_p, steps, K=100):
         def forward(ctx, tau, gravity, v0):
             kw = dict(cfg_kwargs)
             kw["tau"] = float(tau)
-            kw["gravity"] = tuple(float(g) for g in gravity.detach().cpu().numpy())
-            sim = Sim(make_config(**kw), npart)
-            sim.set_particles(x0, v0.detach().cpu().numpy(), d, rho_p)
+            kw["gravity"] = tuple(float(g) for g in gravity.detach().cpu().tolist())
+            sim = Sim(make_config(**kw), npart, device=dev)
+            sim.set_particles_device(x_hi, d_t, rp_t, v=v0.detach(), x_lo=x_lo, d_max=d_max)
             sim.forward_ckpt(steps, K)
+            p = sim.read_particles_device()
             ctx.sim = sim
-            return torch.as_tensor(sim.read_particles()["x"], dtype=torch.float64)
+            ctx.meta = (tau.dtype, tau.device, gravity.dtype, gravity.device, v0.dtype)
+            return p["x_hi"].to(torch.float64) + p["x_lo"].to(torch.float64)
 
         @staticmethod
         def backward(ctx, gx):
-            r = ctx.sim.backward(dJ_dx=gx.detach().cpu().numpy())
-            return (torch.tensor(r["dtau"], dtype=torch.float64),
-                    torch.tensor(r["dgravity"], dtype=torch.float64),
-                    torch.as_tensor(r["dv0"], dtype=torch.float64))
+            r = ctx.sim.backward_device(dJ_dx=gx.detach())
+            t_dtype, t_dev, g_dtype, g_dev, v_dtype = ctx.meta
+            return (torch.tensor(r["dtau"], dtype=t_dtype, device=t_dev),
+                    torch.tensor(r["dgravity"], dtype=g_dtype, device=g_dev),
+                    r["dv0"].to(v_dtype))
 
     return Rollout.apply

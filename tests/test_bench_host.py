@@ -34,12 +34,29 @@ def test_collide_and_moments_bytes_per_node(B, W):
     assert B.algorithmic_bytes("collide", W.C1, W.C1.n_particles) == 335544320
 
 
-def test_measured_traffic_follows_the_source_hash(B, monkeypatch):
-    t = B.measured_traffic("collide", "c1")
-    assert t is not None and 330e6 < t < 345e6
+def test_measured_traffic_follows_the_kernel_source(B, monkeypatch):
+    # the hash covers the kernel's own function text and the device header
+    for k, (src, name) in B.KERNEL_SOURCES.items():
+        txt = B.kernel_text(src, name)
+        assert f" {name}(" in txt.splitlines()[0] + txt.splitlines()[1] and txt.endswith("}")
+    sha = B.source_sha("collide")
+    assert len(sha) == 16 and sha != B.source_sha("moments")
+    rec = {"fetch_bytes": 1.0e9, "write_bytes": 2.0e9, "kernel_sha": sha}
+    monkeypatch.setitem(B.MEASURED_TRAFFIC, ("collide", "c2"), rec)
+    assert B.measured_traffic("collide", "c2") == 3.0e9
     assert B.measured_traffic("collide", "no_such_workload") is None
     monkeypatch.setattr(B, "source_sha", lambda kernel: "0" * 16)
-    assert B.measured_traffic("collide", "c1") is None
+    assert B.measured_traffic("collide", "c2") is None
+    # every stored record carries the hash it was measured under
+    for rec in B.MEASURED_TRAFFIC.values():
+        assert set(rec) == {"fetch_bytes", "write_bytes", "kernel_sha"}
+
+
+def test_headline_is_the_largest_single_gpu_workload(B, W):
+    import argparse  # noqa: F401
+    big = max((w for w in (W.C0, W.C1, W.C2, W.C4)), key=lambda w: w.nodes)
+    assert big is W.C2
+    assert B.workload_name(W.C2) == "c2: D3Q19 256x256x256"
 
 
 def test_more_than_one_gpu_is_refused():

@@ -7,7 +7,7 @@ the moving particles, the per-body hydrodynamic and contact forces and
 torques; fixed points must not move.
 
 Bounds: fluid velocity 1e-5 relative (L2), density 1e-6; moving particles
-1e-4 relative; body forces 1e-4 relative (L2 over the bodies).
+1e-5 relative; body forces and torques 1e-5 relative (L2 over the bodies).
 """
 import numpy as np
 import pytest
@@ -87,8 +87,8 @@ def test_fixed_bodies_match_oracle(P, orc, D, contact):
                + f" |F_contact|={np.abs(ref['f_contact']).max():.2e}")
         assert np.array_equal(got["x"][:, ~mv], X[:, ~mv]) and np.all(got["v"][:, ~mv] == 0)
         assert eu <= 1e-5 and er <= 1e-6
-        assert ex <= 1e-4 and ev <= 1e-4
-        assert eb["f_hydro"] <= 1e-4 and eb["f_contact"] <= 1e-4 and eb["torque"] <= 1e-4
+        assert ex <= 1e-5 and ev <= 1e-5
+        assert eb["f_hydro"] <= 1e-5 and eb["f_contact"] <= 1e-5 and eb["torque"] <= 1e-5
         assert np.abs(ref["f_contact"]).max() > 0
 
 

@@ -66,19 +66,25 @@ def test_lattice_steps_match_oracle(P, W, orc, lat, storage, n, per):
     F = np.tile(np.array(cfg.fluid_force)[: sim.D, None], (1, N))
     f = G.to_oracle_f(orc, lat, h0)
     tol_u, tol_rho = (1e-5, 1e-6) if storage == "fp32" else (1e-3, 1e-5)
+    # element-wise population error against the largest deviation: FP32
+    # arithmetic and storage leave a few units in the last place of the
+    # largest |h| (2^-24 = 6e-8 each), bounded here by 16 of them; FP16
+    # storage rounds each stored deviation once, to within 2^-11 of itself
+    # (nearest-even, 11 significant bits), plus the FP32 part
+    tol_h = 16 * 2.0 ** -24 if storage == "fp32" else 2.0 ** -11 + 16 * 2.0 ** -24
     # one step from an identical state
     sim.step(1)
     f1 = orc.collide_stream(oc, f, F)
     eu, er, eh = G.field_errors(orc, lat, sim.read_populations(), f1, N)
-    _flush(f"  1 step: eps_u={eu:.2e} eps_rho={er:.2e} eps_h={eh:.2e}")
-    assert eu <= tol_u and er <= tol_rho
-    # ten more steps
+    _flush(f"  1 step: eps_u={eu:.2e} eps_rho={er:.2e} eps_h={eh:.2e} (bound {tol_h:.2e})")
+    assert eu <= tol_u and er <= tol_rho and eh <= tol_h
+    # ten more steps, same bounds
     sim.step(10)
     for _ in range(10):
         f1 = orc.collide_stream(oc, f1, F)
     eu, er, eh = G.field_errors(orc, lat, sim.read_populations(), f1, N)
-    _flush(f"  11 steps: eps_u={eu:.2e} eps_rho={er:.2e}")
-    assert eu <= 3 * tol_u and er <= 3 * tol_rho
+    _flush(f"  11 steps: eps_u={eu:.2e} eps_rho={er:.2e} eps_h={eh:.2e}")
+    assert eu <= tol_u and er <= tol_rho
 
 
 @pytest.mark.parametrize("lat,storage", [(9, "fp32"), (19, "fp32"), (15, "fp32"), (9, "fp16"), (19, "fp16"),
@@ -168,9 +174,9 @@ def _coupled_compare(P, orc, cfg, X, U, d, rp, h0=None, steps=1, seed=0, tol=Non
     ev = np.linalg.norm(got["v"] - Uo) / max(np.linalg.norm(Uo), 1e-30)
     fh_ref = -np.pi * d ** 2 / 4 * out["gbar"]
     efh = np.linalg.norm(got["f_hydro"] - fh_ref) / max(np.linalg.norm(fh_ref), 1e-30)
-    _flush(f"  {label} eps_u={eu:.2e} eps_rho={er:.2e} dX={ex:.2e} (disp {disp:.2e}) "
+    _flush(f"  {label} eps_u={eu:.2e} eps_rho={er:.2e} eps_h={eh:.2e} dX={ex:.2e} (disp {disp:.2e}) "
            f"dU={ev:.2e} dFh={efh:.2e}")
-    return dict(eu=eu, er=er, ex=ex, ev=ev, efh=efh, sim=sim, out=out, got=got)
+    return dict(eu=eu, er=er, eh=eh, ex=ex, ev=ev, efh=efh, sim=sim, out=out, got=got)
 
 
 FREE_CASES = [(9, "delta", 0), (19, "delta", 0), (15, "delta", 0), (9, "lagrange", 0), (15, "lagrange", 0),
@@ -210,10 +216,10 @@ def test_coupled_step_free_particles(P, W, orc, lat, interp, bl):
     h0 = G.perturbed_state(orc, sim0, w, seed=7, amp=1e-4)
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, h0=h0, steps=1, label="1 step")
     assert r["eu"] <= 1e-5 and r["er"] <= 1e-6
-    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["efh"] <= 1e-4
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["efh"] <= 1e-5
     assert r["sim"].diagnostics()["active"] == 0
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, h0=h0, steps=5, label="5 steps")
-    assert r["eu"] <= 3e-5 and r["ex"] <= 3e-5 and r["ev"] <= 3e-5
+    assert r["eu"] <= 1e-5 and r["er"] <= 1e-6 and r["ex"] <= 1e-5 and r["ev"] <= 1e-5
 
 
 @pytest.mark.parametrize("lat,interp,bl", [(19, "delta", 0), (15, "lagrange", 0), (19, "delta", 2),
@@ -259,9 +265,9 @@ def test_moments_only_where_gathered(P, W, orc, lat, interp, bl):
     h0 = G.perturbed_state(orc, sim0, w, seed=9, amp=1e-4)
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, h0=h0, steps=1, label="1 step")
     assert r["eu"] <= 1e-5 and r["er"] <= 1e-6
-    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["efh"] <= 1e-4
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["efh"] <= 1e-5
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, h0=h0, steps=3, label="3 steps")
-    assert r["eu"] <= 3e-5 and r["ex"] <= 3e-5 and r["ev"] <= 3e-5
+    assert r["eu"] <= 1e-5 and r["er"] <= 1e-6 and r["ex"] <= 1e-5 and r["ev"] <= 1e-5
 
 
 @pytest.mark.parametrize("lat,contact", [(9, "lsd"), (19, "lsd"), (15, "lsd"), (9, "hertz"), (19, "hertz")])
@@ -300,9 +306,9 @@ def test_coupled_step_with_contacts(P, orc, lat, contact):
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=1, label="1 step")
     assert r["sim"].diagnostics()["active"] > 0
     assert r["eu"] <= 1e-5 and r["er"] <= 1e-6
-    assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["efh"] <= 1e-5
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=4, label="4 steps")
-    assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4 and r["eu"] <= 1e-4
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["eu"] <= 1e-5 and r["er"] <= 1e-6
 
 
 @pytest.mark.parametrize("k", [60, 150])
@@ -332,7 +338,68 @@ def test_big_island(P, orc, k):
     _flush(f"  worst particles {np.argsort(dv)[-5:].tolist()} dv {np.sort(dv)[-5:].tolist()}")
     assert r["sim"].diagnostics()["active"] == k
     assert np.abs(r["got"]["f_contact"]).max() > 0
-    assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4 and r["eu"] <= 1e-5
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["eu"] <= 1e-5 and r["er"] <= 1e-6
+
+
+@pytest.mark.parametrize("lat", [9, 19])
+def test_resting_pile_lasting_contacts(P, orc, lat):
+    """A small pile at rest on the floor: a bottom layer of touching
+    candidates and a second layer in its hollows settle under gravity within
+    a few steps and then stay in contact for the rest of the 60 steps, so
+    the islands cannot jump over their sub-steps and the jump back-off runs
+    step after step.  Every step has contact forces on the oracle's side;
+    the GPU matches the oracle at the per-field bounds after 60 steps."""
+    _flush(f"resting pile {lat}")
+    D = 2 if lat == 9 else 3
+    pts = []
+    if D == 2:
+        n = (24, 12, 1)
+        for k in range(10):
+            pts.append((4.0 + 0.5002 * k, 0.2501))
+        for k in range(9):
+            pts.append((4.2501 + 0.5002 * k, 0.2501 + 0.4331 + 0.0003))
+    else:
+        n = (10, 10, 8)
+        for i in range(3):
+            for j in range(3):
+                pts.append((3.5 + 0.5002 * i, 3.5 + 0.5002 * j, 0.2501))
+        for i in range(2):
+            for j in range(2):
+                pts.append((3.7501 + 0.5002 * i, 3.7501 + 0.5002 * j, 0.2501 + 0.3536 + 0.0003))
+    X = np.array(pts).T.astype(np.float32).astype(np.float64)
+    npart = X.shape[1]
+    d = np.full(npart, 0.5)
+    rp = np.full(npart, 2.5)
+    U = np.zeros_like(X)
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-4
+    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact="lsd")
+    sim = P.Sim(cfg, npart)
+    sim.set_particles(X, U, d, rp)
+    oc = G.oracle_cfg(orc, cfg)
+    f = G.to_oracle_f(orc, lat, sim.read_populations())
+    Xo, Uo = X.copy(), U.copy()
+    in_contact = []
+    active = []
+    for k in range(60):
+        out = orc.step(oc, f, Xo, Uo, d, rp)
+        f, Xo, Uo = out["f"], out["X"], out["U"]
+        in_contact.append(int((np.abs(out["fc"]).max(axis=0) > 0).sum()))
+        sim.step(1)
+        if k % 10 == 9:
+            active.append(sim.diagnostics()["active"])
+    sim.synchronize()
+    got = sim.read_particles()
+    eu, er, eh = G.field_errors(orc, lat, sim.read_populations(), f, sim.N)
+    disp = np.abs(Xo - X).max()
+    ex = np.abs(got["x"] - Xo).max() / disp
+    ev = np.linalg.norm(got["v"] - Uo) / np.linalg.norm(Uo)
+    _flush(f"  60 steps: eps_u={eu:.2e} eps_rho={er:.2e} eps_h={eh:.2e} dX={ex:.2e} (disp {disp:.2e}) "
+           f"dU={ev:.2e}; particles in contact per step {in_contact[::10]}; active {active}")
+    assert min(in_contact[5:]) >= npart // 2          # lasting contacts after the first few steps
+    assert min(active) >= npart // 2
+    assert eu <= 1e-5 and er <= 1e-6
+    assert ex <= 1e-5 and ev <= 1e-5
 
 
 def test_soft_contact_parity(P, orc):
@@ -355,8 +422,8 @@ def test_c0_workload_100_steps(P, W, orc):
     X, U, d, rp = W.make_particles(w)
     cfg = P.config_from_workload(w)
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=100, label="c0")
-    assert r["eu"] <= 1e-4 and r["er"] <= 1e-6
-    assert r["ex"] <= 1e-4 and r["ev"] <= 1e-4
+    assert r["eu"] <= 1e-5 and r["er"] <= 1e-6
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5
 
 
 def test_deterministic_and_resume(P, W, orc):
@@ -518,7 +585,7 @@ def test_dense_tile_spreads_unstaged(P, W, orc, lat):
     g[D - 1] = -1e-5
     cfg = P.make_config(lattice=lat, n=n, tau=0.7, gravity=g, n_sub=20, contact="none")
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=2, label="dense")
-    assert r["eu"] <= 1e-5 and r["er"] <= 1e-6 and r["efh"] <= 1e-4
+    assert r["eu"] <= 1e-5 and r["er"] <= 1e-6 and r["efh"] <= 1e-5
     assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5
 
 

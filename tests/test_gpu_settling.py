@@ -6,10 +6,12 @@ diameters with their relaxation times and time steps.
   FP64 oracle (fluid velocity and particle height and speed), with the
   bounds of the other parity tests: FP32 velocity 1e-5 relative (L2),
   particle speed 1e-5 relative;
-* the settling speeds after 20,000 steps: increasing with the diameter and
-  within 25 % of Stokes' law (Eq. lbm14).  The paper's own numbers agree
-  with Stokes to 1.5 % after a calibration it does not print; this library's
-  momentum-exchange force gives 0.92 .. 1.23 times the Stokes speed.
+* the settling speeds after 20,000 steps against the FP64 oracle's run of
+  the same study (tests/golden/table2_oracle_settling.json), increasing with
+  the diameter.  The paper's own numbers agree with Stokes' law (Eq. lbm14)
+  to 1.5 % after a calibration it does not print; with this reading of the
+  momentum exchange both the oracle and the GPU give 0.92 .. 1.22 times the
+  Stokes speed.
 """
 import numpy as np
 import pytest
@@ -62,14 +64,31 @@ def test_settling_start_matches_oracle(S, orc, row, interp):
     assert ev <= 1e-5 and ez <= 1e-5
 
 
-def test_settling_speeds_near_stokes(S):
+def test_settling_speeds_against_oracle(S):
+    """20,000 steps of each Table 2 row: the settling speed (mean vertical
+    speed over the last tenth of the run, sampled every 1000 steps) against
+    the FP64 oracle's run of the same steps, stored by
+    tests/golden/make_table2_reference.py (only the oracle runs there), to
+    1e-3 relative; and the ratio to Stokes' law, which the paper reaches to
+    1.5 % after a calibration of tau that it does not print, stays within the
+    band this reading of the momentum exchange gives (0.9 .. 1.25)."""
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "table2_oracle_settling.json")) as fh:
+        ref = json.load(fh)
+    assert ref["steps"] == 20000 and ref["sample_every"] == 1000 and ref["interp"] == "lagrange"
     speeds = []
-    for r in S.TABLE2:
-        res = S.run(r, steps=20000, chunk=1000)
+    for r, o in zip(S.TABLE2, ref["rows"]):
+        assert abs(r["tau"] - o["tau"]) < 1e-12
+        res = S.run(r, steps=ref["steps"], chunk=ref["sample_every"])
         vs = S.stokes(r["d"])
-        _flush(f"h/d={r['h_over_d']:.3f}: {res['settling']:.3e} m/s, Stokes {vs:.3e}, "
-               f"ratio {res['settling'] / vs:.3f}, drift {res['drift']:.1e}")
-        assert 0.75 <= res["settling"] / vs <= 1.25
+        e = abs(res["settling"] - o["settling"]) / abs(o["settling"])
+        _flush(f"h/d={r['h_over_d']:.3f}: {res['settling']:.6e} m/s, oracle {o['settling']:.6e} (rel {e:.1e}), "
+               f"Stokes {vs:.3e}, ratio {res['settling'] / vs:.3f}, drift {res['drift']:.1e}")
+        assert e <= 1e-3
+        assert 0.9 <= res["settling"] / vs <= 1.25
         assert res["drift"] < 0.02
         speeds.append(res["settling"])
     assert all(a > b for a, b in zip(speeds, speeds[1:]))      # faster (more negative) with size
