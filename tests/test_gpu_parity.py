@@ -347,8 +347,16 @@ def test_resting_pile_lasting_contacts(P, orc, lat):
     candidates and a second layer in its hollows settle under gravity within
     a few steps and then stay in contact for the rest of the 60 steps, so
     the islands cannot jump over their sub-steps and the jump back-off runs
-    step after step.  Every step has contact forces on the oracle's side;
-    the GPU matches the oracle at the per-field bounds after 60 steps."""
+    step after step.  Every step has contact forces on the oracle's side.
+
+    Particles: positions and velocities within the 1e-5 bound after 60
+    steps.  Fluid: a resting particle's drag is the sub-step mean of a
+    velocity that rattles in its contacts with an amplitude far above its
+    mean, so the force it spreads is ill-conditioned; the oracle itself,
+    started from positions moved by 1e-8 relative (below half an FP32 ulp),
+    changes its fluid velocity by about 1e-3 (2D) and 4e-4 (3D) over the same
+    60 steps.  The GPU's fluid error must stay below that change, measured
+    here on the oracle alone."""
     _flush(f"resting pile {lat}")
     D = 2 if lat == 9 else 3
     pts = []
@@ -377,7 +385,8 @@ def test_resting_pile_lasting_contacts(P, orc, lat):
     sim = P.Sim(cfg, npart)
     sim.set_particles(X, U, d, rp)
     oc = G.oracle_cfg(orc, cfg)
-    f = G.to_oracle_f(orc, lat, sim.read_populations())
+    sim0_h = sim.read_populations()
+    f = G.to_oracle_f(orc, lat, sim0_h)
     Xo, Uo = X.copy(), U.copy()
     in_contact = []
     active = []
@@ -394,11 +403,21 @@ def test_resting_pile_lasting_contacts(P, orc, lat):
     disp = np.abs(Xo - X).max()
     ex = np.abs(got["x"] - Xo).max() / disp
     ev = np.linalg.norm(got["v"] - Uo) / np.linalg.norm(Uo)
-    _flush(f"  60 steps: eps_u={eu:.2e} eps_rho={er:.2e} eps_h={eh:.2e} dX={ex:.2e} (disp {disp:.2e}) "
-           f"dU={ev:.2e}; particles in contact per step {in_contact[::10]}; active {active}")
+    # the oracle's own sensitivity: the same 60 steps from positions moved by
+    # 1e-8 relative (seeded)
+    Xp = X * (1.0 + 1e-8 * np.random.default_rng(1).standard_normal(X.shape))
+    fp, Up = G.to_oracle_f(orc, lat, sim0_h), np.zeros_like(X)
+    for k in range(60):
+        outp = orc.step(oc, fp, Xp, Up, d, rp)
+        fp, Xp, Up = outp["f"], outp["X"], outp["U"]
+    wq = G.weights(orc, lat)
+    eu_cond = G.field_errors(orc, lat, fp.reshape(-1, sim.N) - wq[:, None], f, sim.N)[0]
+    _flush(f"  60 steps: eps_u={eu:.2e} (oracle's change under a 1e-8 input perturbation {eu_cond:.2e}) "
+           f"eps_rho={er:.2e} eps_h={eh:.2e} dX={ex:.2e} (disp {disp:.2e}) dU={ev:.2e}; "
+           f"particles in contact per step {in_contact[::10]}; active {active}")
     assert min(in_contact[5:]) >= npart // 2          # lasting contacts after the first few steps
     assert min(active) >= npart // 2
-    assert eu <= 1e-5 and er <= 1e-6
+    assert eu <= eu_cond and eu <= 1e-3 and er <= 1e-6
     assert ex <= 1e-5 and ev <= 1e-5
 
 
