@@ -40,7 +40,8 @@ class Cfg(C.Structure):
     ]
 
 
-CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3, "hertz_mindlin": 4}
+CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3, "hertz_mindlin": 4, "hertz_mindlin_microslip": 5}
+TS = 10     # doubles of tangential state per contact (ORC_TS in the C source)
 
 _lib = None
 
@@ -82,6 +83,7 @@ def lib():
                                d], C.c_int),
             "orc_step": ([cp, d, d, d, C.c_int, d, d, d, d, d, d, d, d], C.c_int),
             "orc_fluid_totals": ([cp, d, d, d], None),
+            "orc_tangential_update": ([cp, C.c_double, d, d, C.c_double, C.c_double, C.c_double, d], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(_lib, name)
@@ -295,18 +297,31 @@ def dem(cfg, X, U, d, rho_p, rho_i, j_i, pairs=None):
 
 def _hist_arrays(hist):
     if hist is None:
-        return np.zeros((1, 2), np.int32), np.zeros((1, 3)), 0
+        return np.zeros((1, 2), np.int32), np.zeros((1, TS)), 0
     keys, T = hist
     n = len(keys)
     k = np.ascontiguousarray(np.asarray(keys, np.int32).reshape(-1, 2)) if n else np.zeros((1, 2), np.int32)
-    t = np.ascontiguousarray(np.asarray(T, np.float64).reshape(-1, 3)) if n else np.zeros((1, 3))
+    t = np.ascontiguousarray(np.asarray(T, np.float64).reshape(-1, TS)) if n else np.zeros((1, TS))
     return k, t, n
 
 
+def tangential_update(cfg, h, n, vrel, Fn, rstar, delta, state):
+    """One contact's tangential update (contact 4 or 5) on a copy of the
+    state (TS doubles: T, loading direction, k, T*, T**, previous F_n)."""
+    S = np.ascontiguousarray(np.asarray(state, np.float64).reshape(TS)).copy()
+    nn = np.zeros(3)
+    nn[: len(n)] = n
+    vv = np.zeros(3)
+    vv[: len(vrel)] = vrel
+    lib().orc_tangential_update(C.byref(cfg), float(h), _d(nn), _d(vv), float(Fn), float(rstar), float(delta),
+                                _d(S))
+    return S
+
+
 def dem_hm(cfg, X, U, W, d, rho_p, rho_i, j_i, hist=None, pairs=None, fixed=None):
-    """O4 with the Hertz-Mindlin contact and rotation (contact = 4) on
+    """O4 with the Hertz-Mindlin contact and rotation (contact = 4 or 5) on
     copies; W is (3, np) (2D: the z row only is used).  hist = (keys (n, 2),
-    T (n, 3)) or None; fixed: np flags of fixed obstacle points or None.
+    state (n, TS)) or None; fixed: np flags of fixed obstacle points or None.
     Returns (X', U', W', gbar, fc_mean, vmax, hist').  Works for every
     contact model (W and hist then stay unused)."""
     dim = D(cfg)
@@ -325,7 +340,7 @@ def dem_hm(cfg, X, U, W, d, rho_p, rho_i, j_i, hist=None, pairs=None, fixed=None
     kin, tin, hn = _hist_arrays(hist)
     cap = len(pairs) + 6 * np_ + 1
     kout = np.zeros((cap, 2), np.int32)
-    tout = np.zeros((cap, 3))
+    tout = np.zeros((cap, TS))
     fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, np.int32))
     n = lib().orc_dem_full(C.byref(cfg), np_, _d(X), _d(U), _d(W), _d(_f64(d)), _d(_f64(rho_p)),
                            None if fx is None else _i(fx),
@@ -366,7 +381,7 @@ def step_full(cfg, f, X, U, d, rho_p, W=None, hist=None, fixed=None, area=None):
     kin, tin, hn = _hist_arrays(hist)
     cap = 64 * np_ + 6 * np_ + 1
     kout = np.zeros((cap, 2), np.int32)
-    tout = np.zeros((cap, 3))
+    tout = np.zeros((cap, TS))
     hout = np.zeros(1, np.int64)
     nskin = lib().orc_step_full(C.byref(cfg), _d(f), _d(fout), _d(F), np_, _d(X), _d(U), _d(W),
                                 _d(_f64(d)), _d(_f64(rho_p)), None if fx is None else _i(fx),

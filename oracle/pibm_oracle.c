@@ -53,7 +53,8 @@ typedef struct {
     double rho0;            /* fluid density used in the buoyancy term */
     double gravity[3];      /* gravitational acceleration, Eq. demgov */
     double fluid_force[3];  /* uniform body force density on the fluid */
-    int contact;            /* 0 none, 1 linear spring-dashpot, 2 soft */
+    int contact;            /* 0 none, 1 linear spring-dashpot, 2 soft, 3 Hertz, 4 Hertz-Mindlin
+                               (no-slip limit), 5 Hertz-Mindlin with micro-slip */
     double kn, restitution; /* linear spring-dashpot parameters */
     double k_soft;          /* soft repulsion stiffness */
     double skin;            /* candidate-list skin */
@@ -65,7 +66,7 @@ typedef struct {
                                delta kernel still spreads (Eq. lbm10-lbm11) */
     double young, poisson;  /* Hertz contact (contact = 3, 4): Young's modulus and Poisson
                                ratio of the particles and the walls (one material) */
-    double friction;        /* contact = 4: Coulomb friction coefficient mu */
+    double friction;        /* contact = 4, 5: Coulomb friction coefficient mu */
 } orc_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -626,7 +627,8 @@ int64_t orc_candidate_pairs_brute(const orc_cfg *c, int np, const double *X, con
     return count;
 }
 
-/* Mindlin tangential force and rotation (contact = 4, Sec. 2.3, R25).
+/* Mindlin tangential force and rotation (contact = 4, Sec. 2.3, R25; with
+ * the micro-slip factor of R27 for contact = 5).
  * The paper's increment dT = 8 G* r_a theta_k d(delta_t) + (-1)^k mu dF_n (1 - theta_k)
  * is taken in its no-slip limit theta_k = 1, dT = 8 G* r_a d(delta_t), with
  * r_a = sqrt(delta_n R*) and, as printed, 1/G* = (1 - nu^2)/G + (1 - nu^2)/G,
@@ -659,31 +661,127 @@ static void cross3(const double *x, const double *y, double *z)
     z[2] = x[0] * y[1] - x[1] * y[0];
 }
 
+/* Tangential state of one contact, ORC_TS doubles:
+ *   [0..2] T, the tangential force on the particle;
+ *   [3..5] the contact's loading direction (a unit vector in the contact
+ *          plane; zero until the first tangential increment), micro-slip only;
+ *   [6] k: 0 loading, 1 unloading, 2 reloading;  [7] T*, [8] T**: the
+ *   tangential force along the loading direction where the last unloading
+ *   and reloading began;  [9] the normal force of the previous sub-step. */
+#define ORC_TS 10
+
+/* Turn a vector into the contact plane of normal n, keeping its length. */
+static void into_plane(const double *n, double *v)
+{
+    double vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+    double old = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double P[3];
+    for (int a = 0; a < 3; a++) P[a] = v[a] - vn * n[a];
+    double pl = sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+    for (int a = 0; a < 3; a++) v[a] = pl > 0.0 ? P[a] * (old / pl) : 0.0;
+}
+
 /* One contact's tangential update.  n: unit normal (3 components, z = 0 in
  * 2D); vrel: contact-point velocity of the particle minus the partner's;
  * Fn: Hertz normal force; rstar: effective radius; delta: overlap.
- * T (in/out): tangential force on the particle. */
-static void mindlin_update(const orc_cfg *c, double h, const double *n, const double *vrel,
-                           double Fn, double rstar, double delta, double *T)
+ * S (in/out, ORC_TS doubles): the tangential state above.
+ *
+ * The elastic trial increment is E = -8 G* r_a h v_t, r_a = sqrt(delta R*)
+ * (v_t: the tangential part of vrel, so h v_t is the increment of the
+ * tangential surface displacement).  contact = 4 takes the no-slip limit
+ * theta_k = 1 of the paper's increment: T += E.  contact = 5 (R27) takes
+ *   dT = theta_k E + (-1)^k mu dF_n (1 - theta_k) t
+ * along the contact's loading direction t (the direction of its first
+ * tangential increment, turned with the contact plane), with the
+ * Mindlin-Deresiewicz factors in the incremental form of Thornton:
+ *   loading   (k = 0): theta^3 = 1 - (T_t + mu dF_n) / (mu F_n)
+ *   unloading (k = 1): theta^3 = 1 - (T* - T_t + 2 mu dF_n) / (2 mu F_n)
+ *   reloading (k = 2): theta^3 = 1 - (T_t - T** + 2 mu dF_n) / (2 mu F_n)
+ * where T_t = T.t, dF_n is the change of the normal force since the last
+ * sub-step and theta is clamped to [0, 1] (0: the whole contact slides).
+ * k changes where the increment along t, e = E.t, changes sign: loading
+ * with e < 0 starts unloading (T* = T_t), unloading with e > 0 starts
+ * reloading (T** = T_t), reloading with e < 0 unloads again (T* = T_t) and
+ * reloading that reaches T* is back on the loading curve (k = 0).  While the
+ * normal force grows faster than the tangential load, |E| <= mu dF_n, no
+ * slip zone grows and dT = E.  Both forms finally cap |T| at mu F_n
+ * (Coulomb sliding). */
+static void tangential_update(const orc_cfg *c, double h, const double *n, const double *vrel,
+                              double Fn, double rstar, double delta, double *S)
 {
-    double tn = T[0] * n[0] + T[1] * n[1] + T[2] * n[2];
-    double old = sqrt(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
-    double P[3];
-    for (int a = 0; a < 3; a++) P[a] = T[a] - tn * n[a];
-    double pl = sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
-    for (int a = 0; a < 3; a++) T[a] = pl > 0.0 ? P[a] * (old / pl) : 0.0;
+    double *T = S, *t = S + 3;
+    into_plane(n, T);
     double vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
     double kt = 8.0 * mindlin_gstar(c) * sqrt(delta * rstar);
-    for (int a = 0; a < 3; a++) T[a] -= kt * h * (vrel[a] - vn * n[a]);
+    double E[3];
+    for (int a = 0; a < 3; a++) E[a] = -kt * h * (vrel[a] - vn * n[a]);
+    double mu = c->friction;
+    if (c->contact == 5) {
+        into_plane(n, t);
+        double dFn = Fn - S[9];
+        S[9] = Fn;
+        double el = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+        double tl = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        if (tl == 0.0 && el > 0.0) {                  /* the first tangential increment sets t */
+            for (int a = 0; a < 3; a++) t[a] = E[a] / el;
+            S[6] = 0.0;
+            S[7] = S[8] = 0.0;
+            tl = 1.0;
+        }
+        if (tl > 0.0) {
+            double Tt = T[0] * t[0] + T[1] * t[1] + T[2] * t[2];
+            double e = E[0] * t[0] + E[1] * t[1] + E[2] * t[2];
+            int k = (int)S[6];
+            if (k == 0 && e < 0.0) {
+                k = 1;
+                S[7] = Tt;
+            } else if (k == 1 && e > 0.0) {
+                k = 2;
+                S[8] = Tt;
+            } else if (k == 2) {
+                if (e < 0.0) {
+                    k = 1;
+                    S[7] = Tt;
+                } else if (Tt >= S[7]) {
+                    k = 0;
+                }
+            }
+            S[6] = k;
+            if (dFn > 0.0 && el <= mu * dFn) {
+                for (int a = 0; a < 3; a++) T[a] += E[a];
+            } else {
+                double arg;
+                if (k == 0)
+                    arg = 1.0 - (Tt + mu * dFn) / (mu * Fn);
+                else if (k == 1)
+                    arg = 1.0 - (S[7] - Tt + 2.0 * mu * dFn) / (2.0 * mu * Fn);
+                else
+                    arg = 1.0 - (Tt - S[8] + 2.0 * mu * dFn) / (2.0 * mu * Fn);
+                arg = arg < 0.0 ? 0.0 : (arg > 1.0 ? 1.0 : arg);
+                double th = cbrt(arg);
+                double sg = k == 1 ? -1.0 : 1.0;
+                for (int a = 0; a < 3; a++) T[a] += th * E[a] + sg * mu * dFn * (1.0 - th) * t[a];
+            }
+        }
+    } else {
+        for (int a = 0; a < 3; a++) T[a] += E[a];
+    }
     double tl = sqrt(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
-    double lim = c->friction * Fn;
+    double lim = mu * Fn;
     if (tl > lim)
         for (int a = 0; a < 3; a++) T[a] *= lim / tl;
 }
 
+/* The tangential update alone, for the tests (same arguments). */
+void orc_tangential_update(const orc_cfg *c, double h, const double *n, const double *vrel, double Fn,
+                           double rstar, double delta, double *S)
+{
+    tangential_update(c, h, n, vrel, Fn, rstar, delta, S);
+}
+
 /* History of the tangential forces between steps: entry i is the pair
  * key[2i], key[2i+1] (particle indices p < q, or p and -1 - (2 a + side) for
- * the wall at side 0 / n of axis a) with the force T[3i..3i+2] on p. */
+ * the wall at side 0 / n of axis a) with the state S[ORC_TS i ..] of p. */
 static int64_t hist_find(int64_t hn, const int *key, int p, int q)
 {
     for (int64_t i = 0; i < hn; i++)
@@ -698,14 +796,15 @@ static int64_t hist_find(int64_t hn, const int *key, int p, int q)
  *   F_c^k = sum over candidate pairs and walls
  *   U^{k+1} = U^k + h (F_h^k + F_c^k + (1 - rho0/rho_p) m g) / m   (Eq. demgov)
  *   X^{k+1} = X^k + h U^{k+1}
- *   W^{k+1} = W^k + h torque^k / I             (contact = 4 only)
+ *   W^{k+1} = W^k + h torque^k / I             (contact = 4, 5 only)
  * Outputs the final X, U, the sub-step mean gbar of g (what the fluid
  * receives), the sub-step mean contact force, and vmax_p = max_k |U^k|
  * over k = 0..n_sub (the skin check: displacement <= vmax * one step).
  * pairs: candidate pairs at the start of the step (orc_candidate_pairs).
- * With contact = 4: W (3 x np, angular velocities) is updated, and the
- * tangential-force history (hn_in entries) is read and rewritten to
- * key_out / T_out (capacity npairs + 2 D np), returning the entry count.
+ * With contact = 4 or 5: W (3 x np, angular velocities) is updated, and the
+ * tangential history (hn_in entries of ORC_TS doubles each) is read and
+ * rewritten to key_out / T_out (capacity npairs + 2 D np entries),
+ * returning the entry count.
  * fixed (nullable): points of fixed obstacle bodies (R26), which keep X,
  * U = 0 and W = 0, exchange momentum with the fluid like any point (g with
  * U = 0), act on moving particles with infinite mass, and feel neither the
@@ -726,23 +825,23 @@ int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, 
     int D = orc_dim(c->lattice);
     int n_sub = c->n_sub;
     double h = 1.0 / n_sub;
-    int mind = c->contact == 4;
+    int mind = c->contact == 4 || c->contact == 5;
     int npp = np > 0 ? np : 1;
     double *m = malloc(sizeof(double) * npp);
     double *g = malloc(sizeof(double) * 3 * npp);
     double *Fc = malloc(sizeof(double) * 3 * npp);
     double *tq = malloc(sizeof(double) * 3 * npp);
-    double *Tp = malloc(sizeof(double) * 3 * (npairs > 0 ? npairs : 1));
-    double *Tw = malloc(sizeof(double) * 3 * 6 * npp);
+    double *Tp = malloc(sizeof(double) * ORC_TS * (npairs > 0 ? npairs : 1));
+    double *Tw = malloc(sizeof(double) * ORC_TS * 6 * npp);
     /* tangential forces carried over from the previous step */
     for (int64_t i = 0; i < npairs; i++) {
         int64_t e = mind ? hist_find(hn_in, key_in, pairs[2 * i], pairs[2 * i + 1]) : -1;
-        for (int a = 0; a < 3; a++) Tp[3 * i + a] = e >= 0 ? T_in[3 * e + a] : 0.0;
+        for (int a = 0; a < ORC_TS; a++) Tp[ORC_TS * i + a] = e >= 0 ? T_in[ORC_TS * e + a] : 0.0;
     }
     for (int p = 0; p < np; p++)
         for (int w = 0; w < 6; w++) {
             int64_t e = mind ? hist_find(hn_in, key_in, p, -1 - w) : -1;
-            for (int a = 0; a < 3; a++) Tw[3 * (6 * p + w) + a] = e >= 0 ? T_in[3 * e + a] : 0.0;
+            for (int a = 0; a < ORC_TS; a++) Tw[ORC_TS * (6 * p + w) + a] = e >= 0 ? T_in[ORC_TS * e + a] : 0.0;
         }
     for (int p = 0; p < np; p++) {
         m[p] = orc_mass(D, d[p], rho_p[p]);
@@ -778,11 +877,11 @@ int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, 
             for (int a = 0; a < D; a++) {
                 if (c->periodic[a]) continue;
                 for (int side = 0; side < 2; side++) {
-                    double *T = Tw + 3 * (6 * p + 2 * a + side);
+                    double *T = Tw + ORC_TS * (6 * p + 2 * a + side);
                     double dist = side == 0 ? Xp[a] : c->n[a] - Xp[a];
                     double delta = R - dist;
                     if (!(delta > 0.0)) {
-                        T[0] = T[1] = T[2] = 0.0;
+                        memset(T, 0, sizeof(double) * ORC_TS);     /* out of contact: no state */
                         continue;
                     }
                     double n[3] = {0, 0, 0};
@@ -794,7 +893,7 @@ int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, 
                     if (D == 3) { Wp[0] = W[p]; Wp[1] = W[np + p]; }
                     cross3(Wp, arm, wr);
                     for (int b = 0; b < 3; b++) vrel[b] = Up[b] + wr[b];
-                    mindlin_update(c, h, n, vrel, Fn, R, delta, T);
+                    tangential_update(c, h, n, vrel, Fn, R, delta, T);
                     double t[3];
                     cross3(arm, T, t);
                     for (int b = 0; b < 3; b++) {
@@ -821,12 +920,12 @@ int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, 
                     }
                     continue;
                 }
-                double *T = Tp + 3 * i;
+                double *T = Tp + ORC_TS * i;
                 double dist = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
                 double Rp = 0.5 * d[p], Rq = 0.5 * d[q];
                 double delta = Rp + Rq - dist;
                 if (!(delta > 0.0)) {
-                    T[0] = T[1] = T[2] = 0.0;
+                    memset(T, 0, sizeof(double) * ORC_TS);
                     continue;
                 }
                 double rstar = Rp * Rq / (Rp + Rq);
@@ -845,7 +944,7 @@ int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, 
                 cross3(Wp, ap, wp);
                 cross3(Wq, aq, wq);
                 for (int a = 0; a < 3; a++) vrel[a] = (du[a] + wp[a]) - wq[a];
-                mindlin_update(c, h, n, vrel, Fn, rstar, delta, T);
+                tangential_update(c, h, n, vrel, Fn, rstar, delta, T);
                 double tp[3], tqq[3], mT[3] = {-T[0], -T[1], -T[2]};
                 cross3(ap, T, tp);
                 cross3(aq, mT, tqq);
@@ -888,24 +987,29 @@ int64_t orc_dem_full(const orc_cfg *c, int np, double *X, double *U, double *W, 
             gbar[a * np + p] /= n_sub;
             fc_mean[a * np + p] /= n_sub;
         }
-    /* the new history: every contact that still carries a tangential force */
+    /* the new history: every contact whose tangential state is not zero
+     * (the no-slip form carries only T, so a contact carries a force) */
     int64_t hn = 0;
     if (mind) {
         for (int64_t i = 0; i < npairs; i++) {
-            double *T = Tp + 3 * i;
-            if (T[0] == 0.0 && T[1] == 0.0 && T[2] == 0.0) continue;
+            double *T = Tp + ORC_TS * i;
+            int any = 0;
+            for (int a = 0; a < ORC_TS; a++) any |= T[a] != 0.0;
+            if (!any) continue;
             key_out[2 * hn] = pairs[2 * i];
             key_out[2 * hn + 1] = pairs[2 * i + 1];
-            for (int a = 0; a < 3; a++) T_out[3 * hn + a] = T[a];
+            for (int a = 0; a < ORC_TS; a++) T_out[ORC_TS * hn + a] = T[a];
             hn++;
         }
         for (int p = 0; p < np; p++)
             for (int w = 0; w < 6; w++) {
-                double *T = Tw + 3 * (6 * p + w);
-                if (T[0] == 0.0 && T[1] == 0.0 && T[2] == 0.0) continue;
+                double *T = Tw + ORC_TS * (6 * p + w);
+                int any = 0;
+                for (int a = 0; a < ORC_TS; a++) any |= T[a] != 0.0;
+                if (!any) continue;
                 key_out[2 * hn] = p;
                 key_out[2 * hn + 1] = -1 - w;
-                for (int a = 0; a < 3; a++) T_out[3 * hn + a] = T[a];
+                for (int a = 0; a < ORC_TS; a++) T_out[ORC_TS * hn + a] = T[a];
                 hn++;
             }
     }
@@ -931,7 +1035,7 @@ void orc_dem(const orc_cfg *c, int np, double *X, double *U, const double *d,
  *   positions;  O4 particle sub-steps;  O5 spreading of A_p gbar with the
  *   start-of-step weights (if two_way);  O6-O7 collision with
  *   F = fluid_force + spread, and streaming.
- * Particle state X, U (and, with contact = 4, W and the tangential-force
+ * Particle state X, U (and, with contact = 4 or 5, W and the tangential
  * history of orc_dem_full) is updated in place.  Outputs: fout; F (D x N,
  * the force field used by the collision); gbar, fc_mean (D x np); returns
  * the number of particles whose vmax exceeds skin/2 (the skin check). */

@@ -9,9 +9,9 @@
  * paths the parity tests use is then checked.
  *
  * Cases: D2Q9 with the linear spring-dashpot and the Lagrange gather;
- * D3Q19 with Hertz-Mindlin contacts, rotation, the tangential history
- * carried over three steps, and points of fixed obstacle bodies with their
- * own areas; D3Q15 with soft repulsion and bins of four cells; and the
+ * D3Q19 with Hertz-Mindlin contacts (no-slip and micro-slip forms),
+ * rotation, the tangential history carried over three steps, and points of
+ * fixed obstacle bodies with their own areas; D3Q15 with soft repulsion and bins of four cells; and the
  * brute-force and cell-list candidate searches.  It prints one line per
  * case and "sanitize_driver: ok" at the end; a sanitizer finding aborts
  * with a report and a non-zero exit status.
@@ -150,6 +150,10 @@ int main(void)
     c = base_cfg(19, 11, 10, 9);
     c.contact = 4;
     bad |= run_case("D3Q19 Hertz-Mindlin, rotation, fixed bodies", c, 70, 3, 1);
+
+    c = base_cfg(19, 11, 10, 9);
+    c.contact = 5;
+    bad |= run_case("D3Q19 Hertz-Mindlin with micro-slip, rotation, fixed bodies", c, 70, 3, 1);
 
     c = base_cfg(9, 17, 15, 1);
     c.contact = 3;

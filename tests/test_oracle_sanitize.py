@@ -3,8 +3,9 @@
 oracle/sanitize_driver.c compiles the whole oracle into one program and
 runs coupled steps through every entry point the parity tests use: the
 linear spring-dashpot with the Lagrange gather (D2Q9), Hertz-Mindlin
-contacts with rotation, a tangential history carried over three steps and
-fixed obstacle points with their own areas (D3Q19), Hertz with fixed points
+contacts (no-slip and micro-slip) with rotation, a tangential history
+carried over three steps and fixed obstacle points with their own areas
+(D3Q19), Hertz with fixed points
 (D2Q9), soft repulsion with bins of four cells (D3Q15), a periodic lattice,
 and both candidate searches.  Any out-of-bounds access, use after free,
 leak, signed overflow, bad shift or float-to-int overflow aborts the
@@ -33,4 +34,5 @@ def test_oracle_under_address_and_ub_sanitizers(tmp_path):
     assert r.returncode == 0, r.stdout + r.stderr
     assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr, r.stderr
     assert r.stdout.strip().endswith("sanitize_driver: ok")
-    assert "history 0, skin" not in r.stdout.splitlines()[1]      # the Hertz-Mindlin case carried contacts
+    lines = r.stdout.splitlines()
+    assert "history 0, skin" not in lines[1] and "history 0, skin" not in lines[2]   # Hertz-Mindlin carried contacts
