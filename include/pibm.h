@@ -281,6 +281,19 @@ pibm_status pibm_synchronize(pibm_ctx* ctx);
 pibm_status pibm_conservation(pibm_ctx* ctx, double* mass, double* momentum);
 pibm_status pibm_diagnostics(pibm_ctx* ctx, pibm_diag* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as pibm_conservation, bit for bit (same kernels, same order), with
+ * the reductions' partial sums in a module-scope device array of the library
+ * (66.7 KB per GPU, held until the process ends) instead of the context's
+ * workspace.  It allocates nothing and calls no allocating routine.  Nothing
+ * in the array needs clearing (every slot read is first written by the same
+ * call).  Every call on one GPU shares that array: calls that overlap on one
+ * GPU (several streams or host threads at once) race and may return each
+ * other's sums.  A reduction needing more scratch than the array holds is
+ * rejected with PIBM_E_CONFIG.  Synchronising, like pibm_conservation. */
+pibm_status pibm_conservation_noalloc(pibm_ctx* ctx, double* mass, double* momentum);
+
 /* ---- Adjoint of a rollout (reverse-mode gradients) ----------------------
  * Gradients of a scalar objective J(X_T, U_T) of the particle state after
  * n_steps coupled steps with respect to the relaxation time tau (Eq. lbm2),

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -119,6 +120,9 @@ struct pibm_ctx {
     uint64_t steps_done = 0;
     // fixed obstacle bodies: the body of each particle id (-1: moving)
     std::vector<int> body_of;
+    // device address of the module-scope reduction scratch on this
+    // context's GPU (for pibm_conservation_noalloc), resolved at creation
+    double* scratch = nullptr;
     ~pibm_ctx() {
         // nothing to report from a destructor: failures are dropped on purpose
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -163,6 +167,35 @@ struct HipSeq {
         if (e == hipSuccess) e = r;
     }
 };
+
+// Reduction scratch of pibm_conservation_noalloc: the per-block FP64 partial
+// sums of the mass/momentum reductions (8 per block) and their totals.
+// Module-scope device memory, so that entry point allocates nothing; each
+// GPU the library runs on holds its own copy until the process ends.  In
+// host code the name is only a host-side stand-in: device code gets the
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t SCRATCH_DOUBLES = 8 * 1040 + 16;     // 66.7 KB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+double* scratch_addr[MAX_DEVICES] = {};          // per device, resolved once
+
+// The device address of `scratch` on the current device (resolved once per
+// device, with that device current).
+hipError_t scratch_for_current_device(double** out) {
+    int dev = -1;
+    if (hipError_t e = hipGetDevice(&dev)) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_addr[dev]) {
+        void* p = nullptr;
+        if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) return e;
+        scratch_addr[dev] = (double*)p;
+    }
+    *out = scratch_addr[dev];
+    return hipSuccess;
+}
 
 int dimension(int lattice) { return lattice == PIBM_D2Q9 ? 2 : 3; }
 
@@ -506,6 +539,10 @@ pibm_status pibm_create(const pibm_config* cfg, int64_t n_particles, void* dev_w
         return PIBM_E_HIP;
     }
     *(volatile uint32_t*)c->host_active = 0xffffffffu;   // unknown: multi-kernel set-up
+    if (scratch_for_current_device(&c->scratch) != hipSuccess) {
+        delete c;
+        return PIBM_E_HIP;
+    }
     HipSeq q;
     q(hipMemsetAsync(c->F, 0, sizeof(float) * c->D * c->N, c->stream));
     if (c->np > 0) q(hipMemsetAsync(c->pb.cnt, 0, sizeof(uint32_t) * (c->pc.nbins + 1), c->stream));
@@ -1077,20 +1114,25 @@ pibm_status pibm_synchronize(pibm_ctx* c) {
     return sync_and_flags(c);
 }
 
-pibm_status pibm_diagnostics(pibm_ctx* c, pibm_diag* out) {
-    if (!c || !out) return PIBM_E_ARG;
+}  // extern "C"
+
+namespace {
+// Diagnostics with the reductions' partial sums in `part` (8 doubles per
+// block) and their totals in `totals` (16 doubles).  Every slot read is
+// written first by the same call, so neither needs clearing.
+pibm_status diagnostics_with(pibm_ctx* c, double* part, double* totals, pibm_diag* out) {
     std::memset(out, 0, sizeof(*out));
-    lattice_totals(c->Q, c->fp16, c->sl2, c->fA, c->N, c->part, c->totals, c->stream);
+    lattice_totals(c->Q, c->fp16, c->sl2, c->fA, c->N, part, totals, c->stream);
     double fl[8];
     double pt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t cnt[2] = {0, 0};
     HipSeq q;
     q(hipGetLastError());
-    q(hipMemcpyAsync(fl, c->totals, sizeof(fl), hipMemcpyDeviceToHost, c->stream));
+    q(hipMemcpyAsync(fl, totals, sizeof(fl), hipMemcpyDeviceToHost, c->stream));
     if (c->np > 0 && c->particles_set) {
-        particles_totals(c->D, c->pb, c->np, c->part, c->totals + 8, c->stream);
+        particles_totals(c->D, c->pb, c->np, part, totals + 8, c->stream);
         q(hipGetLastError());
-        q(hipMemcpyAsync(pt, c->totals + 8, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        q(hipMemcpyAsync(pt, totals + 8, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         q(hipMemcpyAsync(cnt, c->pb.counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
     }
     // the host buffers above are written by the stream: wait before any return
@@ -1116,9 +1158,39 @@ pibm_status pibm_diagnostics(pibm_ctx* c, pibm_diag* out) {
     return PIBM_OK;
 }
 
+// Scratch doubles the reductions need: partial sums of the larger of the
+// two block counts, then 16 totals.
+size_t reduction_scratch_doubles() {
+    return 8 * ((size_t)std::max(lattice_totals_blocks(), particles_totals_blocks()) + 2) + 16;
+}
+}  // namespace
+
+extern "C" {
+
+pibm_status pibm_diagnostics(pibm_ctx* c, pibm_diag* out) {
+    if (!c || !out) return PIBM_E_ARG;
+    return diagnostics_with(c, c->part, c->totals, out);
+}
+
 pibm_status pibm_conservation(pibm_ctx* c, double* mass, double* momentum) {
     pibm_diag dg;
     pibm_status st = pibm_diagnostics(c, &dg);
+    if (mass) *mass = dg.mass;
+    if (momentum)
+        for (int a = 0; a < 3; a++) momentum[a] = dg.momentum[a];
+    return st;
+}
+
+pibm_status pibm_conservation_noalloc(pibm_ctx* c, double* mass, double* momentum) {
+    if (!c) return PIBM_E_ARG;
+    if (!c->scratch) return fail(c, PIBM_E_STATE, "static reduction scratch not resolved for this context's GPU");
+    const size_t need = reduction_scratch_doubles();
+    if (need > SCRATCH_DOUBLES)
+        return fail(c, PIBM_E_CONFIG, "the reductions need " + std::to_string(need) +
+                                          " doubles of scratch, above the static maximum of " +
+                                          std::to_string(SCRATCH_DOUBLES));
+    pibm_diag dg;
+    pibm_status st = diagnostics_with(c, c->scratch, c->scratch + (need - 16), &dg);
     if (mass) *mass = dg.mass;
     if (momentum)
         for (int a = 0; a < 3; a++) momentum[a] = dg.momentum[a];

@@ -97,6 +97,7 @@ def load():
         "pibm_step": ([vp, C.c_int32], C.c_int),
         "pibm_synchronize": ([vp], C.c_int),
         "pibm_conservation": ([vp, dp, dp], C.c_int),
+        "pibm_conservation_noalloc": ([vp, dp, dp], C.c_int),
         "pibm_diagnostics": ([vp, C.POINTER(Diag)], C.c_int),
         "pibm_set_profiling": ([vp, C.c_int], C.c_int),
         "pibm_phase_times": ([vp, dp, C.POINTER(C.c_int64)], C.c_int),
