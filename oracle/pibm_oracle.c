@@ -689,10 +689,12 @@ static void into_plane(const double *n, double *v)
  * The elastic trial increment is E = -8 G* r_a h v_t, r_a = sqrt(delta R*)
  * (v_t: the tangential part of vrel, so h v_t is the increment of the
  * tangential surface displacement).  contact = 4 takes the no-slip limit
- * theta_k = 1 of the paper's increment: T += E.  contact = 5 (R27) takes
- *   dT = theta_k E + (-1)^k mu dF_n (1 - theta_k) t
- * along the contact's loading direction t (the direction of its first
- * tangential increment, turned with the contact plane), with the
+ * theta_k = 1 of the paper's increment: T += E.  contact = 5 (R27) applies
+ * the paper's increment to the part of E along the contact's loading
+ * direction t (the direction of its first tangential increment, turned with
+ * the contact plane), e = E.t:
+ *   dT = [theta_k e + (-1)^k mu dF_n (1 - theta_k)] t + (E - e t)
+ * (the part of E across t is taken elastically), with the
  * Mindlin-Deresiewicz factors in the incremental form of Thornton:
  *   loading   (k = 0): theta^3 = 1 - (T_t + mu dF_n) / (mu F_n)
  *   unloading (k = 1): theta^3 = 1 - (T* - T_t + 2 mu dF_n) / (2 mu F_n)
@@ -703,8 +705,11 @@ static void into_plane(const double *n, double *v)
  * with e < 0 starts unloading (T* = T_t), unloading with e > 0 starts
  * reloading (T** = T_t), reloading with e < 0 unloads again (T* = T_t) and
  * reloading that reaches T* is back on the loading curve (k = 0).  While the
- * normal force grows faster than the tangential load, |E| <= mu dF_n, no
- * slip zone grows and dT = E.  Both forms finally cap |T| at mu F_n
+ * normal force grows faster than the tangential load, |e| <= mu dF_n, no
+ * slip zone grows and dT = E.  Along one line (E parallel to t) this is
+ * Mindlin-Deresiewicz's law; splitting off the cross part keeps the
+ * increment continuous where k changes (e = 0) and where the slip zone
+ * starts to grow (|e| = mu dF_n).  Both forms finally cap |T| at mu F_n
  * (Coulomb sliding). */
 static void tangential_update(const orc_cfg *c, double h, const double *n, const double *vrel,
                               double Fn, double rstar, double delta, double *S)
@@ -747,7 +752,7 @@ static void tangential_update(const orc_cfg *c, double h, const double *n, const
                 }
             }
             S[6] = k;
-            if (dFn > 0.0 && el <= mu * dFn) {
+            if (dFn > 0.0 && fabs(e) <= mu * dFn) {
                 for (int a = 0; a < 3; a++) T[a] += E[a];
             } else {
                 double arg;
@@ -760,7 +765,8 @@ static void tangential_update(const orc_cfg *c, double h, const double *n, const
                 arg = arg < 0.0 ? 0.0 : (arg > 1.0 ? 1.0 : arg);
                 double th = cbrt(arg);
                 double sg = k == 1 ? -1.0 : 1.0;
-                for (int a = 0; a < 3; a++) T[a] += th * E[a] + sg * mu * dFn * (1.0 - th) * t[a];
+                double dt = th * e + sg * mu * dFn * (1.0 - th);     /* along t */
+                for (int a = 0; a < 3; a++) T[a] += dt * t[a] + (E[a] - e * t[a]);
             }
         }
     } else {

@@ -50,7 +50,7 @@ def _scene(orc, D, contact):
 
 
 @pytest.mark.parametrize("D,contact", [(2, "lsd"), (3, "lsd"), (3, "hertz"), (3, "hertz_mindlin"),
-                                       (2, "hertz_mindlin")])
+                                       (2, "hertz_mindlin"), (3, "hertz_mindlin_microslip")])
 def test_fixed_points_are_supports(orc, D, contact):
     cfg, X, U, d, rp, fixed, area = _scene(orc, D, contact)
     N = orc.nnodes(cfg)
