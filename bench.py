@@ -425,6 +425,8 @@ def main():
         # the paper's contact law on the c2 particles
         r, _ = run_gpu(W.WORKLOADS["c2_hm"], args.extra_steps, 2, "c2_hm")
         extra["c2_hertz_mindlin"] = r
+        r, _ = run_gpu(W.WORKLOADS["c2_hms"], args.extra_steps, 2, "c2_hms")
+        extra["c2_hertz_mindlin_microslip"] = r
         # the hybrid IBM-PIBM case: particles above fixed obstacle bodies
         r, _ = run_gpu(W.WORKLOADS["hybrid"], args.extra_steps, 2, "hybrid")
         extra["hybrid_obstacles"] = r

@@ -77,7 +77,8 @@ enum {
     PIBM_CONTACT_LSD = 1,
     PIBM_CONTACT_SOFT = 2,
     PIBM_CONTACT_HERTZ = 3,
-    PIBM_CONTACT_HERTZ_MINDLIN = 4
+    PIBM_CONTACT_HERTZ_MINDLIN = 4,
+    PIBM_CONTACT_HERTZ_MINDLIN_MICROSLIP = 5
 };
 enum { PIBM_INTERP_DELTA = 0, PIBM_INTERP_LAGRANGE = 1 };
 
@@ -108,7 +109,14 @@ typedef struct {
     double fluid_force[3];    /* uniform body force density on the fluid */
     int32_t contact;          /* PIBM_CONTACT_*: none, linear spring-dashpot, soft repulsion,
                                  Hertz, or Hertz with the Mindlin tangential force and particle
-                                 rotation (Sec. 2.3; young, poisson, friction below) */
+                                 rotation (Sec. 2.3; young, poisson, friction below), in its
+                                 no-slip limit (HERTZ_MINDLIN) or with the Mindlin-Deresiewicz
+                                 micro-slip factors (HERTZ_MINDLIN_MICROSLIP): the increment
+                                 dT = 8 G* r_a theta_k d(delta_t) + (-1)^k mu dF_n (1 - theta_k)
+                                 along the contact's loading direction, with theta_k of loading
+                                 (k = 0), unloading (1) and reloading (2) from the turning points
+                                 T*, T** (Thornton's incremental form), elastic while the normal
+                                 force grows faster than the tangential load */
     int32_t n_sub;            /* DEM sub-steps per lattice step, >= 1 */
     double kn;                /* linear spring stiffness */
     double restitution;       /* normal restitution of the linear spring-dashpot, (0, 1] */
@@ -209,7 +217,7 @@ pibm_status pibm_set_particles_device(pibm_ctx* ctx, const float* x_hi, const fl
  * the sub-step mean contact force.  Asynchronous on the context's stream. */
 pibm_status pibm_read_particles_device(pibm_ctx* ctx, float* x_hi, float* x_lo, float* v,
                                        float* f_hydro, float* f_contact);
-/* Angular velocities for PIBM_CONTACT_HERTZ_MINDLIN (the second line of
+/* Angular velocities for PIBM_CONTACT_HERTZ_MINDLIN(_MICROSLIP) (the second line of
  * Eq. demgov), host FP64 arrays in id order: 3 x N (x, y, z) in 3D, N (the
  * z component) in 2D.  pibm_set_particles sets them to zero and clears the
  * tangential-force history; pibm_set_rotation may follow it before the first

@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_adj_particles(PState A, int np, Grid g,
                                                        const float* __restrict__ xbh, const float* __restrict__ xbl,
                                                        const float* __restrict__ ub, float* __restrict__ xbh_o,
                                                        float* __restrict__ xbl_o, float* __restrict__ ub_o,
-                                                       float* __restrict__ coefS, float* __restrict__ wphi,
+                                                       float* __restrict__ coefS, float* __restrict__ srec,
                                                        short4* __restrict__ wbase, float* __restrict__ gpart) {
     __shared__ float red[3][256];
     const int s = blockIdx.x * 256 + threadIdx.x;
@@ -386,7 +386,8 @@ __global__ __launch_bounds__(256) void k_adj_particles(PState A, int np, Grid g,
 #pragma unroll
         for (int a = 0; a < D; a++)
 #pragma unroll
-            for (int k = 0; k < 4; k++) wphi[(long long)s * (4 * D) + 4 * a + k] = phi[a][k];
+            for (int k = 0; k < 4; k++) srec[(long long)s * SRec<D>::STRIDE + 4 * a + k] = phi[a][k];
+        srec[(long long)s * SRec<D>::STRIDE + SRec<D>::BASE] = __int_as_float(base[0]);
         wbase[s] = make_short4((short)base[0], (short)base[1], (short)base[2], 0);
     }
 #pragma unroll
@@ -562,10 +563,10 @@ void adj_particles(int D, PBuf& b, int np, const Grid& g, const PCfg& c, int two
                    float* xbl_o, float* ub_o, float* coefS, float* gpart, hipStream_t s) {
     if (D == 3)
         hipLaunchKernelGGL(k_adj_particles<3>, dim3(blocks256(np)), dim3(256), 0, s, b.A, np, g, c, two_way, b.start,
-                           b.keys_sorted, mom, Fbar, xbh, xbl, ub, xbh_o, xbl_o, ub_o, coefS, b.wphi, b.wbase, gpart);
+                           b.keys_sorted, mom, Fbar, xbh, xbl, ub, xbh_o, xbl_o, ub_o, coefS, b.srec, b.wbase, gpart);
     else
         hipLaunchKernelGGL(k_adj_particles<2>, dim3(blocks256(np)), dim3(256), 0, s, b.A, np, g, c, two_way, b.start,
-                           b.keys_sorted, mom, Fbar, xbh, xbl, ub, xbh_o, xbl_o, ub_o, coefS, b.wphi, b.wbase, gpart);
+                           b.keys_sorted, mom, Fbar, xbh, xbl, ub, xbh_o, xbl_o, ub_o, coefS, b.srec, b.wbase, gpart);
 }
 
 void adj_accumulate(const float* tpart, int ntb, const float* gpart, int ngb, float* acc, hipStream_t s) {

@@ -358,7 +358,7 @@ __device__ __forceinline__ void axis_gather(float xh, float xl, int n, int& base
 template <int D, bool LAG>
 __global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const float4* __restrict__ mom,
                                                 float* __restrict__ drho_i, float* __restrict__ j_i,
-                                                short4* __restrict__ wbase, float* __restrict__ wphi) {
+                                                short4* __restrict__ wbase, float* __restrict__ srec) {
     constexpr int LP = (D == 3) ? 16 : 4;   // lanes per particle
     long long gt = (long long)xcd_block() * 256 + threadIdx.x;
     int s = (int)(gt / LP);
@@ -403,13 +403,14 @@ __global__ __launch_bounds__(256) void k_interp(PState A, int np, Grid g, const 
         j_i[(long long)np + s] = acc[2];
         if (D == 3) j_i[2LL * np + s] = acc[3];
         wbase[s] = make_short4((short)base[0], (short)base[1], (short)base[2], 0);
+        srec[(long long)s * SRec<D>::STRIDE + SRec<D>::BASE] = __int_as_float(base[0]);
     }
     // weights for the spreading pass: 4 D floats per particle
     if (D == 3) {
-        if (l < 12) wphi[(long long)s * 12 + l] = phi[l >> 2][l & 3];
+        if (l < 12) srec[(long long)s * SRec<D>::STRIDE + l] = phi[l >> 2][l & 3];
     } else {
-        wphi[(long long)s * 8 + l] = phi[0][l];
-        wphi[(long long)s * 8 + 4 + l] = phi[1][l];
+        srec[(long long)s * SRec<D>::STRIDE + l] = phi[0][l];
+        srec[(long long)s * SRec<D>::STRIDE + 4 + l] = phi[1][l];
     }
 }
 
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
                                                      const uint32_t* __restrict__ start,
                                                      Src src,
                                                      float* __restrict__ drho_i, float* __restrict__ j_i,
-                                                     short4* __restrict__ wbase, float* __restrict__ wphi,
+                                                     short4* __restrict__ wbase, float* __restrict__ srec,
                                                      int ntx, int nty) {
     using T0 = InterpTile<D>;
     constexpr int NX = T0::CX + 3, NY = T0::CY + 3, NZ = (D == 3) ? T0::CZ + 3 : 1;
@@ -554,10 +555,12 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
         j_i[(long long)np + s] = acc2;
         if (D == 3) j_i[2LL * np + s] = acc3;
         wbase[s] = make_short4((short)base[0], (short)base[1], (short)base[2], 0);
+        float* rec = srec + (long long)s * SRec<D>::STRIDE;
 #pragma unroll
         for (int a = 0; a < D; a++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) wphi[(long long)s * (4 * D) + 4 * a + q] = phi[a][q];
+            for (int q = 0; q < 4; q++) rec[4 * a + q] = phi[a][q];
+        rec[SRec<D>::BASE] = __int_as_float(base[0]);
     }
 }
 
@@ -656,7 +659,7 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
                                                   const float4* __restrict__ pos4,
                                                   const uint32_t* __restrict__ keys_sorted,
                                                   const float* __restrict__ drho_i, const float* __restrict__ j_i,
-                                                  float* __restrict__ coef, float* __restrict__ fc,
+                                                  float* __restrict__ srec, float* __restrict__ fc,
                                                   unsigned long long* __restrict__ actcc,
                                                   unsigned long long* __restrict__ bsum,
                                                   uint32_t* __restrict__ counters, uint32_t* __restrict__ flags,
@@ -738,7 +741,7 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
                 Bn.xh[a][s] = xh;
                 Bn.xl[a][s] = xl;
                 Bn.u[a][s] = un[a];
-                coef[(long long)a * np + s] = Ap * gb[a];
+                srec[(long long)s * SRec<D>::STRIDE + SRec<D>::COEF + a] = Ap * gb[a];
                 fc[(long long)a * np + s] = 0.f;
             }
             if (hcnt) {
@@ -1018,7 +1021,7 @@ __device__ __forceinline__ void cand_prep_one(uint32_t a, const PState& A, const
         cd.K0 = k0h + (k0e + (qe - sl));
         cd.rc = rch;
         cd.r0[0] = r0[0]; cd.r0[1] = r0[1]; cd.r0[2] = r0[2];
-        if (c.contact == PIBM_CONTACT_HERTZ || c.contact == PIBM_CONTACT_HERTZ_MINDLIN) {
+        if (c.contact == PIBM_CONTACT_HERTZ || c.contact >= PIBM_CONTACT_HERTZ_MINDLIN) {
             // Hertz: gam holds the pair's stiffness (4/3) E* sqrt(R*)
             const float rs = 0.5f * A.d[s], rt = 0.5f * A.d[t];
             const float rstar = rs * rt / (rs + rt);
@@ -1028,15 +1031,18 @@ __device__ __forceinline__ void cand_prep_one(uint32_t a, const PState& A, const
                 const int pid = A.id[t];
                 const long long base = (long long)A.id[s] * c.hmax;
                 const uint32_t hn = md.hcnt[A.id[s]];
-                float T[3] = {0.f, 0.f, 0.f};
+                float S[TSN];
+#pragma unroll
+                for (int q = 0; q < TSN; q++) S[q] = 0.f;
                 for (uint32_t e = 0; e < hn; e++)
                     if (md.hkey[base + e] == pid) {
-                        T[0] = md.hT[3 * (base + e)];
-                        T[1] = md.hT[3 * (base + e) + 1];
-                        T[2] = md.hT[3 * (base + e) + 2];
+#pragma unroll
+                        for (int q = 0; q < TSN; q++) S[q] = md.hT[TSN * (base + e) + q];
                         break;
                     }
-                md.cmd[off + k] = make_float4(T[0], T[1], T[2], c.kt8 * sqrtf(rstar));
+                md.cmd[off + k] = make_float4(S[0], S[1], S[2], c.kt8 * sqrtf(rstar));
+                md.cms[2 * (off + k)] = make_float4(S[3], S[4], S[5], S[9]);
+                md.cms[2 * (off + k) + 1] = make_float4(S[6], S[7], S[8], 0.f);
                 md.cpid[off + k] = pid;
             }
         } else {
@@ -1139,6 +1145,8 @@ struct Active {
     float u[3], cu[3];      // velocity and its compensation
     float ri, j[3];
     float m, Ap, bw[3], d, gw;
+    float hm, hbw[3];       // h / m and h (1 - rho0/rho_p) g: the update without a division
+    float lq, ihc;          // log(1 - hc) (when hc < 1) and 1 / hc, for the closed-form jumps
     float gs[3], fs[3];     // sums of g and of the contact force
     float vmax2;
     uint32_t off;
@@ -1150,9 +1158,9 @@ struct Active {
     // the wall contact of each axis (bit a of wside: the upper wall), moment
     // of inertia, radius, id
     float W[3];
-    float wT[3][3];
+    float wT[3][TSN];       // tangential state of the wall contact of each axis
     uint32_t wside;
-    float I, R;
+    float I, R, hI;         // hI = h / I
     int id;
     // a point of a fixed body: never moves, spreads with its own area Af
     bool fixed;
@@ -1165,28 +1173,107 @@ __device__ __forceinline__ void cross3(const float* x, const float* y, float* z)
     z[2] = x[0] * y[1] - x[1] * y[0];
 }
 
-// Tangential force of one contact, one sub-step (Mindlin in its no-slip
-// limit with the Coulomb bound, Sec. 2.3): turn T into the contact plane
-// keeping its length, add -k_t h v_t, cap |T| at mu F_n.  n: unit normal
-// from the partner to the particle; vrel: contact-point velocity relative to
-// the partner's.
-__device__ __forceinline__ void mindlin_update(const PCfg& c, const float* n, const float* vrel, float Fn, float kt,
-                                               float* T) {
-    const float tn = T[0] * n[0] + T[1] * n[1] + T[2] * n[2];
-    const float old = sqrtf(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
+// Turn v into the contact plane of unit normal n, keeping its length.
+__device__ __forceinline__ void into_plane(const float* n, float* v) {
+    const float vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+    const float old = sqrt_fast(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     float P[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) P[a] = T[a] - tn * n[a];
-    const float pl = sqrtf(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+    for (int a = 0; a < 3; a++) P[a] = v[a] - vn * n[a];
+    const float pl2 = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
+    const float sp = pl2 > 0.f ? old * rsq_fast(pl2) : 0.f;
 #pragma unroll
-    for (int a = 0; a < 3; a++) T[a] = pl > 0.f ? P[a] * (old / pl) : 0.f;
+    for (int a = 0; a < 3; a++) v[a] = P[a] * sp;
+}
+
+// Tangential state of one contact, one sub-step (Sec. 2.3).  n: unit normal
+// from the partner to the particle; vrel: contact-point velocity relative to
+// the partner's; S: the TSN-float state (T first).  The elastic trial
+// increment is E = -k_t h v_t.  No-slip limit (theta_k = 1): T += E.  With
+// micro-slip: dT = theta_k E + (-1)^k mu dF_n (1 - theta_k) t along the
+// contact's loading direction t (set by its first tangential increment):
+// the part e = E.t along t grows by theta_k e + (-1)^k mu dF_n (1 - theta_k),
+// the part across t elastically, with theta_k^3 = 1 - (T_t + mu dF_n)/(mu F_n)
+// when loading (k = 0), 1 - (T* - T_t + 2 mu dF_n)/(2 mu F_n) unloading
+// (k = 1), 1 - (T_t - T** + 2 mu dF_n)/(2 mu F_n) reloading (k = 2), clamped
+// to [0, 1]; k turns where e changes sign, a reloading that reaches T* is
+// loading again, and the step is elastic while |e| <= mu dF_n.  Finally
+// |T| <= mu F_n.
+__device__ __forceinline__ void tangential_update(const PCfg& c, const float* n, const float* vrel, float Fn,
+                                                  float kt, float* S) {
+    float* T = S;
+    into_plane(n, T);
     const float vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+    float E[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) T[a] -= kt * c.h * (vrel[a] - vn * n[a]);
-    const float tl = sqrtf(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
+    for (int a = 0; a < 3; a++) E[a] = -kt * c.h * (vrel[a] - vn * n[a]);
+    if (c.microslip) {
+        float* t = S + 3;
+        // the loading direction is turned into the plane and kept at unit
+        // length: carrying its length like T's would let FP32 rounding
+        // random-walk it, and the law weighs every increment by it
+        {
+            const float tn = t[0] * n[0] + t[1] * n[1] + t[2] * n[2];
+#pragma unroll
+            for (int a = 0; a < 3; a++) t[a] -= tn * n[a];
+            const float q2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+            const float iq = q2 > 0.f ? rsq_fast(q2) : 0.f;
+#pragma unroll
+            for (int a = 0; a < 3; a++) t[a] *= iq;
+        }
+        const float dFn = Fn - S[9];
+        S[9] = Fn;
+        const float el2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
+        float tl2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+        if (tl2 == 0.f && el2 > 0.f) {                   // the first tangential increment sets t
+            const float ie = rsq_fast(el2);
+#pragma unroll
+            for (int a = 0; a < 3; a++) t[a] = E[a] * ie;
+            S[6] = S[7] = S[8] = 0.f;
+            tl2 = 1.f;
+        }
+        if (tl2 > 0.f) {
+            const float Tt = T[0] * t[0] + T[1] * t[1] + T[2] * t[2];
+            const float e = E[0] * t[0] + E[1] * t[1] + E[2] * t[2];
+            int k = (int)S[6];
+            if (k == 0 && e < 0.f) {
+                k = 1;
+                S[7] = Tt;
+            } else if (k == 1 && e > 0.f) {
+                k = 2;
+                S[8] = Tt;
+            } else if (k == 2) {
+                if (e < 0.f) {
+                    k = 1;
+                    S[7] = Tt;
+                } else if (Tt >= S[7]) {
+                    k = 0;
+                }
+            }
+            S[6] = (float)k;
+            const float mdf = c.mu * dFn;
+            if (dFn > 0.f && fabsf(e) <= mdf) {
+#pragma unroll
+                for (int a = 0; a < 3; a++) T[a] += E[a];
+            } else {
+                const float num = k == 0 ? Tt + mdf : (k == 1 ? S[7] - Tt + 2.0f * mdf : Tt - S[8] + 2.0f * mdf);
+                const float den = (k == 0 ? 1.0f : 2.0f) * c.mu * Fn;
+                const float arg = fminf(fmaxf(1.0f - num / den, 0.0f), 1.0f);
+                const float th = cbrtf(arg);
+                const float sg = k == 1 ? -mdf : mdf;
+                const float dt = th * e + sg * (1.0f - th);          // along t
+#pragma unroll
+                for (int a = 0; a < 3; a++) T[a] += dt * t[a] + (E[a] - e * t[a]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; a++) T[a] += E[a];
+    }
+    const float tl2 = T[0] * T[0] + T[1] * T[1] + T[2] * T[2];
     const float lim = c.mu * Fn;
-    if (tl > lim) {
-        const float sc = lim / tl;
+    if (tl2 > lim * lim) {
+        const float sc = lim * rsq_fast(tl2);
 #pragma unroll
         for (int a = 0; a < 3; a++) T[a] *= sc;
     }
@@ -1203,7 +1290,7 @@ __device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const
     P.Ap = 0.25f * PI_F * P.d * P.d;
     P.ri = 1.0f + drho_i[s];
     // wall dashpot coefficient, or the Hertz wall stiffness (4/3) E* sqrt(R_p)
-    const bool hertz = c.contact == PIBM_CONTACT_HERTZ || c.contact == PIBM_CONTACT_HERTZ_MINDLIN;
+    const bool hertz = c.contact == PIBM_CONTACT_HERTZ || c.contact >= PIBM_CONTACT_HERTZ_MINDLIN;
     P.gw = hertz ? c.hk * sqrtf(0.5f * P.d) : 2.0f * c.zeta * sqrtf(c.kn * P.m);
     float v2 = 0.f;
     bool wall = false;
@@ -1236,6 +1323,11 @@ __device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const
     }
     P.veq = sqrtf(ve);
     P.vmax2 = v2;
+    P.hm = c.h / P.m;
+#pragma unroll
+    for (int a = 0; a < 3; a++) P.hbw[a] = c.h * P.bw[a];
+    P.lq = P.hc < 1.0f ? log1pf(-P.hc) : 0.f;
+    P.ihc = 1.0f / P.hc;
     P.off = (uint32_t)(prefix[s] & 0xffffffffULL);
     P.cnt = c.contact != PIBM_CONTACT_NONE ? (int)ccount[s] : 0;
     P.fixed = A.fixa && A.fixa[s] > 0.f;
@@ -1252,13 +1344,16 @@ __device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const
     if (MD) {
         P.R = 0.5f * P.d;
         P.I = (D == 3 ? 0.4f : 0.5f) * P.m * P.R * P.R;
+        P.hI = c.h / P.I;
         P.W[0] = D == 3 ? A.w[0][s] : 0.f;
         P.W[1] = D == 3 ? A.w[1][s] : 0.f;
         P.W[2] = D == 3 ? A.w[2][s] : A.w[0][s];
         P.id = A.id[s];
         P.wside = 0u;
 #pragma unroll
-        for (int a = 0; a < 3; a++) P.wT[a][0] = P.wT[a][1] = P.wT[a][2] = 0.f;
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int q = 0; q < TSN; q++) P.wT[a][q] = 0.f;
         // wall contacts carried over from the last step
         const long long base = (long long)P.id * c.hmax;
         const uint32_t hn = md.hcnt[P.id];
@@ -1269,9 +1364,8 @@ __device__ __forceinline__ void active_load(Active<D>& P, const PState& A, const
 #pragma unroll
             for (int ax = 0; ax < D; ax++)
                 if (ax == a) {
-                    P.wT[ax][0] = md.hT[3 * (base + e)];
-                    P.wT[ax][1] = md.hT[3 * (base + e) + 1];
-                    P.wT[ax][2] = md.hT[3 * (base + e) + 2];
+#pragma unroll
+                    for (int q = 0; q < TSN; q++) P.wT[ax][q] = md.hT[TSN * (base + e) + q];
                     P.wside |= (uint32_t)(code & 1) << ax;
                 }
         }
@@ -1289,25 +1383,27 @@ __device__ __forceinline__ void wall_force_md(Active<D>& P, const PCfg& c, float
         const float dhi = ((rc - ((float)c.n[a] - P.xh[a])) + P.xl[a]) + P.dx[a];
         const bool lo = dlo > 0.f, hi = !lo && dhi > 0.f;
         if (!lo && !hi) {
-            P.wT[a][0] = P.wT[a][1] = P.wT[a][2] = 0.f;
+#pragma unroll
+            for (int q = 0; q < TSN; q++) P.wT[a][q] = 0.f;       // out of contact: no state
             continue;
         }
         const uint32_t side = hi ? 1u : 0u;
         if (((P.wside >> a) & 1u) != side) {
-            P.wT[a][0] = P.wT[a][1] = P.wT[a][2] = 0.f;
+#pragma unroll
+            for (int q = 0; q < TSN; q++) P.wT[a][q] = 0.f;
             P.wside ^= 1u << a;
         }
         const float delta = lo ? dlo : dhi;
         float n[3] = {0.f, 0.f, 0.f};
         n[a] = lo ? 1.0f : -1.0f;              // from the wall to the particle
-        const float Fn = P.gw * delta * sqrtf(delta);
+        const float Fn = P.gw * delta * sqrt_fast(delta);
         float arm[3], wr[3], vrel[3];
 #pragma unroll
         for (int b = 0; b < 3; b++) arm[b] = -P.R * n[b];
         cross3(P.W, arm, wr);
 #pragma unroll
         for (int b = 0; b < 3; b++) vrel[b] = (b < D ? P.u[b] : 0.f) + wr[b];
-        mindlin_update(c, n, vrel, Fn, c.kt8 * sqrtf(delta * P.R), P.wT[a]);
+        tangential_update(c, n, vrel, Fn, c.kt8 * sqrt_fast(delta * P.R), P.wT[a]);
         float t[3];
         cross3(arm, P.wT[a], t);
 #pragma unroll
@@ -1330,11 +1426,12 @@ __device__ __forceinline__ void wall_force(const Active<D>& P, const PCfg& c, fl
             if (dlo > 0.f) F[a] += c.kn * dlo - P.gw * P.u[a];
             if (dhi > 0.f) F[a] -= c.kn * dhi + P.gw * P.u[a];
         } else if (c.contact == PIBM_CONTACT_HERTZ) {
-            if (dlo > 0.f) F[a] += P.gw * dlo * sqrtf(dlo);
-            if (dhi > 0.f) F[a] -= P.gw * dhi * sqrtf(dhi);
+            if (dlo > 0.f) F[a] += P.gw * dlo * sqrt_fast(dlo);
+            if (dhi > 0.f) F[a] -= P.gw * dhi * sqrt_fast(dhi);
         } else {
-            if (dlo > 0.f) { float q = dlo / rc; F[a] += c.ks * q * q; }
-            if (dhi > 0.f) { float q = dhi / rc; F[a] -= c.ks * q * q; }
+            const float irc = rcp_fast(rc);
+            if (dlo > 0.f) { float q = dlo * irc; F[a] += c.ks * q * q; }
+            if (dhi > 0.f) { float q = dhi * irc; F[a] -= c.ks * q * q; }
         }
     }
 }
@@ -1356,9 +1453,9 @@ __device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& c
     float r2 = 0.f;
 #pragma unroll
     for (int a = 0; a < D; a++) r2 += r[a] * r[a];
-    float dist = sqrtf(r2);
-    float delta = num / (cd.rc + dist);          // r_c - |r|
-    float inv = 1.0f / dist;
+    const float inv = rsq_fast(r2);              // 1 / |r|
+    const float dist = r2 * inv;
+    const float delta = num * rcp_fast(cd.rc + dist);   // r_c - |r|
     if (c.contact == PIBM_CONTACT_LSD) {
         float vn = 0.f;
 #pragma unroll
@@ -1367,11 +1464,11 @@ __device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& c
 #pragma unroll
         for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
     } else if (c.contact == PIBM_CONTACT_HERTZ) {
-        float mag = cd.gam * delta * sqrtf(delta);
+        float mag = cd.gam * delta * sqrt_fast(delta);
 #pragma unroll
         for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
     } else {
-        float q = delta / cd.rc;
+        float q = delta * rcp_fast(cd.rc);
         float mag = c.ks * q * q;
 #pragma unroll
         for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
@@ -1384,8 +1481,8 @@ __device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& c
 // at +R_partner n from the partner's.
 template <int D>
 __device__ __forceinline__ void pair_force_md(const Active<D>& P, const CandData& cd, float4* __restrict__ cmd,
-                                              const float* odx, const float* ou, const float* ow, const PCfg& c,
-                                              float* F, float* tq) {
+                                              float4* __restrict__ cms, const float* odx, const float* ou,
+                                              const float* ow, const PCfg& c, float* F, float* tq) {
     float r[3] = {0, 0, 0};
     float rd = 0.f, dd = 0.f;
 #pragma unroll
@@ -1398,15 +1495,20 @@ __device__ __forceinline__ void pair_force_md(const Active<D>& P, const CandData
     const float num = cd.K0 - (2.0f * rd + dd);          // r_c^2 - |r|^2
     float4 m = *cmd;
     if (!(num > 0.f)) {
+        // out of contact: no tangential state
         if (m.x != 0.f || m.y != 0.f || m.z != 0.f) *cmd = make_float4(0.f, 0.f, 0.f, m.w);
+        if (c.microslip) {
+            cms[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+            cms[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         return;
     }
     float r2 = 0.f;
 #pragma unroll
     for (int a = 0; a < D; a++) r2 += r[a] * r[a];
-    const float dist = sqrtf(r2);
-    const float delta = num / (cd.rc + dist);            // r_c - |r|
-    const float inv = 1.0f / dist;
+    const float inv = rsq_fast(r2);                      // 1 / |r|
+    const float dist = r2 * inv;
+    const float delta = num * rcp_fast(cd.rc + dist);    // r_c - |r|
     float n[3], as[3], at[3], ws[3], wt[3], vrel[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -1418,10 +1520,20 @@ __device__ __forceinline__ void pair_force_md(const Active<D>& P, const CandData
     cross3(ow, at, wt);
 #pragma unroll
     for (int a = 0; a < 3; a++) vrel[a] = (((a < D ? P.u[a] : 0.f) - ou[a]) + ws[a]) - wt[a];
-    const float Fn = cd.gam * delta * sqrtf(delta);
-    float T[3] = {m.x, m.y, m.z};
-    mindlin_update(c, n, vrel, Fn, m.w * sqrtf(delta), T);
+    const float sd = sqrt_fast(delta);
+    const float Fn = cd.gam * delta * sd;
+    float T[TSN] = {m.x, m.y, m.z, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (c.microslip) {
+        const float4 s0 = cms[0], s1 = cms[1];
+        T[3] = s0.x; T[4] = s0.y; T[5] = s0.z; T[9] = s0.w;
+        T[6] = s1.x; T[7] = s1.y; T[8] = s1.z;
+    }
+    tangential_update(c, n, vrel, Fn, m.w * sd, T);
     *cmd = make_float4(T[0], T[1], T[2], m.w);
+    if (c.microslip) {
+        cms[0] = make_float4(T[3], T[4], T[5], T[9]);
+        cms[1] = make_float4(T[6], T[7], T[8], 0.f);
+    }
     float t[3];
     cross3(as, T, t);
 #pragma unroll
@@ -1431,11 +1543,38 @@ __device__ __forceinline__ void pair_force_md(const Active<D>& P, const CandData
     }
 }
 
+// Candidate k of a particle: the first n1 from `first`, the rest from global
+// memory.  With LDS (the small-island waves cache their first candidates in
+// LDS) the first ones are read through an LDS pointer: a select between an
+// LDS and a global pointer would turn every read into a much slower
+// generic-address one.
+template <bool LDS>
+__device__ __forceinline__ CandData cand_at(const CandData* first, int n1, const CandData* __restrict__ rest,
+                                            int k) {
+    if constexpr (LDS) {
+        using LC = const __attribute__((address_space(3))) CandData;
+        LC* f = (LC*)first;
+        const int i = k < n1 ? k : 0;
+        CandData v;
+        v.local = f[i].local;
+        v.r0[0] = f[i].r0[0];
+        v.r0[1] = f[i].r0[1];
+        v.r0[2] = f[i].r0[2];
+        v.K0 = f[i].K0;
+        v.rc = f[i].rc;
+        v.gam = f[i].gam;
+        if (k >= n1) v = rest[k];
+        return v;
+    } else {
+        return k < n1 ? first[k] : rest[k];
+    }
+}
+
 // One sub-step for particle P.  Partner states are read through arrays
 // (sdx, su, and with MD the spins sw) of stride `stride` indexed by the
 // candidate's local index; the first nfirst candidates come from `first`
 // (an LDS copy), the rest from `rest` (global).
-template <int D, bool MD>
+template <int D, bool MD, bool LDS = false>
 __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, const CandData* first, int nfirst,
                                                const CandData* __restrict__ rest, const float* sdx,
                                                const float* su, const float* sw, int stride, const MdBuf& md) {
@@ -1451,7 +1590,7 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
     CandData nx{};
     float ndx[3] = {0, 0, 0}, nu[3] = {0, 0, 0}, nw[3] = {0, 0, 0};
     auto fetch = [&](int k) {
-        nx = (k < n1) ? first[k] : rest[k];
+        nx = cand_at<LDS>(first, n1, rest, k);
 #pragma unroll
         for (int a = 0; a < D; a++) {
             ndx[a] = sdx[a * stride + nx.local];
@@ -1474,7 +1613,7 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
         }
         if (k + 1 < P.cnt) fetch(k + 1);
         if (MD) {
-            pair_force_md<D>(P, cd, md.cmd + P.off + k, odx, ou, ow, c, F, tq);
+            pair_force_md<D>(P, cd, md.cmd + P.off + k, md.cms + 2 * (P.off + k), odx, ou, ow, c, F, tq);
         } else {
             pair_force<D>(P, cd, odx, ou, c, F);
         }
@@ -1491,7 +1630,7 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
     if (MD) {
         // I dW/dt = torque (second line of Eq. demgov)
 #pragma unroll
-        for (int a = (D == 3 ? 0 : 2); a < 3; a++) P.W[a] += c.h * tq[a] / P.I;
+        for (int a = (D == 3 ? 0 : 2); a < 3; a++) P.W[a] += tq[a] * P.hI;
     }
     float v2 = 0.f;
 #pragma unroll
@@ -1500,7 +1639,7 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
         float g = 2.0f * (P.ri * P.u[a] - P.j[a]);
         P.gs[a] += g;
         P.fs[a] += F[a];
-        float incr = c.h * ((-P.Ap * g + F[a]) / P.m + P.bw[a]);
+        float incr = (-P.Ap * g + F[a]) * P.hm + P.hbw[a];
         // compensated sums keep the many tiny increments exact to FP32
         float y = incr - P.cu[a];
         float t = P.u[a] + y;
@@ -1517,7 +1656,7 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
 
 template <int D, bool MD>
 __device__ __forceinline__ void active_store(const Active<D>& P, PState& Bn, const PCfg& c, uint32_t s, int np,
-                                             float* coef, float* fc, uint32_t* flags, const MdBuf& md) {
+                                             float* srec, float* fc, uint32_t* flags, const MdBuf& md) {
     float invn = 1.0f / (float)c.n_sub;
 #pragma unroll
     for (int a = 0; a < D; a++) {
@@ -1526,7 +1665,7 @@ __device__ __forceinline__ void active_store(const Active<D>& P, PState& Bn, con
         Bn.xh[a][s] = xh;
         Bn.xl[a][s] = xl;
         Bn.u[a][s] = P.u[a];
-        coef[(long long)a * np + s] = P.Af * (P.gs[a] * invn);
+        srec[(long long)s * SRec<D>::STRIDE + SRec<D>::COEF + a] = P.Af * (P.gs[a] * invn);
         fc[(long long)a * np + s] = P.fs[a] * invn;
     }
     if (sqrtf(P.vmax2) > 0.5f * c.skin) atomicOr(flags, FLAG_SKIN);
@@ -1541,22 +1680,34 @@ __device__ __forceinline__ void active_store(const Active<D>& P, PState& Bn, con
         // the history for the next step: every contact that carries a force
         const long long base = (long long)P.id * c.hmax;
         uint32_t n = 0;
+        // (a contact is kept while any of its state is not zero; the
+        // no-slip form carries T only)
         for (int k = 0; k < P.cnt; k++) {
             const float4 m = md.cmd[P.off + k];
-            if (m.x == 0.f && m.y == 0.f && m.z == 0.f) continue;
+            float S[TSN] = {m.x, m.y, m.z, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (c.microslip) {
+                const float4 s0 = md.cms[2 * (P.off + k)], s1 = md.cms[2 * (P.off + k) + 1];
+                S[3] = s0.x; S[4] = s0.y; S[5] = s0.z; S[9] = s0.w;
+                S[6] = s1.x; S[7] = s1.y; S[8] = s1.z;
+            }
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < TSN; q++) any = any || S[q] != 0.f;
+            if (!any) continue;
             md.hkey[base + n] = md.cpid[P.off + k];
-            md.hT[3 * (base + n)] = m.x;
-            md.hT[3 * (base + n) + 1] = m.y;
-            md.hT[3 * (base + n) + 2] = m.z;
+#pragma unroll
+            for (int q = 0; q < TSN; q++) md.hT[TSN * (base + n) + q] = S[q];
             n++;
         }
 #pragma unroll
         for (int a = 0; a < D; a++) {
-            if (P.wT[a][0] == 0.f && P.wT[a][1] == 0.f && P.wT[a][2] == 0.f) continue;
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < TSN; q++) any = any || P.wT[a][q] != 0.f;
+            if (!any) continue;
             md.hkey[base + n] = -1 - (2 * a + (int)((P.wside >> a) & 1u));
-            md.hT[3 * (base + n)] = P.wT[a][0];
-            md.hT[3 * (base + n) + 1] = P.wT[a][1];
-            md.hT[3 * (base + n) + 2] = P.wT[a][2];
+#pragma unroll
+            for (int q = 0; q < TSN; q++) md.hT[TSN * (base + n) + q] = P.wT[a][q];
             n++;
         }
         md.hcnt[P.id] = n;
@@ -1569,7 +1720,7 @@ constexpr int CAND_LDS = 8;   // candidates per lane cached in LDS
 // contact: along a contact-free stretch U^{k+i} is a convex combination of
 // U^k and U_eq, so every particle moves at most V = max(|U^k|, |U_eq|) per
 // unit time, and a gap g closes by at most (V_p + V_q) i h after i sub-steps.
-template <int D>
+template <int D, bool LDS = false>
 __device__ __forceinline__ int free_allowance(const Active<D>& P, const PCfg& c, const CandData* first, int nfirst,
                                               const CandData* __restrict__ rest, const float* sdx, const float* su,
                                               const float* sveq, int stride, int remaining) {
@@ -1581,20 +1732,22 @@ __device__ __forceinline__ int free_allowance(const Active<D>& P, const PCfg& c,
         float ut = P.u[a] - P.cu[a];
         u2 += ut * ut;
     }
-    const float V = fmaxf(sqrtf(u2), P.veq) * (1.0f + 1e-5f) + 1e-30f;
+    const float V = fmaxf(sqrt_fast(u2), P.veq) * (1.0f + 1e-5f) + 1e-30f;
     float allow = (float)remaining;
     const float rc = 0.5f * P.d;
     if (P.wall) {
+        // (the bounds below carry a 1e-5 margin, far above the reciprocal's rounding)
+        const float iv = rcp_fast(V * c.h) * (1.0f - 1e-5f);
 #pragma unroll
         for (int a = 0; a < D; a++) {
             float glo = P.dx[a] - ((rc - P.xh[a]) - P.xl[a]);
             float ghi = -(((rc - ((float)c.n[a] - P.xh[a])) + P.xl[a]) + P.dx[a]);
-            allow = fminf(allow, fminf(glo, ghi) / (V * c.h));
+            allow = fminf(allow, fminf(glo, ghi) * iv);
         }
     }
     const int n1 = min(P.cnt, nfirst);
     for (int k = 0; k < P.cnt; k++) {
-        CandData cd = (k < n1) ? first[k] : rest[k];
+        CandData cd = cand_at<LDS>(first, n1, rest, k);
         float rd = 0.f, dd = 0.f, r2 = 0.f, ou2 = 0.f;
 #pragma unroll
         for (int a = 0; a < D; a++) {
@@ -1607,9 +1760,9 @@ __device__ __forceinline__ int free_allowance(const Active<D>& P, const PCfg& c,
             ou2 += uo * uo;
         }
         float num = cd.K0 - (2.0f * rd + dd);             // r_c^2 - |r|^2
-        float gap = -num / (cd.rc + sqrtf(r2));          // |r| - r_c
-        float Vt = fmaxf(sqrtf(ou2), sveq[cd.local]) * (1.0f + 1e-5f);
-        allow = fminf(allow, (gap * (1.0f - 1e-5f)) / ((V + Vt) * c.h));
+        float gap = -num * rcp_fast(cd.rc + sqrt_fast(r2));   // |r| - r_c
+        float Vt = fmaxf(sqrt_fast(ou2), sveq[cd.local]) * (1.0f + 1e-5f);
+        allow = fminf(allow, (gap * (1.0f - 2e-5f)) * rcp_fast((V + Vt) * c.h));
     }
     if (!(allow > 0.f)) return 0;
     return allow >= (float)remaining ? remaining : (int)allow;
@@ -1624,10 +1777,16 @@ __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m, 
         // no contact along the stretch: every tangential force lapses, the
         // spin is unchanged
 #pragma unroll
-        for (int a = 0; a < 3; a++) P.wT[a][0] = P.wT[a][1] = P.wT[a][2] = 0.f;
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int q = 0; q < TSN; q++) P.wT[a][q] = 0.f;
         for (int k = 0; k < P.cnt; k++) {
             const float4 q = md.cmd[P.off + k];
             if (q.x != 0.f || q.y != 0.f || q.z != 0.f) md.cmd[P.off + k] = make_float4(0.f, 0.f, 0.f, q.w);
+            if (c.microslip) {
+                md.cms[2 * (P.off + k)] = make_float4(0.f, 0.f, 0.f, 0.f);
+                md.cms[2 * (P.off + k) + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
     }
     if (P.fixed) {
@@ -1637,8 +1796,14 @@ __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m, 
     }
     const float mm = (float)m;
     float qm, omq;
-    drag_power(P.hc, m, qm, omq);
-    const float S = omq / P.hc;
+    if (P.hc < 1.0f) {
+        const float l = mm * P.lq;                   // m log(1 - hc)
+        qm = expf(l);
+        omq = -expm1f(l);
+    } else {
+        drag_power(P.hc, m, qm, omq);
+    }
+    const float S = omq * P.ihc;
     const float q = 1.0f - P.hc;
     float v2 = 0.f;
 #pragma unroll
@@ -1674,7 +1839,7 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
                                                      const uint32_t* __restrict__ isize,
                                                      const CandData* __restrict__ cdata,
                                                      const float* __restrict__ drho_i, const float* __restrict__ j_i,
-                                                     float* __restrict__ coef, float* __restrict__ fc,
+                                                     float* __restrict__ srec, float* __restrict__ fc,
                                                      uint32_t* __restrict__ flags,
                                                      const uint32_t* __restrict__ counters, MdBuf md) {
     __shared__ float sdx[2][3 * WAVE];
@@ -1718,51 +1883,61 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
         __syncthreads();
         const CandData* rest = cdata + (valid ? P.off : 0);
         int k = 0, cur = 0;
-        // After a check that finds no stretch to jump, the island waits 1, 2,
-        // 4, .. 32 sub-steps before it checks again (a pair in lasting
-        // contact would fail every check); a jump resets the wait.  Every
-        // member of an island takes the same decisions (they share k and
-        // the island minimum), and plain sub-steps are always valid.
-        int wait = 0, backoff = 1;
-        while (__any(valid && k < c.n_sub)) {
+        // An island checks for a contact-free stretch to jump over on the
+        // trips (iterations of this loop, counted from 0 for every island)
+        // that are multiples of its back-off b: 1 after a jump, doubled by
+        // every check that finds none, up to 64 (a pair in lasting contact
+        // fails every check).  The check trips of all islands in a wave thus
+        // coincide, and the trips in between cost no check at all.  Every
+        // member of an island takes the same decisions (they share k, b and
+        // the island minimum), an island's decisions depend on its own state
+        // and the trip count only, and plain sub-steps are always valid.
+        // A wave whose members have no partner (islands of one particle in
+        // wall contact) exchanges nothing.
+        int backoff = 1;
+        const bool xchg = __any(valid && P.cnt > 0);        // some member has a partner
+        for (int trip = 0; __any(valid && k < c.n_sub); trip++) {
             const bool more = valid && k < c.n_sub;
-            const bool check = more && wait == 0;
-            int allow = 0;
-            if (check)
-                allow = free_allowance<D>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur], sveq, WAVE,
-                                          c.n_sub - k);
-            sallow[lane] = allow;
-            __syncthreads();
-            int m = allow;
-            if (check)
-                for (int i = 0; i < isz; i++) m = min(m, sallow[ibase + i]);
+            const bool check = more && (trip & (backoff - 1)) == 0;
+            int m = 0;
+            if (__any(check)) {
+                int allow = 0;
+                if (check)
+                    allow = free_allowance<D, true>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur],
+                                                    sveq, WAVE, c.n_sub - k);
+                m = allow;
+                if (xchg) {
+                    sallow[lane] = allow;
+                    __syncthreads();
+                    if (check)
+                        for (int i = 0; i < isz; i++) m = min(m, sallow[ibase + i]);
+                    __syncthreads();
+                }
+            }
             if (more) {
                 if (m >= 2) {
                     active_jump<D, MD>(P, c, m, md);
                     k += m;
                     backoff = 1;
                 } else {
-                    active_substep<D, MD>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur],
-                                          MD ? sw[cur] : nullptr, WAVE, md);
+                    active_substep<D, MD, true>(P, c, scd + lane * CAND_LDS, nfirst, rest, sdx[cur], su[cur],
+                                                MD ? sw[cur] : nullptr, WAVE, md);
                     k += 1;
-                    if (check) {
-                        wait = backoff;
-                        backoff = min(2 * backoff, 32);
-                    } else {
-                        wait--;
-                    }
+                    if (check) backoff = min(2 * backoff, 64);
                 }
             }
+            if (xchg) {
 #pragma unroll
-            for (int ax = 0; ax < 3; ax++) {
-                sdx[cur ^ 1][ax * WAVE + lane] = valid ? P.dx[ax] : 0.f;
-                su[cur ^ 1][ax * WAVE + lane] = valid ? P.u[ax] : 0.f;
-                if (MD) sw[cur ^ 1][ax * WAVE + lane] = valid ? P.W[ax] : 0.f;
+                for (int ax = 0; ax < 3; ax++) {
+                    sdx[cur ^ 1][ax * WAVE + lane] = valid ? P.dx[ax] : 0.f;
+                    su[cur ^ 1][ax * WAVE + lane] = valid ? P.u[ax] : 0.f;
+                    if (MD) sw[cur ^ 1][ax * WAVE + lane] = valid ? P.W[ax] : 0.f;
+                }
+                __syncthreads();
+                cur ^= 1;
             }
-            __syncthreads();
-            cur ^= 1;
         }
-        if (valid) active_store<D, MD>(P, Bn, c, s, np, coef, fc, flags, md);
+        if (valid) active_store<D, MD>(P, Bn, c, s, np, srec, fc, flags, md);
         __syncthreads();
     }
 }
@@ -1781,14 +1956,14 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
                                                     const unsigned long long* __restrict__ prefix,
                                                     const CandData* __restrict__ cdata,
                                                     const float* __restrict__ drho_i, const float* __restrict__ j_i,
-                                                    float* __restrict__ coef, float* __restrict__ fc,
+                                                    float* __restrict__ srec, float* __restrict__ fc,
                                                     float* gdx, float* gu, long long cap,
                                                     uint32_t* __restrict__ flags,
                                                     const uint32_t* __restrict__ counters, MdBuf md) {
-    // MD scratch: spin [2][3][cap], wall tangential forces [9][cap], wall sides [cap]
+    // MD scratch: spin [2][3][cap], wall tangential states [3 TSN][cap], wall sides [cap]
     float* gw = md.gmd;
     float* gwt = md.gmd + 6 * cap;
-    uint32_t* gside = (uint32_t*)(md.gmd + 15 * cap);
+    uint32_t* gside = (uint32_t*)(md.gmd + (6 + 3 * TSN) * cap);
     const uint32_t nbig = counters[CNT_BIG];
     for (uint32_t ib = blockIdx.x; ib < nbig; ib += gridDim.x) {
         uint32_t base = bigoff[ib];
@@ -1828,7 +2003,7 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
 #pragma unroll
                         for (int ax = 0; ax < 3; ax++)
 #pragma unroll
-                            for (int b = 0; b < 3; b++) P.wT[ax][b] = gwt[(3 * ax + b) * cap + a];
+                            for (int b = 0; b < TSN; b++) P.wT[ax][b] = gwt[(TSN * ax + b) * cap + a];
                         P.wside = gside[a];
                     }
                 }
@@ -1850,7 +2025,7 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
                     for (int ax = 0; ax < 3; ax++) {
                         gw[((cur ^ 1) * 3 + ax) * cap + a] = P.W[ax];
 #pragma unroll
-                        for (int b = 0; b < 3; b++) gwt[(3 * ax + b) * cap + a] = P.wT[ax][b];
+                        for (int b = 0; b < TSN; b++) gwt[(TSN * ax + b) * cap + a] = P.wT[ax][b];
                     }
                     gside[a] = P.wside;
                 }
@@ -1864,7 +2039,7 @@ __global__ __launch_bounds__(256) void k_island_big(PState A, PState Bn, int np,
                     aux[(3 * 3 + ax) * cap + a] = P.fs[ax];
                 }
                 aux[12 * cap + a] = P.vmax2;
-                if (k == c.n_sub - 1) active_store<D, MD>(P, Bn, c, s, np, coef, fc, flags, md);
+                if (k == c.n_sub - 1) active_store<D, MD>(P, Bn, c, s, np, srec, fc, flags, md);
             }
             __syncthreads();
         }
@@ -1892,23 +2067,30 @@ template <int D> struct CsrTile;
 template <> struct CsrTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4, MAXP = 256; };
 template <> struct CsrTile<2> { static constexpr int TX = 32, TY = 16, TZ = 1, MAXP = 384; };
 
-// C components are spread: C = D for the force field; the adjoint spreads
-// C = D + 1 (density and momentum adjoints) with the same kernel.
-template <int D, int C = D>
+// C components are spread: REC, C = D: the force field, with the
+// coefficients in the spreading records; the adjoint spreads C = D + 1
+// components (density and momentum adjoints) from the planes coef[a np + s]
+// with the same kernel.  Each staged particle is its record (and the
+// adjoint's planes after it), copied as whole float4s.
+template <int D, int C, bool REC>
 __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32_t* __restrict__ start,
-                                                    const float* __restrict__ wphi, const short4* __restrict__ wbase,
-                                                    const float* __restrict__ coef, int np, float* __restrict__ F,
-                                                    int ntx, int nty) {
+                                                    const float* __restrict__ srec, const float* __restrict__ coef,
+                                                    int np, float* __restrict__ F, int ntx, int nty) {
     using T = CsrTile<D>;
+    using RS = SRec<D>;
     constexpr int TX = T::TX, TY = T::TY, TZ = T::TZ;
     constexpr int HX = TX + 3, HY = TY + 3, HZ = (D == 3) ? TZ + 3 : 1;
     constexpr int NR = HY * HZ;                  // halo rows of cells
-    constexpr int PW = 4 * D + C;                // staged floats per particle
+    // staged floats per particle: the record (and the adjoint's planes), to
+    // an odd stride so that lanes reading different particles hit different
+    // LDS banks
+    constexpr int PW = (REC ? RS::STRIDE : RS::STRIDE + C) | 1;
+    constexpr int CO = REC ? RS::COEF : RS::STRIDE;                    // the coefficients in a staged particle
     constexpr int MAXP = T::MAXP;
+    static_assert(!REC || C == D, "records carry D coefficients");
     __shared__ uint32_t cs[NR * (HX + 1)];       // per row: LDS index of each cell's first particle, then the end
     __shared__ uint32_t rowbase[NR + 1], rowg0[NR];
     __shared__ float sp[MAXP * PW];
-    __shared__ short sb[MAXP];                   // x index of each staged particle's first stencil node (short: 8 workgroups per CU fit the LDS in 3D)
     __shared__ uint8_t rowof[MAXP];              // halo row of each staged particle
     __shared__ uint32_t scan4[4];
     static_assert(NR <= 255, "halo rows must fit the row table");
@@ -1972,11 +2154,19 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
         for (uint32_t k = t; k < total; k += 256) {
             const int r = rowof[k];
             const uint32_t gsl = rowg0[r] + (k - rowbase[r]);
+            const float4* rec = (const float4*)(srec + (long long)gsl * RS::STRIDE);
 #pragma unroll
-            for (int q = 0; q < 4 * D; q++) sp[k * PW + q] = wphi[(long long)gsl * (4 * D) + q];
+            for (int i = 0; i < RS::STRIDE / 4; i++) {
+                const float4 v = rec[i];
+                sp[k * PW + 4 * i] = v.x;
+                sp[k * PW + 4 * i + 1] = v.y;
+                sp[k * PW + 4 * i + 2] = v.z;
+                sp[k * PW + 4 * i + 3] = v.w;
+            }
+            if (!REC) {
 #pragma unroll
-            for (int a = 0; a < C; a++) sp[k * PW + 4 * D + a] = coef[(long long)a * np + gsl];
-            sb[k] = wbase[gsl].x;
+                for (int a = 0; a < C; a++) sp[k * PW + CO + a] = coef[(long long)a * np + gsl];
+            }
         }
     }
     __syncthreads();
@@ -2004,9 +2194,9 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
                 for (int i = 0; i < NRW; i++) {
                     for (uint32_t k = pr[i] & 0xffffu; k < (pr[i] >> 16); k++) {
                         const float* q = sp + k * PW;
-                        const float W = q[x - sb[k]] * q[4 + (i & 3)];
+                        const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + (i & 3)];
 #pragma unroll
-                        for (int a = 0; a < C; a++) acc[a] += W * q[4 * D + a];
+                        for (int a = 0; a < C; a++) acc[a] += W * q[CO + a];
                     }
                 }
             } else if (staged) {
@@ -2032,9 +2222,9 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
                         e = cs[r * (HX + 1) + lx + 4];
                     }
                     const float* q = sp + k * PW;
-                    const float W = q[x - sb[k]] * q[4 + ky] * (D == 3 ? q[8 + kz] : 1.f);
+                    const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + ky] * (D == 3 ? q[8 + kz] : 1.f);
 #pragma unroll
-                    for (int a = 0; a < C; a++) acc[a] += W * q[4 * D + a];
+                    for (int a = 0; a < C; a++) acc[a] += W * q[CO + a];
                     k++;
                 }
             } else {
@@ -2046,10 +2236,12 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
                     for (uint32_t k = k0; k < k1; k++) {
                         // particle k of halo row r sits at sorted slot rowg0[r] + (k - rowbase[r])
                         const uint32_t gsl = rowg0[r] + (k - rowbase[r]);
-                        const float* q = wphi + (long long)gsl * (4 * D);
-                        const float W = q[x - wbase[gsl].x] * q[4 + ky] * (D == 3 ? q[8 % (4 * D) + kz] : 1.f);
+                        const float* q = srec + (long long)gsl * RS::STRIDE;
+                        const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + ky] *
+                                        (D == 3 ? q[8 % (4 * D) + kz] : 1.f);
 #pragma unroll
-                        for (int a = 0; a < C; a++) acc[a] += W * coef[(long long)a * np + gsl];
+                        for (int a = 0; a < C; a++)
+                            acc[a] += W * (REC ? q[CO + a] : coef[(long long)a * np + gsl]);
                     }
                 }
             }
@@ -2060,16 +2252,24 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     }
 }
 
-// Spread C per-particle components (coef[a * np + s], sorted order) with the
-// weights wphi of the same slots onto C node fields (L = 0 only).
+// Spread C per-particle components with the weights of the spreading records
+// of the same slots onto C node fields (L = 0 only): the records' own
+// coefficients (coef == nullptr, C = D), or the planes coef[a * np + s].
 template <int D, int C>
 void spread_fields(const PBuf& b, int np, const PCfg& c, const Grid& g, const float* coef, float* out,
                    hipStream_t s) {
     using T = CsrTile<D>;
     int ntx = (g.n[0] + T::TX - 1) / T::TX, nty = (g.n[1] + T::TY - 1) / T::TY;
     int ntz = (D == 3) ? (g.n[2] + T::TZ - 1) / T::TZ : 1;
-    hipLaunchKernelGGL((k_spread_csr<D, C>), dim3((unsigned)((long long)ntx * nty * ntz)), dim3(256), 0, s, g, c,
-                       b.start, b.wphi, b.wbase, coef, np, out, ntx, nty);
+    const dim3 grid((unsigned)((long long)ntx * nty * ntz));
+    if (coef == nullptr) {
+        if constexpr (C == D)
+            hipLaunchKernelGGL((k_spread_csr<D, C, true>), grid, dim3(256), 0, s, g, c, b.start, b.srec, nullptr, np,
+                               out, ntx, nty);
+    } else {
+        hipLaunchKernelGGL((k_spread_csr<D, C, false>), grid, dim3(256), 0, s, g, c, b.start, b.srec, coef, np, out,
+                           ntx, nty);
+    }
 }
 
 void particles_spread_adjoint(int D, PBuf& b, int np, const PCfg& c, const Grid& g, const float* coef, float* out,
@@ -2090,8 +2290,8 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 
 template <int D>
 __global__ __launch_bounds__(256) void k_spread(Grid g, PCfg c, const uint32_t* __restrict__ start,
-                                                const short4* __restrict__ wbase, const float* __restrict__ wphi,
-                                                const float* __restrict__ coef, int np, float* __restrict__ F,
+                                                const short4* __restrict__ wbase, const float* __restrict__ srec,
+                                                int np, float* __restrict__ F,
                                                 int nbx, int nby, int nbz) {
     using B = SpreadBlock<D>;
     const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
@@ -2117,9 +2317,9 @@ __global__ __launch_bounds__(256) void k_spread(Grid g, PCfg c, const uint32_t* 
             for (uint32_t s = s0; s < s1; s++) {
                 const short4 b = wbase[s];
                 const int kx = x - b.x, ky = y - b.y, kz = (D == 3) ? z - b.z : 0;
-                const float* ph = wphi + (long long)s * (4 * D);
-                const float cx = coef[s], cy = coef[(long long)np + s];
-                const float cz = (D == 3) ? coef[2LL * np + s] : 0.f;
+                const float* ph = srec + (long long)s * SRec<D>::STRIDE;
+                const float cx = ph[SRec<D>::COEF], cy = ph[SRec<D>::COEF + 1];
+                const float cz = (D == 3) ? ph[SRec<D>::COEF + 2 - (D == 3 ? 0 : 1)] : 0.f;
                 const float p0 = ph[0], p1 = ph[1], p2 = ph[2], p3 = ph[3];
                 const float q0 = ph[4], q1 = ph[5], q2 = ph[6], q3 = ph[7];
                 float r0 = 1.f, r1 = 0.f, r2 = 0.f, r3 = 0.f;
@@ -2185,7 +2385,7 @@ __global__ void k_particle_final(const double* __restrict__ part, int nb, double
 
 // state in sorted order -> staging arrays in id order
 template <int D>
-__global__ __launch_bounds__(256) void k_unpermute(PState A, int np, const float* __restrict__ coef,
+__global__ __launch_bounds__(256) void k_unpermute(PState A, int np, const float* __restrict__ srec,
                                                    const float* __restrict__ fc, float* __restrict__ out) {
     // out layout: [xh D][xl D][u D][fh D][fc D] x np
     int s = blockIdx.x * 256 + threadIdx.x;
@@ -2196,7 +2396,8 @@ __global__ __launch_bounds__(256) void k_unpermute(PState A, int np, const float
         out[(long long)(0 * D + a) * np + id] = A.xh[a][s];
         out[(long long)(1 * D + a) * np + id] = A.xl[a][s];
         out[(long long)(2 * D + a) * np + id] = A.u[a][s];
-        out[(long long)(3 * D + a) * np + id] = coef ? -coef[(long long)a * np + s] : 0.f;
+        out[(long long)(3 * D + a) * np + id] =
+            srec ? -srec[(long long)s * SRec<D>::STRIDE + SRec<D>::COEF + a] : 0.f;
         out[(long long)(4 * D + a) * np + id] = fc ? fc[(long long)a * np + s] : 0.f;
     }
 }
@@ -2282,10 +2483,10 @@ static void interp_tile_2d(PBuf& b, int np, const Grid& g, const PCfg& c, Src sr
     const dim3 grid((unsigned)((long long)ntx * nty));
     if (c.lagrange)
         hipLaunchKernelGGL((k_interp_tile<2, Src, true>), grid, dim3(256), 0, s, b.A, np, g, c, b.start, src,
-                           b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+                           b.drho_i, b.j_i, b.wbase, b.srec, ntx, nty);
     else
         hipLaunchKernelGGL((k_interp_tile<2, Src, false>), grid, dim3(256), 0, s, b.A, np, g, c, b.start, src,
-                           b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+                           b.drho_i, b.j_i, b.wbase, b.srec, ntx, nty);
 }
 
 // D2Q9 with bins of edge 1 or 2: moments straight from the populations f
@@ -2310,10 +2511,10 @@ void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, cons
             const dim3 grid((unsigned)((long long)ntx * nty * ntz));
             if (c.lagrange)
                 hipLaunchKernelGGL((k_interp_tile<3, MomSrc, true>), grid, dim3(256), 0, s, b.A, np, g, c, b.start,
-                                   MomSrc{mom}, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+                                   MomSrc{mom}, b.drho_i, b.j_i, b.wbase, b.srec, ntx, nty);
             else
                 hipLaunchKernelGGL((k_interp_tile<3, MomSrc, false>), grid, dim3(256), 0, s, b.A, np, g, c, b.start,
-                                   MomSrc{mom}, b.drho_i, b.j_i, b.wbase, b.wphi, ntx, nty);
+                                   MomSrc{mom}, b.drho_i, b.j_i, b.wbase, b.srec, ntx, nty);
         } else {
             interp_tile_2d(b, np, g, c, MomSrc{mom}, s);
         }
@@ -2322,22 +2523,22 @@ void particles_interp(int D, PBuf& b, int np, const Grid& g, const PCfg& c, cons
     long long threads = (long long)np * (D == 3 ? 16 : 4);
     const dim3 grid(nb256(threads));
     if (D == 3 && c.lagrange)
-        hipLaunchKernelGGL((k_interp<3, true>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+        hipLaunchKernelGGL((k_interp<3, true>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.srec);
     else if (D == 3)
-        hipLaunchKernelGGL((k_interp<3, false>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+        hipLaunchKernelGGL((k_interp<3, false>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.srec);
     else if (c.lagrange)
-        hipLaunchKernelGGL((k_interp<2, true>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+        hipLaunchKernelGGL((k_interp<2, true>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.srec);
     else
-        hipLaunchKernelGGL((k_interp<2, false>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.wphi);
+        hipLaunchKernelGGL((k_interp<2, false>), grid, dim3(256), 0, s, b.A, np, g, mom, b.drho_i, b.j_i, b.wbase, b.srec);
 }
 
 template <int D>
 static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s) {
     // the island chain works on the active particles only (grid-stride)
     const unsigned grid_act = std::min<unsigned>(nb256(np), 128u);
-    const MdBuf md{b.cmd, b.cpid, b.hcnt, b.hkey, b.hT, b.gmd};
+    const MdBuf md{b.cmd, b.cpid, b.hcnt, b.hkey, b.hT, b.gmd, b.cms};
     hipLaunchKernelGGL(k_classify<D>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.Bn, np, c, b.start, b.pos4,
-                       b.keys_sorted, b.drho_i, b.j_i, b.coef, b.fc, b.actcc, b.bsum64, b.counters, b.flags,
+                       b.keys_sorted, b.drho_i, b.j_i, b.srec, b.fc, b.actcc, b.bsum64, b.counters, b.flags,
                        b.hcnt);
     // block offsets and the totals (candidates, active) -> counters[0..1]
     if ((long long)nb256(np) <= RAW_MAX_BLOCKS) {
@@ -2367,20 +2568,20 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
                            b.aidx, b.loc, b.cdata, md, b.counters);
     }
     const dim3 gsmall(std::max<unsigned>(grid_act * 4, 256u));
-    if (c.contact == PIBM_CONTACT_HERTZ_MINDLIN) {
+    if (c.contact >= PIBM_CONTACT_HERTZ_MINDLIN) {
         hipLaunchKernelGGL((k_island_small<D, true>), gsmall, dim3(64), 0, s, b.A, b.Bn, np, c, b.lanemember, b.alist,
-                           b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.coef, b.fc, b.flags,
+                           b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.srec, b.fc, b.flags,
                            b.counters, md);
         hipLaunchKernelGGL((k_island_big<D, true>), dim3(256), dim3(256), 0, s, b.A, b.Bn, np, c, b.bigmember,
                            b.bigoff, b.bigroot, b.isize, b.alist, b.ccount, b.prefix, b.cdata, b.drho_i, b.j_i,
-                           b.coef, b.fc, b.gdx, b.gu, (long long)np, b.flags, b.counters, md);
+                           b.srec, b.fc, b.gdx, b.gu, (long long)np, b.flags, b.counters, md);
     } else {
         hipLaunchKernelGGL((k_island_small<D, false>), gsmall, dim3(64), 0, s, b.A, b.Bn, np, c, b.lanemember, b.alist,
-                           b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.coef, b.fc, b.flags,
+                           b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.srec, b.fc, b.flags,
                            b.counters, md);
         hipLaunchKernelGGL((k_island_big<D, false>), dim3(256), dim3(256), 0, s, b.A, b.Bn, np, c, b.bigmember,
                            b.bigoff, b.bigroot, b.isize, b.alist, b.ccount, b.prefix, b.cdata, b.drho_i, b.j_i,
-                           b.coef, b.fc, b.gdx, b.gu, (long long)np, b.flags, b.counters, md);
+                           b.srec, b.fc, b.gdx, b.gu, (long long)np, b.flags, b.counters, md);
     }
 }
 
@@ -2398,8 +2599,8 @@ void particles_dem(int D, PBuf& b, int np, const PCfg& c, bool one_group, hipStr
 
 void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, float* F, hipStream_t s) {
     if (c.L == 0) {
-        if (D == 3) spread_fields<3, 3>(b, np, c, g, b.coef, F, s);
-        else spread_fields<2, 2>(b, np, c, g, b.coef, F, s);
+        if (D == 3) spread_fields<3, 3>(b, np, c, g, nullptr, F, s);
+        else spread_fields<2, 2>(b, np, c, g, nullptr, F, s);
         return;
     }
 
@@ -2408,13 +2609,13 @@ void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, floa
         int nbx = (g.n[0] + B::BX - 1) / B::BX, nby = (g.n[1] + B::BY - 1) / B::BY, nbz = (g.n[2] + B::BZ - 1) / B::BZ;
         long long nblk = (long long)nbx * nby * nbz;
         hipLaunchKernelGGL(k_spread<3>, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, s, g, c, b.start, b.wbase,
-                           b.wphi, b.coef, np, F, nbx, nby, nbz);
+                           b.srec, np, F, nbx, nby, nbz);
     } else {
         using B = SpreadBlock<2>;
         int nbx = (g.n[0] + B::BX - 1) / B::BX, nby = (g.n[1] + B::BY - 1) / B::BY;
         long long nblk = (long long)nbx * nby;
         hipLaunchKernelGGL(k_spread<2>, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, s, g, c, b.start, b.wbase,
-                           b.wphi, b.coef, np, F, nbx, nby, 1);
+                           b.srec, np, F, nbx, nby, 1);
     }
 }
 
@@ -2441,7 +2642,7 @@ void particles_set_state(int D, PBuf& b, int np, const Grid& g, const float* xh,
 }
 
 void particles_unpermute(int D, PBuf& b, int np, bool have_forces, float* out, hipStream_t s) {
-    const float* coef = have_forces ? b.coef : nullptr;
+    const float* coef = have_forces ? b.srec : nullptr;
     const float* fc = have_forces ? b.fc : nullptr;
     if (D == 3) hipLaunchKernelGGL(k_unpermute<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, coef, fc, out);
     else hipLaunchKernelGGL(k_unpermute<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, coef, fc, out);

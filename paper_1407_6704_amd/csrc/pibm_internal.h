@@ -216,6 +216,15 @@ __device__ __forceinline__ void drag_power(float hc, int m, float& qm, float& om
     }
 }
 
+// Hardware reciprocal, square root and reciprocal square root (about one
+// unit in the last place).  The DEM sub-step runs thousands of times per
+// lattice step as one wave's serial chain of instructions, where a correctly
+// rounded division or square root expands into a dozen instructions; these
+// are single instructions.  Their extra rounding is of the order of FP32's.
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsq_fast(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // Particle mass: sphere (3D) or disk of unit depth (2D).
 __device__ __forceinline__ float particle_mass(int D, float d, float rp) {
     return D == 3 ? rp * (PI_F / 6.0f) * d * d * d : rp * 0.25f * PI_F * d * d;
@@ -243,6 +252,7 @@ struct PCfg {
     float hk;           // Hertz: (4/3) E*, so that F_n = hk sqrt(R*) delta^(3/2)
     float kt8;          // Mindlin: 8 G*, so that k_t = kt8 sqrt(delta R*)
     float mu;           // Coulomb friction coefficient
+    int microslip;      // 1: the Mindlin-Deresiewicz micro-slip factors (contact model 5)
     int hmax;           // tangential-history entries per particle: max candidates + D walls
 };
 
@@ -255,6 +265,13 @@ struct CandData {
     float gam;      // dashpot coefficient 2 zeta sqrt(kn m_eff)
 };
 
+// Tangential state of one Hertz-Mindlin contact, TSN floats: the force T on
+// the particle (3), then for the micro-slip form the loading direction (3),
+// k (0 loading, 1 unloading, 2 reloading), T*, T** and the normal force of
+// the previous sub-step.  The history slots and the big-island scratch keep
+// it in this order.
+constexpr int TSN = 10;
+
 // The Hertz-Mindlin buffers handed to the DEM kernels (all null for the
 // other contact models); see PBuf.
 struct MdBuf {
@@ -262,8 +279,22 @@ struct MdBuf {
     int* cpid;          // per candidate entry: partner id
     uint32_t* hcnt;     // per particle id: history entries
     int* hkey;          // per particle id, hmax slots: partner id, or -1 - (2 axis + side) for a wall
-    float* hT;          // per slot: tangential force (3 floats)
-    float* gmd;         // big islands: spin [2][3][cap], wall forces [9][cap], wall sides [cap]
+    float* hT;          // per slot: tangential state (TSN floats)
+    float* gmd;         // big islands: spin [2][3][cap], wall states [3 TSN][cap], wall sides [cap]
+    float4* cms;        // per candidate entry, two float4: the rest of the tangential state
+                        // (loading direction, previous F_n), (k, T*, T**, 0)
+};
+
+// Spreading record of one sorted particle slot: the 4 D one-dimensional
+// delta-kernel weights of Eq. lbm11 (4 per axis), the x index of the first
+// stencil node (int bits), then the D spreading coefficients A_p gbar of the
+// forward step, padded to whole float4s.  Interpolation writes the weights
+// and the base, the DEM kernels the coefficients; spreading reads each
+// record as one contiguous run.
+template <int D> struct SRec {
+    static constexpr int STRIDE = D == 3 ? 16 : 12;   // floats per slot
+    static constexpr int BASE = 4 * D;
+    static constexpr int COEF = 4 * D + 1;
 };
 
 // Device buffers of the particle side (carved from the workspace).
@@ -273,7 +304,7 @@ struct PBuf {
     float4* pos4;                // (x, y, z) leading parts and d, sorted order
     uint32_t* scan_u32;          // scan block sums
     unsigned long long *actcc, *prefix, *bsum64;   // bsum64: per-block totals of actcc
-    float *drho_i, *j_i, *wphi, *coef, *fc;
+    float *drho_i, *j_i, *srec, *fc;     // srec: spreading records (SRec), per sorted slot
     short4* wbase;
     uint32_t *alist, *aidx, *cand, *ccount, *parent, *isize, *irank, *fill, *loc, *bigroot, *bigoff, *bigmember;
     int* lanemember;
@@ -288,6 +319,7 @@ struct PBuf {
     int* hkey;
     float* hT;
     float* gmd;
+    float4* cms;
     uint32_t* counters;
     uint32_t* flags;
     long long cand_cap, lane_cap;

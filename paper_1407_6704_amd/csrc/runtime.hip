@@ -220,11 +220,11 @@ std::string validate(const pibm_config* cfg, int64_t np) {
         if (cfg->n[a] > 30000) return "axis longer than 30000 nodes";
     if (!(cfg->tau > 0.5)) return "tau must exceed 1/2";
     if (cfg->n_sub < 1) return "n_sub must be >= 1";
-    if (cfg->contact < 0 || cfg->contact > 4) return "unknown contact model";
-    if ((cfg->contact == PIBM_CONTACT_HERTZ || cfg->contact == PIBM_CONTACT_HERTZ_MINDLIN) &&
+    if (cfg->contact < 0 || cfg->contact > 5) return "unknown contact model";
+    if ((cfg->contact == PIBM_CONTACT_HERTZ || cfg->contact >= PIBM_CONTACT_HERTZ_MINDLIN) &&
         (!(cfg->young > 0) || !(cfg->poisson >= 0) || !(cfg->poisson < 0.5)))
         return "Hertz contact needs young > 0 and 0 <= poisson < 1/2";
-    if (cfg->contact == PIBM_CONTACT_HERTZ_MINDLIN && !(cfg->friction >= 0)) return "friction must be >= 0";
+    if (cfg->contact >= PIBM_CONTACT_HERTZ_MINDLIN && !(cfg->friction >= 0)) return "friction must be >= 0";
     if (cfg->bodies != 0 && cfg->bodies != 1) return "bodies must be 0 or 1";
     if (cfg->bin_log2 < 0 || cfg->bin_log2 > 3) return "bin_log2 must be 0..3";
     if (cfg->max_candidates < 1 || cfg->max_candidates > 64) return "max_candidates must be 1..64";
@@ -250,7 +250,7 @@ size_t carve(pibm_ctx& c, char* base) {
     c.mom = cv.take<float4>(N);
     c.F = cv.take<float>((size_t)c.D * N);
     long long np = c.np;
-    const bool md = c.cfg.contact == PIBM_CONTACT_HERTZ_MINDLIN;
+    const bool md = c.cfg.contact >= PIBM_CONTACT_HERTZ_MINDLIN;
     c.stage_floats = std::max<long long>((long long)(c.D + 1) * N, 5LL * c.D * np);
     c.stage = cv.take<float>(c.stage_floats);
     c.part = cv.take<double>(8 * (std::max(lattice_totals_blocks(), particles_totals_blocks()) + 2));
@@ -286,8 +286,7 @@ size_t carve(pibm_ctx& c, char* base) {
         b.bsum64 = cv.take<unsigned long long>(np / 256 + 2);
         b.drho_i = cv.take<float>(np);
         b.j_i = cv.take<float>((size_t)c.D * np);
-        b.wphi = cv.take<float>((size_t)4 * c.D * np);
-        b.coef = cv.take<float>((size_t)c.D * np);
+        b.srec = cv.take<float>((size_t)(c.D == 3 ? SRec<3>::STRIDE : SRec<2>::STRIDE) * np);
         b.fc = cv.take<float>((size_t)c.D * np);
         b.wbase = cv.take<short4>(np);
         b.alist = cv.take<uint32_t>(np);
@@ -314,8 +313,9 @@ size_t carve(pibm_ctx& c, char* base) {
             b.cpid = cv.take<int>(b.cand_cap);
             b.hcnt = cv.take<uint32_t>(np);
             b.hkey = cv.take<int>(np * hmax);
-            b.hT = cv.take<float>(3 * np * hmax);
-            b.gmd = cv.take<float>(16 * np);
+            b.hT = cv.take<float>((long long)TSN * np * hmax);
+            b.gmd = cv.take<float>((6 + 3 * TSN + 1) * np);
+            b.cms = cv.take<float4>(2 * b.cand_cap);
         } else {
             b.cmd = nullptr;
             b.cpid = nullptr;
@@ -323,6 +323,7 @@ size_t carve(pibm_ctx& c, char* base) {
             b.hkey = nullptr;
             b.hT = nullptr;
             b.gmd = nullptr;
+            b.cms = nullptr;
         }
     }
     return cv.off + 256;
@@ -356,6 +357,7 @@ void fill_pcfg(pibm_ctx& c) {
     const double G = c.cfg.young / (2.0 * (1.0 + c.cfg.poisson));
     p.kt8 = (float)(8.0 * G / (2.0 * (1.0 - c.cfg.poisson * c.cfg.poisson)));
     p.mu = (float)c.cfg.friction;
+    p.microslip = c.cfg.contact == PIBM_CONTACT_HERTZ_MINDLIN_MICROSLIP;
     p.hmax = c.cfg.max_candidates + c.D;
     // trailing parts are at most half an ulp of the leading ones; the
     // screened distance is off by at most sqrt(D) ulp(max extent)
@@ -376,7 +378,7 @@ std::string adjoint_unsupported(const pibm_ctx& c) {
     if (c.np < 1) return "the adjoint needs at least one particle";
     if (c.cfg.n_sub != 1) return "the adjoint supports n_sub = 1 only";
     if (c.cfg.contact == PIBM_CONTACT_LSD || c.cfg.contact == PIBM_CONTACT_HERTZ ||
-        c.cfg.contact == PIBM_CONTACT_HERTZ_MINDLIN)
+        c.cfg.contact >= PIBM_CONTACT_HERTZ_MINDLIN)
         return "the adjoint supports no contact or soft contact only";
     if (c.cfg.bin_log2 != 0) return "the adjoint needs bin_log2 = 0";
     if (c.cfg.bodies) return "the adjoint supports no fixed bodies";
@@ -689,7 +691,7 @@ pibm_status pibm_set_particles_device(pibm_ctx* c, const float* x_hi, const floa
 
 pibm_status pibm_set_rotation(pibm_ctx* c, const double* w) {
     if (!c || !w) return PIBM_E_ARG;
-    if (c->cfg.contact != PIBM_CONTACT_HERTZ_MINDLIN) return fail(c, PIBM_E_CONFIG, "no rotation without Hertz-Mindlin contact");
+    if (c->cfg.contact < PIBM_CONTACT_HERTZ_MINDLIN) return fail(c, PIBM_E_CONFIG, "no rotation without Hertz-Mindlin contact");
     if (c->np == 0) return PIBM_OK;
     if (!c->particles_set || c->stepped) return fail(c, PIBM_E_STATE, "set the rotation right after the particles");
     const int nw = spin_components(c->D), np = c->np;
@@ -785,7 +787,7 @@ pibm_status pibm_read_bodies(pibm_ctx* c, int32_t n_bodies, double* f_hydro, dou
 
 pibm_status pibm_read_rotation(pibm_ctx* c, double* w) {
     if (!c || !w) return PIBM_E_ARG;
-    if (c->cfg.contact != PIBM_CONTACT_HERTZ_MINDLIN) return fail(c, PIBM_E_CONFIG, "no rotation without Hertz-Mindlin contact");
+    if (c->cfg.contact < PIBM_CONTACT_HERTZ_MINDLIN) return fail(c, PIBM_E_CONFIG, "no rotation without Hertz-Mindlin contact");
     if (c->np == 0) return PIBM_OK;
     if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
     const int nw = spin_components(c->D), np = c->np;

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pibm.h")
 ABI_VERSION = 6
 D2Q9, D3Q15, D3Q19 = 9, 15, 19
 STORE_FP32, STORE_FP16 = 0, 1
-CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3, "hertz_mindlin": 4}
+CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3, "hertz_mindlin": 4, "hertz_mindlin_microslip": 5}
 INTERP = {"delta": 0, "lagrange": 1}
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_CONFIG", 3: "E_HIP", 4: "E_STATE", 5: "E_UNSTABLE",
           6: "E_SKIN", 7: "E_CAPACITY"}

@@ -106,12 +106,13 @@ C2_D3Q15 = C2.replace(name="c2_d3q15", lattice=15, interp="lagrange")
 # c2 particles with the paper's contact law: Hertz normal and Mindlin tangential
 # forces with rotation (Table 1 Poisson ratio and friction)
 C2_HM = C2.replace(name="c2_hm", contact="hertz_mindlin")
+C2_HMS = C2.replace(name="c2_hms", contact="hertz_mindlin_microslip")
 HYBRID = C2.replace(name="hybrid", n=(128, 128, 128), n_particles=250_000, steps=200, seed=6, obstacles=True)
 C4 = Workload("c4", 9, (512, 512, 1), 0.7, 10_000, ("const", 0.5), 2.5, (0.5, 1.0),
               contact="soft", n_sub=1, steps=2000, seed=4, gap=0.5, wall_clear=3.0)
 C4_FD = C4.replace(name="c4_fd", n=(64, 64, 1), n_particles=50, seed=40)
 
-WORKLOADS = {w.name: w for w in (C0, C1, C2, C3, C3_CROP, C2_D3Q15, C2_HM, HYBRID, C4, C4_FD)}
+WORKLOADS = {w.name: w for w in (C0, C1, C2, C3, C3_CROP, C2_D3Q15, C2_HM, C2_HMS, HYBRID, C4, C4_FD)}
 
 
 def draw_diameters(rng, spec, n):

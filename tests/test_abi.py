@@ -44,7 +44,7 @@ def test_workspace_bytes_and_validation(P):
     assert lib.pibm_workspace_bytes(C.byref(fp16), 0) < lib.pibm_workspace_bytes(C.byref(fp32), 0)
     bad = [
         dict(tau=0.5), dict(tau=0.3), dict(n_sub=0), dict(lattice=27), dict(interp=2), dict(contact="hertz", young=0.0),
-        dict(contact="hertz", poisson=0.5), dict(contact=5),
+        dict(contact="hertz", poisson=0.5), dict(contact=6), dict(contact="hertz_mindlin_microslip", young=0.0),
         dict(contact="hertz_mindlin", friction=-0.1), dict(contact="hertz_mindlin", young=-1.0), dict(n=(8, 8, 2)),
         dict(bin_log2=5), dict(max_candidates=0), dict(restitution=0.0), dict(periodic=(1, 0, 0)),
     ]

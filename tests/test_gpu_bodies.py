@@ -49,7 +49,8 @@ def _body_sums(X, fh, fcn, body, nb):
     return out
 
 
-@pytest.mark.parametrize("D,contact", [(2, "lsd"), (3, "lsd"), (3, "hertz"), (3, "hertz_mindlin")])
+@pytest.mark.parametrize("D,contact", [(2, "lsd"), (3, "lsd"), (3, "hertz"), (3, "hertz_mindlin"),
+                                       (3, "hertz_mindlin_microslip")])
 def test_fixed_bodies_match_oracle(P, orc, D, contact):
     _flush(f"fixed bodies {D}D {contact}")
     ocfg, X, U, d, rp, fixed, area = _scene(orc, D, contact)

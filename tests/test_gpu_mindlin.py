@@ -1,4 +1,5 @@
-"""GPU parity of the Hertz-Mindlin contact with particle rotation (Sec. 2.3)
+"""GPU parity of the Hertz-Mindlin contact with particle rotation (Sec. 2.3),
+in its no-slip limit and with the Mindlin-Deresiewicz micro-slip factors,
 against the FP64 oracle, through the C ABI: clusters of touching and
 approaching particles with initial spins and wall contacts, one step and
 then several more with the tangential-force history carried between steps;
@@ -86,15 +87,16 @@ def _compare(P, orc, cfg, X, U, W, d, rp, steps_list):
     return res
 
 
+@pytest.mark.parametrize("contact", ["hertz_mindlin", "hertz_mindlin_microslip"])
 @pytest.mark.parametrize("lat", [9, 19])
-def test_mindlin_contacts_match_oracle(P, orc, lat):
-    _flush(f"Hertz-Mindlin contacts {lat}")
+def test_mindlin_contacts_match_oracle(P, orc, lat, contact):
+    _flush(f"Hertz-Mindlin contacts {lat} {contact}")
     D = 2 if lat == 9 else 3
     n = (40, 30, 1) if D == 2 else (16, 14, 18)
     X, U, W, d, rp = _clusters(D, n, 41, 12 if D == 2 else 10)
     g = [0.0, 0.0, 0.0]
     g[D - 1] = -1e-5
-    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact="hertz_mindlin", young=1e3,
+    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact=contact, young=1e3,
                         poisson=0.33, friction=0.33)
     r1, r5 = _compare(P, orc, cfg, X, U, W, d, rp, [1, 4])
     assert r1["nh"] > 5 and r5["nh"] >= 4                # contacts carried between steps
@@ -103,10 +105,11 @@ def test_mindlin_contacts_match_oracle(P, orc, lat):
     assert r5["ex"] <= 1e-5 and r5["ev"] <= 1e-5 and r5["ew"] <= 1e-5 and r5["eu"] <= 1e-5
 
 
-def test_mindlin_big_island(P, orc):
+@pytest.mark.parametrize("contact", ["hertz_mindlin", "hertz_mindlin_microslip"])
+def test_mindlin_big_island(P, orc, contact):
     """A chain of 120 particles in alternating contact: one island larger
     than a wave (the workgroup-per-island path)."""
-    _flush("Hertz-Mindlin big island")
+    _flush(f"Hertz-Mindlin big island {contact}")
     k = 120
     x = [10.0]
     for i in range(1, k):
@@ -121,7 +124,7 @@ def test_mindlin_big_island(P, orc):
     W = np.zeros((3, k))
     W[2] = (1e-3 * rng.standard_normal(k)).astype(np.float32)
     cfg = P.make_config(lattice=9, n=(200, 12, 1), tau=0.8, gravity=(0, -1e-5, 0), n_sub=300,
-                        contact="hertz_mindlin", young=1.0, poisson=0.33, friction=0.33)
+                        contact=contact, young=1.0, poisson=0.33, friction=0.33)
     r1, r2 = _compare(P, orc, cfg, X, U, W, np.full(k, 0.5), np.full(k, 2.5), [1, 1])
     assert r1["sim"].diagnostics()["active"] == k
     assert r1["nh"] > 0 and r1["efc"] <= 1e-5           # the contacts acted in the first step
