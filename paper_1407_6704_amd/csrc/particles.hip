@@ -466,8 +466,8 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
     __shared__ float4 sm[NX * NY * NZ];
     __shared__ uint32_t rs[MAXR], re[MAXR], roff[MAXR + 1];
     __shared__ uint32_t scan4[4];
-    const int tile = (int)blockIdx.x;
-    const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
+    int tx, ty, tz;
+    banded_tile(ntx, nty, (int)gridDim.x / (ntx * nty), D == 3 ? 1 : 0, tx, ty, tz);
     const int B0x = tx * T.TBX, B0y = ty * T.TBY, B0z = tz * T.TBZ;
     const int t = threadIdx.x;
     if (t < T.TBY * T.TBZ) {
@@ -493,6 +493,27 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
     __syncthreads();
     const uint32_t total = roff[T.TBY * T.TBZ];
     if (total == 0) return;
+    // sorted slot of entry k: row r is the largest with roff[r] <= k
+    auto slot_of = [&](uint32_t k) {
+        int r = 0, rh = T.TBY * T.TBZ;
+        while (rh - r > 1) {
+            const int mid = (r + rh) >> 1;
+            if (roff[mid] <= k) r = mid;
+            else rh = mid;
+        }
+        return rs[r] + (k - roff[r]);
+    };
+    // the positions of the thread's first particle are loaded together with
+    // the halo (a tile holds fewer than 256 particles as a rule)
+    const uint32_t s_first = t < total ? slot_of((uint32_t)t) : 0u;
+    float xh0[3] = {0.f, 0.f, 0.f}, xl0[3] = {0.f, 0.f, 0.f};
+    if ((uint32_t)t < total) {
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            xh0[a] = A.xh[a][s_first];
+            xl0[a] = A.xl[a][s_first];
+        }
+    }
     // node box: dual cells of the tile are [B0 E - 1, (B0 + TB) E - 2], reaching nodes
     // [B0 E - 2, (B0 + TB) E]
     const int nx0 = B0x * E - 2, ny0 = B0y * E - 2, nz0 = (D == 3) ? B0z * E - 2 : 0;
@@ -518,19 +539,15 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
     }
     __syncthreads();
     for (uint32_t k = t; k < total; k += 256) {
-        // row of entry k: the largest r with roff[r] <= k
-        int r = 0, rh = T.TBY * T.TBZ;
-        while (rh - r > 1) {
-            const int mid = (r + rh) >> 1;
-            if (roff[mid] <= k) r = mid;
-            else rh = mid;
-        }
-        const uint32_t s = rs[r] + (k - roff[r]);
+        const bool first = k == (uint32_t)t;
+        const uint32_t s = first ? s_first : slot_of(k);
         int base[3] = {0, 0, 0};
         float phi[3][4], gw[3][4];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            if (a < D) axis_gather<LAG>(A.xh[a][s], A.xl[a][s], g.n[a], base[a], phi[a], gw[a]);
+            if (a < D)
+                axis_gather<LAG>(first ? xh0[a] : A.xh[a][s], first ? xl0[a] : A.xl[a][s], g.n[a], base[a], phi[a],
+                                 gw[a]);
             else {
                 phi[a][0] = gw[a][0] = 1.f;
                 phi[a][1] = phi[a][2] = phi[a][3] = gw[a][1] = gw[a][2] = gw[a][3] = 0.f;
@@ -2095,19 +2112,38 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     __shared__ uint32_t scan4[4];
     static_assert(NR <= 255, "halo rows must fit the row table");
     const int t = threadIdx.x;
-    const int tile = (int)blockIdx.x;
-    const int tx = tile % ntx, t2 = tile / ntx, ty = t2 % nty, tz = t2 / nty;
+    int tx, ty, tz;
+    banded_tile(ntx, nty, (int)gridDim.x / (ntx * nty), D == 3 ? 1 : 0, tx, ty, tz);
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int cx0 = x0 - 1, cy0 = y0 - 1, cz0 = (D == 3) ? z0 - 1 : 0;
     const int lo = max(cx0, 0), hi = min(cx0 + HX - 1, c.nb[0] - 1);
+    // every cell start of the halo in one batch of independent loads (cells
+    // left of the bins read the row's first start, right of them its end),
+    // then the row counts, their scan and the LDS offsets from LDS alone
+    constexpr int NCS = NR * (HX + 1);
+    constexpr int NIT = (NCS + 255) / 256;
+    uint32_t raw[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int i = t + it * 256;
+        const int r = i / (HX + 1), ix = i % (HX + 1);
+        const int cy = cy0 + r % HY, cz = cz0 + r / HY;
+        const bool ok = i < NCS && cy >= 0 && cy < c.nb[1] && cz >= 0 && cz < c.nb[2] && lo <= hi;
+        const int cx = min(max(cx0 + ix, lo), hi + 1);
+        const long long at = ok ? ((long long)cz * c.nb[1] + cy) * c.nb[0] + cx : 0;
+        raw[it] = start[at];
+        if (!ok) raw[it] = 0;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; it++)
+        if (t + it * 256 < NCS) cs[t + it * 256] = raw[it];
+    __syncthreads();
     uint32_t cnt_row = 0;
     if (t < NR) {
-        const int cy = cy0 + t % HY, cz = cz0 + t / HY;
         uint32_t g0 = 0, g1 = 0;
-        if (cy >= 0 && cy < c.nb[1] && cz >= 0 && cz < c.nb[2] && lo <= hi) {
-            const uint32_t row = (uint32_t)(((long long)cz * c.nb[1] + cy) * c.nb[0]);
-            g0 = start[row + lo];
-            g1 = start[row + hi + 1];
+        if (lo <= hi) {
+            g0 = cs[t * (HX + 1) + (lo - cx0)];
+            g1 = cs[t * (HX + 1) + (hi + 1 - cx0)];
         }
         rowg0[t] = g0;
         cnt_row = g1 - g0;
@@ -2132,19 +2168,15 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
         }
         return;
     }
-    for (int i = t; i < NR * (HX + 1); i += 256) {
-        const int r = i / (HX + 1), ix = i % (HX + 1);
-        const int cy = cy0 + r % HY, cz = cz0 + r / HY, cx = cx0 + ix;
-        uint32_t v = rowbase[r];
-        const bool rowok = cy >= 0 && cy < c.nb[1] && cz >= 0 && cz < c.nb[2] && lo <= hi;
-        if (rowok) {
-            if (cx > hi) v = rowbase[r + 1];
-            else if (cx > lo) {
-                const uint32_t row = (uint32_t)(((long long)cz * c.nb[1] + cy) * c.nb[0]);
-                v = rowbase[r] + (start[row + cx] - rowg0[r]);
-            }
+    // LDS index of each cell's first particle: the row's offset plus the
+    // cell's start within the row (clamped cells give the row's ends)
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int i = t + it * 256;
+        if (i < NCS) {
+            const int r = i / (HX + 1);
+            cs[i] = rowbase[r] + (raw[it] - rowg0[r]);
         }
-        cs[i] = v;
     }
     const bool staged = total <= (uint32_t)MAXP;
     if (staged) {

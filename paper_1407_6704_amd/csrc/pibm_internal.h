@@ -198,6 +198,36 @@ __device__ __forceinline__ unsigned xcd_block() {
     const unsigned x = b % NUM_XCD, i = b / NUM_XCD;
     return x * per + min(x, rem) + i;
 }
+// Tile coordinates for tile kernels whose tiles read a halo shared with
+// their neighbours.  The tile grid is cut into NUM_XCD bands along axis A
+// (one that gravity does not point along, so the particles spread evenly over
+// the bands) and each XCD walks its own band, a row of tiles at a time,
+// layer after layer: the halo a tile reads in the neighbouring rows and
+// layers was then fetched into the same L2 shortly before, and every XCD
+// has about the same work.  A bijection of the dispatch indices onto the
+// tiles (the logical index from xcd_block() is read band-major).
+__device__ __forceinline__ void banded_tile(int ntx, int nty, int ntz, int A, int& tx, int& ty, int& tz) {
+    const int L = (int)xcd_block();
+    const int nA = A == 0 ? ntx : nty;                   // tiles along the banded axis
+    const int other = (A == 0 ? nty : ntx) * ntz;        // tiles of one band position
+    const int q = nA / (int)NUM_XCD, r = nA % (int)NUM_XCD;
+    int b = 0;
+    for (int k = 1; k < (int)NUM_XCD; k++)
+        if ((k * q + min(k, r)) * other <= L) b = k;
+    const int a0 = b * q + min(b, r), nb = q + (b < r ? 1 : 0);
+    const int off = L - a0 * other;
+    if (A == 1) {                                        // rows of x tiles, band rows, then layers
+        tx = off % ntx;
+        const int rest = off / ntx;
+        ty = a0 + rest % nb;
+        tz = rest / nb;
+    } else {                                             // band columns, then rows, then layers
+        tx = a0 + off % nb;
+        const int rest = off / nb;
+        ty = rest % nty;
+        tz = rest / nty;
+    }
+}
 constexpr float PI_F = 3.14159265358979323846f;
 
 // Powers of the drag recurrence factor q = 1 - hc for 0 < hc < 2 (|q| < 1):
