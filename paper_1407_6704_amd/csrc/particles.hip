@@ -2088,7 +2088,14 @@ template <> struct CsrTile<2> { static constexpr int TX = 32, TY = 16, TZ = 1, M
 // coefficients in the spreading records; the adjoint spreads C = D + 1
 // components (density and momentum adjoints) from the planes coef[a np + s]
 // with the same kernel.  Each staged particle is its record (and the
-// adjoint's planes after it), copied as whole float4s.
+// adjoint's planes after it).
+//
+// The halo's cell starts are loaded by one thread per halo row (one batch of
+// independent loads each), and that thread turns them into the row's table
+// pk: for each node column lx of the tile, the LDS index of the first
+// particle of the four cells that reach it and the index one past the last,
+// packed in one word (tile positions < 2^16).  A node then reads one word per
+// halo row.
 template <int D, int C, bool REC>
 __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32_t* __restrict__ start,
                                                     const float* __restrict__ srec, const float* __restrict__ coef,
@@ -2105,54 +2112,46 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
     constexpr int CO = REC ? RS::COEF : RS::STRIDE;                    // the coefficients in a staged particle
     constexpr int MAXP = T::MAXP;
     static_assert(!REC || C == D, "records carry D coefficients");
-    __shared__ uint32_t cs[NR * (HX + 1)];       // per row: LDS index of each cell's first particle, then the end
+    static_assert(NR <= 256 && NR <= 255, "one thread per halo row; rows fit the row table");
+    static_assert(MAXP < 65536, "tile positions fit 16 bits");
+    __shared__ uint32_t pk[NR * TX];             // per row and node column: first | end << 16
     __shared__ uint32_t rowbase[NR + 1], rowg0[NR];
     __shared__ float sp[MAXP * PW];
     __shared__ uint8_t rowof[MAXP];              // halo row of each staged particle
     __shared__ uint32_t scan4[4];
-    static_assert(NR <= 255, "halo rows must fit the row table");
     const int t = threadIdx.x;
     int tx, ty, tz;
     banded_tile(ntx, nty, (int)gridDim.x / (ntx * nty), D == 3 ? 1 : 0, tx, ty, tz);
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int cx0 = x0 - 1, cy0 = y0 - 1, cz0 = (D == 3) ? z0 - 1 : 0;
     const int lo = max(cx0, 0), hi = min(cx0 + HX - 1, c.nb[0] - 1);
-    // every cell start of the halo in one batch of independent loads (cells
-    // left of the bins read the row's first start, right of them its end),
-    // then the row counts, their scan and the LDS offsets from LDS alone
-    constexpr int NCS = NR * (HX + 1);
-    constexpr int NIT = (NCS + 255) / 256;
-    uint32_t raw[NIT];
-#pragma unroll
-    for (int it = 0; it < NIT; it++) {
-        const int i = t + it * 256;
-        const int r = i / (HX + 1), ix = i % (HX + 1);
-        const int cy = cy0 + r % HY, cz = cz0 + r / HY;
-        const bool ok = i < NCS && cy >= 0 && cy < c.nb[1] && cz >= 0 && cz < c.nb[2] && lo <= hi;
-        const int cx = min(max(cx0 + ix, lo), hi + 1);
-        const long long at = ok ? ((long long)cz * c.nb[1] + cy) * c.nb[0] + cx : 0;
-        raw[it] = start[at];
-        if (!ok) raw[it] = 0;
-    }
-#pragma unroll
-    for (int it = 0; it < NIT; it++)
-        if (t + it * 256 < NCS) cs[t + it * 256] = raw[it];
-    __syncthreads();
+    // row t: the starts of its cells cx0 .. cx0 + HX, clamped to the bins
+    // [lo, hi + 1] (so v[0] is the row's first start and v[HX] its end)
+    uint32_t v[HX + 1];
     uint32_t cnt_row = 0;
     if (t < NR) {
-        uint32_t g0 = 0, g1 = 0;
-        if (lo <= hi) {
-            g0 = cs[t * (HX + 1) + (lo - cx0)];
-            g1 = cs[t * (HX + 1) + (hi + 1 - cx0)];
-        }
-        rowg0[t] = g0;
-        cnt_row = g1 - g0;
+        const int cy = cy0 + t % HY, cz = cz0 + t / HY;
+        const bool ok = cy >= 0 && cy < c.nb[1] && cz >= 0 && cz < c.nb[2] && lo <= hi;
+        const uint32_t* row = start + (ok ? ((long long)cz * c.nb[1] + cy) * c.nb[0] : 0);
+#pragma unroll
+        for (int ix = 0; ix <= HX; ix++) v[ix] = row[ok ? min(max(cx0 + ix, lo), hi + 1) : 0];
+        if (!ok)
+#pragma unroll
+            for (int ix = 0; ix <= HX; ix++) v[ix] = 0;
+        cnt_row = v[HX] - v[0];
     }
+    uint32_t rb;
     {
         // row offsets: exclusive scan of the row counts over the block
         uint32_t all;
-        const uint32_t ex = block_exclusive_scan<uint32_t>(cnt_row, scan4, all);
-        if (t < NR) rowbase[t] = ex;
+        rb = block_exclusive_scan<uint32_t>(cnt_row, scan4, all);
+        if (t < NR) {
+            rowbase[t] = rb;
+            rowg0[t] = v[0];
+#pragma unroll
+            for (int lx = 0; lx < TX; lx++)
+                pk[t * TX + lx] = (rb + (v[lx] - v[0])) | ((rb + (v[lx + 4] - v[0])) << 16);
+        }
         if (t == 0) rowbase[NR] = all;
     }
     __syncthreads();
@@ -2168,20 +2167,10 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
         }
         return;
     }
-    // LDS index of each cell's first particle: the row's offset plus the
-    // cell's start within the row (clamped cells give the row's ends)
-#pragma unroll
-    for (int it = 0; it < NIT; it++) {
-        const int i = t + it * 256;
-        if (i < NCS) {
-            const int r = i / (HX + 1);
-            cs[i] = rowbase[r] + (raw[it] - rowg0[r]);
-        }
-    }
     const bool staged = total <= (uint32_t)MAXP;
     if (staged) {
         if (t < NR)
-            for (uint32_t k = rowbase[t]; k < rowbase[t + 1]; k++) rowof[k] = (uint8_t)t;
+            for (uint32_t k = rb; k < rb + cnt_row; k++) rowof[k] = (uint8_t)t;
         __syncthreads();
         for (uint32_t k = t; k < total; k += 256) {
             const int r = rowof[k];
@@ -2189,19 +2178,19 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
             const float4* rec = (const float4*)(srec + (long long)gsl * RS::STRIDE);
 #pragma unroll
             for (int i = 0; i < RS::STRIDE / 4; i++) {
-                const float4 v = rec[i];
-                sp[k * PW + 4 * i] = v.x;
-                sp[k * PW + 4 * i + 1] = v.y;
-                sp[k * PW + 4 * i + 2] = v.z;
-                sp[k * PW + 4 * i + 3] = v.w;
+                const float4 w = rec[i];
+                sp[k * PW + 4 * i] = w.x;
+                sp[k * PW + 4 * i + 1] = w.y;
+                sp[k * PW + 4 * i + 2] = w.z;
+                sp[k * PW + 4 * i + 3] = w.w;
             }
             if (!REC) {
 #pragma unroll
                 for (int a = 0; a < C; a++) sp[k * PW + CO + a] = coef[(long long)a * np + gsl];
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
     for (int node = t; node < TX * TY * TZ; node += 256) {
         const int lx = node % TX, ly = (node / TX) % TY, lz = node / (TX * TY);
         const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
@@ -2209,72 +2198,66 @@ __global__ __launch_bounds__(256) void k_spread_csr(Grid g, PCfg c, const uint32
         float acc[C];
 #pragma unroll
         for (int a = 0; a < C; a++) acc[a] = 0.f;
-        if (total > 0) {
-            // the particle ranges of the node's 4^(D-1) halo rows: the four
-            // cells of a row that reach the node are contiguous in the row's
-            // CSR, and each particle's x weight index is x - base_x
-            constexpr int NRW = (D == 3 ? 16 : 4);
-            uint32_t pr[NRW];                      // first | end << 16 (tile positions < 2^16)
+        // the particle ranges of the node's 4^(D-1) halo rows (i = ky + 4 kz:
+        // row (ly + 3 - ky, lz + 3 - kz)); each particle's x weight index is
+        // x - base_x
+        constexpr int NRW = (D == 3 ? 16 : 4);
+        auto row_of = [&](int i) { return (D == 3 ? (lz + 3 - (i >> 2)) * HY : 0) + (ly + 3 - (i & 3)); };
+        if (staged && D == 2) {
 #pragma unroll
             for (int i = 0; i < NRW; i++) {
-                const int ky = i & 3, kz = i >> 2;
-                const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
-                pr[i] = cs[r * (HX + 1) + lx] | (cs[r * (HX + 1) + lx + 4] << 16);
-            }
-            if (staged && D == 2) {
-#pragma unroll
-                for (int i = 0; i < NRW; i++) {
-                    for (uint32_t k = pr[i] & 0xffffu; k < (pr[i] >> 16); k++) {
-                        const float* q = sp + k * PW;
-                        const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + (i & 3)];
-#pragma unroll
-                        for (int a = 0; a < C; a++) acc[a] += W * q[CO + a];
-                    }
-                }
-            } else if (staged) {
-                // 3D: one flat loop over the lane's particles, rows in
-                // order: a wave then runs as many trips as its busiest lane
-                // has particles, not the sum over the 16 rows of each row's
-                // busiest lane (in 2D the 4-row loop is as fast)
-                uint32_t mask = 0;
-#pragma unroll
-                for (int i = 0; i < NRW; i++)
-                    if ((pr[i] >> 16) > (pr[i] & 0xffffu)) mask |= 1u << i;
-                uint32_t k = 0, e = 0;
-                int ky = 0, kz = 0;
-                while (true) {
-                    if (k == e) {
-                        if (!mask) break;
-                        const int i = __builtin_ctz(mask);
-                        mask &= mask - 1u;
-                        ky = i & 3;
-                        kz = i >> 2;
-                        const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
-                        k = cs[r * (HX + 1) + lx];
-                        e = cs[r * (HX + 1) + lx + 4];
-                    }
+                const uint32_t pr = pk[row_of(i) * TX + lx];
+                for (uint32_t k = pr & 0xffffu; k < (pr >> 16); k++) {
                     const float* q = sp + k * PW;
-                    const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + ky] * (D == 3 ? q[8 + kz] : 1.f);
+                    const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + i];
 #pragma unroll
                     for (int a = 0; a < C; a++) acc[a] += W * q[CO + a];
-                    k++;
                 }
-            } else {
-#pragma unroll 1
-                for (int i = 0; i < NRW; i++) {
-                    const int ky = i & 3, kz = i >> 2;
-                    const int r = (D == 3 ? (lz + 3 - kz) * HY : 0) + (ly + 3 - ky);
-                    const uint32_t k0 = cs[r * (HX + 1) + lx], k1 = cs[r * (HX + 1) + lx + 4];
-                    for (uint32_t k = k0; k < k1; k++) {
-                        // particle k of halo row r sits at sorted slot rowg0[r] + (k - rowbase[r])
-                        const uint32_t gsl = rowg0[r] + (k - rowbase[r]);
-                        const float* q = srec + (long long)gsl * RS::STRIDE;
-                        const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + ky] *
-                                        (D == 3 ? q[8 % (4 * D) + kz] : 1.f);
+            }
+        } else if (staged) {
+            // 3D: one flat loop over the lane's particles, rows in order: a
+            // wave then runs as many trips as its busiest lane has particles,
+            // not the sum over the 16 rows of each row's busiest lane
+            uint32_t mask = 0;
 #pragma unroll
-                        for (int a = 0; a < C; a++)
-                            acc[a] += W * (REC ? q[CO + a] : coef[(long long)a * np + gsl]);
-                    }
+            for (int i = 0; i < NRW; i++) {
+                const uint32_t pr = pk[row_of(i) * TX + lx];
+                if ((pr >> 16) > (pr & 0xffffu)) mask |= 1u << i;
+            }
+            uint32_t k = 0, e = 0;
+            int ky = 0, kz = 0;
+            while (true) {
+                if (k == e) {
+                    if (!mask) break;
+                    const int i = __builtin_ctz(mask);
+                    mask &= mask - 1u;
+                    ky = i & 3;
+                    kz = i >> 2;
+                    const uint32_t pr = pk[row_of(i) * TX + lx];
+                    k = pr & 0xffffu;
+                    e = pr >> 16;
+                }
+                const float* q = sp + k * PW;
+                const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + ky] * q[8 % (4 * D) + kz];
+#pragma unroll
+                for (int a = 0; a < C; a++) acc[a] += W * q[CO + a];
+                k++;
+            }
+        } else {
+#pragma unroll 1
+            for (int i = 0; i < NRW; i++) {
+                const int ky = i & 3, kz = i >> 2;
+                const int r = row_of(i);
+                const uint32_t pr = pk[r * TX + lx];
+                for (uint32_t k = pr & 0xffffu; k < (pr >> 16); k++) {
+                    // particle k of halo row r sits at sorted slot rowg0[r] + (k - rowbase[r])
+                    const uint32_t gsl = rowg0[r] + (k - rowbase[r]);
+                    const float* q = srec + (long long)gsl * RS::STRIDE;
+                    const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + ky] *
+                                    (D == 3 ? q[8 % (4 * D) + kz] : 1.f);
+#pragma unroll
+                    for (int a = 0; a < C; a++)
+                        acc[a] += W * (REC ? q[CO + a] : coef[(long long)a * np + gsl]);
                 }
             }
         }
