@@ -335,6 +335,44 @@ pibm_status pibm_forward_ckpt(pibm_ctx* ctx, int32_t n_steps, int32_t K, void* d
 pibm_status pibm_backward(pibm_ctx* ctx, const float* dJ_dx_T, const float* dJ_dv_T, float* dJ_dx0,
                           float* dJ_dv0, double* dJ_dtau, double* dJ_dgravity);
 
+/* ---- Stages of the reverse step, one at a time --------------------------
+ * For checking each part of the adjoint on its own (a vector-Jacobian
+ * product against an independent derivative of the same stage, or a
+ * transpose against the forward operator it transposes), and for callers
+ * composing objectives of their own.  Each call applies one stage at the
+ * context's current state and leaves that state unchanged (the particles may
+ * be re-sorted, which no output depends on).  Needs a recorded rollout
+ * (pibm_forward_ckpt), whose buffer provides the scratch; the recording stays
+ * valid.  Arrays are DEVICE FP32; n = nodes, np = particles.  Asynchronous,
+ * except that `scalars` (HOST doubles, may be NULL) makes the call
+ * synchronise.  Unknown stages and NULL arrays return PIBM_E_ARG.
+ *
+ * PIBM_STAGE_COLLIDE_T (Eq. lbm2 and lbm9 with push streaming and
+ *   bounce-back, Sec. 2.1): in0 = adjoint of the populations after collision
+ *   and streaming (Q x n, canonical order); out0 = adjoint of the populations
+ *   before the collision, the force field held fixed (Q x n); out1 = adjoint
+ *   of the force field (D x n); scalars[0] = derivative with respect to tau.
+ *   At the current populations and the force field of the last step.
+ * PIBM_STAGE_PARTICLES_T (Eq. lbm7-lbm8, lbm10-lbm13 and demgov, as in
+ *   pibm_backward): in0 = adjoint of the spread force field (D x n), in1 and
+ *   in2 = adjoints of the positions and velocities after the particle update
+ *   (D x np, id order); out0 and out1 = the adjoints of the positions and
+ *   velocities before it (D x np, id order), out2 = adjoint of the node
+ *   moments that were interpolated (delta rho, j: (1 + D) x n);
+ *   scalars[0 .. 2] = derivative with respect to gravity.  At the current
+ *   particle state and the moments of the current populations.
+ * PIBM_STAGE_INTERP (Eq. lbm11-lbm12): in0 = node fields ((1 + D) x n);
+ *   out0 = their interpolation at the particles ((1 + D) x np, in the
+ *   library's sorted order, as pibm_read_cell_list reports it), with the
+ *   delta-kernel weights of the current positions.
+ * PIBM_STAGE_INTERP_T: in0 = (1 + D) x np in the same order; out0 = the
+ *   transpose of the last PIBM_STAGE_INTERP, (1 + D) x n: each particle
+ *   value spread with the same weights (Eq. lbm10-lbm11).  PIBM_E_STATE
+ *   unless PIBM_STAGE_INTERP came first. */
+enum { PIBM_STAGE_COLLIDE_T = 1, PIBM_STAGE_PARTICLES_T = 2, PIBM_STAGE_INTERP = 3, PIBM_STAGE_INTERP_T = 4 };
+pibm_status pibm_adjoint_stage(pibm_ctx* ctx, int32_t stage, const float* in0, const float* in1,
+                               const float* in2, float* out0, float* out1, float* out2, double* scalars);
+
 #ifdef __cplusplus
 }
 #endif

@@ -182,6 +182,14 @@ class Ref:
     def step(self, f, X, U, tau, gvec):
         """One coupled step; returns (f', X', U').  gvec: gravity (D,)."""
         rho, j = self.moments(f)
+        X, U, F = self.particle_part(rho, j, X, U, gvec)
+        f = self.collide_stream(f, rho, j, F, tau)
+        return f, X, U
+
+    def particle_part(self, rho, j, X, U, gvec):
+        """The particle side of one step from the node moments (rho, j) of
+        the populations: interpolation, the sub-stepped update and the
+        spread force field.  Returns (X', U', F)."""
         idx, W = self.stencil(X)
         rho_i = (W * rho[idx]).sum(1)
         j_i = (W[None] * j[:, idx]).sum(2)
@@ -201,8 +209,7 @@ class Ref:
             coef = self.A * gbar                                # (D, np)
             contrib = coef[:, :, None] * W[None]                # (D, np, 4^D)
             F = F.index_add(1, idx.flatten(), contrib.reshape(self.D, -1))
-        f = self.collide_stream(f, rho, j, F, tau)
-        return f, X, U
+        return X, U, F
 
     def rest(self, rho=1.0):
         return (self.w[:, None] * rho).repeat(1, self.N)

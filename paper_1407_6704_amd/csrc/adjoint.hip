@@ -493,6 +493,17 @@ __global__ void k_df_collapse(const float* __restrict__ hi, const float* __restr
     if (i < n) out[i] = hi[i] + lo[i];
 }
 
+// Node fields in planes (comps planes of n) to the float4 moments layout
+// read by the interpolation (components past comps are zero).
+__global__ __launch_bounds__(256) void k_pack_mom(const float* __restrict__ in, int comps, long long n,
+                                                  float4* __restrict__ out) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < comps && k < 4; k++) v[k] = in[(long long)k * n + i];
+    out[i] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
 static inline unsigned blocks256(long long n) { return (unsigned)std::max<long long>((n + 255) / 256, 1); }
 
 // ---------------------------------------------------------------------------
@@ -571,6 +582,10 @@ void adj_particles(int D, PBuf& b, int np, const Grid& g, const PCfg& c, int two
 
 void adj_accumulate(const float* tpart, int ntb, const float* gpart, int ngb, float* acc, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_accumulate, dim3(1), dim3(256), 0, s, tpart, ntb, gpart, ngb, acc);
+}
+
+void adj_pack_mom(const float* in, int comps, long long n, float4* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_mom, dim3(blocks256(n)), dim3(256), 0, s, in, comps, n, out);
 }
 
 }  // namespace pibm

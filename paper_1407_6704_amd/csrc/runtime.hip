@@ -59,6 +59,7 @@ void adj_particles(int D, PBuf& b, int np, const Grid& g, const PCfg& c, int two
                    const float* Fbar, const float* xbh, const float* xbl, const float* ub, float* xbh_o,
                    float* xbl_o, float* ub_o, float* coefS, float* gpart, hipStream_t s);
 void adj_accumulate(const float* tpart, int ntb, const float* gpart, int ngb, float* acc, hipStream_t s);
+void adj_pack_mom(const float* in, int comps, long long n, float4* out, hipStream_t s);
 
 // Layout of the caller's rollout buffer (see pibm_rollout_bytes).
 struct Rollout {
@@ -102,6 +103,10 @@ struct pibm_ctx {
     Rollout ro{};
     bool particles_set = false;
     bool stepped = false;
+    // the spreading records change with every step, particle hand-over and
+    // particle adjoint stage; PIBM_STAGE_INTERP_T needs those of the last
+    // PIBM_STAGE_INTERP
+    uint64_t srec_epoch = 0, interp_stage_epoch = ~0ull;
     // particles handed over in device memory whose validity the device has
     // reported but the host has not read yet: the first step waits for it
     bool device_input_unchecked = false;
@@ -616,6 +621,7 @@ pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, co
     if (!c) return PIBM_E_ARG;
     if (c->np == 0) {
         c->particles_set = true;
+        c->srec_epoch++;
         return PIBM_OK;
     }
     if (!x || !d || !rho_p) return fail(c, PIBM_E_ARG, "null particle array");
@@ -662,6 +668,7 @@ pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, co
     c->body_of.assign(np, -1);
     set_stencil(*c, dmax);
     c->particles_set = true;
+    c->srec_epoch++;
     c->stepped = false;
     c->device_input_unchecked = false;
     return PIBM_OK;
@@ -672,6 +679,7 @@ pibm_status pibm_set_particles_device(pibm_ctx* c, const float* x_hi, const floa
     if (!c) return PIBM_E_ARG;
     if (c->np == 0) {
         c->particles_set = true;
+        c->srec_epoch++;
         return PIBM_OK;
     }
     if (!x_hi || !d || !rho_p) return fail(c, PIBM_E_ARG, "null particle array");
@@ -684,6 +692,7 @@ pibm_status pibm_set_particles_device(pibm_ctx* c, const float* x_hi, const floa
     c->body_of.assign(c->np, -1);
     set_stencil(*c, (double)dmax);
     c->particles_set = true;
+    c->srec_epoch++;
     c->stepped = false;
     c->device_input_unchecked = true;
     return PIBM_OK;
@@ -906,6 +915,7 @@ constexpr uint32_t ONE_GROUP_MAX = 1024;   // one pass per phase: faster than ni
 // launch errors are read by the caller with hipGetLastError).
 hipError_t launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
     HipSeq q;
+    c->srec_epoch++;
     const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
     const bool spread = c->np > 0 && c->cfg.two_way;
     // D2Q9 interpolation takes the moments straight from the populations of
@@ -1080,6 +1090,85 @@ pibm_status pibm_backward(pibm_ctx* c, const float* dJ_dx_T, const float* dJ_dv_
     if (dJ_dtau) *dJ_dtau = (double)acc[0] + (double)acc[1];
     if (dJ_dgravity)
         for (int a = 0; a < 3; a++) dJ_dgravity[a] = a < D ? (double)acc[2 + 2 * a] + (double)acc[3 + 2 * a] : 0.0;
+    return PIBM_OK;
+}
+
+pibm_status pibm_adjoint_stage(pibm_ctx* c, int32_t stage, const float* in0, const float* in1, const float* in2,
+                               float* out0, float* out1, float* out2, double* scalars) {
+    if (!c) return PIBM_E_ARG;
+    Rollout& R = c->ro;
+    if (!R.valid) return fail(c, PIBM_E_STATE, "adjoint stages need a recorded rollout (pibm_forward_ckpt)");
+    const int D = c->D, np = c->np, Q = c->Q;
+    const long long N = c->N, DN = (long long)D * np;
+    hipStream_t s = c->stream;
+    const float tau = (float)c->cfg.tau;
+    const int spread = c->cfg.two_way ? 1 : 0;
+    HipSeq q;
+    int nsc = 0;
+    float acc[8];
+    switch (stage) {
+    case PIBM_STAGE_COLLIDE_T: {
+        if (!in0 || !out0 || !out1) return fail(c, PIBM_E_ARG, "collide stage: null array");
+        const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1],
+                             (float)c->cfg.fluid_force[2]};
+        adj_fill(R.acc, 8, 0.f, s);
+        adj_collide(Q, c->fp16, c->sl2, in0, c->fA, c->F, np > 0 && spread, ff, c->grid, tau, c->mom, out1, R.Mc,
+                    R.tpart, s);
+        adj_assemble(Q, in0, R.Mc, nullptr, 0, c->grid, tau, out0, s);
+        adj_accumulate(R.tpart, adj_collide_blocks(N), nullptr, 0, R.acc, s);
+        nsc = 1;
+        break;
+    }
+    case PIBM_STAGE_PARTICLES_T: {
+        if (!in0 || !in1 || !in2 || !out0 || !out1 || !out2)
+            return fail(c, PIBM_E_ARG, "particle stage: null array");
+        if (np == 0) return fail(c, PIBM_E_STATE, "particle stage: no particles");
+        particles_sort(D, c->pb, np, c->pc, s);
+        lattice_moments(Q, c->fp16, c->sl2, c->fA, c->mom, N, RowMask{}, s);
+        adj_fill(R.acc, 8, 0.f, s);
+        adj_fill(R.xbl[0], DN, 0.f, s);
+        adj_particles(D, c->pb, np, c->grid, c->pc, spread, c->mom, in0, in1, R.xbl[0], in2, R.xbh[1], R.xbl[1],
+                      out1, R.coefS, R.gpart, s);
+        particles_spread_adjoint(D, c->pb, np, c->pc, c->grid, R.coefS, out2, s);
+        adj_df_collapse(R.xbh[1], R.xbl[1], out0, DN, s);
+        adj_accumulate(nullptr, 0, R.gpart, adj_particle_blocks(np), R.acc, s);
+        c->srec_epoch++;
+        nsc = 3;
+        break;
+    }
+    case PIBM_STAGE_INTERP: {
+        if (!in0 || !out0) return fail(c, PIBM_E_ARG, "interpolation stage: null array");
+        if (np == 0) return fail(c, PIBM_E_STATE, "interpolation stage: no particles");
+        particles_sort(D, c->pb, np, c->pc, s);
+        adj_pack_mom(in0, 1 + D, N, c->mom, s);
+        particles_interp(D, c->pb, np, c->grid, c->pc, c->mom, s);
+        q(hipMemcpyAsync(out0, c->pb.drho_i, 4 * (size_t)np, hipMemcpyDeviceToDevice, s));
+        q(hipMemcpyAsync(out0 + np, c->pb.j_i, 4 * (size_t)DN, hipMemcpyDeviceToDevice, s));
+        c->interp_stage_epoch = ++c->srec_epoch;
+        break;
+    }
+    case PIBM_STAGE_INTERP_T: {
+        if (!in0 || !out0) return fail(c, PIBM_E_ARG, "interpolation transpose: null array");
+        if (c->interp_stage_epoch != c->srec_epoch)
+            return fail(c, PIBM_E_STATE, "interpolation transpose: PIBM_STAGE_INTERP must come first");
+        particles_spread_adjoint(D, c->pb, np, c->pc, c->grid, in0, out0, s);
+        break;
+    }
+    default:
+        return fail(c, PIBM_E_ARG, "unknown adjoint stage");
+    }
+    if (scalars && nsc > 0) q(hipMemcpyAsync(acc, R.acc, sizeof(acc), hipMemcpyDeviceToHost, s));
+    if (q.e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        return check_hip(c, q.e, "adjoint stage: copy");
+    }
+    if (pibm_status st = check_hip(c, hipGetLastError(), "adjoint stage launch")) return st;
+    if (scalars && nsc > 0) {
+        if (pibm_status st = sync_and_flags(c)) return st;
+        if (stage == PIBM_STAGE_COLLIDE_T) scalars[0] = (double)acc[0] + (double)acc[1];
+        else
+            for (int a = 0; a < 3; a++) scalars[a] = a < D ? (double)acc[2 + 2 * a] + (double)acc[3 + 2 * a] : 0.0;
+    }
     return PIBM_OK;
 }
 

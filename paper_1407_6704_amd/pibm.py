@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pibm.h")
 ABI_VERSION = 6
 D2Q9, D3Q15, D3Q19 = 9, 15, 19
 STORE_FP32, STORE_FP16 = 0, 1
+STAGE = {"collide_t": 1, "particles_t": 2, "interp": 3, "interp_t": 4}    # PIBM_STAGE_* in the header
 CONTACT = {"none": 0, "lsd": 1, "soft": 2, "hertz": 3, "hertz_mindlin": 4, "hertz_mindlin_microslip": 5}
 INTERP = {"delta": 0, "lagrange": 1}
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_CONFIG", 3: "E_HIP", 4: "E_STATE", 5: "E_UNSTABLE",
@@ -108,6 +109,7 @@ def load():
         "pibm_read_particles_device": ([vp, vp, vp, vp, vp, vp], C.c_int),
         "pibm_read_fields_device": ([vp, vp, vp], C.c_int),
         "pibm_read_force_device": ([vp, vp], C.c_int),
+        "pibm_adjoint_stage": ([vp, C.c_int32, vp, vp, vp, vp, vp, vp, dp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -416,6 +418,36 @@ class Sim:
 
         self._check(self.lib.pibm_backward(self.ctx, ptr(gx), ptr(gv), ptr(dx0), ptr(dv0), C.byref(dtau), dg))
         return {"dx0": dx0, "dv0": dv0, "dtau": dtau.value, "dgravity": list(dg)}
+
+    def adjoint_stage(self, stage, in0, in1=None, in2=None):
+        """One stage of the reverse step at the current state (see
+        pibm_adjoint_stage; needs forward_ckpt first).  stage: "collide_t",
+        "particles_t", "interp" or "interp_t"; inputs are arrays or tensors
+        of the shapes the header gives.  Returns a dict of FP32 device
+        tensors (and the stage's scalars as floats)."""
+        import torch
+
+        D, Q, N, n = self.D, self.cfg.lattice, self.N, self.np
+        code = STAGE[stage]
+        shapes = {"collide_t": ([(Q, N)], [(Q, N), (D, N)], 1),
+                  "particles_t": ([(D, N), (D, n), (D, n)], [(D, n), (D, n), (1 + D, N)], 3),
+                  "interp": ([(1 + D, N)], [(1 + D, n)], 0),
+                  "interp_t": ([(1 + D, n)], [(1 + D, N)], 0)}[stage]
+        ins = [self._dev_f32(a).reshape(sh) for a, sh in zip((in0, in1, in2), shapes[0])]
+        outs = [torch.empty(sh, dtype=torch.float32, device=self.device) for sh in shapes[1]]
+        nsc = shapes[2]
+        sc = (C.c_double * 3)() if nsc else None
+        vps = [self._vp(t) for t in ins] + [None] * (3 - len(ins))
+        ops = [self._vp(t) for t in outs] + [None] * (3 - len(outs))
+        self._check(self.lib.pibm_adjoint_stage(self.ctx, code, *vps, *ops, sc))
+        names = {"collide_t": ("fbar", "Fbar"), "particles_t": ("xbar", "ubar", "mbar"),
+                 "interp": ("out",), "interp_t": ("out",)}[stage]
+        r = dict(zip(names, outs))
+        if stage == "collide_t":
+            r["dtau"] = sc[0]
+        elif stage == "particles_t":
+            r["dgravity"] = list(sc)
+        return r
 
     def backward(self, dJ_dx=None, dJ_dv=None):
         """As backward_device, with dx0 and dv0 returned as numpy arrays."""
