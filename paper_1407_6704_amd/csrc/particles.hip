@@ -260,18 +260,22 @@ __global__ __launch_bounds__(256) void k_bin_count(PState A, int np, PCfg c, uin
     slot[s] = atomicAdd(&cnt[key], 1u);
 }
 
+// The id of each particle to its place among its bin (in the order the
+// counts were taken), so that ranking reads the ids of a bin from
+// consecutive words.
 __global__ void k_scatter(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ slot,
-                          const uint32_t* __restrict__ start, uint32_t* __restrict__ tmp, int np) {
+                          const uint32_t* __restrict__ start, const int* __restrict__ id,
+                          int* __restrict__ tmpid, int np) {
     int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= np) return;
-    tmp[start[keys[s]] + slot[s]] = s;
+    tmpid[start[keys[s]] + slot[s]] = id[s];
 }
 
 // Final slot = bin start + rank of the particle's id among its bin.
 template <int D>
 __global__ __launch_bounds__(256) void k_reorder(PState A, PState B, const uint32_t* __restrict__ keys,
                                                  const uint32_t* __restrict__ start,
-                                                 const uint32_t* __restrict__ tmp,
+                                                 const int* __restrict__ tmpid,
                                                  uint32_t* __restrict__ keys_sorted, float4* __restrict__ pos4,
                                                  int np) {
     int s = xcd_block() * 256 + threadIdx.x;
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(256) void k_reorder(PState A, PState B, const uint3
     uint32_t b0 = start[k], b1 = start[k + 1];
     int myid = A.id[s];
     uint32_t rank = 0;
-    for (uint32_t t = b0; t < b1; t++) rank += (A.id[tmp[t]] < myid) ? 1u : 0u;
+    for (uint32_t t = b0; t < b1; t++) rank += (tmpid[t] < myid) ? 1u : 0u;
     uint32_t o = b0 + rank;
 #pragma unroll
     for (int a = 0; a < D; a++) {
@@ -2479,11 +2483,13 @@ void particles_sort(int D, PBuf& b, int np, const PCfg& c, hipStream_t s) {
     else
         hipLaunchKernelGGL(k_bin_count<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, np, c, b.cnt, b.keys, b.slot, b.flags);
     scan_exclusive<uint32_t>(b.cnt, b.start, nbins + 1, b.scan_u32, nullptr, true, s);
-    hipLaunchKernelGGL(k_scatter, dim3(nb256(np)), dim3(256), 0, s, b.keys, b.slot, b.start, b.tmp, np);
+    hipLaunchKernelGGL(k_scatter, dim3(nb256(np)), dim3(256), 0, s, b.keys, b.slot, b.start, b.A.id, b.tmpid, np);
     if (D == 3)
-        hipLaunchKernelGGL(k_reorder<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, b.pos4, np);
+        hipLaunchKernelGGL(k_reorder<3>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmpid,
+                           b.keys_sorted, b.pos4, np);
     else
-        hipLaunchKernelGGL(k_reorder<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmp, b.keys_sorted, b.pos4, np);
+        hipLaunchKernelGGL(k_reorder<2>, dim3(nb256(np)), dim3(256), 0, s, b.A, b.B, b.keys, b.start, b.tmpid,
+                           b.keys_sorted, b.pos4, np);
     PState t = b.A;
     b.A = b.B;
     b.B = t;

@@ -330,7 +330,8 @@ template <int D> struct SRec {
 // Device buffers of the particle side (carved from the workspace).
 struct PBuf {
     PState A, B, Bn;             // current, reorder target, next (after DEM)
-    uint32_t *cnt, *start, *keys, *slot, *tmp, *keys_sorted;
+    uint32_t *cnt, *start, *keys, *slot, *keys_sorted;
+    int* tmpid;                  // particle ids grouped by bin (unranked within a bin)
     float4* pos4;                // (x, y, z) leading parts and d, sorted order
     uint32_t* scan_u32;          // scan block sums
     unsigned long long *actcc, *prefix, *bsum64;   // bsum64: per-block totals of actcc

@@ -282,7 +282,7 @@ size_t carve(pibm_ctx& c, char* base) {
         b.start = cv.take<uint32_t>(nb1);
         b.keys = cv.take<uint32_t>(np);
         b.slot = cv.take<uint32_t>(np);
-        b.tmp = cv.take<uint32_t>(np);
+        b.tmpid = cv.take<int>(np);
         b.keys_sorted = cv.take<uint32_t>(np);
         b.pos4 = cv.take<float4>(np);
         b.scan_u32 = cv.take<uint32_t>(scan_blocks(nb1) + 1);
