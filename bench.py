@@ -61,12 +61,14 @@ def algorithmic_bytes(phase: str, w, np_: int) -> float:
         return N * (2 * Q * es + (4 * D if coupled else 0))
     if phase == "moments":
         return N * (Q * es + 16)
+    rec = 4 * (16 if D == 3 else 12)       # a particle's spreading record: weights, x base, coefficients
     if phase == "spread":
-        # force field write + per-particle weights, base and coefficients read
-        return N * 4 * D + np_ * (8 + 16 * D + 4 * D)
+        # force field write + each particle's record read once
+        return N * 4 * D + np_ * rec
     if phase == "interp":
-        # particle position read, moments gathered once per node (dense), outputs
-        return np_ * (8 * D + 4 + 4 * D + 8 + 16 * D) + N * 16
+        # moments read once per node; positions read; interpolated moments,
+        # record and stencil bases written
+        return N * 16 + np_ * (8 * D + 4 + 4 * D + rec + 8)
     if phase == "cell_list":
         return np_ * (2 * (12 * D + 12) + 16)
     if phase == "dem":
