@@ -44,7 +44,19 @@ PROFILE_SAMPLES = 10     # timed steps that record the phase events (evenly spac
 # entry applies only while the kernel's own source (its __global__ function
 # and the shared device header) hashes to `kernel_sha`: a changed kernel
 # reports null until it is measured again.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("collide", "c1"): {"fetch_bytes": 184657106, "write_bytes": 153742632, "kernel_sha": "3b5a733495964ce5"},
+    ("collide", "c2"): {"fetch_bytes": 1476574203, "write_bytes": 1282894584, "kernel_sha": "3b5a733495964ce5"},
+    ("collide", "c3"): {"fetch_bytes": 838978130, "write_bytes": 645541636, "kernel_sha": "3b5a733495964ce5"},
+    ("interp", "c1"): {"fetch_bytes": 146701708, "write_bytes": 35859633, "kernel_sha": "ec2c21fbd4d1d896"},
+    ("interp", "c2"): {"fetch_bytes": 268623185, "write_bytes": 180321752, "kernel_sha": "ec2c21fbd4d1d896"},
+    ("interp", "c3"): {"fetch_bytes": 268623185, "write_bytes": 180492349, "kernel_sha": "ec2c21fbd4d1d896"},
+    ("moments", "c2"): {"fetch_bytes": 884715750, "write_bytes": 180287632, "kernel_sha": "802e830f6353c655"},
+    ("moments", "c3"): {"fetch_bytes": 365832693, "write_bytes": 136273430, "kernel_sha": "802e830f6353c655"},
+    ("spread", "c1"): {"fetch_bytes": 44515674, "write_bytes": 33539504, "kernel_sha": "d52b0d772beea154"},
+    ("spread", "c2"): {"fetch_bytes": 212372739, "write_bytes": 201237028, "kernel_sha": "d52b0d772beea154"},
+    ("spread", "c3"): {"fetch_bytes": 212372739, "write_bytes": 201271147, "kernel_sha": "d52b0d772beea154"},
+}
 KERNEL_SOURCES = {"collide": ("lattice.hip", "k_collide"), "moments": ("lattice.hip", "k_moments"),
                   "spread": ("particles.hip", "k_spread_csr"), "interp": ("particles.hip", "k_interp_tile")}
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
