@@ -57,8 +57,13 @@ MEASURED_TRAFFIC = {
     ("spread", "c2"): {"fetch_bytes": 212372739, "write_bytes": 201237028, "kernel_sha": "d52b0d772beea154"},
     ("spread", "c3"): {"fetch_bytes": 212372739, "write_bytes": 201271147, "kernel_sha": "d52b0d772beea154"},
 }
-KERNEL_SOURCES = {"collide": ("lattice.hip", "k_collide"), "moments": ("lattice.hip", "k_moments"),
-                  "spread": ("particles.hip", "k_spread_csr"), "interp": ("particles.hip", "k_interp_tile")}
+# the source of each measured kernel: its __global__ function and the device
+# routines of its own file that carry its arithmetic (pibm_internal.h, which
+# holds the per-node collision, is hashed with every kernel)
+KERNEL_SOURCES = {"collide": [("lattice.hip", "k_collide")], "moments": [("lattice.hip", "k_moments")],
+                  "spread": [("particles.hip", "spread_tile"), ("particles.hip", "k_spread_csr")],
+                  "spread_collide": [("particles.hip", "spread_tile"), ("particles.hip", "k_spread_collide")],
+                  "interp": [("particles.hip", "k_interp_tile")]}
 METRIC = "coupled LBM-PIBM-DEM MLUPS + particle-updates/s; FP16 vs FP32; adjoint/fwd ratio"
 
 
@@ -77,6 +82,10 @@ def algorithmic_bytes(phase: str, w, np_: int) -> float:
     if phase == "spread":
         # force field write + each particle's record read once
         return N * 4 * D + np_ * rec
+    if phase == "spread_collide":
+        # 3D spreading fused into the collision: populations read and
+        # written, each particle's record read once, no force field
+        return N * 2 * Q * es + np_ * rec
     if phase == "interp":
         # moments read once per node; positions read; interpolated moments,
         # record and stencil bases written
@@ -88,12 +97,19 @@ def algorithmic_bytes(phase: str, w, np_: int) -> float:
     return 0.0
 
 
+def fused_spread(w, np_: int) -> bool:
+    """3D steps with bins of one dual cell and FP32 storage spread into the
+    collision."""
+    return w.dim == 3 and w.bin_log2 == 0 and np_ > 0 and bool(w.two_way) and w.storage == "fp32"
+
+
 def kernel_text(src: str, name: str) -> str:
     """The source text of kernel `name` in csrc/`src`: from the template line
     before its __global__ declaration to the closing brace in column 0."""
     with open(os.path.join(ROOT, "paper_1407_6704_amd", "csrc", src)) as fh:
         lines = fh.read().split("\n")
-    start = next(i for i, ln in enumerate(lines) if "__global__" in ln and f" {name}(" in ln)
+    start = next(i for i, ln in enumerate(lines)
+                 if ("__global__" in ln or "__device__" in ln) and f" {name}(" in ln)
     if start > 0 and lines[start - 1].startswith("template"):
         start -= 1
     end = next(i for i in range(start + 1, len(lines)) if lines[i] == "}")
@@ -104,8 +120,9 @@ def source_sha(kernel: str) -> str:
     """Hash of a kernel's own source and of the device header it includes."""
     import hashlib
 
-    src, name = KERNEL_SOURCES[kernel]
-    h = hashlib.sha256(kernel_text(src, name).encode())
+    h = hashlib.sha256()
+    for src, name in KERNEL_SOURCES[kernel]:
+        h.update(kernel_text(src, name).encode())
     with open(os.path.join(ROOT, "paper_1407_6704_amd", "csrc", "pibm_internal.h"), "rb") as fh:
         h.update(fh.read())
     return h.hexdigest()[:16]
@@ -214,6 +231,9 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
     # moments pass is left out: it skips the node rows no particle reaches, so
     # its bytes depend on where the particles are)
     single = {k: v for k, v in res["phases_ms_per_step"].items() if k in ("collide", "spread")}
+    if fused_spread(w, np_):
+        # the collision phase is the fused spreading and collision kernel
+        single = {"spread_collide": single["collide"]}
     dom = max(single, key=single.get)
     b = algorithmic_bytes(dom, w, np_)
     t = single[dom] * 1e-3

@@ -86,64 +86,18 @@ __global__ __launch_bounds__((collide_bs<Q, S>())) void k_collide(const typename
     const long long N = g.N;
     long long r = (long long)blockIdx.x * collide_bs<Q, S>() + threadIdx.x;
     if (r >= N) return;
-    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int nx = g.n[0], ny = g.n[1];
     const int x = (int)(r % nx);
     const long long t = r / nx;
     const int y = (int)(t % ny);
     const int z = (int)(t / ny);
-
-    float h[Q];
-#pragma unroll
-    for (int q = 0; q < Q; q++) h[q] = st.load_stream(fin + (long long)q * N + r);
-
-    float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int q = 0; q < Q; q++) {
-        dr += h[q];
-        if (L::ex(q)) jx += L::ex(q) * h[q];
-        if (L::ey(q)) jy += L::ey(q) * h[q];
-        if (L::ez(q)) jz += L::ez(q) * h[q];
-    }
     float Fx = ffx, Fy = ffy, Fz = ffz;
     if (hasF) {
         Fx += F[r];
         Fy += F[N + r];
         if (L::D == 3) Fz += F[2 * N + r];
     }
-    const float rho = 1.0f + dr;
-    const float ir = 1.0f / rho;
-    const float ux = (jx + 0.5f * Fx) * ir, uy = (jy + 0.5f * Fy) * ir, uz = (jz + 0.5f * Fz) * ir;
-    const float uu = ux * ux + uy * uy + uz * uz;
-    const float uF = ux * Fx + uy * Fy + uz * Fz;
-
-    // neighbour offsets with wrap (periodic) or a bounce flag (wall)
-    const long long sx = 1, sy = nx, sz = (long long)nx * ny;
-    const bool xlo = (x == 0), xhi = (x == nx - 1);
-    const bool ylo = (y == 0), yhi = (y == ny - 1);
-    const bool zlo = (z == 0), zhi = (z == nz - 1);
-
-#pragma unroll
-    for (int q = 0; q < Q; q++) {
-        const int ex = L::ex(q), ey = L::ey(q), ez = L::ez(q);
-        const float eu = ex * ux + ey * uy + ez * uz;
-        const float eF = ex * Fx + ey * Fy + ez * Fz;
-        const float heq = L::w(q) * (dr + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
-        const float src = fpref * L::w(q) * (3.0f * (eF - uF) + 9.0f * eu * eF);
-        const float hs = h[q] - omega * (h[q] - heq) + src;
-
-        long long dst = r;
-        bool out = false;
-        if (ex > 0) { if (xhi) { if (g.periodic[0]) dst -= (nx - 1) * sx; else out = true; } else dst += sx; }
-        if (ex < 0) { if (xlo) { if (g.periodic[0]) dst += (nx - 1) * sx; else out = true; } else dst -= sx; }
-        if (ey > 0) { if (yhi) { if (g.periodic[1]) dst -= (ny - 1) * sy; else out = true; } else dst += sy; }
-        if (ey < 0) { if (ylo) { if (g.periodic[1]) dst += (ny - 1) * sy; else out = true; } else dst -= sy; }
-        if (ez > 0) { if (zhi) { if (g.periodic[2]) dst -= (long long)(nz - 1) * sz; else out = true; } else dst += sz; }
-        if (ez < 0) { if (zlo) { if (g.periodic[2]) dst += (long long)(nz - 1) * sz; else out = true; } else dst -= sz; }
-        if (out)
-            st.store(fout + (long long)L::opp(q) * N + r, hs);
-        else
-            st.store(fout + (long long)q * N + dst, hs);
-    }
+    collide_node<Q, S>(fin, fout, r, x, y, z, g, Fx, Fy, Fz, omega, fpref, st);
 }
 
 // Equilibrium populations (Eq. lbm3) from density and velocity fields.

@@ -104,6 +104,80 @@ struct Grid {
     long long N;       // nodes
 };
 
+// BGK collision with Guo forcing (Eq. lbm2, lbm9) of node r = (x, y, z) and
+// push streaming into fout, with halfway bounce-back on wall links (Sec. 3.3)
+// and wrap-around on periodic axes.  F: the force density at the node (the
+// spread field plus any constant body force).  omega = 1/tau, fpref =
+// 1 - 1/(2 tau).  The stored populations are deviations from the rest state.
+// In two parts, so that a caller can issue the loads early: collide_load
+// reads the node's populations, collide_finish does the rest.
+template <int Q, class S>
+__device__ __forceinline__ void collide_load(const typename S::T* __restrict__ fin, long long r, const Grid& g,
+                                             float* h, const S& st) {
+#pragma unroll
+    for (int q = 0; q < Q; q++) h[q] = st.load_stream(fin + (long long)q * g.N + r);
+}
+
+template <int Q, class S>
+__device__ __forceinline__ void collide_finish(const float* h, typename S::T* __restrict__ fout, long long r, int x,
+                                               int y, int z, const Grid& g, float Fx, float Fy, float Fz,
+                                               float omega, float fpref, const S& st) {
+    using L = Lattice<Q>;
+    const long long N = g.N;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        dr += h[q];
+        if (L::ex(q)) jx += L::ex(q) * h[q];
+        if (L::ey(q)) jy += L::ey(q) * h[q];
+        if (L::ez(q)) jz += L::ez(q) * h[q];
+    }
+    const float rho = 1.0f + dr;
+    const float ir = 1.0f / rho;
+    const float ux = (jx + 0.5f * Fx) * ir, uy = (jy + 0.5f * Fy) * ir, uz = (jz + 0.5f * Fz) * ir;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float uF = ux * Fx + uy * Fy + uz * Fz;
+
+    // neighbour offsets with wrap (periodic) or a bounce flag (wall)
+    const long long sx = 1, sy = nx, sz = (long long)nx * ny;
+    const bool xlo = (x == 0), xhi = (x == nx - 1);
+    const bool ylo = (y == 0), yhi = (y == ny - 1);
+    const bool zlo = (z == 0), zhi = (z == nz - 1);
+
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int ex = L::ex(q), ey = L::ey(q), ez = L::ez(q);
+        const float eu = ex * ux + ey * uy + ez * uz;
+        const float eF = ex * Fx + ey * Fy + ez * Fz;
+        const float heq = L::w(q) * (dr + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
+        const float src = fpref * L::w(q) * (3.0f * (eF - uF) + 9.0f * eu * eF);
+        const float hs = h[q] - omega * (h[q] - heq) + src;
+
+        long long dst = r;
+        bool out = false;
+        if (ex > 0) { if (xhi) { if (g.periodic[0]) dst -= (nx - 1) * sx; else out = true; } else dst += sx; }
+        if (ex < 0) { if (xlo) { if (g.periodic[0]) dst += (nx - 1) * sx; else out = true; } else dst -= sx; }
+        if (ey > 0) { if (yhi) { if (g.periodic[1]) dst -= (ny - 1) * sy; else out = true; } else dst += sy; }
+        if (ey < 0) { if (ylo) { if (g.periodic[1]) dst += (ny - 1) * sy; else out = true; } else dst -= sy; }
+        if (ez > 0) { if (zhi) { if (g.periodic[2]) dst -= (long long)(nz - 1) * sz; else out = true; } else dst += sz; }
+        if (ez < 0) { if (zlo) { if (g.periodic[2]) dst += (long long)(nz - 1) * sz; else out = true; } else dst -= sz; }
+        if (out)
+            st.store(fout + (long long)L::opp(q) * N + r, hs);
+        else
+            st.store(fout + (long long)q * N + dst, hs);
+    }
+}
+
+template <int Q, class S>
+__device__ __forceinline__ void collide_node(const typename S::T* __restrict__ fin, typename S::T* __restrict__ fout,
+                                             long long r, int x, int y, int z, const Grid& g, float Fx, float Fy,
+                                             float Fz, float omega, float fpref, const S& st) {
+    float h[Q];
+    collide_load<Q, S>(fin, r, g, h, st);
+    collide_finish<Q, S>(h, fout, r, x, y, z, g, Fx, Fy, Fz, omega, fpref, st);
+}
+
 // Which node rows the particle gather can reach: the cell list's bin starts
 // (start == nullptr: every row), the grid and the binning.
 struct RowMask {

@@ -35,6 +35,8 @@ void particles_interp_from_populations(PBuf& b, int np, const Grid& g, const PCf
                                        int sl2, hipStream_t s);
 void particles_dem(int D, PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t s);
 void particles_spread(int D, PBuf& b, int np, const PCfg& c, const Grid& g, float* F, hipStream_t s);
+void particles_spread_collide(int Q, int fp16, int sl2, const PBuf& b, int np, const PCfg& c, const Grid& g,
+                              const void* fin, void* fout, const float* ff, float tau, hipStream_t s);
 int particles_totals_blocks();
 void particles_totals(int D, PBuf& b, int np, double* part, double* out, hipStream_t s);
 void particles_unpermute(int D, PBuf& b, int np, bool have_forces, float* out, hipStream_t s);
@@ -107,6 +109,9 @@ struct pibm_ctx {
     // particle adjoint stage; PIBM_STAGE_INTERP_T needs those of the last
     // PIBM_STAGE_INTERP
     uint64_t srec_epoch = 0, interp_stage_epoch = ~0ull;
+    // the last step spread its force straight into the collision: the field
+    // in F is recomputed from the spreading records when someone needs it
+    bool F_stale = false;
     // particles handed over in device memory whose validity the device has
     // reported but the host has not read yet: the first step waits for it
     bool device_input_unchecked = false;
@@ -453,6 +458,15 @@ hipError_t clear_spin_history(pibm_ctx* c) {
     return q.e;
 }
 
+// The force field of the last step in F, spread again from the records the
+// step left (the same sums in the same order: bitwise the field the fused
+// collision used).  Before anything that rewrites the records.
+void ensure_force(pibm_ctx* c) {
+    if (!c->F_stale) return;
+    particles_spread(c->D, c->pb, c->np, c->pc, c->grid, c->F, c->stream);
+    c->F_stale = false;
+}
+
 pibm_status sync_and_flags(pibm_ctx* c) {
     pibm_status st = check_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (st) return st;
@@ -619,6 +633,7 @@ pibm_status pibm_read_populations(pibm_ctx* c, float* h) {
 pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, const double* d,
                                const double* rho_p) {
     if (!c) return PIBM_E_ARG;
+    ensure_force(c);
     if (c->np == 0) {
         c->particles_set = true;
         c->srec_epoch++;
@@ -677,6 +692,7 @@ pibm_status pibm_set_particles(pibm_ctx* c, const double* x, const double* v, co
 pibm_status pibm_set_particles_device(pibm_ctx* c, const float* x_hi, const float* x_lo, const float* v,
                                       const float* d, const float* rho_p, double d_max) {
     if (!c) return PIBM_E_ARG;
+    ensure_force(c);
     if (c->np == 0) {
         c->particles_set = true;
         c->srec_epoch++;
@@ -872,6 +888,7 @@ pibm_status pibm_read_fields_device(pibm_ctx* c, float* rho, float* u) {
 
 pibm_status pibm_read_force(pibm_ctx* c, float* F) {
     if (!c || !F) return PIBM_E_ARG;
+    ensure_force(c);
     HipSeq q;
     q(hipMemcpyAsync(F, c->F, sizeof(float) * c->D * c->N, hipMemcpyDeviceToHost, c->stream));
     q(hipStreamSynchronize(c->stream));
@@ -886,6 +903,7 @@ pibm_status pibm_read_force(pibm_ctx* c, float* F) {
 
 pibm_status pibm_read_force_device(pibm_ctx* c, float* F) {
     if (!c || !F) return PIBM_E_ARG;
+    ensure_force(c);
     const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
     lattice_add_const(c->F, F, c->N, c->D, ff, c->stream);
     return check_hip(c, hipGetLastError(), "force launch");
@@ -913,11 +931,17 @@ constexpr uint32_t ONE_GROUP_MAX = 1024;   // one pass per phase: faster than ni
 // One coupled step from populations fin to fout, with the force field in F.
 // Returns the first failure of the enqueued event records and copies (kernel
 // launch errors are read by the caller with hipGetLastError).
-hipError_t launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row) {
+// One coupled step from fin into fout.  want_F: the force field must be
+// written to F (a rollout records it); otherwise 3D spreading with bins of
+// one dual cell and FP32 storage is fused into the collision (with FP16
+// storage the collision is short enough that the fused tile order costs
+// more than the force field's traffic saves).
+hipError_t launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int row, bool want_F) {
     HipSeq q;
     c->srec_epoch++;
     const float ff[3] = {(float)c->cfg.fluid_force[0], (float)c->cfg.fluid_force[1], (float)c->cfg.fluid_force[2]};
     const bool spread = c->np > 0 && c->cfg.two_way;
+    const bool fuse_sc = spread && !want_F && c->D == 3 && c->pc.L == 0 && !c->fp16;
     // D2Q9 interpolation takes the moments straight from the populations of
     // the tiles that hold particles; 3D (15 or 19 planes, a larger halo) and
     // the coarse-bin path read them from a moments pass, which the cell list
@@ -948,10 +972,17 @@ hipError_t launch_step(pibm_ctx* c, const void* fin, void* fout, float* F, int r
     }
     c->steps_done++;
     q(mark(c, row, 4));
-    if (spread) particles_spread(c->D, c->pb, c->np, c->pc, c->grid, F, c->stream);
+    if (spread && !fuse_sc) particles_spread(c->D, c->pb, c->np, c->pc, c->grid, F, c->stream);
     q(mark(c, row, 5));
-    lattice_collide(c->Q, c->fp16, c->sl2, fin, fout, F, spread ? 1 : 0, ff, c->grid, (float)c->cfg.tau,
-                    c->stream);
+    if (fuse_sc) {
+        particles_spread_collide(c->Q, c->fp16, c->sl2, c->pb, c->np, c->pc, c->grid, fin, fout, ff,
+                                 (float)c->cfg.tau, c->stream);
+        if (F == c->F) c->F_stale = true;
+    } else {
+        lattice_collide(c->Q, c->fp16, c->sl2, fin, fout, F, spread ? 1 : 0, ff, c->grid, (float)c->cfg.tau,
+                        c->stream);
+        if (F == c->F) c->F_stale = false;
+    }
     q(mark(c, row, 6));
     return q.e;
 }
@@ -980,7 +1011,7 @@ pibm_status pibm_step(pibm_ctx* c, int32_t n_steps) {
                 if (pibm_status s = drain_events(c)) return s;
             row = c->ev_used++;
         }
-        const hipError_t e = launch_step(c, c->fA, c->fB, c->F, row);
+        const hipError_t e = launch_step(c, c->fA, c->fB, c->F, row, false);
         std::swap(c->fA, c->fB);
         c->stepped = true;
         HIP_TRY(c, e, "step: event record or copy");
@@ -1014,7 +1045,7 @@ pibm_status pibm_forward_ckpt(pibm_ctx* c, int32_t n_steps, int32_t K, void* dev
     HipSeq q;
     for (int t = 0; t < n_steps; t++) {
         if (t % K == 0) q(save_checkpoint(c, t / K));
-        q(launch_step(c, c->fA, c->fB, c->F, -1));
+        q(launch_step(c, c->fA, c->fB, c->F, -1, true));
         std::swap(c->fA, c->fB);
     }
     q(save_checkpoint(c, c->ro.nck - 1));
@@ -1028,6 +1059,7 @@ pibm_status pibm_forward_ckpt(pibm_ctx* c, int32_t n_steps, int32_t K, void* dev
 pibm_status pibm_backward(pibm_ctx* c, const float* dJ_dx_T, const float* dJ_dv_T, float* dJ_dx0, float* dJ_dv0,
                           double* dJ_dtau, double* dJ_dgravity) {
     if (!c) return PIBM_E_ARG;
+    ensure_force(c);
     Rollout& R = c->ro;
     if (!R.valid) return fail(c, PIBM_E_STATE, "no recorded rollout (call pibm_forward_ckpt first)");
     const int D = c->D, np = c->np, Q = c->Q;
@@ -1055,7 +1087,7 @@ pibm_status pibm_backward(pibm_ctx* c, const float* dJ_dx_T, const float* dJ_dv_
         for (int k = 0; k < len; k++) {
             adj_save_state(D, c->pb, np, R.tape_p + k * pf, s);
             void* fout = (k + 1 < len) ? (void*)(R.tape_f + (k + 1) * fbytes) : c->fB;
-            q(launch_step(c, R.tape_f + k * fbytes, fout, R.tape_F + (size_t)k * D * N, -1));
+            q(launch_step(c, R.tape_f + k * fbytes, fout, R.tape_F + (size_t)k * D * N, -1, true));
         }
         // reverse it
         for (int k = len - 1; k >= 0; k--) {
@@ -1096,6 +1128,7 @@ pibm_status pibm_backward(pibm_ctx* c, const float* dJ_dx_T, const float* dJ_dv_
 pibm_status pibm_adjoint_stage(pibm_ctx* c, int32_t stage, const float* in0, const float* in1, const float* in2,
                                float* out0, float* out1, float* out2, double* scalars) {
     if (!c) return PIBM_E_ARG;
+    ensure_force(c);
     Rollout& R = c->ro;
     if (!R.valid) return fail(c, PIBM_E_STATE, "adjoint stages need a recorded rollout (pibm_forward_ckpt)");
     const int D = c->D, np = c->np, Q = c->Q;

@@ -35,10 +35,13 @@ def test_collide_and_moments_bytes_per_node(B, W):
 
 
 def test_measured_traffic_follows_the_kernel_source(B, monkeypatch):
-    # the hash covers the kernel's own function text and the device header
-    for k, (src, name) in B.KERNEL_SOURCES.items():
-        txt = B.kernel_text(src, name)
-        assert f" {name}(" in txt.splitlines()[0] + txt.splitlines()[1] and txt.endswith("}")
+    # the hash covers the kernel's own function text, the device routines
+    # that carry its arithmetic, and the device header
+    for k, parts in B.KERNEL_SOURCES.items():
+        for src, name in parts:
+            txt = B.kernel_text(src, name)
+            assert f" {name}(" in txt.splitlines()[0] + txt.splitlines()[1] and txt.endswith("}")
+    assert B.source_sha("spread") != B.source_sha("spread_collide")
     sha = B.source_sha("collide")
     assert len(sha) == 16 and sha != B.source_sha("moments")
     rec = {"fetch_bytes": 1.0e9, "write_bytes": 2.0e9, "kernel_sha": sha}
