@@ -1435,18 +1435,20 @@ __device__ __forceinline__ void wall_force_md(Active<D>& P, const PCfg& c, float
     }
 }
 
-template <int D>
+// CT: the contact model when known at compile time (-1: read from c).
+template <int D, int CT = -1>
 __device__ __forceinline__ void wall_force(const Active<D>& P, const PCfg& c, float* F) {
+    const int ct = CT < 0 ? c.contact : CT;
     const float rc = 0.5f * P.d;
 #pragma unroll
     for (int a = 0; a < D; a++) {
         // lower wall at 0: overlap = d/2 - X; upper wall at n: d/2 - (n - X)
         float dlo = ((rc - P.xh[a]) - P.xl[a]) - P.dx[a];
         float dhi = ((rc - ((float)c.n[a] - P.xh[a])) + P.xl[a]) + P.dx[a];
-        if (c.contact == PIBM_CONTACT_LSD) {
+        if (ct == PIBM_CONTACT_LSD) {
             if (dlo > 0.f) F[a] += c.kn * dlo - P.gw * P.u[a];
             if (dhi > 0.f) F[a] -= c.kn * dhi + P.gw * P.u[a];
-        } else if (c.contact == PIBM_CONTACT_HERTZ) {
+        } else if (ct == PIBM_CONTACT_HERTZ) {
             if (dlo > 0.f) F[a] += P.gw * dlo * sqrt_fast(dlo);
             if (dhi > 0.f) F[a] -= P.gw * dhi * sqrt_fast(dhi);
         } else {
@@ -1457,9 +1459,10 @@ __device__ __forceinline__ void wall_force(const Active<D>& P, const PCfg& c, fl
     }
 }
 
-template <int D>
+template <int D, int CT = -1>
 __device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& cd, const float* odx,
                                            const float* ou, const PCfg& c, float* F) {
+    const int ct = CT < 0 ? c.contact : CT;
     float del[3] = {0, 0, 0}, r[3] = {0, 0, 0};
     float rd = 0.f, dd = 0.f;
 #pragma unroll
@@ -1477,14 +1480,14 @@ __device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& c
     const float inv = rsq_fast(r2);              // 1 / |r|
     const float dist = r2 * inv;
     const float delta = num * rcp_fast(cd.rc + dist);   // r_c - |r|
-    if (c.contact == PIBM_CONTACT_LSD) {
+    if (ct == PIBM_CONTACT_LSD) {
         float vn = 0.f;
 #pragma unroll
         for (int a = 0; a < D; a++) vn += (P.u[a] - ou[a]) * (r[a] * inv);
         float mag = c.kn * delta - cd.gam * vn;
 #pragma unroll
         for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
-    } else if (c.contact == PIBM_CONTACT_HERTZ) {
+    } else if (ct == PIBM_CONTACT_HERTZ) {
         float mag = cd.gam * delta * sqrt_fast(delta);
 #pragma unroll
         for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
@@ -1595,6 +1598,9 @@ __device__ __forceinline__ CandData cand_at(const CandData* first, int n1, const
 // (sdx, su, and with MD the spins sw) of stride `stride` indexed by the
 // candidate's local index; the first nfirst candidates come from `first`
 // (an LDS copy), the rest from `rest` (global).
+template <int D, bool MD>
+__device__ __forceinline__ void substep_update(Active<D>& P, const PCfg& c, const float* F, const float* tq);
+
 template <int D, bool MD, bool LDS = false>
 __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, const CandData* first, int nfirst,
                                                const CandData* __restrict__ rest, const float* sdx,
@@ -1639,6 +1645,14 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
             pair_force<D>(P, cd, odx, ou, c, F);
         }
     }
+    substep_update<D, MD>(P, c, F, tq);
+}
+
+// The update of one sub-step from the contact force F and torque tq
+// (Eq. demgov, Jacobi): drag from the momentum exchange, buoyant weight,
+// compensated velocity and displacement sums.
+template <int D, bool MD>
+__device__ __forceinline__ void substep_update(Active<D>& P, const PCfg& c, const float* F, const float* tq) {
     if (P.fixed) {
         // a fixed point keeps its state; g = -2 j_i with U = 0, contact reactions summed
 #pragma unroll
@@ -1737,6 +1751,46 @@ __device__ __forceinline__ void active_store(const Active<D>& P, PState& Bn, con
 
 constexpr int CAND_LDS = 8;   // candidates per lane cached in LDS
 
+// The walls' bound on the contact-free sub-steps (remaining if none is
+// near), for a particle moving at most V per unit time.
+template <int D>
+__device__ __forceinline__ float wall_allowance(const Active<D>& P, const PCfg& c, float V, int remaining) {
+    float allow = (float)remaining;
+    const float rc = 0.5f * P.d;
+    if (P.wall) {
+        // (the bounds below carry a 1e-5 margin, far above the reciprocal's rounding)
+        const float iv = rcp_fast(V * c.h) * (1.0f - 1e-5f);
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            float glo = P.dx[a] - ((rc - P.xh[a]) - P.xl[a]);
+            float ghi = -(((rc - ((float)c.n[a] - P.xh[a])) + P.xl[a]) + P.dx[a]);
+            allow = fminf(allow, fminf(glo, ghi) * iv);
+        }
+    }
+    return allow;
+}
+
+// One candidate's bound: the gap closes by at most (V + Vt) h per sub-step,
+// Vt from the partner's speed |ou| and equilibrium speed oveq.
+template <int D>
+__device__ __forceinline__ float cand_allowance(const Active<D>& P, const PCfg& c, const CandData& cd,
+                                                const float* odx, const float* ou, float oveq, float V) {
+    float rd = 0.f, dd = 0.f, r2 = 0.f, ou2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        float del = P.dx[a] - odx[a];
+        float r = cd.r0[a] + del;
+        rd += cd.r0[a] * del;
+        dd += del * del;
+        r2 += r * r;
+        ou2 += ou[a] * ou[a];
+    }
+    float num = cd.K0 - (2.0f * rd + dd);             // r_c^2 - |r|^2
+    float gap = -num * rcp_fast(cd.rc + sqrt_fast(r2));   // |r| - r_c
+    float Vt = fmaxf(sqrt_fast(ou2), oveq) * (1.0f + 1e-5f);
+    return (gap * (1.0f - 2e-5f)) * rcp_fast((V + Vt) * c.h);
+}
+
 // Number of sub-steps (<= remaining) that particle P can advance with no
 // contact: along a contact-free stretch U^{k+i} is a convex combination of
 // U^k and U_eq, so every particle moves at most V = max(|U^k|, |U_eq|) per
@@ -1754,37 +1808,37 @@ __device__ __forceinline__ int free_allowance(const Active<D>& P, const PCfg& c,
         u2 += ut * ut;
     }
     const float V = fmaxf(sqrt_fast(u2), P.veq) * (1.0f + 1e-5f) + 1e-30f;
-    float allow = (float)remaining;
-    const float rc = 0.5f * P.d;
-    if (P.wall) {
-        // (the bounds below carry a 1e-5 margin, far above the reciprocal's rounding)
-        const float iv = rcp_fast(V * c.h) * (1.0f - 1e-5f);
-#pragma unroll
-        for (int a = 0; a < D; a++) {
-            float glo = P.dx[a] - ((rc - P.xh[a]) - P.xl[a]);
-            float ghi = -(((rc - ((float)c.n[a] - P.xh[a])) + P.xl[a]) + P.dx[a]);
-            allow = fminf(allow, fminf(glo, ghi) * iv);
-        }
-    }
+    float allow = wall_allowance<D>(P, c, V, remaining);
     const int n1 = min(P.cnt, nfirst);
     for (int k = 0; k < P.cnt; k++) {
         CandData cd = cand_at<LDS>(first, n1, rest, k);
-        float rd = 0.f, dd = 0.f, r2 = 0.f, ou2 = 0.f;
+        float odx[3], ou[3];
 #pragma unroll
         for (int a = 0; a < D; a++) {
-            float del = P.dx[a] - sdx[a * stride + cd.local];
-            float r = cd.r0[a] + del;
-            rd += cd.r0[a] * del;
-            dd += del * del;
-            r2 += r * r;
-            float uo = su[a * stride + cd.local];
-            ou2 += uo * uo;
+            odx[a] = sdx[a * stride + cd.local];
+            ou[a] = su[a * stride + cd.local];
         }
-        float num = cd.K0 - (2.0f * rd + dd);             // r_c^2 - |r|^2
-        float gap = -num * rcp_fast(cd.rc + sqrt_fast(r2));   // |r| - r_c
-        float Vt = fmaxf(sqrt_fast(ou2), sveq[cd.local]) * (1.0f + 1e-5f);
-        allow = fminf(allow, (gap * (1.0f - 2e-5f)) * rcp_fast((V + Vt) * c.h));
+        allow = fminf(allow, cand_allowance<D>(P, c, cd, odx, ou, sveq[cd.local], V));
     }
+    if (!(allow > 0.f)) return 0;
+    return allow >= (float)remaining ? remaining : (int)allow;
+}
+
+// The same for a particle whose only candidate's state at this sub-step is
+// odx, ou (equilibrium speed oveq).
+template <int D>
+__device__ __forceinline__ int free_allowance_one(const Active<D>& P, const PCfg& c, const CandData& cd,
+                                                  const float* odx, const float* ou, float oveq, int remaining) {
+    if (!(P.hc < 1.0f)) return 0;
+    float u2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        float ut = P.u[a] - P.cu[a];
+        u2 += ut * ut;
+    }
+    const float V = fmaxf(sqrt_fast(u2), P.veq) * (1.0f + 1e-5f) + 1e-30f;
+    float allow = wall_allowance<D>(P, c, V, remaining);
+    allow = fminf(allow, cand_allowance<D>(P, c, cd, odx, ou, oveq, V));
     if (!(allow > 0.f)) return 0;
     return allow >= (float)remaining ? remaining : (int)allow;
 }
@@ -1850,6 +1904,87 @@ __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m, 
 // contact-free stretch (all of its members agree on the shortest allowance)
 // or takes one Jacobi sub-step; so the result of an island does not depend
 // on which other islands share its wave.
+// The value of the other lane of each lane pair (2i, 2i + 1): a DPP
+// quad permutation [1, 0, 3, 2] within the VALU, no LDS.  Every lane of the
+// wave must be active.
+__device__ __forceinline__ float lane_swap(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ int lane_swap(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+
+// All sub-steps of a wave of islands of one (NC = 0: a particle near a wall
+// with no candidate) or of two (NC = 1: lanes 2i, 2i + 1, each member the
+// other's only candidate), for contact model CT.  The partner's state comes
+// by a lane swap, the candidate stays in registers; the decisions and
+// arithmetic are those of the general island loop.
+template <int D, int CT, int NC>
+__device__ __forceinline__ void small_wave(Active<D>& P, const PCfg& c, bool valid, const CandData& cd,
+                                           const MdBuf& md) {
+    if (!valid) P = Active<D>{};      // padding lanes compute on a zero state, never stored
+    const float oveq = NC ? lane_swap(P.veq) : 0.f;
+    int k = 0, backoff = 1, trip = 0;
+    // the partner's state at this sub-step, and the island's allowance for
+    // a contact-free stretch on the check trips
+    auto swap_in = [&](float* odx, float* ou) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            odx[a] = (NC && a < D) ? lane_swap(P.dx[a]) : 0.f;
+            ou[a] = (NC && a < D) ? lane_swap(P.u[a]) : 0.f;
+        }
+    };
+    auto allowance = [&](bool check, const float* odx, const float* ou) {
+        int m = 0;
+        if (__any(check)) {
+            int allow = 0;
+            if (check) {
+                if (NC) allow = free_allowance_one<D>(P, c, cd, odx, ou, oveq, c.n_sub - k);
+                else allow = free_allowance<D>(P, c, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, c.n_sub - k);
+            }
+            const int other = NC ? lane_swap(allow) : allow;
+            m = check ? min(allow, other) : 0;
+        }
+        return m;
+    };
+    auto substep = [&](const float* odx, const float* ou) {
+        float F[3] = {0.f, 0.f, 0.f}, tq[3] = {0.f, 0.f, 0.f};
+        if (P.wall) wall_force<D, CT>(P, c, F);
+        if (NC && P.cnt > 0) pair_force<D, CT>(P, cd, odx, ou, c, F);
+        substep_update<D, false>(P, c, F, tq);
+    };
+    // lockstep: while every island takes a plain sub-step (the lasting-contact
+    // regime), straight-line code for the whole wave, padding lanes included
+    for (; __any(valid && k < c.n_sub); trip++) {
+        float odx[3], ou[3];
+        swap_in(odx, ou);
+        const bool more = valid && k < c.n_sub;
+        const bool check = more && (trip & (backoff - 1)) == 0;
+        const int m = allowance(check, odx, ou);
+        if (__any(more && m >= 2) || !__all(!valid || more)) break;   // this trip again below
+        substep(odx, ou);
+        k += 1;
+        if (check) backoff = min(2 * backoff, 64);
+    }
+    // the rest: jumps and islands that finished early
+    for (; __any(valid && k < c.n_sub); trip++) {
+        float odx[3], ou[3];
+        swap_in(odx, ou);
+        const bool more = valid && k < c.n_sub;
+        const bool check = more && (trip & (backoff - 1)) == 0;
+        const int m = allowance(check, odx, ou);
+        if (more) {
+            if (m >= 2) {
+                active_jump<D, false>(P, c, m, md);
+                k += m;
+                backoff = 1;
+            } else {
+                substep(odx, ou);
+                k += 1;
+                if (check) backoff = min(2 * backoff, 64);
+            }
+        }
+    }
+}
+
 template <int D, bool MD>
 __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np, PCfg c,
                                                      const int* __restrict__ lanemember,
@@ -1902,6 +2037,31 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
         }
         sveq[lane] = valid ? P.veq : 0.f;
         __syncthreads();
+        if (!MD && sz == 1 && __all(!valid || P.cnt == 0)) {
+            // islands of one: particles near a wall with no candidate
+            const CandData cd{};
+            if (c.contact == PIBM_CONTACT_LSD) small_wave<D, PIBM_CONTACT_LSD, 0>(P, c, valid, cd, md);
+            else if (c.contact == PIBM_CONTACT_HERTZ) small_wave<D, PIBM_CONTACT_HERTZ, 0>(P, c, valid, cd, md);
+            else small_wave<D, -1, 0>(P, c, valid, cd, md);
+            if (valid) active_store<D, MD>(P, Bn, c, s, np, srec, fc, flags, md);
+            __syncthreads();
+            continue;
+        }
+        if (!MD && sz == 2 && __all(!valid || (P.cnt == 1 && scd[lane * CAND_LDS].local == (lane ^ 1)))) {
+            // Islands of two, each member the other's only candidate (a
+            // settling suspension in its late phase holds almost only such
+            // pairs in lasting contact): the partner is the neighbouring
+            // lane, its state comes by a lane swap instead of through LDS,
+            // and the candidate stays in registers.  The same decisions and
+            // arithmetic as the general loop below.
+            const CandData cd = valid ? scd[lane * CAND_LDS] : CandData{};
+            if (c.contact == PIBM_CONTACT_LSD) small_wave<D, PIBM_CONTACT_LSD, 1>(P, c, valid, cd, md);
+            else if (c.contact == PIBM_CONTACT_HERTZ) small_wave<D, PIBM_CONTACT_HERTZ, 1>(P, c, valid, cd, md);
+            else small_wave<D, -1, 1>(P, c, valid, cd, md);
+            if (valid) active_store<D, MD>(P, Bn, c, s, np, srec, fc, flags, md);
+            __syncthreads();
+            continue;
+        }
         const CandData* rest = cdata + (valid ? P.off : 0);
         int k = 0, cur = 0;
         // An island checks for a contact-free stretch to jump over on the
