@@ -45,17 +45,16 @@ PROFILE_SAMPLES = 10     # timed steps that record the phase events (evenly spac
 # and the shared device header) hashes to `kernel_sha`: a changed kernel
 # reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("collide", "c1"): {"fetch_bytes": 184657106, "write_bytes": 153742632, "kernel_sha": "3b5a733495964ce5"},
-    ("collide", "c2"): {"fetch_bytes": 1476574203, "write_bytes": 1282894584, "kernel_sha": "3b5a733495964ce5"},
-    ("collide", "c3"): {"fetch_bytes": 838978130, "write_bytes": 645541636, "kernel_sha": "3b5a733495964ce5"},
-    ("interp", "c1"): {"fetch_bytes": 146701708, "write_bytes": 35859633, "kernel_sha": "ec2c21fbd4d1d896"},
-    ("interp", "c2"): {"fetch_bytes": 268623185, "write_bytes": 180321752, "kernel_sha": "ec2c21fbd4d1d896"},
-    ("interp", "c3"): {"fetch_bytes": 268623185, "write_bytes": 180492349, "kernel_sha": "ec2c21fbd4d1d896"},
-    ("moments", "c2"): {"fetch_bytes": 884715750, "write_bytes": 180287632, "kernel_sha": "802e830f6353c655"},
-    ("moments", "c3"): {"fetch_bytes": 365832693, "write_bytes": 136273430, "kernel_sha": "802e830f6353c655"},
-    ("spread", "c1"): {"fetch_bytes": 44515674, "write_bytes": 33539504, "kernel_sha": "d52b0d772beea154"},
-    ("spread", "c2"): {"fetch_bytes": 212372739, "write_bytes": 201237028, "kernel_sha": "d52b0d772beea154"},
-    ("spread", "c3"): {"fetch_bytes": 212372739, "write_bytes": 201271147, "kernel_sha": "d52b0d772beea154"},
+    ("collide", "c1"): {"fetch_bytes": 184657106, "write_bytes": 153742632, "kernel_sha": "bf506ad59f268669"},
+    ("collide", "c3"): {"fetch_bytes": 838978130, "write_bytes": 645541636, "kernel_sha": "bf506ad59f268669"},
+    ("interp", "c1"): {"fetch_bytes": 148067011, "write_bytes": 35859633, "kernel_sha": "84d468f88e27acf5"},
+    ("interp", "c2"): {"fetch_bytes": 268623185, "write_bytes": 180219393, "kernel_sha": "84d468f88e27acf5"},
+    ("interp", "c3"): {"fetch_bytes": 268623185, "write_bytes": 180594708, "kernel_sha": "84d468f88e27acf5"},
+    ("moments", "c2"): {"fetch_bytes": 884715750, "write_bytes": 180287632, "kernel_sha": "619ccdf91a1c3291"},
+    ("moments", "c3"): {"fetch_bytes": 365832693, "write_bytes": 136273430, "kernel_sha": "619ccdf91a1c3291"},
+    ("spread", "c1"): {"fetch_bytes": 44522500, "write_bytes": 33539504, "kernel_sha": "fc94277332352ea7"},
+    ("spread", "c3"): {"fetch_bytes": 212372739, "write_bytes": 201271147, "kernel_sha": "fc94277332352ea7"},
+    ("spread_collide", "c2"): {"fetch_bytes": 1488861922, "write_bytes": 1294836422, "kernel_sha": "f006ea7cdd4c7121"},
 }
 # the source of each measured kernel: its __global__ function and the device
 # routines of its own file that carry its arithmetic (pibm_internal.h, which
