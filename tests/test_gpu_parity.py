@@ -421,6 +421,87 @@ def test_resting_pile_lasting_contacts(P, orc, lat):
     assert ex <= 1e-5 and ev <= 1e-5
 
 
+@pytest.mark.parametrize("contact", ["lsd", "hertz"])
+@pytest.mark.parametrize("lat", [9, 19])
+def test_pairs_and_wall_singles_lasting_contact(P, orc, lat, contact):
+    """Islands of one and two members, the ones the island kernel runs with
+    lane swaps and a lockstep loop: pairs of touching particles stacked on
+    the floor (gravity keeps them in contact), particles resting on the floor, and
+    one pair whose members fly apart (its islands leave the lockstep loop to
+    jump).  40 steps against the oracle: particles within the 1e-5 bound;
+    the fluid within the larger of 1e-5 and the oracle's own change under
+    a 1e-8 relative move of the positions (resting contacts, as in the pile
+    test)."""
+    _flush(f"pairs and wall singles {lat} {contact}")
+    D = 2 if lat == 9 else 3
+    n = (32, 16, 1) if D == 2 else (16, 12, 12)
+    rng = np.random.default_rng(8)
+    pts, vel = [], []
+    for k in range(5):                                    # pairs stacked on the floor
+        base = np.array([3.0 + 2.5 * k, 6.0, 5.0][:D])
+        if D == 3:
+            base[1] = 3.0 + 1.5 * (k % 3)
+        base[D - 1] = 0.2499
+        for i in range(2):
+            p = base.copy()
+            p[D - 1] += 0.4999 * i
+            p[0] += 0.01 * i
+            pts.append(p)
+            vel.append(np.zeros(D))
+    for k in range(4):                                    # resting on the floor
+        p = np.array([4.25 + 2.5 * k, 4.0, 7.0][:D])        # between the pairs
+        p[D - 1] = 0.2499
+        pts.append(p)
+        vel.append(np.zeros(D))
+    p = np.array([10.0, 10.0, 8.0][:D])                   # a pair flying apart
+    for i, sgn in enumerate((-1.0, 1.0)):
+        q = p.copy()
+        q[0] += 0.4999 * i
+        pts.append(q)
+        v = np.zeros(D)
+        v[0] = sgn * 2e-3
+        vel.append(v)
+    X = np.array(pts).T.astype(np.float32).astype(np.float64)
+    U = np.array(vel).T.astype(np.float32).astype(np.float64)
+    npart = X.shape[1]
+    d = np.full(npart, 0.5)
+    rp = np.full(npart, 2.5)
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-4
+    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact=contact, young=1e3)
+    sim = P.Sim(cfg, npart)
+    sim.set_particles(X, U, d, rp)
+    oc = G.oracle_cfg(orc, cfg)
+    h0 = sim.read_populations()
+    f = G.to_oracle_f(orc, lat, h0)
+    Xo, Uo = X.copy(), U.copy()
+    touching = []
+    for k in range(40):
+        out = orc.step(oc, f, Xo, Uo, d, rp)
+        f, Xo, Uo = out["f"], out["X"], out["U"]
+        touching.append(int((np.abs(out["fc"]).max(axis=0) > 0).sum()))
+    sim.step(40)
+    sim.synchronize()
+    got = sim.read_particles()
+    eu, er, eh = G.field_errors(orc, lat, sim.read_populations(), f, sim.N)
+    disp = np.abs(Xo - X).max()
+    ex = np.abs(got["x"] - Xo).max() / disp
+    ev = np.linalg.norm(got["v"] - Uo) / np.linalg.norm(Uo)
+    Xp = X * (1.0 + 1e-8 * np.random.default_rng(2).standard_normal(X.shape))
+    fp, Up = G.to_oracle_f(orc, lat, h0), U.copy()
+    for k in range(40):
+        outp = orc.step(oc, fp, Xp, Up, d, rp)
+        fp, Xp, Up = outp["f"], outp["X"], outp["U"]
+    wq = G.weights(orc, lat)
+    eu_cond = G.field_errors(orc, lat, fp.reshape(-1, sim.N) - wq[:, None], f, sim.N)[0]
+    _flush(f"  40 steps: eps_u={eu:.2e} (oracle's own change {eu_cond:.2e}) eps_rho={er:.2e} dX={ex:.2e} "
+           f"dU={ev:.2e}; particles in contact {touching[::8]}")
+    # lasting contacts (the spring-dashpot pairs settle after a few bounces)
+    assert min(touching[10:]) >= 10 if contact == "hertz" else np.mean(touching[20:]) >= 4
+    assert ex <= 1e-5 and ev <= 1e-5
+    assert eu <= max(1e-5, eu_cond) and er <= 1e-6
+
+
 def test_soft_contact_parity(P, orc):
     _flush("soft contacts")
     n = (32, 32, 1)
