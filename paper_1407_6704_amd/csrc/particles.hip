@@ -1435,68 +1435,95 @@ __device__ __forceinline__ void wall_force_md(Active<D>& P, const PCfg& c, float
     }
 }
 
+// The wall force along one axis on a particle of diameter d (wall
+// coefficient gw) with velocity u along it, from the overlaps dlo with the
+// lower wall at 0 (d/2 - X) and dhi with the upper wall at n (d/2 - (n - X)).
 // CT: the contact model when known at compile time (-1: read from c).
-template <int D, int CT = -1>
-__device__ __forceinline__ void wall_force(const Active<D>& P, const PCfg& c, float* F) {
+template <int CT>
+__device__ __forceinline__ float wall_axis(const PCfg& c, float gw, float d, float dlo, float dhi, float u, float F) {
     const int ct = CT < 0 ? c.contact : CT;
-    const float rc = 0.5f * P.d;
-#pragma unroll
-    for (int a = 0; a < D; a++) {
-        // lower wall at 0: overlap = d/2 - X; upper wall at n: d/2 - (n - X)
-        float dlo = ((rc - P.xh[a]) - P.xl[a]) - P.dx[a];
-        float dhi = ((rc - ((float)c.n[a] - P.xh[a])) + P.xl[a]) + P.dx[a];
-        if (ct == PIBM_CONTACT_LSD) {
-            if (dlo > 0.f) F[a] += c.kn * dlo - P.gw * P.u[a];
-            if (dhi > 0.f) F[a] -= c.kn * dhi + P.gw * P.u[a];
-        } else if (ct == PIBM_CONTACT_HERTZ) {
-            if (dlo > 0.f) F[a] += P.gw * dlo * sqrt_fast(dlo);
-            if (dhi > 0.f) F[a] -= P.gw * dhi * sqrt_fast(dhi);
-        } else {
-            const float irc = rcp_fast(rc);
-            if (dlo > 0.f) { float q = dlo * irc; F[a] += c.ks * q * q; }
-            if (dhi > 0.f) { float q = dhi * irc; F[a] -= c.ks * q * q; }
-        }
+    if (ct == PIBM_CONTACT_LSD) {
+        if (dlo > 0.f) F += c.kn * dlo - gw * u;
+        if (dhi > 0.f) F -= c.kn * dhi + gw * u;
+    } else if (ct == PIBM_CONTACT_HERTZ) {
+        if (dlo > 0.f) F += gw * dlo * sqrt_fast(dlo);
+        if (dhi > 0.f) F -= gw * dhi * sqrt_fast(dhi);
+    } else {
+        const float irc = rcp_fast(0.5f * d);
+        if (dlo > 0.f) { float q = dlo * irc; F += c.ks * q * q; }
+        if (dhi > 0.f) { float q = dhi * irc; F -= c.ks * q * q; }
     }
+    return F;
+}
+
+// The overlap offsets of the lower and upper wall along axis a: the
+// overlaps at displacement dx are elo - dx and ehi + dx.
+template <int D>
+__device__ __forceinline__ void wall_offsets(const Active<D>& P, const PCfg& c, int a, float& elo, float& ehi) {
+    const float rc = 0.5f * P.d;
+    elo = (rc - P.xh[a]) - P.xl[a];
+    ehi = (rc - ((float)c.n[a] - P.xh[a])) + P.xl[a];
 }
 
 template <int D, int CT = -1>
-__device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& cd, const float* odx,
-                                           const float* ou, const PCfg& c, float* F) {
+__device__ __forceinline__ void wall_force(const Active<D>& P, const PCfg& c, float* F) {
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        float elo, ehi;
+        wall_offsets<D>(P, c, a, elo, ehi);
+        F[a] = wall_axis<CT>(c, P.gw, P.d, elo - P.dx[a], ehi + P.dx[a], P.u[a], F[a]);
+    }
+}
+
+// The normal contact force of a pair: del is this particle's displacement
+// in the step minus the candidate's, w (read by the dashpot only) its
+// velocity minus the candidate's.  Out of contact: false.  Otherwise the
+// force on this particle is mag n, n = r inv, r = r0 + del.
+template <int D, int CT>
+__device__ __forceinline__ bool pair_normal(const CandData& cd, const float* del, const float* w, const PCfg& c,
+                                            float* r, float& inv, float& mag) {
     const int ct = CT < 0 ? c.contact : CT;
-    float del[3] = {0, 0, 0}, r[3] = {0, 0, 0};
     float rd = 0.f, dd = 0.f;
 #pragma unroll
     for (int a = 0; a < D; a++) {
-        del[a] = P.dx[a] - odx[a];
         r[a] = cd.r0[a] + del[a];
         rd += cd.r0[a] * del[a];
         dd += del[a] * del[a];
     }
     float num = cd.K0 - (2.0f * rd + dd);        // r_c^2 - |r|^2
-    if (!(num > 0.f)) return;
+    if (!(num > 0.f)) return false;
     float r2 = 0.f;
 #pragma unroll
     for (int a = 0; a < D; a++) r2 += r[a] * r[a];
-    const float inv = rsq_fast(r2);              // 1 / |r|
+    inv = rsq_fast(r2);                          // 1 / |r|
     const float dist = r2 * inv;
     const float delta = num * rcp_fast(cd.rc + dist);   // r_c - |r|
     if (ct == PIBM_CONTACT_LSD) {
         float vn = 0.f;
 #pragma unroll
-        for (int a = 0; a < D; a++) vn += (P.u[a] - ou[a]) * (r[a] * inv);
-        float mag = c.kn * delta - cd.gam * vn;
-#pragma unroll
-        for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
+        for (int a = 0; a < D; a++) vn += w[a] * (r[a] * inv);
+        mag = c.kn * delta - cd.gam * vn;
     } else if (ct == PIBM_CONTACT_HERTZ) {
-        float mag = cd.gam * delta * sqrt_fast(delta);
-#pragma unroll
-        for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
+        mag = cd.gam * delta * sqrt_fast(delta);
     } else {
         float q = delta * rcp_fast(cd.rc);
-        float mag = c.ks * q * q;
-#pragma unroll
-        for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
+        mag = c.ks * q * q;
     }
+    return true;
+}
+
+template <int D, int CT = -1>
+__device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& cd, const float* odx,
+                                           const float* ou, const PCfg& c, float* F) {
+    float del[3] = {0, 0, 0}, w[3] = {0, 0, 0}, r[3], inv, mag;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        del[a] = P.dx[a] - odx[a];
+        w[a] = P.u[a] - ou[a];
+    }
+    if (!pair_normal<D, CT>(cd, del, w, c, r, inv, mag)) return;
+#pragma unroll
+    for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
 }
 
 // Hertz-Mindlin pair contact: Hertz normal force, tangential force T
@@ -1598,7 +1625,7 @@ __device__ __forceinline__ CandData cand_at(const CandData* first, int n1, const
 // (sdx, su, and with MD the spins sw) of stride `stride` indexed by the
 // candidate's local index; the first nfirst candidates come from `first`
 // (an LDS copy), the rest from `rest` (global).
-template <int D, bool MD>
+template <int D, bool MD, bool FIXED = true>
 __device__ __forceinline__ void substep_update(Active<D>& P, const PCfg& c, const float* F, const float* tq);
 
 template <int D, bool MD, bool LDS = false>
@@ -1648,12 +1675,43 @@ __device__ __forceinline__ void active_substep(Active<D>& P, const PCfg& c, cons
     substep_update<D, MD>(P, c, F, tq);
 }
 
-// The update of one sub-step from the contact force F and torque tq
-// (Eq. demgov, Jacobi): drag from the momentum exchange, buoyant weight,
+// One axis of a sub-step (Eq. demgov, Jacobi) from the contact force F
+// along it: drag from the momentum exchange j, buoyant weight (hbw = h bw),
 // compensated velocity and displacement sums.
-template <int D, bool MD>
+template <int D>
+__device__ __forceinline__ void axis_update(const Active<D>& P, const PCfg& c, float F, float j, float hbw, float& u,
+                                            float& cu, float& dx, float& cdx, float& gs, float& fs) {
+#pragma clang fp contract(off)
+    float g = 2.0f * (P.ri * u - j);
+    gs += g;
+    fs += F;
+    float incr = (-P.Ap * g + F) * P.hm + hbw;
+    // compensated sums keep the many tiny increments exact to FP32
+    float y = incr - cu;
+    float t = u + y;
+    cu = (t - u) - y;
+    u = t;
+    float yx = c.h * u - cdx;
+    float tx = dx + yx;
+    cdx = (tx - dx) - yx;
+    dx = tx;
+}
+
+template <int D>
+__device__ __forceinline__ float speed2(const float* u) {
+#pragma clang fp contract(off)
+    float v2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; a++) v2 += u[a] * u[a];
+    return v2;
+}
+
+// The update of one sub-step from the contact force F and torque tq
+// (Eq. demgov, Jacobi).  FIXED = false: no particle is a point of a fixed
+// body.
+template <int D, bool MD, bool FIXED>
 __device__ __forceinline__ void substep_update(Active<D>& P, const PCfg& c, const float* F, const float* tq) {
-    if (P.fixed) {
+    if (FIXED && P.fixed) {
         // a fixed point keeps its state; g = -2 j_i with U = 0, contact reactions summed
 #pragma unroll
         for (int a = 0; a < D; a++) {
@@ -1667,26 +1725,10 @@ __device__ __forceinline__ void substep_update(Active<D>& P, const PCfg& c, cons
 #pragma unroll
         for (int a = (D == 3 ? 0 : 2); a < 3; a++) P.W[a] += tq[a] * P.hI;
     }
-    float v2 = 0.f;
 #pragma unroll
-    for (int a = 0; a < D; a++) {
-#pragma clang fp contract(off)
-        float g = 2.0f * (P.ri * P.u[a] - P.j[a]);
-        P.gs[a] += g;
-        P.fs[a] += F[a];
-        float incr = (-P.Ap * g + F[a]) * P.hm + P.hbw[a];
-        // compensated sums keep the many tiny increments exact to FP32
-        float y = incr - P.cu[a];
-        float t = P.u[a] + y;
-        P.cu[a] = (t - P.u[a]) - y;
-        P.u[a] = t;
-        float yx = c.h * P.u[a] - P.cdx[a];
-        float tx = P.dx[a] + yx;
-        P.cdx[a] = (tx - P.dx[a]) - yx;
-        P.dx[a] = tx;
-        v2 += P.u[a] * P.u[a];
-    }
-    P.vmax2 = fmaxf(P.vmax2, v2);
+    for (int a = 0; a < D; a++)
+        axis_update(P, c, F[a], P.j[a], P.hbw[a], P.u[a], P.cu[a], P.dx[a], P.cdx[a], P.gs[a], P.fs[a]);
+    P.vmax2 = fmaxf(P.vmax2, speed2<D>(P.u));
 }
 
 template <int D, bool MD>
@@ -1904,85 +1946,126 @@ __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m, 
 // contact-free stretch (all of its members agree on the shortest allowance)
 // or takes one Jacobi sub-step; so the result of an island does not depend
 // on which other islands share its wave.
-// The value of the other lane of each lane pair (2i, 2i + 1): a DPP
-// quad permutation [1, 0, 3, 2] within the VALU, no LDS.  Every lane of the
-// wave must be active.
-__device__ __forceinline__ float lane_swap(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+//
+// Islands of one and two without fixed points take the split form below:
+// a wave holds 16 particles, four lanes each.  Lane l updates axis l & 3 of
+// its particle (with D = 2, lanes 2 and 3 repeat axis 1) and holds a copy
+// of the particle's other state; the two members of an island of two sit
+// eight lanes apart in one row of 16 lanes.  Cross-lane reads are DPP moves
+// within the VALU: a broadcast from lane b of the quad, a rotation of the
+// row by 8.  The lanes a move reads from belong to the reading lane's own
+// island, which takes the same branches, so they are active whenever the
+// reader is.
+template <int B>
+__device__ __forceinline__ float quad_get(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), B * 0x55, 0xF, 0xF, false));
 }
-__device__ __forceinline__ int lane_swap(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ float row_swap8(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));
+}
+__device__ __forceinline__ int row_swap8(int v) { return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false); }
 
-// All sub-steps of a wave of islands of one (NC = 0: a particle near a wall
-// with no candidate) or of two (NC = 1: lanes 2i, 2i + 1, each member the
-// other's only candidate), for contact model CT.  The partner's state comes
-// by a lane swap, the candidate stays in registers; the decisions and
-// arithmetic are those of the general island loop.
+// The full vector of a per-axis value (axis b from lane b of the quad).
+template <int D>
+__device__ __forceinline__ void quad_gather(float v, float* out) {
+    out[0] = quad_get<0>(v);
+    out[1] = quad_get<1>(v);
+    if (D == 3) out[2] = quad_get<2>(v);
+}
+
+__device__ __forceinline__ float pick3(const float* v, int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
+
+// All sub-steps of a split wave of islands of one (NC = 0: a particle near
+// a wall with no candidate) or of two (NC = 1: each member the other's only
+// candidate), contact model CT; the partner's state by a row rotation, the
+// candidate in registers.  The decisions and arithmetic are those of the
+// general island loop: every lane of a quad holds the same copy of the
+// particle's scalars and takes the same decisions.
 template <int D, int CT, int NC>
-__device__ __forceinline__ void small_wave(Active<D>& P, const PCfg& c, bool valid, const CandData& cd,
+__device__ __forceinline__ void split_wave(Active<D>& P, const PCfg& c, bool valid, const CandData& cd,
                                            const MdBuf& md) {
-    if (!valid) P = Active<D>{};      // padding lanes compute on a zero state, never stored
-    const float oveq = NC ? lane_swap(P.veq) : 0.f;
-    int k = 0, backoff = 1, trip = 0;
-    // the partner's state at this sub-step, and the island's allowance for
-    // a contact-free stretch on the check trips
-    auto swap_in = [&](float* odx, float* ou) {
+    const int ax = min((int)(threadIdx.x & 3u), D - 1);
+    const int ct = CT < 0 ? c.contact : CT;
+    if (!valid) P = Active<D>{};      // padding lanes: a zero state, never stored
+    const float oveq = NC ? row_swap8(P.veq) : 0.f;
+    // this lane's axis: the running state and the step's constants
+    float u = pick3(P.u, ax), cu = pick3(P.cu, ax), dx = pick3(P.dx, ax), cdx = pick3(P.cdx, ax);
+    float gs = pick3(P.gs, ax), fs = pick3(P.fs, ax);
+    const float j = pick3(P.j, ax), hbw = pick3(P.hbw, ax), r0 = pick3(cd.r0, ax);
+    float elo = 0.f, ehi = 0.f;
+    {
+        float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int a = 0; a < 3; a++) {
-            odx[a] = (NC && a < D) ? lane_swap(P.dx[a]) : 0.f;
-            ou[a] = (NC && a < D) ? lane_swap(P.u[a]) : 0.f;
-        }
-    };
-    auto allowance = [&](bool check, const float* odx, const float* ou) {
+        for (int a = 0; a < D; a++) wall_offsets<D>(P, c, a, lo[a], hi[a]);
+        elo = pick3(lo, ax);
+        ehi = pick3(hi, ax);
+    }
+    int k = 0, backoff = 1;
+    for (int trip = 0; __any(valid && k < c.n_sub); trip++) {
+        const bool more = valid && k < c.n_sub;
+        const bool check = more && (trip & (backoff - 1)) == 0;
         int m = 0;
         if (__any(check)) {
+            // the full vectors of this particle and of its partner
+            quad_gather<D>(u, P.u);
+            quad_gather<D>(cu, P.cu);
+            quad_gather<D>(dx, P.dx);
+            float odx[3] = {0.f, 0.f, 0.f}, ou[3] = {0.f, 0.f, 0.f};
+            if (NC) {
+#pragma unroll
+                for (int a = 0; a < D; a++) {
+                    odx[a] = row_swap8(P.dx[a]);
+                    ou[a] = row_swap8(P.u[a]);
+                }
+            }
             int allow = 0;
             if (check) {
                 if (NC) allow = free_allowance_one<D>(P, c, cd, odx, ou, oveq, c.n_sub - k);
                 else allow = free_allowance<D>(P, c, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, c.n_sub - k);
             }
-            const int other = NC ? lane_swap(allow) : allow;
+            const int other = NC ? row_swap8(allow) : allow;
             m = check ? min(allow, other) : 0;
         }
-        return m;
-    };
-    auto substep = [&](const float* odx, const float* ou) {
-        float F[3] = {0.f, 0.f, 0.f}, tq[3] = {0.f, 0.f, 0.f};
-        if (P.wall) wall_force<D, CT>(P, c, F);
-        if (NC && P.cnt > 0) pair_force<D, CT>(P, cd, odx, ou, c, F);
-        substep_update<D, false>(P, c, F, tq);
-    };
-    // lockstep: while every island takes a plain sub-step (the lasting-contact
-    // regime), straight-line code for the whole wave, padding lanes included
-    for (; __any(valid && k < c.n_sub); trip++) {
-        float odx[3], ou[3];
-        swap_in(odx, ou);
-        const bool more = valid && k < c.n_sub;
-        const bool check = more && (trip & (backoff - 1)) == 0;
-        const int m = allowance(check, odx, ou);
-        if (__any(more && m >= 2) || !__all(!valid || more)) break;   // this trip again below
-        substep(odx, ou);
-        k += 1;
-        if (check) backoff = min(2 * backoff, 64);
-    }
-    // the rest: jumps and islands that finished early
-    for (; __any(valid && k < c.n_sub); trip++) {
-        float odx[3], ou[3];
-        swap_in(odx, ou);
-        const bool more = valid && k < c.n_sub;
-        const bool check = more && (trip & (backoff - 1)) == 0;
-        const int m = allowance(check, odx, ou);
         if (more) {
             if (m >= 2) {
+                // (u, cu, dx are current in P from the check of this trip)
+                quad_gather<D>(cdx, P.cdx);
+                quad_gather<D>(gs, P.gs);
                 active_jump<D, false>(P, c, m, md);
+                u = pick3(P.u, ax);
+                cu = pick3(P.cu, ax);
+                dx = pick3(P.dx, ax);
+                cdx = pick3(P.cdx, ax);
+                gs = pick3(P.gs, ax);
                 k += m;
                 backoff = 1;
             } else {
-                substep(odx, ou);
+                float F = 0.f;
+                if (P.wall) F = wall_axis<CT>(c, P.gw, P.d, elo - dx, ehi + dx, u, F);
+                if (NC && P.cnt > 0) {
+                    // the relative displacement and velocity, axis by axis
+                    // (this lane's component of r = r0 + del is r0 + its own del)
+                    float del[3] = {0.f, 0.f, 0.f}, w[3] = {0.f, 0.f, 0.f}, r[3], inv, mag;
+                    const float dl = dx - row_swap8(dx);
+                    quad_gather<D>(dl, del);
+                    if (ct == PIBM_CONTACT_LSD) quad_gather<D>(u - row_swap8(u), w);
+                    if (pair_normal<D, CT>(cd, del, w, c, r, inv, mag)) F += mag * ((r0 + dl) * inv);
+                }
+                axis_update<D>(P, c, F, j, hbw, u, cu, dx, cdx, gs, fs);
+                float uv[3] = {0.f, 0.f, 0.f};
+                quad_gather<D>(u, uv);
+                P.vmax2 = fmaxf(P.vmax2, speed2<D>(uv));
                 k += 1;
                 if (check) backoff = min(2 * backoff, 64);
             }
         }
     }
+    quad_gather<D>(u, P.u);
+    quad_gather<D>(cu, P.cu);
+    quad_gather<D>(dx, P.dx);
+    quad_gather<D>(cdx, P.cdx);
+    quad_gather<D>(gs, P.gs);
+    quad_gather<D>(fs, P.fs);
 }
 
 template <int D, bool MD>
@@ -2008,7 +2091,14 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
     const int lane = threadIdx.x;
     // first wave of size class lane + 1 (non-decreasing in the class)
     const uint32_t wb_lane = counters[CNT_WAVEBASE + 1 + lane];
-    for (uint32_t w = blockIdx.x; w < nw; w += gridDim.x) {
+    // Without Mindlin, each packed wave is worked by QUARTERS workgroups:
+    // quarter q takes the islands of one or two at its lanes
+    // [16 q, 16 q + 16) in the split form (or in the general loop below,
+    // restricted to those lanes, when one of them does not qualify); a wave
+    // of larger islands is worked by quarter 0 alone.
+    constexpr uint32_t QUARTERS = MD ? 1u : 4u;
+    for (uint32_t v = blockIdx.x; v < nw * QUARTERS; v += gridDim.x) {
+        const uint32_t w = v / QUARTERS, part = v % QUARTERS;
         // the wave's size class is the largest whose first wave is <= w;
         // its islands fill lanes [0, islands_here * size)
         const unsigned long long le = __ballot(wb_lane <= w);
@@ -2017,7 +2107,38 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
         const uint32_t nisl = counters[CNT_CLASS + sz];
         const uint32_t idx = w - counters[CNT_WAVEBASE + sz];
         const uint32_t here = min(per, nisl - idx * per);
-        bool valid = (uint32_t)lane < here * (uint32_t)sz;
+        const bool quartered = !MD && sz <= 2;
+        if (!quartered && part != 0) continue;
+        if (quartered) {
+            // the split form: original lane ol of this quarter for each group of four lanes
+            const int ol = (int)part * 16 +
+                           (sz == 2 ? (((lane >> 4) << 2) | (((lane >> 2) & 1) << 1) | ((lane >> 3) & 1)) : (lane >> 2));
+            const bool sv = (uint32_t)ol < here * (uint32_t)sz;
+            const uint32_t ss = sv ? alist[lanemember[(long long)w * WAVE + ol]] : 0;
+            Active<D> P;
+            CandData cd{};
+            if (sv) {
+                active_load<D, MD>(P, A, c, ss, drho_i, j_i, np, ccount, prefix, md);
+                if (sz == 2 && P.cnt > 0) cd = cdata[P.off];
+            }
+            const bool ok = sv && (sz == 1 ? (P.cnt == 0 && !P.fixed)
+                                           : (P.cnt == 1 && !P.fixed && cd.local == (ol ^ 1)));
+            if (__all(!sv || ok)) {
+                if (sz == 1) {
+                    if (c.contact == PIBM_CONTACT_LSD) split_wave<D, PIBM_CONTACT_LSD, 0>(P, c, sv, cd, md);
+                    else if (c.contact == PIBM_CONTACT_HERTZ) split_wave<D, PIBM_CONTACT_HERTZ, 0>(P, c, sv, cd, md);
+                    else split_wave<D, -1, 0>(P, c, sv, cd, md);
+                } else {
+                    if (c.contact == PIBM_CONTACT_LSD) split_wave<D, PIBM_CONTACT_LSD, 1>(P, c, sv, cd, md);
+                    else if (c.contact == PIBM_CONTACT_HERTZ) split_wave<D, PIBM_CONTACT_HERTZ, 1>(P, c, sv, cd, md);
+                    else split_wave<D, -1, 1>(P, c, sv, cd, md);
+                }
+                if (sv && (lane & 3) == 0) active_store<D, MD>(P, Bn, c, ss, np, srec, fc, flags, md);
+                continue;
+            }
+        }
+        // the general loop: the whole wave, or this quarter's lanes of it
+        bool valid = (uint32_t)lane < here * (uint32_t)sz && (!quartered || (uint32_t)(lane >> 4) == part);
         int a = valid ? lanemember[(long long)w * WAVE + lane] : -1;
         uint32_t s = valid ? alist[a] : 0;
         Active<D> P;
@@ -2037,31 +2158,6 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
         }
         sveq[lane] = valid ? P.veq : 0.f;
         __syncthreads();
-        if (!MD && sz == 1 && __all(!valid || P.cnt == 0)) {
-            // islands of one: particles near a wall with no candidate
-            const CandData cd{};
-            if (c.contact == PIBM_CONTACT_LSD) small_wave<D, PIBM_CONTACT_LSD, 0>(P, c, valid, cd, md);
-            else if (c.contact == PIBM_CONTACT_HERTZ) small_wave<D, PIBM_CONTACT_HERTZ, 0>(P, c, valid, cd, md);
-            else small_wave<D, -1, 0>(P, c, valid, cd, md);
-            if (valid) active_store<D, MD>(P, Bn, c, s, np, srec, fc, flags, md);
-            __syncthreads();
-            continue;
-        }
-        if (!MD && sz == 2 && __all(!valid || (P.cnt == 1 && scd[lane * CAND_LDS].local == (lane ^ 1)))) {
-            // Islands of two, each member the other's only candidate (a
-            // settling suspension in its late phase holds almost only such
-            // pairs in lasting contact): the partner is the neighbouring
-            // lane, its state comes by a lane swap instead of through LDS,
-            // and the candidate stays in registers.  The same decisions and
-            // arithmetic as the general loop below.
-            const CandData cd = valid ? scd[lane * CAND_LDS] : CandData{};
-            if (c.contact == PIBM_CONTACT_LSD) small_wave<D, PIBM_CONTACT_LSD, 1>(P, c, valid, cd, md);
-            else if (c.contact == PIBM_CONTACT_HERTZ) small_wave<D, PIBM_CONTACT_HERTZ, 1>(P, c, valid, cd, md);
-            else small_wave<D, -1, 1>(P, c, valid, cd, md);
-            if (valid) active_store<D, MD>(P, Bn, c, s, np, srec, fc, flags, md);
-            __syncthreads();
-            continue;
-        }
         const CandData* rest = cdata + (valid ? P.off : 0);
         int k = 0, cur = 0;
         // An island checks for a contact-free stretch to jump over on the
@@ -2820,7 +2916,9 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
         hipLaunchKernelGGL(k_cand_prep<D>, dim3(grid_act), dim3(256), 0, s, b.A, c, b.alist, b.ccount, b.prefix, b.cand,
                            b.aidx, b.loc, b.cdata, md, b.counters);
     }
+    // (a workgroup per packed wave, four per wave of islands of one or two without Mindlin)
     const dim3 gsmall(std::max<unsigned>(grid_act * 4, 256u));
+    const dim3 gsplit(4 * gsmall.x);
     if (c.contact >= PIBM_CONTACT_HERTZ_MINDLIN) {
         hipLaunchKernelGGL((k_island_small<D, true>), gsmall, dim3(64), 0, s, b.A, b.Bn, np, c, b.lanemember, b.alist,
                            b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.srec, b.fc, b.flags,
@@ -2829,7 +2927,7 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
                            b.bigoff, b.bigroot, b.isize, b.alist, b.ccount, b.prefix, b.cdata, b.drho_i, b.j_i,
                            b.srec, b.fc, b.gdx, b.gu, (long long)np, b.flags, b.counters, md);
     } else {
-        hipLaunchKernelGGL((k_island_small<D, false>), gsmall, dim3(64), 0, s, b.A, b.Bn, np, c, b.lanemember, b.alist,
+        hipLaunchKernelGGL((k_island_small<D, false>), gsplit, dim3(64), 0, s, b.A, b.Bn, np, c, b.lanemember, b.alist,
                            b.ccount, b.prefix, b.parent, b.isize, b.cdata, b.drho_i, b.j_i, b.srec, b.fc, b.flags,
                            b.counters, md);
         hipLaunchKernelGGL((k_island_big<D, false>), dim3(256), dim3(256), 0, s, b.A, b.Bn, np, c, b.bigmember,
