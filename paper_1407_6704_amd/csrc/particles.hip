@@ -1478,8 +1478,9 @@ __device__ __forceinline__ void wall_force(const Active<D>& P, const PCfg& c, fl
 // The normal contact force of a pair: del is this particle's displacement
 // in the step minus the candidate's, w (read by the dashpot only) its
 // velocity minus the candidate's.  Out of contact: false.  Otherwise the
-// force on this particle is mag n, n = r inv, r = r0 + del.
-template <int D, int CT>
+// force on this particle is mag n, n = r inv, r = r0 + del.  FLAT: no
+// early return (mag is then meaningless out of contact).
+template <int D, int CT, bool FLAT = false>
 __device__ __forceinline__ bool pair_normal(const CandData& cd, const float* del, const float* w, const PCfg& c,
                                             float* r, float& inv, float& mag) {
     const int ct = CT < 0 ? c.contact : CT;
@@ -1491,7 +1492,7 @@ __device__ __forceinline__ bool pair_normal(const CandData& cd, const float* del
         dd += del[a] * del[a];
     }
     float num = cd.K0 - (2.0f * rd + dd);        // r_c^2 - |r|^2
-    if (!(num > 0.f)) return false;
+    if (!FLAT && !(num > 0.f)) return false;
     float r2 = 0.f;
 #pragma unroll
     for (int a = 0; a < D; a++) r2 += r[a] * r[a];
@@ -1509,7 +1510,7 @@ __device__ __forceinline__ bool pair_normal(const CandData& cd, const float* del
         float q = delta * rcp_fast(cd.rc);
         mag = c.ks * q * q;
     }
-    return true;
+    return num > 0.f;
 }
 
 template <int D, int CT = -1>
@@ -2007,28 +2008,31 @@ __device__ __forceinline__ void split_wave(Active<D>& P, const PCfg& c, bool val
         int m = 0;
         if (__any(check)) {
             // the full vectors of this particle and of its partner
-            quad_gather<D>(u, P.u);
-            quad_gather<D>(cu, P.cu);
-            quad_gather<D>(dx, P.dx);
+            Active<D> Q = P;
+            quad_gather<D>(u, Q.u);
+            quad_gather<D>(cu, Q.cu);
+            quad_gather<D>(dx, Q.dx);
             float odx[3] = {0.f, 0.f, 0.f}, ou[3] = {0.f, 0.f, 0.f};
             if (NC) {
 #pragma unroll
                 for (int a = 0; a < D; a++) {
-                    odx[a] = row_swap8(P.dx[a]);
-                    ou[a] = row_swap8(P.u[a]);
+                    odx[a] = row_swap8(Q.dx[a]);
+                    ou[a] = row_swap8(Q.u[a]);
                 }
             }
             int allow = 0;
             if (check) {
-                if (NC) allow = free_allowance_one<D>(P, c, cd, odx, ou, oveq, c.n_sub - k);
-                else allow = free_allowance<D>(P, c, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, c.n_sub - k);
+                if (NC) allow = free_allowance_one<D>(Q, c, cd, odx, ou, oveq, c.n_sub - k);
+                else allow = free_allowance<D>(Q, c, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, c.n_sub - k);
             }
             const int other = NC ? row_swap8(allow) : allow;
             m = check ? min(allow, other) : 0;
         }
-        if (more) {
-            if (m >= 2) {
-                // (u, cu, dx are current in P from the check of this trip)
+        if (__any(more && m >= 2)) {
+            if (more && m >= 2) {
+                quad_gather<D>(u, P.u);
+                quad_gather<D>(cu, P.cu);
+                quad_gather<D>(dx, P.dx);
                 quad_gather<D>(cdx, P.cdx);
                 quad_gather<D>(gs, P.gs);
                 active_jump<D, false>(P, c, m, md);
@@ -2039,26 +2043,38 @@ __device__ __forceinline__ void split_wave(Active<D>& P, const PCfg& c, bool val
                 gs = pick3(P.gs, ax);
                 k += m;
                 backoff = 1;
-            } else {
-                float F = 0.f;
-                if (P.wall) F = wall_axis<CT>(c, P.gw, P.d, elo - dx, ehi + dx, u, F);
-                if (NC && P.cnt > 0) {
-                    // the relative displacement and velocity, axis by axis
-                    // (this lane's component of r = r0 + del is r0 + its own del)
-                    float del[3] = {0.f, 0.f, 0.f}, w[3] = {0.f, 0.f, 0.f}, r[3], inv, mag;
-                    const float dl = dx - row_swap8(dx);
-                    quad_gather<D>(dl, del);
-                    if (ct == PIBM_CONTACT_LSD) quad_gather<D>(u - row_swap8(u), w);
-                    if (pair_normal<D, CT>(cd, del, w, c, r, inv, mag)) F += mag * ((r0 + dl) * inv);
-                }
-                axis_update<D>(P, c, F, j, hbw, u, cu, dx, cdx, gs, fs);
-                float uv[3] = {0.f, 0.f, 0.f};
-                quad_gather<D>(u, uv);
-                P.vmax2 = fmaxf(P.vmax2, speed2<D>(uv));
-                k += 1;
-                if (check) backoff = min(2 * backoff, 64);
             }
         }
+        // a sub-step, computed on every lane and kept where the island takes one
+        const bool step = more && m < 2;
+        float F = 0.f;
+        if (P.wall) F = wall_axis<CT>(c, P.gw, P.d, elo - dx, ehi + dx, u, F);
+        if (NC) {
+            // (every member of a split pair wave has its partner as only candidate)
+            // the relative displacement and velocity, axis by axis
+            // (this lane's component of r = r0 + del is r0 + its own del)
+            float del[3] = {0.f, 0.f, 0.f}, w[3] = {0.f, 0.f, 0.f}, r[3], inv, mag;
+            const float dl = dx - row_swap8(dx);
+            quad_gather<D>(dl, del);
+            if (ct == PIBM_CONTACT_LSD) quad_gather<D>(u - row_swap8(u), w);
+            const bool on = pair_normal<D, CT, true>(cd, del, w, c, r, inv, mag);
+            const float Fp = F + mag * ((r0 + dl) * inv);
+            F = on ? Fp : F;
+        }
+        float u1 = u, cu1 = cu, dx1 = dx, cdx1 = cdx, gs1 = gs, fs1 = fs;
+        axis_update<D>(P, c, F, j, hbw, u1, cu1, dx1, cdx1, gs1, fs1);
+        float uv[3] = {0.f, 0.f, 0.f};
+        quad_gather<D>(u1, uv);
+        const float vm = fmaxf(P.vmax2, speed2<D>(uv));
+        u = step ? u1 : u;
+        cu = step ? cu1 : cu;
+        dx = step ? dx1 : dx;
+        cdx = step ? cdx1 : cdx;
+        gs = step ? gs1 : gs;
+        fs = step ? fs1 : fs;
+        P.vmax2 = step ? vm : P.vmax2;
+        k += step ? 1 : 0;
+        if (step && check) backoff = min(2 * backoff, 64);
     }
     quad_gather<D>(u, P.u);
     quad_gather<D>(cu, P.cu);
