@@ -897,17 +897,50 @@ __device__ __forceinline__ void wave_plan(const uint32_t* cls, uint32_t* wb) {
     }
 }
 
+// An island of two (root a) whose members touch at the start of the step,
+// or would close their gap within the step at their present speeds: such a
+// pair is likely to be in contact for most of the step, and so to take
+// every sub-step.  These pairs are ranked apart (rank | TOUCH_BIT) and
+// packed into the first waves of the class, so that they fill few waves;
+// the pairs that can jump fill the rest.  (Only the packing depends on this
+// test: an island's result does not depend on its wave.)
+constexpr uint32_t TOUCH_BIT = 0x80000000u;
+template <int D>
+__device__ __forceinline__ bool pair_touching(uint32_t a, const PState& A, const uint32_t* __restrict__ alist,
+                                              const uint32_t* __restrict__ ccount,
+                                              const unsigned long long* __restrict__ prefix,
+                                              const uint32_t* __restrict__ cand) {
+    const uint32_t s = alist[a];
+    if (ccount[s] == 0) return false;
+    const uint32_t t = cand[(uint32_t)(prefix[s] & 0xffffffffULL)];
+    float r2 = 0.f, us = 0.f, ut = 0.f;
+#pragma unroll
+    for (int ax = 0; ax < D; ax++) {
+        const float e = (A.xh[ax][s] - A.xh[ax][t]) + (A.xl[ax][s] - A.xl[ax][t]);
+        r2 += e * e;
+        us += A.u[ax][s] * A.u[ax][s];
+        ut += A.u[ax][t] * A.u[ax][t];
+    }
+    const float reach = 0.5f * (A.d[s] + A.d[t]) + sqrtf(us) + sqrtf(ut);
+    return r2 < reach * reach;
+}
+
 // islands by size class: 1..64 packed into waves, 65 = larger than a wave
 // (ranks within a class are counted in LDS per chunk of 256 and reserved
 // with one global atomic per class and chunk: no contended counter)
-__global__ __launch_bounds__(256) void k_island_class(const uint32_t* __restrict__ parent,
+template <int D>
+__global__ __launch_bounds__(256) void k_island_class(PState A, const uint32_t* __restrict__ alist,
+                                                      const uint32_t* __restrict__ ccount,
+                                                      const unsigned long long* __restrict__ prefix,
+                                                      const uint32_t* __restrict__ cand,
+                                                      const uint32_t* __restrict__ parent,
                                                       const uint32_t* __restrict__ isize, uint32_t* __restrict__ irank,
                                                       uint32_t* __restrict__ bigroot, uint32_t* counters) {
-    __shared__ uint32_t lc[WAVE + 2], gbase[WAVE + 2];
+    __shared__ uint32_t lc[WAVE + 3], gbase[WAVE + 3];     // [WAVE + 2]: touching pairs
     const uint32_t t = threadIdx.x;
     const uint32_t na = counters[CNT_ACTIVE];
     for (uint32_t c0 = blockIdx.x * 256; c0 < na; c0 += gridDim.x * 256) {
-        if (t < WAVE + 2) lc[t] = 0;
+        if (t < WAVE + 3) lc[t] = 0;
         __syncthreads();
         const uint32_t a = c0 + t;
         uint32_t cls = 0, lr = 0;
@@ -915,14 +948,16 @@ __global__ __launch_bounds__(256) void k_island_class(const uint32_t* __restrict
         if (root) {
             const uint32_t sz = isize[a];
             cls = sz <= WAVE ? sz : WAVE + 1;
+            if (cls == 2 && pair_touching<D>(a, A, alist, ccount, prefix, cand)) cls = WAVE + 2;
             lr = atomicAdd(&lc[cls], 1u);
         }
         __syncthreads();
         if (t < WAVE + 2 && lc[t] > 0) gbase[t] = atomicAdd(&counters[CNT_CLASS + t], lc[t]);
+        if (t == WAVE + 2 && lc[t] > 0) gbase[t] = atomicAdd(&counters[CNT_PAIRC], lc[t]);
         __syncthreads();
         if (root) {
             const uint32_t r = gbase[cls] + lr;
-            irank[a] = r;
+            irank[a] = cls == WAVE + 2 ? (r | TOUCH_BIT) : r;
             if (cls == WAVE + 1) bigroot[r] = a;
         }
         __syncthreads();
@@ -938,14 +973,18 @@ __device__ __forceinline__ void island_place_one(uint32_t a, const uint32_t* __r
                                                  const uint32_t* __restrict__ irank, uint32_t* __restrict__ fill,
                                                  int* __restrict__ lanemember, uint32_t* __restrict__ loc,
                                                  const uint32_t* __restrict__ bigoff,
-                                                 uint32_t* __restrict__ bigmember, const uint32_t* wavebase) {
+                                                 uint32_t* __restrict__ bigmember, const uint32_t* wavebase,
+                                                 uint32_t ntouch) {
     uint32_t r = parent[a];
     uint32_t pos = atomicAdd(&fill[r], 1u);
     uint32_t sz = isize[r];
     if (sz <= WAVE) {
+        // islands of two: the ntouch touching pairs first
+        uint32_t ir = irank[r];
+        if (sz == 2) ir = (ir & TOUCH_BIT) ? (ir & ~TOUCH_BIT) : ir + ntouch;
         uint32_t per = WAVE / sz;
-        uint32_t w = wavebase[sz] + irank[r] / per;
-        uint32_t lane = (irank[r] % per) * sz + pos;
+        uint32_t w = wavebase[sz] + ir / per;
+        uint32_t lane = (ir % per) * sz + pos;
         lanemember[(long long)w * WAVE + lane] = (int)a;
         loc[a] = lane;
     } else {
@@ -967,7 +1006,11 @@ __global__ __launch_bounds__(256) void k_island_place(const uint32_t* __restrict
                                                       uint32_t* __restrict__ counters) {
     __shared__ uint32_t wb[WAVE + 1];
     __shared__ uint32_t scan4[4];
-    wave_plan(counters + CNT_CLASS, wb);
+    __shared__ uint32_t cls[WAVE + 1];
+    const uint32_t ntouch = counters[CNT_PAIRC];
+    if (threadIdx.x <= WAVE) cls[threadIdx.x] = counters[CNT_CLASS + threadIdx.x] + (threadIdx.x == 2 ? ntouch : 0u);
+    __syncthreads();
+    wave_plan(cls, wb);
     const uint32_t nbig = counters[CNT_CLASS + WAVE + 1];
     uint32_t run = 0;
     for (uint32_t k0 = 0; k0 < nbig; k0 += 256) {
@@ -986,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_island_place(const uint32_t* __restrict
     }
     const uint32_t na = counters[CNT_ACTIVE];
     for (uint32_t a = blockIdx.x * 256 + threadIdx.x; a < na; a += gridDim.x * 256)
-        island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, wb);
+        island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, wb, ntouch);
 }
 
 // Candidate constants for the sub-steps.  K0 = r_c^2 - |r0|^2 is formed in
@@ -1106,12 +1149,12 @@ __global__ __launch_bounds__(SETUP_THREADS) void k_island_setup(
     const uint32_t* __restrict__ aidx, uint32_t* parent, uint32_t* isize, uint32_t* irank, uint32_t* fill,
     int* lanemember, uint32_t* loc, uint32_t* bigroot, uint32_t* bigoff, uint32_t* bigmember, CandData* cdata, MdBuf md,
     uint32_t* counters, long long lane_cap) {
-    __shared__ uint32_t ccls[WAVE + 2];
+    __shared__ uint32_t ccls[WAVE + 3];     // [WAVE + 2]: touching pairs
     __shared__ uint32_t wbase[WAVE + 1];
     __shared__ uint32_t nwaves;
     const uint32_t t = threadIdx.x;
     const uint32_t na = counters[CNT_ACTIVE];
-    if (t < WAVE + 2) ccls[t] = 0;
+    if (t < WAVE + 3) ccls[t] = 0;
     __syncthreads();
     for (uint32_t a = t; a < na; a += SETUP_THREADS) uf_hook_one(a, alist, ccount, prefix, cand, aidx, parent);
     __syncthreads();
@@ -1125,10 +1168,14 @@ __global__ __launch_bounds__(SETUP_THREADS) void k_island_setup(
         if (parent[a] != a) continue;
         uint32_t sz = isize[a];
         uint32_t cls = sz <= WAVE ? sz : WAVE + 1;
+        if (cls == 2 && pair_touching<D>(a, A, alist, ccount, prefix, cand)) cls = WAVE + 2;
         uint32_t r = atomicAdd(&ccls[cls], 1u);
-        irank[a] = r;
+        irank[a] = cls == WAVE + 2 ? (r | TOUCH_BIT) : r;
         if (cls == WAVE + 1) bigroot[r] = a;
     }
+    __syncthreads();
+    const uint32_t ntouch = ccls[WAVE + 2];
+    if (t == 0) ccls[2] += ntouch;
     __syncthreads();
     wave_plan(ccls, wbase);
     __syncthreads();
@@ -1150,7 +1197,7 @@ __global__ __launch_bounds__(SETUP_THREADS) void k_island_setup(
     }
     __syncthreads();
     for (uint32_t a = t; a < na; a += SETUP_THREADS)
-        island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, wbase);
+        island_place_one(a, parent, isize, irank, fill, lanemember, loc, bigoff, bigmember, wbase, ntouch);
     __syncthreads();
     for (uint32_t a = t; a < na; a += SETUP_THREADS)
         cand_prep_one<D>(a, A, c, alist, ccount, prefix, cand, aidx, loc, cdata, md);
@@ -1957,6 +2004,8 @@ __device__ __forceinline__ void active_jump(Active<D>& P, const PCfg& c, int m, 
 // row by 8.  The lanes a move reads from belong to the reading lane's own
 // island, which takes the same branches, so they are active whenever the
 // reader is.
+extern "C" __device__ int __ockl_wfred_min_i32(int);   // minimum over the wave's active lanes
+
 template <int B>
 __device__ __forceinline__ float quad_get(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), B * 0x55, 0xF, 0xF, false));
@@ -2001,52 +2050,8 @@ __device__ __forceinline__ void split_wave(Active<D>& P, const PCfg& c, bool val
         elo = pick3(lo, ax);
         ehi = pick3(hi, ax);
     }
-    int k = 0, backoff = 1;
-    for (int trip = 0; __any(valid && k < c.n_sub); trip++) {
-        const bool more = valid && k < c.n_sub;
-        const bool check = more && (trip & (backoff - 1)) == 0;
-        int m = 0;
-        if (__any(check)) {
-            // the full vectors of this particle and of its partner
-            Active<D> Q = P;
-            quad_gather<D>(u, Q.u);
-            quad_gather<D>(cu, Q.cu);
-            quad_gather<D>(dx, Q.dx);
-            float odx[3] = {0.f, 0.f, 0.f}, ou[3] = {0.f, 0.f, 0.f};
-            if (NC) {
-#pragma unroll
-                for (int a = 0; a < D; a++) {
-                    odx[a] = row_swap8(Q.dx[a]);
-                    ou[a] = row_swap8(Q.u[a]);
-                }
-            }
-            int allow = 0;
-            if (check) {
-                if (NC) allow = free_allowance_one<D>(Q, c, cd, odx, ou, oveq, c.n_sub - k);
-                else allow = free_allowance<D>(Q, c, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, c.n_sub - k);
-            }
-            const int other = NC ? row_swap8(allow) : allow;
-            m = check ? min(allow, other) : 0;
-        }
-        if (__any(more && m >= 2)) {
-            if (more && m >= 2) {
-                quad_gather<D>(u, P.u);
-                quad_gather<D>(cu, P.cu);
-                quad_gather<D>(dx, P.dx);
-                quad_gather<D>(cdx, P.cdx);
-                quad_gather<D>(gs, P.gs);
-                active_jump<D, false>(P, c, m, md);
-                u = pick3(P.u, ax);
-                cu = pick3(P.cu, ax);
-                dx = pick3(P.dx, ax);
-                cdx = pick3(P.cdx, ax);
-                gs = pick3(P.gs, ax);
-                k += m;
-                backoff = 1;
-            }
-        }
-        // a sub-step, computed on every lane and kept where the island takes one
-        const bool step = more && m < 2;
+    // one sub-step of this lane's axis
+    auto substep = [&](float& u, float& cu, float& dx, float& cdx, float& gs, float& fs, float& vm) {
         float F = 0.f;
         if (P.wall) F = wall_axis<CT>(c, P.gw, P.d, elo - dx, ehi + dx, u, F);
         if (NC) {
@@ -2061,20 +2066,94 @@ __device__ __forceinline__ void split_wave(Active<D>& P, const PCfg& c, bool val
             const float Fp = F + mag * ((r0 + dl) * inv);
             F = on ? Fp : F;
         }
-        float u1 = u, cu1 = cu, dx1 = dx, cdx1 = cdx, gs1 = gs, fs1 = fs;
-        axis_update<D>(P, c, F, j, hbw, u1, cu1, dx1, cdx1, gs1, fs1);
+        axis_update<D>(P, c, F, j, hbw, u, cu, dx, cdx, gs, fs);
         float uv[3] = {0.f, 0.f, 0.f};
-        quad_gather<D>(u1, uv);
-        const float vm = fmaxf(P.vmax2, speed2<D>(uv));
-        u = step ? u1 : u;
-        cu = step ? cu1 : cu;
-        dx = step ? dx1 : dx;
-        cdx = step ? cdx1 : cdx;
-        gs = step ? gs1 : gs;
-        fs = step ? fs1 : fs;
-        P.vmax2 = step ? vm : P.vmax2;
-        k += step ? 1 : 0;
-        if (step && check) backoff = min(2 * backoff, 64);
+        quad_gather<D>(u, uv);
+        vm = fmaxf(vm, speed2<D>(uv));
+    };
+    // Each island keeps its own trip count (its sub-steps and jumps so far),
+    // back-off and k, and takes the decisions of the general loop in the
+    // same order; only the interleaving of islands within the wave differs.
+    int k = 0, backoff = 1, trip = 0;
+    while (__any(valid && k < c.n_sub)) {
+        // Checks, and the jumps they allow: an island that jumps checks again
+        // on its next trip (back-off 1), taken here at once.
+        bool more, check;
+        int m;
+        for (;;) {
+            more = valid && k < c.n_sub;
+            check = more && (trip & (backoff - 1)) == 0;
+            m = 0;
+            if (__any(check)) {
+                // the full vectors of this particle and of its partner
+                Active<D> Q = P;
+                quad_gather<D>(u, Q.u);
+                quad_gather<D>(cu, Q.cu);
+                quad_gather<D>(dx, Q.dx);
+                float odx[3] = {0.f, 0.f, 0.f}, ou[3] = {0.f, 0.f, 0.f};
+                if (NC) {
+#pragma unroll
+                    for (int a = 0; a < D; a++) {
+                        odx[a] = row_swap8(Q.dx[a]);
+                        ou[a] = row_swap8(Q.u[a]);
+                    }
+                }
+                int allow = 0;
+                if (check) {
+                    if (NC) allow = free_allowance_one<D>(Q, c, cd, odx, ou, oveq, c.n_sub - k);
+                    else allow = free_allowance<D>(Q, c, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, c.n_sub - k);
+                }
+                const int other = NC ? row_swap8(allow) : allow;
+                m = check ? min(allow, other) : 0;
+            }
+            const bool jump = more && m >= 2;
+            if (!__any(jump)) break;
+            if (jump) {
+                quad_gather<D>(u, P.u);
+                quad_gather<D>(cu, P.cu);
+                quad_gather<D>(dx, P.dx);
+                quad_gather<D>(cdx, P.cdx);
+                quad_gather<D>(gs, P.gs);
+                active_jump<D, false>(P, c, m, md);
+                u = pick3(P.u, ax);
+                cu = pick3(P.cu, ax);
+                dx = pick3(P.dx, ax);
+                cdx = pick3(P.cdx, ax);
+                gs = pick3(P.gs, ax);
+                k += m;
+                backoff = 1;
+                trip += 1;
+            }
+        }
+        // a sub-step for every island left, computed on every lane and kept where it steps
+        {
+            float u1 = u, cu1 = cu, dx1 = dx, cdx1 = cdx, gs1 = gs, fs1 = fs, vm1 = P.vmax2;
+            substep(u1, cu1, dx1, cdx1, gs1, fs1, vm1);
+            u = more ? u1 : u;
+            cu = more ? cu1 : cu;
+            dx = more ? dx1 : dx;
+            cdx = more ? cdx1 : cdx;
+            gs = more ? gs1 : gs;
+            fs = more ? fs1 : fs;
+            P.vmax2 = more ? vm1 : P.vmax2;
+        }
+        if (more) {
+            k += 1;
+            trip += 1;
+            if (check) backoff = min(2 * backoff, 64);
+        }
+        // The trips before the next check of any island, and before any
+        // island ends, hold plain sub-steps only: run them with no decision.
+        const bool run = valid && k < c.n_sub;
+        int T = __ockl_wfred_min_i32(run ? min((-trip) & (backoff - 1), c.n_sub - k) : INT_MAX);
+        if (T == INT_MAX) T = 0;
+        if (run) {
+            float vm = P.vmax2;
+            for (int t = 0; t < T; t++) substep(u, cu, dx, cdx, gs, fs, vm);
+            P.vmax2 = vm;
+            k += T;
+            trip += T;
+        }
     }
     quad_gather<D>(u, P.u);
     quad_gather<D>(cu, P.cu);
@@ -2120,7 +2199,7 @@ __global__ __launch_bounds__(64) void k_island_small(PState A, PState Bn, int np
         const unsigned long long le = __ballot(wb_lane <= w);
         const int sz = 64 - __clzll(le);
         const uint32_t per = WAVE / sz;
-        const uint32_t nisl = counters[CNT_CLASS + sz];
+        const uint32_t nisl = counters[CNT_CLASS + sz] + (sz == 2 ? counters[CNT_PAIRC] : 0u);
         const uint32_t idx = w - counters[CNT_WAVEBASE + sz];
         const uint32_t here = min(per, nisl - idx * per);
         const bool quartered = !MD && sz <= 2;
@@ -2925,7 +3004,8 @@ static void dem_impl(PBuf& b, int np, const PCfg& c, bool one_group, hipStream_t
         hipLaunchKernelGGL(k_uf_hook, dim3(grid_act), dim3(256), 0, s, b.alist, b.ccount, b.prefix, b.cand, b.aidx, b.parent,
                            b.counters);
         hipLaunchKernelGGL(k_uf_flatten, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.counters);
-        hipLaunchKernelGGL(k_island_class, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.bigroot,
+        hipLaunchKernelGGL(k_island_class<D>, dim3(grid_act), dim3(256), 0, s, b.A, b.alist, b.ccount, b.prefix,
+                           b.cand, b.parent, b.isize, b.irank, b.bigroot,
                            b.counters);
         hipLaunchKernelGGL(k_island_place, dim3(grid_act), dim3(256), 0, s, b.parent, b.isize, b.irank, b.fill,
                            b.lanemember, b.loc, b.bigoff, b.bigmember, b.bigroot, b.counters);

@@ -254,6 +254,7 @@ enum {
     CNT_ACTIVE = 1,      // active particles of the current step (high word)
     CNT_WAVES = 2,       // packed waves of small islands
     CNT_BIG = 3,         // islands larger than one wave
+    CNT_PAIRC = 4,       // islands of two whose members touch at the start of the step
     CNT_CLASS = 8,       // 65 class counters (index 1..64 sizes, 65 big) at 8..73
     CNT_WAVEBASE = 80,   // 66 prefix entries at 80..145
     CNT_SIZE = 160
