@@ -1522,15 +1522,21 @@ __device__ __forceinline__ void wall_force(const Active<D>& P, const PCfg& c, fl
     }
 }
 
-// The normal contact force of a pair: del is this particle's displacement
-// in the step minus the candidate's, w (read by the dashpot only) its
-// velocity minus the candidate's.  Out of contact: false.  Otherwise the
-// force on this particle is mag n, n = r inv, r = r0 + del.  FLAT: no
-// early return (mag is then meaningless out of contact).
-template <int D, int CT, bool FLAT = false>
-__device__ __forceinline__ bool pair_normal(const CandData& cd, const float* del, const float* w, const PCfg& c,
-                                            float* r, float& inv, float& mag) {
-    const int ct = CT < 0 ? c.contact : CT;
+// The sum of a vector's D components in the fixed order (x + y) + z.
+template <int D>
+__device__ __forceinline__ float sum_d(const float* p) {
+#pragma clang fp contract(off)
+    float v = p[0] + p[1];
+    if (D == 3) v = v + p[2];
+    return v;
+}
+
+// The geometry of a pair contact: del is this particle's displacement in
+// the step minus the candidate's.  Out of contact: false.  Otherwise
+// r = r0 + del, inv = 1/|r| and delta = r_c - |r| (the overlap).  FLAT: no
+// early return (the outputs are then meaningless out of contact).
+template <int D, bool FLAT = false>
+__device__ __forceinline__ bool pair_geom(const CandData& cd, const float* del, float* r, float& inv, float& delta) {
     float rd = 0.f, dd = 0.f;
 #pragma unroll
     for (int a = 0; a < D; a++) {
@@ -1545,33 +1551,42 @@ __device__ __forceinline__ bool pair_normal(const CandData& cd, const float* del
     for (int a = 0; a < D; a++) r2 += r[a] * r[a];
     inv = rsq_fast(r2);                          // 1 / |r|
     const float dist = r2 * inv;
-    const float delta = num * rcp_fast(cd.rc + dist);   // r_c - |r|
-    if (ct == PIBM_CONTACT_LSD) {
-        float vn = 0.f;
-#pragma unroll
-        for (int a = 0; a < D; a++) vn += w[a] * (r[a] * inv);
-        mag = c.kn * delta - cd.gam * vn;
-    } else if (ct == PIBM_CONTACT_HERTZ) {
-        mag = cd.gam * delta * sqrt_fast(delta);
-    } else {
-        float q = delta * rcp_fast(cd.rc);
-        mag = c.ks * q * q;
-    }
+    delta = num * rcp_fast(cd.rc + dist);        // r_c - |r|
     return num > 0.f;
+}
+
+// The normal force magnitude at overlap delta; vn (read by the dashpot
+// only) is the normal component of this particle's velocity relative to
+// the candidate's, sum_d of (u - u_c)_a n_a.
+template <int CT>
+__device__ __forceinline__ float pair_mag(const CandData& cd, const PCfg& c, float delta, float vn) {
+    const int ct = CT < 0 ? c.contact : CT;
+    if (ct == PIBM_CONTACT_LSD) return c.kn * delta - cd.gam * vn;
+    if (ct == PIBM_CONTACT_HERTZ) return cd.gam * delta * sqrt_fast(delta);
+    const float q = delta * rcp_fast(cd.rc);
+    return c.ks * q * q;
 }
 
 template <int D, int CT = -1>
 __device__ __forceinline__ void pair_force(const Active<D>& P, const CandData& cd, const float* odx,
                                            const float* ou, const PCfg& c, float* F) {
-    float del[3] = {0, 0, 0}, w[3] = {0, 0, 0}, r[3], inv, mag;
+    const int ct = CT < 0 ? c.contact : CT;
+    float del[3] = {0, 0, 0}, r[3], inv, delta;
 #pragma unroll
-    for (int a = 0; a < D; a++) {
-        del[a] = P.dx[a] - odx[a];
-        w[a] = P.u[a] - ou[a];
+    for (int a = 0; a < D; a++) del[a] = P.dx[a] - odx[a];
+    if (!pair_geom<D>(cd, del, r, inv, delta)) return;
+    float n[3] = {0, 0, 0}, p[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; a++) n[a] = r[a] * inv;
+    float vn = 0.f;
+    if (ct == PIBM_CONTACT_LSD) {
+#pragma unroll
+        for (int a = 0; a < D; a++) p[a] = (P.u[a] - ou[a]) * n[a];
+        vn = sum_d<D>(p);
     }
-    if (!pair_normal<D, CT>(cd, del, w, c, r, inv, mag)) return;
+    const float mag = pair_mag<CT>(cd, c, delta, vn);
 #pragma unroll
-    for (int a = 0; a < D; a++) F[a] += mag * (r[a] * inv);
+    for (int a = 0; a < D; a++) F[a] += mag * n[a];
 }
 
 // Hertz-Mindlin pair contact: Hertz normal force, tangential force T
@@ -1730,28 +1745,29 @@ template <int D>
 __device__ __forceinline__ void axis_update(const Active<D>& P, const PCfg& c, float F, float j, float hbw, float& u,
                                             float& cu, float& dx, float& cdx, float& gs, float& fs) {
 #pragma clang fp contract(off)
-    float g = 2.0f * (P.ri * u - j);
+    // (the products enter their sums fused, each rounded once)
+    float g = 2.0f * fmaf(P.ri, u, -j);
     gs += g;
     fs += F;
-    float incr = (-P.Ap * g + F) * P.hm + hbw;
+    float incr = fmaf(fmaf(-P.Ap, g, F), P.hm, hbw);
     // compensated sums keep the many tiny increments exact to FP32
     float y = incr - cu;
     float t = u + y;
     cu = (t - u) - y;
     u = t;
-    float yx = c.h * u - cdx;
+    float yx = fmaf(c.h, u, -cdx);
     float tx = dx + yx;
     cdx = (tx - dx) - yx;
     dx = tx;
 }
 
+// |u|^2: the squares summed by sum_d
 template <int D>
 __device__ __forceinline__ float speed2(const float* u) {
-#pragma clang fp contract(off)
-    float v2 = 0.f;
+    float sq[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-    for (int a = 0; a < D; a++) v2 += u[a] * u[a];
-    return v2;
+    for (int a = 0; a < D; a++) sq[a] = u[a] * u[a];
+    return sum_d<D>(sq);
 }
 
 // The update of one sub-step from the contact force F and torque tq
@@ -2058,18 +2074,24 @@ __device__ __forceinline__ void split_wave(Active<D>& P, const PCfg& c, bool val
             // (every member of a split pair wave has its partner as only candidate)
             // the relative displacement and velocity, axis by axis
             // (this lane's component of r = r0 + del is r0 + its own del)
-            float del[3] = {0.f, 0.f, 0.f}, w[3] = {0.f, 0.f, 0.f}, r[3], inv, mag;
+            float del[3] = {0.f, 0.f, 0.f}, r[3], inv, delta;
             const float dl = dx - row_swap8(dx);
             quad_gather<D>(dl, del);
-            if (ct == PIBM_CONTACT_LSD) quad_gather<D>(u - row_swap8(u), w);
-            const bool on = pair_normal<D, CT, true>(cd, del, w, c, r, inv, mag);
-            const float Fp = F + mag * ((r0 + dl) * inv);
+            const bool on = pair_geom<D, true>(cd, del, r, inv, delta);
+            const float n = (r0 + dl) * inv;
+            float vn = 0.f;
+            if (ct == PIBM_CONTACT_LSD) {
+                float pv[3] = {0.f, 0.f, 0.f};
+                quad_gather<D>((u - row_swap8(u)) * n, pv);
+                vn = sum_d<D>(pv);
+            }
+            const float Fp = F + pair_mag<CT>(cd, c, delta, vn) * n;
             F = on ? Fp : F;
         }
         axis_update<D>(P, c, F, j, hbw, u, cu, dx, cdx, gs, fs);
-        float uv[3] = {0.f, 0.f, 0.f};
-        quad_gather<D>(u, uv);
-        vm = fmaxf(vm, speed2<D>(uv));
+        float sq[3] = {0.f, 0.f, 0.f};
+        quad_gather<D>(u * u, sq);
+        vm = fmaxf(vm, sum_d<D>(sq));
     };
     // Each island keeps its own trip count (its sub-steps and jumps so far),
     // back-off and k, and takes the decisions of the general loop in the
