@@ -706,3 +706,57 @@ def test_phase_times_sampled(P):
     sim.step(2)
     ph, n = sim.phase_times()
     assert n == 0
+
+
+@pytest.mark.parametrize("contact", ["lsd", "hertz"])
+@pytest.mark.parametrize("lat", [9, 19])
+def test_pairs_and_singles_closing_in(P, orc, lat, contact):
+    """Islands of one and two that come into contact during the run, beside
+    a pair resting on the floor in the same size class: particles settling
+    onto the floor from small gaps, and particles settling onto a particle
+    that rests on the floor (straight above it and off-centre).  Before the
+    onset such an island jumps over contact-free stretches that shrink as
+    the gap closes, checking again after each jump; after it, it sub-steps.
+    30 steps against the oracle: particles within the 1e-5 bound, and every
+    settling particle touches at some step."""
+    _flush(f"pairs and singles closing in {lat} {contact}")
+    D = 2 if lat == 9 else 3
+    n = (32, 16, 1) if D == 2 else (16, 12, 12)
+    r = 0.2499                                           # resting height (radius 0.25)
+
+    def at(x, y, h):                                     # h along gravity (the last axis)
+        return [x, h] if D == 2 else [x, y, h]
+
+    pts = [at(2.0, 3.0, r + 2e-4), at(4.0, 5.0, r + 4e-4),            # settling onto the floor
+           at(7.0, 3.0, r), at(7.0, 3.0, r + 0.5 + 2e-4),                # onto a resting particle
+           at(10.0, 6.0, r), at(10.2, 6.0, r + np.sqrt(0.25 - 0.04) + 2e-4),   # off-centre
+           at(13.0, 8.0, r), at(13.01, 8.0, r + 0.4999)]                 # resting pair
+    X = np.array(pts).T.astype(np.float32).astype(np.float64)
+    U = np.zeros_like(X)
+    npart = X.shape[1]
+    d = np.full(npart, 0.5)
+    rp = np.full(npart, 2.5)
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-4
+    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact=contact, young=1e3)
+    sim = P.Sim(cfg, npart)
+    sim.set_particles(X, U, d, rp)
+    oc = G.oracle_cfg(orc, cfg)
+    f = G.to_oracle_f(orc, lat, sim.read_populations())
+    Xo, Uo = X.copy(), U.copy()
+    touched = np.zeros(npart, bool)
+    for k in range(30):
+        out = orc.step(oc, f, Xo, Uo, d, rp)
+        f, Xo, Uo = out["f"], out["X"], out["U"]
+        touched |= np.abs(out["fc"]).max(axis=0) > 0
+    sim.step(30)
+    sim.synchronize()
+    got = sim.read_particles()
+    eu, er, eh = G.field_errors(orc, lat, sim.read_populations(), f, sim.N)
+    disp = np.abs(Xo - X).max()
+    ex = np.abs(got["x"] - Xo).max() / disp
+    ev = np.linalg.norm(got["v"] - Uo) / np.linalg.norm(Uo)
+    _flush(f"  30 steps: eps_u={eu:.2e} eps_rho={er:.2e} dX={ex:.2e} (disp {disp:.2e}) dU={ev:.2e}; "
+           f"touched {touched.astype(int).tolist()}")
+    assert touched[[0, 1, 3, 5]].all()         # every settling particle made contact
+    assert ex <= 1e-5 and ev <= 1e-5
