@@ -2557,14 +2557,14 @@ __device__ __forceinline__ void spread_tile(const Grid& g, const PCfg& c, const 
 #pragma unroll
             for (int i = 0; i < RS::STRIDE / 4; i++) {
                 const float4 w = rec[i];
-                sp[k * PW + 4 * i] = w.x;
-                sp[k * PW + 4 * i + 1] = w.y;
-                sp[k * PW + 4 * i + 2] = w.z;
-                sp[k * PW + 4 * i + 3] = w.w;
+                sp[__umul24(k, PW) + 4 * i] = w.x;
+                sp[__umul24(k, PW) + 4 * i + 1] = w.y;
+                sp[__umul24(k, PW) + 4 * i + 2] = w.z;
+                sp[__umul24(k, PW) + 4 * i + 3] = w.w;
             }
             if (!REC) {
 #pragma unroll
-                for (int a = 0; a < C; a++) sp[k * PW + CO + a] = coef[(long long)a * np + gsl];
+                for (int a = 0; a < C; a++) sp[__umul24(k, PW) + CO + a] = coef[(long long)a * np + gsl];
             }
         }
         __syncthreads();
@@ -2586,7 +2586,7 @@ __device__ __forceinline__ void spread_tile(const Grid& g, const PCfg& c, const 
             for (int i = 0; i < NRW; i++) {
                 const uint32_t pr = pk[row_of(i) * TX + lx];
                 for (uint32_t k = pr & 0xffffu; k < (pr >> 16); k++) {
-                    const float* q = sp + k * PW;
+                    const float* q = sp + __umul24(k, PW);
                     const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + i];
 #pragma unroll
                     for (int a = 0; a < C; a++) acc[a] += W * q[CO + a];
@@ -2615,7 +2615,8 @@ __device__ __forceinline__ void spread_tile(const Grid& g, const PCfg& c, const 
                     k = pr & 0xffffu;
                     e = pr >> 16;
                 }
-                const float* q = sp + k * PW;
+                // (k < 2^16: the 24-bit multiply, full rate, not the 32-bit one)
+                const float* q = sp + __umul24(k, PW);
                 const float W = q[x - __float_as_int(q[RS::BASE])] * q[4 + ky] * q[8 % (4 * D) + kz];
 #pragma unroll
                 for (int a = 0; a < C; a++) acc[a] += W * q[CO + a];
