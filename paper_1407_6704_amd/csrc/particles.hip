@@ -1688,7 +1688,7 @@ __device__ __forceinline__ CandData cand_at(const CandData* first, int n1, const
 // (sdx, su, and with MD the spins sw) of stride `stride` indexed by the
 // candidate's local index; the first nfirst candidates come from `first`
 // (an LDS copy), the rest from `rest` (global).
-template <int D, bool MD, bool FIXED = true>
+template <int D, bool MD>
 __device__ __forceinline__ void substep_update(Active<D>& P, const PCfg& c, const float* F, const float* tq);
 
 template <int D, bool MD, bool LDS = false>
@@ -1771,11 +1771,10 @@ __device__ __forceinline__ float speed2(const float* u) {
 }
 
 // The update of one sub-step from the contact force F and torque tq
-// (Eq. demgov, Jacobi).  FIXED = false: no particle is a point of a fixed
-// body.
-template <int D, bool MD, bool FIXED>
+// (Eq. demgov, Jacobi).
+template <int D, bool MD>
 __device__ __forceinline__ void substep_update(Active<D>& P, const PCfg& c, const float* F, const float* tq) {
-    if (FIXED && P.fixed) {
+    if (P.fixed) {
         // a fixed point keeps its state; g = -2 j_i with U = 0, contact reactions summed
 #pragma unroll
         for (int a = 0; a < D; a++) {
