@@ -424,11 +424,12 @@ def test_resting_pile_lasting_contacts(P, orc, lat):
 @pytest.mark.parametrize("contact", ["lsd", "hertz"])
 @pytest.mark.parametrize("lat", [9, 19])
 def test_pairs_and_wall_singles_lasting_contact(P, orc, lat, contact):
-    """Islands of one and two members, the ones the island kernel runs with
-    lane swaps and a lockstep loop: pairs of touching particles stacked on
-    the floor (gravity keeps them in contact), particles resting on the floor, and
-    one pair whose members fly apart (its islands leave the lockstep loop to
-    jump).  40 steps against the oracle: particles within the 1e-5 bound;
+    """Islands of one and two members, the ones the island kernel runs in
+    its split form (four lanes per particle): pairs of touching particles
+    stacked on the floor (gravity keeps them in contact), particles resting
+    on the floor, and one pair whose members fly apart (its island jumps
+    while the others sub-step).  40 steps against the oracle: particles
+    within the 1e-5 bound;
     the fluid within the larger of 1e-5 and the oracle's own change under
     a 1e-8 relative move of the positions (resting contacts, as in the pile
     test)."""
