@@ -146,20 +146,37 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const T* __restrict__ in, l
 // One block of 1024 threads: exclusive scan of the nb tile sums in place
 // (each thread takes a run of consecutive sums), grand total to *total.
 constexpr int TOP_THREADS = 1024;
+constexpr int TOP_ITEMS = 16;      // sums per thread held in registers (up to 16384 blocks)
 template <class T>
 __global__ __launch_bounds__(TOP_THREADS) void k_scan_top(T* __restrict__ bsum, long long nb, T* __restrict__ total) {
     __shared__ T sh[TOP_THREADS / 64];
     const long long per = (nb + TOP_THREADS - 1) / TOP_THREADS;
     const long long b0 = (long long)threadIdx.x * per;
     const long long b1 = b0 + per < nb ? b0 + per : nb;
-    T s = 0;
-    for (long long i = b0; i < b1; i++) s += bsum[i];
-    T tot;
-    T run = block_exclusive_scan<T, TOP_THREADS / 64>(s, sh, tot);
-    for (long long i = b0; i < b1; i++) {
-        const T x = bsum[i];
-        bsum[i] = run;
-        run += x;
+    T s = 0, tot;
+    if (per <= TOP_ITEMS) {
+        // the usual case: a thread's sums loaded together into registers
+        T v[TOP_ITEMS];
+#pragma unroll
+        for (int k = 0; k < TOP_ITEMS; k++) {
+            v[k] = b0 + k < b1 ? bsum[b0 + k] : (T)0;
+            s += v[k];
+        }
+        T run = block_exclusive_scan<T, TOP_THREADS / 64>(s, sh, tot);
+#pragma unroll
+        for (int k = 0; k < TOP_ITEMS; k++)
+            if (b0 + k < b1) {
+                bsum[b0 + k] = run;
+                run += v[k];
+            }
+    } else {
+        for (long long i = b0; i < b1; i++) s += bsum[i];
+        T run = block_exclusive_scan<T, TOP_THREADS / 64>(s, sh, tot);
+        for (long long i = b0; i < b1; i++) {
+            const T x = bsum[i];
+            bsum[i] = run;
+            run += x;
+        }
     }
     if (threadIdx.x == 0 && total) *total = tot;
 }
