@@ -249,9 +249,12 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
 
 def run_adjoint(w, K: int = 100):
     """Adjoint/forward cost on the differentiation workload: plain FP32
-    stepping of w.steps steps against the backward pass (segment re-runs plus
-    the reverse steps) of a checkpointed rollout of the same steps, for
-    J = mean particle height."""
+    stepping of w.steps steps against the backward pass of a recorded rollout
+    of the same steps, for J = mean particle height.  The forward pass tapes
+    its last segment, so the backward pass re-runs every segment but the
+    last before reversing it.  Two layouts: the whole rollout as one taped
+    segment when it fits in a quarter of the free device memory (nothing is
+    run twice), and checkpoints every K steps (one segment's tape)."""
     import numpy as np
     import torch
 
@@ -277,21 +280,33 @@ def run_adjoint(w, K: int = 100):
     sim.synchronize()
     t_fwd, _ = timed(lambda: sim.step(steps), sim.stream)
     sim.synchronize()
+    full_bytes = sim.lib.pibm_rollout_bytes(sim.ctx, int(steps), int(steps))
     del sim
-    rs = pibm.Sim(cfg, X.shape[1])
-    rs.set_particles(X, U, d, rp)
-    t_ck, _ = timed(lambda: rs.forward_ckpt(steps, K), rs.stream)
+    torch.cuda.empty_cache()
     dJdx = np.zeros_like(X)
     dJdx[w.dim - 1] = 1.0 / X.shape[1]
-    t_bwd, r = timed(lambda: rs.backward(dJ_dx=dJdx), rs.stream)
+
+    def rollout(k):
+        rs = pibm.Sim(cfg, X.shape[1])
+        rs.set_particles(X, U, d, rp)
+        t_ck, _ = timed(lambda: rs.forward_ckpt(steps, k), rs.stream)
+        t_bwd, r = timed(lambda: rs.backward(dJ_dx=dJdx), rs.stream)
+        res = {"checkpoint_every": k, "forward_ckpt_ms": t_ck, "backward_ms": t_bwd, "ratio": t_bwd / t_fwd,
+               "rollout_buffer_MB": rs.rollout_buf.numel() / 1e6, "dJ_dtau": r["dtau"],
+               "dJ_dgravity_y": r["dgravity"][w.dim - 1], "dJ_dv0_norm": float(np.linalg.norm(r["dv0"]))}
+        del rs
+        torch.cuda.empty_cache()
+        return res
+
+    ck = rollout(K)
     out = {"workload": f"{w.name}: D2Q9 {w.n[0]}x{w.n[1]}, {X.shape[1]} particles, soft contact, n_sub 1",
-           "steps": steps, "checkpoint_every": K, "forward_ms": t_fwd, "forward_ckpt_ms": t_ck,
-           "backward_ms": t_bwd, "ratio": t_bwd / t_fwd,
-           "rollout_buffer_MB": rs.rollout_buf.numel() / 1e6,
-           "dJ_dtau": r["dtau"], "dJ_dgravity_y": r["dgravity"][w.dim - 1],
-           "dJ_dv0_norm": float(np.linalg.norm(r["dv0"]))}
-    del rs
-    torch.cuda.empty_cache()
+           "steps": steps, "forward_ms": t_fwd}
+    free, _ = torch.cuda.mem_get_info()
+    if 0 < full_bytes <= free // 4:
+        out.update(rollout(steps))
+        out["checkpointed"] = ck
+    else:
+        out.update(ck)
     return out
 
 

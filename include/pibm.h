@@ -314,7 +314,9 @@ pibm_status pibm_conservation_noalloc(pibm_ctx* ctx, double* mass, double* momen
  * explicit update of Eq. demgov), contact NONE or SOFT, bin_log2 = 0, FP32
  * or FP16 storage; other configurations return
  * PIBM_E_CONFIG.  Memory stays bounded by checkpointing: the state is saved
- * every K steps and each K-step segment is re-run before it is reversed.
+ * every K steps and each K-step segment is re-run before it is reversed,
+ * except the last, which the forward pass records as it runs it (with
+ * K >= n_steps the whole rollout is recorded once and nothing runs twice).
  *
  * Bytes of the caller-owned device buffer for a rollout of n_steps steps with
  * checkpoints every K steps (checkpoints, one segment's recorded states and

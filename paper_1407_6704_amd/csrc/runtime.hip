@@ -67,6 +67,7 @@ void adj_pack_mom(const float* in, int comps, long long n, float4* out, hipStrea
 struct Rollout {
     int steps = 0, K = 0, nck = 0;
     bool valid = false;
+    int taped = -1;               // the segment whose steps the tape holds (-1: none)
     std::vector<char*> ck_f;      // populations (storage format) at steps 0, K, 2K, ... and the final step
     std::vector<float*> ck_p;     // particle state [xh D][xl D][u D] x np, id order
     float *d_id = nullptr, *rp_id = nullptr;
@@ -1033,8 +1034,8 @@ pibm_status pibm_forward_ckpt(pibm_ctx* c, int32_t n_steps, int32_t K, void* dev
     if (!why.empty()) return fail(c, PIBM_E_CONFIG, why);
     if (!c->particles_set) return fail(c, PIBM_E_STATE, "particles not set");
     if (pibm_status st = check_device_input(c)) return st;
-    Rollout R;
-    const size_t need = carve_rollout(*c, n_steps, K, nullptr, R);
+    Rollout plan;
+    const size_t need = carve_rollout(*c, n_steps, K, nullptr, plan);
     if (!dev_buf || buf_bytes < need) return fail(c, PIBM_E_ARG, "rollout buffer too small");
     char* base = (char*)(((uintptr_t)dev_buf + 255) & ~(uintptr_t)255);
     if ((size_t)(base - (char*)dev_buf) + need - 256 > buf_bytes) return fail(c, PIBM_E_ARG, "rollout buffer too small");
@@ -1042,11 +1043,32 @@ pibm_status pibm_forward_ckpt(pibm_ctx* c, int32_t n_steps, int32_t K, void* dev
     c->ro.steps = n_steps;
     c->ro.K = K;
     adj_save_const(c->pb, c->np, c->ro.d_id, c->ro.rp_id, c->stream);
+    Rollout& R = c->ro;
+    R.taped = -1;
+    const int last = n_steps > 0 ? (n_steps - 1) / K : -1;    // the last segment
+    const size_t fbytes = pop_bytes(c), pf = (size_t)3 * c->D * c->np;
     HipSeq q;
     for (int t = 0; t < n_steps; t++) {
         if (t % K == 0) q(save_checkpoint(c, t / K));
-        q(launch_step(c, c->fA, c->fB, c->F, -1, true));
+        if (t / K != last) {
+            q(launch_step(c, c->fA, c->fB, c->F, -1, true));
+        } else {
+            // The last segment runs on the tape, as the backward pass would
+            // re-run it (same steps, same buffers): the backward pass then
+            // starts reversing at once.  One segment (K >= n_steps) tapes
+            // the whole rollout and nothing is run twice.
+            const int k = t - last * K, len = n_steps - last * K;
+            if (k == 0) q(hipMemcpyAsync(R.tape_f, c->fA, fbytes, hipMemcpyDeviceToDevice, c->stream));
+            adj_save_state(c->D, c->pb, c->np, R.tape_p + k * pf, c->stream);
+            void* fout = (k + 1 < len) ? (void*)(R.tape_f + (k + 1) * fbytes) : c->fB;
+            q(launch_step(c, R.tape_f + k * fbytes, fout, R.tape_F + (size_t)k * c->D * c->N, -1, true));
+        }
         std::swap(c->fA, c->fB);
+    }
+    if (last >= 0) {
+        R.taped = last;
+        // the last force field went to the tape: F is spread again when read
+        if (c->np > 0 && c->cfg.two_way) c->F_stale = true;
     }
     q(save_checkpoint(c, c->ro.nck - 1));
     if (n_steps > 0) c->stepped = true;
@@ -1082,12 +1104,16 @@ pibm_status pibm_backward(pibm_ctx* c, const float* dJ_dx_T, const float* dJ_dv_
     for (int seg = nseg - 1; seg >= 0; seg--) {
         const int t0 = seg * R.K, len = std::min(R.K, R.steps - t0);
         // re-run the segment, recording the state at the start of every step
-        q(hipMemcpyAsync(R.tape_f, R.ck_f[seg], fbytes, hipMemcpyDeviceToDevice, s));
-        adj_load_state(D, c->pb, np, R.ck_p[seg], R.d_id, R.rp_id, s);
-        for (int k = 0; k < len; k++) {
-            adj_save_state(D, c->pb, np, R.tape_p + k * pf, s);
-            void* fout = (k + 1 < len) ? (void*)(R.tape_f + (k + 1) * fbytes) : c->fB;
-            q(launch_step(c, R.tape_f + k * fbytes, fout, R.tape_F + (size_t)k * D * N, -1, true));
+        // (the last one was taped by the forward pass)
+        if (seg != R.taped) {
+            q(hipMemcpyAsync(R.tape_f, R.ck_f[seg], fbytes, hipMemcpyDeviceToDevice, s));
+            adj_load_state(D, c->pb, np, R.ck_p[seg], R.d_id, R.rp_id, s);
+            for (int k = 0; k < len; k++) {
+                adj_save_state(D, c->pb, np, R.tape_p + k * pf, s);
+                void* fout = (k + 1 < len) ? (void*)(R.tape_f + (k + 1) * fbytes) : c->fB;
+                q(launch_step(c, R.tape_f + k * fbytes, fout, R.tape_F + (size_t)k * D * N, -1, true));
+            }
+            R.taped = seg;
         }
         // reverse it
         for (int k = len - 1; k >= 0; k--) {
