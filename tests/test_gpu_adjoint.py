@@ -12,8 +12,11 @@ called through the C ABI) for J = mean particle height after T steps.
     components, and each component's error against the largest), and over
     300 steps against autograd through the FP64 reference, every component;
   - invariance of the gradients to the checkpoint interval (bitwise: the
-    re-run reproduces the forward exactly), and the context's state after
-    the rollout and after the backward pass.
+    re-run reproduces the forward exactly, and the last segment, which the
+    forward pass tapes as it runs it, equals its re-run; K >= T tapes the
+    whole rollout), a second objective reversed on the same recording (whose
+    last segment is then re-run), and the context's state after the rollout
+    and after the backward pass.
 """
 import numpy as np
 import pytest
