@@ -818,6 +818,18 @@ __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const
     __shared__ unsigned long long sh4[4];
     const unsigned lb = xcd_block();
     int s = lb * 256 + threadIdx.x;
+    // A block without active particles has nothing to do (active particles
+    // are a small share: those near walls or near each other).  RAW: bsum[lb]
+    // is the block's total (block 0 still writes the grand totals below);
+    // else bsum is scanned and the total is the step to the next block's
+    // offset (the last block's: to the grand total in counters[0..1]).
+    if (RAW) {
+        if (lb != 0 && bsum[lb] == 0ULL) return;
+    } else {
+        const unsigned long long next = lb + 1 < gridDim.x ? bsum[lb + 1]
+                                                            : *(const unsigned long long*)counters;
+        if (next == bsum[lb]) return;
+    }
     // bsum holds the blocks' (active << 32 | candidates) totals of k_classify:
     // this block's offset is the sum of those before it; block 0 also writes
     // the grand totals (candidates, active) to counters[0..1]
