@@ -388,7 +388,10 @@ class Sim:
     # --- adjoint ---------------------------------------------------------
     def forward_ckpt(self, n_steps, K=100):
         """Run n_steps steps, recording checkpoints every K steps in a device
-        buffer owned by this object (for backward)."""
+        buffer owned by this object (for backward).  The last segment is
+        recorded step by step as it runs, and backward re-runs the others
+        from their checkpoints: K >= n_steps records the whole rollout (the
+        most memory, nothing run twice; see rollout_interval)."""
         import torch
 
         nbytes = self.lib.pibm_rollout_bytes(self.ctx, int(n_steps), int(K))
@@ -397,6 +400,15 @@ class Sim:
         self.rollout_buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
         self._check(self.lib.pibm_forward_ckpt(self.ctx, int(n_steps), int(K),
                                                C.c_void_p(self.rollout_buf.data_ptr()), int(nbytes)))
+
+    def rollout_interval(self, n_steps, share=0.25, K=100):
+        """n_steps (the whole rollout recorded, no re-runs) when its buffer
+        fits in `share` of the free device memory, else K."""
+        import torch
+
+        full = self.lib.pibm_rollout_bytes(self.ctx, int(n_steps), int(n_steps))
+        free, _ = torch.cuda.mem_get_info(self.device)
+        return int(n_steps) if 0 < full <= share * free else int(K)
 
     def backward_device(self, dJ_dx=None, dJ_dv=None):
         """Gradients of J given dJ/dX_T and dJ/dU_T ((D, N) arrays or tensors,
@@ -456,7 +468,7 @@ class Sim:
         return r
 
 
-def settling_rollout(cfg_kwargs, x0, d, rho_p, steps, K=100, device="cuda:0"):
+def settling_rollout(cfg_kwargs, x0, d, rho_p, steps, K=None, device="cuda:0"):
     """A torch.autograd.Function over a checkpointed rollout of `steps`
     coupled steps, whose backward is the library's hand-written adjoint.
 
@@ -467,7 +479,9 @@ def settling_rollout(cfg_kwargs, x0, d, rho_p, steps, K=100, device="cuda:0"):
     dJ/dv0 and the position data: the particle state moves in and out
     through the device-pointer calls, with no host copy.  x0 (D, N), d and
     rho_p (N) may be host arrays or device tensors.  Gradients of any
-    J(X_T) with respect to tau, gravity and v0 come from pibm_backward."""
+    J(X_T) with respect to tau, gravity and v0 come from pibm_backward.
+    K: the checkpoint interval (None: Sim.rollout_interval, the whole
+    rollout recorded when it fits)."""
     import torch
 
     dev = torch.device(device)
@@ -487,7 +501,7 @@ def settling_rollout(cfg_kwargs, x0, d, rho_p, steps, K=100, device="cuda:0"):
             kw["gravity"] = tuple(float(g) for g in gravity.detach().cpu().tolist())
             sim = Sim(make_config(**kw), npart, device=dev)
             sim.set_particles_device(x_hi, d_t, rp_t, v=v0.detach(), x_lo=x_lo, d_max=d_max)
-            sim.forward_ckpt(steps, K)
+            sim.forward_ckpt(steps, sim.rollout_interval(steps) if K is None else K)
             p = sim.read_particles_device()
             ctx.sim = sim
             ctx.meta = (tau.dtype, tau.device, gravity.dtype, gravity.device, v0.dtype)

@@ -162,6 +162,13 @@ def test_autograd_function_stays_on_device(P):
     assert g_tau.item() == r["dtau"]
     assert np.array_equal(g_grav.numpy()[:2], np.array(r["dgravity"][:2]))
     assert np.array_equal(g_v0.cpu().numpy(), r["dv0"].astype(np.float64))
+    # the default interval (the whole rollout recorded, nothing re-run): the same gradients
+    assert sim.rollout_interval(steps) == steps
+    f_all = P.settling_rollout(kw, X, d, rp, steps)
+    v0b = torch.tensor(U, dtype=torch.float64, device="cuda", requires_grad=True)
+    g_all = torch.autograd.grad(f_all(tau, grav, v0b)[1].mean(), (tau, grav, v0b))
+    assert g_all[0].item() == g_tau.item() and torch.equal(g_all[1], g_grav)
+    assert torch.equal(g_all[2], g_v0)
 
     # autograd through the FP64 reference
     ref = TR.Ref(9, n, d, rp, k_soft=2e-3, contact="soft", n_sub=1)
