@@ -605,74 +605,132 @@ __global__ __launch_bounds__(256) void k_interp_tile(PState A, int np, Grid g, P
 // ---------------------------------------------------------------------------
 // DEM: classification and the free-particle closed form
 // ---------------------------------------------------------------------------
-// Neighbour scan over the bins around particle s that its reach meets (at
-// most (2H + 1)^D, usually 2^D).  Counting mode: the
-// number of candidates within (d_s + d_t)/2 + skin, and whether any lies
-// within (d_s + d_t)/2 + thr.  Collect mode: the candidates that are active,
-// in scan order (bins ascending, sorted order within a bin).
-template <int D, bool COLLECT>
-__device__ __forceinline__ int scan_neighbours(const float4* __restrict__ pos4, const uint32_t* __restrict__ start,
-                                               const uint32_t* __restrict__ keys_sorted,
-                                               const PCfg& c, int s, float thr, bool& close,
-                                               const unsigned long long* __restrict__ actcc, uint32_t* list,
-                                               int cap, const float* __restrict__ fixa) {
-    // points of fixed bodies do not interact with each other
-    const bool mefix = fixa && fixa[s] > 0.f;
-    // Screening uses the leading FP32 parts of the positions; c.eps bounds
-    // the neglected trailing parts, and every test is widened by it (more
-    // candidates or more active particles only cost time).
-    const float4 me = pos4[s];
-    const uint32_t key = keys_sorted[s];
+// The bins around particle s that its reach meets: at most (2H + 1)^D,
+// usually 2 or 3 per axis.  A partner within (d_s + d_t)/2 + skin + eps
+// <= r_s lies at most ceil(r_s / edge) bins away (bin = (floor(X - 1/2) + 1)
+// >> L).  Per axis, only the bins that meet [X - r_s, X + r_s]: a particle
+// of bin k lies in [k - 1/2, k + 1/2) (edge 1), so every bin beyond
+// bin(X + r_s) or below bin(X - r_s) is farther than r_s along that axis.
+// The 1/64 margin covers the rounding of X +- r_s against the bin keys.
+// The range never excludes the own bin, so a stray position cannot widen it.
+template <int D>
+__device__ __forceinline__ void neighbour_bins(const float4& me, uint32_t key, const PCfg& c, int lo[3], int hi[3]) {
     int b[3];
     b[0] = (int)(key % (uint32_t)c.nb[0]);
     b[1] = (int)((key / (uint32_t)c.nb[0]) % (uint32_t)c.nb[1]);
     b[2] = (int)(key / ((uint32_t)c.nb[0] * (uint32_t)c.nb[1]));
-    int cnt = 0;
-    // a partner within (d_s + d_t)/2 + skin + eps <= r_s lies at most
-    // ceil(r_s / edge) bins away (bin = (floor(X - 1/2) + 1) >> L)
     const float r_s = (0.5f * (me.w + c.dmax) + c.skin + c.eps) * (1.0f + 1e-6f);
     const int H = min(c.H, max(1, (int)ceilf(r_s * ldexpf(1.0f, -c.L))));
-    // Per axis, only the bins that meet [X - r_s, X + r_s]: a particle of
-    // bin k lies in [k - 1/2, k + 1/2) (edge 1), so every bin beyond
-    // bin(X + r_s) or below bin(X - r_s) is farther than r_s along that axis.
-    // The 1/64 margin covers the rounding of X +- r_s against the bin keys.
-    // Usually 2 bins per axis instead of 3: the same candidates, in the
-    // same order.
     const float rr = r_s + 0.015625f;
-    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    lo[1] = lo[2] = hi[1] = hi[2] = 0;
 #pragma unroll
     for (int a = 0; a < D; a++) {
         const float xa = a == 0 ? me.x : (a == 1 ? me.y : me.z);
         const int l = ((int)floorf(xa - rr - 0.5f) + 1) >> c.L;
         const int h = ((int)floorf(xa + rr - 0.5f) + 1) >> c.L;
-        // within b +- H and the grid, and never excluding the own bin (so
-        // also a stray position cannot widen the range)
         lo[a] = min(max(max(l, b[a] - H), 0), b[a]);
         hi[a] = max(min(min(h, b[a] + H), c.nb[a] - 1), b[a]);
     }
+}
+
+// Screening uses the leading FP32 parts of the positions; c.eps bounds the
+// neglected trailing parts, and every test is widened by it (more candidates
+// or more active particles only cost time).  Points of fixed bodies do not
+// interact with each other.
+
+// Counting scan: the number of candidates within (d_s + d_t)/2 + skin, and
+// whether any lies within (d_s + d_t)/2 + thr.  The order of the visits does
+// not matter here, so the scan is laid out for memory-level parallelism:
+// the start and end of up to R rows of bins (bins of one row are contiguous
+// in the sorted order) are loaded together, their particles are numbered
+// 0..tot-1 across the rows, and the positions are fetched four at a time.
+template <int D>
+__device__ __forceinline__ int count_neighbours(const float4* __restrict__ pos4, const uint32_t* __restrict__ start,
+                                                const float4& me, uint32_t key, const PCfg& c, int s, float thr,
+                                                bool& close, bool mefix, const float* __restrict__ fixa) {
+    constexpr int R = (D == 3) ? 9 : 3;          // rows per batch: every row of a reach of 3 bins per axis
+    int lo[3], hi[3];
+    neighbour_bins<D>(me, key, c, lo, hi);
+    const int ny = hi[1] - lo[1] + 1;
+    const int nr = ny * (hi[2] - lo[2] + 1);
+    int cnt = 0;
+    int cy = lo[1], cz = lo[2];                  // next row to load
+    for (int r0 = 0; r0 < nr; r0 += R) {
+        // particle k (pre[i] <= k < pre[i + 1]) of this batch is t = k + off[i]
+        uint32_t pre[R + 1], off[R];
+        pre[0] = 0u;
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            uint32_t t0 = 0u, t1 = 0u;
+            if (r0 + i < nr) {
+                const uint32_t row = (uint32_t)(((long long)cz * c.nb[1] + cy) * c.nb[0]);
+                t0 = start[row + lo[0]];
+                t1 = start[row + hi[0] + 1];
+                if (++cy > hi[1]) {
+                    cy = lo[1];
+                    cz++;
+                }
+            }
+            off[i] = t0 - pre[i];
+            pre[i + 1] = pre[i] + (t1 - t0);
+        }
+        const uint32_t tot = pre[R];
+        for (uint32_t k = 0; k < tot; k += 4) {
+            int t[4];
+            float4 o[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t kk = k + j;
+                uint32_t tt = kk + off[0];
+#pragma unroll
+                for (int i = 1; i < R; i++) tt = kk >= pre[i] ? kk + off[i] : tt;
+                t[j] = kk < tot ? (int)tt : s;   // past the end: the particle itself, skipped
+                o[j] = pos4[t[j]];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                bool ok = t[j] != s;
+                if (mefix) ok = ok && !(fixa[t[j]] > 0.f);
+                const float dx = me.x - o[j].x, dy = me.y - o[j].y, dz = (D == 3) ? me.z - o[j].z : 0.f;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float rc = 0.5f * (me.w + o[j].w);
+                const float cut = rc + c.skin + c.eps;
+                const float lim = rc + thr + c.eps;
+                ok = ok && r2 < cut * cut;
+                cnt += ok ? 1 : 0;
+                close = close || (ok && r2 <= lim * lim);
+            }
+        }
+    }
+    return cnt;
+}
+
+// Collecting scan: the candidates within (d_s + d_t)/2 + skin that are
+// active, in scan order (bins ascending, sorted order within a bin).
+template <int D>
+__device__ __forceinline__ int collect_neighbours(const float4* __restrict__ pos4, const uint32_t* __restrict__ start,
+                                                  const uint32_t* __restrict__ keys_sorted, const PCfg& c, int s,
+                                                  const unsigned long long* __restrict__ actcc, uint32_t* list,
+                                                  int cap, const float* __restrict__ fixa) {
+    const bool mefix = fixa && fixa[s] > 0.f;
+    const float4 me = pos4[s];
+    int lo[3], hi[3];
+    neighbour_bins<D>(me, keys_sorted[s], c, lo, hi);
+    int cnt = 0;
     for (int bz = lo[2]; bz <= hi[2]; bz++)
         for (int by = lo[1]; by <= hi[1]; by++) {
-            // bins of one row are contiguous in the sorted order
-            const int bxl = lo[0], bxh = hi[0];
-            uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
-            uint32_t t0 = start[row + bxl], t1 = start[row + bxh + 1];
+            const uint32_t row = (uint32_t)(((long long)bz * c.nb[1] + by) * c.nb[0]);
+            const uint32_t t0 = start[row + lo[0]], t1 = start[row + hi[0] + 1];
             for (uint32_t t = t0; t < t1; t++) {
                 if ((int)t == s) continue;
                 if (mefix && fixa[t] > 0.f) continue;
                 const float4 o = pos4[t];
-                float dx = me.x - o.x, dy = me.y - o.y, dz = (D == 3) ? me.z - o.z : 0.f;
-                float r2 = dx * dx + dy * dy + dz * dz;
-                float rc = 0.5f * (me.w + o.w);
-                float cut = rc + c.skin + c.eps;
-                if (r2 < cut * cut) {
-                    if (!COLLECT) {
-                        cnt++;
-                        float lim = rc + thr + c.eps;
-                        if (r2 <= lim * lim) close = true;
-                    } else if (actcc[t] != 0ULL) {
-                        if (cnt < cap) list[cnt] = t;
-                        cnt++;
-                    }
+                const float dx = me.x - o.x, dy = me.y - o.y, dz = (D == 3) ? me.z - o.z : 0.f;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float cut = 0.5f * (me.w + o.w) + c.skin + c.eps;
+                if (r2 < cut * cut && actcc[t] != 0ULL) {
+                    if (cnt < cap) list[cnt] = t;
+                    cnt++;
                 }
             }
         }
@@ -692,7 +750,7 @@ __device__ __forceinline__ int scan_neighbours(const float4* __restrict__ pos4, 
 // scan turns them into block offsets, and k_collect adds the offsets within
 // the block.
 template <int D>
-__global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, PCfg c,
+__global__ __launch_bounds__(256, 8) void k_classify(PState A, PState Bn, int np, PCfg c,
                                                   const uint32_t* __restrict__ start,
                                                   const float4* __restrict__ pos4,
                                                   const uint32_t* __restrict__ keys_sorted,
@@ -710,7 +768,18 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
     bool active = false;
     uint32_t ncand = 0;
     if (valid) {
-        float d = A.d[s], rp = A.rp[s];
+        // pos4 holds the leading position parts and the diameter of the
+        // sorted particles (k_reorder): every per-particle load is issued here
+        const float4 me = pos4[s];
+        const uint32_t key = keys_sorted[s];
+        float xl[3], jv[3], u0v[3];
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            xl[a] = A.xl[a][s];
+            jv[a] = j_i[(long long)a * np + s];
+            u0v[a] = A.u[a][s];
+        }
+        const float d = me.w, rp = A.rp[s];
         float m = particle_mass(D, d, rp);
         float Ap = 0.25f * PI_F * d * d;
         float ri = 1.0f + drho_i[s];
@@ -727,11 +796,10 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
         float un[3], dx[3], gb[3];
 #pragma unroll
         for (int a = 0; a < D; a++) {
-            float ja = j_i[(long long)a * np + s];
-            float ustar = ja / ri;
+            float ustar = jv[a] / ri;
             float slip = bw * c.g[a] / cc;   // U_eq - u*
             float ueq = ustar + slip;
-            float u0 = A.u[a][s];
+            float u0 = u0v[a];
             un[a] = ueq + (u0 - ueq) * qn;
             dx[a] = ueq + (u0 - ueq) * (c.h * q * geo);
             gb[a] = 2.0f * ri * (slip + (u0 - ueq) * (geo * c.h));
@@ -746,25 +814,35 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
             for (int a = 0; a < D; a++) {
                 un[a] = 0.f;
                 dx[a] = 0.f;
-                gb[a] = -2.0f * j_i[(long long)a * np + s];
+                gb[a] = -2.0f * jv[a];
             }
             v0s = vns = ves = dvs = 0.f;
             Ap = A.fixa[s];
         }
         // q > 0: U^k moves along the segment from U^0 to U^n; q < 0: it
         // alternates around U_eq within |U^0 - U_eq|
-        float B = (q > 0.f) ? sqrtf(fmaxf(v0s, vns)) : sqrtf(ves) + sqrtf(dvs);
+        const float B = (q > 0.f) ? sqrtf(fmaxf(v0s, vns)) : sqrtf(ves) + sqrtf(dvs);
+        const bool skin_out = B > 0.5f * c.skin;
+        // The free result is written for every particle before the scan (the
+        // island kernels overwrite it for the active ones), so that none of
+        // it stays live across the scan.
+        bool wall = false;
+#pragma unroll
+        for (int a = 0; a < D; a++) {
+            float xh = a == 0 ? me.x : (a == 1 ? me.y : me.z), xla = xl[a];
+            const float x = xh + xla;
+            wall = wall || (x - 0.5f * d <= B) || (((float)c.n[a] - x) - 0.5f * d <= B);
+            df_add(xh, xla, dx[a]);
+            Bn.xh[a][s] = xh;
+            Bn.xl[a][s] = xla;
+            Bn.u[a][s] = un[a];
+            srec[(long long)s * SRec<D>::STRIDE + SRec<D>::COEF + a] = Ap * gb[a];
+            fc[(long long)a * np + s] = 0.f;
+        }
+        wall = wall && !fixedp;                             // fixed points feel no wall
         if (c.contact != PIBM_CONTACT_NONE) {
             bool close = false;
-            int cnt = scan_neighbours<D, false>(pos4, start, keys_sorted, c, s, B + 0.5f * c.skin, close, nullptr,
-                                               nullptr, 0, A.fixa);
-            bool wall = false;
-#pragma unroll
-            for (int a = 0; a < D; a++) {
-                float x = A.xh[a][s] + A.xl[a][s];
-                wall = wall || (x - 0.5f * d <= B) || (((float)c.n[a] - x) - 0.5f * d <= B);
-            }
-            wall = wall && !fixedp;                         // fixed points feel no wall
+            const int cnt = count_neighbours<D>(pos4, start, me, key, c, s, B + 0.5f * c.skin, close, fixedp, A.fixa);
             if (close || wall) {
                 if (cnt > c.maxc) atomicOr(flags, FLAG_CAPACITY);
                 active = true;
@@ -772,16 +850,6 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
             }
         }
         if (!active) {
-#pragma unroll
-            for (int a = 0; a < D; a++) {
-                float xh = A.xh[a][s], xl = A.xl[a][s];
-                df_add(xh, xl, dx[a]);
-                Bn.xh[a][s] = xh;
-                Bn.xl[a][s] = xl;
-                Bn.u[a][s] = un[a];
-                srec[(long long)s * SRec<D>::STRIDE + SRec<D>::COEF + a] = Ap * gb[a];
-                fc[(long long)a * np + s] = 0.f;
-            }
             if (hcnt) {
                 // no contact: the spin is unchanged and no tangential force is carried
 #pragma unroll
@@ -789,7 +857,7 @@ __global__ __launch_bounds__(256) void k_classify(PState A, PState Bn, int np, P
                     if (A.w[a]) Bn.w[a][s] = A.w[a][s];
                 hcnt[A.id[s]] = 0u;
             }
-            if (B > 0.5f * c.skin) atomicOr(flags, FLAG_SKIN);
+            if (skin_out) atomicOr(flags, FLAG_SKIN);
         }
         actcc[s] = active ? ((1ULL << 32) | (unsigned long long)ncand) : 0ULL;
     }
@@ -853,10 +921,7 @@ __global__ __launch_bounds__(256) void k_collect(PState A, int np, PCfg c, const
     parent[a] = a;
     isize[a] = 0;
     fill[a] = 0;
-    bool dummy = false;
-    int n = cap > 0 ? scan_neighbours<D, true>(pos4, start, keys_sorted, c, s, 0.f, dummy, actcc, cand + off, cap,
-                                               A.fixa)
-                    : 0;
+    int n = cap > 0 ? collect_neighbours<D>(pos4, start, keys_sorted, c, s, actcc, cand + off, cap, A.fixa) : 0;
     ccount[s] = (uint32_t)min(n, cap);
 }
 

@@ -311,6 +311,71 @@ def test_coupled_step_with_contacts(P, orc, lat, contact):
     assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["eu"] <= 1e-5 and r["er"] <= 1e-6
 
 
+@pytest.mark.parametrize("lat", [9, 19])
+def test_contacts_of_particles_wider_than_a_bin(P, orc, lat):
+    """Polydisperse clusters with diameters up to 2.4 bin edges, some resting
+    on the floor: a particle's neighbour reach then spans up to seven bins
+    per axis, so the counting scan takes its rows of bins in several batches
+    (up to 49 rows in 3D, 7 in 2D), and every contact it misses would leave a
+    particle on the free closed form."""
+    _flush(f"wide particles {lat}")
+    D = 2 if lat == 9 else 3
+    n = (48, 40, 1) if D == 2 else (24, 22, 26)
+    rng = np.random.default_rng(57)
+    sizes = [0.5, 1.6, 2.4, 0.8]
+    pts, ds = [], []
+
+    def fits(p, dd, floor=False):
+        for q, e in zip(pts, ds):
+            if np.sqrt(((p - q) ** 2).sum()) < 0.5 * (dd + e) + 0.3:
+                return False
+        return all((floor and a == D - 1) or dd / 2 + 1.0 <= p[a] <= n[a] - dd / 2 - 1.0 for a in range(D))
+
+    clusters = 0
+    for _ in range(4000):
+        if clusters == (8 if D == 2 else 10):
+            break
+        k = 2 + clusters % 3
+        axis = rng.standard_normal(D)
+        axis /= np.linalg.norm(axis)
+        dd = [sizes[(clusters + i) % 4] for i in range(k)]
+        new = [np.array([rng.uniform(3, n[a] - 3) for a in range(D)])]
+        for i in range(1, k):      # touching chain, gaps of 1e-3
+            new.append(new[-1] + axis * (0.5 * (dd[i - 1] + dd[i]) + 1e-3))
+        if all(fits(p, e) for p, e in zip(new, dd)):
+            pts += new
+            ds += dd
+            clusters += 1
+    assert clusters == (8 if D == 2 else 10)
+    floor = 0
+    for _ in range(4000):          # wide particles just touching the floor
+        if floor == 3:
+            break
+        p = np.array([rng.uniform(3, n[a] - 3) for a in range(D)])
+        p[D - 1] = 0.79999
+        if fits(p, 1.6, floor=True):
+            pts.append(p)
+            ds.append(1.6)
+            floor += 1
+    assert floor == 3
+    # both sides start from the same FP32-representable numbers: 1.6 rounded
+    # to FP32 moves a radius by 1e-8, 1e-3 of the floor overlap
+    X = np.array(pts).T.astype(np.float32).astype(np.float64)
+    d = np.array(ds).astype(np.float32).astype(np.float64)
+    npart = X.shape[1]
+    U = (3e-4 * rng.standard_normal((D, npart))).astype(np.float32).astype(np.float64)
+    rp = np.full(npart, 2.5)
+    g = [0.0, 0.0, 0.0]
+    g[D - 1] = -1e-5
+    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact="lsd")
+    r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=1, label="1 step")
+    assert r["sim"].diagnostics()["active"] > 0
+    assert r["eu"] <= 1e-5 and r["er"] <= 1e-6
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["efh"] <= 1e-5
+    r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=3, label="3 steps")
+    assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["eu"] <= 1e-5 and r["er"] <= 1e-6
+
+
 @pytest.mark.parametrize("k", [60, 150])
 def test_big_island(P, orc, k):
     """150 particles linked by candidate pairs form one island larger than a
