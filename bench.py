@@ -187,10 +187,7 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
         if warmup > 500:
             print(f"[bench] {label}: {done} of {warmup} untimed steps ({time.time() - t_w:.1f} s)",
                   file=sys.stderr, flush=True)
-    # phase events on PROFILE_SAMPLES evenly spaced timed steps: each recorded
-    # step carries 7 event records, which add a few microseconds each
-    sim.set_profiling(True, every=max(1, steps // PROFILE_SAMPLES))
-    sim.phase_times()
+    # no phase events in the timed steps
     stream = sim.stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -200,6 +197,12 @@ def run_gpu(w, steps: int, warmup: int, label: str, keep_fields: bool = False):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
+    # the phase breakdown comes from the next `steps` steps, with events on
+    # PROFILE_SAMPLES evenly spaced ones (each recorded step carries 7 event
+    # records, which add a few microseconds each)
+    sim.set_profiling(True, every=max(1, steps // PROFILE_SAMPLES))
+    sim.phase_times()
+    sim.step(steps)
     phases, nsteps = sim.phase_times()
     status = "ok"
     try:
