@@ -311,14 +311,16 @@ def test_coupled_step_with_contacts(P, orc, lat, contact):
     assert r["ex"] <= 1e-5 and r["ev"] <= 1e-5 and r["eu"] <= 1e-5 and r["er"] <= 1e-6
 
 
-@pytest.mark.parametrize("lat", [9, 19])
-def test_contacts_of_particles_wider_than_a_bin(P, orc, lat):
-    """Polydisperse clusters with diameters up to 2.4 bin edges, some resting
-    on the floor: a particle's neighbour reach then spans up to seven bins
-    per axis, so the counting scan takes its rows of bins in several batches
-    (up to 49 rows in 3D, 7 in 2D), and every contact it misses would leave a
-    particle on the free closed form."""
-    _flush(f"wide particles {lat}")
+@pytest.mark.parametrize("lat,bl", [(9, 0), (19, 0), (9, 1), (19, 2)])
+def test_contacts_of_particles_wider_than_a_bin(P, orc, lat, bl):
+    """Polydisperse clusters with diameters up to 2.4 dual cells, some resting
+    on the floor.  With bins of one dual cell a particle's neighbour reach
+    spans up to seven bins per axis, so the counting scan takes its rows of
+    bins in several batches (up to 49 rows in 3D, 7 in 2D); with bins of 2
+    or 4 cells (bin_log2 1, 2) the same contacts are found in coarser rows.
+    Every contact the scan misses would leave a particle on the free closed
+    form."""
+    _flush(f"wide particles {lat} bin_log2={bl}")
     D = 2 if lat == 9 else 3
     n = (48, 40, 1) if D == 2 else (24, 22, 26)
     rng = np.random.default_rng(57)
@@ -367,7 +369,7 @@ def test_contacts_of_particles_wider_than_a_bin(P, orc, lat):
     rp = np.full(npart, 2.5)
     g = [0.0, 0.0, 0.0]
     g[D - 1] = -1e-5
-    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact="lsd")
+    cfg = P.make_config(lattice=lat, n=n, tau=0.8, gravity=g, n_sub=400, contact="lsd", bin_log2=bl)
     r = _coupled_compare(P, orc, cfg, X, U, d, rp, steps=1, label="1 step")
     assert r["sim"].diagnostics()["active"] > 0
     assert r["eu"] <= 1e-5 and r["er"] <= 1e-6
