@@ -195,9 +195,16 @@ __global__ __launch_bounds__(256) void k_scan_down(T* __restrict__ in, T* __rest
     load_items<T>(in, base, n, v);
     if (zero_in) {
         if (base + SCAN_ITEMS <= n) {
-            uint4* p = reinterpret_cast<uint4*>(in + base);
+            // items that are all zero stay as they are (the bin counts of
+            // the empty parts of the box cost no writes)
+            T any = 0;
 #pragma unroll
-            for (int k = 0; k < (int)(SCAN_ITEMS * sizeof(T) / 16); k++) p[k] = make_uint4(0u, 0u, 0u, 0u);
+            for (int k = 0; k < SCAN_ITEMS; k++) any |= v[k];
+            if (any != 0) {
+                uint4* p = reinterpret_cast<uint4*>(in + base);
+#pragma unroll
+                for (int k = 0; k < (int)(SCAN_ITEMS * sizeof(T) / 16); k++) p[k] = make_uint4(0u, 0u, 0u, 0u);
+            }
         } else {
             for (int k = 0; k < SCAN_ITEMS; k++)
                 if (base + k < n) in[base + k] = (T)0;
